@@ -1,0 +1,541 @@
+"""Seeded synthetic inputs for the known-object prediction path.
+
+This module produces *inputs only*: a Chebyshev-tabulated perturber
+ephemeris (a stand-in for a planetary SPK kernel), Cartesian states of
+massless small bodies, and telescope frames (time, observer position and
+the inward great-circle normals of each rectangular field of view).
+Both the GPU path and the CPU oracle consume what it writes; it performs
+none of the prediction arithmetic itself (no Chebyshev evaluation, no
+force model, no integration, no universal-variable propagation, no light
+time, no membership test).
+
+Where an input needs orbital geometry (placing bodies on orbits, aiming
+frames), it uses the textbook elliptic-elements construction: mean
+anomaly -> eccentric anomaly by Newton on Kepler's equation -> perifocal
+coordinates -> ecliptic rotation.  That builds *inputs*; it is not the
+propagation method under test.
+
+Units: au, TDB days, au/day.  Frame: ecliptic J2000, origin at the solar
+system barycentre.  Time zero is the J2000 epoch label.
+
+The synthetic configurations restate the workload sizes of the paper's
+two survey simulations (Sect. 2) with generated stand-ins: the real
+ZTF/WISE metadata, the MPC catalogue and DE440 are not used.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Dict, List, Optional
+
+import numpy as np
+
+# --------------------------------------------------------------------------
+# Constants (public values).
+# --------------------------------------------------------------------------
+AU_KM = 149597870.7
+C_AU_PER_DAY = 299792.458 * 86400.0 / AU_KM          # 173.144632674...
+OBLIQUITY_J2000_RAD = math.radians(84381.448 / 3600.0)
+
+# GM in au^3/day^2 (DE440 values for the Sun and the planetary systems).
+GM_SUN = 2.9591220828411956e-04
+_PLANETS = [
+    # name, GM, a[au], e, I[deg], L[deg], long.peri[deg], node[deg]
+    # J2000 mean elements (Standish, "Keplerian elements for approximate
+    # positions of the major planets", table 1).
+    ("mercury", 4.9125001948893182e-11, 0.38709927, 0.20563593, 7.00497902, 252.25032350, 77.45779628, 48.33076593),
+    ("venus",   7.2434523326441187e-10, 0.72333566, 0.00677672, 3.39467605, 181.97909950, 131.60246718, 76.67984255),
+    ("earth",   8.9970116036316091e-10, 1.00000261, 0.01671123, -0.00001531, 100.46457166, 102.93768193, 0.0),
+    ("mars",    9.5495488297258119e-11, 1.52371034, 0.09339410, 1.84969142, -4.55343205, -23.94362959, 49.55953891),
+    ("jupiter", 2.8253458252257917e-07, 5.20288700, 0.04838624, 1.30439695, 34.39644051, 14.72847983, 100.47390909),
+    ("saturn",  8.4597059933762903e-08, 9.53667594, 0.05386179, 2.48599187, 49.95424423, 92.59887831, 113.66242448),
+    ("uranus",  1.2920265649682399e-08, 19.18916464, 0.04725744, 0.77263783, 313.23810451, 170.95427630, 74.01692503),
+    ("neptune", 1.5243573478851939e-08, 30.06992276, 0.00859048, 1.77004347, -55.12002969, 44.96476227, 131.78422574),
+]
+PLANET_NAMES = [p[0] for p in _PLANETS]
+# Bodies that carry the first post-Newtonian correction (Sun, Jupiter, Earth).
+GR_BODIES = ("sun", "jupiter", "earth")
+
+SEG_DAYS = 8.0
+CHEB_DEGREE = 12
+
+
+# --------------------------------------------------------------------------
+# Elliptic elements -> Cartesian (input construction only).
+# --------------------------------------------------------------------------
+def _solve_kepler_E(M: np.ndarray, e: np.ndarray) -> np.ndarray:
+    M = np.mod(M, 2.0 * np.pi)
+    E = np.where(e < 0.8, M, np.pi * np.ones_like(M))
+    for _ in range(60):
+        f = E - e * np.sin(E) - M
+        fp = 1.0 - e * np.cos(E)
+        dE = f / fp
+        E = E - dE
+        if np.max(np.abs(dE)) < 1e-15:
+            break
+    return E
+
+
+def elements_to_state(a, e, inc, node, peri, M, mu):
+    """Elliptic elements (radians) -> heliocentric ecliptic state [..., 6]."""
+    a = np.asarray(a, float); e = np.asarray(e, float)
+    E = _solve_kepler_E(np.asarray(M, float), e)
+    cE, sE = np.cos(E), np.sin(E)
+    b = np.sqrt(1.0 - e * e)
+    r = a * (1.0 - e * cE)
+    xp = a * (cE - e)
+    yp = a * b * sE
+    k = np.sqrt(mu * a) / r
+    vxp = -k * sE
+    vyp = k * b * cE
+    cO, sO = np.cos(node), np.sin(node)
+    ci, si = np.cos(inc), np.sin(inc)
+    cw, sw = np.cos(peri), np.sin(peri)
+    # Columns of the perifocal -> ecliptic rotation R3(-node) R1(-inc) R3(-peri).
+    Px = cO * cw - sO * sw * ci
+    Py = sO * cw + cO * sw * ci
+    Pz = sw * si
+    Qx = -cO * sw - sO * cw * ci
+    Qy = -sO * sw + cO * cw * ci
+    Qz = cw * si
+    out = np.empty(np.broadcast(a, M).shape + (6,))
+    out[..., 0] = xp * Px + yp * Qx
+    out[..., 1] = xp * Py + yp * Qy
+    out[..., 2] = xp * Pz + yp * Qz
+    out[..., 3] = vxp * Px + vyp * Qx
+    out[..., 4] = vxp * Py + vyp * Qy
+    out[..., 5] = vxp * Pz + vyp * Qz
+    return out
+
+
+@dataclasses.dataclass
+class PlanetModel:
+    """Sun plus planets on fixed heliocentric ellipses (an analytic stand-in
+    for a planetary ephemeris)."""
+    names: List[str]
+    gm: np.ndarray          # [n_body] (index 0 = Sun)
+    el: np.ndarray          # [n_planet, 6]: a, e, I, node, peri, M0 (radians)
+    n: np.ndarray           # mean motions [rad/day]
+
+    @staticmethod
+    def make(planets: Optional[List[str]] = None) -> "PlanetModel":
+        planets = PLANET_NAMES if planets is None else list(planets)
+        rows = [p for p in _PLANETS if p[0] in planets]
+        rows.sort(key=lambda p: PLANET_NAMES.index(p[0]))
+        gm = np.array([GM_SUN] + [p[1] for p in rows])
+        el = []
+        for p in rows:
+            a, e, I, L, varpi, node = p[2:]
+            el.append([a, e, math.radians(I), math.radians(node),
+                       math.radians(varpi - node), math.radians(L - varpi)])
+        el = np.array(el).reshape(-1, 6)
+        n = np.sqrt((GM_SUN + gm[1:]) / el[:, 0] ** 3)
+        return PlanetModel(["sun"] + [p[0] for p in rows], gm, el, n)
+
+    def helio(self, t: np.ndarray) -> np.ndarray:
+        """Heliocentric planet states [..., n_planet, 6] at times t [...]."""
+        t = np.asarray(t, float)
+        M = self.el[:, 5] + self.n * t[..., None]
+        mu = GM_SUN + self.gm[1:]
+        return elements_to_state(self.el[:, 0], self.el[:, 1], self.el[:, 2],
+                                 self.el[:, 3], self.el[:, 4], M, mu)
+
+    def bary(self, t: np.ndarray) -> np.ndarray:
+        """Barycentric states [..., n_body, 6]; body 0 is the Sun."""
+        h = self.helio(t)
+        m = self.gm[1:] / self.gm.sum()
+        sun = -(m[:, None] * h).sum(axis=-2)
+        return np.concatenate([sun[..., None, :], sun[..., None, :] + h], axis=-2)
+
+    def sun(self, t):
+        return self.bary(t)[..., 0, :]
+
+
+# --------------------------------------------------------------------------
+# Chebyshev tables.
+# --------------------------------------------------------------------------
+@dataclasses.dataclass
+class Ephemeris:
+    """Chebyshev-tabulated perturber positions.
+
+    coef[body][seg][xyz][k] gives the position of `body` inside segment
+    `seg` (covering [t_start + seg*seg_days, t_start + (seg+1)*seg_days])
+    as sum_k coef[k] T_k(tau), tau = 2 (t - t_seg)/seg_days - 1.
+    """
+    coef: np.ndarray
+    gm: np.ndarray
+    flags: np.ndarray       # uint32, bit0 = first post-Newtonian term
+    t_start: float
+    seg_days: float
+    names: List[str]
+
+    @property
+    def n_body(self): return self.coef.shape[0]
+    @property
+    def n_seg(self): return self.coef.shape[1]
+    @property
+    def degree(self): return self.coef.shape[3] - 1
+    @property
+    def t_end(self): return self.t_start + self.n_seg * self.seg_days
+
+
+def cheb_fit_nodes(degree: int) -> np.ndarray:
+    """Chebyshev-Gauss nodes (roots of T_{degree+1}) on [-1, 1]."""
+    m = degree + 1
+    return np.cos(np.pi * (np.arange(m) + 0.5) / m)
+
+
+def cheb_fit_matrix(degree: int) -> np.ndarray:
+    """Discrete Chebyshev transform: coef = W @ f(nodes)."""
+    m = degree + 1
+    x = cheb_fit_nodes(degree)
+    T = np.cos(np.outer(np.arange(m), np.arccos(x)))   # T[k, j] = T_k(x_j)
+    W = (2.0 / m) * T
+    W[0] *= 0.5
+    return W
+
+
+def make_ephemeris(model: PlanetModel, t_start: float, n_seg: int,
+                   seg_days: float = SEG_DAYS, degree: int = CHEB_DEGREE,
+                   gr: bool = True) -> Ephemeris:
+    """Tabulate `model` as Chebyshev segments by interpolation at the
+    Chebyshev-Gauss nodes of every segment."""
+    x = cheb_fit_nodes(degree)
+    W = cheb_fit_matrix(degree)
+    seg0 = t_start + seg_days * np.arange(n_seg)
+    tn = seg0[:, None] + 0.5 * seg_days * (x[None, :] + 1.0)     # [seg, node]
+    st = model.bary(tn)                                           # [seg, node, body, 6]
+    pos = st[..., :3]                                             # [seg, node, body, 3]
+    coef = np.einsum("kj,sjbc->bsck", W, pos)                     # [body, seg, 3, deg+1]
+    flags = np.array([1 if (gr and nm in GR_BODIES) else 0 for nm in model.names],
+                     dtype=np.uint32)
+    return Ephemeris(np.ascontiguousarray(coef), model.gm.copy(), flags,
+                     float(t_start), float(seg_days), list(model.names))
+
+
+def sun_only_ephemeris(t_start: float, n_seg: int, gr: bool = False,
+                       seg_days: float = SEG_DAYS, degree: int = CHEB_DEGREE) -> Ephemeris:
+    """A single perturber (the Sun) fixed at the origin."""
+    coef = np.zeros((1, n_seg, 3, degree + 1))
+    return Ephemeris(coef, np.array([GM_SUN]), np.array([1 if gr else 0], np.uint32),
+                     float(t_start), float(seg_days), ["sun"])
+
+
+def polynomial_ephemeris(rng: np.random.Generator, n_body: int, t_start: float,
+                         n_seg: int, seg_days: float = SEG_DAYS,
+                         degree: int = CHEB_DEGREE) -> Ephemeris:
+    """Random coefficient tables (for evaluator tests)."""
+    coef = rng.normal(size=(n_body, n_seg, 3, degree + 1))
+    gm = np.full(n_body, 1e-9)
+    return Ephemeris(coef, gm, np.zeros(n_body, np.uint32), float(t_start),
+                     float(seg_days), [f"b{i}" for i in range(n_body)])
+
+
+# --------------------------------------------------------------------------
+# Small bodies.
+# --------------------------------------------------------------------------
+def _rayleigh_truncated(rng, sigma, n, upper):
+    out = rng.rayleigh(sigma, n)
+    bad = out >= upper
+    while bad.any():
+        out[bad] = rng.rayleigh(sigma, bad.sum())
+        bad = out >= upper
+    return out
+
+
+def main_belt_elements(rng: np.random.Generator, n: int) -> np.ndarray:
+    """a ~ U(2.1, 3.3) au; e ~ Rayleigh(0.1) resampled until e < 0.4;
+    i ~ Rayleigh(8 deg); node, peri, M ~ U(0, 2 pi)."""
+    a = rng.uniform(2.1, 3.3, n)
+    e = _rayleigh_truncated(rng, 0.1, n, 0.4)
+    inc = rng.rayleigh(math.radians(8.0), n)
+    ang = rng.uniform(0.0, 2.0 * np.pi, (3, n))
+    return np.stack([a, e, inc, ang[0], ang[1], ang[2]], axis=1)
+
+
+def neo_elements(rng: np.random.Generator, n: int) -> np.ndarray:
+    """a ~ U(0.8, 2.0) au; e ~ U(0.1, 0.7); i ~ Rayleigh(8 deg)."""
+    a = rng.uniform(0.8, 2.0, n)
+    e = rng.uniform(0.1, 0.7, n)
+    inc = rng.rayleigh(math.radians(8.0), n)
+    ang = rng.uniform(0.0, 2.0 * np.pi, (3, n))
+    return np.stack([a, e, inc, ang[0], ang[1], ang[2]], axis=1)
+
+
+def bodies_from_elements(model: PlanetModel, el: np.ndarray, epoch: float) -> np.ndarray:
+    """Barycentric states [n, 6] at `epoch` from heliocentric elements."""
+    st = elements_to_state(el[:, 0], el[:, 1], el[:, 2], el[:, 3], el[:, 4], el[:, 5], GM_SUN)
+    return st + model.sun(np.array(epoch))[None, :]
+
+
+def make_population(rng, model, n, neo_frac, epoch):
+    n_neo = int(round(n * neo_frac))
+    el = np.concatenate([main_belt_elements(rng, n - n_neo), neo_elements(rng, n_neo)])
+    is_neo = np.zeros(n, bool); is_neo[n - n_neo:] = True
+    perm = rng.permutation(n)
+    el, is_neo = el[perm], is_neo[perm]
+    return bodies_from_elements(model, el, epoch), el, is_neo
+
+
+# --------------------------------------------------------------------------
+# Frames.
+# --------------------------------------------------------------------------
+def tangent_basis(center: np.ndarray):
+    """Local east/north unit vectors at ecliptic directions `center` [...,3]."""
+    z = np.array([0.0, 0.0, 1.0])
+    east = np.cross(z, center)
+    nrm = np.linalg.norm(east, axis=-1, keepdims=True)
+    polar = nrm[..., 0] < 1e-12
+    east = np.where(polar[..., None], np.array([0.0, 1.0, 0.0]), east / np.where(nrm > 0, nrm, 1))
+    north = np.cross(center, east)
+    return east, north
+
+
+def rect_normals(center, u, w, half_u, half_w):
+    """Inward great-circle normals [..., 4, 3] of the gnomonic rectangle
+    |d.u/d.c| < tan(half_u), |d.w/d.c| < tan(half_w)."""
+    su, cu = np.sin(half_u)[..., None], np.cos(half_u)[..., None]
+    sw, cw = np.sin(half_w)[..., None], np.cos(half_w)[..., None]
+    n = np.stack([su * center - cu * u, su * center + cu * u,
+                  sw * center - cw * w, sw * center + cw * w], axis=-2)
+    return n
+
+
+@dataclasses.dataclass
+class Frames:
+    t: np.ndarray          # [F]
+    obs: np.ndarray        # [F, 3] barycentric observer position
+    center: np.ndarray     # [F, S, 3] sub-frame centres
+    u: np.ndarray          # [F, S, 3]
+    w: np.ndarray          # [F, S, 3]
+    half_u: np.ndarray     # [F, S] radians
+    half_w: np.ndarray     # [F, S]
+    normals: np.ndarray    # [F, S, 4, 3]
+
+    @property
+    def n_frames(self): return self.t.shape[0]
+    @property
+    def n_sub(self): return self.normals.shape[1]
+
+    def subset(self, idx):
+        idx = np.asarray(idx)
+        return Frames(self.t[idx], self.obs[idx], self.center[idx], self.u[idx], self.w[idx],
+                      self.half_u[idx], self.half_w[idx], self.normals[idx])
+
+    @staticmethod
+    def concat(parts):
+        return Frames(*[np.concatenate([getattr(p, f.name) for p in parts])
+                        for f in dataclasses.fields(Frames)])
+
+
+def _frames_from_pointing(t, obs, center, roll, half_u, half_w):
+    east, north = tangent_basis(center)
+    cr, sr = np.cos(roll)[..., None], np.sin(roll)[..., None]
+    u = cr * east + sr * north
+    w = -sr * east + cr * north
+    half_u = np.broadcast_to(half_u, center.shape[:-1]).astype(float)
+    half_w = np.broadcast_to(half_w, center.shape[:-1]).astype(float)
+    return Frames(t, obs, center[:, None], u[:, None], w[:, None],
+                  half_u[:, None], half_w[:, None],
+                  rect_normals(center, u, w, half_u, half_w)[:, None])
+
+
+def circular_observer(model: PlanetModel, t: np.ndarray, phase0: float = 0.0) -> np.ndarray:
+    """Barycentric position of an observer on a 1 au circular heliocentric
+    orbit in the ecliptic."""
+    n = math.sqrt(GM_SUN)
+    th = phase0 + n * t
+    helio = np.stack([np.cos(th), np.sin(th), np.zeros_like(th)], axis=-1)
+    return helio + model.sun(t)[..., :3]
+
+
+def frames_tiny(rng, model, n_frames, t0, span, width_deg, max_lat_deg=20.0):
+    """Square frames pointed uniformly (in solid angle) within +-max_lat of
+    the ecliptic, exposure times uniform over [t0, t0+span], roll 0."""
+    t = np.sort(rng.uniform(t0, t0 + span, n_frames))
+    lon = rng.uniform(0.0, 2.0 * np.pi, n_frames)
+    slat = rng.uniform(-math.sin(math.radians(max_lat_deg)), math.sin(math.radians(max_lat_deg)), n_frames)
+    clat = np.sqrt(1.0 - slat ** 2)
+    center = np.stack([clat * np.cos(lon), clat * np.sin(lon), slat], axis=1)
+    obs = circular_observer(model, t)
+    h = math.radians(width_deg / 2.0)
+    return _frames_from_pointing(t, obs, center, np.zeros(n_frames), h, h)
+
+
+def frames_survey(rng, model, n_frames, t0, span, width_deg=0.78, seq_len=12,
+                  cadence_s=11.0, step_deg=0.7, offset_km=7000.0,
+                  offset_period_min=97.1, max_lat_deg=40.0):
+    """Space-survey frames: observer on a 1 au circle plus a circular
+    terminator offset orbit; sequences of `seq_len` exposures `cadence_s`
+    apart, stepping `step_deg` along the 90-degree-elongation great circle,
+    each frame rolled so that its first axis is the scan direction."""
+    n_seq = -(-n_frames // seq_len)
+    t_seq = t0 + (np.arange(n_seq) + rng.uniform(0, 1, n_seq)) * (span - 1.0 / 24.0) / n_seq
+    j = np.arange(seq_len)
+    t = (t_seq[:, None] + j[None, :] * cadence_s / 86400.0).reshape(-1)[:n_frames]
+    n = math.sqrt(GM_SUN)
+    th = n * t
+    rhat = np.stack([np.cos(th), np.sin(th), np.zeros_like(th)], axis=-1)
+    along = np.stack([-np.sin(th), np.cos(th), np.zeros_like(th)], axis=-1)
+    zhat = np.broadcast_to(np.array([0.0, 0.0, 1.0]), rhat.shape)
+    phi = 2.0 * np.pi * t / (offset_period_min / 1440.0)
+    R = offset_km / AU_KM
+    obs = model.sun(t)[..., :3] + rhat + R * (np.cos(phi)[:, None] * zhat + np.sin(phi)[:, None] * along)
+    # start angle on the elongation-90 circle: d(psi) = cos psi along + sin psi z
+    side = rng.integers(0, 2, n_seq) * np.pi
+    psi0 = rng.uniform(-math.radians(max_lat_deg), math.radians(max_lat_deg), n_seq)
+    psi = ((psi0[:, None] + j[None, :] * math.radians(step_deg)).reshape(-1)[:n_frames]
+           + np.repeat(side, seq_len)[:n_frames])
+    cp, sp = np.cos(psi)[:, None], np.sin(psi)[:, None]
+    center = cp * along + sp * zhat
+    u = -sp * along + cp * zhat                   # scan direction
+    w = np.cross(center, u)
+    h = math.radians(width_deg / 2.0)
+    hu = np.full(n_frames, h); hw = np.full(n_frames, h)
+    return Frames(t, obs, center[:, None], u[:, None], w[:, None], hu[:, None], hw[:, None],
+                  rect_normals(center, u, w, hu, hw)[:, None])
+
+
+def frames_targeted(rng, model, states_el, t0, span, n_frames, width_deg=1.5,
+                    straddle_frac=0.5):
+    """Frames aimed at the analytic two-body direction of randomly chosen
+    bodies (from their elements), half of them offset so that the body
+    lies near an edge.  Used to obtain many (object, frame) pairs in
+    small parity cases."""
+    el = states_el
+    idx = rng.integers(0, el.shape[0], n_frames)
+    t = np.sort(rng.uniform(t0, t0 + span, n_frames))
+    M = el[idx, 5] + np.sqrt(GM_SUN / el[idx, 0] ** 3) * (t - t0)
+    helio = elements_to_state(el[idx, 0], el[idx, 1], el[idx, 2], el[idx, 3], el[idx, 4], M, GM_SUN)
+    obs = circular_observer(model, t)
+    pos = helio[:, :3] + model.sun(t)[:, :3]
+    d = pos - obs
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    h = math.radians(width_deg / 2.0)
+    east, north = tangent_basis(d)
+    off = np.zeros((n_frames, 2))
+    k = rng.uniform(0, 1, n_frames) < straddle_frac
+    # put the body near an edge: shift the centre by about one half-width
+    off[k, 0] = rng.choice([-1, 1], k.sum()) * h * rng.uniform(0.9, 1.1, k.sum())
+    off[k, 1] = rng.uniform(-0.5, 0.5, k.sum()) * h
+    center = d + off[:, :1] * east + off[:, 1:] * north
+    center /= np.linalg.norm(center, axis=1, keepdims=True)
+    roll = rng.uniform(0, 2 * np.pi, n_frames)
+    return _frames_from_pointing(t, obs, center, roll, h, h)
+
+
+def ecliptic_to_equatorial(v: np.ndarray) -> np.ndarray:
+    ce, se = math.cos(OBLIQUITY_J2000_RAD), math.sin(OBLIQUITY_J2000_RAD)
+    out = np.empty_like(v)
+    out[..., 0] = v[..., 0]
+    out[..., 1] = ce * v[..., 1] - se * v[..., 2]
+    out[..., 2] = se * v[..., 1] + ce * v[..., 2]
+    return out
+
+
+# --------------------------------------------------------------------------
+# Configurations (sizes of the five workloads; `scale` shrinks counts).
+# --------------------------------------------------------------------------
+@dataclasses.dataclass
+class PropagationCase:
+    name: str
+    ephem: Ephemeris
+    model: PlanetModel
+    x0: np.ndarray           # [N, 6]
+    elements: np.ndarray     # [N, 6] heliocentric elements at t0
+    is_neo: np.ndarray
+    t0: float
+    span: float
+    frames: Optional[Frames]
+    seed: int
+
+
+def tiny_case(seed: int = 1, n_obj: int = 1000, n_frames: int = 100, span: float = 30.0,
+              n_targeted: int = 0) -> PropagationCase:
+    """1,000 main-belt bodies, Sun + Jupiter + Saturn as 8-day degree-12
+    Chebyshev segments, 30 days, 100 frames of 1.5 deg x 1.5 deg from a
+    1 au circular observer pointed within +-20 deg of the ecliptic."""
+    rng = np.random.default_rng(seed)
+    model = PlanetModel.make(["jupiter", "saturn"])
+    n_seg = int(math.ceil((span + 24.0) / SEG_DAYS))
+    eph = make_ephemeris(model, -8.0, n_seg)
+    el = main_belt_elements(rng, n_obj)
+    x0 = bodies_from_elements(model, el, 0.0)
+    fr = frames_tiny(rng, model, n_frames, 0.0, span, 1.5)
+    if n_targeted:
+        fr = Frames.concat([fr, frames_targeted(rng, model, el, 0.0, span, n_targeted)])
+        order = np.argsort(fr.t, kind="stable")
+        fr = fr.subset(order)
+    return PropagationCase("tiny", eph, model, x0, el, np.zeros(n_obj, bool), 0.0, span, fr, seed)
+
+
+def survey_case(seed: int = 2, n_obj: int = 100_000, n_frames: int = 500_000,
+                span: float = 365.25, neo_frac: float = 0.05) -> PropagationCase:
+    """100,000 bodies (95% main belt, 5% NEO-like), all 8 planets, one year,
+    500,000 frames of 0.78 deg from a space observer on a 1 au orbit plus
+    a 7,000 km offset orbit, in 11 s sequences of 12 along great circles."""
+    rng = np.random.default_rng(seed)
+    model = PlanetModel.make()
+    n_seg = int(math.ceil((span + 24.0) / SEG_DAYS))
+    eph = make_ephemeris(model, -8.0, n_seg)
+    x0, el, is_neo = make_population(rng, model, n_obj, neo_frac, 0.0)
+    fr = frames_survey(rng, model, n_frames, 0.0, span) if n_frames else None
+    return PropagationCase("survey", eph, model, x0, el, is_neo, 0.0, span, fr, seed)
+
+
+@dataclasses.dataclass
+class GradientCase:
+    ephem: Ephemeris
+    x_true: np.ndarray       # [N, 6]
+    x0: np.ndarray           # [N, 6] perturbed start
+    t0: float
+    t_obs: np.ndarray        # [N, K]
+    obs_pos: np.ndarray      # [N, K, 3]
+    radec_obs: np.ndarray    # [N, K, 2] equatorial RA/Dec (radians)
+    arc: float
+
+
+def gradient_case(seed: int = 4, n_obj: int = 100_000, k_obs: int = 20, arc: float = 60.0,
+                  neo_frac: float = 0.05, noise_arcsec: float = 0.1) -> GradientCase:
+    """Bodies with a 60-day arc of 20 observations each from a 1 au
+    observer.  The observed RA/Dec are the analytic two-body directions of
+    the generating elements plus Gaussian noise; the start state is the
+    generating state plus N(0, 1e-6 au), N(0, 1e-8 au/day)."""
+    rng = np.random.default_rng(seed)
+    model = PlanetModel.make()
+    eph = make_ephemeris(model, -8.0, int(math.ceil((arc + 24.0) / SEG_DAYS)))
+    x_true, el, _ = make_population(rng, model, n_obj, neo_frac, 0.0)
+    t_obs = np.sort(rng.uniform(0.0, arc, (n_obj, k_obs)), axis=1)
+    obs = circular_observer(model, t_obs)
+    M = el[:, None, 5] + np.sqrt(GM_SUN / el[:, None, 0] ** 3) * t_obs
+    helio = elements_to_state(el[:, None, 0], el[:, None, 1], el[:, None, 2],
+                              el[:, None, 3], el[:, None, 4], M, GM_SUN)
+    pos = helio[..., :3] + model.sun(t_obs)[..., :3]
+    d = ecliptic_to_equatorial(pos - obs)
+    ra = np.arctan2(d[..., 1], d[..., 0]) % (2 * np.pi)
+    dec = np.arcsin(d[..., 2] / np.linalg.norm(d, axis=-1))
+    sig = math.radians(noise_arcsec / 3600.0)
+    dec_o = dec + rng.normal(0, sig, dec.shape)
+    ra_o = (ra + rng.normal(0, sig, ra.shape) / np.cos(dec)) % (2 * np.pi)
+    x0 = x_true.copy()
+    x0[:, :3] += rng.normal(0, 1e-6, (n_obj, 3))
+    x0[:, 3:] += rng.normal(0, 1e-8, (n_obj, 3))
+    return GradientCase(eph, x_true, x0, 0.0, t_obs, obs, np.stack([ra_o, dec_o], -1), arc)
+
+
+@dataclasses.dataclass
+class JobSpec:
+    n_obj: np.ndarray        # [J]
+    span: np.ndarray         # [J] days
+    n_frames: np.ndarray     # [J]
+
+
+def batched_job_specs(seed: int = 5, n_jobs: int = 4096, max_obj: int = 20_000,
+                      max_span: float = 3652.5, max_frames: int = 5000) -> JobSpec:
+    """Log-uniform object counts [1, 20000], spans [1 d, 10 yr] and frame
+    counts [1, 5000]."""
+    rng = np.random.default_rng(seed)
+    lu = lambda lo, hi: np.exp(rng.uniform(math.log(lo), math.log(hi), n_jobs))
+    return JobSpec(np.maximum(1, np.round(lu(1, max_obj))).astype(np.int64),
+                   lu(1.0, max_span),
+                   np.maximum(1, np.round(lu(1, max_frames))).astype(np.int64))
