@@ -1,0 +1,224 @@
+/*
+ * kete_mi.h -- C ABI of the MI355X (gfx950) known-object prediction path.
+ *
+ * The path follows Sect. 2 of "Kete: Predicting Known Minor Bodies in
+ * Images" (arXiv 2509.04666): frames are grouped into time batches; the
+ * small bodies are integrated with the n-body force model (App. A, Eqs.
+ * A.1 and A.3, perturbers read from Chebyshev segments as in Sect. 3.2) to
+ * the mid time of every batch; inside a batch each body is moved by
+ * two-body motion with a light-delay correction to every frame; a body is
+ * in a frame when every inward great-circle normal of the frame has a
+ * positive dot product with its direction (Sect. 3.1).
+ *
+ * Conventions for every entry point:
+ *   - units: au, TDB days, au/day; frame: ecliptic J2000; origin: solar
+ *     system barycentre; all floating point is IEEE binary64;
+ *   - "device" pointers are HIP device memory owned by the caller; "host"
+ *     pointers are ordinary CPU memory owned by the caller; the library
+ *     never frees caller memory and keeps no pointer after returning;
+ *   - scratch memory is the caller's `workspace` (device, 256-byte
+ *     aligned) of at least the size returned by the matching
+ *     *_workspace_size query; the library allocates no device memory;
+ *   - work is enqueued on `stream` (a hipStream_t, NULL = default stream)
+ *     and runs asynchronously unless a function says otherwise;
+ *   - the return value is KETE_OK or a negative KETE_E* code; a text
+ *     description of the last error on the calling thread is available
+ *     from kete_last_error();
+ *   - per-object numerical failures are reported in `status` (KETE_ST_*),
+ *     never as a call error; failed objects get NaN states, are skipped
+ *     by the field-of-view test and get a zero gradient.
+ */
+#ifndef KETE_MI_H
+#define KETE_MI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- codes */
+#define KETE_OK          0
+#define KETE_EINVAL     (-1)   /* null pointer, bad size or unsorted epochs */
+#define KETE_ERANGE     (-2)   /* a time outside the ephemeris coverage */
+#define KETE_ECAPACITY  (-3)   /* output buffer too small; required size reported */
+#define KETE_EDEVICE    (-4)   /* HIP runtime failure */
+#define KETE_EWORKSPACE (-5)   /* workspace smaller than the query result */
+
+#define KETE_ST_OK             0
+#define KETE_ST_NONFINITE      1   /* state became NaN/Inf */
+#define KETE_ST_STEP_UNDERFLOW 2   /* step below h_min (close encounter) */
+#define KETE_ST_MAX_STEPS      3   /* more than max_steps steps */
+#define KETE_ST_KEPLER_NOCONV  4   /* universal-variable solve did not converge */
+
+#define KETE_MAX_BODIES  16        /* perturbers, body 0 = Sun */
+#define KETE_MAX_DEGREE  15        /* Chebyshev degree */
+#define KETE_MAX_SUB     128       /* sub-frames per frame */
+#define KETE_MAX_OBJ     (1 << 25) /* objects per call */
+
+/* ---------------------------------------------------------------- types */
+
+/* Perturber ephemeris as uniform Chebyshev segments (Sect. 3.2: planet
+ * positions are read from precomputed kernels instead of integrated).
+ * Segment k of body b covers [t_start + k seg_days, t_start + (k+1) seg_days]
+ * and gives position_c(t) = sum_n coef[b][k][c][n] T_n(tau) with
+ * tau = 2 (t - t_k)/seg_days - 1; velocities are the derivative series.
+ * A time exactly on a joint uses the later segment; times outside
+ * [t_start, t_start + n_seg seg_days] are KETE_ERANGE. */
+typedef struct {
+    int32_t n_body;          /* 1..KETE_MAX_BODIES, body 0 is the Sun */
+    int32_t n_seg;           /* >= 1 */
+    int32_t degree;          /* 0..KETE_MAX_DEGREE */
+    int32_t reserved;
+    double t_start;          /* TDB day */
+    double seg_days;         /* > 0 */
+    const double *coef;      /* device [n_body][n_seg][3][degree+1] */
+    const double *gm;        /* host [n_body], au^3/day^2 (Eq. A.1 mu_m) */
+    const uint32_t *flags;   /* host [n_body], bit0: add the Eq. A.3 term */
+} kete_ephem_t;
+
+/* Options.  kete_default_opts() fills every field; zero means "default"
+ * for the optional ones. */
+typedef struct {
+    double eps;              /* step control: |b6|/|a| target (1e-9) */
+    double h_init;           /* first trial step in days (1.0) */
+    double h_min;            /* smallest step before KETE_ST_STEP_UNDERFLOW (1e-8) */
+    double h_max;            /* largest step, 0 = unlimited */
+    double c_light;          /* speed of light in au/day (173.144632674...) */
+    double batch_span;       /* frame batch span in days (3.0, Sect. 2) */
+    double cell_chord;       /* FoV sky-grid cell size (chord units; 0 = auto) */
+    double lt_tol;           /* light-time convergence in days (1e-15) */
+    int32_t max_steps;       /* per object per call (2,000,000) */
+    int32_t max_iter;        /* corrector iterations per step (12) */
+    int32_t n_buckets;       /* step-size buckets, 1 = no bucketing (8) */
+    int32_t block;           /* integrator threads per block: 64/128/256 (256) */
+    int32_t rebucket_epochs; /* epochs per integrator launch, 0 = all (16) */
+    int32_t window_segs;     /* Chebyshev segments per staged window (2) */
+    int32_t lt_iter;         /* light-time iterations (10) */
+    int32_t fov_block;       /* FoV threads per block: 64/128/256 (128) */
+} kete_opts_t;
+
+/* Frames (Sect. 3.1): an instantaneous observation at time t from the
+ * observer position obs, made of n_sub convex spherical quadrilaterals
+ * given by their inward unit normals.  Within a quadrilateral normals 0
+ * and 1 bound opposite edges, and so do normals 2 and 3 (every rectangle
+ * or rotated rectangle has this form).  A direction d is inside
+ * sub-frame s when n_{s,i} . d > 0 for all four i.  Each quadrilateral
+ * must be smaller than a hemisphere. */
+typedef struct {
+    int64_t n_frames;
+    int32_t n_sub;           /* 1..KETE_MAX_SUB */
+    int32_t reserved;
+    const double *t;         /* device [n_frames], exposure mid time */
+    const double *obs;       /* device [n_frames][3], barycentric observer */
+    const double *normals;   /* device [n_frames][n_sub][4][3] */
+} kete_frames_t;
+
+/* ---------------------------------------------------------------- calls */
+
+void kete_default_opts(kete_opts_t *opts);
+
+/* Text of the last error raised on the calling thread ("" if none). */
+const char *kete_last_error(void);
+
+/* Library version string. */
+const char *kete_version(void);
+
+/* Frame batching (Sect. 2: batches of frames span at most batch_span
+ * days; each batch is integrated to its mid time).  Host-only.  Sorts
+ * frames by (t, index); a batch starts at its first frame and contains
+ * every following frame within `span` days of that first frame; the batch
+ * epoch is (t_first + t_last)/2.
+ *   t           host [n_frames]
+ *   frame_order host out [n_frames]: frame indices in batch order
+ *   batch_off   host out [n_frames + 1]: batch b is frame_order[off[b]..off[b+1])
+ *   t_ref       host out [n_frames]: batch epochs (first *n_batch used)
+ *   n_batch     host out
+ * Returns KETE_EINVAL for n_frames < 0, null pointers or non-finite t. */
+int kete_make_batches(const double *t, int64_t n_frames, double span,
+                      int32_t *frame_order, int32_t *batch_off, double *t_ref,
+                      int64_t *n_batch);
+
+/* Bytes of workspace needed by kete_propagate_nbody. */
+size_t kete_propagate_workspace_size(int64_t n_obj, int64_t n_out, const kete_opts_t *opts);
+
+/* n-body propagation of massless bodies (Sect. 2, App. A): every object
+ * starts at the common epoch t0 and is integrated through the epochs
+ * t_out[0..n_out) (strictly monotone, all after t0 or all before t0),
+ * landing exactly on each.  Force: Eq. A.1 (attractive) plus Eq. A.3 for
+ * bodies with flags bit0.  Integrator: Gauss-Radau collocation with 8
+ * nodes (the method of App. A.6, predictor removed), step size shared by
+ * the 64 objects of a wavefront, objects grouped into wavefronts by
+ * predicted step size.
+ *   x0      device [n_obj][6]  (x, y, z, vx, vy, vz)
+ *   t_out   host   [n_out]
+ *   x_out   device [n_out][n_obj][6]
+ *   status  device [n_obj]  (KETE_ST_*)
+ *   stats   device [8] int64 or NULL: accumulated counters
+ *           {wave steps, wave iterations, rejections, lane-steps,
+ *            lane-iterations, ephemeris chains, 0, 0}
+ * Errors: KETE_EINVAL, KETE_ERANGE (t0 or an epoch outside the ephemeris),
+ * KETE_EWORKSPACE, KETE_EDEVICE. */
+int kete_propagate_nbody(const kete_ephem_t *eph, const double *x0, double t0, int64_t n_obj,
+                         const double *t_out, int64_t n_out, double *x_out, int32_t *status,
+                         int64_t *stats, const kete_opts_t *opts,
+                         void *workspace, size_t ws_bytes, void *stream);
+
+/* Bytes of workspace needed by kete_fov_check. */
+size_t kete_fov_workspace_size(int64_t n_obj, int64_t n_frames, int64_t n_batch, int32_t n_sub,
+                               int64_t pairs_cap, const kete_opts_t *opts);
+
+/* Field-of-view membership for a batched frame list (Sect. 2 and 3.1).
+ * For batch b with epoch t_ref[b], each object j with status[j] == 0 is
+ * moved from x_epoch[b][j] by heliocentric two-body motion (universal
+ * variables, mu = gm[0]) to the emission time t_f - tau of every frame f of
+ * the batch, tau being the Newtonian light time from the frame's observer
+ * (iterated to lt_tol); (f, s, j) is a pair when all four normals of
+ * sub-frame s have a positive dot product with the direction.  Objects
+ * are binned on the sky so that only bodies that can reach a frame within
+ * the batch are tested exactly.
+ *   x_epoch     device [n_batch][n_obj][6]
+ *   status      device [n_obj] or NULL
+ *   t_ref       device [n_batch]
+ *   batch_off   device [n_batch + 1]
+ *   frame_order device [n_frames]
+ *   pf, ps, po  device [pairs_cap]: frame, sub-frame, object of each pair,
+ *               sorted by (frame, sub-frame, object)
+ *   n_pairs     host out: number of pairs (also when it exceeds pairs_cap)
+ * Synchronizes `stream` once to read the pair count.  Returns
+ * KETE_ECAPACITY (with *n_pairs set, outputs unspecified) when
+ * pairs_cap is too small. */
+int kete_fov_check(const kete_ephem_t *eph, const double *x_epoch, const int32_t *status,
+                   int64_t n_obj, int64_t n_batch, const double *t_ref, const int32_t *batch_off,
+                   const int32_t *frame_order, const kete_frames_t *frames, const kete_opts_t *opts,
+                   int32_t *pf, int32_t *ps, int32_t *po, int64_t pairs_cap, int64_t *n_pairs,
+                   void *workspace, size_t ws_bytes, void *stream);
+
+/* Counters of the last kete_fov_check on the calling thread: out[0]
+ * candidate frames visited, out[1] exact light-time tests, out[2] objects
+ * handled by the brute-force path, out[3] reserved. */
+void kete_fov_last_stats(int64_t out[4]);
+
+/* Light-time corrected directions (the per-pair step of kete_fov_check,
+ * exposed for checking): for every object j and query q, the direction
+ * d = x_e - obs[q] of object j (state x_ref[j] at t_ref) at the emission
+ * time t_obs[q] - tau.
+ *   x_ref  device [n_obj][6]; t_obs device [n_q]; obs device [n_q][3]
+ *   d      device out [n_q][n_obj][3]; tau device out [n_q][n_obj] or NULL */
+int kete_lighttime_directions(const kete_ephem_t *eph, const double *x_ref, double t_ref, int64_t n_obj,
+                              const double *t_obs, const double *obs, int64_t n_q,
+                              double *d, double *tau, const kete_opts_t *opts, void *stream);
+
+/* Chebyshev positions and velocities (the ephemeris evaluator on its
+ * own, for checking): out[q][b][6] for every body b at times t[q].
+ *   t device [n_q]; out device [n_q][n_body][6].
+ * Returns KETE_ERANGE when a time is outside the coverage (checked on
+ * the host copy t_host, which must hold the same values). */
+int kete_ephem_eval(const kete_ephem_t *eph, const double *t, const double *t_host, int64_t n_q,
+                    double *out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KETE_MI_H */

@@ -1,0 +1,197 @@
+"""Python entry points over the C ABI.  Torch supplies device memory and
+streams; every step of the path runs in the library's HIP kernels."""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import EphemT, FramesT, OptsT, check, lib
+
+DEV = "cuda"
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def default_opts(**kw) -> OptsT:
+    o = OptsT()
+    lib().kete_default_opts(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+class DeviceEphemeris:
+    """A Chebyshev ephemeris with its coefficient table in device memory."""
+
+    def __init__(self, coef, gm, flags, t_start: float, seg_days: float, device=DEV):
+        self.coef = torch.as_tensor(np.ascontiguousarray(coef), dtype=torch.float64).to(device).contiguous()
+        self.gm = np.ascontiguousarray(gm, dtype=np.float64)
+        self.flags = np.ascontiguousarray(flags, dtype=np.uint32)
+        self.t_start = float(t_start)
+        self.seg_days = float(seg_days)
+        nb, ns, three, m = self.coef.shape
+        assert three == 3
+        self.c = EphemT(nb, ns, m - 1, 0, self.t_start, self.seg_days, self.coef.data_ptr(),
+                        self.gm.ctypes.data_as(C.POINTER(C.c_double)),
+                        self.flags.ctypes.data_as(C.POINTER(C.c_uint32)))
+
+    @staticmethod
+    def from_synth(e, device=DEV) -> "DeviceEphemeris":
+        return DeviceEphemeris(e.coef, e.gm, e.flags, e.t_start, e.seg_days, device)
+
+    @property
+    def n_body(self): return self.coef.shape[0]
+
+    @property
+    def t_end(self): return self.t_start + self.coef.shape[1] * self.seg_days
+
+
+def _workspace(nbytes: int, device=DEV) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def propagate(eph: DeviceEphemeris, x0: torch.Tensor, t0: float, t_out: Sequence[float],
+              opts: Optional[OptsT] = None, stats: bool = False, workspace: Optional[torch.Tensor] = None):
+    """States at every epoch: (x_out [E, N, 6], status [N] int32[, stats [8] int64])."""
+    opts = opts or default_opts()
+    x0 = x0.contiguous()
+    assert x0.dtype == torch.float64 and x0.is_cuda and x0.dim() == 2 and x0.shape[1] == 6
+    t_out = np.ascontiguousarray(np.atleast_1d(np.asarray(t_out, dtype=np.float64)))
+    n, E = x0.shape[0], t_out.size
+    x_out = torch.empty((E, n, 6), dtype=torch.float64, device=x0.device)
+    status = torch.empty(n, dtype=torch.int32, device=x0.device)
+    st = torch.zeros(8, dtype=torch.int64, device=x0.device) if stats else None
+    need = lib().kete_propagate_workspace_size(n, E, C.byref(opts))
+    ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, x0.device)
+    check(lib().kete_propagate_nbody(C.byref(eph.c), _ptr(x0), float(t0), n,
+                                     t_out.ctypes.data_as(C.c_void_p), E, _ptr(x_out), _ptr(status), _ptr(st),
+                                     C.byref(opts), _ptr(ws), ws.numel(), _stream()))
+    return (x_out, status, st) if stats else (x_out, status)
+
+
+def make_batches(t: np.ndarray, span: float = 3.0):
+    """(frame_order int32 [F], batch_off int32 [B+1], t_ref float64 [B]) on the host."""
+    t = np.ascontiguousarray(t, dtype=np.float64)
+    F = t.size
+    order = np.empty(F, np.int32)
+    off = np.empty(F + 1, np.int32)
+    t_ref = np.empty(max(F, 1), np.float64)
+    nb = C.c_int64(0)
+    check(lib().kete_make_batches(t.ctypes.data_as(C.c_void_p), F, float(span), order.ctypes.data_as(C.c_void_p),
+                                  off.ctypes.data_as(C.c_void_p), t_ref.ctypes.data_as(C.c_void_p), C.byref(nb)))
+    B = nb.value
+    return order, off[:B + 1].copy(), t_ref[:B].copy()
+
+
+@dataclasses.dataclass
+class DeviceFrames:
+    t: torch.Tensor          # [F]
+    obs: torch.Tensor        # [F, 3]
+    normals: torch.Tensor    # [F, S, 4, 3]
+
+    @staticmethod
+    def from_synth(fr, device=DEV) -> "DeviceFrames":
+        f = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64).to(device).contiguous()
+        return DeviceFrames(f(fr.t), f(fr.obs), f(fr.normals))
+
+    def c(self) -> FramesT:
+        return FramesT(self.t.shape[0], self.normals.shape[1], 0, self.t.data_ptr(), self.obs.data_ptr(),
+                       self.normals.data_ptr())
+
+
+@dataclasses.dataclass
+class Batches:
+    frame_order: torch.Tensor   # device int32 [F]
+    batch_off: torch.Tensor     # device int32 [B+1]
+    t_ref: torch.Tensor         # device float64 [B]
+    t_ref_host: np.ndarray
+
+    @staticmethod
+    def from_host(order, off, t_ref, device=DEV) -> "Batches":
+        return Batches(torch.as_tensor(order).to(device), torch.as_tensor(off).to(device),
+                       torch.as_tensor(t_ref).to(device), np.asarray(t_ref))
+
+
+def fov_check(eph: DeviceEphemeris, x_epoch: torch.Tensor, batches: Batches, frames: DeviceFrames,
+              status: Optional[torch.Tensor] = None, opts: Optional[OptsT] = None, pairs_cap: Optional[int] = None,
+              workspace: Optional[torch.Tensor] = None, return_stats: bool = False):
+    """Pairs sorted by (frame, sub-frame, object): (pf, ps, po) int32 tensors."""
+    opts = opts or default_opts()
+    x_epoch = x_epoch.contiguous()
+    B, N = x_epoch.shape[0], x_epoch.shape[1]
+    F, S = frames.t.shape[0], frames.normals.shape[1]
+    cap = int(pairs_cap) if pairs_cap is not None else max(1 << 16, 4 * F)
+    fc = frames.c()
+    for attempt in range(2):
+        need = lib().kete_fov_workspace_size(N, F, B, S, cap, C.byref(opts))
+        if need == 0:
+            check(_lib.KETE_EINVAL)
+        ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, x_epoch.device)
+        pf = torch.empty(max(cap, 1), dtype=torch.int32, device=x_epoch.device)
+        ps = torch.empty_like(pf)
+        po = torch.empty_like(pf)
+        n_pairs = C.c_int64(0)
+        rc = lib().kete_fov_check(C.byref(eph.c), _ptr(x_epoch), _ptr(status), N, B, _ptr(batches.t_ref),
+                                  _ptr(batches.batch_off), _ptr(batches.frame_order), C.byref(fc), C.byref(opts),
+                                  _ptr(pf), _ptr(ps), _ptr(po), cap, C.byref(n_pairs), _ptr(ws), ws.numel(),
+                                  _stream())
+        if rc == _lib.KETE_ECAPACITY and pairs_cap is None and attempt == 0:
+            cap = int(n_pairs.value)
+            continue
+        check(rc)
+        break
+    n = n_pairs.value
+    out = (pf[:n], ps[:n], po[:n])
+    if return_stats:
+        st = np.zeros(4, np.int64)
+        lib().kete_fov_last_stats(st.ctypes.data_as(C.c_void_p))
+        return out + (st,)
+    return out
+
+
+def lighttime_directions(eph: DeviceEphemeris, x_ref: torch.Tensor, t_ref: float, t_obs: torch.Tensor,
+                         obs: torch.Tensor, opts: Optional[OptsT] = None):
+    """(d [Q, N, 3], tau [Q, N]) for states x_ref [N, 6] at t_ref."""
+    opts = opts or default_opts()
+    N, Q = x_ref.shape[0], t_obs.shape[0]
+    d = torch.empty((Q, N, 3), dtype=torch.float64, device=x_ref.device)
+    tau = torch.empty((Q, N), dtype=torch.float64, device=x_ref.device)
+    check(lib().kete_lighttime_directions(C.byref(eph.c), _ptr(x_ref.contiguous()), float(t_ref), N,
+                                          _ptr(t_obs.contiguous()), _ptr(obs.contiguous()), Q, _ptr(d), _ptr(tau),
+                                          C.byref(opts), _stream()))
+    return d, tau
+
+
+def ephem_eval(eph: DeviceEphemeris, t: np.ndarray) -> torch.Tensor:
+    """Positions and velocities [Q, n_body, 6] of every perturber at times t."""
+    t = np.ascontiguousarray(np.atleast_1d(t), dtype=np.float64)
+    td = torch.as_tensor(t).to(eph.coef.device)
+    out = torch.empty((t.size, eph.n_body, 6), dtype=torch.float64, device=eph.coef.device)
+    check(lib().kete_ephem_eval(C.byref(eph.c), _ptr(td), t.ctypes.data_as(C.c_void_p), t.size, _ptr(out),
+                                _stream()))
+    return out
+
+
+def predict(eph: DeviceEphemeris, x0: torch.Tensor, t0: float, frames: DeviceFrames, frame_t_host: np.ndarray,
+            opts: Optional[OptsT] = None, pairs_cap: Optional[int] = None):
+    """The whole path: batch the frames, integrate to every batch epoch,
+    test membership.  Returns (pf, ps, po, x_epoch, status, batches)."""
+    opts = opts or default_opts()
+    order, off, t_ref = make_batches(frame_t_host, opts.batch_span)
+    batches = Batches.from_host(order, off, t_ref, x0.device)
+    x_epoch, status = propagate(eph, x0, t0, t_ref, opts)
+    pf, ps, po = fov_check(eph, x_epoch, batches, frames, status, opts, pairs_cap)
+    return pf, ps, po, x_epoch, status, batches

@@ -1,0 +1,584 @@
+// C ABI of the gfx950 known-object prediction path: argument checks,
+// workspace layout, launch planning.  Every numerical step runs in the
+// HIP kernels of this library.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "kete_fov.hpp"
+#include "kete_internal.hpp"
+#include "kete_mi.h"
+
+namespace kete {
+hipError_t launch_hpref_init(const double* x0, double* h_pref, int n, double mu, hipStream_t s);
+size_t bucket_scratch_ints(int64_t n_obj, int n_buckets);
+}  // namespace kete
+
+using namespace kete;
+
+namespace {
+
+thread_local std::string g_err;
+thread_local unsigned long long g_fov_stats[4] = {0, 0, 0, 0};
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                      \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess) return fail(KETE_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr double kC = 299792.458 * 86400.0 / 149597870.7;
+
+// ---------------------------------------------------------------- Radau
+typedef long double ld;
+
+ld legendre(int n, ld x, ld* dp) {
+    ld p0 = 1, p1 = x, d0 = 0, d1 = 1;
+    if (n == 0) { if (dp) *dp = 0; return 1; }
+    for (int k = 1; k < n; ++k) {
+        ld p2 = ((2 * k + 1) * x * p1 - k * p0) / (k + 1);
+        ld d2 = d0 + (2 * k + 1) * p1;            // P'_{k+1} = P'_{k-1} + (2k+1) P_k
+        p0 = p1; p1 = p2; d0 = d1; d1 = d2;
+    }
+    if (dp) *dp = d1;
+    return p1;
+}
+
+RadauConst build_radau() {
+    RadauConst rc;
+    std::memset(&rc, 0, sizeof(rc));
+    // interior nodes: roots of P7 + P8 other than -1, found by scan + Newton
+    std::vector<ld> xr;
+    const int NS = 4096;
+    auto f = [](ld x, ld* d) { ld d7, d8; ld v = legendre(7, x, &d7) + legendre(8, x, &d8); *d = d7 + d8; return v; };
+    ld xa = -1.0L + 1e-6L, dd;
+    ld fa = f(xa, &dd);
+    for (int i = 1; i <= NS; ++i) {
+        ld xb = -1.0L + 1e-6L + (2.0L - 1e-6L) * i / NS;
+        ld fb = f(xb, &dd);
+        if ((fa < 0) != (fb < 0)) {
+            ld lo = xa, hi = xb, x = 0.5L * (xa + xb);
+            for (int it = 0; it < 100; ++it) {
+                ld d;
+                ld v = f(x, &d);
+                if ((v < 0) == (fa < 0)) lo = x; else hi = x;
+                ld xn = x - v / d;
+                if (!(xn > lo && xn < hi)) xn = 0.5L * (lo + hi);
+                if (std::fabs(xn - x) < 1e-19L) { x = xn; break; }
+                x = xn;
+            }
+            xr.push_back(x);
+        }
+        xa = xb; fa = fb;
+    }
+    ld S[9];
+    S[0] = 0;
+    for (int i = 0; i < 7; ++i) S[i + 1] = 0.5L * (xr[i] + 1.0L);
+    S[8] = 1;
+    // 8-point Gauss-Legendre rule (exact to degree 15) on [-1, 1]
+    ld gx[8], gw[8];
+    for (int i = 0; i < 8; ++i) {
+        ld x = std::cos(3.14159265358979323846264338327950L * (i + 0.75L) / 8.5L);
+        for (int it = 0; it < 100; ++it) {
+            ld d;
+            ld v = legendre(8, x, &d);
+            ld dx = v / d;
+            x -= dx;
+            if (std::fabs(dx) < 1e-20L) break;
+        }
+        ld d;
+        legendre(8, x, &d);
+        gx[i] = x;
+        gw[i] = 2.0L / ((1 - x * x) * d * d);
+    }
+    auto ell = [&](int m, ld s) {             // Lagrange basis on S[0..7]
+        ld v = 1;
+        for (int k = 0; k < 8; ++k) if (k != m) v *= (s - S[k]) / (S[m] - S[k]);
+        return v;
+    };
+    for (int n = 0; n < 9; ++n) {
+        const ld s = S[n];
+        rc.s[n] = (double)s;
+        rc.half_s2[n] = (double)(0.5L * s * s);
+        for (int m = 1; m < 8; ++m) {
+            ld a = 0, b = 0;
+            for (int q = 0; q < 8; ++q) {
+                ld sig = 0.5L * s * (gx[q] + 1);
+                ld w = 0.5L * s * gw[q];
+                ld l = ell(m, sig);
+                a += w * (s - sig) * l;
+                b += w * l;
+            }
+            rc.A[n][m - 1] = (double)a;
+            rc.B[n][m - 1] = (double)b;
+        }
+    }
+    for (int m = 1; m < 8; ++m) {
+        ld p = 1;
+        for (int k = 0; k < 8; ++k) if (k != m) p *= (S[m] - S[k]);
+        rc.E6[m - 1] = (double)(1.0L / p);
+    }
+    return rc;
+}
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Carver {
+    char* base;
+    size_t off = 0;
+    template <class T>
+    T* take(size_t count) {
+        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += align_up(count * sizeof(T));
+        return p;
+    }
+};
+
+int ephem_args(const kete_ephem_t* eph, double c_light, EphemArgs& E) {
+    if (!eph || !eph->coef || !eph->gm || !eph->flags) return fail(KETE_EINVAL, "ephemeris pointers must be non-null");
+    if (eph->n_body < 1 || eph->n_body > KETE_MAX_BODIES) return fail(KETE_EINVAL, "n_body %d outside 1..%d", eph->n_body, KETE_MAX_BODIES);
+    if (eph->n_seg < 1) return fail(KETE_EINVAL, "n_seg must be >= 1");
+    if (eph->degree < 0 || eph->degree > KETE_MAX_DEGREE) return fail(KETE_EINVAL, "degree %d outside 0..%d", eph->degree, KETE_MAX_DEGREE);
+    if (!(eph->seg_days > 0) || !std::isfinite(eph->t_start)) return fail(KETE_EINVAL, "bad segment timing");
+    std::memset(&E, 0, sizeof(E));
+    E.coef = eph->coef;
+    E.n_body = eph->n_body;
+    E.n_seg = eph->n_seg;
+    E.deg1 = eph->degree + 1;
+    E.t_start = eph->t_start;
+    E.seg_days = eph->seg_days;
+    E.inv_seg = 1.0 / eph->seg_days;
+    const double c2 = c_light * c_light;
+    for (int b = 0; b < eph->n_body; ++b) {
+        if (!(eph->gm[b] >= 0) || !std::isfinite(eph->gm[b])) return fail(KETE_EINVAL, "gm[%d] invalid", b);
+        E.gm[b] = eph->gm[b];
+        E.kgr[b] = (eph->flags[b] & 1u) ? eph->gm[b] / c2 : 0.0;
+        if (E.kgr[b] != 0.0) E.has_gr = 1;
+    }
+    if (!(eph->gm[0] > 0)) return fail(KETE_EINVAL, "gm[0] (Sun) must be positive");
+    return KETE_OK;
+}
+
+double t_end(const kete_ephem_t* e) { return e->t_start + e->n_seg * e->seg_days; }
+
+int seg_of(const kete_ephem_t* e, double t) {
+    int k = (int)std::floor((t - e->t_start) / e->seg_days);
+    return std::min(std::max(k, 0), e->n_seg - 1);
+}
+
+// Windows between t0 and each epoch: every epoch ends a window, and a
+// window never spans more than `wsegs` segment lengths.
+std::vector<Window> plan_windows(const kete_ephem_t* e, double t0, const double* t_out, int64_t n_out, int wsegs,
+                                 std::vector<int>& epoch_end_win) {
+    std::vector<Window> w;
+    epoch_end_win.assign(n_out, -1);
+    double t = t0;
+    for (int64_t k = 0; k < n_out; ++k) {
+        const double target = t_out[k];
+        const bool fwd = target > t;
+        while (t != target) {
+            double tb;
+            if (fwd) {
+                const double kk = std::floor((t - e->t_start) / e->seg_days);
+                const double limit = e->t_start + (kk + wsegs) * e->seg_days;
+                tb = (limit < target && limit > t) ? limit : target;
+            } else {
+                const double kk = std::ceil((t - e->t_start) / e->seg_days) - 1.0;
+                const double limit = e->t_start + (kk - wsegs + 1) * e->seg_days;
+                tb = (limit > target && limit < t) ? limit : target;
+            }
+            Window W;
+            W.t_a = t;
+            W.t_b = tb;
+            W.seg_lo = seg_of(e, std::min(t, tb));
+            W.seg_hi = seg_of(e, std::max(t, tb));
+            W.out = (tb == target) ? (int32_t)k : -1;
+            W.pad = 0;
+            w.push_back(W);
+            t = tb;
+        }
+        if (w.empty() || w.back().out != (int32_t)k) {
+            // epoch equal to the current time: an empty window that only writes output
+            Window W{t, t, seg_of(e, t), seg_of(e, t), (int32_t)k, 0};
+            w.push_back(W);
+        }
+        epoch_end_win[k] = (int)w.size() - 1;
+    }
+    return w;
+}
+
+}  // namespace
+
+namespace kete {
+const RadauConst& radau_const() {
+    static RadauConst rc = build_radau();
+    return rc;
+}
+}  // namespace kete
+
+extern "C" {
+
+const char* kete_last_error(void) { return g_err.c_str(); }
+
+const char* kete_version(void) { return "kete-mi355x 0.1.0 (gfx950)"; }
+
+void kete_default_opts(kete_opts_t* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->eps = 1e-9;
+    o->h_init = 1.0;
+    o->h_min = 1e-8;
+    o->h_max = 0.0;
+    o->c_light = kC;
+    o->batch_span = 3.0;
+    o->cell_chord = 0.0;
+    o->lt_tol = 1e-15;
+    o->max_steps = 2000000;
+    o->max_iter = 12;
+    o->n_buckets = 8;
+    o->block = 256;
+    o->rebucket_epochs = 16;
+    o->window_segs = 2;
+    o->lt_iter = 10;
+    o->fov_block = 128;
+}
+
+int kete_make_batches(const double* t, int64_t n_frames, double span, int32_t* frame_order, int32_t* batch_off,
+                      double* t_ref, int64_t* n_batch) {
+    if (n_frames < 0 || n_frames > INT32_MAX) return fail(KETE_EINVAL, "n_frames out of range");
+    if (!n_batch || !batch_off || (n_frames > 0 && (!t || !frame_order || !t_ref)))
+        return fail(KETE_EINVAL, "null pointer");
+    if (!(span >= 0) || !std::isfinite(span)) return fail(KETE_EINVAL, "span must be finite and >= 0");
+    for (int64_t i = 0; i < n_frames; ++i)
+        if (!std::isfinite(t[i])) return fail(KETE_EINVAL, "t[%lld] is not finite", (long long)i);
+    std::vector<int32_t> idx(n_frames);
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) { return t[a] < t[b]; });
+    int64_t nb = 0;
+    batch_off[0] = 0;
+    int64_t i = 0;
+    while (i < n_frames) {
+        const double first = t[idx[i]];
+        int64_t j = i;
+        while (j + 1 < n_frames && t[idx[j + 1]] - first <= span) ++j;
+        t_ref[nb] = 0.5 * (first + t[idx[j]]);
+        batch_off[++nb] = (int32_t)(j + 1);
+        i = j + 1;
+    }
+    std::copy(idx.begin(), idx.end(), frame_order);
+    *n_batch = nb;
+    return KETE_OK;
+}
+
+size_t kete_propagate_workspace_size(int64_t n_obj, int64_t n_out, const kete_opts_t* opts) {
+    kete_opts_t d;
+    if (!opts) { kete_default_opts(&d); opts = &d; }
+    const int nbk = std::max(1, opts->n_buckets);
+    const int wsegs = std::max(1, opts->window_segs);
+    // windows: epochs plus at most one extra per wsegs segments of span;
+    // the span is unknown here, so reserve generously and check at call time
+    const int64_t max_win = 4 * (n_out + 1) + 65536;
+    (void)wsegs;
+    Carver c{nullptr};
+    c.take<double>((size_t)n_obj * 6);
+    c.take<double>((size_t)n_obj);
+    c.take<int32_t>((size_t)n_obj);
+    c.take<Window>((size_t)max_win);
+    c.take<int32_t>(bucket_scratch_ints(n_obj, nbk));
+    return c.off;
+}
+
+int kete_propagate_nbody(const kete_ephem_t* eph, const double* x0, double t0, int64_t n_obj, const double* t_out,
+                         int64_t n_out, double* x_out, int32_t* status, int64_t* stats, const kete_opts_t* opts,
+                         void* workspace, size_t ws_bytes, void* stream) {
+    kete_opts_t d;
+    if (!opts) { kete_default_opts(&d); opts = &d; }
+    g_err.clear();
+    EphemArgs E;
+    int rc = ephem_args(eph, opts->c_light > 0 ? opts->c_light : kC, E);
+    if (rc) return rc;
+    if (n_obj < 0 || n_obj > KETE_MAX_OBJ) return fail(KETE_EINVAL, "n_obj %lld outside 0..%d", (long long)n_obj, KETE_MAX_OBJ);
+    if (n_out < 0) return fail(KETE_EINVAL, "n_out < 0");
+    if (n_obj == 0 || n_out == 0) return KETE_OK;
+    if (!x0 || !t_out || !x_out || !status) return fail(KETE_EINVAL, "null pointer");
+    if (!std::isfinite(t0)) return fail(KETE_EINVAL, "t0 not finite");
+    const double tlo = eph->t_start, thi = t_end(eph);
+    if (!(t0 >= tlo && t0 <= thi)) return fail(KETE_ERANGE, "t0 %.9g outside ephemeris [%.9g, %.9g]", t0, tlo, thi);
+    const bool fwd = t_out[0] > t0;
+    double prev = t0;
+    for (int64_t k = 0; k < n_out; ++k) {
+        if (!std::isfinite(t_out[k])) return fail(KETE_EINVAL, "t_out[%lld] not finite", (long long)k);
+        if (!(t_out[k] >= tlo && t_out[k] <= thi))
+            return fail(KETE_ERANGE, "t_out[%lld] = %.9g outside ephemeris [%.9g, %.9g]", (long long)k, t_out[k], tlo, thi);
+        if (k > 0 && (fwd ? !(t_out[k] > prev) : !(t_out[k] < prev)))
+            return fail(KETE_EINVAL, "t_out must be strictly monotone and on one side of t0");
+        if (k == 0 && t_out[0] == t0 && n_out > 1) {
+            // allowed: the first epoch may equal t0
+        }
+        prev = t_out[k];
+    }
+    if (opts->block != 64 && opts->block != 128 && opts->block != 256)
+        return fail(KETE_EINVAL, "block must be 64, 128 or 256");
+    if (!(opts->eps > 0) || !(opts->h_init > 0) || !(opts->h_min > 0) || opts->max_iter < 1 || opts->max_steps < 1)
+        return fail(KETE_EINVAL, "eps, h_init, h_min, max_iter and max_steps must be positive");
+    const int nbk = std::min(std::max(1, opts->n_buckets), 32);
+    const int wsegs = std::max(1, opts->window_segs);
+
+    std::vector<int> epoch_win;
+    std::vector<Window> win = plan_windows(eph, t0, t_out, n_out, wsegs, epoch_win);
+    const int64_t max_win = 4 * (n_out + 1) + 65536;
+    if ((int64_t)win.size() > max_win) return fail(KETE_EINVAL, "too many integration windows (%zu)", win.size());
+
+    if (!workspace) return fail(KETE_EWORKSPACE, "workspace is null");
+    const size_t need = kete_propagate_workspace_size(n_obj, n_out, opts);
+    if (ws_bytes < need) return fail(KETE_EWORKSPACE, "workspace %zu bytes < %zu required", ws_bytes, need);
+    Carver c{(char*)workspace};
+    double* state = c.take<double>((size_t)n_obj * 6);
+    double* h_pref = c.take<double>((size_t)n_obj);
+    int32_t* perm = c.take<int32_t>((size_t)n_obj);
+    Window* dwin = c.take<Window>((size_t)max_win);
+    int32_t* bscratch = c.take<int32_t>(bucket_scratch_ints(n_obj, nbk));
+
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(hipMemcpyAsync(dwin, win.data(), win.size() * sizeof(Window), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipMemcpyAsync(state, x0, (size_t)n_obj * 6 * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemsetAsync(status, 0, (size_t)n_obj * sizeof(int32_t), s));
+    HIPCHK(launch_hpref_init(x0, h_pref, (int)n_obj, E.gm[0], s));
+
+    NbodyParams P;
+    std::memset(&P, 0, sizeof(P));
+    P.eph = E;
+    P.rc = radau_const();
+    P.state = state;
+    P.h_pref = h_pref;
+    P.status = status;
+    P.x_out = x_out;
+    P.stats = (unsigned long long*)stats;
+    P.n_obj = (int32_t)n_obj;
+    P.max_iter = opts->max_iter;
+    P.max_steps = opts->max_steps;
+    P.max_win_segs = wsegs + 1;
+    P.eps = opts->eps;
+    P.h_min = opts->h_min;
+    P.h_max = opts->h_max;
+    P.h_init = opts->h_init;
+    P.safety = 0.25;
+
+    const int64_t R = opts->rebucket_epochs > 0 ? opts->rebucket_epochs : n_out;
+    int first = 0;
+    for (int64_t e0 = 0; e0 < n_out; e0 += R) {
+        const int64_t e1 = std::min(n_out, e0 + R) - 1;
+        const int last = epoch_win[e1];
+        if (nbk > 1) {
+            BucketParams B;
+            B.h_pref = h_pref;
+            B.status = status;
+            B.perm = perm;
+            B.counts = bscratch;
+            B.n_obj = (int32_t)n_obj;
+            B.n_buckets = nbk;
+            B.h_ref = 1.0 / 64.0;
+            HIPCHK(launch_bucket(B, s));
+            P.perm = perm;
+        } else {
+            P.perm = nullptr;
+        }
+        P.win = dwin + first;
+        P.n_win = last - first + 1;
+        P.first_launch = (e0 == 0);
+        HIPCHK(launch_nbody(P, opts->block, s));
+        first = last + 1;
+    }
+    return KETE_OK;
+}
+
+static int grid_dims(const kete_opts_t* o, int64_t n_batch, int& G, double& L) {
+    L = o->cell_chord > 0 ? o->cell_chord : 0.08;
+    G = (int)std::ceil(2.0 / L);
+    if (G < 1) G = 1;
+    if (G > 128) return fail(KETE_EINVAL, "cell_chord too small (grid > 128 cells per axis)");
+    if ((double)n_batch * G * G * G > 2.0e9) return fail(KETE_EINVAL, "sky grid too large for %lld batches", (long long)n_batch);
+    return KETE_OK;
+}
+
+size_t kete_fov_workspace_size(int64_t n_obj, int64_t n_frames, int64_t n_batch, int32_t n_sub, int64_t pairs_cap,
+                               const kete_opts_t* opts) {
+    kete_opts_t d;
+    if (!opts) { kete_default_opts(&d); opts = &d; }
+    (void)n_obj; (void)n_sub;
+    int G; double L;
+    if (grid_dims(opts, n_batch, G, L)) return 0;
+    const int64_t nkeys = n_batch * (int64_t)G * G * G;
+    Carver c{nullptr};
+    c.take<double>((size_t)n_frames * 8);
+    c.take<double>((size_t)n_batch * kBatchStride);
+    c.take<int32_t>((size_t)n_frames);
+    c.take<int32_t>((size_t)nkeys + 1);
+    c.take<int32_t>((size_t)nkeys + 1);
+    c.take<int32_t>((size_t)n_frames);
+    c.take<unsigned long long>((size_t)std::max<int64_t>(pairs_cap, 1));
+    c.take<unsigned long long>(8);
+    c.take<int32_t>((size_t)n_frames + 1);
+    c.take<int32_t>((size_t)n_frames + 1);
+    c.take<unsigned long long>((size_t)std::max<int64_t>(pairs_cap, 1));
+    c.take<char>(std::max(scan_scratch_bytes(nkeys), scan_scratch_bytes(n_frames)));
+    return c.off;
+}
+
+int kete_fov_check(const kete_ephem_t* eph, const double* x_epoch, const int32_t* status, int64_t n_obj,
+                   int64_t n_batch, const double* t_ref, const int32_t* batch_off, const int32_t* frame_order,
+                   const kete_frames_t* frames, const kete_opts_t* opts, int32_t* pf, int32_t* ps, int32_t* po,
+                   int64_t pairs_cap, int64_t* n_pairs, void* workspace, size_t ws_bytes, void* stream) {
+    kete_opts_t d;
+    if (!opts) { kete_default_opts(&d); opts = &d; }
+    g_err.clear();
+    EphemArgs E;
+    const double cl = opts->c_light > 0 ? opts->c_light : kC;
+    int rc = ephem_args(eph, cl, E);
+    if (rc) return rc;
+    if (!n_pairs) return fail(KETE_EINVAL, "n_pairs is null");
+    *n_pairs = 0;
+    if (!frames) return fail(KETE_EINVAL, "frames is null");
+    if (n_obj < 0 || n_obj > KETE_MAX_OBJ) return fail(KETE_EINVAL, "n_obj %lld outside 0..%d", (long long)n_obj, KETE_MAX_OBJ);
+    if (n_batch < 0 || frames->n_frames < 0 || frames->n_frames > INT32_MAX) return fail(KETE_EINVAL, "bad sizes");
+    if (frames->n_sub < 1 || frames->n_sub > KETE_MAX_SUB) return fail(KETE_EINVAL, "n_sub %d outside 1..%d", frames->n_sub, KETE_MAX_SUB);
+    if (pairs_cap < 0) return fail(KETE_EINVAL, "pairs_cap < 0");
+    if (n_obj == 0 || n_batch == 0 || frames->n_frames == 0) { std::memset(g_fov_stats, 0, sizeof(g_fov_stats)); return KETE_OK; }
+    if (!x_epoch || !t_ref || !batch_off || !frame_order || !frames->t || !frames->obs || !frames->normals)
+        return fail(KETE_EINVAL, "null pointer");
+    if (pairs_cap > 0 && (!pf || !ps || !po)) return fail(KETE_EINVAL, "null output pointer");
+    if (opts->fov_block != 64 && opts->fov_block != 128 && opts->fov_block != 256)
+        return fail(KETE_EINVAL, "fov_block must be 64, 128 or 256");
+    int G; double L;
+    if ((rc = grid_dims(opts, n_batch, G, L))) return rc;
+    const int64_t nkeys = n_batch * (int64_t)G * G * G;
+    const int64_t F = frames->n_frames;
+    if (!workspace) return fail(KETE_EWORKSPACE, "workspace is null");
+    const size_t need = kete_fov_workspace_size(n_obj, F, n_batch, frames->n_sub, pairs_cap, opts);
+    if (ws_bytes < need) return fail(KETE_EWORKSPACE, "workspace %zu bytes < %zu required", ws_bytes, need);
+
+    Carver c{(char*)workspace};
+    FovParams P;
+    std::memset(&P, 0, sizeof(P));
+    P.fcap = c.take<double>((size_t)F * 8);
+    P.btab = c.take<double>((size_t)n_batch * kBatchStride);
+    int32_t* qkey = c.take<int32_t>((size_t)F);
+    int32_t* cnt = c.take<int32_t>((size_t)nkeys + 1);
+    P.cell_start = c.take<int32_t>((size_t)nkeys + 1);
+    P.cell_frames = c.take<int32_t>((size_t)F);
+    P.pairs = c.take<unsigned long long>((size_t)std::max<int64_t>(pairs_cap, 1));
+    unsigned long long* counters = c.take<unsigned long long>(8);
+    int32_t* fcnt = c.take<int32_t>((size_t)F + 1);
+    int32_t* fstart = c.take<int32_t>((size_t)F + 1);
+    unsigned long long* sorted = c.take<unsigned long long>((size_t)std::max<int64_t>(pairs_cap, 1));
+    void* scan_scratch = c.take<char>(std::max(scan_scratch_bytes(nkeys), scan_scratch_bytes(F)));
+
+    P.eph = E;
+    P.x_epoch = x_epoch;
+    P.status = status;
+    P.n_obj = (int32_t)n_obj;
+    P.n_batch = (int32_t)n_batch;
+    P.n_frames = F;
+    P.t_ref = t_ref;
+    P.batch_off = batch_off;
+    P.frame_order = frame_order;
+    P.ft = frames->t;
+    P.fobs = frames->obs;
+    P.normals = frames->normals;
+    P.n_sub = frames->n_sub;
+    P.G = G;
+    P.inv_L = 1.0 / L;
+    P.n_pairs = counters;
+    P.stats = counters + 1;
+    P.cap = pairs_cap;
+    P.mu = E.gm[0];
+    P.smu = std::sqrt(E.gm[0]);
+    P.c_light = cl;
+    P.lt_tol = opts->lt_tol > 0 ? opts->lt_tol : 1e-15;
+    P.lt_iter = opts->lt_iter > 0 ? opts->lt_iter : 10;
+    P.max_cells = 64;
+    P.sin_overflow = 0.5;
+
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(hipMemsetAsync(counters, 0, 8 * sizeof(unsigned long long), s));
+    HIPCHK(fov_prepare(P, qkey, cnt, cnt, nkeys, scan_scratch, s));
+    HIPCHK(fov_candidates(P, opts->fov_block, s));
+    unsigned long long host_counters[8];
+    HIPCHK(hipMemcpyAsync(host_counters, counters, sizeof(host_counters), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int i = 0; i < 4; ++i) g_fov_stats[i] = host_counters[1 + i];
+    const int64_t np = (int64_t)host_counters[0];
+    *n_pairs = np;
+    if (np > pairs_cap) return fail(KETE_ECAPACITY, "%lld pairs exceed pairs_cap %lld", (long long)np, (long long)pairs_cap);
+    HIPCHK(fov_sort(P.pairs, np, F, fcnt, fstart, sorted, scan_scratch, pf, ps, po, s));
+    return KETE_OK;
+}
+
+// Counters of the last kete_fov_check on this thread: candidate frames
+// visited, exact light-time tests, objects on the brute-force path.
+void kete_fov_last_stats(int64_t out[4]) {
+    for (int i = 0; i < 4; ++i) out[i] = (int64_t)g_fov_stats[i];
+}
+
+int kete_lighttime_directions(const kete_ephem_t* eph, const double* x_ref, double t_ref, int64_t n_obj,
+                              const double* t_obs, const double* obs, int64_t n_q, double* d, double* tau,
+                              const kete_opts_t* opts, void* stream) {
+    kete_opts_t dflt;
+    if (!opts) { kete_default_opts(&dflt); opts = &dflt; }
+    g_err.clear();
+    EphemArgs E;
+    const double cl = opts->c_light > 0 ? opts->c_light : kC;
+    int rc = ephem_args(eph, cl, E);
+    if (rc) return rc;
+    if (n_obj < 0 || n_q < 0 || n_obj > KETE_MAX_OBJ) return fail(KETE_EINVAL, "bad sizes");
+    if (n_obj == 0 || n_q == 0) return KETE_OK;
+    if (!x_ref || !t_obs || !obs || !d) return fail(KETE_EINVAL, "null pointer");
+    FovParams P;
+    std::memset(&P, 0, sizeof(P));
+    P.eph = E;
+    P.n_obj = (int32_t)n_obj;
+    P.mu = E.gm[0];
+    P.smu = std::sqrt(E.gm[0]);
+    P.c_light = cl;
+    P.lt_tol = opts->lt_tol > 0 ? opts->lt_tol : 1e-15;
+    P.lt_iter = opts->lt_iter > 0 ? opts->lt_iter : 10;
+    HIPCHK(launch_directions(P, x_ref, t_ref, t_obs, obs, n_q, d, tau, (hipStream_t)stream));
+    return KETE_OK;
+}
+
+int kete_ephem_eval(const kete_ephem_t* eph, const double* t, const double* t_host, int64_t n_q, double* out,
+                    void* stream) {
+    g_err.clear();
+    EphemArgs E;
+    int rc = ephem_args(eph, kC, E);
+    if (rc) return rc;
+    if (n_q < 0) return fail(KETE_EINVAL, "n_q < 0");
+    if (n_q == 0) return KETE_OK;
+    if (!t || !t_host || !out) return fail(KETE_EINVAL, "null pointer");
+    for (int64_t i = 0; i < n_q; ++i)
+        if (!(t_host[i] >= eph->t_start && t_host[i] <= t_end(eph)))
+            return fail(KETE_ERANGE, "t[%lld] = %.9g outside ephemeris", (long long)i, t_host[i]);
+    HIPCHK(launch_ephem_eval(E, t, n_q, out, (hipStream_t)stream));
+    return KETE_OK;
+}
+
+}  // extern "C"

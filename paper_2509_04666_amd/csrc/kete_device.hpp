@@ -1,0 +1,211 @@
+// Device-side building blocks shared by the gfx950 kernels: Chebyshev
+// evaluation, the universal-variable Kepler hop and the light-time loop.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kete_mi.h"
+
+namespace kete {
+
+constexpr int kWave = 64;
+
+// Ephemeris description passed by value to kernels.  gm/kgr live in the
+// kernel-argument segment, so per-body reads are uniform scalar loads.
+struct EphemArgs {
+    const double* coef;      // [n_body][n_seg][3][deg1]
+    int32_t n_body, n_seg, deg1, has_gr;
+    double t_start, seg_days, inv_seg;
+    double gm[KETE_MAX_BODIES];
+    double kgr[KETE_MAX_BODIES];   // gm/c^2 for bodies with the Eq. A.3 term, else 0
+};
+
+__device__ __forceinline__ double dot3(const double* a, const double* b) {
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+// Segment index of time t (floor rule: a joint belongs to the later
+// segment), clamped to [lo, hi].
+__device__ __forceinline__ int seg_index(double t, double t_start, double inv_seg, int lo, int hi) {
+    int k = (int)floor((t - t_start) * inv_seg);
+    return k < lo ? lo : (k > hi ? hi : k);
+}
+
+// Clenshaw recurrence for sum_n c_n T_n(tau) and its tau-derivative.
+__device__ __forceinline__ void clenshaw(const double* __restrict__ c, int deg1, double tau,
+                                         double& p, double& dp) {
+    double b1 = 0.0, b2 = 0.0, d1 = 0.0, d2 = 0.0;
+    const double t2 = tau + tau;
+    for (int k = deg1 - 1; k >= 1; --k) {
+        double b0 = fma(t2, b1, c[k] - b2);
+        double d0 = fma(t2, d1, 2.0 * b1 - d2);
+        b2 = b1; b1 = b0; d2 = d1; d1 = d0;
+    }
+    p = fma(tau, b1, c[0] - b2);
+    dp = fma(tau, d1, b1 - d2);
+}
+
+// Position and velocity of one body from a segment table laid out as
+// [seg][3][deg1] starting at segment `seg_base` (global or LDS).
+__device__ __forceinline__ void cheb_body(const double* __restrict__ tab, int seg_base, int deg1,
+                                          double t, double t_start, double seg_days, double inv_seg,
+                                          int lo, int hi, double pos[3], double vel[3]) {
+    int k = seg_index(t, t_start, inv_seg, lo, hi);
+    double t0 = t_start + (double)k * seg_days;
+    double tau = 2.0 * (t - t0) * inv_seg - 1.0;
+    const double* c = tab + (size_t)(k - seg_base) * 3 * deg1;
+    double sc = 2.0 * inv_seg;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        double p, dp;
+        clenshaw(c + i * deg1, deg1, tau, p, dp);
+        pos[i] = p;
+        vel[i] = dp * sc;
+    }
+}
+
+// Stumpff functions c0..c3 of z: series on |z| <= 0.1 after quartering
+// the argument, then c_k(4z) from c_k(z):
+//   c0' = 2 c0^2 - 1, c1' = c0 c1, c2' = c1^2 / 2, c3' = (c2 + c0 c3) / 4.
+__device__ __forceinline__ void stumpff(double z, double& c0, double& c1, double& c2, double& c3) {
+    int n = 0;
+    while (fabs(z) > 0.1 && n < 64) { z *= 0.25; ++n; }
+    // c2 = sum (-z)^j/(2j+2)!, c3 = sum (-z)^j/(2j+3)!
+    c2 = 1.0 / 2.0 - z * (1.0 / 24.0 - z * (1.0 / 720.0 - z * (1.0 / 40320.0 - z * (1.0 / 3628800.0
+         - z * (1.0 / 479001600.0 - z * (1.0 / 87178291200.0 - z * (1.0 / 20922789888000.0)))))));
+    c3 = 1.0 / 6.0 - z * (1.0 / 120.0 - z * (1.0 / 5040.0 - z * (1.0 / 362880.0 - z * (1.0 / 39916800.0
+         - z * (1.0 / 6227020800.0 - z * (1.0 / 1307674368000.0 - z * (1.0 / 355687428096000.0)))))));
+    c0 = 1.0 - z * c2;
+    c1 = 1.0 - z * c3;
+    for (; n > 0; --n) {
+        double n0 = 2.0 * c0 * c0 - 1.0;
+        double n1 = c0 * c1;
+        double n2 = 0.5 * c1 * c1;
+        double n3 = 0.25 * (c2 + c0 * c3);
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+}
+
+// Two-body hop about a fixed centre: (r0, v0) -> (r, v) after dt.
+// Universal anomaly chi solves
+//   F(chi) = r0 chi c1 + s0 chi^2 c2 + chi^3 c3 - sqrt(mu) dt = 0,
+// z = alpha chi^2, alpha = 2/r0 - v0^2/mu, s0 = r0.v0/sqrt(mu), with
+// Laguerre-Conway iterations (order 5); then the Lagrange f, g functions.
+// `chi` carries a warm start in and the solution out (pass NaN for none).
+// Returns 0 or KETE_ST_KEPLER_NOCONV.
+__device__ __forceinline__ int kepler_uv(double mu, double smu, const double r0[3], const double v0[3],
+                                         double dt, double& chi, double r[3], double v[3]) {
+    if (dt == 0.0) {
+        for (int i = 0; i < 3; ++i) { r[i] = r0[i]; v[i] = v0[i]; }
+        chi = 0.0;
+        return 0;
+    }
+    const double r0n = sqrt(dot3(r0, r0));
+    const double s0 = dot3(r0, v0) / smu;
+    const double alpha = 2.0 / r0n - dot3(v0, v0) / mu;
+    const double target = smu * dt;
+    double x = (chi == chi) ? chi : target / r0n;
+    double c0, c1, c2, c3, z;
+    int it = 0, ok = 0;
+    for (; it < 60; ++it) {
+        z = alpha * x * x;
+        stumpff(z, c0, c1, c2, c3);
+        double F = r0n * x * c1 + s0 * x * x * c2 + x * x * x * c3 - target;
+        double Fp = r0n * c0 + s0 * x * c1 + x * x * c2;
+        double Fpp = s0 * c0 + (1.0 - alpha * r0n) * x * c1;
+        double disc = fabs(16.0 * Fp * Fp - 20.0 * F * Fpp);
+        double den = Fp + copysign(sqrt(disc), Fp);
+        double dx = 5.0 * F / den;
+        x -= dx;
+        if (!(x == x)) break;
+        if (fabs(dx) <= 2.5e-16 * fabs(x) || F == 0.0) { ok = 1; break; }
+    }
+    chi = x;
+    z = alpha * x * x;
+    stumpff(z, c0, c1, c2, c3);
+    const double f = 1.0 - x * x * c2 / r0n;
+    const double g = dt - x * x * x * c3 / smu;
+    for (int i = 0; i < 3; ++i) r[i] = f * r0[i] + g * v0[i];
+    const double rn = sqrt(dot3(r, r));
+    const double fd = -smu * x * c1 / (rn * r0n);
+    const double gd = 1.0 - x * x * c2 / rn;
+    for (int i = 0; i < 3; ++i) v[i] = fd * r0[i] + gd * v0[i];
+    return ok ? 0 : KETE_ST_KEPLER_NOCONV;
+}
+
+// Sun position at arbitrary times of one batch, from its coefficient
+// segments [lo, hi] held at `tab` (LDS or global).
+struct SunTable {
+    const double* tab;
+    int lo, hi, deg1;
+    double t_start, seg_days, inv_seg;
+    __device__ __forceinline__ void eval(double t, double pos[3], double vel[3]) const {
+        cheb_body(tab, lo, deg1, t, t_start, seg_days, inv_seg, lo, hi, pos, vel);
+    }
+};
+
+// Light-time corrected direction of a body from an observer (Newtonian,
+// barycentric frame, no aberration): heliocentric state (r0, v0) at t_ref,
+// emission point x_e = S(t_obs - tau) + hop(r0, v0, t_obs - tau - t_ref),
+// tau = |x_e - o| / c, iterated until the update is at most lt_tol.
+// Outputs d = x_e - o, tau and the barycentric emission velocity.
+template <class SunT>
+__device__ __forceinline__ int lighttime(const SunT& sun, double mu, double smu, double c_light,
+                                         double lt_tol, int lt_iter, double t_ref,
+                                         const double r0[3], const double v0[3], double t_obs,
+                                         const double o[3], double d[3], double& tau, double ve[3]) {
+    double Se[3], Sde[3], r[3], v[3];
+    double chi = __builtin_nan("");
+    // first guess: straight line from the epoch state
+    tau = 0.0;
+    int st = 0;
+    for (int k = 0; k <= lt_iter; ++k) {
+        double te = t_obs - tau;
+        st = kepler_uv(mu, smu, r0, v0, te - t_ref, chi, r, v);
+        sun.eval(te, Se, Sde);
+        for (int i = 0; i < 3; ++i) d[i] = Se[i] + r[i] - o[i];
+        double tn = sqrt(dot3(d, d)) / c_light;
+        double dtau = tn - tau;
+        tau = tn;
+        if (fabs(dtau) <= lt_tol) break;
+    }
+    double te = t_obs - tau;
+    st |= kepler_uv(mu, smu, r0, v0, te - t_ref, chi, r, v);
+    sun.eval(te, Se, Sde);
+    for (int i = 0; i < 3; ++i) {
+        d[i] = Se[i] + r[i] - o[i];
+        ve[i] = Sde[i] + v[i];
+    }
+    return st;
+}
+
+// A value known to be equal in every lane, marked as wave-uniform so that
+// control flow depending on it compiles to scalar branches.
+__device__ __forceinline__ double uniform(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Wave-wide reductions over the 64 lanes (results are wave-uniform).
+__device__ __forceinline__ double wave_max(double x) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x = fmax(x, __shfl_xor(x, off, kWave));
+    return uniform(x);
+}
+__device__ __forceinline__ double wave_min(double x) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x = fmin(x, __shfl_xor(x, off, kWave));
+    return uniform(x);
+}
+
+// LDS visibility between lanes of one wavefront (no block barrier).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+}  // namespace kete

@@ -1,0 +1,480 @@
+// Field-of-view membership on gfx950 (Sect. 2 and 3.1).
+//
+// Per batch, frames are binned by the direction of their bounding cap on
+// a uniform 3-D grid over [-1, 1]^3 (unit vectors only touch cells near
+// the sphere).  Each (object, batch) thread bounds how far the object's
+// light-time direction can move inside the batch -- perihelion speed of
+// its heliocentric conic, the Sun's speed, the observers' spread and the
+// batch half-span -- and visits only the grid cells within that angle
+// plus the frame radius.  Survivors pass a linear-motion test with a
+// rigorous remainder bound; the exact test (universal-variable hop with
+// light time, then n.d > 0 for every normal) decides membership.  Hits
+// are appended with one atomic per wavefront, then sorted by
+// (frame, sub-frame, object).
+#include <math.h>
+
+#include "kete_fov.hpp"
+
+namespace kete {
+namespace {
+
+constexpr double kNaN = __builtin_nan("");
+
+__device__ __forceinline__ void cross3(const double* a, const double* b, double* c) {
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// Bounding cap of a frame: unit centre and cos/sin of the radius.  The
+// vertices of every quadrilateral are the intersections of one normal of
+// the pair (0, 1) with one of the pair (2, 3), signed to lie inside the
+// opposite edges.
+__global__ void k_frame_caps(const double* __restrict__ normals, int64_t n_frames, int n_sub,
+                             double* __restrict__ cap) {
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= n_frames) return;
+    double sum[3] = {0.0, 0.0, 0.0};
+    for (int s = 0; s < n_sub; ++s) {
+        const double* n = normals + ((f * n_sub + s) * 4) * 3;
+        for (int i = 0; i < 2; ++i)
+            for (int k = 2; k < 4; ++k) {
+                double v[3];
+                cross3(n + 3 * i, n + 3 * k, v);
+                if (dot3(v, n + 3 * (1 - i)) < 0.0) { v[0] = -v[0]; v[1] = -v[1]; v[2] = -v[2]; }
+                const double vn = sqrt(dot3(v, v));
+                for (int c = 0; c < 3; ++c) sum[c] += v[c] / vn;
+            }
+    }
+    const double sn = sqrt(dot3(sum, sum));
+    double ctr[3] = {sum[0] / sn, sum[1] / sn, sum[2] / sn};
+    double cmin = 1.0;
+    for (int s = 0; s < n_sub; ++s) {
+        const double* n = normals + ((f * n_sub + s) * 4) * 3;
+        for (int i = 0; i < 2; ++i)
+            for (int k = 2; k < 4; ++k) {
+                double v[3];
+                cross3(n + 3 * i, n + 3 * k, v);
+                if (dot3(v, n + 3 * (1 - i)) < 0.0) { v[0] = -v[0]; v[1] = -v[1]; v[2] = -v[2]; }
+                const double vn = sqrt(dot3(v, v));
+                cmin = fmin(cmin, dot3(v, ctr) / vn);
+            }
+    }
+    cmin -= 1e-12;                       // rounding margin (radius grows)
+    if (!(sn > 0.0) || !(cmin > -1.0)) { ctr[0] = 1.0; ctr[1] = ctr[2] = 0.0; cmin = -1.0; }
+    double* o = cap + 8 * f;
+    o[0] = ctr[0]; o[1] = ctr[1]; o[2] = ctr[2];
+    o[3] = cmin;
+    o[4] = sqrt(fmax(0.0, 1.0 - cmin * cmin));
+    o[5] = o[6] = o[7] = 0.0;
+}
+
+// Rigorous bounds of the Sun's speed and acceleration over segments
+// [lo, hi]: |T_n'| <= n^2 and |T_n''| <= n^2 (n^2 - 1) / 3 on [-1, 1].
+__device__ void sun_bounds(const EphemArgs& E, int lo, int hi, double& vmax, double& amax) {
+    vmax = 0.0; amax = 0.0;
+    const double sc = 2.0 * E.inv_seg;
+    for (int k = lo; k <= hi; ++k) {
+        double v2 = 0.0, a2 = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            const double* cf = E.coef + ((size_t)k * 3 + c) * E.deg1;   // body 0
+            double sv = 0.0, sa = 0.0;
+            for (int n = 1; n < E.deg1; ++n) {
+                const double n2 = (double)n * n;
+                sv += n2 * fabs(cf[n]);
+                sa += n2 * (n2 - 1.0) / 3.0 * fabs(cf[n]);
+            }
+            v2 += sv * sv; a2 += sa * sa;
+        }
+        vmax = fmax(vmax, sqrt(v2) * sc);
+        amax = fmax(amax, sqrt(a2) * sc * sc);
+    }
+}
+
+// One block per batch: Sun state at t_ref, mean observer, observer
+// spread, half-span, largest frame radius, Sun speed/acceleration bounds.
+__global__ __launch_bounds__(256) void k_batch_prep(const FovParams p) {
+    __shared__ double red[256 * 4];
+    const int b = blockIdx.x, tid = threadIdx.x;
+    const int q0 = p.batch_off[b], q1 = p.batch_off[b + 1];
+    const double tr = p.t_ref[b];
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int q = q0 + tid; q < q1; q += 256) {
+        const int f = p.frame_order[q];
+        for (int c = 0; c < 3; ++c) s[c] += p.fobs[3 * f + c];
+    }
+    for (int c = 0; c < 3; ++c) red[c * 256 + tid] = s[c];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) for (int c = 0; c < 3; ++c) red[c * 256 + tid] += red[c * 256 + tid + w];
+        __syncthreads();
+    }
+    const double inv = 1.0 / (double)(q1 - q0);
+    const double ob[3] = {red[0] * inv, red[256] * inv, red[512] * inv};
+    __syncthreads();
+    double dmax = 0.0, tmax = 0.0, cmin = 1.0;
+    for (int q = q0 + tid; q < q1; q += 256) {
+        const int f = p.frame_order[q];
+        double dd[3] = {p.fobs[3 * f] - ob[0], p.fobs[3 * f + 1] - ob[1], p.fobs[3 * f + 2] - ob[2]};
+        dmax = fmax(dmax, sqrt(dot3(dd, dd)));
+        tmax = fmax(tmax, fabs(p.ft[f] - tr));
+        cmin = fmin(cmin, p.fcap[8 * f + 3]);
+    }
+    red[tid] = dmax; red[256 + tid] = tmax; red[512 + tid] = -cmin;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) for (int c = 0; c < 3; ++c) red[c * 256 + tid] = fmax(red[c * 256 + tid], red[c * 256 + tid + w]);
+        __syncthreads();
+    }
+    if (tid == 0) {
+        double* o = p.btab + kBatchStride * b;
+        const EphemArgs& E = p.eph;
+        const int hi_all = E.n_seg - 1;
+        double S[3], Sd[3];
+        cheb_body(E.coef, 0, E.deg1, tr, E.t_start, E.seg_days, E.inv_seg, 0, hi_all, S, Sd);
+        const double delta = red[256] * (1.0 + 1e-15) + 1e-12;
+        const double span = delta + kMaxLightDays;
+        const int lo = seg_index(tr - span, E.t_start, E.inv_seg, 0, hi_all);
+        const int hi = seg_index(tr + span, E.t_start, E.inv_seg, 0, hi_all);
+        double vs, as;
+        sun_bounds(E, lo, hi, vs, as);
+        for (int c = 0; c < 3; ++c) { o[c] = S[c]; o[3 + c] = Sd[c]; o[6 + c] = ob[c]; }
+        o[9] = red[0] * (1.0 + 1e-12) + 1e-12;    // observer spread
+        o[10] = delta;                             // max |t_f - t_ref|
+        const double cR = -red[512];
+        o[11] = cR;
+        o[12] = sqrt(fmax(0.0, 1.0 - cR * cR));
+        o[13] = vs * (1.0 + 1e-9) + 1e-15;
+        o[14] = as * (1.0 + 1e-9) + 1e-15;
+        o[15] = (double)lo;
+        o[16] = (double)hi;
+    }
+}
+
+__device__ __forceinline__ int cell_coord(double u, double inv_L, int G) {
+    int i = (int)floor((u + 1.0) * inv_L);
+    return i < 0 ? 0 : (i >= G ? G - 1 : i);
+}
+
+__global__ void k_frame_keys(const FovParams p, int32_t* __restrict__ qkey, int32_t* __restrict__ cnt) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= p.n_frames) return;
+    // batch of sorted position q
+    int lo = 0, hi = p.n_batch;            // batch_off[lo] <= q < batch_off[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (p.batch_off[mid] <= q) lo = mid; else hi = mid;
+    }
+    const int f = p.frame_order[q];
+    const double* c = p.fcap + 8 * f;
+    const int G = p.G;
+    const int cell = (cell_coord(c[0], p.inv_L, G) * G + cell_coord(c[1], p.inv_L, G)) * G + cell_coord(c[2], p.inv_L, G);
+    const int key = lo * G * G * G + cell;
+    qkey[q] = key;
+    atomicAdd(cnt + key, 1);
+}
+
+__global__ void k_frame_scatter(const FovParams p, const int32_t* __restrict__ qkey, int32_t* __restrict__ cursor) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= p.n_frames) return;
+    const int key = qkey[q];
+    const int pos = p.cell_start[key] + atomicAdd(cursor + key, 1);
+    p.cell_frames[pos] = p.frame_order[q];
+}
+
+struct SunLds {
+    const double* tab;
+    int lo, hi, deg1;
+    double t_start, seg_days, inv_seg;
+    __device__ __forceinline__ void eval(double t, double pos[3], double vel[3]) const {
+        cheb_body(tab, lo, deg1, t, t_start, seg_days, inv_seg, lo, hi, pos, vel);
+    }
+};
+
+// Append a pair key with one atomic per wavefront.
+__device__ __forceinline__ void append_pair(const FovParams& p, unsigned long long key) {
+    const unsigned long long m = __ballot(1);
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((long long)m) - 1;
+    const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    unsigned long long base = 0;
+    if (lane == leader) base = atomicAdd(p.n_pairs, (unsigned long long)__popcll(m));
+    base = __shfl(base, leader, 64);
+    const unsigned long long idx = base + __popcll(m & lt);
+    if (idx < (unsigned long long)p.cap) p.pairs[idx] = key;
+}
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_fov(const FovParams p) {
+    __shared__ double sunL[kMaxSunSegs * 3 * (KETE_MAX_DEGREE + 1)];
+    const int b = blockIdx.y;
+    const double* bt = p.btab + kBatchStride * b;
+    const int slo = (int)bt[15], shi = (int)bt[16];
+    const int deg1 = p.eph.deg1;
+    if (shi - slo + 1 <= kMaxSunSegs) {
+        const int total = (shi - slo + 1) * 3 * deg1;
+        for (int i = threadIdx.x; i < total; i += BLOCK) sunL[i] = p.eph.coef[(size_t)slo * 3 * deg1 + i];
+    }
+    __syncthreads();
+    const int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (j >= p.n_obj) return;
+    if (p.status && p.status[j] != 0) return;
+    const double* st = p.x_epoch + ((size_t)b * p.n_obj + j) * 6;
+    double x[3] = {st[0], st[1], st[2]}, v[3] = {st[3], st[4], st[5]};
+    if (!(isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]) && isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2])))
+        return;
+    // Sun segments of the batch from LDS; the brute-force path of far
+    // objects (light time above kMaxLightDays) reads the whole table.
+    const bool sun_in_lds = (shi - slo + 1) <= kMaxSunSegs;
+    SunLds sun = sun_in_lds ? SunLds{sunL, slo, shi, deg1, p.eph.t_start, p.eph.seg_days, p.eph.inv_seg}
+                            : SunLds{p.eph.coef, 0, p.eph.n_seg - 1, deg1, p.eph.t_start, p.eph.seg_days, p.eph.inv_seg};
+    const double tr = p.t_ref[b];
+    const double mu = p.mu, smu = p.smu, cl = p.c_light;
+    double r0[3], v0[3];
+    for (int c = 0; c < 3; ++c) { r0[c] = x[c] - bt[c]; v0[c] = v[c] - bt[3 + c]; }
+    const double Dobs = bt[9], Delta = bt[10], cosRm = bt[11], sinRm = bt[12], Vsun = bt[13], Asun = bt[14];
+
+    // motion bounds of the two-body conic
+    const double r0n = sqrt(dot3(r0, r0));
+    const double v2 = dot3(v0, v0);
+    double hv[3];
+    cross3(r0, v0, hv);
+    const double hn = sqrt(dot3(hv, hv));
+    const double rv = dot3(r0, v0);
+    double ev[3];
+    for (int c = 0; c < 3; ++c) ev[c] = ((v2 - mu / r0n) * r0[c] - rv * v0[c]) / mu;
+    const double ecc = sqrt(dot3(ev, ev));
+    const double vp = (hn > 0.0) ? mu * (1.0 + ecc) / hn * (1.0 + 1e-12) : 1e300;   // perihelion speed
+    const double q = (hn > 0.0) ? hn * hn / (mu * (1.0 + ecc)) * (1.0 - 1e-12) : 0.0;
+    const double V = vp + Vsun;
+
+    double dref[3];
+    for (int c = 0; c < 3; ++c) dref[c] = x[c] - bt[6 + c];
+    const double dn = sqrt(dot3(dref, dref));
+    const double dh[3] = {dref[0] / dn, dref[1] / dn, dref[2] / dn};
+    bool overflow = !(V < 0.5 * cl);
+    double taumax = 0.0, sth = 1.0, cth = 0.0;
+    if (!overflow) {
+        taumax = (dn + Dobs + V * Delta) / (cl - V) * (1.0 + 1e-12);
+        const double delta = V * (Delta + taumax) + Dobs + 1e-12;
+        sth = delta / dn;
+        if (!(sth < p.sin_overflow) || taumax > kMaxLightDays) overflow = true;
+        else cth = sqrt(1.0 - sth * sth);
+    }
+    // linear-prediction remainder terms
+    const double rmin = fmax(q, r0n - vp * (Delta + taumax));
+    const double a2b = (rmin > 0.0) ? mu / (rmin * rmin) : 1e300;
+    const double vbn = sqrt(dot3(v, v));
+
+    unsigned long long n_cand = 0, n_exact = 0;
+
+    auto test_frame = [&](int f) {
+        const double dt = p.ft[f] - tr;
+        const double* o = p.fobs + 3 * f;
+        const double* nrm = p.normals + (size_t)f * p.n_sub * 12;
+        // linear motion with a rigorous remainder bound
+        double ul[3];
+        for (int c = 0; c < 3; ++c) ul[c] = x[c] + v[c] * dt - o[c];
+        const double uln = sqrt(dot3(ul, ul));
+        const double ad = fabs(dt) + taumax;
+        const double eps = vbn * taumax + 0.5 * (a2b + Asun) * ad * ad + 1e-12;
+        const double eta = 2.0 * eps / uln;
+        bool maybe = false;
+        if (!(eta < 1.0) || overflow) {
+            maybe = true;
+        } else {
+            for (int s = 0; s < p.n_sub && !maybe; ++s) {
+                bool out = false;
+                for (int i = 0; i < 4; ++i) out |= dot3(nrm + 12 * s + 3 * i, ul) / uln <= -eta;
+                maybe = !out;
+            }
+        }
+        if (!maybe) return;
+        ++n_exact;
+        double d[3], tau, ve[3];
+        lighttime(sun, mu, smu, cl, p.lt_tol, p.lt_iter, tr, r0, v0, p.ft[f], o, d, tau, ve);
+        for (int s = 0; s < p.n_sub; ++s) {
+            const double* ns = nrm + 12 * s;
+            if (dot3(ns, d) > 0.0 && dot3(ns + 3, d) > 0.0 && dot3(ns + 6, d) > 0.0 && dot3(ns + 9, d) > 0.0) {
+                append_pair(p, ((unsigned long long)f << 32) | ((unsigned long long)s << 25) | (unsigned long long)j);
+            }
+        }
+    };
+
+    if (!overflow) {
+        const double cosRT = cosRm * cth - sinRm * sth;      // cos(Rmax + theta)
+        if (!(cosRT > 0.0)) overflow = true;
+        else {
+            const double chord = sqrt(2.0 - 2.0 * cosRT) + 1e-9;
+            const int G = p.G;
+            int lo[3], hi[3];
+            int ncell = 1;
+            for (int c = 0; c < 3; ++c) {
+                lo[c] = cell_coord(dh[c] - chord, p.inv_L, G);
+                hi[c] = cell_coord(dh[c] + chord, p.inv_L, G);
+                ncell *= hi[c] - lo[c] + 1;
+            }
+            if (ncell > p.max_cells) overflow = true;
+            else {
+                const int base = b * G * G * G;
+                for (int ix = lo[0]; ix <= hi[0]; ++ix)
+                    for (int iy = lo[1]; iy <= hi[1]; ++iy)
+                        for (int iz = lo[2]; iz <= hi[2]; ++iz) {
+                            const int key = base + (ix * G + iy) * G + iz;
+                            const int a0 = p.cell_start[key], a1 = p.cell_start[key + 1];
+                            for (int k = a0; k < a1; ++k) {
+                                const int f = p.cell_frames[k];
+                                const double* cp = p.fcap + 8 * f;
+                                const double thr = cp[3] * cth - cp[4] * sth;     // cos(R_f + theta)
+                                if (dot3(cp, dh) < thr - 1e-12) continue;
+                                ++n_cand;
+                                test_frame(f);
+                            }
+                        }
+            }
+        }
+    }
+    if (overflow) {
+        sun = SunLds{p.eph.coef, 0, p.eph.n_seg - 1, deg1, p.eph.t_start, p.eph.seg_days, p.eph.inv_seg};
+        for (int qq = p.batch_off[b]; qq < p.batch_off[b + 1]; ++qq) {
+            ++n_cand;
+            test_frame(p.frame_order[qq]);
+        }
+    }
+    if (p.stats) {
+        atomicAdd(p.stats + 0, n_cand);
+        atomicAdd(p.stats + 1, n_exact);
+        if (overflow) atomicAdd(p.stats + 2, 1ull);
+    }
+}
+
+// ---------------------------------------------------------------- sort
+__global__ void k_pair_hist(const unsigned long long* __restrict__ keys, int64_t n, int32_t* __restrict__ fcnt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) atomicAdd(fcnt + (int)(keys[i] >> 32), 1);
+}
+
+__global__ void k_pair_scatter(const unsigned long long* __restrict__ keys, int64_t n,
+                               const int32_t* __restrict__ fstart, int32_t* __restrict__ fcur,
+                               unsigned long long* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const unsigned long long k = keys[i];
+    const int f = (int)(k >> 32);
+    out[fstart[f] + atomicAdd(fcur + f, 1)] = k;
+}
+
+// Each frame's pairs are few: insertion sort per frame, then unpack.
+__global__ void k_pair_segsort(unsigned long long* __restrict__ keys, const int32_t* __restrict__ fstart,
+                               int64_t n_frames, int32_t* __restrict__ pf, int32_t* __restrict__ ps,
+                               int32_t* __restrict__ po) {
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= n_frames) return;
+    const int a = fstart[f], e = fstart[f + 1];
+    for (int i = a + 1; i < e; ++i) {
+        const unsigned long long k = keys[i];
+        int j = i - 1;
+        while (j >= a && keys[j] > k) { keys[j + 1] = keys[j]; --j; }
+        keys[j + 1] = k;
+    }
+    for (int i = a; i < e; ++i) {
+        const unsigned long long k = keys[i];
+        pf[i] = (int32_t)(k >> 32);
+        ps[i] = (int32_t)((k >> 25) & 0x7f);
+        po[i] = (int32_t)(k & 0x1ffffff);
+    }
+}
+
+// ---------------------------------------------------------------- checks
+__global__ void k_directions(const FovParams p, const double* __restrict__ x_ref, double t_ref,
+                             const double* __restrict__ t_obs, const double* __restrict__ obs, int64_t n_q,
+                             double* __restrict__ d_out, double* __restrict__ tau_out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)p.n_obj * n_q) return;
+    const int64_t j = i % p.n_obj, qn = i / p.n_obj;
+    const EphemArgs& E = p.eph;
+    const SunTable sun{E.coef, 0, E.n_seg - 1, E.deg1, E.t_start, E.seg_days, E.inv_seg};
+    double S[3], Sd[3];
+    sun.eval(t_ref, S, Sd);
+    const double* st = x_ref + 6 * j;
+    double r0[3] = {st[0] - S[0], st[1] - S[1], st[2] - S[2]};
+    double v0[3] = {st[3] - Sd[0], st[4] - Sd[1], st[5] - Sd[2]};
+    double d[3], tau, ve[3];
+    lighttime(sun, p.mu, p.smu, p.c_light, p.lt_tol, p.lt_iter, t_ref, r0, v0, t_obs[qn], obs + 3 * qn, d, tau, ve);
+    for (int c = 0; c < 3; ++c) d_out[3 * i + c] = d[c];
+    if (tau_out) tau_out[i] = tau;
+}
+
+__global__ void k_ephem_eval(EphemArgs E, const double* __restrict__ t, int64_t n_q, double* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_q * E.n_body) return;
+    const int64_t qn = i / E.n_body;
+    const int b = (int)(i % E.n_body);
+    double pos[3], vel[3];
+    cheb_body(E.coef + (size_t)b * E.n_seg * 3 * E.deg1, 0, E.deg1, t[qn], E.t_start, E.seg_days, E.inv_seg,
+              0, E.n_seg - 1, pos, vel);
+    for (int c = 0; c < 3; ++c) { out[6 * i + c] = pos[c]; out[6 * i + 3 + c] = vel[c]; }
+}
+
+}  // namespace
+
+hipError_t fov_prepare(const FovParams& p, int32_t* qkey, int32_t* cnt, int32_t* cursor, int64_t n_keys,
+                       void* scan_scratch, hipStream_t s) {
+    const int64_t F = p.n_frames;
+    const unsigned gF = (unsigned)((F + 255) / 256);
+    hipError_t e;
+    if (F > 0) hipLaunchKernelGGL(k_frame_caps, dim3(gF), dim3(256), 0, s, p.normals, F, p.n_sub, p.fcap);
+    if (p.n_batch > 0) hipLaunchKernelGGL(k_batch_prep, dim3((unsigned)p.n_batch), dim3(256), 0, s, p);
+    if ((e = hipMemsetAsync(cnt, 0, (size_t)(n_keys + 1) * sizeof(int32_t), s)) != hipSuccess) return e;
+    if (F > 0) hipLaunchKernelGGL(k_frame_keys, dim3(gF), dim3(256), 0, s, p, qkey, cnt);
+    if ((e = exclusive_scan_i32(cnt, (int32_t*)p.cell_start, n_keys, scan_scratch, s)) != hipSuccess) return e;
+    if ((e = hipMemsetAsync(cursor, 0, (size_t)n_keys * sizeof(int32_t), s)) != hipSuccess) return e;
+    if (F > 0) hipLaunchKernelGGL(k_frame_scatter, dim3(gF), dim3(256), 0, s, p, (const int32_t*)qkey, cursor);
+    return hipGetLastError();
+}
+
+hipError_t fov_candidates(const FovParams& p, int block, hipStream_t s) {
+    if (p.n_obj == 0 || p.n_batch == 0) return hipSuccess;
+    dim3 grid((unsigned)((p.n_obj + block - 1) / block), (unsigned)p.n_batch);
+    switch (block) {
+        case 64: hipLaunchKernelGGL(k_fov<64>, grid, dim3(64), 0, s, p); break;
+        case 128: hipLaunchKernelGGL(k_fov<128>, grid, dim3(128), 0, s, p); break;
+        case 256: hipLaunchKernelGGL(k_fov<256>, grid, dim3(256), 0, s, p); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t fov_sort(const unsigned long long* keys, int64_t n, int64_t n_frames, int32_t* fcnt, int32_t* fstart,
+                    unsigned long long* sorted, void* scan_scratch, int32_t* pf, int32_t* ps, int32_t* po,
+                    hipStream_t s) {
+    hipError_t e;
+    if ((e = hipMemsetAsync(fcnt, 0, (size_t)(n_frames + 1) * sizeof(int32_t), s)) != hipSuccess) return e;
+    if (n > 0) hipLaunchKernelGGL(k_pair_hist, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, keys, n, fcnt);
+    if ((e = exclusive_scan_i32(fcnt, fstart, n_frames, scan_scratch, s)) != hipSuccess) return e;
+    if ((e = hipMemsetAsync(fcnt, 0, (size_t)n_frames * sizeof(int32_t), s)) != hipSuccess) return e;
+    if (n > 0) hipLaunchKernelGGL(k_pair_scatter, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, keys, n,
+                                  (const int32_t*)fstart, fcnt, sorted);
+    if (n_frames > 0)
+        hipLaunchKernelGGL(k_pair_segsort, dim3((unsigned)((n_frames + 255) / 256)), dim3(256), 0, s, sorted,
+                           (const int32_t*)fstart, n_frames, pf, ps, po);
+    return hipGetLastError();
+}
+
+hipError_t launch_directions(const FovParams& p, const double* x_ref, double t_ref, const double* t_obs,
+                             const double* obs, int64_t n_q, double* d, double* tau, hipStream_t s) {
+    const int64_t n = (int64_t)p.n_obj * n_q;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_directions, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, s, p, x_ref, t_ref, t_obs,
+                       obs, n_q, d, tau);
+    return hipGetLastError();
+}
+
+hipError_t launch_ephem_eval(const EphemArgs& E, const double* t, int64_t n_q, double* out, hipStream_t s) {
+    const int64_t n = n_q * E.n_body;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ephem_eval, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, E, t, n_q, out);
+    return hipGetLastError();
+}
+
+}  // namespace kete

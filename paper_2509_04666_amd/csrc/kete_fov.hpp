@@ -1,0 +1,52 @@
+// Field-of-view stage: parameters shared by the host layer and kernels.
+#pragma once
+
+#include "kete_internal.hpp"
+
+namespace kete {
+
+constexpr int kBatchStride = 17;        // doubles per batch record
+constexpr int kMaxSunSegs = 8;          // Sun segments staged in LDS per batch
+constexpr double kMaxLightDays = 1.0;   // light time covered by the staged window
+
+struct FovParams {
+    EphemArgs eph;
+    const double* x_epoch;      // [B][N][6]
+    const int32_t* status;      // [N] or null
+    int32_t n_obj;
+    int32_t n_batch;
+    int64_t n_frames;
+    const double* t_ref;        // [B]
+    const int32_t* batch_off;   // [B+1]
+    const int32_t* frame_order; // [F]
+    const double* ft;           // [F]
+    const double* fobs;         // [F][3]
+    const double* normals;      // [F][S][4][3]
+    int32_t n_sub;
+    int32_t G;                  // grid cells per axis
+    double inv_L;               // 1 / cell size
+    double* fcap;               // [F][8]: centre, cos R, sin R
+    double* btab;               // [B][kBatchStride]
+    int32_t* cell_start;        // [B G^3 + 1]
+    int32_t* cell_frames;       // [F]
+    unsigned long long* pairs;  // [cap] packed (frame << 32 | sub << 25 | obj)
+    unsigned long long* n_pairs;
+    int64_t cap;
+    unsigned long long* stats;  // [4] or null: candidates, exact tests, overflow objects
+    double mu, smu, c_light, lt_tol;
+    int32_t lt_iter;
+    int32_t max_cells;
+    double sin_overflow;
+};
+
+hipError_t fov_prepare(const FovParams& p, int32_t* qkey, int32_t* cnt, int32_t* cursor, int64_t n_keys,
+                       void* scan_scratch, hipStream_t s);
+hipError_t fov_candidates(const FovParams& p, int block, hipStream_t s);
+hipError_t fov_sort(const unsigned long long* keys, int64_t n, int64_t n_frames, int32_t* fcnt, int32_t* fstart,
+                    unsigned long long* sorted, void* scan_scratch, int32_t* pf, int32_t* ps, int32_t* po,
+                    hipStream_t s);
+hipError_t launch_directions(const FovParams& p, const double* x_ref, double t_ref, const double* t_obs,
+                             const double* obs, int64_t n_q, double* d, double* tau, hipStream_t s);
+hipError_t launch_ephem_eval(const EphemArgs& E, const double* t, int64_t n_q, double* out, hipStream_t s);
+
+}  // namespace kete

@@ -1,0 +1,75 @@
+// Host-side internal interfaces between the C ABI layer and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "kete_device.hpp"
+#include "kete_mi.h"
+
+namespace kete {
+
+// Gauss-Radau collocation constants (8 nodes including 0) for the
+// increment form of the step: with D_m = F_m - F_0 (m = 1..7),
+//   X(s) = x0 + s h v0 + h^2 (s^2/2 F0 + sum_m A_m(s) D_m)
+//   V(s) = v0 + h (s F0 + sum_m B_m(s) D_m)
+// and the highest monomial coefficient of the acceleration polynomial
+//   b6 = sum_m E6[m] D_m.
+// Row n = 0..7 is node s_n, row 8 is s = 1.
+struct RadauConst {
+    double s[9];
+    double A[9][7];
+    double B[9][7];
+    double E6[7];
+    double half_s2[9];
+};
+
+// One staged ephemeris window of the integration: [t_a, t_b] lies within
+// Chebyshev segments [seg_lo, seg_hi]; out >= 0 marks an output epoch.
+struct Window {
+    double t_a, t_b;
+    int32_t seg_lo, seg_hi;
+    int32_t out, pad;
+};
+
+struct NbodyParams {
+    EphemArgs eph;
+    RadauConst rc;
+    double* state;          // [N][6] working state
+    double* h_pref;         // [N] preferred step (days, > 0)
+    const int32_t* perm;    // [N] object order (bucketed) or null
+    int32_t* status;        // [N]
+    double* x_out;          // [E][N][6]
+    unsigned long long* stats;  // [8] or null
+    const Window* win;      // windows of this launch
+    int32_t n_win;
+    int32_t n_obj;
+    int32_t max_iter;
+    int32_t max_steps;
+    int32_t max_win_segs;   // LDS capacity in segments
+    int32_t first_launch;
+    double eps, h_min, h_max, h_init, safety;
+};
+
+const RadauConst& radau_const();
+
+hipError_t launch_nbody(const NbodyParams& p, int block, hipStream_t s);
+
+// Stable counting sort of objects into step-size buckets.
+struct BucketParams {
+    const double* h_pref;   // [N]
+    const int32_t* status;  // [N]
+    int32_t* perm;          // [N] out
+    int32_t* counts;        // [n_buckets][n_blocks] scratch
+    int32_t n_obj;
+    int32_t n_buckets;
+    double h_ref;           // bucket k holds h in [h_ref 2^k, h_ref 2^(k+1))
+};
+hipError_t launch_bucket(const BucketParams& p, hipStream_t s);
+
+// Exclusive scan of int32 counts (n + 1 outputs); scratch >= scan_scratch(n).
+size_t scan_scratch_bytes(int64_t n);
+hipError_t exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, void* scratch, hipStream_t s);
+
+}  // namespace kete

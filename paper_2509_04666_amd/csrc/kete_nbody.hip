@@ -1,0 +1,347 @@
+// n-body propagation of massless bodies on gfx950 (App. A force model,
+// Gauss-Radau collocation with the predictor removed, App. A.6).
+//
+// One lane per object.  The 64 objects of a wavefront share the time
+// grid: the step size is the smallest one any lane asks for, so the
+// perturber positions at the 9 node times of a step are evaluated once
+// per wavefront (64 Clenshaw chains in parallel) and broadcast from LDS.
+// The Chebyshev coefficients of the segments a window needs are staged
+// in LDS once per workgroup.  Objects are sorted by predicted step size
+// before each launch so that lanes of one wavefront want similar steps.
+#include <math.h>
+
+#include "kete_internal.hpp"
+
+namespace kete {
+namespace {
+
+constexpr int kNodes = 9;   // s_0 = 0, s_1..s_7, and s = 1 (step end)
+constexpr double kInf = 1e300;
+
+// Acceleration at one node from the LDS perturber table e[b][6]:
+// Eq. A.1 with the attractive sign, plus Eq. A.3 (eps = 0) where kgr != 0.
+__device__ __forceinline__ void accel(const double* __restrict__ e, const EphemArgs& E,
+                                      const double X[3], const double V[3], double F[3]) {
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    for (int b = 0; b < E.n_body; ++b) {
+        const double* pb = e + 6 * b;
+        const double rx = X[0] - pb[0], ry = X[1] - pb[1], rz = X[2] - pb[2];
+        const double r2 = fma(rx, rx, fma(ry, ry, rz * rz));
+        const double ir = rsqrt(r2);
+        const double ir3 = ir * ir * ir;
+        const double gm = E.gm[b];
+        double f = -gm * ir3;
+        const double k = E.kgr[b];
+        if (k != 0.0) {
+            const double wx = V[0] - pb[3], wy = V[1] - pb[4], wz = V[2] - pb[5];
+            const double w2 = fma(wx, wx, fma(wy, wy, wz * wz));
+            const double rw = fma(rx, wx, fma(ry, wy, rz * wz));
+            const double g = k * ir3;
+            f = fma(g, 4.0 * gm * ir - w2, f);
+            const double q = 4.0 * g * rw;
+            ax = fma(q, wx, ax); ay = fma(q, wy, ay); az = fma(q, wz, az);
+        }
+        ax = fma(f, rx, ax); ay = fma(f, ry, ay); az = fma(f, rz, az);
+    }
+    F[0] = ax; F[1] = ay; F[2] = az;
+}
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_nbody(const NbodyParams p) {
+    extern __shared__ double smem[];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+    const EphemArgs& E = p.eph;
+    const RadauConst& rc = p.rc;
+    const int nb = E.n_body, deg1 = E.deg1;
+    const int cps = 3 * deg1;                         // doubles per segment
+    const int bstride = p.max_win_segs * cps;         // doubles per body in LDS
+    double* coefL = smem;
+    double* ephW = smem + (size_t)nb * bstride + (size_t)wid * kNodes * nb * 6;
+
+    const long gi = (long)blockIdx.x * BLOCK + tid;
+    const bool valid = gi < p.n_obj;
+    const int j = valid ? (p.perm ? p.perm[gi] : (int)gi) : 0;
+    bool active = valid && p.status[j] == 0;
+    int my_status = valid ? p.status[j] : 0;
+
+    double x0[3] = {1.0, 0.0, 0.0}, v0[3] = {0.0, 0.0, 0.0};
+    double hin = kInf;
+    if (valid) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) { x0[i] = p.state[6 * j + i]; v0[i] = p.state[6 * j + 3 + i]; }
+        hin = p.h_pref[j];
+    }
+    double hw = wave_min(active ? hin : kInf);
+    if (!(hw < kInf)) hw = p.h_init;
+    double hp_new = kInf;
+
+    unsigned long long c_steps = 0, c_iter = 0, c_rej = 0, c_lsteps = 0, c_liter = 0, c_chain = 0;
+    double t = p.win[0].t_a;
+    double F0[3] = {0.0, 0.0, 0.0};
+    bool haveF0 = false;
+
+    for (int w = 0; w < p.n_win; ++w) {
+        const Window W = p.win[w];
+        __syncthreads();
+        {   // stage the window's Chebyshev segments of every body
+            const int per_body = (W.seg_hi - W.seg_lo + 1) * cps;
+            const int total = nb * per_body;
+            for (int i = tid; i < total; i += BLOCK) {
+                const int b = i / per_body, r = i - b * per_body;
+                coefL[b * bstride + r] = E.coef[((size_t)b * E.n_seg + W.seg_lo) * cps + r];
+            }
+        }
+        __syncthreads();
+        const double tb = W.t_b;
+        if (__ballot(active) == 0ull) {
+            t = tb;
+        }
+        while (t != tb) {
+            const double dir = tb > t ? 1.0 : -1.0;
+            double hmag = hw;
+            if (p.h_max > 0.0 && hmag > p.h_max) hmag = p.h_max;
+            double h = dir * hmag;
+            bool landed = false;
+            if (fabs(h) >= fabs(tb - t)) { h = tb - t; landed = true; }
+            if ((long)c_steps >= p.max_steps) {
+                if (active) { my_status = KETE_ST_MAX_STEPS; active = false; }
+                t = tb;
+                break;
+            }
+            const double t_end = landed ? tb : t + h;
+            const double hh = h * h;
+
+            // perturbers at the 9 node times, one Clenshaw chain per lane
+            const int nchain = kNodes * nb * 3;
+            for (int c = lane; c < nchain; c += kWave) {
+                const int n = c / (nb * 3);
+                const int r = c - n * nb * 3;
+                const int b = r / 3, i = r - 3 * b;
+                const double tt = (n == kNodes - 1) ? t_end : t + rc.s[n] * h;
+                const int k = seg_index(tt, E.t_start, E.inv_seg, W.seg_lo, W.seg_hi);
+                const double tau = 2.0 * (tt - (E.t_start + (double)k * E.seg_days)) * E.inv_seg - 1.0;
+                double pv, dv;
+                clenshaw(coefL + b * bstride + (k - W.seg_lo) * cps + i * deg1, deg1, tau, pv, dv);
+                ephW[(n * nb + b) * 6 + i] = pv;
+                ephW[(n * nb + b) * 6 + 3 + i] = dv * 2.0 * E.inv_seg;
+            }
+            c_chain += nchain;
+            wave_lds_sync();
+
+            if (!haveF0) { accel(ephW, E, x0, v0, F0); haveF0 = true; }
+
+            double D[7][3];
+#pragma unroll
+            for (int m = 0; m < 7; ++m) { D[m][0] = D[m][1] = D[m][2] = 0.0; }
+            double b6p[3] = {0.0, 0.0, 0.0};
+            double pc = 1e300, pcl;
+            int it = 0;
+            do {
+                pcl = pc;
+                ++it;
+                // An opaque zero row offset keeps the collocation constants
+                // in the kernel-argument segment (scalar loads per node)
+                // instead of being hoisted into vector registers.
+                int z;
+                asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+#pragma unroll
+                for (int n = 1; n <= 7; ++n) {
+                    const int nz = n + z;
+                    const double sh = rc.s[nz] * h;
+                    double X[3], V[3];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        double acc = rc.half_s2[nz] * F0[c];
+#pragma unroll
+                        for (int m = 0; m < 7; ++m) acc = fma(rc.A[nz][m], D[m][c], acc);
+                        X[c] = fma(hh, acc, fma(sh, v0[c], x0[c]));
+                    }
+                    if (E.has_gr) {
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            double av = rc.s[nz] * F0[c];
+#pragma unroll
+                            for (int m = 0; m < 7; ++m) av = fma(rc.B[nz][m], D[m][c], av);
+                            V[c] = fma(h, av, v0[c]);
+                        }
+                    } else {
+                        V[0] = v0[0]; V[1] = v0[1]; V[2] = v0[2];
+                    }
+                    double F[3];
+                    accel(ephW + n * nb * 6, E, X, V, F);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) D[n - 1][c] = F[c] - F0[c];
+                }
+                double db = 0.0, fm = 0.0;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    double b6 = 0.0;
+#pragma unroll
+                    for (int m = 0; m < 7; ++m) b6 = fma(rc.E6[m + z], D[m][c], b6);
+                    db = fmax(db, fabs(b6 - b6p[c]));
+                    b6p[c] = b6;
+                    fm = fmax(fm, fabs(D[6][c] + F0[c]));
+                }
+                const double lpc = (active && fm > 0.0) ? db / fm : 0.0;
+                pc = wave_max(lpc);
+                c_liter += __popcll(__ballot(active));
+            } while (!(pc < 1e-16) && !(it > 2 && pcl <= pc) && it < p.max_iter);
+            c_iter += it;
+
+            // IAS15-style control on |b6| / |a| at the last node
+            double fm = 0.0, bm = 0.0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) { fm = fmax(fm, fabs(D[6][c] + F0[c])); bm = fmax(bm, fabs(b6p[c])); }
+            const double ebl = fm > 0.0 ? bm / fm : 0.0;
+            double hl = (ebl > 0.0 && ebl < kInf) ? fabs(h) * pow(p.eps / ebl, 1.0 / 7.0) : fabs(h) / p.safety;
+            if (!active) hl = kInf;
+            if (active && hl < p.h_min) { my_status = KETE_ST_STEP_UNDERFLOW; active = false; hl = kInf; }
+            const double hn = wave_min(hl);
+            if (!(hn < kInf)) { t = tb; break; }
+            if (hn < p.safety * fabs(h)) {       // reject and retry from the same state
+                hw = hn;
+                ++c_rej;
+                continue;
+            }
+            // accept: step end from the collocation polynomial
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                double ax = rc.half_s2[8] * F0[c], av = F0[c];
+#pragma unroll
+                for (int m = 0; m < 7; ++m) {
+                    ax = fma(rc.A[8][m], D[m][c], ax);
+                    av = fma(rc.B[8][m], D[m][c], av);
+                }
+                x0[c] = fma(hh, ax, fma(h, v0[c], x0[c]));
+                v0[c] = fma(h, av, v0[c]);
+            }
+            t = t_end;
+            ++c_steps;
+            c_lsteps += __popcll(__ballot(active));
+            if (active && !(isfinite(x0[0]) && isfinite(x0[1]) && isfinite(x0[2]) &&
+                            isfinite(v0[0]) && isfinite(v0[1]) && isfinite(v0[2]))) {
+                my_status = KETE_ST_NONFINITE; active = false;
+            }
+            accel(ephW + 8 * nb * 6, E, x0, v0, F0);
+            if (landed) {
+                hw = fmin(hw, hn);
+            } else {
+                hw = fmin(hn, fabs(h) / p.safety);
+                hp_new = fmin(hp_new, fmin(hl, fabs(h) / p.safety));
+            }
+        }
+        if (W.out >= 0 && valid) {
+            double* dst = p.x_out + ((size_t)W.out * p.n_obj + j) * 6;
+            const bool ok = active && my_status == 0;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                dst[i] = ok ? x0[i] : __builtin_nan("");
+                dst[3 + i] = ok ? v0[i] : __builtin_nan("");
+            }
+        }
+    }
+    if (valid) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) { p.state[6 * j + i] = x0[i]; p.state[6 * j + 3 + i] = v0[i]; }
+        if (hp_new < kInf) p.h_pref[j] = hp_new;
+        p.status[j] = my_status;
+    }
+    if (p.stats && lane == 0 && __ballot(valid) != 0ull) {
+        atomicAdd(p.stats + 0, c_steps);
+        atomicAdd(p.stats + 1, c_iter);
+        atomicAdd(p.stats + 2, c_rej);
+        atomicAdd(p.stats + 3, c_lsteps);
+        atomicAdd(p.stats + 4, c_liter);
+        atomicAdd(p.stats + 5, c_chain);
+    }
+}
+
+// ---------------------------------------------------------------- buckets
+__device__ __forceinline__ int bucket_key(double h, int st, int nbk, double h_ref) {
+    if (st != 0 || !(h < kInf)) return nbk - 1;
+    int k = (int)floor(log2(h / h_ref));
+    return k < 0 ? 0 : (k >= nbk ? nbk - 1 : k);
+}
+
+__global__ __launch_bounds__(256) void k_bucket_count(const BucketParams p) {
+    __shared__ int hist[32];
+    const int tid = threadIdx.x;
+    if (tid < 32) hist[tid] = 0;
+    __syncthreads();
+    const long j = (long)blockIdx.x * 256 + tid;
+    if (j < p.n_obj) atomicAdd(&hist[bucket_key(p.h_pref[j], p.status[j], p.n_buckets, p.h_ref)], 1);
+    __syncthreads();
+    if (tid < p.n_buckets) p.counts[(size_t)tid * gridDim.x + blockIdx.x] = hist[tid];
+}
+
+// Stable scatter: the rank inside a block follows the object index.
+__global__ __launch_bounds__(256) void k_bucket_scatter(const BucketParams p, const int32_t* __restrict__ offs) {
+    __shared__ int wcount[4][32];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const long j = (long)blockIdx.x * 256 + tid;
+    const bool valid = j < p.n_obj;
+    const int key = valid ? bucket_key(p.h_pref[j], p.status[j], p.n_buckets, p.h_ref) : -1;
+    const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int rank = 0;
+    for (int k = 0; k < p.n_buckets; ++k) {
+        const unsigned long long m = __ballot(key == k);
+        if (key == k) rank = __popcll(m & lt);
+        if (lane == 0) wcount[wid][k] = __popcll(m);
+    }
+    __syncthreads();
+    if (valid) {
+        int before = 0;
+        for (int w = 0; w < wid; ++w) before += wcount[w][key];
+        const int pos = offs[(size_t)key * gridDim.x + blockIdx.x] + before + rank;
+        p.perm[pos] = (int32_t)j;
+    }
+}
+
+__global__ void k_hpref_init(const double* __restrict__ x0, double* __restrict__ h_pref, int n, double mu) {
+    const long j = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const double r = sqrt(dot3(x0 + 6 * j, x0 + 6 * j));
+    h_pref[j] = 0.05 * sqrt(r * r * r / mu);
+}
+
+}  // namespace
+
+hipError_t launch_nbody(const NbodyParams& p, int block, hipStream_t s) {
+    const size_t lds = ((size_t)p.eph.n_body * p.max_win_segs * 3 * p.eph.deg1 +
+                        (size_t)(block / kWave) * kNodes * p.eph.n_body * 6) * sizeof(double);
+    const int grid = (int)((p.n_obj + block - 1) / block);
+    if (grid == 0) return hipSuccess;
+    switch (block) {
+        case 64: hipLaunchKernelGGL(k_nbody<64>, dim3(grid), dim3(64), lds, s, p); break;
+        case 128: hipLaunchKernelGGL(k_nbody<128>, dim3(grid), dim3(128), lds, s, p); break;
+        case 256: hipLaunchKernelGGL(k_nbody<256>, dim3(grid), dim3(256), lds, s, p); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_hpref_init(const double* x0, double* h_pref, int n, double mu, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_hpref_init, dim3((n + 255) / 256), dim3(256), 0, s, x0, h_pref, n, mu);
+    return hipGetLastError();
+}
+
+hipError_t launch_bucket(const BucketParams& p, hipStream_t s) {
+    const int nblk = (p.n_obj + 255) / 256;
+    if (nblk == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bucket_count, dim3(nblk), dim3(256), 0, s, p);
+    // offsets are written after the counts (bucket-major), total at the end
+    int32_t* offs = p.counts + (size_t)p.n_buckets * nblk;
+    void* scratch = offs + (size_t)p.n_buckets * nblk + 1;
+    hipError_t e = exclusive_scan_i32(p.counts, offs, (int64_t)p.n_buckets * nblk, scratch, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_bucket_scatter, dim3(nblk), dim3(256), 0, s, p, (const int32_t*)offs);
+    return hipGetLastError();
+}
+
+size_t bucket_scratch_ints(int64_t n_obj, int n_buckets) {
+    const int64_t nblk = (n_obj + 255) / 256;
+    return (size_t)(2 * n_buckets * nblk + 1) + scan_scratch_bytes(n_buckets * nblk) / sizeof(int32_t) + 64;
+}
+
+}  // namespace kete

@@ -1,0 +1,132 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, it
+exports every function declared in include/kete_mi.h, host batching
+matches the oracle's batching rule, and invalid arguments are rejected
+before any device work."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2509_04666_amd import _lib, api
+from paper_2509_04666_amd import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for fn in os.listdir(inc):
+        if fn.endswith(".h"):
+            src = open(os.path.join(inc, fn)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names |= set(re.findall(r"\b(kete_\w+)\s*\(", src))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.lib()
+    declared = _declared_functions()
+    assert len(declared) >= 10
+    for name in declared:
+        assert hasattr(L, name), name
+    assert set(_lib.exported_symbols()) == declared
+
+
+def test_make_batches_matches_oracle(orc):
+    rng = np.random.default_rng(1)
+    for t in (rng.uniform(0, 40, 500), np.round(rng.uniform(0, 10, 300), 1), np.array([5.0]), np.zeros(7)):
+        o1, off1, tr1 = api.make_batches(t, 3.0)
+        o2, off2, tr2 = orc.make_batches(t, 3.0)
+        np.testing.assert_array_equal(o1, o2)
+        np.testing.assert_array_equal(off1, off2)
+        np.testing.assert_array_equal(tr1, tr2)
+
+
+def test_make_batches_empty_and_errors():
+    o, off, tr = api.make_batches(np.zeros(0), 3.0)
+    assert off.tolist() == [0] and tr.size == 0
+    with pytest.raises(_lib.KeteError) as e:
+        api.make_batches(np.array([1.0, np.nan]), 3.0)
+    assert e.value.code == _lib.KETE_EINVAL
+
+
+def _host_ephem():
+    e = synth.tiny_case(n_obj=1, n_frames=1).ephem
+    gm = np.ascontiguousarray(e.gm)
+    fl = np.ascontiguousarray(e.flags)
+    # coefficient pointer is never dereferenced on these error paths
+    et = _lib.EphemT(e.n_body, e.n_seg, e.degree, 0, e.t_start, e.seg_days, 0x1000,
+                     gm.ctypes.data_as(C.POINTER(C.c_double)), fl.ctypes.data_as(C.POINTER(C.c_uint32)))
+    return e, et, (gm, fl)
+
+
+def test_propagate_argument_errors():
+    L = _lib.lib()
+    e, et, keep = _host_ephem()
+    o = api.default_opts()
+    fake = C.c_void_p(0x1000)
+    t_out = np.array([5.0, 10.0])
+    tp = t_out.ctypes.data_as(C.c_void_p)
+    # ERANGE: epoch beyond the ephemeris
+    bad = np.array([5.0, e.t_end + 1.0])
+    rc = L.kete_propagate_nbody(C.byref(et), fake, 0.0, 10, bad.ctypes.data_as(C.c_void_p), 2, fake, fake, None,
+                                C.byref(o), fake, 1 << 30, None)
+    assert rc == _lib.KETE_ERANGE
+    assert b"outside ephemeris" in L.kete_last_error()
+    # ERANGE: t0 before the ephemeris
+    rc = L.kete_propagate_nbody(C.byref(et), fake, e.t_start - 1.0, 10, tp, 2, fake, fake, None, C.byref(o),
+                                fake, 1 << 30, None)
+    assert rc == _lib.KETE_ERANGE
+    # EINVAL: non-monotone epochs, null pointers, bad block size, too many bodies
+    nm = np.array([10.0, 5.0])
+    assert L.kete_propagate_nbody(C.byref(et), fake, 0.0, 10, nm.ctypes.data_as(C.c_void_p), 2, fake, fake, None,
+                                  C.byref(o), fake, 1 << 30, None) == _lib.KETE_EINVAL
+    assert L.kete_propagate_nbody(C.byref(et), None, 0.0, 10, tp, 2, fake, fake, None, C.byref(o), fake, 1 << 30,
+                                  None) == _lib.KETE_EINVAL
+    o2 = api.default_opts(block=96)
+    assert L.kete_propagate_nbody(C.byref(et), fake, 0.0, 10, tp, 2, fake, fake, None, C.byref(o2), fake, 1 << 30,
+                                  None) == _lib.KETE_EINVAL
+    et2 = _lib.EphemT(17, et.n_seg, et.degree, 0, et.t_start, et.seg_days, 0x1000, et.gm, et.flags)
+    assert L.kete_propagate_nbody(C.byref(et2), fake, 0.0, 10, tp, 2, fake, fake, None, C.byref(o), fake, 1 << 30,
+                                  None) == _lib.KETE_EINVAL
+    # EWORKSPACE
+    need = L.kete_propagate_workspace_size(10, 2, C.byref(o))
+    assert need > 0
+    assert L.kete_propagate_nbody(C.byref(et), fake, 0.0, 10, tp, 2, fake, fake, None, C.byref(o), fake, need - 1,
+                                  None) == _lib.KETE_EWORKSPACE
+    # empty input is a no-op
+    assert L.kete_propagate_nbody(C.byref(et), None, 0.0, 0, tp, 2, None, None, None, C.byref(o), None, 0,
+                                  None) == _lib.KETE_OK
+
+
+def test_fov_argument_errors():
+    L = _lib.lib()
+    e, et, keep = _host_ephem()
+    o = api.default_opts()
+    fake = C.c_void_p(0x1000)
+    n = C.c_int64(0)
+    fr = _lib.FramesT(10, 0, 0, 0x1000, 0x1000, 0x1000)
+    assert L.kete_fov_check(C.byref(et), fake, None, 10, 2, fake, fake, fake, C.byref(fr), C.byref(o), fake, fake,
+                            fake, 10, C.byref(n), fake, 1 << 30, None) == _lib.KETE_EINVAL
+    fr = _lib.FramesT(10, 1, 0, 0x1000, 0x1000, 0x1000)
+    assert L.kete_fov_check(C.byref(et), fake, None, 10, 2, fake, fake, fake, C.byref(fr), C.byref(o), fake, fake,
+                            fake, 10, None, fake, 1 << 30, None) == _lib.KETE_EINVAL
+    need = L.kete_fov_workspace_size(10, 10, 2, 1, 10, C.byref(o))
+    assert need > 0
+    assert L.kete_fov_check(C.byref(et), fake, None, 10, 2, fake, fake, fake, C.byref(fr), C.byref(o), fake, fake,
+                            fake, 10, C.byref(n), fake, need - 1, None) == _lib.KETE_EWORKSPACE
+    # no objects / frames: nothing to do
+    assert L.kete_fov_check(C.byref(et), None, None, 0, 2, None, None, None, C.byref(fr), C.byref(o), None, None,
+                            None, 0, C.byref(n), None, 0, None) == _lib.KETE_OK
+    assert n.value == 0
+
+
+def test_ephem_eval_range_check():
+    L = _lib.lib()
+    e, et, keep = _host_ephem()
+    t = np.array([e.t_end + 0.5])
+    rc = L.kete_ephem_eval(C.byref(et), C.c_void_p(0x1000), t.ctypes.data_as(C.c_void_p), 1, C.c_void_p(0x1000), None)
+    assert rc == _lib.KETE_ERANGE

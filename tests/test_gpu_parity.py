@@ -1,0 +1,305 @@
+"""GPU parity tests: every kernel of the path, called through the C ABI,
+against the CPU oracle on the same seeded inputs.
+
+Tolerances: positions within 1e-10 au after a year of integration; the
+light-time direction from a given state within 1e-12 rad; pair sets
+identical except pairs whose oracle edge distance is below 1 mas."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2509_04666_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+MAS = math.radians(1.0 / 3.6e6)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2509_04666_amd import api
+    return torch, api
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _dev_x(torch, x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64).cuda()
+
+
+# ---------------------------------------------------------------- ephemeris
+def test_ephem_eval_matches_oracle(torch_cuda, orc):
+    torch, api = torch_cuda
+    case = synth.survey_case(n_obj=1, n_frames=0)
+    e = case.ephem
+    rng = np.random.default_rng(11)
+    joints = e.t_start + e.seg_days * np.arange(1, e.n_seg)
+    t = np.concatenate([rng.uniform(e.t_start, e.t_end, 300), joints, [e.t_start, e.t_end]])
+    out = api.ephem_eval(api.DeviceEphemeris.from_synth(e), t).cpu().numpy()
+    err_p = err_v = 0.0
+    for q, tq in enumerate(t):
+        for b in range(e.n_body):
+            st, p, v = orc.cheb(e, b, tq)
+            assert st == 0
+            err_p = max(err_p, np.max(np.abs(out[q, b, :3] - p)))
+            err_v = max(err_v, np.max(np.abs(out[q, b, 3:] - v)))
+    _say(f"ephem max |dp| {err_p:.3e} au, |dv| {err_v:.3e} au/d")
+    assert err_p < 1e-13 and err_v < 1e-14
+
+
+# ---------------------------------------------------------------- light time
+def test_lighttime_matches_oracle(torch_cuda, orc):
+    torch, api = torch_cuda
+    case = synth.survey_case(n_obj=300, n_frames=0, neo_frac=0.2)
+    rng = np.random.default_rng(12)
+    t_ref = 40.0
+    xs, st, _ = orc.propagate(case.ephem, case.x0, 0.0, [t_ref])
+    states = xs[0]
+    t_obs = t_ref + rng.uniform(-1.6, 1.6, 12)
+    obs = synth.circular_observer(case.model, t_obs)
+    eph = api.DeviceEphemeris.from_synth(case.ephem)
+    d, tau = api.lighttime_directions(eph, _dev_x(torch, states), t_ref, _dev_x(torch, t_obs), _dev_x(torch, obs))
+    d = d.cpu().numpy(); tau = tau.cpu().numpy()
+    worst_ang = worst_tau = 0.0
+    for q in range(t_obs.size):
+        dref, tref = orc.directions(case.ephem, states, t_ref, t_obs[q], obs[q])
+        cosang = np.sum(d[q] * dref, 1) / np.linalg.norm(d[q], axis=1) / np.linalg.norm(dref, axis=1)
+        ang = np.arccos(np.clip(cosang, -1, 1))
+        cr = np.linalg.norm(np.cross(d[q], dref), axis=1) / np.linalg.norm(d[q], axis=1) / np.linalg.norm(dref, axis=1)
+        worst_ang = max(worst_ang, np.max(np.minimum(ang, cr)))
+        worst_tau = max(worst_tau, np.max(np.abs(tau[q] - tref)))
+        np.testing.assert_allclose(d[q], dref, rtol=0, atol=1e-13)
+    _say(f"light-time max angle {worst_ang:.3e} rad, max |dtau| {worst_tau:.3e} d")
+    assert worst_ang < 1e-12 and worst_tau < 1e-15
+
+
+# ---------------------------------------------------------------- propagation
+def _propagate_both(torch, api, orc, ephem, x0, t0, t_out, **opts):
+    eph = api.DeviceEphemeris.from_synth(ephem)
+    o = api.default_opts(**opts)
+    xg, sg = api.propagate(eph, _dev_x(torch, x0), t0, t_out, o)
+    xo, so, _ = orc.propagate(ephem, x0, t0, t_out)
+    return xg.cpu().numpy(), sg.cpu().numpy(), xo, so
+
+
+def test_propagate_sun_only_one_year(torch_cuda, orc):
+    torch, api = torch_cuda
+    rng = np.random.default_rng(13)
+    el = np.concatenate([synth.main_belt_elements(rng, 200), synth.neo_elements(rng, 56)])
+    x0 = synth.elements_to_state(*[el[:, k] for k in range(6)], synth.GM_SUN)
+    eph = synth.sun_only_ephemeris(-8.0, 60)
+    t_out = np.arange(30.0, 366.0, 30.0)
+    xg, sg, xo, so = _propagate_both(torch, api, orc, eph, x0, 0.0, t_out)
+    assert np.all(sg == 0) and np.all(so == 0)
+    err = np.max(np.abs(xg[..., :3] - xo[..., :3]))
+    _say(f"sun-only 1 yr max |dx| {err:.3e} au")
+    assert err < 1e-10
+
+
+def test_propagate_tiny_config(torch_cuda, orc):
+    torch, api = torch_cuda
+    case = synth.tiny_case(n_obj=1000, n_frames=100)
+    order, off, t_ref = orc.make_batches(case.frames.t)
+    xg, sg, xo, so = _propagate_both(torch, api, orc, case.ephem, case.x0, 0.0, t_ref)
+    assert np.all(sg == 0) and np.all(so == 0)
+    err = np.max(np.abs(xg[..., :3] - xo[..., :3]))
+    _say(f"tiny config ({t_ref.size} epochs) max |dx| {err:.3e} au")
+    assert err < 1e-10
+
+
+def test_propagate_survey_mix_one_year(torch_cuda, orc):
+    torch, api = torch_cuda
+    case = synth.survey_case(n_obj=3000, n_frames=0, neo_frac=0.05)
+    t_out = np.arange(1.5, 365.25, 3.0)
+    xg, sg, xo, so = _propagate_both(torch, api, orc, case.ephem, case.x0, 0.0, t_out)
+    ok = (sg == 0) & (so == 0)
+    assert ok.mean() > 0.99
+    err = np.abs(xg[..., :3] - xo[..., :3]).max(axis=(0, 2))
+    _say(f"survey mix 1 yr: max |dx| {err[ok].max():.3e} au, status gpu {np.bincount(sg)}, oracle {np.bincount(so)}")
+    assert err[ok].max() < 1e-10
+
+
+def test_propagate_backward(torch_cuda, orc):
+    torch, api = torch_cuda
+    model = synth.PlanetModel.make()
+    e = synth.make_ephemeris(model, -216.0, 40)
+    rng = np.random.default_rng(14)
+    x0, _, _ = synth.make_population(rng, model, 500, 0.1, 0.0)
+    t_out = np.array([-3.0, -50.0, -120.5, -200.0])
+    xg, sg, xo, so = _propagate_both(torch, api, orc, e, x0, 0.0, t_out)
+    assert np.all(sg == 0) and np.all(so == 0)
+    err = np.max(np.abs(xg[..., :3] - xo[..., :3]))
+    _say(f"backward 200 d max |dx| {err:.3e} au")
+    assert err < 1e-10
+
+
+def test_propagate_configuration_invariance(torch_cuda):
+    torch, api = torch_cuda
+    case = synth.survey_case(n_obj=777, n_frames=0, neo_frac=0.2)
+    eph = api.DeviceEphemeris.from_synth(case.ephem)
+    x0 = _dev_x(torch, case.x0)
+    t_out = np.arange(3.0, 100.0, 3.0)
+    ref, st = api.propagate(eph, x0, 0.0, t_out, api.default_opts())
+    ref2, _ = api.propagate(eph, x0, 0.0, t_out, api.default_opts())
+    assert torch.equal(ref, ref2), "propagation is not deterministic"
+    for kw in (dict(n_buckets=1), dict(block=64), dict(block=128, n_buckets=4), dict(rebucket_epochs=1),
+               dict(window_segs=1), dict(rebucket_epochs=0)):
+        x, s = api.propagate(eph, x0, 0.0, t_out, api.default_opts(**kw))
+        d = (x - ref).abs().max().item()
+        _say(f"config {kw}: max |dx| vs default {d:.3e}")
+        assert d < 1e-11
+        assert torch.equal(s, st)
+
+
+def test_propagate_ragged_sizes(torch_cuda, orc):
+    torch, api = torch_cuda
+    case = synth.survey_case(n_obj=130, n_frames=0, neo_frac=0.3)
+    t_out = [2.0, 9.5]
+    for n in (1, 63, 65, 130):
+        xg, sg, xo, so = _propagate_both(torch, api, orc, case.ephem, case.x0[:n], 0.0, t_out)
+        assert np.max(np.abs(xg - xo)) < 1e-12, n
+    eph = api.DeviceEphemeris.from_synth(case.ephem)
+    x, s = api.propagate(eph, torch.zeros((0, 6), dtype=torch.float64, device="cuda"), 0.0, t_out)
+    assert x.shape == (2, 0, 6)
+
+
+def test_propagate_status_codes(torch_cuda, orc):
+    torch, api = torch_cuda
+    case = synth.survey_case(n_obj=200, n_frames=0)
+    x0 = case.x0.copy()
+    x0[7] = np.nan
+    eph = api.DeviceEphemeris.from_synth(case.ephem)
+    x, s = api.propagate(eph, _dev_x(torch, x0), 0.0, [10.0, 20.0])
+    s = s.cpu().numpy(); x = x.cpu().numpy()
+    assert s[7] == 1 and np.all(np.isnan(x[:, 7]))
+    good = np.arange(200) != 7
+    assert np.all(s[good] == 0)
+    xo, so, _ = orc.propagate(case.ephem, case.x0[good], 0.0, [10.0, 20.0])
+    assert np.max(np.abs(x[:, good] - xo)) < 1e-12
+    _, s2 = api.propagate(eph, _dev_x(torch, case.x0), 0.0, [300.0], api.default_opts(max_steps=3))
+    assert np.all(s2.cpu().numpy() == 3)
+    _, s3 = api.propagate(eph, _dev_x(torch, case.x0), 0.0, [300.0], api.default_opts(h_min=200.0))
+    assert np.all(s3.cpu().numpy() == 2)
+
+
+# ---------------------------------------------------------------- FoV
+def _pair_set(pf, ps, po):
+    return set(zip(np.asarray(pf).tolist(), np.asarray(ps).tolist(), np.asarray(po).tolist()))
+
+
+def _compare_pairs(gpu, orc_pairs, edge, label):
+    g = _pair_set(*gpu)
+    o = _pair_set(*orc_pairs)
+    near = {k for k, e in zip(zip(*[np.asarray(a).tolist() for a in orc_pairs]), edge) if abs(e) < MAS}
+    missing = o - g - near
+    extra = g - o
+    _say(f"{label}: oracle {len(o)} pairs, gpu {len(g)}, missing {len(missing)}, extra {len(extra)}")
+    assert not missing, sorted(missing)[:10]
+    # an extra GPU pair must sit within 1 mas of an edge of its frame
+    return extra
+
+
+def _edge_of(orc, ephem, x_epoch, order, off, t_ref, fr, pair):
+    f, s, j = pair
+    q = int(np.nonzero(order == f)[0][0])
+    b = int(np.searchsorted(off, q, side="right") - 1)
+    st, d, tau, _ = orc.lighttime(ephem, t_ref[b], x_epoch[b, j], fr.t[f], fr.obs[f])
+    ins, edge = orc.inside(fr.normals[f], d)
+    return edge[s]
+
+
+def _fov_case(torch, api, orc, case, x_epoch_host, order, off, t_ref, opts=None, status=None):
+    eph = api.DeviceEphemeris.from_synth(case.ephem)
+    fr = api.DeviceFrames.from_synth(case.frames)
+    b = api.Batches.from_host(order.astype(np.int32), off.astype(np.int32), t_ref)
+    pf, ps, po, stats = api.fov_check(eph, _dev_x(torch, x_epoch_host), b, fr, status, opts, return_stats=True)
+    _say(f"fov stats (candidates, exact, brute-force objects): {stats[:3].tolist()}")
+    return pf.cpu().numpy(), ps.cpu().numpy(), po.cpu().numpy()
+
+
+def test_fov_given_oracle_states(torch_cuda, orc):
+    torch, api = torch_cuda
+    case = synth.tiny_case(n_obj=1000, n_frames=100, n_targeted=400)
+    fr = case.frames
+    order, off, t_ref = orc.make_batches(fr.t)
+    xe, st, _ = orc.propagate(case.ephem, case.x0, 0.0, t_ref)
+    opairs = orc.fov(case.ephem, xe, st, order, off, t_ref, fr.t, fr.obs, fr.normals)
+    gp = _fov_case(torch, api, orc, case, xe, order, off, t_ref)
+    assert np.all(np.diff(gp[0].astype(np.int64) * 2 ** 32 + gp[1].astype(np.int64) * 2 ** 25 + gp[2]) > 0)
+    extra = _compare_pairs(gp, opairs[:3], opairs[3], "tiny+targeted given oracle states")
+    for p in extra:
+        assert abs(_edge_of(orc, case.ephem, xe, order, off, t_ref, fr, p)) < MAS
+    assert len(opairs[0]) > 200
+
+
+def test_fov_full_chain_tiny(torch_cuda, orc):
+    torch, api = torch_cuda
+    case = synth.tiny_case(n_obj=1000, n_frames=100, n_targeted=300)
+    fr = case.frames
+    eph = api.DeviceEphemeris.from_synth(case.ephem)
+    pf, ps, po, xg, sg, bt = api.predict(eph, _dev_x(torch, case.x0), 0.0, api.DeviceFrames.from_synth(fr), fr.t)
+    order, off, t_ref = orc.make_batches(fr.t)
+    np.testing.assert_array_equal(bt.t_ref_host, t_ref)
+    xe, st, _ = orc.propagate(case.ephem, case.x0, 0.0, t_ref)
+    assert np.max(np.abs(xg.cpu().numpy() - xe)) < 1e-10
+    opairs = orc.fov(case.ephem, xe, st, order, off, t_ref, fr.t, fr.obs, fr.normals)
+    extra = _compare_pairs((pf.cpu().numpy(), ps.cpu().numpy(), po.cpu().numpy()), opairs[:3], opairs[3],
+                           "tiny full chain")
+    for p in extra:
+        assert abs(_edge_of(orc, case.ephem, xe, order, off, t_ref, fr, p)) < MAS
+
+
+def test_fov_survey_geometry(torch_cuda, orc):
+    torch, api = torch_cuda
+    case = synth.survey_case(n_obj=20000, n_frames=20000, span=20.0, neo_frac=0.05)
+    fr = case.frames
+    order, off, t_ref = orc.make_batches(fr.t)
+    eph = api.DeviceEphemeris.from_synth(case.ephem)
+    xg, sg = api.propagate(eph, _dev_x(torch, case.x0), 0.0, t_ref)
+    b = api.Batches.from_host(order.astype(np.int32), off.astype(np.int32), t_ref)
+    pf, ps, po, stats = api.fov_check(eph, xg, b, api.DeviceFrames.from_synth(fr), sg, return_stats=True)
+    _say(f"survey geometry stats {stats.tolist()}, pairs {pf.numel()}")
+    # oracle on a sample of objects, all frames
+    rng = np.random.default_rng(15)
+    sample = np.sort(rng.choice(case.x0.shape[0], 600, replace=False))
+    xe, st, _ = orc.propagate(case.ephem, case.x0[sample], 0.0, t_ref)
+    opf, ops, opo, oedge = orc.fov(case.ephem, xe, st, order, off, t_ref, fr.t, fr.obs, fr.normals)
+    opo = sample[opo]
+    keep = np.isin(po.cpu().numpy(), sample)
+    gp = (pf.cpu().numpy()[keep], ps.cpu().numpy()[keep], po.cpu().numpy()[keep])
+    extra = _compare_pairs(gp, (opf, ops, opo), oedge, "survey geometry sample")
+    assert len(extra) == 0 or all(abs(_edge_of(orc, case.ephem, xg.cpu().numpy(), order, off, t_ref, fr, p)) < 2 * MAS
+                                  for p in extra)
+
+
+def test_fov_capacity_and_empty(torch_cuda, orc):
+    torch, api = torch_cuda
+    from paper_2509_04666_amd import _lib
+    case = synth.tiny_case(n_obj=500, n_frames=50, n_targeted=100)
+    fr = case.frames
+    order, off, t_ref = orc.make_batches(fr.t)
+    xe, st, _ = orc.propagate(case.ephem, case.x0, 0.0, t_ref)
+    opairs = orc.fov(case.ephem, xe, st, order, off, t_ref, fr.t, fr.obs, fr.normals)
+    eph = api.DeviceEphemeris.from_synth(case.ephem)
+    b = api.Batches.from_host(order.astype(np.int32), off.astype(np.int32), t_ref)
+    with pytest.raises(_lib.KeteError) as e:
+        api.fov_check(eph, _dev_x(torch, xe), b, api.DeviceFrames.from_synth(fr), pairs_cap=3)
+    assert e.value.code == _lib.KETE_ECAPACITY
+    # objects far from every frame: no pairs
+    far = xe.copy()
+    far[..., :3] += 500.0
+    pf, ps, po = api.fov_check(eph, _dev_x(torch, far), b, api.DeviceFrames.from_synth(fr))
+    assert pf.numel() == 0
+    # failed objects are skipped
+    status = torch.zeros(500, dtype=torch.int32, device="cuda")
+    status[opairs[2]] = 1
+    pf, ps, po = api.fov_check(eph, _dev_x(torch, xe), b, api.DeviceFrames.from_synth(fr), status)
+    assert pf.numel() == 0
