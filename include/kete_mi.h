@@ -218,6 +218,15 @@ int kete_lighttime_directions(const kete_ephem_t *eph, const double *x_ref, doub
 int kete_ephem_eval(const kete_ephem_t *eph, const double *t, const double *t_host, int64_t n_q,
                     double *out, void *stream);
 
+/* Live kernel timing for measurement.  While enabled, every integrator
+ * and FoV-candidate launch made by the calling thread is bracketed by HIP
+ * events on the stream it is launched on.  kete_timing_read waits for
+ * those events and returns the summed milliseconds ms[k] and launch
+ * counts count[k] per kind k (0 integrator, 1 FoV candidates, 2 adjoint,
+ * 3 batched), then forgets them. */
+void kete_timing_enable(int on);
+int kete_timing_read(double ms[4], int64_t count[4]);
+
 #ifdef __cplusplus
 }
 #endif

@@ -67,6 +67,8 @@ SIGNATURES = {
                                             C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.POINTER(OptsT),
                                             C.c_void_p]),
     "kete_ephem_eval": (C.c_int, [C.POINTER(EphemT), C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
+    "kete_timing_enable": (None, [C.c_int]),
+    "kete_timing_read": (C.c_int, [C.c_void_p, C.c_void_p]),
 }
 
 _lib = None

@@ -227,7 +227,33 @@ std::vector<Window> plan_windows(const kete_ephem_t* e, double t0, const double*
 
 }  // namespace
 
+namespace {
+struct TimedRec { int kind; hipEvent_t a, b; };
+thread_local bool g_timing = false;
+thread_local std::vector<TimedRec> g_timed;
+thread_local std::vector<hipEvent_t> g_event_pool;
+
+hipEvent_t pool_event() {
+    if (!g_event_pool.empty()) { hipEvent_t e = g_event_pool.back(); g_event_pool.pop_back(); return e; }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+}  // namespace
+
 namespace kete {
+TimedScope::TimedScope(int k, hipStream_t s) : kind(k), stream(s), stop(nullptr) {
+    if (!g_timing) return;
+    hipEvent_t a = pool_event(), b = pool_event();
+    if (!a || !b) return;
+    hipEventRecord(a, s);
+    g_timed.push_back({k, a, b});
+    stop = b;
+}
+TimedScope::~TimedScope() {
+    if (stop) hipEventRecord((hipEvent_t)stop, stream);
+}
+
 const RadauConst& radau_const() {
     static RadauConst rc = build_radau();
     return rc;
@@ -271,7 +297,8 @@ int kete_make_batches(const double* t, int64_t n_frames, double span, int32_t* f
         if (!std::isfinite(t[i])) return fail(KETE_EINVAL, "t[%lld] is not finite", (long long)i);
     std::vector<int32_t> idx(n_frames);
     std::iota(idx.begin(), idx.end(), 0);
-    std::stable_sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) { return t[a] < t[b]; });
+    if (!std::is_sorted(t, t + n_frames))
+        std::stable_sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) { return t[a] < t[b]; });
     int64_t nb = 0;
     batch_off[0] = 0;
     int64_t i = 0;
@@ -405,10 +432,18 @@ int kete_propagate_nbody(const kete_ephem_t* eph, const double* x0, double t0, i
         P.win = dwin + first;
         P.n_win = last - first + 1;
         P.first_launch = (e0 == 0);
-        HIPCHK(launch_nbody(P, opts->block, s));
+        {
+            TimedScope ts(kTimeNbody, s);
+            HIPCHK(launch_nbody(P, opts->block, s));
+        }
         first = last + 1;
     }
     return KETE_OK;
+}
+
+// Exact-test candidates kept between the two FoV kernels.
+static int64_t cand_capacity(int64_t n_frames, int64_t pairs_cap) {
+    return std::max<int64_t>(1 << 16, std::max<int64_t>(16 * n_frames, 8 * pairs_cap));
 }
 
 static int grid_dims(const kete_opts_t* o, int64_t n_batch, int& G, double& L) {
@@ -441,6 +476,14 @@ size_t kete_fov_workspace_size(int64_t n_obj, int64_t n_frames, int64_t n_batch,
     c.take<int32_t>((size_t)n_frames + 1);
     c.take<unsigned long long>((size_t)std::max<int64_t>(pairs_cap, 1));
     c.take<char>(std::max(scan_scratch_bytes(nkeys), scan_scratch_bytes(n_frames)));
+    c.take<unsigned long long>((size_t)cand_capacity(n_frames, pairs_cap));
+    c.take<int32_t>((size_t)n_frames);
+    c.take<int32_t>((size_t)(n_batch * n_obj));     // object cell keys
+    c.take<int32_t>((size_t)(n_batch * n_obj));     // objects sorted by cell
+    c.take<int32_t>((size_t)(nkeys + n_batch) + 1); // object cell starts and counts
+    c.take<int32_t>((size_t)(nkeys + n_batch) + 1);
+    c.take<unsigned long long>((size_t)(n_batch * n_obj));   // wide objects
+    c.take<char>(scan_scratch_bytes(nkeys + n_batch));
     return c.off;
 }
 
@@ -460,6 +503,7 @@ int kete_fov_check(const kete_ephem_t* eph, const double* x_epoch, const int32_t
     if (!frames) return fail(KETE_EINVAL, "frames is null");
     if (n_obj < 0 || n_obj > KETE_MAX_OBJ) return fail(KETE_EINVAL, "n_obj %lld outside 0..%d", (long long)n_obj, KETE_MAX_OBJ);
     if (n_batch < 0 || frames->n_frames < 0 || frames->n_frames > INT32_MAX) return fail(KETE_EINVAL, "bad sizes");
+    if ((double)n_batch * (double)n_obj >= 2.0e9) return fail(KETE_EINVAL, "n_batch x n_obj must stay below 2^31");
     if (frames->n_sub < 1 || frames->n_sub > KETE_MAX_SUB) return fail(KETE_EINVAL, "n_sub %d outside 1..%d", frames->n_sub, KETE_MAX_SUB);
     if (pairs_cap < 0) return fail(KETE_EINVAL, "pairs_cap < 0");
     if (n_obj == 0 || n_batch == 0 || frames->n_frames == 0) { std::memset(g_fov_stats, 0, sizeof(g_fov_stats)); return KETE_OK; }
@@ -491,6 +535,15 @@ int kete_fov_check(const kete_ephem_t* eph, const double* x_epoch, const int32_t
     int32_t* fstart = c.take<int32_t>((size_t)F + 1);
     unsigned long long* sorted = c.take<unsigned long long>((size_t)std::max<int64_t>(pairs_cap, 1));
     void* scan_scratch = c.take<char>(std::max(scan_scratch_bytes(nkeys), scan_scratch_bytes(F)));
+    P.cand_cap = cand_capacity(F, pairs_cap);
+    P.cand = c.take<unsigned long long>((size_t)P.cand_cap);
+    P.frame_batch = c.take<int32_t>((size_t)F);
+    int32_t* okey = c.take<int32_t>((size_t)(n_batch * n_obj));
+    int32_t* osorted = c.take<int32_t>((size_t)(n_batch * n_obj));
+    int32_t* ostart = c.take<int32_t>((size_t)(nkeys + n_batch) + 1);
+    int32_t* ocnt = c.take<int32_t>((size_t)(nkeys + n_batch) + 1);
+    P.wide = c.take<unsigned long long>((size_t)(n_batch * n_obj));
+    void* oscan = c.take<char>(scan_scratch_bytes(nkeys + n_batch));
 
     P.eph = E;
     P.x_epoch = x_epoch;
@@ -509,28 +562,66 @@ int kete_fov_check(const kete_ephem_t* eph, const double* x_epoch, const int32_t
     P.inv_L = 1.0 / L;
     P.n_pairs = counters;
     P.stats = counters + 1;
+    P.n_cand = counters + 5;
     P.cap = pairs_cap;
     P.mu = E.gm[0];
     P.smu = std::sqrt(E.gm[0]);
     P.c_light = cl;
     P.lt_tol = opts->lt_tol > 0 ? opts->lt_tol : 1e-15;
     P.lt_iter = opts->lt_iter > 0 ? opts->lt_iter : 10;
-    P.max_cells = 64;
+    P.max_cells = 1024;
     P.sin_overflow = 0.5;
 
     hipStream_t s = (hipStream_t)stream;
     HIPCHK(hipMemsetAsync(counters, 0, 8 * sizeof(unsigned long long), s));
     HIPCHK(fov_prepare(P, qkey, cnt, cnt, nkeys, scan_scratch, s));
-    HIPCHK(fov_candidates(P, opts->fov_block, s));
+    P.n_wide = counters + 6;
+    HIPCHK(fov_sort_objects(P, okey, ocnt, ostart, osorted, oscan, s));
+    P.obj_sorted = osorted;
+    {
+        TimedScope ts(kTimeFov, s);
+        HIPCHK(fov_candidates(P, opts->fov_block, s));
+        HIPCHK(fov_exact(P, s));
+    }
     unsigned long long host_counters[8];
     HIPCHK(hipMemcpyAsync(host_counters, counters, sizeof(host_counters), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     for (int i = 0; i < 4; ++i) g_fov_stats[i] = host_counters[1 + i];
     const int64_t np = (int64_t)host_counters[0];
     *n_pairs = np;
+    if ((int64_t)host_counters[5] > P.cand_cap)
+        return fail(KETE_ECAPACITY, "%llu exact-test candidates exceed the workspace capacity %lld",
+                    host_counters[5], (long long)P.cand_cap);
     if (np > pairs_cap) return fail(KETE_ECAPACITY, "%lld pairs exceed pairs_cap %lld", (long long)np, (long long)pairs_cap);
     HIPCHK(fov_sort(P.pairs, np, F, fcnt, fstart, sorted, scan_scratch, pf, ps, po, s));
     return KETE_OK;
+}
+
+// Live kernel timing: while enabled, every integrator / FoV launch made by
+// this thread is bracketed by HIP events on its stream.
+void kete_timing_enable(int on) {
+    g_timing = on != 0;
+}
+
+// Waits for the recorded events, returns the summed milliseconds and the
+// launch count per kind (0 integrator, 1 FoV candidates, 2 adjoint,
+// 3 batched) and forgets them.
+int kete_timing_read(double ms[4], int64_t count[4]) {
+    for (int k = 0; k < 4; ++k) { ms[k] = 0.0; count[k] = 0; }
+    int rc = KETE_OK;
+    for (auto& r : g_timed) {
+        float t = 0.0f;
+        if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) {
+            rc = fail(KETE_EDEVICE, "event timing failed");
+        } else {
+            ms[r.kind] += t;
+            count[r.kind] += 1;
+        }
+        g_event_pool.push_back(r.a);
+        g_event_pool.push_back(r.b);
+    }
+    g_timed.clear();
+    return rc;
 }
 
 // Counters of the last kete_fov_check on this thread: candidate frames

@@ -171,6 +171,7 @@ __global__ void k_frame_keys(const FovParams p, int32_t* __restrict__ qkey, int3
     const int cell = (cell_coord(c[0], p.inv_L, G) * G + cell_coord(c[1], p.inv_L, G)) * G + cell_coord(c[2], p.inv_L, G);
     const int key = lo * G * G * G + cell;
     qkey[q] = key;
+    p.frame_batch[f] = lo;
     atomicAdd(cnt + key, 1);
 }
 
@@ -191,50 +192,55 @@ struct SunLds {
     }
 };
 
-// Append a pair key with one atomic per wavefront.
-__device__ __forceinline__ void append_pair(const FovParams& p, unsigned long long key) {
+// Append a key to a bounded list with one atomic per wavefront: the
+// active lanes take consecutive slots in lane order (ballot + popcount).
+__device__ __forceinline__ void wave_append(unsigned long long* list, unsigned long long* count, int64_t cap,
+                                            unsigned long long key) {
     const unsigned long long m = __ballot(1);
     const int lane = threadIdx.x & 63;
     const int leader = __ffsll((long long)m) - 1;
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     unsigned long long base = 0;
-    if (lane == leader) base = atomicAdd(p.n_pairs, (unsigned long long)__popcll(m));
+    if (lane == leader) base = atomicAdd(count, (unsigned long long)__popcll(m));
     base = __shfl(base, leader, 64);
     const unsigned long long idx = base + __popcll(m & lt);
-    if (idx < (unsigned long long)p.cap) p.pairs[idx] = key;
+    if (idx < (unsigned long long)cap) list[idx] = key;
 }
 
-template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_fov(const FovParams p) {
-    __shared__ double sunL[kMaxSunSegs * 3 * (KETE_MAX_DEGREE + 1)];
-    const int b = blockIdx.y;
-    const double* bt = p.btab + kBatchStride * b;
-    const int slo = (int)bt[15], shi = (int)bt[16];
-    const int deg1 = p.eph.deg1;
-    if (shi - slo + 1 <= kMaxSunSegs) {
-        const int total = (shi - slo + 1) * 3 * deg1;
-        for (int i = threadIdx.x; i < total; i += BLOCK) sunL[i] = p.eph.coef[(size_t)slo * 3 * deg1 + i];
-    }
-    __syncthreads();
-    const int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (j >= p.n_obj) return;
-    if (p.status && p.status[j] != 0) return;
-    const double* st = p.x_epoch + ((size_t)b * p.n_obj + j) * 6;
-    double x[3] = {st[0], st[1], st[2]}, v[3] = {st[3], st[4], st[5]};
-    if (!(isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]) && isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2])))
-        return;
-    // Sun segments of the batch from LDS; the brute-force path of far
-    // objects (light time above kMaxLightDays) reads the whole table.
-    const bool sun_in_lds = (shi - slo + 1) <= kMaxSunSegs;
-    SunLds sun = sun_in_lds ? SunLds{sunL, slo, shi, deg1, p.eph.t_start, p.eph.seg_days, p.eph.inv_seg}
-                            : SunLds{p.eph.coef, 0, p.eph.n_seg - 1, deg1, p.eph.t_start, p.eph.seg_days, p.eph.inv_seg};
-    const double tr = p.t_ref[b];
-    const double mu = p.mu, smu = p.smu, cl = p.c_light;
-    double r0[3], v0[3];
-    for (int c = 0; c < 3; ++c) { r0[c] = x[c] - bt[c]; v0[c] = v[c] - bt[3 + c]; }
-    const double Dobs = bt[9], Delta = bt[10], cosRm = bt[11], sinRm = bt[12], Vsun = bt[13], Asun = bt[14];
+// Everything one (object, batch) needs to skip frames it cannot reach.
+struct ObjBounds {
+    double x[3], v[3];        // barycentric state at the batch epoch
+    double dh[3];             // unit direction from the batch's mean observer
+    double sth, cth;          // sin/cos of the cap on the direction's motion
+    double taumax;            // light-time bound
+    double a2b, vbn;          // heliocentric acceleration bound, |v|
+    int lo[3], hi[3];         // grid box of the cap (valid when !overflow)
+    int ncell;
+    bool lin_ok;              // the linear-motion test is valid
+    bool overflow;            // no usable cap: test every frame of the batch
+};
 
-    // motion bounds of the two-body conic
+// Rigorous motion bounds inside batch b (half-span Delta):
+//  - speed on the heliocentric conic <= perihelion speed mu (1 + e) / |r x v|,
+//    plus the Sun's speed bound;
+//  - light time tau <= (|d| + D_obs + V Delta) / (c - V);
+//  - |x_e - o_f - d_ref| <= V (Delta + tau) + D_obs, so the direction
+//    moves by at most asin of that over |d_ref|;
+//  - between the batch epoch and the emission time the heliocentric
+//    acceleration is at most mu / r_min^2 with r_min >= perihelion.
+// Returns false for failed or non-finite objects.
+__device__ __forceinline__ bool object_bounds(const FovParams& p, int b, int64_t j, ObjBounds& o) {
+    if (p.status && p.status[j] != 0) return false;
+    const double* st = p.x_epoch + ((size_t)b * p.n_obj + j) * 6;
+    for (int c = 0; c < 3; ++c) { o.x[c] = st[c]; o.v[c] = st[3 + c]; }
+    if (!(isfinite(o.x[0]) && isfinite(o.x[1]) && isfinite(o.x[2]) && isfinite(o.v[0]) && isfinite(o.v[1]) &&
+          isfinite(o.v[2])))
+        return false;
+    const double* bt = p.btab + kBatchStride * b;
+    const double mu = p.mu, cl = p.c_light;
+    const double Dobs = bt[9], Delta = bt[10], cosRm = bt[11], sinRm = bt[12], Vsun = bt[13];
+    double r0[3], v0[3];
+    for (int c = 0; c < 3; ++c) { r0[c] = o.x[c] - bt[c]; v0[c] = o.v[c] - bt[3 + c]; }
     const double r0n = sqrt(dot3(r0, r0));
     const double v2 = dot3(v0, v0);
     double hv[3];
@@ -244,107 +250,250 @@ __global__ __launch_bounds__(BLOCK) void k_fov(const FovParams p) {
     double ev[3];
     for (int c = 0; c < 3; ++c) ev[c] = ((v2 - mu / r0n) * r0[c] - rv * v0[c]) / mu;
     const double ecc = sqrt(dot3(ev, ev));
-    const double vp = (hn > 0.0) ? mu * (1.0 + ecc) / hn * (1.0 + 1e-12) : 1e300;   // perihelion speed
+    const double vp = (hn > 0.0) ? mu * (1.0 + ecc) / hn * (1.0 + 1e-12) : 1e300;
     const double q = (hn > 0.0) ? hn * hn / (mu * (1.0 + ecc)) * (1.0 - 1e-12) : 0.0;
     const double V = vp + Vsun;
-
     double dref[3];
-    for (int c = 0; c < 3; ++c) dref[c] = x[c] - bt[6 + c];
+    for (int c = 0; c < 3; ++c) dref[c] = o.x[c] - bt[6 + c];
     const double dn = sqrt(dot3(dref, dref));
-    const double dh[3] = {dref[0] / dn, dref[1] / dn, dref[2] / dn};
-    bool overflow = !(V < 0.5 * cl);
-    double taumax = 0.0, sth = 1.0, cth = 0.0;
-    if (!overflow) {
-        taumax = (dn + Dobs + V * Delta) / (cl - V) * (1.0 + 1e-12);
-        const double delta = V * (Delta + taumax) + Dobs + 1e-12;
-        sth = delta / dn;
-        if (!(sth < p.sin_overflow) || taumax > kMaxLightDays) overflow = true;
-        else cth = sqrt(1.0 - sth * sth);
+    for (int c = 0; c < 3; ++c) o.dh[c] = dref[c] / dn;
+    const bool bounded = (V < 0.5 * cl) && (dn > 0.0);
+    o.taumax = 0.0; o.sth = 1.0; o.cth = 0.0;
+    o.overflow = !bounded;
+    if (bounded) {
+        o.taumax = (dn + Dobs + V * Delta) / (cl - V) * (1.0 + 1e-12);
+        const double delta = V * (Delta + o.taumax) + Dobs + 1e-12;
+        o.sth = delta / dn;
+        if (!(o.sth < p.sin_overflow)) o.overflow = true;
+        else o.cth = sqrt(1.0 - o.sth * o.sth);
     }
-    // linear-prediction remainder terms
-    const double rmin = fmax(q, r0n - vp * (Delta + taumax));
-    const double a2b = (rmin > 0.0) ? mu / (rmin * rmin) : 1e300;
-    const double vbn = sqrt(dot3(v, v));
-
-    unsigned long long n_cand = 0, n_exact = 0;
-
-    auto test_frame = [&](int f) {
-        const double dt = p.ft[f] - tr;
-        const double* o = p.fobs + 3 * f;
-        const double* nrm = p.normals + (size_t)f * p.n_sub * 12;
-        // linear motion with a rigorous remainder bound
-        double ul[3];
-        for (int c = 0; c < 3; ++c) ul[c] = x[c] + v[c] * dt - o[c];
-        const double uln = sqrt(dot3(ul, ul));
-        const double ad = fabs(dt) + taumax;
-        const double eps = vbn * taumax + 0.5 * (a2b + Asun) * ad * ad + 1e-12;
-        const double eta = 2.0 * eps / uln;
-        bool maybe = false;
-        if (!(eta < 1.0) || overflow) {
-            maybe = true;
+    // the linear test also uses the Sun's acceleration bound, which covers
+    // light times up to kMaxLightDays
+    o.lin_ok = bounded && o.taumax <= kMaxLightDays;
+    const double rmin = fmax(q, r0n - vp * (Delta + o.taumax));
+    o.a2b = (rmin > 0.0) ? mu / (rmin * rmin) : 1e300;
+    o.vbn = sqrt(dot3(o.v, o.v));
+    o.ncell = 0;
+    if (!o.overflow) {
+        const double cosRT = cosRm * o.cth - sinRm * o.sth;      // cos(Rmax + theta)
+        if (!(cosRT > 0.0)) {
+            o.overflow = true;
         } else {
-            for (int s = 0; s < p.n_sub && !maybe; ++s) {
-                bool out = false;
-                for (int i = 0; i < 4; ++i) out |= dot3(nrm + 12 * s + 3 * i, ul) / uln <= -eta;
-                maybe = !out;
-            }
-        }
-        if (!maybe) return;
-        ++n_exact;
-        double d[3], tau, ve[3];
-        lighttime(sun, mu, smu, cl, p.lt_tol, p.lt_iter, tr, r0, v0, p.ft[f], o, d, tau, ve);
-        for (int s = 0; s < p.n_sub; ++s) {
-            const double* ns = nrm + 12 * s;
-            if (dot3(ns, d) > 0.0 && dot3(ns + 3, d) > 0.0 && dot3(ns + 6, d) > 0.0 && dot3(ns + 9, d) > 0.0) {
-                append_pair(p, ((unsigned long long)f << 32) | ((unsigned long long)s << 25) | (unsigned long long)j);
-            }
-        }
-    };
-
-    if (!overflow) {
-        const double cosRT = cosRm * cth - sinRm * sth;      // cos(Rmax + theta)
-        if (!(cosRT > 0.0)) overflow = true;
-        else {
             const double chord = sqrt(2.0 - 2.0 * cosRT) + 1e-9;
-            const int G = p.G;
-            int lo[3], hi[3];
-            int ncell = 1;
+            o.ncell = 1;
             for (int c = 0; c < 3; ++c) {
-                lo[c] = cell_coord(dh[c] - chord, p.inv_L, G);
-                hi[c] = cell_coord(dh[c] + chord, p.inv_L, G);
-                ncell *= hi[c] - lo[c] + 1;
+                o.lo[c] = cell_coord(o.dh[c] - chord, p.inv_L, p.G);
+                o.hi[c] = cell_coord(o.dh[c] + chord, p.inv_L, p.G);
+                o.ncell *= o.hi[c] - o.lo[c] + 1;
             }
-            if (ncell > p.max_cells) overflow = true;
-            else {
-                const int base = b * G * G * G;
-                for (int ix = lo[0]; ix <= hi[0]; ++ix)
-                    for (int iy = lo[1]; iy <= hi[1]; ++iy)
-                        for (int iz = lo[2]; iz <= hi[2]; ++iz) {
-                            const int key = base + (ix * G + iy) * G + iz;
-                            const int a0 = p.cell_start[key], a1 = p.cell_start[key + 1];
-                            for (int k = a0; k < a1; ++k) {
-                                const int f = p.cell_frames[k];
-                                const double* cp = p.fcap + 8 * f;
-                                const double thr = cp[3] * cth - cp[4] * sth;     // cos(R_f + theta)
-                                if (dot3(cp, dh) < thr - 1e-12) continue;
-                                ++n_cand;
-                                test_frame(f);
-                            }
-                        }
-            }
+            if (o.ncell > p.max_cells) o.overflow = true;
         }
     }
-    if (overflow) {
-        sun = SunLds{p.eph.coef, 0, p.eph.n_seg - 1, deg1, p.eph.t_start, p.eph.seg_days, p.eph.inv_seg};
-        for (int qq = p.batch_off[b]; qq < p.batch_off[b + 1]; ++qq) {
-            ++n_cand;
-            test_frame(p.frame_order[qq]);
+    return true;
+}
+
+constexpr int kNarrowCells = 27;
+
+__device__ __forceinline__ bool is_narrow(const ObjBounds& o) { return !o.overflow && o.ncell <= kNarrowCells; }
+
+// Cap test with the frame's own radius, then the linear-motion test with
+// its remainder bound; survivors become exact-test candidates.
+__device__ __forceinline__ bool frame_may_contain(const FovParams& p, const ObjBounds& o, int f, double tr,
+                                                  double Asun, unsigned long long& n_cand) {
+    const double* cp = p.fcap + 8 * f;
+    if (!o.overflow) {
+        const double thr = cp[3] * o.cth - cp[4] * o.sth;     // cos(R_f + theta)
+        if (dot3(cp, o.dh) < thr - 1e-12) return false;
+    }
+    ++n_cand;
+    if (!o.lin_ok) return true;
+    const double dt = p.ft[f] - tr;
+    const double* ob = p.fobs + 3 * f;
+    double ul[3];
+    for (int c = 0; c < 3; ++c) ul[c] = o.x[c] + o.v[c] * dt - ob[c];
+    const double uln = sqrt(dot3(ul, ul));
+    const double ad = fabs(dt) + o.taumax;
+    const double eps = o.vbn * o.taumax + 0.5 * (o.a2b + Asun) * ad * ad + 1e-12;
+    const double eta = 2.0 * eps / uln;
+    if (!(eta < 1.0)) return true;
+    const double* nrm = p.normals + (size_t)f * p.n_sub * 12;
+    for (int s = 0; s < p.n_sub; ++s) {
+        bool out = false;
+        for (int i = 0; i < 4; ++i) out |= dot3(nrm + 12 * s + 3 * i, ul) / uln <= -eta;
+        if (!out) return true;
+    }
+    return false;
+}
+
+// Narrow objects: one lane per (object, batch), objects of a batch in sky
+// cell order so that the lanes of a wavefront visit the same cells.
+// Wide objects are handed to k_fov_wide.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_fov(const FovParams p) {
+    const int b = blockIdx.y;
+    const int64_t pos = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const int64_t j = (pos < p.n_obj && p.obj_sorted) ? p.obj_sorted[(size_t)b * p.n_obj + pos] : pos;
+    unsigned long long n_cand = 0, n_exact = 0;
+    ObjBounds o;
+    const bool live = pos < p.n_obj && object_bounds(p, b, j, o);
+    if (live && !is_narrow(o)) {
+        wave_append(p.wide, p.n_wide, (int64_t)p.n_batch * p.n_obj,
+                    ((unsigned long long)b << 32) | (unsigned long long)j);
+    } else if (live) {
+        const double tr = p.t_ref[b];
+        const double Asun = p.btab[kBatchStride * b + 14];
+        const int G = p.G;
+        const int base = b * G * G * G;
+        for (int ix = o.lo[0]; ix <= o.hi[0]; ++ix)
+            for (int iy = o.lo[1]; iy <= o.hi[1]; ++iy)
+                for (int iz = o.lo[2]; iz <= o.hi[2]; ++iz) {
+                    const int key = base + (ix * G + iy) * G + iz;
+                    const int a0 = p.cell_start[key], a1 = p.cell_start[key + 1];
+                    for (int k = a0; k < a1; ++k) {
+                        const int f = p.cell_frames[k];
+                        if (frame_may_contain(p, o, f, tr, Asun, n_cand)) {
+                            ++n_exact;
+                            wave_append(p.cand, p.n_cand, p.cand_cap,
+                                        ((unsigned long long)f << 32) | (unsigned long long)j);
+                        }
+                    }
+                }
+    }
+    if (p.stats) {
+        unsigned long long a = n_cand, e = n_exact;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            a += __shfl_xor(a, off, 64);
+            e += __shfl_xor(e, off, 64);
+        }
+        if ((threadIdx.x & 63) == 0) {
+            atomicAdd(p.stats + 0, a);
+            atomicAdd(p.stats + 1, e);
+        }
+    }
+}
+
+// Wide objects: one wavefront per (object, batch); its lanes split the
+// object's grid cells, or every frame of the batch when no cap applies.
+__global__ __launch_bounds__(256) void k_fov_wide(const FovParams p) {
+    const int lane = threadIdx.x & 63;
+    const unsigned long long nw = *p.n_wide;
+    const int64_t n_items = (int64_t)(nw < (unsigned long long)p.n_batch * p.n_obj ? nw : p.n_batch * p.n_obj);
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    unsigned long long n_cand = 0, n_exact = 0, n_over = 0;
+    for (int64_t it = wave; it < n_items; it += n_waves) {
+        const unsigned long long w = p.wide[it];
+        const int b = (int)(w >> 32);
+        const int64_t j = (int64_t)(w & 0xffffffffull);
+        ObjBounds o;
+        if (!object_bounds(p, b, j, o)) continue;
+        const double tr = p.t_ref[b];
+        const double Asun = p.btab[kBatchStride * b + 14];
+        if (o.overflow) {
+            if (lane == 0) ++n_over;
+            for (int q = p.batch_off[b] + lane; q < p.batch_off[b + 1]; q += 64) {
+                const int f = p.frame_order[q];
+                if (frame_may_contain(p, o, f, tr, Asun, n_cand)) {
+                    ++n_exact;
+                    wave_append(p.cand, p.n_cand, p.cand_cap, ((unsigned long long)f << 32) | (unsigned long long)j);
+                }
+            }
+        } else {
+            const int G = p.G;
+            const int nx = o.hi[0] - o.lo[0] + 1, ny = o.hi[1] - o.lo[1] + 1, nz = o.hi[2] - o.lo[2] + 1;
+            const int base = b * G * G * G;
+            for (int c = lane; c < o.ncell; c += 64) {
+                const int ix = o.lo[0] + c / (ny * nz);
+                const int iy = o.lo[1] + (c / nz) % ny;
+                const int iz = o.lo[2] + c % nz;
+                (void)nx;
+                const int key = base + (ix * G + iy) * G + iz;
+                const int a0 = p.cell_start[key], a1 = p.cell_start[key + 1];
+                for (int k = a0; k < a1; ++k) {
+                    const int f = p.cell_frames[k];
+                    if (frame_may_contain(p, o, f, tr, Asun, n_cand)) {
+                        ++n_exact;
+                        wave_append(p.cand, p.n_cand, p.cand_cap,
+                                    ((unsigned long long)f << 32) | (unsigned long long)j);
+                    }
+                }
+            }
         }
     }
     if (p.stats) {
-        atomicAdd(p.stats + 0, n_cand);
-        atomicAdd(p.stats + 1, n_exact);
-        if (overflow) atomicAdd(p.stats + 2, 1ull);
+        unsigned long long a = n_cand, e = n_exact;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            a += __shfl_xor(a, off, 64);
+            e += __shfl_xor(e, off, 64);
+        }
+        if (lane == 0) {
+            atomicAdd(p.stats + 0, a);
+            atomicAdd(p.stats + 1, e);
+            atomicAdd(p.stats + 2, n_over);
+            atomicAdd(p.stats + 3, (unsigned long long)0);
+        }
+    }
+}
+
+// Sky cell of every (object, batch): direction from the batch's mean
+// observer, on the frame grid; wide and failed objects sort after the
+// narrow ones of their batch.
+__global__ void k_obj_keys(const FovParams p, int32_t* __restrict__ okey, int32_t* __restrict__ cnt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)p.n_batch * p.n_obj) return;
+    const int b = (int)(i / p.n_obj);
+    const int64_t j = i % p.n_obj;
+    ObjBounds o;
+    const int G = p.G, G3 = G * G * G;
+    int key;
+    if (object_bounds(p, b, j, o) && is_narrow(o)) {
+        const int cell = (cell_coord(o.dh[0], p.inv_L, G) * G + cell_coord(o.dh[1], p.inv_L, G)) * G +
+                         cell_coord(o.dh[2], p.inv_L, G);
+        key = b * (G3 + 1) + cell;
+    } else {
+        key = b * (G3 + 1) + G3;
+    }
+    okey[i] = key;
+    atomicAdd(cnt + key, 1);
+}
+
+__global__ void k_obj_scatter(const FovParams p, const int32_t* __restrict__ okey, const int32_t* __restrict__ start,
+                              int32_t* __restrict__ cursor, int32_t* __restrict__ sorted) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)p.n_batch * p.n_obj) return;
+    const int key = okey[i];
+    // positions are global in key order, so batch b occupies [b N, (b+1) N)
+    sorted[start[key] + atomicAdd(cursor + key, 1)] = (int32_t)(i % p.n_obj);
+}
+
+// Exact test of every candidate (one lane per candidate, grid-stride).
+__global__ __launch_bounds__(256) void k_fov_exact(const FovParams p) {
+    const unsigned long long nc = *p.n_cand;
+    const unsigned long long n = nc < (unsigned long long)p.cand_cap ? nc : (unsigned long long)p.cand_cap;
+    const EphemArgs& E = p.eph;
+    const SunLds sun{E.coef, 0, E.n_seg - 1, E.deg1, E.t_start, E.seg_days, E.inv_seg};
+    for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (unsigned long long)gridDim.x * blockDim.x) {
+        const unsigned long long c = p.cand[i];
+        const int f = (int)(c >> 32);
+        const int j = (int)(c & 0xffffffffull);
+        const int b = p.frame_batch[f];
+        const double* bt = p.btab + kBatchStride * b;
+        const double* st = p.x_epoch + ((size_t)b * p.n_obj + j) * 6;
+        double r0[3], v0[3];
+        for (int k = 0; k < 3; ++k) { r0[k] = st[k] - bt[k]; v0[k] = st[3 + k] - bt[3 + k]; }
+        double d[3], tau, ve[3];
+        lighttime(sun, p.mu, p.smu, p.c_light, p.lt_tol, p.lt_iter, p.t_ref[b], r0, v0, p.ft[f], p.fobs + 3 * f,
+                  d, tau, ve);
+        const double* nrm = p.normals + (size_t)f * p.n_sub * 12;
+        for (int s = 0; s < p.n_sub; ++s) {
+            const double* ns = nrm + 12 * s;
+            if (dot3(ns, d) > 0.0 && dot3(ns + 3, d) > 0.0 && dot3(ns + 6, d) > 0.0 && dot3(ns + 9, d) > 0.0)
+                wave_append(p.pairs, p.n_pairs, p.cap,
+                            ((unsigned long long)f << 32) | ((unsigned long long)s << 25) | (unsigned long long)j);
+        }
     }
 }
 
@@ -433,6 +582,22 @@ hipError_t fov_prepare(const FovParams& p, int32_t* qkey, int32_t* cnt, int32_t*
     return hipGetLastError();
 }
 
+hipError_t fov_sort_objects(const FovParams& p, int32_t* okey, int32_t* cnt, int32_t* start, int32_t* sorted,
+                            void* scan_scratch, hipStream_t s) {
+    const int64_t n = (int64_t)p.n_batch * p.n_obj;
+    const int64_t nkeys = (int64_t)p.n_batch * ((int64_t)p.G * p.G * p.G + 1);
+    if (n == 0) return hipSuccess;
+    hipError_t e;
+    if ((e = hipMemsetAsync(cnt, 0, (size_t)(nkeys + 1) * sizeof(int32_t), s)) != hipSuccess) return e;
+    const unsigned g = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_obj_keys, dim3(g), dim3(256), 0, s, p, okey, cnt);
+    if ((e = exclusive_scan_i32(cnt, start, nkeys, scan_scratch, s)) != hipSuccess) return e;
+    if ((e = hipMemsetAsync(cnt, 0, (size_t)nkeys * sizeof(int32_t), s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_obj_scatter, dim3(g), dim3(256), 0, s, p, (const int32_t*)okey, (const int32_t*)start, cnt,
+                       sorted);
+    return hipGetLastError();
+}
+
 hipError_t fov_candidates(const FovParams& p, int block, hipStream_t s) {
     if (p.n_obj == 0 || p.n_batch == 0) return hipSuccess;
     dim3 grid((unsigned)((p.n_obj + block - 1) / block), (unsigned)p.n_batch);
@@ -442,6 +607,18 @@ hipError_t fov_candidates(const FovParams& p, int block, hipStream_t s) {
         case 256: hipLaunchKernelGGL(k_fov<256>, grid, dim3(256), 0, s, p); break;
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+static int cu_count() {
+    int dev = 0, ncu = 256;
+    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    return ncu;
+}
+
+hipError_t fov_exact(const FovParams& p, hipStream_t s) {
+    hipLaunchKernelGGL(k_fov_wide, dim3((unsigned)(cu_count() * 8)), dim3(256), 0, s, p);
+    hipLaunchKernelGGL(k_fov_exact, dim3((unsigned)(cu_count() * 16)), dim3(256), 0, s, p);
     return hipGetLastError();
 }
 

@@ -6,7 +6,6 @@
 namespace kete {
 
 constexpr int kBatchStride = 17;        // doubles per batch record
-constexpr int kMaxSunSegs = 8;          // Sun segments staged in LDS per batch
 constexpr double kMaxLightDays = 1.0;   // light time covered by the staged window
 
 struct FovParams {
@@ -32,7 +31,14 @@ struct FovParams {
     unsigned long long* pairs;  // [cap] packed (frame << 32 | sub << 25 | obj)
     unsigned long long* n_pairs;
     int64_t cap;
-    unsigned long long* stats;  // [4] or null: candidates, exact tests, overflow objects
+    unsigned long long* stats;  // [4] or null: candidates, exact tests, brute-force objects
+    unsigned long long* cand;   // [cand_cap] packed (frame << 32 | obj) for the exact test
+    unsigned long long* n_cand;
+    int64_t cand_cap;
+    int32_t* frame_batch;       // [F] batch of each frame
+    const int32_t* obj_sorted;  // [B][N] objects of each batch ordered by sky cell (or null)
+    unsigned long long* wide;   // [B N] (batch << 32 | obj) of objects with wide motion caps
+    unsigned long long* n_wide;
     double mu, smu, c_light, lt_tol;
     int32_t lt_iter;
     int32_t max_cells;
@@ -41,7 +47,10 @@ struct FovParams {
 
 hipError_t fov_prepare(const FovParams& p, int32_t* qkey, int32_t* cnt, int32_t* cursor, int64_t n_keys,
                        void* scan_scratch, hipStream_t s);
+hipError_t fov_sort_objects(const FovParams& p, int32_t* okey, int32_t* cnt, int32_t* start, int32_t* sorted,
+                            void* scan_scratch, hipStream_t s);
 hipError_t fov_candidates(const FovParams& p, int block, hipStream_t s);
+hipError_t fov_exact(const FovParams& p, hipStream_t s);
 hipError_t fov_sort(const unsigned long long* keys, int64_t n, int64_t n_frames, int32_t* fcnt, int32_t* fstart,
                     unsigned long long* sorted, void* scan_scratch, int32_t* pf, int32_t* ps, int32_t* po,
                     hipStream_t s);

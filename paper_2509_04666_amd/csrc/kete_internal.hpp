@@ -68,6 +68,16 @@ struct BucketParams {
 };
 hipError_t launch_bucket(const BucketParams& p, hipStream_t s);
 
+// Optional live timing of kernel launches with HIP events (per thread).
+enum TimedKernel { kTimeNbody = 0, kTimeFov = 1, kTimeAdjoint = 2, kTimeBatch = 3, kTimeKinds = 4 };
+struct TimedScope {
+    TimedScope(int kind, hipStream_t s);
+    ~TimedScope();
+    int kind;
+    hipStream_t stream;
+    void* stop;
+};
+
 // Exclusive scan of int32 counts (n + 1 outputs); scratch >= scan_scratch(n).
 size_t scan_scratch_bytes(int64_t n);
 hipError_t exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, void* scratch, hipStream_t s);
