@@ -97,6 +97,8 @@ typedef struct {
     int32_t window_segs;     /* Chebyshev segments per staged window (2) */
     int32_t lt_iter;         /* light-time iterations (10) */
     int32_t fov_block;       /* FoV threads per block: 64/128/256 (128) */
+    int32_t adj_seg_steps;   /* adjoint: steps stored per checkpoint segment (32) */
+    int32_t reserved;
 } kete_opts_t;
 
 /* Frames (Sect. 3.1): an instantaneous observation at time t from the
@@ -217,6 +219,36 @@ int kete_lighttime_directions(const kete_ephem_t *eph, const double *x_ref, doub
  * the host copy t_host, which must hold the same values). */
 int kete_ephem_eval(const kete_ephem_t *eph, const double *t, const double *t_host, int64_t n_q,
                     double *out, void *stream);
+
+#define KETE_ADJ_FWD 0
+#define KETE_ADJ_BWD 1
+
+/* Bytes of workspace needed by kete_propagate_adjoint (the same
+ * workspace must be passed to the forward and the backward call). */
+size_t kete_adjoint_workspace_size(int64_t n_obj, double t0, double t_end, double ckpt_days,
+                                   const kete_opts_t *opts);
+
+/* Sky positions of observations and their gradient with respect to the
+ * initial states.  Each object j starts from x0[j] at t0 and is integrated
+ * with the force model of kete_propagate_nbody; its observations k at
+ * times t_obs[j][k] (ascending, in [t0, t_end]) from observers at
+ * obs_pos[j][k] get the state at t_obs from the integrator's collocation
+ * polynomial, the light-time hop of Sect. 2 back to the emission time,
+ * and RA/Dec (radians) in the equatorial J2000 frame (ecliptic rotated by
+ * the obliquity 84381.448").
+ *   mode KETE_ADJ_FWD: writes sky_out [N][K][2] and status [N], and stores
+ *     checkpoints every ckpt_days in the workspace;
+ *   mode KETE_ADJ_BWD: given dL_dsky [N][K][2] (device) for the same
+ *     inputs and workspace, writes grad_x0 [N][6] = dL/dx0: the discrete
+ *     adjoint of the forward computation, recomputing each checkpoint
+ *     segment.  Objects with a non-zero status get a zero gradient.
+ * All arrays are device memory; t0, t_end and ckpt_days are host values.
+ * Errors: KETE_EINVAL, KETE_ERANGE, KETE_EWORKSPACE, KETE_EDEVICE. */
+int kete_propagate_adjoint(const kete_ephem_t *eph, int32_t mode, const double *x0, double t0, double t_end,
+                           int64_t n_obj, int32_t k_obs, const double *t_obs, const double *obs_pos,
+                           const double *dL_dsky, double ckpt_days, double *sky_out, double *grad_x0,
+                           int32_t *status, const kete_opts_t *opts, void *workspace, size_t ws_bytes,
+                           void *stream);
 
 /* Live kernel timing for measurement.  While enabled, every integrator
  * and FoV-candidate launch made by the calling thread is bracketed by HIP

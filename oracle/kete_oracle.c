@@ -200,42 +200,53 @@ static double legendre(int n, double x)
 }
 
 /* The 8 Radau nodes on [0,1] are 0 and the 7 other roots of
- * P_7(x) + P_8(x) (x = 2s - 1).  Found by a sign scan and bisection. */
+ * P_7(x) + P_8(x) (x = 2s - 1).  Found by a sign scan and bisection.
+ * Built into locals and published once; every entry point calls this
+ * before any parallel region, so threads only ever read the tables. */
 static void orc_init_nodes(void)
 {
-    if (orc_nodes_ready) return;
-    double roots[8]; int nr = 0;
-    const int NS = 20000;
-    double xa = -1.0 + 1e-7, fa = legendre(7, xa) + legendre(8, xa);
-    for (int i = 1; i <= NS && nr < 7; i++) {
-        double xb = -1.0 + 1e-7 + (2.0 - 1e-7) * i / NS;
-        double fb = legendre(7, xb) + legendre(8, xb);
-        if (fa == 0.0 || (fa < 0) != (fb < 0)) {
-            double lo = xa, hi = xb, flo = fa;
-            for (int it = 0; it < 200; it++) {
-                double mid = 0.5 * (lo + hi);
-                double fm = legendre(7, mid) + legendre(8, mid);
-                if ((fm < 0) == (flo < 0)) { lo = mid; flo = fm; } else hi = mid;
-                if (hi - lo <= 0.0) break;
+#ifdef _OPENMP
+#pragma omp critical(orc_nodes)
+#endif
+    {
+        if (!orc_nodes_ready) {
+            double roots[8]; int nr = 0;
+            const int NS = 20000;
+            double xa = -1.0 + 1e-7, fa = legendre(7, xa) + legendre(8, xa);
+            for (int i = 1; i <= NS && nr < 7; i++) {
+                double xb = -1.0 + 1e-7 + (2.0 - 1e-7) * i / NS;
+                double fb = legendre(7, xb) + legendre(8, xb);
+                if (fa == 0.0 || (fa < 0) != (fb < 0)) {
+                    double lo = xa, hi = xb, flo = fa;
+                    for (int it = 0; it < 200; it++) {
+                        double mid = 0.5 * (lo + hi);
+                        double fm = legendre(7, mid) + legendre(8, mid);
+                        if ((fm < 0) == (flo < 0)) { lo = mid; flo = fm; } else hi = mid;
+                        if (hi - lo <= 0.0) break;
+                    }
+                    roots[nr++] = 0.5 * (lo + hi);
+                }
+                xa = xb; fa = fb;
             }
-            roots[nr++] = 0.5 * (lo + hi);
+            double hn[8], cc[7][7];
+            hn[0] = 0.0;
+            for (int i = 0; i < 7; i++) hn[i + 1] = 0.5 * (roots[i] + 1.0);
+            /* monomial coefficients of the Newton basis polynomials */
+            double p[8] = {0};
+            memset(cc, 0, sizeof(cc));
+            p[0] = 1.0;                        /* omega_0(s) = s */
+            for (int m = 0; m < 7; m++) cc[0][m] = p[m];
+            for (int k = 1; k < 7; k++) {
+                double q[8] = {0};
+                for (int m = 0; m <= k; m++) q[m] = (m > 0 ? p[m - 1] : 0.0) - hn[k] * p[m];
+                memcpy(p, q, sizeof(p));
+                for (int m = 0; m < 7; m++) cc[k][m] = p[m];
+            }
+            memcpy(orc_hn, hn, sizeof(hn));
+            memcpy(orc_cc, cc, sizeof(cc));
+            orc_nodes_ready = 1;
         }
-        xa = xb; fa = fb;
     }
-    orc_hn[0] = 0.0;
-    for (int i = 0; i < 7; i++) orc_hn[i + 1] = 0.5 * (roots[i] + 1.0);
-    /* monomial coefficients of the Newton basis polynomials */
-    double p[8] = {0};
-    memset(orc_cc, 0, sizeof(orc_cc));
-    p[0] = 1.0;                        /* omega_0(s) = s */
-    for (int m = 0; m < 7; m++) orc_cc[0][m] = p[m];
-    for (int k = 1; k < 7; k++) {
-        double q[8] = {0};
-        for (int m = 0; m <= k; m++) q[m] = (m > 0 ? p[m - 1] : 0.0) - orc_hn[k] * p[m];
-        memcpy(p, q, sizeof(p));
-        for (int m = 0; m < 7; m++) orc_cc[k][m] = p[m];
-    }
-    orc_nodes_ready = 1;
 }
 
 void orc_radau_nodes(double out[8])
@@ -266,7 +277,7 @@ typedef struct {
  * size from call to call.  Returns a per-object status. */
 static int orc_radau_advance(orc_radau *R, double *t, double *x, double *v, double t_target, double *h_io)
 {
-    orc_init_nodes();
+    if (!orc_nodes_ready) orc_init_nodes();
     const int D = R->D;
     double a0[ORC_MAXD], F[ORC_MAXD], xs[ORC_MAXD], vs[ORC_MAXD];
     double b[7][ORC_MAXD], g[7][ORC_MAXD];
@@ -430,6 +441,7 @@ int orc_propagate(const orc_ephem *E, const orc_opts *o, int64_t n_obj, const do
                   int64_t n_out, const double *t_out, double *x_out, int32_t *status, int64_t *stats)
 {
     if (n_obj < 0 || n_out < 0) return ORC_EINVAL;
+    orc_init_nodes();
     int64_t s_steps = 0, s_iter = 0, s_rej = 0, s_force = 0;
 #ifdef _OPENMP
     int nt = o->n_threads > 0 ? o->n_threads : omp_get_max_threads();
@@ -801,6 +813,7 @@ int orc_sky_grad(const orc_ephem *E, const orc_opts *o, int64_t n_obj, const dou
                  const double *t_obs, const double *obs_pos, const double *radec_obs,
                  double *radec_out, double *loss, double *grad, int32_t want_grad, int32_t *status)
 {
+    orc_init_nodes();
 #ifdef _OPENMP
     int nt = o->n_threads > 0 ? o->n_threads : omp_get_max_threads();
 #pragma omp parallel for schedule(dynamic, 4) num_threads(nt)

@@ -13,6 +13,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libkete_mi.so")
 
 KETE_OK, KETE_EINVAL, KETE_ERANGE, KETE_ECAPACITY, KETE_EDEVICE, KETE_EWORKSPACE = 0, -1, -2, -3, -4, -5
+ADJ_FWD, ADJ_BWD = 0, 1
 ST_OK, ST_NONFINITE, ST_STEP_UNDERFLOW, ST_MAX_STEPS, ST_KEPLER_NOCONV = 0, 1, 2, 3, 4
 MAX_BODIES, MAX_DEGREE, MAX_SUB, MAX_OBJ = 16, 15, 128, 1 << 25
 
@@ -37,7 +38,8 @@ class OptsT(C.Structure):
                 ("c_light", C.c_double), ("batch_span", C.c_double), ("cell_chord", C.c_double),
                 ("lt_tol", C.c_double), ("max_steps", C.c_int32), ("max_iter", C.c_int32),
                 ("n_buckets", C.c_int32), ("block", C.c_int32), ("rebucket_epochs", C.c_int32),
-                ("window_segs", C.c_int32), ("lt_iter", C.c_int32), ("fov_block", C.c_int32)]
+                ("window_segs", C.c_int32), ("lt_iter", C.c_int32), ("fov_block", C.c_int32),
+                ("adj_seg_steps", C.c_int32), ("reserved", C.c_int32)]
 
 
 class FramesT(C.Structure):
@@ -67,6 +69,11 @@ SIGNATURES = {
                                             C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.POINTER(OptsT),
                                             C.c_void_p]),
     "kete_ephem_eval": (C.c_int, [C.POINTER(EphemT), C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
+    "kete_adjoint_workspace_size": (C.c_size_t, [C.c_int64, C.c_double, C.c_double, C.c_double, C.POINTER(OptsT)]),
+    "kete_propagate_adjoint": (C.c_int, [C.POINTER(EphemT), C.c_int32, C.c_void_p, C.c_double, C.c_double,
+                                         C.c_int64, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
+                                         C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(OptsT), C.c_void_p,
+                                         C.c_size_t, C.c_void_p]),
     "kete_timing_enable": (None, [C.c_int]),
     "kete_timing_read": (C.c_int, [C.c_void_p, C.c_void_p]),
 }

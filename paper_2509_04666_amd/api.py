@@ -4,6 +4,7 @@ from __future__ import annotations
 
 import ctypes as C
 import dataclasses
+import math
 from typing import Optional, Sequence
 
 import numpy as np
@@ -195,3 +196,64 @@ def predict(eph: DeviceEphemeris, x0: torch.Tensor, t0: float, frames: DeviceFra
     x_epoch, status = propagate(eph, x0, t0, t_ref, opts)
     pf, ps, po = fov_check(eph, x_epoch, batches, frames, status, opts, pairs_cap)
     return pf, ps, po, x_epoch, status, batches
+
+
+class AdjointContext:
+    """Inputs and workspace shared by the forward and backward adjoint calls."""
+
+    def __init__(self, eph: DeviceEphemeris, t0: float, t_end: float, t_obs: torch.Tensor, obs_pos: torch.Tensor,
+                 ckpt_days: float = 5.0, opts: Optional[OptsT] = None):
+        self.eph, self.t0, self.t_end, self.ckpt_days = eph, float(t0), float(t_end), float(ckpt_days)
+        self.t_obs = t_obs.contiguous()
+        self.obs_pos = obs_pos.contiguous()
+        self.opts = opts or default_opts()
+        self.n_obj, self.k_obs = self.t_obs.shape
+        need = lib().kete_adjoint_workspace_size(self.n_obj, self.t0, self.t_end, self.ckpt_days,
+                                                 C.byref(self.opts))
+        if need == 0:
+            check(_lib.KETE_EINVAL)
+        self.workspace = _workspace(need, self.t_obs.device)
+        self.status = torch.zeros(self.n_obj, dtype=torch.int32, device=self.t_obs.device)
+
+    def forward(self, x0: torch.Tensor) -> torch.Tensor:
+        sky = torch.empty((self.n_obj, self.k_obs, 2), dtype=torch.float64, device=x0.device)
+        check(lib().kete_propagate_adjoint(C.byref(self.eph.c), _lib.ADJ_FWD, _ptr(x0.contiguous()), self.t0,
+                                           self.t_end, self.n_obj, self.k_obs, _ptr(self.t_obs), _ptr(self.obs_pos),
+                                           None, self.ckpt_days, _ptr(sky), None, _ptr(self.status),
+                                           C.byref(self.opts), _ptr(self.workspace), self.workspace.numel(),
+                                           _stream()))
+        return sky
+
+    def backward(self, x0: torch.Tensor, dL_dsky: torch.Tensor) -> torch.Tensor:
+        grad = torch.empty((self.n_obj, 6), dtype=torch.float64, device=x0.device)
+        check(lib().kete_propagate_adjoint(C.byref(self.eph.c), _lib.ADJ_BWD, _ptr(x0.contiguous()), self.t0,
+                                           self.t_end, self.n_obj, self.k_obs, _ptr(self.t_obs), _ptr(self.obs_pos),
+                                           _ptr(dL_dsky.contiguous()), self.ckpt_days, None, _ptr(grad),
+                                           _ptr(self.status), C.byref(self.opts), _ptr(self.workspace),
+                                           self.workspace.numel(), _stream()))
+        return grad
+
+
+class AdjointSky(torch.autograd.Function):
+    """sky = AdjointSky.apply(x0, ctx): RA/Dec [N, K, 2] of every
+    observation; backward runs the library's adjoint kernel."""
+
+    @staticmethod
+    def forward(fctx, x0: torch.Tensor, actx: AdjointContext):
+        fctx.actx = actx
+        fctx.save_for_backward(x0)
+        return actx.forward(x0.detach())
+
+    @staticmethod
+    def backward(fctx, g_sky):
+        (x0,) = fctx.saved_tensors
+        return fctx.actx.backward(x0.detach(), g_sky), None
+
+
+def sky_residual_loss(sky: torch.Tensor, radec_obs: torch.Tensor) -> torch.Tensor:
+    """Sum over objects and observations of ((ra - ra_obs) cos dec)^2 + (dec - dec_obs)^2,
+    with the RA difference wrapped to (-pi, pi]."""
+    dra = torch.remainder(sky[..., 0] - radec_obs[..., 0] + math.pi, 2 * math.pi) - math.pi
+    r1 = dra * torch.cos(sky[..., 1])
+    r2 = sky[..., 1] - radec_obs[..., 1]
+    return (r1 * r1 + r2 * r2).sum()

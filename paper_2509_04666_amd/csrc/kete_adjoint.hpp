@@ -1,0 +1,47 @@
+// Adjoint (sky-residual gradient) stage: parameters shared by the host
+// layer and kernels.
+#pragma once
+
+#include "kete_internal.hpp"
+
+namespace kete {
+
+constexpr int kCkptDoubles = 8;     // x[3], v[3], wave step, failed flag
+
+struct AdjParams {
+    EphemArgs eph;
+    RadauConst rc;
+    const double* x0;           // [N][6]
+    const int32_t* perm;        // [N] object order (bucketed)
+    double t0;
+    int32_t n_obj;
+    int32_t k_obs;
+    const double* t_obs;        // [N][K], ascending per object, in [t0, t_end]
+    const double* obs_pos;      // [N][K][3]
+    const double* dL_dsky;      // [N][K][2] (backward)
+    double* sky_out;            // [N][K][2] (forward)
+    double* grad;               // [N][6] (backward)
+    int32_t* status;            // [N]
+    double* h_pref;             // [N]
+    double* ckpt;               // [C+1][N][kCkptDoubles]
+    const Window* win;
+    const int32_t* seg_win;     // [C+1]: first window of each checkpoint segment
+    int32_t n_win;
+    int32_t n_ckpt;             // C segments
+    double* steps;              // [s_max][32][N]
+    double* jac;                // [s_max][8][18][N]
+    int32_t s_max;
+    int32_t max_win_segs;
+    int32_t max_iter;
+    int32_t max_steps;
+    double eps, h_min, h_max, h_init, safety;
+    double smu, c_light, lt_tol, cos_eps, sin_eps;
+    int32_t lt_iter;
+    int32_t pad;
+};
+
+size_t adjoint_lds_bytes(const AdjParams& p);
+hipError_t launch_adjoint(const AdjParams& p, int mode, hipStream_t s);
+size_t adjoint_step_doubles();
+
+}  // namespace kete

@@ -13,12 +13,14 @@
 #include <string>
 #include <vector>
 
+#include "kete_adjoint.hpp"
 #include "kete_fov.hpp"
 #include "kete_internal.hpp"
 #include "kete_mi.h"
 
 namespace kete {
 hipError_t launch_hpref_init(const double* x0, double* h_pref, int n, double mu, hipStream_t s);
+hipError_t launch_iota(int32_t* perm, int n, hipStream_t s);
 size_t bucket_scratch_ints(int64_t n_obj, int n_buckets);
 }  // namespace kete
 
@@ -135,6 +137,24 @@ RadauConst build_radau() {
         ld p = 1;
         for (int k = 0; k < 8; ++k) if (k != m) p *= (S[m] - S[k]);
         rc.E6[m - 1] = (double)(1.0L / p);
+        // monomial coefficients of the Lagrange basis polynomial ell_m
+        ld poly[8] = {1, 0, 0, 0, 0, 0, 0, 0};
+        int deg = 0;
+        for (int k = 0; k < 8; ++k) {
+            if (k == m) continue;
+            ld nxt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            for (int q = 0; q <= deg; ++q) {
+                nxt[q + 1] += poly[q];
+                nxt[q] -= S[k] * poly[q];
+            }
+            ++deg;
+            for (int q = 0; q < 8; ++q) poly[q] = nxt[q];
+        }
+        for (int q = 0; q < 8; ++q) {
+            const ld pk = poly[q] / p;
+            rc.Bp[m - 1][q] = (double)(pk / (q + 1));
+            rc.Ap[m - 1][q] = (double)(pk / ((q + 1) * (q + 2)));
+        }
     }
     return rc;
 }
@@ -177,7 +197,7 @@ int ephem_args(const kete_ephem_t* eph, double c_light, EphemArgs& E) {
     return KETE_OK;
 }
 
-double t_end(const kete_ephem_t* e) { return e->t_start + e->n_seg * e->seg_days; }
+double t_end_of(const kete_ephem_t* e) { return e->t_start + e->n_seg * e->seg_days; }
 
 int seg_of(const kete_ephem_t* e, double t) {
     int k = (int)std::floor((t - e->t_start) / e->seg_days);
@@ -285,6 +305,7 @@ void kete_default_opts(kete_opts_t* o) {
     o->window_segs = 2;
     o->lt_iter = 10;
     o->fov_block = 128;
+    o->adj_seg_steps = 32;
 }
 
 int kete_make_batches(const double* t, int64_t n_frames, double span, int32_t* frame_order, int32_t* batch_off,
@@ -347,7 +368,7 @@ int kete_propagate_nbody(const kete_ephem_t* eph, const double* x0, double t0, i
     if (n_obj == 0 || n_out == 0) return KETE_OK;
     if (!x0 || !t_out || !x_out || !status) return fail(KETE_EINVAL, "null pointer");
     if (!std::isfinite(t0)) return fail(KETE_EINVAL, "t0 not finite");
-    const double tlo = eph->t_start, thi = t_end(eph);
+    const double tlo = eph->t_start, thi = t_end_of(eph);
     if (!(t0 >= tlo && t0 <= thi)) return fail(KETE_ERANGE, "t0 %.9g outside ephemeris [%.9g, %.9g]", t0, tlo, thi);
     const bool fwd = t_out[0] > t0;
     double prev = t0;
@@ -597,6 +618,154 @@ int kete_fov_check(const kete_ephem_t* eph, const double* x_epoch, const int32_t
     return KETE_OK;
 }
 
+static int adjoint_plan(const kete_ephem_t* eph, double t0, double t_end, double ckpt_days, int wsegs,
+                        std::vector<Window>& win, std::vector<int32_t>& seg_win) {
+    if (!std::isfinite(t0) || !std::isfinite(t_end) || !(t_end > t0))
+        return fail(KETE_EINVAL, "need finite t0 < t_end");
+    if (!(ckpt_days > 0) || !std::isfinite(ckpt_days)) return fail(KETE_EINVAL, "ckpt_days must be positive");
+    const double tlo = eph->t_start, thi = t_end_of(eph);
+    if (!(t0 >= tlo && t_end <= thi)) return fail(KETE_ERANGE, "[t0, t_end] outside the ephemeris");
+    const int64_t C = (int64_t)std::ceil((t_end - t0) / ckpt_days - 1e-12);
+    if (C < 1 || C > 1000000) return fail(KETE_EINVAL, "bad checkpoint count");
+    std::vector<double> tc(C);
+    for (int64_t c = 0; c < C; ++c) tc[c] = (c == C - 1) ? t_end : t0 + (c + 1) * ckpt_days;
+    std::vector<int> ew;
+    win = plan_windows(eph, t0, tc.data(), C, wsegs, ew);
+    seg_win.assign(C + 1, 0);
+    for (int64_t c = 1; c <= C; ++c) seg_win[c] = ew[c - 1] + 1;
+    return KETE_OK;
+}
+
+static int adj_steps(const kete_opts_t* o) { return o->adj_seg_steps > 0 ? std::min(o->adj_seg_steps, 4096) : 32; }
+
+// Windows of the adjoint plan: at most 64 per checkpoint segment.
+static int64_t adjoint_max_windows(int64_t n_ckpt) { return 64 * (n_ckpt + 1) + 16; }
+
+size_t kete_adjoint_workspace_size(int64_t n_obj, double t0, double t_end, double ckpt_days, const kete_opts_t* opts) {
+    kete_opts_t d;
+    if (!opts) { kete_default_opts(&d); opts = &d; }
+    if (!(t_end > t0) || !(ckpt_days > 0) || n_obj < 0) return 0;
+    const int64_t C = (int64_t)std::ceil((t_end - t0) / ckpt_days - 1e-12);
+    const int nbk = std::max(1, opts->n_buckets);
+    Carver c{nullptr};
+    c.take<int32_t>((size_t)n_obj);                                   // perm
+    c.take<double>((size_t)n_obj);                                    // h_pref
+    c.take<Window>((size_t)adjoint_max_windows(C));
+    c.take<int32_t>((size_t)C + 1);
+    c.take<double>((size_t)(C + 1) * n_obj * kCkptDoubles);
+    c.take<double>((size_t)adj_steps(opts) * adjoint_step_doubles() * n_obj);
+    c.take<int32_t>(bucket_scratch_ints(n_obj, nbk));
+    return c.off;
+}
+
+int kete_propagate_adjoint(const kete_ephem_t* eph, int32_t mode, const double* x0, double t0, double t_end,
+                           int64_t n_obj, int32_t k_obs, const double* t_obs, const double* obs_pos,
+                           const double* dL_dsky, double ckpt_days, double* sky_out, double* grad_x0,
+                           int32_t* status, const kete_opts_t* opts, void* workspace, size_t ws_bytes,
+                           void* stream) {
+    kete_opts_t dflt;
+    if (!opts) { kete_default_opts(&dflt); opts = &dflt; }
+    g_err.clear();
+    EphemArgs E;
+    const double cl = opts->c_light > 0 ? opts->c_light : kC;
+    int rc = ephem_args(eph, cl, E);
+    if (rc) return rc;
+    if (mode != KETE_ADJ_FWD && mode != KETE_ADJ_BWD) return fail(KETE_EINVAL, "mode must be KETE_ADJ_FWD or KETE_ADJ_BWD");
+    if (n_obj < 0 || n_obj > KETE_MAX_OBJ || k_obs < 0) return fail(KETE_EINVAL, "bad sizes");
+    std::vector<Window> win;
+    std::vector<int32_t> seg_win;
+    if ((rc = adjoint_plan(eph, t0, t_end, ckpt_days, std::max(1, opts->window_segs), win, seg_win))) return rc;
+    if (n_obj == 0) return KETE_OK;
+    if (!x0 || !status || (k_obs > 0 && (!t_obs || !obs_pos))) return fail(KETE_EINVAL, "null pointer");
+    if (mode == KETE_ADJ_FWD && k_obs > 0 && !sky_out) return fail(KETE_EINVAL, "sky_out is null");
+    if (mode == KETE_ADJ_BWD && (!grad_x0 || (k_obs > 0 && !dL_dsky))) return fail(KETE_EINVAL, "null gradient pointer");
+    if (!(opts->eps > 0) || !(opts->h_init > 0) || !(opts->h_min > 0) || opts->max_iter < 1 || opts->max_steps < 1)
+        return fail(KETE_EINVAL, "eps, h_init, h_min, max_iter and max_steps must be positive");
+    const int64_t C = (int64_t)seg_win.size() - 1;
+    const int nbk = std::min(std::max(1, opts->n_buckets), 32);
+    if (!workspace) return fail(KETE_EWORKSPACE, "workspace is null");
+    const size_t need = kete_adjoint_workspace_size(n_obj, t0, t_end, ckpt_days, opts);
+    if (ws_bytes < need) return fail(KETE_EWORKSPACE, "workspace %zu bytes < %zu required", ws_bytes, need);
+    Carver c{(char*)workspace};
+    int32_t* perm = c.take<int32_t>((size_t)n_obj);
+    double* h_pref = c.take<double>((size_t)n_obj);
+    const size_t max_win = (size_t)adjoint_max_windows(C);
+    if (win.size() > max_win) return fail(KETE_EINVAL, "too many integration windows (ckpt_days spans too many segments)");
+    Window* dwin = c.take<Window>(max_win);
+    int32_t* dseg = c.take<int32_t>((size_t)C + 1);
+    double* ckpt = c.take<double>((size_t)(C + 1) * n_obj * kCkptDoubles);
+    double* scratch = c.take<double>((size_t)adj_steps(opts) * adjoint_step_doubles() * n_obj);
+    int32_t* bscratch = c.take<int32_t>(bucket_scratch_ints(n_obj, nbk));
+
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(hipMemcpyAsync(dwin, win.data(), win.size() * sizeof(Window), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(dseg, seg_win.data(), seg_win.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+
+    AdjParams P;
+    std::memset(&P, 0, sizeof(P));
+    P.eph = E;
+    P.rc = radau_const();
+    P.x0 = x0;
+    P.perm = perm;
+    P.t0 = t0;
+    P.n_obj = (int32_t)n_obj;
+    P.k_obs = k_obs;
+    P.t_obs = t_obs;
+    P.obs_pos = obs_pos;
+    P.dL_dsky = dL_dsky;
+    P.sky_out = sky_out;
+    P.grad = grad_x0;
+    P.status = status;
+    P.h_pref = h_pref;
+    P.ckpt = ckpt;
+    P.win = dwin;
+    P.seg_win = dseg;
+    P.n_win = (int32_t)win.size();
+    P.n_ckpt = (int32_t)C;
+    P.steps = scratch;
+    P.jac = scratch + (size_t)adj_steps(opts) * 32 * n_obj;
+    P.s_max = adj_steps(opts);
+    P.max_win_segs = std::max(1, opts->window_segs) + 1;
+    P.max_iter = opts->max_iter;
+    P.max_steps = opts->max_steps;
+    P.eps = opts->eps;
+    P.h_min = opts->h_min;
+    P.h_max = opts->h_max;
+    P.h_init = opts->h_init;
+    P.safety = 0.25;
+    P.smu = std::sqrt(E.gm[0]);
+    P.c_light = cl;
+    P.lt_tol = opts->lt_tol > 0 ? opts->lt_tol : 1e-15;
+    P.lt_iter = opts->lt_iter > 0 ? opts->lt_iter : 10;
+    const double obliq = 84381.448 / 3600.0 * 3.14159265358979323846 / 180.0;
+    P.cos_eps = std::cos(obliq);
+    P.sin_eps = std::sin(obliq);
+
+    if (mode == KETE_ADJ_FWD) {
+        HIPCHK(hipMemsetAsync(status, 0, (size_t)n_obj * sizeof(int32_t), s));
+        HIPCHK(launch_hpref_init(x0, h_pref, (int)n_obj, E.gm[0], s));
+        if (nbk > 1) {
+            BucketParams B;
+            B.h_pref = h_pref;
+            B.status = status;
+            B.perm = perm;
+            B.counts = bscratch;
+            B.n_obj = (int32_t)n_obj;
+            B.n_buckets = nbk;
+            B.h_ref = 1.0 / 64.0;
+            HIPCHK(launch_bucket(B, s));
+        } else {
+            HIPCHK(launch_iota(perm, (int)n_obj, s));
+        }
+    }
+    {
+        TimedScope ts(kTimeAdjoint, s);
+        HIPCHK(launch_adjoint(P, mode, s));
+    }
+    return KETE_OK;
+}
+
 // Live kernel timing: while enabled, every integrator / FoV launch made by
 // this thread is bracketed by HIP events on its stream.
 void kete_timing_enable(int on) {
@@ -666,7 +835,7 @@ int kete_ephem_eval(const kete_ephem_t* eph, const double* t, const double* t_ho
     if (n_q == 0) return KETE_OK;
     if (!t || !t_host || !out) return fail(KETE_EINVAL, "null pointer");
     for (int64_t i = 0; i < n_q; ++i)
-        if (!(t_host[i] >= eph->t_start && t_host[i] <= t_end(eph)))
+        if (!(t_host[i] >= eph->t_start && t_host[i] <= t_end_of(eph)))
             return fail(KETE_ERANGE, "t[%lld] = %.9g outside ephemeris", (long long)i, t_host[i]);
     HIPCHK(launch_ephem_eval(E, t, n_q, out, (hipStream_t)stream));
     return KETE_OK;

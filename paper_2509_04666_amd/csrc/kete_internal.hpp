@@ -23,6 +23,10 @@ struct RadauConst {
     double B[9][7];
     double E6[7];
     double half_s2[9];
+    // dense output at any sig in [0, 1]:
+    //   A_m(sig) = sum_k Ap[m][k] sig^(k+2),  B_m(sig) = sum_k Bp[m][k] sig^(k+1)
+    double Ap[7][8];
+    double Bp[7][8];
 };
 
 // One staged ephemeris window of the integration: [t_a, t_b] lies within

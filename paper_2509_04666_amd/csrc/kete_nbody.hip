@@ -10,41 +10,10 @@
 // before each launch so that lanes of one wavefront want similar steps.
 #include <math.h>
 
-#include "kete_internal.hpp"
+#include "kete_radau.hpp"
 
 namespace kete {
 namespace {
-
-constexpr int kNodes = 9;   // s_0 = 0, s_1..s_7, and s = 1 (step end)
-constexpr double kInf = 1e300;
-
-// Acceleration at one node from the LDS perturber table e[b][6]:
-// Eq. A.1 with the attractive sign, plus Eq. A.3 (eps = 0) where kgr != 0.
-__device__ __forceinline__ void accel(const double* __restrict__ e, const EphemArgs& E,
-                                      const double X[3], const double V[3], double F[3]) {
-    double ax = 0.0, ay = 0.0, az = 0.0;
-    for (int b = 0; b < E.n_body; ++b) {
-        const double* pb = e + 6 * b;
-        const double rx = X[0] - pb[0], ry = X[1] - pb[1], rz = X[2] - pb[2];
-        const double r2 = fma(rx, rx, fma(ry, ry, rz * rz));
-        const double ir = rsqrt(r2);
-        const double ir3 = ir * ir * ir;
-        const double gm = E.gm[b];
-        double f = -gm * ir3;
-        const double k = E.kgr[b];
-        if (k != 0.0) {
-            const double wx = V[0] - pb[3], wy = V[1] - pb[4], wz = V[2] - pb[5];
-            const double w2 = fma(wx, wx, fma(wy, wy, wz * wz));
-            const double rw = fma(rx, wx, fma(ry, wy, rz * wz));
-            const double g = k * ir3;
-            f = fma(g, 4.0 * gm * ir - w2, f);
-            const double q = 4.0 * g * rw;
-            ax = fma(q, wx, ax); ay = fma(q, wy, ay); az = fma(q, wz, az);
-        }
-        ax = fma(f, rx, ax); ay = fma(f, ry, ay); az = fma(f, rz, az);
-    }
-    F[0] = ax; F[1] = ay; F[2] = az;
-}
 
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_nbody(const NbodyParams p) {
@@ -83,14 +52,7 @@ __global__ __launch_bounds__(BLOCK) void k_nbody(const NbodyParams p) {
     for (int w = 0; w < p.n_win; ++w) {
         const Window W = p.win[w];
         __syncthreads();
-        {   // stage the window's Chebyshev segments of every body
-            const int per_body = (W.seg_hi - W.seg_lo + 1) * cps;
-            const int total = nb * per_body;
-            for (int i = tid; i < total; i += BLOCK) {
-                const int b = i / per_body, r = i - b * per_body;
-                coefL[b * bstride + r] = E.coef[((size_t)b * E.n_seg + W.seg_lo) * cps + r];
-            }
-        }
+        stage_window(E, W.seg_lo, W.seg_hi, bstride, tid, BLOCK, coefL);
         __syncthreads();
         const double tb = W.t_b;
         if (__ballot(active) == 0ull) {
@@ -112,80 +74,13 @@ __global__ __launch_bounds__(BLOCK) void k_nbody(const NbodyParams p) {
             const double hh = h * h;
 
             // perturbers at the 9 node times, one Clenshaw chain per lane
-            const int nchain = kNodes * nb * 3;
-            for (int c = lane; c < nchain; c += kWave) {
-                const int n = c / (nb * 3);
-                const int r = c - n * nb * 3;
-                const int b = r / 3, i = r - 3 * b;
-                const double tt = (n == kNodes - 1) ? t_end : t + rc.s[n] * h;
-                const int k = seg_index(tt, E.t_start, E.inv_seg, W.seg_lo, W.seg_hi);
-                const double tau = 2.0 * (tt - (E.t_start + (double)k * E.seg_days)) * E.inv_seg - 1.0;
-                double pv, dv;
-                clenshaw(coefL + b * bstride + (k - W.seg_lo) * cps + i * deg1, deg1, tau, pv, dv);
-                ephW[(n * nb + b) * 6 + i] = pv;
-                ephW[(n * nb + b) * 6 + 3 + i] = dv * 2.0 * E.inv_seg;
-            }
-            c_chain += nchain;
-            wave_lds_sync();
+            node_ephemeris(coefL, bstride, E, rc, W.seg_lo, W.seg_hi, t, h, t_end, lane, ephW);
+            c_chain += kNodes * nb * 3;
 
             if (!haveF0) { accel(ephW, E, x0, v0, F0); haveF0 = true; }
 
-            double D[7][3];
-#pragma unroll
-            for (int m = 0; m < 7; ++m) { D[m][0] = D[m][1] = D[m][2] = 0.0; }
-            double b6p[3] = {0.0, 0.0, 0.0};
-            double pc = 1e300, pcl;
-            int it = 0;
-            do {
-                pcl = pc;
-                ++it;
-                // An opaque zero row offset keeps the collocation constants
-                // in the kernel-argument segment (scalar loads per node)
-                // instead of being hoisted into vector registers.
-                int z;
-                asm volatile("s_mov_b32 %0, 0" : "=s"(z));
-#pragma unroll
-                for (int n = 1; n <= 7; ++n) {
-                    const int nz = n + z;
-                    const double sh = rc.s[nz] * h;
-                    double X[3], V[3];
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        double acc = rc.half_s2[nz] * F0[c];
-#pragma unroll
-                        for (int m = 0; m < 7; ++m) acc = fma(rc.A[nz][m], D[m][c], acc);
-                        X[c] = fma(hh, acc, fma(sh, v0[c], x0[c]));
-                    }
-                    if (E.has_gr) {
-#pragma unroll
-                        for (int c = 0; c < 3; ++c) {
-                            double av = rc.s[nz] * F0[c];
-#pragma unroll
-                            for (int m = 0; m < 7; ++m) av = fma(rc.B[nz][m], D[m][c], av);
-                            V[c] = fma(h, av, v0[c]);
-                        }
-                    } else {
-                        V[0] = v0[0]; V[1] = v0[1]; V[2] = v0[2];
-                    }
-                    double F[3];
-                    accel(ephW + n * nb * 6, E, X, V, F);
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) D[n - 1][c] = F[c] - F0[c];
-                }
-                double db = 0.0, fm = 0.0;
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    double b6 = 0.0;
-#pragma unroll
-                    for (int m = 0; m < 7; ++m) b6 = fma(rc.E6[m + z], D[m][c], b6);
-                    db = fmax(db, fabs(b6 - b6p[c]));
-                    b6p[c] = b6;
-                    fm = fmax(fm, fabs(D[6][c] + F0[c]));
-                }
-                const double lpc = (active && fm > 0.0) ? db / fm : 0.0;
-                pc = wave_max(lpc);
-                c_liter += __popcll(__ballot(active));
-            } while (!(pc < 1e-16) && !(it > 2 && pcl <= pc) && it < p.max_iter);
+            double D[7][3], b6p[3];
+            const int it = corrector(rc, E, ephW, x0, v0, F0, h, active, p.max_iter, D, b6p, c_liter);
             c_iter += it;
 
             // IAS15-style control on |b6| / |a| at the last node
@@ -297,6 +192,11 @@ __global__ __launch_bounds__(256) void k_bucket_scatter(const BucketParams p, co
     }
 }
 
+__global__ void k_iota(int32_t* __restrict__ perm, int n) {
+    const long j = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n) perm[j] = (int32_t)j;
+}
+
 __global__ void k_hpref_init(const double* __restrict__ x0, double* __restrict__ h_pref, int n, double mu) {
     const long j = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
@@ -323,6 +223,12 @@ hipError_t launch_nbody(const NbodyParams& p, int block, hipStream_t s) {
 hipError_t launch_hpref_init(const double* x0, double* h_pref, int n, double mu, hipStream_t s) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_hpref_init, dim3((n + 255) / 256), dim3(256), 0, s, x0, h_pref, n, mu);
+    return hipGetLastError();
+}
+
+hipError_t launch_iota(int32_t* perm, int n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_iota, dim3((n + 255) / 256), dim3(256), 0, s, perm, n);
     return hipGetLastError();
 }
 

@@ -1,0 +1,216 @@
+// Device pieces of the Gauss-Radau collocation step shared by the
+// propagation and adjoint kernels: perturber chains into LDS, the force
+// of Eqs. A.1 + A.3, its Jacobians, and the corrector sweep.
+#pragma once
+
+#include "kete_internal.hpp"
+
+namespace kete {
+
+constexpr int kNodes = 9;   // s_0 = 0, s_1..s_7, and s = 1 (step end)
+constexpr double kInf = 1e300;
+
+// Acceleration at one node from the LDS perturber table e[b][6]:
+// Eq. A.1 with the attractive sign, plus Eq. A.3 (eps = 0) where kgr != 0.
+__device__ __forceinline__ void accel(const double* __restrict__ e, const EphemArgs& E,
+                                      const double X[3], const double V[3], double F[3]) {
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    for (int b = 0; b < E.n_body; ++b) {
+        const double* pb = e + 6 * b;
+        const double rx = X[0] - pb[0], ry = X[1] - pb[1], rz = X[2] - pb[2];
+        const double r2 = fma(rx, rx, fma(ry, ry, rz * rz));
+        const double ir = rsqrt(r2);
+        const double ir3 = ir * ir * ir;
+        const double gm = E.gm[b];
+        double f = -gm * ir3;
+        const double k = E.kgr[b];
+        if (k != 0.0) {
+            const double wx = V[0] - pb[3], wy = V[1] - pb[4], wz = V[2] - pb[5];
+            const double w2 = fma(wx, wx, fma(wy, wy, wz * wz));
+            const double rw = fma(rx, wx, fma(ry, wy, rz * wz));
+            const double g = k * ir3;
+            f = fma(g, 4.0 * gm * ir - w2, f);
+            const double q = 4.0 * g * rw;
+            ax = fma(q, wx, ax); ay = fma(q, wy, ay); az = fma(q, wz, az);
+        }
+        ax = fma(f, rx, ax); ay = fma(f, ry, ay); az = fma(f, rz, az);
+    }
+    F[0] = ax; F[1] = ay; F[2] = az;
+}
+
+// Jacobians Jx = da/dx and Jv = da/dv (row-major 3x3) of the same force.
+// Newtonian part: mu (3 r r^T / r^5 - I / r^3).  Eq. A.3 part, with
+// a = k/r^3 (s1 r + 4 (r.w) w), s1 = 4 mu/r - w^2:
+//   da/dr = k [ -3 P r^T / r^5 - 4 mu r r^T / r^6 + s1 I / r^3 + 4 w w^T / r^3 ]
+//   da/dw = k / r^3 [ -2 r w^T + 4 w r^T + 4 (r.w) I ]
+// where P = s1 r + 4 (r.w) w.
+__device__ __forceinline__ void accel_jac(const double* __restrict__ e, const EphemArgs& E, const double X[3],
+                                          const double V[3], double Jx[9], double Jv[9]) {
+    for (int i = 0; i < 9; ++i) { Jx[i] = 0.0; Jv[i] = 0.0; }
+    for (int b = 0; b < E.n_body; ++b) {
+        const double* pb = e + 6 * b;
+        const double r[3] = {X[0] - pb[0], X[1] - pb[1], X[2] - pb[2]};
+        const double r2 = dot3(r, r);
+        const double ir = rsqrt(r2);
+        const double ir2 = ir * ir, ir3 = ir2 * ir, ir5 = ir3 * ir2;
+        const double gm = E.gm[b];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                Jx[3 * i + j] += gm * (3.0 * r[i] * r[j] * ir5 - (i == j ? ir3 : 0.0));
+        const double k = E.kgr[b];
+        if (k != 0.0) {
+            const double w[3] = {V[0] - pb[3], V[1] - pb[4], V[2] - pb[5]};
+            const double w2 = dot3(w, w), rw = dot3(r, w);
+            const double s1 = 4.0 * gm * ir - w2;
+            const double P[3] = {s1 * r[0] + 4.0 * rw * w[0], s1 * r[1] + 4.0 * rw * w[1], s1 * r[2] + 4.0 * rw * w[2]};
+            const double ir6 = ir3 * ir3;
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    const double d = (i == j) ? 1.0 : 0.0;
+                    Jx[3 * i + j] += k * (-3.0 * P[i] * r[j] * ir5 - 4.0 * gm * r[i] * r[j] * ir6 + s1 * d * ir3 +
+                                          4.0 * w[i] * w[j] * ir3);
+                    Jv[3 * i + j] += k * ir3 * (-2.0 * r[i] * w[j] + 4.0 * w[i] * r[j] + 4.0 * rw * d);
+                }
+        }
+    }
+}
+
+// Perturber positions and velocities at the 9 node times of a step
+// (t + s_n h, and t_end for s = 1), one Clenshaw chain per lane, from the
+// LDS window of segments [seg_lo, seg_hi]; results in ephW[n][b][6].
+__device__ __forceinline__ void node_ephemeris(const double* __restrict__ coefL, int bstride, const EphemArgs& E,
+                                               const RadauConst& rc, int seg_lo, int seg_hi, double t, double h,
+                                               double t_end, int lane, double* __restrict__ ephW) {
+    const int nb = E.n_body, deg1 = E.deg1, cps = 3 * deg1;
+    const int nchain = kNodes * nb * 3;
+    for (int c = lane; c < nchain; c += kWave) {
+        const int n = c / (nb * 3);
+        const int r = c - n * nb * 3;
+        const int b = r / 3, i = r - 3 * b;
+        const double tt = (n == kNodes - 1) ? t_end : t + rc.s[n] * h;
+        const int k = seg_index(tt, E.t_start, E.inv_seg, seg_lo, seg_hi);
+        const double tau = 2.0 * (tt - (E.t_start + (double)k * E.seg_days)) * E.inv_seg - 1.0;
+        double pv, dv;
+        clenshaw(coefL + b * bstride + (k - seg_lo) * cps + i * deg1, deg1, tau, pv, dv);
+        ephW[(n * nb + b) * 6 + i] = pv;
+        ephW[(n * nb + b) * 6 + 3 + i] = dv * 2.0 * E.inv_seg;
+    }
+    wave_lds_sync();
+}
+
+// Stage the Chebyshev segments [seg_lo, seg_hi] of every body into LDS
+// (cooperatively by `nthreads` threads; the caller synchronizes).
+__device__ __forceinline__ void stage_window(const EphemArgs& E, int seg_lo, int seg_hi, int bstride, int tid,
+                                             int nthreads, double* __restrict__ coefL) {
+    const int cps = 3 * E.deg1;
+    const int per_body = (seg_hi - seg_lo + 1) * cps;
+    const int total = E.n_body * per_body;
+    for (int i = tid; i < total; i += nthreads) {
+        const int b = i / per_body, r = i - b * per_body;
+        coefL[b * bstride + r] = E.coef[((size_t)b * E.n_seg + seg_lo) * cps + r];
+    }
+}
+
+// The collocation corrector: fixed-point sweeps over the 7 nodes
+// (Gauss-Seidel: each node sees the increments already updated) until the
+// change of b6 relative to |a| is below 1e-16, stops decreasing after the
+// third sweep, or max_iter sweeps ran.  Returns the sweep count; b6 gets
+// the final highest coefficient.
+__device__ __forceinline__ int corrector(const RadauConst& rc, const EphemArgs& E, const double* __restrict__ ephW,
+                                         const double x0[3], const double v0[3], const double F0[3], double h,
+                                         bool active, int max_iter, double D[7][3], double b6[3],
+                                         unsigned long long& lane_iters) {
+    const double hh = h * h;
+#pragma unroll
+    for (int m = 0; m < 7; ++m) { D[m][0] = D[m][1] = D[m][2] = 0.0; }
+    b6[0] = b6[1] = b6[2] = 0.0;
+    double pc = 1e300, pcl;
+    int it = 0;
+    do {
+        pcl = pc;
+        ++it;
+        // An opaque zero row offset keeps the collocation constants in the
+        // kernel-argument segment (scalar loads per node) instead of being
+        // hoisted into vector registers.
+        int z;
+        asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+#pragma unroll
+        for (int n = 1; n <= 7; ++n) {
+            const int nz = n + z;
+            const double sh = rc.s[nz] * h;
+            double X[3], V[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                double acc = rc.half_s2[nz] * F0[c];
+#pragma unroll
+                for (int m = 0; m < 7; ++m) acc = fma(rc.A[nz][m], D[m][c], acc);
+                X[c] = fma(hh, acc, fma(sh, v0[c], x0[c]));
+            }
+            if (E.has_gr) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    double av = rc.s[nz] * F0[c];
+#pragma unroll
+                    for (int m = 0; m < 7; ++m) av = fma(rc.B[nz][m], D[m][c], av);
+                    V[c] = fma(h, av, v0[c]);
+                }
+            } else {
+                V[0] = v0[0]; V[1] = v0[1]; V[2] = v0[2];
+            }
+            double F[3];
+            accel(ephW + n * E.n_body * 6, E, X, V, F);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) D[n - 1][c] = F[c] - F0[c];
+        }
+        double db = 0.0, fm = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double b = 0.0;
+#pragma unroll
+            for (int m = 0; m < 7; ++m) b = fma(rc.E6[m + z], D[m][c], b);
+            db = fmax(db, fabs(b - b6[c]));
+            b6[c] = b;
+            fm = fmax(fm, fabs(D[6][c] + F0[c]));
+        }
+        const double lpc = (active && fm > 0.0) ? db / fm : 0.0;
+        pc = wave_max(lpc);
+        lane_iters += __popcll(__ballot(active));
+    } while (!(pc < 1e-16) && !(it > 2 && pcl <= pc) && it < max_iter);
+    return it;
+}
+
+// Collocation polynomial at fraction sig of the step (sig = 1: step end),
+// from the monomial weights alpha_m(sig) = sum_k Ap[m][k] sig^(k+2) and
+// beta_m(sig) = sum_k Bp[m][k] sig^(k+1) (m = 1..7, k = 0..7).
+__device__ __forceinline__ void dense_weights(const RadauConst& rc, double sig, double al[7], double be[7]) {
+#pragma unroll
+    for (int m = 0; m < 7; ++m) {
+        double a = rc.Ap[m][7], b = rc.Bp[m][7];
+#pragma unroll
+        for (int k = 6; k >= 0; --k) { a = fma(a, sig, rc.Ap[m][k]); b = fma(b, sig, rc.Bp[m][k]); }
+        al[m] = a * sig * sig;
+        be[m] = b * sig;
+    }
+}
+
+__device__ __forceinline__ void dense_state(const RadauConst& rc, const double x0[3], const double v0[3],
+                                            const double F0[3], const double D[7][3], double h, double sig,
+                                            double X[3], double V[3]) {
+    double al[7], be[7];
+    dense_weights(rc, sig, al, be);
+    const double hh = h * h;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        double ax = 0.5 * sig * sig * F0[c], av = sig * F0[c];
+#pragma unroll
+        for (int m = 0; m < 7; ++m) { ax = fma(al[m], D[m][c], ax); av = fma(be[m], D[m][c], av); }
+        X[c] = fma(hh, ax, fma(sig * h, v0[c], x0[c]));
+        V[c] = fma(h, av, v0[c]);
+    }
+}
+
+}  // namespace kete
