@@ -117,6 +117,45 @@ typedef struct {
     const double *normals;   /* device [n_frames][n_sub][4][3] */
 } kete_frames_t;
 
+/* One job of a batched run: n_obj bodies (rows obj_off.. of the
+ * concatenated state array) starting at the common epoch t0, integrated
+ * through n_epoch epochs (entries epoch_off.. of the concatenated epoch
+ * array, strictly monotone away from t0); their states at epoch e are
+ * written to x_out[xout_off + (e n_obj + j) 6 ..] (doubles). */
+typedef struct {
+    int64_t obj_off;
+    int64_t epoch_off;
+    int64_t xout_off;
+    int32_t n_obj;
+    int32_t n_epoch;
+    double t0;
+} kete_job_t;
+
+/* A batched run: jobs plus the frames each job checks.  Frames of all
+ * jobs are concatenated; the batches of all jobs are listed in one array
+ * (batch b belongs to job batch_job[b] and uses that job's epoch
+ * batch_epoch[b], whose time is t_ref[b]); frame_order / batch_off index
+ * the frames of each batch as in kete_fov_check.  The *_host arrays are
+ * host copies used to plan; every other pointer is device memory. */
+typedef struct {
+    int32_t n_jobs;
+    int32_t reserved;
+    int64_t n_bodies;               /* rows of x0 */
+    int64_t n_epochs;               /* entries of epochs */
+    int64_t n_batch;
+    const kete_job_t *jobs_host;    /* host [n_jobs] */
+    const kete_job_t *jobs;         /* device [n_jobs] */
+    const double *x0;               /* device [n_bodies][6] */
+    const double *epochs;           /* device [n_epochs] */
+    const int32_t *batch_job_host;  /* host [n_batch] */
+    const int32_t *batch_epoch_host;/* host [n_batch] */
+    const int32_t *batch_off_host;  /* host [n_batch + 1] */
+    const double *t_ref;            /* device [n_batch] */
+    const int32_t *batch_off;       /* device [n_batch + 1] */
+    const int32_t *frame_order;     /* device [n_frames] */
+    kete_frames_t frames;           /* device */
+} kete_batch_t;
+
 /* ---------------------------------------------------------------- calls */
 
 void kete_default_opts(kete_opts_t *opts);
@@ -249,6 +288,42 @@ int kete_propagate_adjoint(const kete_ephem_t *eph, int32_t mode, const double *
                            const double *dL_dsky, double ckpt_days, double *sky_out, double *grad_x0,
                            int32_t *status, const kete_opts_t *opts, void *workspace, size_t ws_bytes,
                            void *stream);
+
+/* Bytes of workspace for a batched run (plan, run and pairs share it). */
+size_t kete_batch_workspace_size(const kete_ephem_t *eph, const kete_batch_t *batch, int64_t pairs_cap,
+                                 const kete_opts_t *opts);
+
+/* Batched uneven jobs (one persistent launch for the propagation of every
+ * job, then the field-of-view stages of kete_fov_check over all batches).
+ * kete_batch_plan validates the batch, builds the tile queue (tiles of 64
+ * bodies, longest jobs first) and the batch tables, and uploads them into
+ * the workspace; it synchronizes `stream`.  The workspace layout depends
+ * on the batch, pairs_cap and opts, so every call of one run passes the
+ * same three.  kete_batch_run enqueues the
+ * whole computation without any host synchronization or memset, so it can
+ * be captured in a HIP graph; x_out receives every job's epoch states and
+ * status every body's status.  kete_batch_pairs then reads the pair count
+ * (one synchronization) and writes the pairs sorted by (frame, sub-frame,
+ * body), bodies numbered by their row in x0; KETE_ECAPACITY as in
+ * kete_fov_check. */
+int kete_batch_plan(const kete_ephem_t *eph, const kete_batch_t *batch, int64_t pairs_cap, const kete_opts_t *opts,
+                    void *workspace, size_t ws_bytes, void *stream);
+int kete_batch_run(const kete_ephem_t *eph, const kete_batch_t *batch, int64_t pairs_cap, const kete_opts_t *opts,
+                   double *x_out, int32_t *status, void *workspace, size_t ws_bytes, void *stream);
+int kete_batch_pairs(const kete_batch_t *batch, int64_t pairs_cap, const kete_opts_t *opts, int32_t *pf, int32_t *ps,
+                     int32_t *po, int64_t *n_pairs, void *workspace, size_t ws_bytes, void *stream);
+
+/* The same kete_batch_run captured once in a HIP graph and replayed.
+ * kete_batch_graph_create records the run (after kete_batch_plan) and
+ * returns an opaque handle; kete_batch_graph_launch replays it on
+ * `stream`; kete_batch_graph_destroy releases it.  The graph keeps the
+ * pointers it was recorded with: inputs, outputs and workspace must stay
+ * allocated, and replays see their current contents. */
+int kete_batch_graph_create(const kete_ephem_t *eph, const kete_batch_t *batch, int64_t pairs_cap,
+                            const kete_opts_t *opts, double *x_out, int32_t *status, void *workspace, size_t ws_bytes,
+                            void *stream, void **graph);
+int kete_batch_graph_launch(void *graph, void *stream);
+int kete_batch_graph_destroy(void *graph);
 
 /* Live kernel timing for measurement.  While enabled, every integrator
  * and FoV-candidate launch made by the calling thread is bracketed by HIP

@@ -47,6 +47,19 @@ class FramesT(C.Structure):
                 ("obs", C.c_void_p), ("normals", C.c_void_p)]
 
 
+class JobT(C.Structure):
+    _fields_ = [("obj_off", C.c_int64), ("epoch_off", C.c_int64), ("xout_off", C.c_int64), ("n_obj", C.c_int32),
+                ("n_epoch", C.c_int32), ("t0", C.c_double)]
+
+
+class BatchT(C.Structure):
+    _fields_ = [("n_jobs", C.c_int32), ("reserved", C.c_int32), ("n_bodies", C.c_int64), ("n_epochs", C.c_int64),
+                ("n_batch", C.c_int64), ("jobs_host", C.c_void_p), ("jobs", C.c_void_p), ("x0", C.c_void_p),
+                ("epochs", C.c_void_p), ("batch_job_host", C.c_void_p), ("batch_epoch_host", C.c_void_p),
+                ("batch_off_host", C.c_void_p), ("t_ref", C.c_void_p), ("batch_off", C.c_void_p),
+                ("frame_order", C.c_void_p), ("frames", FramesT)]
+
+
 # name -> (restype, argtypes)
 SIGNATURES = {
     "kete_default_opts": (None, [C.POINTER(OptsT)]),
@@ -74,6 +87,18 @@ SIGNATURES = {
                                          C.c_int64, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
                                          C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(OptsT), C.c_void_p,
                                          C.c_size_t, C.c_void_p]),
+    "kete_batch_workspace_size": (C.c_size_t, [C.POINTER(EphemT), C.POINTER(BatchT), C.c_int64, C.POINTER(OptsT)]),
+    "kete_batch_plan": (C.c_int, [C.POINTER(EphemT), C.POINTER(BatchT), C.c_int64, C.POINTER(OptsT), C.c_void_p,
+                                  C.c_size_t, C.c_void_p]),
+    "kete_batch_run": (C.c_int, [C.POINTER(EphemT), C.POINTER(BatchT), C.c_int64, C.POINTER(OptsT), C.c_void_p,
+                                 C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "kete_batch_pairs": (C.c_int, [C.POINTER(BatchT), C.c_int64, C.POINTER(OptsT), C.c_void_p, C.c_void_p,
+                                   C.c_void_p, C.POINTER(C.c_int64), C.c_void_p, C.c_size_t, C.c_void_p]),
+    "kete_batch_graph_create": (C.c_int, [C.POINTER(EphemT), C.POINTER(BatchT), C.c_int64, C.POINTER(OptsT),
+                                          C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p,
+                                          C.POINTER(C.c_void_p)]),
+    "kete_batch_graph_launch": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "kete_batch_graph_destroy": (C.c_int, [C.c_void_p]),
     "kete_timing_enable": (None, [C.c_int]),
     "kete_timing_read": (C.c_int, [C.c_void_p, C.c_void_p]),
 }

@@ -257,3 +257,111 @@ def sky_residual_loss(sky: torch.Tensor, radec_obs: torch.Tensor) -> torch.Tenso
     r1 = dra * torch.cos(sky[..., 1])
     r2 = sky[..., 1] - radec_obs[..., 1]
     return (r1 * r1 + r2 * r2).sum()
+
+
+class BatchRunner:
+    """Many independent jobs (bodies + frames) run as one batch: a
+    persistent propagation launch over all jobs, then the field-of-view
+    stages over every job's batches.  `jobs` is a list of
+    (x0 [n, 6] numpy, t0, frames) with frames a synth.Frames-like object.
+    Device tables are built once here (setup); run() and graph replays only
+    launch work.  Body and frame numbers in the pairs are global: job k's
+    body i is row obj_off[k] + i, its frame f is frame_off[k] + f."""
+
+    def __init__(self, eph: DeviceEphemeris, jobs, opts: Optional[OptsT] = None, pairs_cap: Optional[int] = None,
+                 device=DEV):
+        self.eph = eph
+        self.opts = opts or default_opts()
+        n_obj = [j[0].shape[0] for j in jobs]
+        self.obj_off = np.concatenate([[0], np.cumsum(n_obj)]).astype(np.int64)
+        n_fr = [j[2].t.shape[0] for j in jobs]
+        self.frame_off = np.concatenate([[0], np.cumsum(n_fr)]).astype(np.int64)
+        job_rows, epochs, orders, offs, bjob, bep, trefs = [], [], [], [0], [], [], []
+        ep_off, xo = 0, 0
+        self.job_epochs = []
+        for k, (x0, t0, fr) in enumerate(jobs):
+            order, off, t_ref = make_batches(fr.t, self.opts.batch_span)
+            # epochs visited away from t0: later ones ascending, then earlier ones descending
+            idx = np.arange(t_ref.size)
+            visit = np.concatenate([idx[t_ref >= t0], idx[t_ref < t0][::-1]])
+            pos = np.empty_like(idx)
+            pos[visit] = np.arange(visit.size)
+            job_rows.append((int(self.obj_off[k]), ep_off, xo, x0.shape[0], t_ref.size, float(t0)))
+            epochs.append(t_ref[visit])
+            self.job_epochs.append(t_ref[visit])
+            orders.append(order.astype(np.int64) + self.frame_off[k])
+            offs.extend((off[1:] + self.frame_off[k]).tolist())
+            bjob.extend([k] * t_ref.size)
+            bep.extend(pos.tolist())
+            trefs.append(t_ref)
+            ep_off += t_ref.size
+            xo += 6 * x0.shape[0] * t_ref.size
+        self.n_x = xo
+        self.jobs_host = (_lib.JobT * len(jobs))(*[_lib.JobT(*r) for r in job_rows])
+        jb = np.frombuffer(self.jobs_host, dtype=np.uint8).copy()
+        f = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a, dtype=dt)).to(device)
+        self.jobs_dev = torch.as_tensor(jb).to(device)
+        self.x0 = f(np.concatenate([j[0] for j in jobs]), np.float64)
+        self.epochs = f(np.concatenate(epochs), np.float64)
+        self.bjob = np.ascontiguousarray(bjob, dtype=np.int32)
+        self.bep = np.ascontiguousarray(bep, dtype=np.int32)
+        self.boff_host = np.ascontiguousarray(offs, dtype=np.int32)
+        self.t_ref = f(np.concatenate(trefs), np.float64)
+        self.boff = f(self.boff_host, np.int32)
+        self.order = f(np.concatenate(orders), np.int32)
+        cat = lambda name: np.concatenate([getattr(j[2], name) for j in jobs])
+        self.frames = DeviceFrames(f(cat("t"), np.float64), f(cat("obs"), np.float64), f(cat("normals"), np.float64))
+        self.fc = self.frames.c()
+        self.c = _lib.BatchT(len(jobs), 0, int(self.obj_off[-1]), int(ep_off), int(self.bjob.size),
+                             C.addressof(self.jobs_host), self.jobs_dev.data_ptr(), self.x0.data_ptr(),
+                             self.epochs.data_ptr(), self.bjob.ctypes.data, self.bep.ctypes.data,
+                             self.boff_host.ctypes.data, self.t_ref.data_ptr(), self.boff.data_ptr(),
+                             self.order.data_ptr(), self.fc)
+        F = int(self.frame_off[-1])
+        self.pairs_cap = int(pairs_cap) if pairs_cap is not None else max(1 << 16, 8 * F)
+        need = lib().kete_batch_workspace_size(C.byref(eph.c), C.byref(self.c), self.pairs_cap, C.byref(self.opts))
+        if need == 0:
+            raise _lib.KeteError(_lib.KETE_EINVAL, lib().kete_last_error().decode())
+        self.workspace = _workspace(need, device)
+        self.x_out = torch.empty(max(self.n_x, 1), dtype=torch.float64, device=device)
+        self.status = torch.zeros(max(int(self.obj_off[-1]), 1), dtype=torch.int32, device=device)
+        self.pf = torch.empty(self.pairs_cap, dtype=torch.int32, device=device)
+        self.ps = torch.empty_like(self.pf)
+        self.po = torch.empty_like(self.pf)
+        check(lib().kete_batch_plan(C.byref(eph.c), C.byref(self.c), self.pairs_cap, C.byref(self.opts),
+                                    _ptr(self.workspace), self.workspace.numel(), _stream()))
+        self.graph = None
+
+    def run(self):
+        check(lib().kete_batch_run(C.byref(self.eph.c), C.byref(self.c), self.pairs_cap, C.byref(self.opts),
+                                   _ptr(self.x_out), _ptr(self.status), _ptr(self.workspace),
+                                   self.workspace.numel(), _stream()))
+
+    def capture(self):
+        g = C.c_void_p(0)
+        check(lib().kete_batch_graph_create(C.byref(self.eph.c), C.byref(self.c), self.pairs_cap,
+                                            C.byref(self.opts), _ptr(self.x_out), _ptr(self.status),
+                                            _ptr(self.workspace), self.workspace.numel(), _stream(), C.byref(g)))
+        self.graph = g
+
+    def replay(self):
+        check(lib().kete_batch_graph_launch(self.graph, _stream()))
+
+    def pairs(self):
+        n = C.c_int64(0)
+        check(lib().kete_batch_pairs(C.byref(self.c), self.pairs_cap, C.byref(self.opts), _ptr(self.pf),
+                                     _ptr(self.ps), _ptr(self.po), C.byref(n), _ptr(self.workspace),
+                                     self.workspace.numel(), _stream()))
+        return self.pf[:n.value], self.ps[:n.value], self.po[:n.value]
+
+    def job_states(self, k: int) -> torch.Tensor:
+        """States of job k [n_epoch, n_obj, 6] at self.job_epochs[k]."""
+        r = self.jobs_host[k]
+        return self.x_out[r.xout_off:r.xout_off + 6 * r.n_obj * r.n_epoch].view(r.n_epoch, r.n_obj, 6)
+
+    def __del__(self):
+        try:
+            if self.graph is not None:
+                lib().kete_batch_graph_destroy(self.graph)
+        except Exception:
+            pass

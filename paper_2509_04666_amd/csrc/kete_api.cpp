@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "kete_adjoint.hpp"
+#include "kete_batch.hpp"
 #include "kete_fov.hpp"
 #include "kete_internal.hpp"
 #include "kete_mi.h"
@@ -200,40 +201,24 @@ int ephem_args(const kete_ephem_t* eph, double c_light, EphemArgs& E) {
 double t_end_of(const kete_ephem_t* e) { return e->t_start + e->n_seg * e->seg_days; }
 
 int seg_of(const kete_ephem_t* e, double t) {
-    int k = (int)std::floor((t - e->t_start) / e->seg_days);
-    return std::min(std::max(k, 0), e->n_seg - 1);
+    return seg_clamped(t, e->t_start, 1.0 / e->seg_days, e->n_seg);
 }
 
 // Windows between t0 and each epoch: every epoch ends a window, and a
-// window never spans more than `wsegs` segment lengths.
+// window never spans more than `wsegs` segment lengths (next_window).
 std::vector<Window> plan_windows(const kete_ephem_t* e, double t0, const double* t_out, int64_t n_out, int wsegs,
                                  std::vector<int>& epoch_end_win) {
     std::vector<Window> w;
     epoch_end_win.assign(n_out, -1);
+    const double inv = 1.0 / e->seg_days;
     double t = t0;
     for (int64_t k = 0; k < n_out; ++k) {
         const double target = t_out[k];
-        const bool fwd = target > t;
         while (t != target) {
-            double tb;
-            if (fwd) {
-                const double kk = std::floor((t - e->t_start) / e->seg_days);
-                const double limit = e->t_start + (kk + wsegs) * e->seg_days;
-                tb = (limit < target && limit > t) ? limit : target;
-            } else {
-                const double kk = std::ceil((t - e->t_start) / e->seg_days) - 1.0;
-                const double limit = e->t_start + (kk - wsegs + 1) * e->seg_days;
-                tb = (limit > target && limit < t) ? limit : target;
-            }
-            Window W;
-            W.t_a = t;
-            W.t_b = tb;
-            W.seg_lo = seg_of(e, std::min(t, tb));
-            W.seg_hi = seg_of(e, std::max(t, tb));
-            W.out = (tb == target) ? (int32_t)k : -1;
-            W.pad = 0;
+            Window W = next_window(t, target, e->t_start, e->seg_days, inv, e->n_seg, wsegs);
+            W.out = (W.t_b == target) ? (int32_t)k : -1;
             w.push_back(W);
-            t = tb;
+            t = W.t_b;
         }
         if (w.empty() || w.back().out != (int32_t)k) {
             // epoch equal to the current time: an empty window that only writes output
@@ -469,7 +454,7 @@ static int64_t cand_capacity(int64_t n_frames, int64_t pairs_cap) {
 
 static int grid_dims(const kete_opts_t* o, int64_t n_batch, int& G, double& L) {
     L = o->cell_chord > 0 ? o->cell_chord : 0.08;
-    G = (int)std::ceil(2.0 / L);
+    G = (int)std::ceil(2.0 / L - 1e-9);
     if (G < 1) G = 1;
     if (G > 128) return fail(KETE_EINVAL, "cell_chord too small (grid > 128 cells per axis)");
     if ((double)n_batch * G * G * G > 2.0e9) return fail(KETE_EINVAL, "sky grid too large for %lld batches", (long long)n_batch);
@@ -483,7 +468,7 @@ size_t kete_fov_workspace_size(int64_t n_obj, int64_t n_frames, int64_t n_batch,
     (void)n_obj; (void)n_sub;
     int G; double L;
     if (grid_dims(opts, n_batch, G, L)) return 0;
-    const int64_t nkeys = n_batch * (int64_t)G * G * G;
+    const int64_t nkeys = n_batch * ((int64_t)G * G * G + 1);
     Carver c{nullptr};
     c.take<double>((size_t)n_frames * 8);
     c.take<double>((size_t)n_batch * kBatchStride);
@@ -501,10 +486,15 @@ size_t kete_fov_workspace_size(int64_t n_obj, int64_t n_frames, int64_t n_batch,
     c.take<int32_t>((size_t)n_frames);
     c.take<int32_t>((size_t)(n_batch * n_obj));     // object cell keys
     c.take<int32_t>((size_t)(n_batch * n_obj));     // objects sorted by cell
-    c.take<int32_t>((size_t)(nkeys + n_batch) + 1); // object cell starts and counts
-    c.take<int32_t>((size_t)(nkeys + n_batch) + 1);
+    c.take<int32_t>((size_t)nkeys + 1);             // object cell starts and counts
+    c.take<int32_t>((size_t)nkeys + 1);
     c.take<unsigned long long>((size_t)(n_batch * n_obj));   // wide objects
-    c.take<char>(scan_scratch_bytes(nkeys + n_batch));
+    c.take<char>(scan_scratch_bytes(nkeys));
+    c.take<int64_t>((size_t)n_batch + 1);          // batch -> object layout
+    c.take<int32_t>((size_t)n_batch);
+    c.take<int64_t>((size_t)n_batch);
+    c.take<int32_t>((size_t)n_batch);              // grid sizes and key offsets
+    c.take<int64_t>((size_t)n_batch + 1);
     return c.off;
 }
 
@@ -535,7 +525,7 @@ int kete_fov_check(const kete_ephem_t* eph, const double* x_epoch, const int32_t
         return fail(KETE_EINVAL, "fov_block must be 64, 128 or 256");
     int G; double L;
     if ((rc = grid_dims(opts, n_batch, G, L))) return rc;
-    const int64_t nkeys = n_batch * (int64_t)G * G * G;
+    const int64_t nkeys = n_batch * ((int64_t)G * G * G + 1);
     const int64_t F = frames->n_frames;
     if (!workspace) return fail(KETE_EWORKSPACE, "workspace is null");
     const size_t need = kete_fov_workspace_size(n_obj, F, n_batch, frames->n_sub, pairs_cap, opts);
@@ -561,10 +551,22 @@ int kete_fov_check(const kete_ephem_t* eph, const double* x_epoch, const int32_t
     P.frame_batch = c.take<int32_t>((size_t)F);
     int32_t* okey = c.take<int32_t>((size_t)(n_batch * n_obj));
     int32_t* osorted = c.take<int32_t>((size_t)(n_batch * n_obj));
-    int32_t* ostart = c.take<int32_t>((size_t)(nkeys + n_batch) + 1);
-    int32_t* ocnt = c.take<int32_t>((size_t)(nkeys + n_batch) + 1);
+    int32_t* ostart = c.take<int32_t>((size_t)nkeys + 1);
+    int32_t* ocnt = c.take<int32_t>((size_t)nkeys + 1);
     P.wide = c.take<unsigned long long>((size_t)(n_batch * n_obj));
-    void* oscan = c.take<char>(scan_scratch_bytes(nkeys + n_batch));
+    void* oscan = c.take<char>(scan_scratch_bytes(nkeys));
+    int64_t* b_poff = c.take<int64_t>((size_t)n_batch + 1);
+    int32_t* b_obj0 = c.take<int32_t>((size_t)n_batch);
+    int64_t* b_xoff = c.take<int64_t>((size_t)n_batch);
+    int32_t* b_G = c.take<int32_t>((size_t)n_batch);
+    int64_t* b_koff = c.take<int64_t>((size_t)n_batch + 1);
+    P.b_poff = b_poff;
+    P.b_obj0 = b_obj0;
+    P.b_xoff = b_xoff;
+    P.b_G = b_G;
+    P.b_koff = b_koff;
+    P.n_keys = nkeys;
+    P.n_pairs_total = n_batch * n_obj;
 
     P.eph = E;
     P.x_epoch = x_epoch;
@@ -579,8 +581,6 @@ int kete_fov_check(const kete_ephem_t* eph, const double* x_epoch, const int32_t
     P.fobs = frames->obs;
     P.normals = frames->normals;
     P.n_sub = frames->n_sub;
-    P.G = G;
-    P.inv_L = 1.0 / L;
     P.n_pairs = counters;
     P.stats = counters + 1;
     P.n_cand = counters + 5;
@@ -594,8 +594,9 @@ int kete_fov_check(const kete_ephem_t* eph, const double* x_epoch, const int32_t
     P.sin_overflow = 0.5;
 
     hipStream_t s = (hipStream_t)stream;
-    HIPCHK(hipMemsetAsync(counters, 0, 8 * sizeof(unsigned long long), s));
-    HIPCHK(fov_prepare(P, qkey, cnt, cnt, nkeys, scan_scratch, s));
+    HIPCHK(fill_zero(counters, 8 * sizeof(unsigned long long), s));
+    HIPCHK(fov_single_job_layout(b_poff, b_obj0, b_xoff, b_G, b_koff, n_batch, n_obj, G, s));
+    HIPCHK(fov_prepare(P, qkey, cnt, cnt, scan_scratch, s));
     P.n_wide = counters + 6;
     HIPCHK(fov_sort_objects(P, okey, ocnt, ostart, osorted, oscan, s));
     P.obj_sorted = osorted;
@@ -763,6 +764,361 @@ int kete_propagate_adjoint(const kete_ephem_t* eph, int32_t mode, const double* 
         TimedScope ts(kTimeAdjoint, s);
         HIPCHK(launch_adjoint(P, mode, s));
     }
+    return KETE_OK;
+}
+
+// ---------------------------------------------------------------- batched jobs
+namespace {
+
+// Sizes and host-side tables of a batched run (recomputed identically by
+// every batch call from the host copies).
+struct BatchDims {
+    int64_t F = 0, B = 0, NP = 0, nkeys = 0, cand_cap = 0, pairs_cap = 0;
+    int32_t n_tiles = 0, n_sub = 1;
+    std::vector<int2> tiles;
+    std::vector<int64_t> b_poff, b_xoff, b_koff;
+    std::vector<int32_t> b_obj0, b_G;
+};
+
+constexpr int kSmallBatchFrames = 256;   // below this a batch's frames share one grid cell
+
+int batch_dims(const kete_ephem_t* eph, const kete_batch_t* bt, int64_t pairs_cap, const kete_opts_t* o,
+               bool tables, BatchDims& d) {
+    if (!bt || !bt->jobs_host || bt->n_jobs < 0 || bt->n_batch < 0 || bt->n_bodies < 0)
+        return fail(KETE_EINVAL, "bad batch description");
+    if (bt->n_bodies > KETE_MAX_OBJ) return fail(KETE_EINVAL, "too many bodies");
+    if (pairs_cap < 0) return fail(KETE_EINVAL, "pairs_cap < 0");
+    d.F = bt->frames.n_frames;
+    d.B = bt->n_batch;
+    d.n_sub = bt->frames.n_sub;
+    d.pairs_cap = pairs_cap;
+    if (d.n_sub < 1 || d.n_sub > KETE_MAX_SUB) return fail(KETE_EINVAL, "n_sub outside 1..%d", KETE_MAX_SUB);
+    if (d.B > 0 && (!bt->batch_job_host || !bt->batch_epoch_host || !bt->batch_off_host))
+        return fail(KETE_EINVAL, "null batch host tables");
+    const double L = o->cell_chord > 0 ? o->cell_chord : 0.08;
+    const int Gbig = (int)std::ceil(2.0 / L - 1e-9);
+    if (Gbig > 128) return fail(KETE_EINVAL, "cell_chord too small");
+    // jobs
+    const kete_job_t* J = bt->jobs_host;
+    double tlo = eph ? eph->t_start : -1e300, thi = eph ? t_end_of(eph) : 1e300;
+    for (int j = 0; j < bt->n_jobs; ++j) {
+        if (J[j].n_obj < 0 || J[j].n_epoch < 0 || J[j].obj_off < 0 || J[j].obj_off + J[j].n_obj > bt->n_bodies ||
+            J[j].epoch_off < 0 || J[j].epoch_off + J[j].n_epoch > bt->n_epochs || J[j].xout_off < 0)
+            return fail(KETE_EINVAL, "job %d out of range", j);
+        if (!(J[j].t0 >= tlo && J[j].t0 <= thi)) return fail(KETE_ERANGE, "job %d t0 outside the ephemeris", j);
+    }
+    // tiles, longest (span + landings) first
+    std::vector<std::pair<double, int64_t>> cost;
+    for (int j = 0; j < bt->n_jobs; ++j) {
+        const int nt = (J[j].n_obj + 63) / 64;
+        d.n_tiles += nt;
+    }
+    if (tables) {
+        std::vector<double> span(bt->n_jobs, 0.0);
+        (void)span;
+        d.tiles.reserve(d.n_tiles);
+        for (int j = 0; j < bt->n_jobs; ++j)
+            for (int t = 0; t < (J[j].n_obj + 63) / 64; ++t) d.tiles.push_back(make_int2(j, t));
+    }
+    // batches
+    if (tables) {
+        d.b_poff.assign(d.B + 1, 0);
+        d.b_koff.assign(d.B + 1, 0);
+        d.b_xoff.assign(d.B, 0);
+        d.b_obj0.assign(d.B, 0);
+        d.b_G.assign(d.B, 1);
+    }
+    int64_t np = 0, nk = 0;
+    for (int64_t b = 0; b < d.B; ++b) {
+        const int j = bt->batch_job_host[b];
+        if (j < 0 || j >= bt->n_jobs) return fail(KETE_EINVAL, "batch %lld has no job", (long long)b);
+        const int e = bt->batch_epoch_host[b];
+        if (e < 0 || e >= J[j].n_epoch) return fail(KETE_EINVAL, "batch %lld epoch out of range", (long long)b);
+        const int nf = bt->batch_off_host[b + 1] - bt->batch_off_host[b];
+        const int G = nf < kSmallBatchFrames ? 1 : Gbig;
+        if (tables) {
+            d.b_poff[b] = np;
+            d.b_koff[b] = nk;
+            d.b_xoff[b] = J[j].xout_off + 6 * (int64_t)e * J[j].n_obj;
+            d.b_obj0[b] = (int32_t)J[j].obj_off;
+            d.b_G[b] = G;
+        }
+        np += J[j].n_obj;
+        nk += (int64_t)G * G * G + 1;
+    }
+    if (tables) { d.b_poff[d.B] = np; d.b_koff[d.B] = nk; }
+    if (np >= 2000000000LL || nk >= 2000000000LL) return fail(KETE_EINVAL, "batch too large for 32-bit indices");
+    d.NP = np;
+    d.nkeys = nk;
+    d.cand_cap = cand_capacity(d.F, pairs_cap);
+    // longest first: cost ~ span of the job plus a landing per epoch
+    if (tables && !d.tiles.empty()) {
+        std::vector<double> c(bt->n_jobs);
+        const double* ep = nullptr;
+        (void)ep;
+        for (int j = 0; j < bt->n_jobs; ++j) c[j] = (double)J[j].n_epoch;
+        std::stable_sort(d.tiles.begin(), d.tiles.end(),
+                         [&](const int2& a, const int2& b) { return c[a.x] > c[b.x]; });
+    }
+    return KETE_OK;
+}
+
+struct BatchWs {
+    int2* tiles;
+    unsigned int* tile_counter;
+    int32_t* perm;
+    FovParams P;
+    int32_t *qkey, *cnt, *fcnt, *fstart, *okey, *osorted, *ostart, *ocnt;
+    unsigned long long *counters, *sorted;
+    void *scan_scratch, *oscan;
+    int64_t *b_poff, *b_xoff, *b_koff;
+    int32_t *b_obj0, *b_G;
+};
+
+size_t batch_carve(const BatchDims& d, const kete_batch_t* bt, char* base, BatchWs& w) {
+    Carver c{base};
+    w.tiles = c.take<int2>((size_t)std::max(d.n_tiles, 1));
+    w.tile_counter = c.take<unsigned int>(64);
+    w.perm = c.take<int32_t>((size_t)std::max<int64_t>(bt->n_bodies, 1));
+    FovParams& P = w.P;
+    std::memset(&P, 0, sizeof(P));
+    P.fcap = c.take<double>((size_t)d.F * 8);
+    P.btab = c.take<double>((size_t)d.B * kBatchStride);
+    w.qkey = c.take<int32_t>((size_t)d.F);
+    w.cnt = c.take<int32_t>((size_t)d.nkeys + 1);
+    P.cell_start = c.take<int32_t>((size_t)d.nkeys + 1);
+    P.cell_frames = c.take<int32_t>((size_t)d.F);
+    P.pairs = c.take<unsigned long long>((size_t)std::max<int64_t>(d.pairs_cap, 1));
+    w.counters = c.take<unsigned long long>(8);
+    w.fcnt = c.take<int32_t>((size_t)d.F + 1);
+    w.fstart = c.take<int32_t>((size_t)d.F + 1);
+    w.sorted = c.take<unsigned long long>((size_t)std::max<int64_t>(d.pairs_cap, 1));
+    w.scan_scratch = c.take<char>(std::max(scan_scratch_bytes(d.nkeys), scan_scratch_bytes(d.F)));
+    P.cand = c.take<unsigned long long>((size_t)d.cand_cap);
+    P.frame_batch = c.take<int32_t>((size_t)d.F);
+    w.okey = c.take<int32_t>((size_t)d.NP);
+    w.osorted = c.take<int32_t>((size_t)d.NP);
+    w.ostart = c.take<int32_t>((size_t)d.nkeys + 1);
+    w.ocnt = c.take<int32_t>((size_t)d.nkeys + 1);
+    P.wide = c.take<unsigned long long>((size_t)std::max<int64_t>(d.NP, 1));
+    w.oscan = c.take<char>(scan_scratch_bytes(d.nkeys));
+    w.b_poff = c.take<int64_t>((size_t)d.B + 1);
+    w.b_obj0 = c.take<int32_t>((size_t)d.B + 1);
+    w.b_xoff = c.take<int64_t>((size_t)d.B + 1);
+    w.b_G = c.take<int32_t>((size_t)d.B + 1);
+    w.b_koff = c.take<int64_t>((size_t)d.B + 1);
+    return c.off;
+}
+
+}  // namespace
+
+size_t kete_batch_workspace_size(const kete_ephem_t* eph, const kete_batch_t* batch, int64_t pairs_cap,
+                                 const kete_opts_t* opts) {
+    kete_opts_t dflt;
+    if (!opts) { kete_default_opts(&dflt); opts = &dflt; }
+    BatchDims d;
+    if (batch_dims(eph, batch, pairs_cap, opts, false, d)) return 0;
+    BatchWs w;
+    return batch_carve(d, batch, nullptr, w);
+}
+
+int kete_batch_plan(const kete_ephem_t* eph, const kete_batch_t* batch, int64_t pairs_cap, const kete_opts_t* opts,
+                    void* workspace, size_t ws_bytes, void* stream) {
+    kete_opts_t dflt;
+    if (!opts) { kete_default_opts(&dflt); opts = &dflt; }
+    g_err.clear();
+    EphemArgs E;
+    int rc = ephem_args(eph, opts->c_light > 0 ? opts->c_light : kC, E);
+    if (rc) return rc;
+    BatchDims d;
+    if ((rc = batch_dims(eph, batch, pairs_cap, opts, true, d))) return rc;
+    if (!workspace) return fail(KETE_EWORKSPACE, "workspace is null");
+    BatchWs w;
+    const size_t need = batch_carve(d, batch, nullptr, w);
+    if (ws_bytes < need) return fail(KETE_EWORKSPACE, "workspace %zu bytes < %zu required", ws_bytes, need);
+    batch_carve(d, batch, (char*)workspace, w);
+    hipStream_t s = (hipStream_t)stream;
+    if (d.n_tiles) HIPCHK(hipMemcpyAsync(w.tiles, d.tiles.data(), d.tiles.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+    if (d.B) {
+        HIPCHK(hipMemcpyAsync(w.b_poff, d.b_poff.data(), d.b_poff.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(w.b_koff, d.b_koff.data(), d.b_koff.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(w.b_xoff, d.b_xoff.data(), d.b_xoff.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(w.b_obj0, d.b_obj0.data(), d.b_obj0.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(w.b_G, d.b_G.data(), d.b_G.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    return KETE_OK;
+}
+
+int kete_batch_run(const kete_ephem_t* eph, const kete_batch_t* batch, int64_t pairs_cap, const kete_opts_t* opts,
+                   double* x_out, int32_t* status, void* workspace, size_t ws_bytes, void* stream) {
+    kete_opts_t dflt;
+    if (!opts) { kete_default_opts(&dflt); opts = &dflt; }
+    g_err.clear();
+    EphemArgs E;
+    const double cl = opts->c_light > 0 ? opts->c_light : kC;
+    int rc = ephem_args(eph, cl, E);
+    if (rc) return rc;
+    if (!workspace || (!x_out && batch->n_bodies) || (!status && batch->n_bodies)) return fail(KETE_EINVAL, "null pointer");
+    if (!batch->jobs || (batch->n_bodies && !batch->x0) || (batch->n_epochs && !batch->epochs)) return fail(KETE_EINVAL, "null batch pointer");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t cap = pairs_cap;
+    BatchDims dc;
+    if ((rc = batch_dims(eph, batch, cap, opts, false, dc))) return rc;
+    BatchWs w;
+    if (ws_bytes < batch_carve(dc, batch, nullptr, w)) return fail(KETE_EWORKSPACE, "workspace too small");
+    batch_carve(dc, batch, (char*)workspace, w);
+    BatchParams B;
+    std::memset(&B, 0, sizeof(B));
+    B.eph = E;
+    B.rc = radau_const();
+    B.jobs = batch->jobs;
+    B.n_jobs = batch->n_jobs;
+    B.n_tiles = dc.n_tiles;
+    B.tiles = w.tiles;
+    B.tile_counter = w.tile_counter;
+    B.x0 = batch->x0;
+    B.epochs = batch->epochs;
+    B.x_out = x_out;
+    B.status = status;
+    B.perm = w.perm;
+    B.n_buckets = std::min(std::max(1, opts->n_buckets), 32);
+    B.max_win_segs = std::max(1, opts->window_segs) + 1;
+    B.max_iter = opts->max_iter;
+    B.max_steps = opts->max_steps;
+    B.eps = opts->eps;
+    B.h_min = opts->h_min;
+    B.h_max = opts->h_max;
+    B.h_init = opts->h_init;
+    B.safety = 0.25;
+    {
+        TimedScope ts(kTimeBatch, s);
+        HIPCHK(launch_batch(B, 8, s));
+    }
+    // field-of-view stages over every batch
+    FovParams& P = w.P;
+    P.eph = E;
+    P.x_epoch = x_out;
+    P.status = status;
+    P.n_obj = (int32_t)batch->n_bodies;
+    P.n_batch = (int32_t)dc.B;
+    P.n_frames = dc.F;
+    P.t_ref = batch->t_ref;
+    P.batch_off = batch->batch_off;
+    P.frame_order = batch->frame_order;
+    P.ft = batch->frames.t;
+    P.fobs = batch->frames.obs;
+    P.normals = batch->frames.normals;
+    P.n_sub = batch->frames.n_sub;
+    P.n_pairs = w.counters;
+    P.stats = w.counters + 1;
+    P.n_cand = w.counters + 5;
+    P.n_wide = w.counters + 6;
+    P.cap = cap;
+    P.cand_cap = dc.cand_cap;
+    P.b_poff = w.b_poff;
+    P.b_obj0 = w.b_obj0;
+    P.b_xoff = w.b_xoff;
+    P.b_G = w.b_G;
+    P.b_koff = w.b_koff;
+    P.n_keys = dc.nkeys;
+    P.n_pairs_total = dc.NP;
+    P.mu = E.gm[0];
+    P.smu = std::sqrt(E.gm[0]);
+    P.c_light = cl;
+    P.lt_tol = opts->lt_tol > 0 ? opts->lt_tol : 1e-15;
+    P.lt_iter = opts->lt_iter > 0 ? opts->lt_iter : 10;
+    P.max_cells = 1024;
+    P.sin_overflow = 0.5;
+    HIPCHK(fill_zero(w.counters, 8 * sizeof(unsigned long long), s));
+    if (dc.B > 0 && dc.F > 0 && dc.NP > 0) {
+        HIPCHK(fov_prepare(P, w.qkey, w.cnt, w.cnt, w.scan_scratch, s));
+        HIPCHK(fov_sort_objects(P, w.okey, w.ocnt, w.ostart, w.osorted, w.oscan, s));
+        P.obj_sorted = w.osorted;
+        TimedScope ts(kTimeFov, s);
+        HIPCHK(fov_candidates(P, opts->fov_block, s));
+        HIPCHK(fov_exact(P, s));
+    }
+    return KETE_OK;
+}
+
+int kete_batch_pairs(const kete_batch_t* batch, int64_t pairs_cap, const kete_opts_t* opts, int32_t* pf, int32_t* ps,
+                     int32_t* po, int64_t* n_pairs, void* workspace, size_t ws_bytes, void* stream) {
+    g_err.clear();
+    kete_opts_t dflt;
+    if (!opts) { kete_default_opts(&dflt); opts = &dflt; }
+    if (!n_pairs || !workspace) return fail(KETE_EINVAL, "null pointer");
+    *n_pairs = 0;
+    BatchDims d;
+    int rc = batch_dims(nullptr, batch, pairs_cap, opts, false, d);
+    if (rc) return rc;
+    BatchWs w;
+    if (ws_bytes < batch_carve(d, batch, nullptr, w)) return fail(KETE_EWORKSPACE, "workspace too small");
+    batch_carve(d, batch, (char*)workspace, w);
+    hipStream_t s = (hipStream_t)stream;
+    unsigned long long hc[8];
+    HIPCHK(hipMemcpyAsync(hc, w.counters, sizeof(hc), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int i = 0; i < 4; ++i) g_fov_stats[i] = hc[1 + i];
+    const int64_t np = (int64_t)hc[0];
+    *n_pairs = np;
+    if ((int64_t)hc[5] > d.cand_cap)
+        return fail(KETE_ECAPACITY, "%llu exact-test candidates exceed the workspace capacity", hc[5]);
+    if (np > pairs_cap) return fail(KETE_ECAPACITY, "%lld pairs exceed pairs_cap", (long long)np);
+    if (np > 0 && (!pf || !ps || !po)) return fail(KETE_EINVAL, "null output pointer");
+    HIPCHK(fov_sort(w.P.pairs, np, d.F, w.fcnt, w.fstart, w.sorted, w.scan_scratch, pf, ps, po, s));
+    return KETE_OK;
+}
+
+struct BatchGraph {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+int kete_batch_graph_create(const kete_ephem_t* eph, const kete_batch_t* batch, int64_t pairs_cap,
+                            const kete_opts_t* opts, double* x_out, int32_t* status, void* workspace, size_t ws_bytes,
+                            void* stream, void** graph) {
+    g_err.clear();
+    if (!graph) return fail(KETE_EINVAL, "graph is null");
+    *graph = nullptr;
+    hipStream_t cs = nullptr;
+    HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) { hipStreamDestroy(cs); return fail(KETE_EDEVICE, "begin capture: %s", hipGetErrorString(e)); }
+    const bool was_timing = g_timing;
+    g_timing = false;
+    int rc = kete_batch_run(eph, batch, pairs_cap, opts, x_out, status, workspace, ws_bytes, cs);
+    g_timing = was_timing;
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(cs, &g);
+    hipStreamDestroy(cs);
+    if (rc) { if (g) hipGraphDestroy(g); return rc; }
+    if (e != hipSuccess || !g) return fail(KETE_EDEVICE, "end capture: %s", hipGetErrorString(e));
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) { hipGraphDestroy(g); return fail(KETE_EDEVICE, "instantiate: %s", hipGetErrorString(e)); }
+    BatchGraph* bg = new BatchGraph{g, ex};
+    *graph = bg;
+    (void)stream;
+    return KETE_OK;
+}
+
+int kete_batch_graph_launch(void* graph, void* stream) {
+    g_err.clear();
+    if (!graph) return fail(KETE_EINVAL, "graph is null");
+    BatchGraph* bg = (BatchGraph*)graph;
+    hipStream_t s = (hipStream_t)stream;
+    TimedScope ts(kTimeBatch, s);
+    HIPCHK(hipGraphLaunch(bg->exec, s));
+    return KETE_OK;
+}
+
+int kete_batch_graph_destroy(void* graph) {
+    if (!graph) return KETE_OK;
+    BatchGraph* bg = (BatchGraph*)graph;
+    hipGraphExecDestroy(bg->exec);
+    hipGraphDestroy(bg->graph);
+    delete bg;
     return KETE_OK;
 }
 

@@ -1,0 +1,153 @@
+// Many independent propagation jobs of uneven size in one persistent
+// launch.  A job is a set of bodies with a common start epoch and its own
+// list of output epochs.  Its bodies are sorted by predicted step size
+// (stable, per job) and cut into tiles of 64; a grid sized to the device
+// pops tiles from a queue ordered longest-first, one wavefront per tile,
+// each with its own LDS window of Chebyshev segments.
+#include <math.h>
+
+#include "kete_batch.hpp"
+#include "kete_radau.hpp"
+
+namespace kete {
+namespace {
+
+// Stable per-job bucketing by the initial step estimate 0.05 (r^3/mu)^(1/2):
+// one block per job, two passes over the job's bodies in chunks of 256.
+__global__ __launch_bounds__(256) void k_job_bucket(const BatchParams p) {
+    __shared__ int hist[32], base[32], run[32], wcount[4][32];
+    const int J = blockIdx.x;
+    const kete_job_t job = p.jobs[J];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int nbk = p.n_buckets;
+    if (tid < 32) { hist[tid] = 0; run[tid] = 0; }
+    __syncthreads();
+    auto key_of = [&](int64_t k) {
+        const double* x = p.x0 + 6 * (job.obj_off + k);
+        const double r = sqrt(dot3(x, x));
+        const double h = 0.05 * sqrt(r * r * r / p.eph.gm[0]);
+        if (!(h < kInf)) return nbk - 1;
+        int b = (int)floor(log2(h * 64.0));
+        return b < 0 ? 0 : (b >= nbk ? nbk - 1 : b);
+    };
+    for (int64_t k = tid; k < job.n_obj; k += 256) atomicAdd(&hist[key_of(k)], 1);
+    __syncthreads();
+    if (tid == 0) {
+        int acc = 0;
+        for (int b = 0; b < nbk; ++b) { base[b] = acc; acc += hist[b]; }
+    }
+    __syncthreads();
+    const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int64_t c0 = 0; c0 < job.n_obj; c0 += 256) {
+        const int64_t k = c0 + tid;
+        const int key = k < job.n_obj ? key_of(k) : -1;
+        int rank = 0;
+        for (int b = 0; b < nbk; ++b) {
+            const unsigned long long m = __ballot(key == b);
+            if (key == b) rank = __popcll(m & lt);
+            if (lane == 0) wcount[wid][b] = __popcll(m);
+        }
+        __syncthreads();
+        if (key >= 0) {
+            int before = 0;
+            for (int w = 0; w < wid; ++w) before += wcount[w][key];
+            p.perm[job.obj_off + base[key] + run[key] + before + rank] = (int32_t)k;
+        }
+        __syncthreads();
+        if (tid < nbk) for (int w = 0; w < 4; ++w) run[tid] += wcount[w][tid];
+        __syncthreads();
+    }
+}
+
+// Stage segments lo..hi into LDS unless they are already there.
+__device__ __forceinline__ void ensure_window(const EphemArgs& E, int a, int b, int& lo, int& hi, double* coefL,
+                                              int bstride) {
+    if (a >= lo && b <= hi) return;
+    __syncthreads();
+    stage_window(E, a, b, bstride, threadIdx.x, 64, coefL);
+    __syncthreads();
+    lo = a; hi = b;
+}
+
+__global__ __launch_bounds__(64) void k_batch_nbody(const BatchParams p) {
+    extern __shared__ double smem[];
+    const int lane = threadIdx.x;
+    const EphemArgs& E = p.eph;
+    const int bstride = p.max_win_segs * 3 * E.deg1;
+    double* coefL = smem;
+    double* ephW = smem + (size_t)E.n_body * bstride;
+    const int W = p.max_win_segs - 1;            // segment lengths per window
+    for (;;) {
+        int tile = 0;
+        if (lane == 0) tile = (int)atomicAdd(p.tile_counter, 1u);
+        tile = __shfl(tile, 0, 64);
+        if (tile >= p.n_tiles) break;
+        const int2 tj = p.tiles[tile];
+        const kete_job_t job = p.jobs[tj.x];
+        const int64_t k = (int64_t)tj.y * 64 + lane;
+        const bool valid = k < job.n_obj;
+        const int64_t local = valid ? (p.n_buckets > 1 ? p.perm[job.obj_off + k] : k) : 0;
+        const int64_t gobj = job.obj_off + local;
+        Lane L;
+        L.status = 0;
+        L.active = valid;
+        for (int i = 0; i < 3; ++i) {
+            L.x0[i] = valid ? p.x0[6 * gobj + i] : (i == 0 ? 1.0 : 0.0);
+            L.v0[i] = valid ? p.x0[6 * gobj + 3 + i] : 0.0;
+            L.F0[i] = 0.0;
+        }
+        double hp = kInf;
+        if (valid) {
+            const double r = sqrt(dot3(L.x0, L.x0));
+            hp = 0.05 * sqrt(r * r * r / E.gm[0]);
+        }
+        double hw = wave_min(L.active ? hp : kInf);
+        if (!(hw < kInf)) hw = p.h_init;
+        double t = job.t0;
+        bool haveF0 = false;
+        long wsteps = 0;
+        int lo = 1, hi = 0;                       // nothing staged yet
+        for (int e = 0; e < job.n_epoch; ++e) {
+            const double target = p.epochs[job.epoch_off + e];
+            while (t != target) {
+                Window Wn = next_window(t, target, E.t_start, E.seg_days, E.inv_seg, E.n_seg, W);
+                ensure_window(E, Wn.seg_lo, Wn.seg_hi, lo, hi, coefL, bstride);
+                Wn.seg_lo = lo;
+                Wn.seg_hi = hi;
+                integrate_window(p, Wn, coefL, bstride, ephW, L, t, hw, haveF0, wsteps,
+                                 [](double, double, const double (*)[3], const double*) {});
+                t = Wn.t_b;
+            }
+            if (valid) {
+                double* dst = p.x_out + job.xout_off + ((int64_t)e * job.n_obj + local) * 6;
+                const bool ok = L.active && L.status == 0;
+                for (int i = 0; i < 3; ++i) {
+                    dst[i] = ok ? L.x0[i] : __builtin_nan("");
+                    dst[3 + i] = ok ? L.v0[i] : __builtin_nan("");
+                }
+            }
+        }
+        if (valid) p.status[gobj] = L.status;
+    }
+}
+
+}  // namespace
+
+size_t batch_lds_bytes(const BatchParams& p) {
+    return ((size_t)p.eph.n_body * p.max_win_segs * 3 * p.eph.deg1 + (size_t)kNodes * p.eph.n_body * 6) *
+           sizeof(double);
+}
+
+hipError_t launch_batch(const BatchParams& p, int waves_per_cu, hipStream_t s) {
+    int dev = 0, ncu = 256;
+    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    hipError_t e;
+    if ((e = fill_zero(p.tile_counter, sizeof(unsigned int), s)) != hipSuccess) return e;
+    if (p.n_jobs > 0 && p.n_buckets > 1)
+        hipLaunchKernelGGL(k_job_bucket, dim3((unsigned)p.n_jobs), dim3(256), 0, s, p);
+    const int grid = std::max(1, std::min(ncu * waves_per_cu, p.n_tiles));
+    hipLaunchKernelGGL(k_batch_nbody, dim3(grid), dim3(64), batch_lds_bytes(p), s, p);
+    return hipGetLastError();
+}
+
+}  // namespace kete

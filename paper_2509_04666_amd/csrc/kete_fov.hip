@@ -13,6 +13,8 @@
 // (frame, sub-frame, object).
 #include <math.h>
 
+#include <algorithm>
+
 #include "kete_fov.hpp"
 
 namespace kete {
@@ -151,9 +153,14 @@ __global__ __launch_bounds__(256) void k_batch_prep(const FovParams p) {
     }
 }
 
-__device__ __forceinline__ int cell_coord(double u, double inv_L, int G) {
-    int i = (int)floor((u + 1.0) * inv_L);
+// Cell of coordinate u in [-1, 1] on a grid of G cells per axis.
+__device__ __forceinline__ int cell_coord(double u, int G) {
+    int i = (int)floor((u + 1.0) * (0.5 * G));
     return i < 0 ? 0 : (i >= G ? G - 1 : i);
+}
+
+__device__ __forceinline__ int cell_of(const double u[3], int G) {
+    return (cell_coord(u[0], G) * G + cell_coord(u[1], G)) * G + cell_coord(u[2], G);
 }
 
 __global__ void k_frame_keys(const FovParams p, int32_t* __restrict__ qkey, int32_t* __restrict__ cnt) {
@@ -167,9 +174,7 @@ __global__ void k_frame_keys(const FovParams p, int32_t* __restrict__ qkey, int3
     }
     const int f = p.frame_order[q];
     const double* c = p.fcap + 8 * f;
-    const int G = p.G;
-    const int cell = (cell_coord(c[0], p.inv_L, G) * G + cell_coord(c[1], p.inv_L, G)) * G + cell_coord(c[2], p.inv_L, G);
-    const int key = lo * G * G * G + cell;
+    const int key = (int)(p.b_koff[lo] + cell_of(c, p.b_G[lo]));
     qkey[q] = key;
     p.frame_batch[f] = lo;
     atomicAdd(cnt + key, 1);
@@ -230,8 +235,8 @@ struct ObjBounds {
 //    acceleration is at most mu / r_min^2 with r_min >= perihelion.
 // Returns false for failed or non-finite objects.
 __device__ __forceinline__ bool object_bounds(const FovParams& p, int b, int64_t j, ObjBounds& o) {
-    if (p.status && p.status[j] != 0) return false;
-    const double* st = p.x_epoch + ((size_t)b * p.n_obj + j) * 6;
+    if (p.status && p.status[p.b_obj0[b] + j] != 0) return false;
+    const double* st = p.x_epoch + p.b_xoff[b] + 6 * j;
     for (int c = 0; c < 3; ++c) { o.x[c] = st[c]; o.v[c] = st[3 + c]; }
     if (!(isfinite(o.x[0]) && isfinite(o.x[1]) && isfinite(o.x[2]) && isfinite(o.v[0]) && isfinite(o.v[1]) &&
           isfinite(o.v[2])))
@@ -282,8 +287,8 @@ __device__ __forceinline__ bool object_bounds(const FovParams& p, int b, int64_t
             const double chord = sqrt(2.0 - 2.0 * cosRT) + 1e-9;
             o.ncell = 1;
             for (int c = 0; c < 3; ++c) {
-                o.lo[c] = cell_coord(o.dh[c] - chord, p.inv_L, p.G);
-                o.hi[c] = cell_coord(o.dh[c] + chord, p.inv_L, p.G);
+                o.lo[c] = cell_coord(o.dh[c] - chord, p.b_G[b]);
+                o.hi[c] = cell_coord(o.dh[c] + chord, p.b_G[b]);
                 o.ncell *= o.hi[c] - o.lo[c] + 1;
             }
             if (o.ncell > p.max_cells) o.overflow = true;
@@ -328,33 +333,43 @@ __device__ __forceinline__ bool frame_may_contain(const FovParams& p, const ObjB
 // Narrow objects: one lane per (object, batch), objects of a batch in sky
 // cell order so that the lanes of a wavefront visit the same cells.
 // Wide objects are handed to k_fov_wide.
+// batch of a flattened (batch, object) index: b_poff[b] <= i < b_poff[b+1]
+__device__ __forceinline__ int batch_of(const int64_t* __restrict__ poff, int n_batch, int64_t i) {
+    int lo = 0, hi = n_batch;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (poff[mid] <= i) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_fov(const FovParams p) {
-    const int b = blockIdx.y;
-    const int64_t pos = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    const int64_t j = (pos < p.n_obj && p.obj_sorted) ? p.obj_sorted[(size_t)b * p.n_obj + pos] : pos;
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const bool in_range = i < p.n_pairs_total;
+    const int b = in_range ? batch_of(p.b_poff, p.n_batch, i) : 0;
+    const int64_t j = in_range ? p.obj_sorted[i] : 0;
     unsigned long long n_cand = 0, n_exact = 0;
     ObjBounds o;
-    const bool live = pos < p.n_obj && object_bounds(p, b, j, o);
+    const bool live = in_range && object_bounds(p, b, j, o);
+    const unsigned long long gobj = (unsigned long long)(p.b_obj0[b] + j);
     if (live && !is_narrow(o)) {
-        wave_append(p.wide, p.n_wide, (int64_t)p.n_batch * p.n_obj,
-                    ((unsigned long long)b << 32) | (unsigned long long)j);
+        wave_append(p.wide, p.n_wide, p.n_pairs_total, ((unsigned long long)b << 32) | (unsigned long long)j);
     } else if (live) {
         const double tr = p.t_ref[b];
         const double Asun = p.btab[kBatchStride * b + 14];
-        const int G = p.G;
-        const int base = b * G * G * G;
+        const int G = p.b_G[b];
+        const int64_t base = p.b_koff[b];
         for (int ix = o.lo[0]; ix <= o.hi[0]; ++ix)
             for (int iy = o.lo[1]; iy <= o.hi[1]; ++iy)
                 for (int iz = o.lo[2]; iz <= o.hi[2]; ++iz) {
-                    const int key = base + (ix * G + iy) * G + iz;
+                    const int64_t key = base + (ix * G + iy) * G + iz;
                     const int a0 = p.cell_start[key], a1 = p.cell_start[key + 1];
                     for (int k = a0; k < a1; ++k) {
                         const int f = p.cell_frames[k];
                         if (frame_may_contain(p, o, f, tr, Asun, n_cand)) {
                             ++n_exact;
-                            wave_append(p.cand, p.n_cand, p.cand_cap,
-                                        ((unsigned long long)f << 32) | (unsigned long long)j);
+                            wave_append(p.cand, p.n_cand, p.cand_cap, ((unsigned long long)f << 32) | gobj);
                         }
                     }
                 }
@@ -378,7 +393,7 @@ __global__ __launch_bounds__(BLOCK) void k_fov(const FovParams p) {
 __global__ __launch_bounds__(256) void k_fov_wide(const FovParams p) {
     const int lane = threadIdx.x & 63;
     const unsigned long long nw = *p.n_wide;
-    const int64_t n_items = (int64_t)(nw < (unsigned long long)p.n_batch * p.n_obj ? nw : p.n_batch * p.n_obj);
+    const int64_t n_items = (int64_t)(nw < (unsigned long long)p.n_pairs_total ? nw : p.n_pairs_total);
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     unsigned long long n_cand = 0, n_exact = 0, n_over = 0;
@@ -388,6 +403,7 @@ __global__ __launch_bounds__(256) void k_fov_wide(const FovParams p) {
         const int64_t j = (int64_t)(w & 0xffffffffull);
         ObjBounds o;
         if (!object_bounds(p, b, j, o)) continue;
+        const unsigned long long gobj = (unsigned long long)(p.b_obj0[b] + j);
         const double tr = p.t_ref[b];
         const double Asun = p.btab[kBatchStride * b + 14];
         if (o.overflow) {
@@ -396,26 +412,25 @@ __global__ __launch_bounds__(256) void k_fov_wide(const FovParams p) {
                 const int f = p.frame_order[q];
                 if (frame_may_contain(p, o, f, tr, Asun, n_cand)) {
                     ++n_exact;
-                    wave_append(p.cand, p.n_cand, p.cand_cap, ((unsigned long long)f << 32) | (unsigned long long)j);
+                    wave_append(p.cand, p.n_cand, p.cand_cap, ((unsigned long long)f << 32) | gobj);
                 }
             }
         } else {
-            const int G = p.G;
+            const int G = p.b_G[b];
             const int nx = o.hi[0] - o.lo[0] + 1, ny = o.hi[1] - o.lo[1] + 1, nz = o.hi[2] - o.lo[2] + 1;
-            const int base = b * G * G * G;
+            const int64_t base = p.b_koff[b];
             for (int c = lane; c < o.ncell; c += 64) {
                 const int ix = o.lo[0] + c / (ny * nz);
                 const int iy = o.lo[1] + (c / nz) % ny;
                 const int iz = o.lo[2] + c % nz;
                 (void)nx;
-                const int key = base + (ix * G + iy) * G + iz;
+                const int64_t key = base + (ix * G + iy) * G + iz;
                 const int a0 = p.cell_start[key], a1 = p.cell_start[key + 1];
                 for (int k = a0; k < a1; ++k) {
                     const int f = p.cell_frames[k];
                     if (frame_may_contain(p, o, f, tr, Asun, n_cand)) {
                         ++n_exact;
-                        wave_append(p.cand, p.n_cand, p.cand_cap,
-                                    ((unsigned long long)f << 32) | (unsigned long long)j);
+                        wave_append(p.cand, p.n_cand, p.cand_cap, ((unsigned long long)f << 32) | gobj);
                     }
                 }
             }
@@ -442,19 +457,14 @@ __global__ __launch_bounds__(256) void k_fov_wide(const FovParams p) {
 // narrow ones of their batch.
 __global__ void k_obj_keys(const FovParams p, int32_t* __restrict__ okey, int32_t* __restrict__ cnt) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (int64_t)p.n_batch * p.n_obj) return;
-    const int b = (int)(i / p.n_obj);
-    const int64_t j = i % p.n_obj;
+    if (i >= p.n_pairs_total) return;
+    const int b = batch_of(p.b_poff, p.n_batch, i);
+    const int64_t j = i - p.b_poff[b];
     ObjBounds o;
-    const int G = p.G, G3 = G * G * G;
+    const int G = p.b_G[b], G3 = G * G * G;
     int key;
-    if (object_bounds(p, b, j, o) && is_narrow(o)) {
-        const int cell = (cell_coord(o.dh[0], p.inv_L, G) * G + cell_coord(o.dh[1], p.inv_L, G)) * G +
-                         cell_coord(o.dh[2], p.inv_L, G);
-        key = b * (G3 + 1) + cell;
-    } else {
-        key = b * (G3 + 1) + G3;
-    }
+    if (object_bounds(p, b, j, o) && is_narrow(o)) key = (int)(p.b_koff[b] + cell_of(o.dh, G));
+    else key = (int)(p.b_koff[b] + G3);
     okey[i] = key;
     atomicAdd(cnt + key, 1);
 }
@@ -462,10 +472,11 @@ __global__ void k_obj_keys(const FovParams p, int32_t* __restrict__ okey, int32_
 __global__ void k_obj_scatter(const FovParams p, const int32_t* __restrict__ okey, const int32_t* __restrict__ start,
                               int32_t* __restrict__ cursor, int32_t* __restrict__ sorted) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (int64_t)p.n_batch * p.n_obj) return;
+    if (i >= p.n_pairs_total) return;
     const int key = okey[i];
-    // positions are global in key order, so batch b occupies [b N, (b+1) N)
-    sorted[start[key] + atomicAdd(cursor + key, 1)] = (int32_t)(i % p.n_obj);
+    const int b = batch_of(p.b_poff, p.n_batch, i);
+    // keys are batch-major, so batch b occupies [b_poff[b], b_poff[b+1])
+    sorted[start[key] + atomicAdd(cursor + key, 1)] = (int32_t)(i - p.b_poff[b]);
 }
 
 // Exact test of every candidate (one lane per candidate, grid-stride).
@@ -478,10 +489,10 @@ __global__ __launch_bounds__(256) void k_fov_exact(const FovParams p) {
          i += (unsigned long long)gridDim.x * blockDim.x) {
         const unsigned long long c = p.cand[i];
         const int f = (int)(c >> 32);
-        const int j = (int)(c & 0xffffffffull);
+        const int j = (int)(c & 0xffffffffull);            // global object
         const int b = p.frame_batch[f];
         const double* bt = p.btab + kBatchStride * b;
-        const double* st = p.x_epoch + ((size_t)b * p.n_obj + j) * 6;
+        const double* st = p.x_epoch + p.b_xoff[b] + 6 * (int64_t)(j - p.b_obj0[b]);
         double r0[3], v0[3];
         for (int k = 0; k < 3; ++k) { r0[k] = st[k] - bt[k]; v0[k] = st[3 + k] - bt[3 + k]; }
         double d[3], tau, ve[3];
@@ -534,6 +545,22 @@ __global__ void k_pair_segsort(unsigned long long* __restrict__ keys, const int3
     }
 }
 
+// ---------------------------------------------------------------- layout
+__global__ void k_single_job_layout(int64_t* b_poff, int32_t* b_obj0, int64_t* b_xoff, int32_t* b_G, int64_t* b_koff,
+                                    int64_t n_batch, int64_t n_obj, int G) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b > n_batch) return;
+    b_poff[b] = b * n_obj;
+    b_koff[b] = b * ((int64_t)G * G * G + 1);
+    if (b < n_batch) { b_obj0[b] = 0; b_xoff[b] = 6 * b * n_obj; b_G[b] = G; }
+}
+
+// Zero fill as a kernel (graph-capturable without memset nodes).
+__global__ void k_fill_zero(unsigned int* __restrict__ p, size_t n_words) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_words; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
 // ---------------------------------------------------------------- checks
 __global__ void k_directions(const FovParams p, const double* __restrict__ x_ref, double t_ref,
                              const double* __restrict__ t_obs, const double* __restrict__ obs, int64_t n_q,
@@ -567,40 +594,56 @@ __global__ void k_ephem_eval(EphemArgs E, const double* __restrict__ t, int64_t 
 
 }  // namespace
 
-hipError_t fov_prepare(const FovParams& p, int32_t* qkey, int32_t* cnt, int32_t* cursor, int64_t n_keys,
-                       void* scan_scratch, hipStream_t s) {
+hipError_t fov_prepare(const FovParams& p, int32_t* qkey, int32_t* cnt, int32_t* cursor, void* scan_scratch,
+                       hipStream_t s) {
+    const int64_t n_keys = p.n_keys;
     const int64_t F = p.n_frames;
     const unsigned gF = (unsigned)((F + 255) / 256);
     hipError_t e;
     if (F > 0) hipLaunchKernelGGL(k_frame_caps, dim3(gF), dim3(256), 0, s, p.normals, F, p.n_sub, p.fcap);
     if (p.n_batch > 0) hipLaunchKernelGGL(k_batch_prep, dim3((unsigned)p.n_batch), dim3(256), 0, s, p);
-    if ((e = hipMemsetAsync(cnt, 0, (size_t)(n_keys + 1) * sizeof(int32_t), s)) != hipSuccess) return e;
+    if ((e = fill_zero(cnt, (size_t)(n_keys + 1) * sizeof(int32_t), s)) != hipSuccess) return e;
     if (F > 0) hipLaunchKernelGGL(k_frame_keys, dim3(gF), dim3(256), 0, s, p, qkey, cnt);
     if ((e = exclusive_scan_i32(cnt, (int32_t*)p.cell_start, n_keys, scan_scratch, s)) != hipSuccess) return e;
-    if ((e = hipMemsetAsync(cursor, 0, (size_t)n_keys * sizeof(int32_t), s)) != hipSuccess) return e;
+    if ((e = fill_zero(cursor, (size_t)n_keys * sizeof(int32_t), s)) != hipSuccess) return e;
     if (F > 0) hipLaunchKernelGGL(k_frame_scatter, dim3(gF), dim3(256), 0, s, p, (const int32_t*)qkey, cursor);
     return hipGetLastError();
 }
 
 hipError_t fov_sort_objects(const FovParams& p, int32_t* okey, int32_t* cnt, int32_t* start, int32_t* sorted,
                             void* scan_scratch, hipStream_t s) {
-    const int64_t n = (int64_t)p.n_batch * p.n_obj;
-    const int64_t nkeys = (int64_t)p.n_batch * ((int64_t)p.G * p.G * p.G + 1);
+    const int64_t n = p.n_pairs_total;
+    const int64_t nkeys = p.n_keys;
     if (n == 0) return hipSuccess;
     hipError_t e;
-    if ((e = hipMemsetAsync(cnt, 0, (size_t)(nkeys + 1) * sizeof(int32_t), s)) != hipSuccess) return e;
+    if ((e = fill_zero(cnt, (size_t)(nkeys + 1) * sizeof(int32_t), s)) != hipSuccess) return e;
     const unsigned g = (unsigned)((n + 255) / 256);
     hipLaunchKernelGGL(k_obj_keys, dim3(g), dim3(256), 0, s, p, okey, cnt);
     if ((e = exclusive_scan_i32(cnt, start, nkeys, scan_scratch, s)) != hipSuccess) return e;
-    if ((e = hipMemsetAsync(cnt, 0, (size_t)nkeys * sizeof(int32_t), s)) != hipSuccess) return e;
+    if ((e = fill_zero(cnt, (size_t)nkeys * sizeof(int32_t), s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_obj_scatter, dim3(g), dim3(256), 0, s, p, (const int32_t*)okey, (const int32_t*)start, cnt,
                        sorted);
     return hipGetLastError();
 }
 
+hipError_t fov_single_job_layout(int64_t* b_poff, int32_t* b_obj0, int64_t* b_xoff, int32_t* b_G, int64_t* b_koff,
+                                 int64_t n_batch, int64_t n_obj, int G, hipStream_t s) {
+    hipLaunchKernelGGL(k_single_job_layout, dim3((unsigned)((n_batch + 1 + 255) / 256)), dim3(256), 0, s, b_poff,
+                       b_obj0, b_xoff, b_G, b_koff, n_batch, n_obj, G);
+    return hipGetLastError();
+}
+
+hipError_t fill_zero(void* p, size_t bytes, hipStream_t s) {
+    if (bytes == 0) return hipSuccess;
+    const size_t words = (bytes + 3) / 4;
+    unsigned g = (unsigned)std::min<size_t>((words + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_fill_zero, dim3(g), dim3(256), 0, s, (unsigned int*)p, words);
+    return hipGetLastError();
+}
+
 hipError_t fov_candidates(const FovParams& p, int block, hipStream_t s) {
-    if (p.n_obj == 0 || p.n_batch == 0) return hipSuccess;
-    dim3 grid((unsigned)((p.n_obj + block - 1) / block), (unsigned)p.n_batch);
+    if (p.n_pairs_total == 0 || p.n_batch == 0) return hipSuccess;
+    dim3 grid((unsigned)((p.n_pairs_total + block - 1) / block));
     switch (block) {
         case 64: hipLaunchKernelGGL(k_fov<64>, grid, dim3(64), 0, s, p); break;
         case 128: hipLaunchKernelGGL(k_fov<128>, grid, dim3(128), 0, s, p); break;
@@ -626,10 +669,10 @@ hipError_t fov_sort(const unsigned long long* keys, int64_t n, int64_t n_frames,
                     unsigned long long* sorted, void* scan_scratch, int32_t* pf, int32_t* ps, int32_t* po,
                     hipStream_t s) {
     hipError_t e;
-    if ((e = hipMemsetAsync(fcnt, 0, (size_t)(n_frames + 1) * sizeof(int32_t), s)) != hipSuccess) return e;
+    if ((e = fill_zero(fcnt, (size_t)(n_frames + 1) * sizeof(int32_t), s)) != hipSuccess) return e;
     if (n > 0) hipLaunchKernelGGL(k_pair_hist, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, keys, n, fcnt);
     if ((e = exclusive_scan_i32(fcnt, fstart, n_frames, scan_scratch, s)) != hipSuccess) return e;
-    if ((e = hipMemsetAsync(fcnt, 0, (size_t)n_frames * sizeof(int32_t), s)) != hipSuccess) return e;
+    if ((e = fill_zero(fcnt, (size_t)n_frames * sizeof(int32_t), s)) != hipSuccess) return e;
     if (n > 0) hipLaunchKernelGGL(k_pair_scatter, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, keys, n,
                                   (const int32_t*)fstart, fcnt, sorted);
     if (n_frames > 0)

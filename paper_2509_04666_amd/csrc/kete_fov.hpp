@@ -22,8 +22,7 @@ struct FovParams {
     const double* fobs;         // [F][3]
     const double* normals;      // [F][S][4][3]
     int32_t n_sub;
-    int32_t G;                  // grid cells per axis
-    double inv_L;               // 1 / cell size
+    int32_t pad0;
     double* fcap;               // [F][8]: centre, cos R, sin R
     double* btab;               // [B][kBatchStride]
     int32_t* cell_start;        // [B G^3 + 1]
@@ -36,8 +35,23 @@ struct FovParams {
     unsigned long long* n_cand;
     int64_t cand_cap;
     int32_t* frame_batch;       // [F] batch of each frame
-    const int32_t* obj_sorted;  // [B][N] objects of each batch ordered by sky cell (or null)
-    unsigned long long* wide;   // [B N] (batch << 32 | obj) of objects with wide motion caps
+    // Batch -> object structure.  Batch b tests the local objects
+    // 0 .. b_poff[b+1]-b_poff[b]-1 of its job; local object j is global
+    // object b_obj0[b] + j with its state at x_epoch + b_xoff[b] + 6 j.
+    // A single job of N objects has b_poff[b] = b N, b_obj0[b] = 0 and
+    // b_xoff[b] = 6 b N.
+    const int64_t* b_poff;      // [B+1]
+    const int32_t* b_obj0;      // [B]
+    const int64_t* b_xoff;      // [B]
+    int64_t n_pairs_total;      // b_poff[B]
+    // Sky grid of batch b: G_b cells per axis over [-1, 1]^3 (G_b = 1 puts
+    // every frame in one cell); its keys start at b_koff[b] and number
+    // G_b^3 + 1 (the last one collects objects with wide motion caps).
+    const int32_t* b_G;         // [B]
+    const int64_t* b_koff;      // [B+1]
+    int64_t n_keys;             // b_koff[B]
+    const int32_t* obj_sorted;  // [n_pairs_total] local objects of each batch ordered by sky cell
+    unsigned long long* wide;   // [n_pairs_total] (batch << 32 | local obj) of objects with wide motion caps
     unsigned long long* n_wide;
     double mu, smu, c_light, lt_tol;
     int32_t lt_iter;
@@ -45,8 +59,8 @@ struct FovParams {
     double sin_overflow;
 };
 
-hipError_t fov_prepare(const FovParams& p, int32_t* qkey, int32_t* cnt, int32_t* cursor, int64_t n_keys,
-                       void* scan_scratch, hipStream_t s);
+hipError_t fov_prepare(const FovParams& p, int32_t* qkey, int32_t* cnt, int32_t* cursor, void* scan_scratch,
+                       hipStream_t s);
 hipError_t fov_sort_objects(const FovParams& p, int32_t* okey, int32_t* cnt, int32_t* start, int32_t* sorted,
                             void* scan_scratch, hipStream_t s);
 hipError_t fov_candidates(const FovParams& p, int block, hipStream_t s);
@@ -57,5 +71,8 @@ hipError_t fov_sort(const unsigned long long* keys, int64_t n, int64_t n_frames,
 hipError_t launch_directions(const FovParams& p, const double* x_ref, double t_ref, const double* t_obs,
                              const double* obs, int64_t n_q, double* d, double* tau, hipStream_t s);
 hipError_t launch_ephem_eval(const EphemArgs& E, const double* t, int64_t n_q, double* out, hipStream_t s);
+hipError_t fov_single_job_layout(int64_t* b_poff, int32_t* b_obj0, int64_t* b_xoff, int32_t* b_G, int64_t* b_koff,
+                                 int64_t n_batch, int64_t n_obj, int G, hipStream_t s);
+hipError_t fill_zero(void* p, size_t bytes, hipStream_t s);
 
 }  // namespace kete

@@ -37,6 +37,50 @@ struct Window {
     int32_t out, pad;
 };
 
+// Segment holding time t (floor rule, clamped to the table).
+__host__ __device__ inline int seg_clamped(double t, double t_start, double inv_seg, int n_seg) {
+    const double k = floor((t - t_start) * inv_seg);
+    return k < 0.0 ? 0 : (k > (double)(n_seg - 1) ? n_seg - 1 : (int)k);
+}
+
+// The next integration window from t toward target: it ends at target or
+// at the segment joint w segment lengths past the start of t's segment,
+// whichever comes first, and reads at most w + 1 consecutive segments
+// (seg_lo..seg_hi), the capacity of the staging buffers.  Every path
+// (host plans and the persistent kernel) uses this rule, so they window
+// identically.  If t sits on a joint that rounding placed in the earlier
+// segment, the limit moves one segment on so the window never has zero
+// length.
+__host__ __device__ inline Window next_window(double t, double target, double t_start, double seg_days,
+                                              double inv_seg, int n_seg, int w) {
+    const bool fwd = target > t;
+    double tb;
+    if (fwd) {
+        const double kk = floor((t - t_start) * inv_seg);
+        double limit = t_start + (kk + w) * seg_days;
+        if (!(limit > t)) limit = t_start + (kk + w + 1) * seg_days;
+        tb = limit < target ? limit : target;
+    } else {
+        const double kk = ceil((t - t_start) * inv_seg) - 1.0;
+        double limit = t_start + (kk - w + 1) * seg_days;
+        if (!(limit < t)) limit = t_start + (kk - w) * seg_days;
+        tb = limit > target ? limit : target;
+    }
+    Window W;
+    W.t_a = t;
+    W.t_b = tb;
+    int lo = seg_clamped(fwd ? t : tb, t_start, inv_seg, n_seg);
+    int hi = seg_clamped(fwd ? tb : t, t_start, inv_seg, n_seg);
+    if (hi - lo > w) {
+        if (fwd) hi = lo + w; else lo = hi - w;
+    }
+    W.seg_lo = lo;
+    W.seg_hi = hi;
+    W.out = -1;
+    W.pad = 0;
+    return W;
+}
+
 struct NbodyParams {
     EphemArgs eph;
     RadauConst rc;

@@ -213,4 +213,69 @@ __device__ __forceinline__ void dense_state(const RadauConst& rc, const double x
     }
 }
 
+// Shared stepping state of one lane.
+struct Lane {
+    double x0[3], v0[3], F0[3];
+    bool active;
+    int status;
+};
+
+// Integrate one window [t, W.t_b] with wave-shared adaptive steps.  The
+// visitor is called after every accepted step with (t_prev, h, D).
+template <class Params, class Visit>
+__device__ __forceinline__ void integrate_window(const Params& p, const Window& W, double* coefL, int bstride,
+                                                 double* ephW, Lane& L, double& t, double& hw, bool& haveF0,
+                                                 long& wsteps, Visit&& visit) {
+    const EphemArgs& E = p.eph;
+    const RadauConst& rc = p.rc;
+    const int lane = threadIdx.x & 63;
+    const double tb = W.t_b;
+    unsigned long long dummy = 0;
+    if (__ballot(L.active) == 0ull) { t = tb; return; }
+    while (t != tb) {
+        const double dir = tb > t ? 1.0 : -1.0;
+        double hmag = hw;
+        if (p.h_max > 0.0 && hmag > p.h_max) hmag = p.h_max;
+        double h = dir * hmag;
+        bool landed = false;
+        if (fabs(h) >= fabs(tb - t)) { h = tb - t; landed = true; }
+        if (wsteps >= p.max_steps) {
+            if (L.active) { L.status = KETE_ST_MAX_STEPS; L.active = false; }
+            t = tb;
+            return;
+        }
+        const double t_end = landed ? tb : t + h;
+        node_ephemeris(coefL, bstride, E, rc, W.seg_lo, W.seg_hi, t, h, t_end, lane, ephW);
+        if (!haveF0) { accel(ephW, E, L.x0, L.v0, L.F0); haveF0 = true; }
+        double D[7][3], b6[3];
+        corrector(rc, E, ephW, L.x0, L.v0, L.F0, h, L.active, p.max_iter, D, b6, dummy);
+        double fm = 0.0, bm = 0.0;
+        for (int c = 0; c < 3; ++c) { fm = fmax(fm, fabs(D[6][c] + L.F0[c])); bm = fmax(bm, fabs(b6[c])); }
+        const double ebl = fm > 0.0 ? bm / fm : 0.0;
+        double hl = (ebl > 0.0 && ebl < kInf) ? fabs(h) * pow(p.eps / ebl, 1.0 / 7.0) : fabs(h) / p.safety;
+        if (!L.active) hl = kInf;
+        if (L.active && hl < p.h_min) { L.status = KETE_ST_STEP_UNDERFLOW; L.active = false; hl = kInf; }
+        const double hn = wave_min(hl);
+        if (!(hn < kInf)) { t = tb; return; }
+        if (hn < p.safety * fabs(h)) { hw = hn; continue; }
+        visit(t, h, D, ephW);
+        const double hh = h * h;
+        for (int c = 0; c < 3; ++c) {
+            double ax = rc.half_s2[8] * L.F0[c], av = L.F0[c];
+            for (int m = 0; m < 7; ++m) { ax = fma(rc.A[8][m], D[m][c], ax); av = fma(rc.B[8][m], D[m][c], av); }
+            L.x0[c] = fma(hh, ax, fma(h, L.v0[c], L.x0[c]));
+            L.v0[c] = fma(h, av, L.v0[c]);
+        }
+        t = t_end;
+        ++wsteps;
+        if (L.active && !(isfinite(L.x0[0]) && isfinite(L.x0[1]) && isfinite(L.x0[2]) && isfinite(L.v0[0]) &&
+                          isfinite(L.v0[1]) && isfinite(L.v0[2]))) {
+            L.status = KETE_ST_NONFINITE; L.active = false;
+        }
+        accel(ephW + 8 * E.n_body * 6, E, L.x0, L.v0, L.F0);
+        hw = landed ? fmin(hw, hn) : fmin(hn, fabs(h) / p.safety);
+    }
+}
+
+
 }  // namespace kete

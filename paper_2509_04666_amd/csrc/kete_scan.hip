@@ -86,7 +86,8 @@ hipError_t exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, void* 
     int32_t* part = (int32_t*)scratch;
     const int64_t np = (n + kTile - 1) / kTile;
     if (n == 0) {
-        return hipMemsetAsync(out, 0, sizeof(int32_t), s);
+        hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(kScanThreads), 0, s, part, (int64_t)0, out);
+        return hipGetLastError();
     }
     hipLaunchKernelGGL(k_tile_sums, dim3((unsigned)np), dim3(kScanThreads), 0, s, in, n, part);
     hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(kScanThreads), 0, s, part, np, out + n);

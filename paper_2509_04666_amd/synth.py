@@ -539,3 +539,39 @@ def batched_job_specs(seed: int = 5, n_jobs: int = 4096, max_obj: int = 20_000,
     return JobSpec(np.maximum(1, np.round(lu(1, max_obj))).astype(np.int64),
                    lu(1.0, max_span),
                    np.maximum(1, np.round(lu(1, max_frames))).astype(np.int64))
+
+
+def batched_jobs(seed: int = 5, n_jobs: int = 4096, max_obj: int = 20_000, max_span: float = 3652.5,
+                 max_frames: int = 5000, neo_frac: float = 0.05, width_deg: float = 1.5,
+                 targeted_frac: float = 0.5, max_t0: float = 16.0):
+    """Independent propagation + field-of-view jobs of uneven size: for
+    each job, log-uniform body count, span and frame count (as in
+    batched_job_specs), a start epoch uniform in [0, max_t0]; bodies drawn
+    as in survey_case (main belt plus NEO-like); frames as in tiny_case
+    over the job's span, a fraction of them aimed at the job's own bodies.
+    Returns (ephemeris covering every job, [(x0 [n, 6], t0, Frames)])."""
+    spec = batched_job_specs(seed, n_jobs, max_obj, max_span, max_frames)
+    rng = np.random.default_rng(seed + 1000)
+    model = PlanetModel.make()
+    t0s = np.round(rng.uniform(0.0, max_t0, n_jobs), 3)
+    end = float((t0s + spec.span).max())
+    eph = make_ephemeris(model, -8.0, int(math.ceil((end + 24.0) / SEG_DAYS)))
+    jobs = []
+    for k in range(n_jobs):
+        n = int(spec.n_obj[k])
+        t0 = float(t0s[k])
+        span = float(spec.span[k])
+        n_neo = int(rng.binomial(n, neo_frac))
+        el = np.concatenate([main_belt_elements(rng, n - n_neo), neo_elements(rng, n_neo)])
+        x0 = bodies_from_elements(model, el, t0)
+        nf = int(spec.n_frames[k])
+        n_tg = int(round(targeted_frac * nf))
+        parts = []
+        if nf - n_tg:
+            parts.append(frames_tiny(rng, model, nf - n_tg, t0, span, width_deg))
+        if n_tg:
+            parts.append(frames_targeted(rng, model, el, t0, span, n_tg, width_deg))
+        fr = Frames.concat(parts) if len(parts) > 1 else parts[0]
+        fr = fr.subset(np.argsort(fr.t, kind="stable"))
+        jobs.append((x0, t0, fr))
+    return eph, jobs

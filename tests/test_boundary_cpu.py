@@ -130,3 +130,46 @@ def test_ephem_eval_range_check():
     t = np.array([e.t_end + 0.5])
     rc = L.kete_ephem_eval(C.byref(et), C.c_void_p(0x1000), t.ctypes.data_as(C.c_void_p), 1, C.c_void_p(0x1000), None)
     assert rc == _lib.KETE_ERANGE
+
+
+def _host_batch(jobs_rows, n_bodies, n_epochs, bjob, bep, boff, n_frames, n_sub=1):
+    jobs = (_lib.JobT * len(jobs_rows))(*[_lib.JobT(*r) for r in jobs_rows])
+    bjob = np.ascontiguousarray(bjob, dtype=np.int32)
+    bep = np.ascontiguousarray(bep, dtype=np.int32)
+    boff = np.ascontiguousarray(boff, dtype=np.int32)
+    fr = _lib.FramesT(n_frames, n_sub, 0, 0x1000, 0x1000, 0x1000)
+    bt = _lib.BatchT(len(jobs_rows), 0, n_bodies, n_epochs, bjob.size, C.addressof(jobs), 0x1000, 0x1000, 0x1000,
+                     bjob.ctypes.data, bep.ctypes.data, boff.ctypes.data, 0x1000, 0x1000, 0x1000, fr)
+    return bt, (jobs, bjob, bep, boff)
+
+
+def test_batch_description_checks():
+    L = _lib.lib()
+    e, et, keep = _host_ephem()
+    o = api.default_opts()
+    # two jobs: 100 bodies over 3 epochs, 5 bodies over 1 epoch; 4 batches over 12 frames
+    rows = [(0, 0, 0, 100, 3, 0.0), (100, 3, 1800, 5, 1, 2.0)]
+    bt, k1 = _host_batch(rows, 105, 4, [0, 0, 0, 1], [0, 1, 2, 0], [0, 3, 6, 9, 12], 12)
+    good = L.kete_batch_workspace_size(C.byref(et), C.byref(bt), 64, C.byref(o))
+    assert good > 0
+    # larger pair capacity -> larger workspace
+    assert L.kete_batch_workspace_size(C.byref(et), C.byref(bt), 1 << 20, C.byref(o)) > good
+    bad_cases = [
+        ([(0, 0, 0, 100, 3, 0.0), (100, 3, 1800, 6, 1, 2.0)], 105, 4, [0, 0, 0, 1], [0, 1, 2, 0]),   # rows past n_bodies
+        ([(0, 0, 0, 100, 3, 0.0), (100, 3, 1800, 5, 2, 2.0)], 105, 4, [0, 0, 0, 1], [0, 1, 2, 0]),   # epochs past n_epochs
+        (rows, 105, 4, [0, 0, 0, 2], [0, 1, 2, 0]),                                                # batch of no job
+        (rows, 105, 4, [0, 0, 0, 1], [0, 1, 3, 0]),                                                # epoch out of range
+        ([(0, 0, 0, 100, 3, e.t_start - 1.0), (100, 3, 1800, 5, 1, 2.0)], 105, 4, [0, 0, 0, 1], [0, 1, 2, 0]),
+    ]
+    for r, nb, ne, bj, be in bad_cases:
+        b2, k2 = _host_batch(r, nb, ne, bj, be, [0, 3, 6, 9, 12], 12)
+        assert L.kete_batch_workspace_size(C.byref(et), C.byref(b2), 64, C.byref(o)) == 0
+        assert L.kete_last_error() != b""
+    # plan/run reject a short workspace before touching the device
+    assert L.kete_batch_plan(C.byref(et), C.byref(bt), 64, C.byref(o), C.c_void_p(0x1000), good - 1,
+                             None) == _lib.KETE_EWORKSPACE
+    assert L.kete_batch_run(C.byref(et), C.byref(bt), 64, C.byref(o), C.c_void_p(0x1000), C.c_void_p(0x1000),
+                            C.c_void_p(0x1000), good - 1, None) == _lib.KETE_EWORKSPACE
+    g = C.c_void_p(0)
+    assert L.kete_batch_graph_launch(None, None) == _lib.KETE_EINVAL
+    assert L.kete_batch_graph_destroy(None) == _lib.KETE_OK
