@@ -95,6 +95,133 @@ def cpu_baseline(case, t_ref, order, off, n_obj_prop=1000, n_obj_fov=600, n_batc
     }
 
 
+def adjoint_component(api, synth, torch, n_obj, log, reps=3):
+    """Forward sky positions and the backward gradient of the summed squared
+    sky residual: 100,000 bodies, 20 observations each over a 60-day arc,
+    checkpoints every 5 days."""
+    t_setup = time.perf_counter()
+    g = synth.gradient_case(n_obj=n_obj, k_obs=20, arc=60.0)
+    dev = torch.device("cuda:0")
+    f = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64).to(dev)
+    eph = api.DeviceEphemeris.from_synth(g.ephem)
+    ctx = api.AdjointContext(eph, g.t0, g.arc, f(g.t_obs), f(g.obs_pos), 5.0, api.default_opts())
+    x0 = f(g.x0)
+    radec = f(g.radec_obs)
+    log(f"adjoint setup {time.perf_counter() - t_setup:.1f} s")
+
+    def fwd():
+        return ctx.forward(x0)
+
+    def bwd(sky):
+        s = sky.detach().requires_grad_(True)
+        loss = api.sky_residual_loss(s, radec)
+        (gs,) = torch.autograd.grad(loss, s)
+        return ctx.backward(x0, gs)
+
+    sky = fwd()
+    bwd(sky)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sky = fwd()
+    torch.cuda.synchronize()
+    t_f = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        grad = bwd(sky)
+    torch.cuda.synchronize()
+    t_b = (time.perf_counter() - t0) / reps
+    n_fail = int((ctx.status != 0).sum().item())
+    return {
+        "workload": f"{n_obj} bodies x 20 observations over 60 days, Sun + 8 planets, checkpoints every 5 days",
+        "forward_ms": t_f * 1e3, "backward_ms": t_b * 1e3, "backward_over_forward": t_b / t_f,
+        "forward_object_days_per_s": n_obj * 60.0 / t_f, "failed_objects": n_fail,
+        "grad_finite": bool(torch.isfinite(grad).all().item()),
+    }
+
+
+def batched_component(api, synth, torch, n_jobs, log, reps=2, tune_cache=None):
+    """Uneven jobs (log-uniform 1-20,000 bodies, 1 day-10 years, 1-5,000
+    frames): the whole set as one captured graph replay against one
+    propagation call and one FoV call per job."""
+    from paper_2509_04666_amd import _lib
+    import ctypes as C
+    t_setup = time.perf_counter()
+    ephem, jobs = synth.batched_jobs(n_jobs=n_jobs)
+    dev = torch.device("cuda:0")
+    eph = api.DeviceEphemeris.from_synth(ephem)
+    runner = api.BatchRunner(eph, jobs)
+    n_bodies = int(runner.obj_off[-1])
+    obj_days = float(sum(x0.shape[0] * np.abs(np.concatenate([[t0], runner.job_epochs[k]]) -
+                                              np.concatenate([runner.job_epochs[k], [t0]]))[:-1].sum()
+                         for k, (x0, t0, fr) in enumerate(jobs)))
+    log(f"batched setup {time.perf_counter() - t_setup:.1f} s: {len(jobs)} jobs, {n_bodies} bodies, "
+        f"{int(runner.frame_off[-1])} frames, {runner.bjob.size} batches")
+    t_tune = time.perf_counter()
+    best, tune_ms, hit = runner.autotune(reps=1, cache=tune_cache,
+                                         progress=lambda o, t: log(f"  tune {o}: {t:.1f} ms"))
+    log(f"autotune {'(cached) ' if hit else ''}{time.perf_counter() - t_tune:.1f} s: {tune_ms:.1f} ms per run")
+    runner.capture()
+    runner.replay()
+    torch.cuda.synchronize()
+    L = _lib.lib()
+    L.kete_timing_enable(1)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        runner.replay()
+    torch.cuda.synchronize()
+    t_graph = (time.perf_counter() - t0) / reps
+    L.kete_timing_enable(0)
+    ms = np.zeros(4); cnt = np.zeros(4, np.int64)
+    _lib.check(L.kete_timing_read(ms.ctypes.data_as(C.c_void_p), cnt.ctypes.data_as(C.c_void_p)))
+    pf, ps, po = runner.pairs()
+    n_pairs_batched = pf.numel()
+
+    # one propagation call and one FoV call per job, inputs already on the device
+    opts = api.default_opts()
+    x0_dev = [runner.x0[runner.obj_off[k]:runner.obj_off[k + 1]] for k in range(len(jobs))]
+    fr_dev, bt_dev, ws_p, ws_f = [], [], 0, 0
+    for k, (x0, t0, fr) in enumerate(jobs):
+        f0, f1 = int(runner.frame_off[k]), int(runner.frame_off[k + 1])
+        fr_dev.append(api.DeviceFrames(runner.frames.t[f0:f1], runner.frames.obs[f0:f1],
+                                       runner.frames.normals[f0:f1]))
+        order, off, t_ref = api.make_batches(fr.t, opts.batch_span)
+        bt_dev.append(api.Batches.from_host(order, off, t_ref, dev))
+        n, nb = x0.shape[0], t_ref.size
+        ws_p = max(ws_p, L.kete_propagate_workspace_size(n, nb, C.byref(opts)))
+        ws_f = max(ws_f, L.kete_fov_workspace_size(n, f1 - f0, nb, fr.n_sub, max(1 << 16, 8 * (f1 - f0)),
+                                                   C.byref(opts)))
+    wp = torch.empty(max(ws_p, 256), dtype=torch.uint8, device=dev)
+    wf = torch.empty(max(ws_f, 256), dtype=torch.uint8, device=dev)
+
+    def per_job():
+        n_pairs = 0
+        for k, (x0, t0, fr) in enumerate(jobs):
+            if x0.shape[0] == 0 or fr.t.size == 0:
+                continue
+            b = bt_dev[k]
+            x, st = api.propagate(eph, x0_dev[k], t0, b.t_ref_host, opts, workspace=wp)
+            pf, ps, po = api.fov_check(eph, x, b, fr_dev[k], st, opts, workspace=wf)
+            n_pairs += pf.numel()
+        return n_pairs
+
+    t0 = time.perf_counter()
+    n_pairs_job = per_job()
+    torch.cuda.synchronize()
+    t_job = time.perf_counter() - t0
+    return {
+        "workload": (f"{len(jobs)} uneven jobs: log-uniform 1-20,000 bodies, 1 day-10 years, 1-5,000 frames; "
+                     f"{n_bodies} bodies, {int(runner.frame_off[-1])} frames"),
+        "object_days": obj_days, "graph_ms": t_graph * 1e3, "per_job_ms": t_job * 1e3,
+        "speedup_vs_per_job": t_job / t_graph, "object_days_per_s": obj_days / t_graph,
+        "graph_launch_event_ms": ms[3] / max(cnt[3], 1),
+        "pairs": n_pairs_batched, "pairs_per_job_path": n_pairs_job,
+        "tuned": {k: getattr(best, k) for k in ("n_buckets", "persist_waves", "window_segs", "fov_block",
+                                                "cell_chord")},
+        "tuning_from_cache": hit,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,6 +230,11 @@ def main():
     ap.add_argument("--objects", type=int, default=100_000)
     ap.add_argument("--frames", type=int, default=500_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--adjoint-objects", type=int, default=100_000)
+    ap.add_argument("--batched-jobs", type=int, default=4096)
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2509_04666_amd", "tuning.json"))
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported (the objects are independent "
@@ -205,6 +337,13 @@ def main():
             "integrator_counters": st[:6].tolist(),
         },
     }
+    if not args.no_adjoint:
+        log("adjoint component ...")
+        out["components"]["adjoint"] = adjoint_component(api, synth, torch, args.adjoint_objects, log)
+    if not args.no_batched:
+        log("batched component ...")
+        out["components"]["batched"] = batched_component(api, synth, torch, args.batched_jobs, log,
+                                                         tune_cache=args.tune_cache)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample ...")
         out["cpu_baseline"] = cpu_baseline(case, t_ref, order, off)

@@ -98,7 +98,7 @@ typedef struct {
     int32_t lt_iter;         /* light-time iterations (10) */
     int32_t fov_block;       /* FoV threads per block: 64/128/256 (128) */
     int32_t adj_seg_steps;   /* adjoint: steps stored per checkpoint segment (32) */
-    int32_t reserved;
+    int32_t persist_waves;   /* batched runs: resident waves per compute unit (8) */
 } kete_opts_t;
 
 /* Frames (Sect. 3.1): an instantaneous observation at time t from the
@@ -147,6 +147,7 @@ typedef struct {
     const kete_job_t *jobs;         /* device [n_jobs] */
     const double *x0;               /* device [n_bodies][6] */
     const double *epochs;           /* device [n_epochs] */
+    const double *epochs_host;      /* host [n_epochs] or NULL (orders the tile queue) */
     const int32_t *batch_job_host;  /* host [n_batch] */
     const int32_t *batch_epoch_host;/* host [n_batch] */
     const int32_t *batch_off_host;  /* host [n_batch + 1] */
@@ -324,6 +325,24 @@ int kete_batch_graph_create(const kete_ephem_t *eph, const kete_batch_t *batch, 
                             void *stream, void **graph);
 int kete_batch_graph_launch(void *graph, void *stream);
 int kete_batch_graph_destroy(void *graph);
+
+/* Autotuner for batched runs: coordinate descent, starting from `base`
+ * (NULL = defaults), over n_buckets {1,4,8,16}, persist_waves {2,4,8,12},
+ * window_segs {1,2,4}, fov_block {64,128,256} and cell_chord
+ * {0.04,0.08,0.16}, in that order; each candidate is planned, run once to
+ * warm up and timed with HIP events over `reps` (1..100) runs of
+ * kete_batch_run on `stream`.  Candidates whose workspace exceeds
+ * ws_bytes are skipped.  progress (may be NULL) is called with user after
+ * every timed candidate.  Every candidate computes the same states and
+ * pairs (they change launch shapes and groupings only).  On return *best
+ * holds the fastest options, *best_ms (if not NULL) its time per run, and
+ * the workspace is planned for *best.  Synchronizes `stream`; x_out and
+ * status are overwritten. */
+typedef void (*kete_tune_progress_fn)(const kete_opts_t *tried, double ms, void *user);
+int kete_batch_autotune(const kete_ephem_t *eph, const kete_batch_t *batch, int64_t pairs_cap,
+                        const kete_opts_t *base, int32_t reps, double *x_out, int32_t *status, void *workspace,
+                        size_t ws_bytes, void *stream, kete_tune_progress_fn progress, void *user,
+                        kete_opts_t *best, double *best_ms);
 
 /* Live kernel timing for measurement.  While enabled, every integrator
  * and FoV-candidate launch made by the calling thread is bracketed by HIP

@@ -39,7 +39,7 @@ class OptsT(C.Structure):
                 ("lt_tol", C.c_double), ("max_steps", C.c_int32), ("max_iter", C.c_int32),
                 ("n_buckets", C.c_int32), ("block", C.c_int32), ("rebucket_epochs", C.c_int32),
                 ("window_segs", C.c_int32), ("lt_iter", C.c_int32), ("fov_block", C.c_int32),
-                ("adj_seg_steps", C.c_int32), ("reserved", C.c_int32)]
+                ("adj_seg_steps", C.c_int32), ("persist_waves", C.c_int32)]
 
 
 class FramesT(C.Structure):
@@ -55,10 +55,12 @@ class JobT(C.Structure):
 class BatchT(C.Structure):
     _fields_ = [("n_jobs", C.c_int32), ("reserved", C.c_int32), ("n_bodies", C.c_int64), ("n_epochs", C.c_int64),
                 ("n_batch", C.c_int64), ("jobs_host", C.c_void_p), ("jobs", C.c_void_p), ("x0", C.c_void_p),
-                ("epochs", C.c_void_p), ("batch_job_host", C.c_void_p), ("batch_epoch_host", C.c_void_p),
+                ("epochs", C.c_void_p), ("epochs_host", C.c_void_p), ("batch_job_host", C.c_void_p), ("batch_epoch_host", C.c_void_p),
                 ("batch_off_host", C.c_void_p), ("t_ref", C.c_void_p), ("batch_off", C.c_void_p),
                 ("frame_order", C.c_void_p), ("frames", FramesT)]
 
+
+TUNE_PROGRESS = C.CFUNCTYPE(None, C.POINTER(OptsT), C.c_double, C.c_void_p)
 
 # name -> (restype, argtypes)
 SIGNATURES = {
@@ -99,6 +101,9 @@ SIGNATURES = {
                                           C.POINTER(C.c_void_p)]),
     "kete_batch_graph_launch": (C.c_int, [C.c_void_p, C.c_void_p]),
     "kete_batch_graph_destroy": (C.c_int, [C.c_void_p]),
+    "kete_batch_autotune": (C.c_int, [C.POINTER(EphemT), C.POINTER(BatchT), C.c_int64, C.POINTER(OptsT), C.c_int32,
+                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, TUNE_PROGRESS,
+                                      C.c_void_p, C.POINTER(OptsT), C.POINTER(C.c_double)]),
     "kete_timing_enable": (None, [C.c_int]),
     "kete_timing_read": (C.c_int, [C.c_void_p, C.c_void_p]),
 }

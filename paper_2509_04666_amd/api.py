@@ -2,9 +2,13 @@
 streams; every step of the path runs in the library's HIP kernels."""
 from __future__ import annotations
 
+import copy
 import ctypes as C
 import dataclasses
+import hashlib
+import json
 import math
+import os
 from typing import Optional, Sequence
 
 import numpy as np
@@ -302,7 +306,8 @@ class BatchRunner:
         f = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a, dtype=dt)).to(device)
         self.jobs_dev = torch.as_tensor(jb).to(device)
         self.x0 = f(np.concatenate([j[0] for j in jobs]), np.float64)
-        self.epochs = f(np.concatenate(epochs), np.float64)
+        self.epochs_host = np.ascontiguousarray(np.concatenate(epochs), dtype=np.float64)
+        self.epochs = f(self.epochs_host, np.float64)
         self.bjob = np.ascontiguousarray(bjob, dtype=np.int32)
         self.bep = np.ascontiguousarray(bep, dtype=np.int32)
         self.boff_host = np.ascontiguousarray(offs, dtype=np.int32)
@@ -314,23 +319,96 @@ class BatchRunner:
         self.fc = self.frames.c()
         self.c = _lib.BatchT(len(jobs), 0, int(self.obj_off[-1]), int(ep_off), int(self.bjob.size),
                              C.addressof(self.jobs_host), self.jobs_dev.data_ptr(), self.x0.data_ptr(),
-                             self.epochs.data_ptr(), self.bjob.ctypes.data, self.bep.ctypes.data,
+                             self.epochs.data_ptr(), self.epochs_host.ctypes.data, self.bjob.ctypes.data,
+                             self.bep.ctypes.data,
                              self.boff_host.ctypes.data, self.t_ref.data_ptr(), self.boff.data_ptr(),
                              self.order.data_ptr(), self.fc)
         F = int(self.frame_off[-1])
         self.pairs_cap = int(pairs_cap) if pairs_cap is not None else max(1 << 16, 8 * F)
-        need = lib().kete_batch_workspace_size(C.byref(eph.c), C.byref(self.c), self.pairs_cap, C.byref(self.opts))
-        if need == 0:
-            raise _lib.KeteError(_lib.KETE_EINVAL, lib().kete_last_error().decode())
-        self.workspace = _workspace(need, device)
+        self.device = device
         self.x_out = torch.empty(max(self.n_x, 1), dtype=torch.float64, device=device)
         self.status = torch.zeros(max(int(self.obj_off[-1]), 1), dtype=torch.int32, device=device)
         self.pf = torch.empty(self.pairs_cap, dtype=torch.int32, device=device)
         self.ps = torch.empty_like(self.pf)
         self.po = torch.empty_like(self.pf)
-        check(lib().kete_batch_plan(C.byref(eph.c), C.byref(self.c), self.pairs_cap, C.byref(self.opts),
-                                    _ptr(self.workspace), self.workspace.numel(), _stream()))
+        self.workspace = None
         self.graph = None
+        self.set_opts(self.opts)
+
+    def _ws_size(self, opts) -> int:
+        need = lib().kete_batch_workspace_size(C.byref(self.eph.c), C.byref(self.c), self.pairs_cap, C.byref(opts))
+        if need == 0:
+            raise _lib.KeteError(_lib.KETE_EINVAL, lib().kete_last_error().decode())
+        return need
+
+    def set_opts(self, opts: OptsT, workspace_bytes: int = 0):
+        """Adopt `opts`: (re)allocate the workspace if it is too small and plan."""
+        self.drop_graph()
+        self.opts = opts
+        need = max(self._ws_size(opts), int(workspace_bytes))
+        if self.workspace is None or self.workspace.numel() < need:
+            self.workspace = None
+            self.workspace = _workspace(need, self.device)
+        check(lib().kete_batch_plan(C.byref(self.eph.c), C.byref(self.c), self.pairs_cap, C.byref(opts),
+                                    _ptr(self.workspace), self.workspace.numel(), _stream()))
+
+    def signature(self) -> str:
+        """Hash of the batch description (jobs, epochs and batch tables)."""
+        h = hashlib.sha1()
+        for a in (np.frombuffer(self.jobs_host, dtype=np.uint8), self.epochs_host, self.bjob, self.bep,
+                  self.boff_host):
+            h.update(np.ascontiguousarray(a).tobytes())
+        h.update(np.int64([self.pairs_cap, self.fc.n_sub]).tobytes())
+        return h.hexdigest()
+
+    def autotune(self, reps: int = 1, cache: Optional[str] = None, progress=None):
+        """Pick launch parameters with the library's autotuner.  With `cache`
+        (a JSON file), a result stored under this device and batch is reused
+        and a new one is stored.  Returns (opts, ms per run, from_cache)."""
+        props = torch.cuda.get_device_properties(self.device)
+        key = f"{getattr(props, 'gcnArchName', props.name)}|cu{props.multi_processor_count}|{self.signature()}"
+        tuned = ("n_buckets", "persist_waves", "window_segs", "fov_block", "cell_chord")
+        if cache and os.path.exists(cache):
+            with open(cache) as fh:
+                entry = json.load(fh).get(key)
+            if entry:
+                o = copy.copy(self.opts)
+                for k in tuned:
+                    setattr(o, k, entry[k])
+                self.set_opts(o)
+                return o, float(entry["ms"]), True
+        # room for the largest candidate grid (smaller sky cells need more keys)
+        probe = copy.copy(self.opts)
+        probe.cell_chord = 0.04
+        self.set_opts(self.opts, max(self._ws_size(probe), self._ws_size(self.opts)))
+        best = OptsT()
+        ms = C.c_double(0.0)
+
+        def report(o, t, _user):
+            if progress is not None:
+                progress({k: getattr(o.contents, k) for k in tuned}, t)
+
+        cb = _lib.TUNE_PROGRESS(report)
+        check(lib().kete_batch_autotune(C.byref(self.eph.c), C.byref(self.c), self.pairs_cap, C.byref(self.opts),
+                                        int(reps), _ptr(self.x_out), _ptr(self.status), _ptr(self.workspace),
+                                        self.workspace.numel(), _stream(), cb, None, C.byref(best), C.byref(ms)))
+        self.opts = best
+        if cache:
+            data = {}
+            if os.path.exists(cache):
+                with open(cache) as fh:
+                    data = json.load(fh)
+            data[key] = {k: getattr(best, k) for k in tuned}
+            data[key]["ms"] = ms.value
+            os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
+            with open(cache, "w") as fh:
+                json.dump(data, fh, indent=1, sort_keys=True)
+        return best, ms.value, False
+
+    def drop_graph(self):
+        if getattr(self, "graph", None) is not None:
+            lib().kete_batch_graph_destroy(self.graph)
+            self.graph = None
 
     def run(self):
         check(lib().kete_batch_run(C.byref(self.eph.c), C.byref(self.c), self.pairs_cap, C.byref(self.opts),
@@ -338,6 +416,7 @@ class BatchRunner:
                                    self.workspace.numel(), _stream()))
 
     def capture(self):
+        self.drop_graph()
         g = C.c_void_p(0)
         check(lib().kete_batch_graph_create(C.byref(self.eph.c), C.byref(self.c), self.pairs_cap,
                                             C.byref(self.opts), _ptr(self.x_out), _ptr(self.status),
@@ -361,7 +440,6 @@ class BatchRunner:
 
     def __del__(self):
         try:
-            if self.graph is not None:
-                lib().kete_batch_graph_destroy(self.graph)
+            self.drop_graph()
         except Exception:
             pass

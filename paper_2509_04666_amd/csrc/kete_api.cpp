@@ -288,6 +288,7 @@ void kete_default_opts(kete_opts_t* o) {
     o->block = 256;
     o->rebucket_epochs = 16;
     o->window_segs = 2;
+    o->persist_waves = 8;
     o->lt_iter = 10;
     o->fov_block = 128;
     o->adj_seg_steps = 32;
@@ -807,15 +808,9 @@ int batch_dims(const kete_ephem_t* eph, const kete_batch_t* bt, int64_t pairs_ca
             return fail(KETE_EINVAL, "job %d out of range", j);
         if (!(J[j].t0 >= tlo && J[j].t0 <= thi)) return fail(KETE_ERANGE, "job %d t0 outside the ephemeris", j);
     }
-    // tiles, longest (span + landings) first
-    std::vector<std::pair<double, int64_t>> cost;
-    for (int j = 0; j < bt->n_jobs; ++j) {
-        const int nt = (J[j].n_obj + 63) / 64;
-        d.n_tiles += nt;
-    }
+    // tiles of 64 bodies
+    for (int j = 0; j < bt->n_jobs; ++j) d.n_tiles += (J[j].n_obj + 63) / 64;
     if (tables) {
-        std::vector<double> span(bt->n_jobs, 0.0);
-        (void)span;
         d.tiles.reserve(d.n_tiles);
         for (int j = 0; j < bt->n_jobs; ++j)
             for (int t = 0; t < (J[j].n_obj + 63) / 64; ++t) d.tiles.push_back(make_int2(j, t));
@@ -851,12 +846,21 @@ int batch_dims(const kete_ephem_t* eph, const kete_batch_t* bt, int64_t pairs_ca
     d.NP = np;
     d.nkeys = nk;
     d.cand_cap = cand_capacity(d.F, pairs_cap);
-    // longest first: cost ~ span of the job plus a landing per epoch
+    // Longest first: a tile's cost is about the integrated path length of
+    // its job (days from t0 through every epoch in order) plus a couple of
+    // steps per landing; without host epochs the landing count alone.
     if (tables && !d.tiles.empty()) {
         std::vector<double> c(bt->n_jobs);
-        const double* ep = nullptr;
-        (void)ep;
-        for (int j = 0; j < bt->n_jobs; ++j) c[j] = (double)J[j].n_epoch;
+        for (int j = 0; j < bt->n_jobs; ++j) {
+            double len = 0.0, t = J[j].t0;
+            if (bt->epochs_host)
+                for (int e = 0; e < J[j].n_epoch; ++e) {
+                    const double te = bt->epochs_host[J[j].epoch_off + e];
+                    len += std::fabs(te - t);
+                    t = te;
+                }
+            c[j] = len + 8.0 * J[j].n_epoch;
+        }
         std::stable_sort(d.tiles.begin(), d.tiles.end(),
                          [&](const int2& a, const int2& b) { return c[a.x] > c[b.x]; });
     }
@@ -993,7 +997,7 @@ int kete_batch_run(const kete_ephem_t* eph, const kete_batch_t* batch, int64_t p
     B.safety = 0.25;
     {
         TimedScope ts(kTimeBatch, s);
-        HIPCHK(launch_batch(B, 8, s));
+        HIPCHK(launch_batch(B, opts->persist_waves > 0 ? std::min(opts->persist_waves, 32) : 8, s));
     }
     // field-of-view stages over every batch
     FovParams& P = w.P;
@@ -1119,6 +1123,86 @@ int kete_batch_graph_destroy(void* graph) {
     hipGraphExecDestroy(bg->exec);
     hipGraphDestroy(bg->graph);
     delete bg;
+    return KETE_OK;
+}
+
+// Coordinate descent over the launch parameters of a batched run, each
+// candidate timed with events over `reps` runs after one warm-up run.
+int kete_batch_autotune(const kete_ephem_t* eph, const kete_batch_t* batch, int64_t pairs_cap,
+                        const kete_opts_t* base, int32_t reps, double* x_out, int32_t* status, void* workspace,
+                        size_t ws_bytes, void* stream, kete_tune_progress_fn progress, void* user,
+                        kete_opts_t* best, double* best_ms) {
+    g_err.clear();
+    if (!best) return fail(KETE_EINVAL, "best is null");
+    if (reps < 1 || reps > 100) return fail(KETE_EINVAL, "reps outside 1..100");
+    kete_opts_t cur;
+    if (base) cur = *base; else kete_default_opts(&cur);
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t ea = nullptr, eb = nullptr;
+    HIPCHK(hipEventCreate(&ea));
+    if (hipEventCreate(&eb) != hipSuccess) { hipEventDestroy(ea); return fail(KETE_EDEVICE, "event create"); }
+    auto trial = [&](const kete_opts_t& o, double& ms) -> int {
+        ms = HUGE_VAL;
+        const size_t need = kete_batch_workspace_size(eph, batch, pairs_cap, &o);
+        if (need == 0) return KETE_EINVAL;
+        if (need > ws_bytes) return KETE_OK;          // candidate does not fit: skipped
+        int rc = kete_batch_plan(eph, batch, pairs_cap, &o, workspace, ws_bytes, stream);
+        if (!rc) rc = kete_batch_run(eph, batch, pairs_cap, &o, x_out, status, workspace, ws_bytes, stream);
+        if (rc) return rc;
+        if (hipEventRecord(ea, s) != hipSuccess) return fail(KETE_EDEVICE, "event record");
+        for (int r = 0; r < reps && !rc; ++r)
+            rc = kete_batch_run(eph, batch, pairs_cap, &o, x_out, status, workspace, ws_bytes, stream);
+        if (rc) return rc;
+        float t = 0.0f;
+        if (hipEventRecord(eb, s) != hipSuccess || hipEventSynchronize(eb) != hipSuccess ||
+            hipEventElapsedTime(&t, ea, eb) != hipSuccess)
+            return fail(KETE_EDEVICE, "event timing");
+        ms = (double)t / reps;
+        if (progress) progress(&o, ms, user);
+        return KETE_OK;
+    };
+    double cur_ms;
+    int rc = trial(cur, cur_ms);
+    if (!rc && !(cur_ms < HUGE_VAL)) rc = fail(KETE_EWORKSPACE, "workspace too small for the base options");
+    struct Axis { int which; double v[5]; int n; };
+    const Axis axes[] = {
+        {0, {1, 4, 8, 16}, 4},             // n_buckets
+        {1, {2, 4, 8, 12}, 4},             // persist_waves
+        {2, {1, 2, 4}, 3},                 // window_segs
+        {3, {64, 128, 256}, 3},            // fov_block
+        {4, {0.04, 0.08, 0.16}, 3},        // cell_chord
+    };
+    auto with = [](kete_opts_t o, int which, double v) {
+        switch (which) {
+            case 0: o.n_buckets = (int32_t)v; break;
+            case 1: o.persist_waves = (int32_t)v; break;
+            case 2: o.window_segs = (int32_t)v; break;
+            case 3: o.fov_block = (int32_t)v; break;
+            default: o.cell_chord = v; break;
+        }
+        return o;
+    };
+    for (const Axis& a : axes) {
+        if (rc) break;
+        kete_opts_t axis_best = cur;
+        double axis_ms = cur_ms;
+        for (int i = 0; i < a.n && !rc; ++i) {
+            const kete_opts_t o = with(cur, a.which, a.v[i]);
+            if (std::memcmp(&o, &cur, sizeof(o)) == 0) continue;
+            double ms;
+            rc = trial(o, ms);
+            if (!rc && ms < axis_ms) { axis_ms = ms; axis_best = o; }
+        }
+        cur = axis_best;
+        cur_ms = axis_ms;
+    }
+    hipEventDestroy(ea);
+    hipEventDestroy(eb);
+    if (rc) return rc;
+    // leave the workspace planned for the winner
+    if ((rc = kete_batch_plan(eph, batch, pairs_cap, &cur, workspace, ws_bytes, stream))) return rc;
+    *best = cur;
+    if (best_ms) *best_ms = cur_ms;
     return KETE_OK;
 }
 

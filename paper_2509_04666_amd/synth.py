@@ -66,13 +66,15 @@ CHEB_DEGREE = 12
 def _solve_kepler_E(M: np.ndarray, e: np.ndarray) -> np.ndarray:
     M = np.mod(M, 2.0 * np.pi)
     E = np.where(e < 0.8, M, np.pi * np.ones_like(M))
+    small = False
     for _ in range(60):
         f = E - e * np.sin(E) - M
         fp = 1.0 - e * np.cos(E)
         dE = f / fp
         E = E - dE
-        if np.max(np.abs(dE)) < 1e-15:
+        if small:            # one Newton step past |dE| < 1e-12 reaches round-off
             break
+        small = E.size == 0 or np.max(np.abs(dE)) < 1e-12
     return E
 
 

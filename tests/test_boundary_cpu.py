@@ -139,7 +139,7 @@ def _host_batch(jobs_rows, n_bodies, n_epochs, bjob, bep, boff, n_frames, n_sub=
     boff = np.ascontiguousarray(boff, dtype=np.int32)
     fr = _lib.FramesT(n_frames, n_sub, 0, 0x1000, 0x1000, 0x1000)
     bt = _lib.BatchT(len(jobs_rows), 0, n_bodies, n_epochs, bjob.size, C.addressof(jobs), 0x1000, 0x1000, 0x1000,
-                     bjob.ctypes.data, bep.ctypes.data, boff.ctypes.data, 0x1000, 0x1000, 0x1000, fr)
+                     None, bjob.ctypes.data, bep.ctypes.data, boff.ctypes.data, 0x1000, 0x1000, 0x1000, fr)
     return bt, (jobs, bjob, bep, boff)
 
 
@@ -170,6 +170,8 @@ def test_batch_description_checks():
                              None) == _lib.KETE_EWORKSPACE
     assert L.kete_batch_run(C.byref(et), C.byref(bt), 64, C.byref(o), C.c_void_p(0x1000), C.c_void_p(0x1000),
                             C.c_void_p(0x1000), good - 1, None) == _lib.KETE_EWORKSPACE
-    g = C.c_void_p(0)
+    best = _lib.OptsT()
+    assert L.kete_batch_autotune(C.byref(et), C.byref(bt), 64, C.byref(o), 0, None, None, None, 0, None,
+                                 _lib.TUNE_PROGRESS(), None, C.byref(best), None) == _lib.KETE_EINVAL
     assert L.kete_batch_graph_launch(None, None) == _lib.KETE_EINVAL
     assert L.kete_batch_graph_destroy(None) == _lib.KETE_OK

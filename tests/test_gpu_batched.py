@@ -197,3 +197,24 @@ def test_batched_configurations_agree(torch_cuda, batched):
         assert d < 1e-11
         assert torch.equal(r.status, status)
         assert same
+
+
+def test_batched_autotune_and_cache(torch_cuda, batched, tmp_path):
+    torch, api = torch_cuda
+    ephem, jobs, eph, runner, x_out, status, pairs = batched
+    r = api.BatchRunner(eph, jobs)
+    cache = str(tmp_path / "tune.json")
+    best, ms, hit = r.autotune(reps=1, cache=cache)
+    assert not hit and ms > 0
+    _say(f"autotune: n_buckets {best.n_buckets}, persist_waves {best.persist_waves}, window_segs {best.window_segs}, "
+         f"fov_block {best.fov_block}, cell_chord {best.cell_chord}: {ms:.3f} ms per run")
+    r.run()
+    torch.cuda.synchronize()
+    pf, ps, po = r.pairs()
+    assert all(np.array_equal(g.cpu().numpy(), p) for g, p in zip((pf, ps, po), pairs))
+    assert (r.x_out - x_out)[torch.isfinite(x_out)].abs().max().item() < 1e-11
+    r2 = api.BatchRunner(eph, jobs)
+    best2, ms2, hit2 = r2.autotune(cache=cache)
+    assert hit2 and ms2 == ms
+    for k in ("n_buckets", "persist_waves", "window_segs", "fov_block", "cell_chord"):
+        assert getattr(best2, k) == getattr(best, k)
