@@ -285,10 +285,11 @@ void kete_default_opts(kete_opts_t* o) {
     o->max_steps = 2000000;
     o->max_iter = 12;
     o->n_buckets = 8;
-    o->block = 256;
+    o->block = 64;
     o->rebucket_epochs = 16;
     o->window_segs = 2;
     o->persist_waves = 8;
+    o->lanes_per_body = 8;
     o->lt_iter = 10;
     o->fov_block = 128;
     o->adj_seg_steps = 32;
@@ -371,6 +372,8 @@ int kete_propagate_nbody(const kete_ephem_t* eph, const double* x0, double t0, i
     }
     if (opts->block != 64 && opts->block != 128 && opts->block != 256)
         return fail(KETE_EINVAL, "block must be 64, 128 or 256");
+    if (opts->lanes_per_body != 1 && opts->lanes_per_body != 8)
+        return fail(KETE_EINVAL, "lanes_per_body must be 1 or 8");
     if (!(opts->eps > 0) || !(opts->h_init > 0) || !(opts->h_min > 0) || opts->max_iter < 1 || opts->max_steps < 1)
         return fail(KETE_EINVAL, "eps, h_init, h_min, max_iter and max_steps must be positive");
     const int nbk = std::min(std::max(1, opts->n_buckets), 32);
@@ -441,7 +444,7 @@ int kete_propagate_nbody(const kete_ephem_t* eph, const double* x0, double t0, i
         P.first_launch = (e0 == 0);
         {
             TimedScope ts(kTimeNbody, s);
-            HIPCHK(launch_nbody(P, opts->block, s));
+            HIPCHK(launch_nbody(P, opts->block, opts->lanes_per_body, s));
         }
         first = last + 1;
     }

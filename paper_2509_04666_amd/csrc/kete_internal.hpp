@@ -102,7 +102,8 @@ struct NbodyParams {
 
 const RadauConst& radau_const();
 
-hipError_t launch_nbody(const NbodyParams& p, int block, hipStream_t s);
+// lanes_per_body: 1 (one lane per object) or 8 (an 8-lane group per object).
+hipError_t launch_nbody(const NbodyParams& p, int block, int lanes_per_body, hipStream_t s);
 
 // Stable counting sort of objects into step-size buckets.
 struct BucketParams {

@@ -151,6 +151,136 @@ __global__ __launch_bounds__(BLOCK) void k_nbody(const NbodyParams p) {
     }
 }
 
+// Eight lanes per object: a wavefront integrates 8 objects, each spread
+// over an 8-lane group whose lanes own one collocation node each.  The
+// 8 objects of a wavefront share the time grid and the perturber table
+// as above; each sweep evaluates the force at all 7 nodes of an object
+// at once.  Output and counters are per object, as in k_nbody.
+template <int BLOCK, int NB>
+__global__ __launch_bounds__(BLOCK) void k_nbody_g8(const NbodyParams p) {
+    extern __shared__ double smem[];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+    const int gl = lane & (kGroup - 1);               // lane within the object's group
+    const int node = gl < 7 ? gl + 1 : 7;
+    const EphemArgs& E = p.eph;
+    const RadauConst& rc = p.rc;
+    const int nb = E.n_body, deg1 = E.deg1;
+    const int cps = 3 * deg1;
+    const int bstride = p.max_win_segs * cps;
+    double* coefL = smem;
+    double* ephW = smem + (size_t)nb * bstride + (size_t)wid * kNodes * nb * 6;
+    NodeRow R;
+    load_node_row(rc, node, R);
+
+    const long gi = ((long)blockIdx.x * BLOCK + tid) / kGroup;
+    const bool valid = gi < p.n_obj;
+    const int j = valid ? (p.perm ? p.perm[gi] : (int)gi) : 0;
+    bool active = valid && p.status[j] == 0;
+    int my_status = valid ? p.status[j] : 0;
+
+    double x0[3] = {1.0, 0.0, 0.0}, v0[3] = {0.0, 0.0, 0.0};
+    double hin = kInf;
+    if (valid) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) { x0[i] = p.state[6 * j + i]; v0[i] = p.state[6 * j + 3 + i]; }
+        hin = p.h_pref[j];
+    }
+    double hw = wave_min(active ? hin : kInf);
+    if (!(hw < kInf)) hw = p.h_init;
+    double hp_new = kInf;
+
+    unsigned long long c_steps = 0, c_iter = 0, c_rej = 0, c_lsteps = 0, c_liter = 0, c_chain = 0;
+    double t = p.win[0].t_a;
+    double F0[3] = {0.0, 0.0, 0.0};
+    bool haveF0 = false;
+
+    for (int w = 0; w < p.n_win; ++w) {
+        const Window W = p.win[w];
+        __syncthreads();
+        stage_window(E, W.seg_lo, W.seg_hi, bstride, tid, BLOCK, coefL);
+        __syncthreads();
+        const double tb = W.t_b;
+        if (__ballot(active) == 0ull) t = tb;
+        while (t != tb) {
+            const double dir = tb > t ? 1.0 : -1.0;
+            double hmag = hw;
+            if (p.h_max > 0.0 && hmag > p.h_max) hmag = p.h_max;
+            double h = dir * hmag;
+            bool landed = false;
+            if (fabs(h) >= fabs(tb - t)) { h = tb - t; landed = true; }
+            if ((long)c_steps >= p.max_steps) {
+                if (active) { my_status = KETE_ST_MAX_STEPS; active = false; }
+                t = tb;
+                break;
+            }
+            const double t_end = landed ? tb : t + h;
+            const double hh = h * h;
+            node_ephemeris(coefL, bstride, E, rc, W.seg_lo, W.seg_hi, t, h, t_end, lane, ephW);
+            c_chain += kNodes * nb * 3;
+            if (!haveF0) { accel_n<NB>(ephW, E, x0, v0, F0); haveF0 = true; }
+
+            double dn[3], b6p[3], d6[3];
+            const int it = corrector_g8<NB>(rc, E, ephW, R, node, x0, v0, F0, h, active, p.max_iter, dn, b6p, d6);
+            c_iter += it;
+            const unsigned long long n_act = __popcll(__ballot(active)) / kGroup;
+            c_liter += (unsigned long long)it * n_act;
+
+            double fm = 0.0, bm = 0.0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) { fm = fmax(fm, fabs(d6[c] + F0[c])); bm = fmax(bm, fabs(b6p[c])); }
+            const double ebl = fm > 0.0 ? bm / fm : 0.0;
+            double hl = (ebl > 0.0 && ebl < kInf) ? fabs(h) * pow(p.eps / ebl, 1.0 / 7.0) : fabs(h) / p.safety;
+            if (!active) hl = kInf;
+            if (active && hl < p.h_min) { my_status = KETE_ST_STEP_UNDERFLOW; active = false; hl = kInf; }
+            const double hn = wave_min(hl);
+            if (!(hn < kInf)) { t = tb; break; }
+            if (hn < p.safety * fabs(h)) {
+                hw = hn;
+                ++c_rej;
+                continue;
+            }
+            step_end_g8(rc, dn, h, x0, v0, F0);
+            t = t_end;
+            ++c_steps;
+            c_lsteps += n_act;
+            if (active && !(isfinite(x0[0]) && isfinite(x0[1]) && isfinite(x0[2]) &&
+                            isfinite(v0[0]) && isfinite(v0[1]) && isfinite(v0[2]))) {
+                my_status = KETE_ST_NONFINITE; active = false;
+            }
+            accel_n<NB>(ephW + 8 * nb * 6, E, x0, v0, F0);
+            if (landed) {
+                hw = fmin(hw, hn);
+            } else {
+                hw = fmin(hn, fabs(h) / p.safety);
+                hp_new = fmin(hp_new, fmin(hl, fabs(h) / p.safety));
+            }
+        }
+        if (W.out >= 0 && valid && gl < 6) {
+            // lane gl of the group writes component gl of the state
+            double* dst = p.x_out + ((size_t)W.out * p.n_obj + j) * 6;
+            const bool ok = active && my_status == 0;
+            double v = gl == 0 ? x0[0] : gl == 1 ? x0[1] : gl == 2 ? x0[2] : gl == 3 ? v0[0] : gl == 4 ? v0[1] : v0[2];
+            dst[gl] = ok ? v : __builtin_nan("");
+        }
+    }
+    if (valid && gl < 6) {
+        const double v = gl == 0 ? x0[0] : gl == 1 ? x0[1] : gl == 2 ? x0[2] : gl == 3 ? v0[0] : gl == 4 ? v0[1] : v0[2];
+        p.state[6 * j + gl] = v;
+    }
+    if (valid && gl == 0) {
+        if (hp_new < kInf) p.h_pref[j] = hp_new;
+        p.status[j] = my_status;
+    }
+    if (p.stats && lane == 0 && __ballot(valid) != 0ull) {
+        atomicAdd(p.stats + 0, c_steps);
+        atomicAdd(p.stats + 1, c_iter);
+        atomicAdd(p.stats + 2, c_rej);
+        atomicAdd(p.stats + 3, c_lsteps);
+        atomicAdd(p.stats + 4, c_liter);
+        atomicAdd(p.stats + 5, c_chain);
+    }
+}
+
 // ---------------------------------------------------------------- buckets
 __device__ __forceinline__ int bucket_key(double h, int st, int nbk, double h_ref) {
     if (st != 0 || !(h < kInf)) return nbk - 1;
@@ -206,9 +336,31 @@ __global__ void k_hpref_init(const double* __restrict__ x0, double* __restrict__
 
 }  // namespace
 
-hipError_t launch_nbody(const NbodyParams& p, int block, hipStream_t s) {
+hipError_t launch_nbody(const NbodyParams& p, int block, int lanes_per_body, hipStream_t s) {
     const size_t lds = ((size_t)p.eph.n_body * p.max_win_segs * 3 * p.eph.deg1 +
                         (size_t)(block / kWave) * kNodes * p.eph.n_body * 6) * sizeof(double);
+    if (lanes_per_body == kGroup) {
+        const long threads = (long)p.n_obj * kGroup;
+        const int grid = (int)((threads + block - 1) / block);
+        if (grid == 0) return hipSuccess;
+        // perturber counts of the common tables get an unrolled force loop
+        const int nb = p.eph.n_body;
+#define KETE_G8(B)                                                                        \
+    do {                                                                                  \
+        if (nb == 9) hipLaunchKernelGGL((k_nbody_g8<B, 9>), dim3(grid), dim3(B), lds, s, p);      \
+        else if (nb == 3) hipLaunchKernelGGL((k_nbody_g8<B, 3>), dim3(grid), dim3(B), lds, s, p); \
+        else hipLaunchKernelGGL((k_nbody_g8<B, 0>), dim3(grid), dim3(B), lds, s, p);              \
+    } while (0)
+        switch (block) {
+            case 64: KETE_G8(64); break;
+            case 128: KETE_G8(128); break;
+            case 256: KETE_G8(256); break;
+            default: return hipErrorInvalidValue;
+        }
+#undef KETE_G8
+        return hipGetLastError();
+    }
+    if (lanes_per_body != 1) return hipErrorInvalidValue;
     const int grid = (int)((p.n_obj + block - 1) / block);
     if (grid == 0) return hipSuccess;
     switch (block) {

@@ -38,6 +38,42 @@ __device__ __forceinline__ void accel(const double* __restrict__ e, const EphemA
     F[0] = ax; F[1] = ay; F[2] = az;
 }
 
+// The same force with the perturber count fixed at compile time (NB > 0):
+// the loop is unrolled, so the perturber loads of all bodies can be in
+// flight together and GM values stay in scalar registers.  NB = 0 falls
+// back to the runtime loop.
+template <int NB>
+__device__ __forceinline__ void accel_n(const double* __restrict__ e, const EphemArgs& E, const double X[3],
+                                        const double V[3], double F[3]) {
+    if constexpr (NB == 0) {
+        accel(e, E, X, V, F);
+    } else {
+        double ax = 0.0, ay = 0.0, az = 0.0;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const double* pb = e + 6 * b;
+            const double rx = X[0] - pb[0], ry = X[1] - pb[1], rz = X[2] - pb[2];
+            const double r2 = fma(rx, rx, fma(ry, ry, rz * rz));
+            const double ir = rsqrt(r2);
+            const double ir3 = ir * ir * ir;
+            const double gm = E.gm[b];
+            double f = -gm * ir3;
+            const double k = E.kgr[b];
+            if (k != 0.0) {
+                const double wx = V[0] - pb[3], wy = V[1] - pb[4], wz = V[2] - pb[5];
+                const double w2 = fma(wx, wx, fma(wy, wy, wz * wz));
+                const double rw = fma(rx, wx, fma(ry, wy, rz * wz));
+                const double g = k * ir3;
+                f = fma(g, 4.0 * gm * ir - w2, f);
+                const double q = 4.0 * g * rw;
+                ax = fma(q, wx, ax); ay = fma(q, wy, ay); az = fma(q, wz, az);
+            }
+            ax = fma(f, rx, ax); ay = fma(f, ry, ay); az = fma(f, rz, az);
+        }
+        F[0] = ax; F[1] = ay; F[2] = az;
+    }
+}
+
 // Jacobians Jx = da/dx and Jv = da/dv (row-major 3x3) of the same force.
 // Newtonian part: mu (3 r r^T / r^5 - I / r^3).  Eq. A.3 part, with
 // a = k/r^3 (s1 r + 4 (r.w) w), s1 = 4 mu/r - w^2:
@@ -181,6 +217,126 @@ __device__ __forceinline__ int corrector(const RadauConst& rc, const EphemArgs& 
         lane_iters += __popcll(__ballot(active));
     } while (!(pc < 1e-16) && !(it > 2 && pcl <= pc) && it < max_iter);
     return it;
+}
+
+// ---------------------------------------------------------------- 8 lanes per body
+// A body can be spread over an 8-lane group: lane k of the group owns
+// collocation node k + 1 (lane 7 repeats node 7), every lane keeps the
+// body's state and all seven increments, and one corrector sweep updates
+// all nodes at once from the previous sweep's increments (a Jacobi sweep
+// of the same fixed-point map, converging to the same collocation
+// solution).
+constexpr int kGroup = 8;
+
+// Constants of one node, held in registers by the lane that owns it.
+struct NodeRow {
+    double s, hs2, A[7], B[7];
+};
+
+// Row n (lane-varying, 1..7) selected from uniform constants without any
+// lane-indexed memory access.
+__device__ __forceinline__ void load_node_row(const RadauConst& rc, int n, NodeRow& r) {
+    r.s = 0.0; r.hs2 = 0.0;
+#pragma unroll
+    for (int m = 0; m < 7; ++m) { r.A[m] = 0.0; r.B[m] = 0.0; }
+#pragma unroll
+    for (int k = 1; k <= 7; ++k) {
+        const bool me = (n == k);
+        r.s = me ? rc.s[k] : r.s;
+        r.hs2 = me ? rc.half_s2[k] : r.hs2;
+#pragma unroll
+        for (int m = 0; m < 7; ++m) {
+            r.A[m] = me ? rc.A[k][m] : r.A[m];
+            r.B[m] = me ? rc.B[k][m] : r.B[m];
+        }
+    }
+}
+
+// Corrector for a body spread over an 8-lane group (see above), with the
+// same stopping rule as corrector().  Each lane keeps only its own node's
+// increment dn; the other nodes' increments are read from the group's
+// lanes when the predictor sums and b6 are formed.  On return dn holds
+// the converged increment of this lane's node, b6 the highest
+// coefficient and d6 the increment of node 7 (all lanes).
+template <int NB>
+__device__ __forceinline__ int corrector_g8(const RadauConst& rc, const EphemArgs& E, const double* __restrict__ ephW,
+                                            const NodeRow& R, int node, const double x0[3], const double v0[3],
+                                            const double F0[3], double h, bool active, int max_iter, double dn[3],
+                                            double b6[3], double d6[3]) {
+    const double hh = h * h, sh = R.s * h;
+    const double* en = ephW + node * E.n_body * 6;
+    dn[0] = dn[1] = dn[2] = 0.0;
+    b6[0] = b6[1] = b6[2] = 0.0;
+    d6[0] = d6[1] = d6[2] = 0.0;
+    double pc = 1e300;
+    int it = 0;
+    for (;;) {
+        double ax[3], av[3], bb[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) { ax[c] = R.hs2 * F0[c]; av[c] = R.s * F0[c]; bb[c] = 0.0; }
+        if (it > 0) {
+#pragma unroll
+            for (int m = 0; m < 7; ++m) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const double d = __shfl(dn[c], m, kGroup);
+                    ax[c] = fma(R.A[m], d, ax[c]);
+                    av[c] = fma(R.B[m], d, av[c]);
+                    bb[c] = fma(rc.E6[m], d, bb[c]);
+                    if (m == 6) d6[c] = d;
+                }
+            }
+            const double pcl = pc;
+            double db = 0.0, fm = 0.0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                db = fmax(db, fabs(bb[c] - b6[c]));
+                b6[c] = bb[c];
+                fm = fmax(fm, fabs(d6[c] + F0[c]));
+            }
+            const double lpc = (active && fm > 0.0) ? db / fm : 0.0;
+            pc = wave_max(lpc);
+            if (pc < 1e-16 || (it > 2 && pcl <= pc) || it >= max_iter) break;
+        }
+        ++it;
+        double X[3], V[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) X[c] = fma(hh, ax[c], fma(sh, v0[c], x0[c]));
+        if (E.has_gr) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) V[c] = fma(h, av[c], v0[c]);
+        } else {
+            V[0] = v0[0]; V[1] = v0[1]; V[2] = v0[2];
+        }
+        double F[3];
+        accel_n<NB>(en, E, X, V, F);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) dn[c] = F[c] - F0[c];
+    }
+    return it;
+}
+
+// Step end of a group-integrated body from the converged increments.
+__device__ __forceinline__ void step_end_g8(const RadauConst& rc, const double dn[3], double h, double x0[3],
+                                            double v0[3], const double F0[3]) {
+    double ax[3], av[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) { ax[c] = rc.half_s2[8] * F0[c]; av[c] = F0[c]; }
+#pragma unroll
+    for (int m = 0; m < 7; ++m) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double d = __shfl(dn[c], m, kGroup);
+            ax[c] = fma(rc.A[8][m], d, ax[c]);
+            av[c] = fma(rc.B[8][m], d, av[c]);
+        }
+    }
+    const double hh = h * h;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        x0[c] = fma(hh, ax[c], fma(h, v0[c], x0[c]));
+        v0[c] = fma(h, av[c], v0[c]);
+    }
 }
 
 // Collocation polynomial at fraction sig of the step (sig = 1: step end),
