@@ -33,7 +33,8 @@ FP64_PEAK_TFLOPS = 78.6      # MI355X vector FP64: 256 CU x 64 lanes x 2 flop x 
 HBM_PEAK_GBS = 8000.0
 
 # Algorithmic flop weights (FMA = 2, add/sub/mul = 1, rsqrt/sqrt/div = 1).
-CLENSHAW_CHAIN_FLOPS = lambda deg1: 7 * (deg1 - 1) + 12
+CLENSHAW_CHAIN_FLOPS = lambda deg1: 7 * (deg1 - 1) + 12     # value and derivative
+CLENSHAW_VALUE_FLOPS = lambda deg1: 3 * (deg1 - 1) + 9      # value only
 
 
 def node_flops(n_body: int, n_gr: int) -> int:
@@ -45,12 +46,13 @@ def node_flops(n_body: int, n_gr: int) -> int:
 
 def integrator_flops(stats, n_body: int, n_gr: int, deg1: int) -> float:
     """Algorithmic FP64 flops from the kernel's own counters:
-    stats = [wave steps, wave iterations, rejections, lane-steps,
-    lane-iterations, Clenshaw chains, ...]."""
-    lane_steps, lane_iter, chains = float(stats[3]), float(stats[4]), float(stats[5])
+    stats = [wave steps, wave iterations, rejections, body-steps,
+    body-sweeps, Clenshaw chains with derivative, value-only chains]."""
+    lane_steps, lane_iter, chains, vchains = float(stats[3]), float(stats[4]), float(stats[5]), float(stats[6])
     per_iter = 7 * node_flops(n_body, n_gr) + 3 * 14 + 12
     per_step = 3 * (1 + 28 + 4 + 2) + (18 * n_body + 27 * n_gr) + 10
-    return lane_iter * per_iter + lane_steps * per_step + chains * CLENSHAW_CHAIN_FLOPS(deg1)
+    return (lane_iter * per_iter + lane_steps * per_step + chains * CLENSHAW_CHAIN_FLOPS(deg1)
+            + vchains * CLENSHAW_VALUE_FLOPS(deg1))
 
 
 def workload_name(case, F):
@@ -334,7 +336,7 @@ def main():
             "fov_tests_per_s_bruteforce_equiv": N * F * S / (fov_ms_step / 1e3) if fov_ms_step > 0 else None,
             "pairs": n_pairs, "fov_candidates": int(fst[0]), "fov_exact_tests": int(fst[1]),
             "fov_bruteforce_objects": int(fst[2]), "failed_objects": n_fail,
-            "integrator_counters": st[:6].tolist(),
+            "integrator_counters": st[:7].tolist(),
         },
     }
     if not args.no_adjoint:

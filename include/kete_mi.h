@@ -91,7 +91,7 @@ typedef struct {
     double lt_tol;           /* light-time convergence in days (1e-15) */
     int32_t max_steps;       /* per object per call (2,000,000) */
     int32_t max_iter;        /* corrector iterations per step (12) */
-    int32_t n_buckets;       /* step-size buckets, 1 = no bucketing (8) */
+    int32_t n_buckets;       /* step-size buckets (octaves of the predicted step), 1 = none (16) */
     int32_t block;           /* integrator threads per block: 64/128/256 (64) */
     int32_t rebucket_epochs; /* epochs per integrator launch, 0 = all (16) */
     int32_t window_segs;     /* Chebyshev segments per staged window (2) */

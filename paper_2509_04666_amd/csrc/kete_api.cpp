@@ -195,6 +195,15 @@ int ephem_args(const kete_ephem_t* eph, double c_light, EphemArgs& E) {
         if (E.kgr[b] != 0.0) E.has_gr = 1;
     }
     if (!(eph->gm[0] > 0)) return fail(KETE_EINVAL, "gm[0] (Sun) must be positive");
+    int slot = 0;
+    for (int pass = 0; pass < 2; ++pass)
+        for (int b = 0; b < eph->n_body; ++b)
+            if ((E.kgr[b] != 0.0) == (pass == 0)) {
+                E.slot_of |= (unsigned long long)slot << (4 * b);
+                E.body_at |= (unsigned long long)b << (4 * slot);
+                ++slot;
+                if (pass == 0) ++E.n_gr;
+            }
     return KETE_OK;
 }
 
@@ -284,7 +293,7 @@ void kete_default_opts(kete_opts_t* o) {
     o->lt_tol = 1e-15;
     o->max_steps = 2000000;
     o->max_iter = 12;
-    o->n_buckets = 8;
+    o->n_buckets = 16;
     o->block = 64;
     o->rebucket_epochs = 16;
     o->window_segs = 2;

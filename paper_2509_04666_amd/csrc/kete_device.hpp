@@ -19,7 +19,16 @@ struct EphemArgs {
     double t_start, seg_days, inv_seg;
     double gm[KETE_MAX_BODIES];
     double kgr[KETE_MAX_BODIES];   // gm/c^2 for bodies with the Eq. A.3 term, else 0
+    // Slot order of the grouped integrator's perturber table: bodies with
+    // the Eq. A.3 term first (n_gr of them), then the others, each group
+    // in body order.  slot_of holds 4 bits per body.
+    int32_t n_gr, pad_;
+    unsigned long long slot_of;    // slot of body b: 4 bits at 4 b
+    unsigned long long body_at;    // body in slot s: 4 bits at 4 s
 };
+
+__host__ __device__ inline int body_slot(const EphemArgs& E, int b) { return (int)((E.slot_of >> (4 * b)) & 15ull); }
+__host__ __device__ inline int slot_body(const EphemArgs& E, int s) { return (int)((E.body_at >> (4 * s)) & 15ull); }
 
 __device__ __forceinline__ double dot3(const double* a, const double* b) {
     return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
@@ -44,6 +53,17 @@ __device__ __forceinline__ void clenshaw(const double* __restrict__ c, int deg1,
     }
     p = fma(tau, b1, c[0] - b2);
     dp = fma(tau, d1, b1 - d2);
+}
+
+// Clenshaw recurrence for the value only.
+__device__ __forceinline__ double clenshaw_value(const double* __restrict__ c, int deg1, double tau) {
+    double b1 = 0.0, b2 = 0.0;
+    const double t2 = tau + tau;
+    for (int k = deg1 - 1; k >= 1; --k) {
+        const double b0 = fma(t2, b1, c[k] - b2);
+        b2 = b1; b1 = b0;
+    }
+    return fma(tau, b1, c[0] - b2);
 }
 
 // Position and velocity of one body from a segment table laid out as

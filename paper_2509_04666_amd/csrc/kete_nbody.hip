@@ -156,7 +156,7 @@ __global__ __launch_bounds__(BLOCK) void k_nbody(const NbodyParams p) {
 // 8 objects of a wavefront share the time grid and the perturber table
 // as above; each sweep evaluates the force at all 7 nodes of an object
 // at once.  Output and counters are per object, as in k_nbody.
-template <int BLOCK, int NB>
+template <int BLOCK, int NB, int NGR>
 __global__ __launch_bounds__(BLOCK) void k_nbody_g8(const NbodyParams p) {
     extern __shared__ double smem[];
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
@@ -168,7 +168,9 @@ __global__ __launch_bounds__(BLOCK) void k_nbody_g8(const NbodyParams p) {
     const int cps = 3 * deg1;
     const int bstride = p.max_win_segs * cps;
     double* coefL = smem;
-    double* ephW = smem + (size_t)nb * bstride + (size_t)wid * kNodes * nb * 6;
+    // the table is read with 16-byte loads: start it on a 16-byte boundary
+    double* e8 = smem + (((size_t)nb * bstride + 1) & ~(size_t)1) + (size_t)wid * kNodes * g8_row(nb);
+    g8_table_init(E, lane, e8);
     NodeRow R;
     load_node_row(rc, node, R);
 
@@ -185,11 +187,11 @@ __global__ __launch_bounds__(BLOCK) void k_nbody_g8(const NbodyParams p) {
         for (int i = 0; i < 3; ++i) { x0[i] = p.state[6 * j + i]; v0[i] = p.state[6 * j + 3 + i]; }
         hin = p.h_pref[j];
     }
-    double hw = wave_min(active ? hin : kInf);
+    double hw = groups_min(active ? hin : kInf);
     if (!(hw < kInf)) hw = p.h_init;
     double hp_new = kInf;
 
-    unsigned long long c_steps = 0, c_iter = 0, c_rej = 0, c_lsteps = 0, c_liter = 0, c_chain = 0;
+    unsigned long long c_steps = 0, c_iter = 0, c_rej = 0, c_lsteps = 0, c_liter = 0, c_chain = 0, c_vchain = 0;
     double t = p.win[0].t_a;
     double F0[3] = {0.0, 0.0, 0.0};
     bool haveF0 = false;
@@ -215,12 +217,14 @@ __global__ __launch_bounds__(BLOCK) void k_nbody_g8(const NbodyParams p) {
             }
             const double t_end = landed ? tb : t + h;
             const double hh = h * h;
-            node_ephemeris(coefL, bstride, E, rc, W.seg_lo, W.seg_hi, t, h, t_end, lane, ephW);
-            c_chain += kNodes * nb * 3;
-            if (!haveF0) { accel_n<NB>(ephW, E, x0, v0, F0); haveF0 = true; }
+            const int n0 = haveF0 ? 1 : 0;
+            node_ephemeris8(coefL, bstride, E, rc, W.seg_lo, W.seg_hi, t, h, t_end, n0, lane, e8);
+            c_chain += (kNodes - n0) * E.n_gr * 3;
+            c_vchain += (kNodes - n0) * (nb - E.n_gr) * 3;
+            if (!haveF0) { accel8<NB, NGR>(e8, E, x0, v0, F0); haveF0 = true; }
 
             double dn[3], b6p[3], d6[3];
-            const int it = corrector_g8<NB>(rc, E, ephW, R, node, x0, v0, F0, h, active, p.max_iter, dn, b6p, d6);
+            const int it = corrector_g8<NB, NGR>(rc, E, e8, R, node, x0, v0, F0, h, active, p.max_iter, dn, b6p, d6);
             c_iter += it;
             const unsigned long long n_act = __popcll(__ballot(active)) / kGroup;
             c_liter += (unsigned long long)it * n_act;
@@ -232,7 +236,7 @@ __global__ __launch_bounds__(BLOCK) void k_nbody_g8(const NbodyParams p) {
             double hl = (ebl > 0.0 && ebl < kInf) ? fabs(h) * pow(p.eps / ebl, 1.0 / 7.0) : fabs(h) / p.safety;
             if (!active) hl = kInf;
             if (active && hl < p.h_min) { my_status = KETE_ST_STEP_UNDERFLOW; active = false; hl = kInf; }
-            const double hn = wave_min(hl);
+            const double hn = groups_min(hl);
             if (!(hn < kInf)) { t = tb; break; }
             if (hn < p.safety * fabs(h)) {
                 hw = hn;
@@ -247,7 +251,7 @@ __global__ __launch_bounds__(BLOCK) void k_nbody_g8(const NbodyParams p) {
                             isfinite(v0[0]) && isfinite(v0[1]) && isfinite(v0[2]))) {
                 my_status = KETE_ST_NONFINITE; active = false;
             }
-            accel_n<NB>(ephW + 8 * nb * 6, E, x0, v0, F0);
+            accel8<NB, NGR>(e8 + 8 * g8_row(nb), E, x0, v0, F0);
             if (landed) {
                 hw = fmin(hw, hn);
             } else {
@@ -278,6 +282,7 @@ __global__ __launch_bounds__(BLOCK) void k_nbody_g8(const NbodyParams p) {
         atomicAdd(p.stats + 3, c_lsteps);
         atomicAdd(p.stats + 4, c_liter);
         atomicAdd(p.stats + 5, c_chain);
+        atomicAdd(p.stats + 6, c_vchain);
     }
 }
 
@@ -340,16 +345,19 @@ hipError_t launch_nbody(const NbodyParams& p, int block, int lanes_per_body, hip
     const size_t lds = ((size_t)p.eph.n_body * p.max_win_segs * 3 * p.eph.deg1 +
                         (size_t)(block / kWave) * kNodes * p.eph.n_body * 6) * sizeof(double);
     if (lanes_per_body == kGroup) {
+        const size_t lds8 = ((((size_t)p.eph.n_body * p.max_win_segs * 3 * p.eph.deg1 + 1) & ~(size_t)1) +
+                             (size_t)(block / kWave) * kNodes * g8_row(p.eph.n_body)) * sizeof(double);
         const long threads = (long)p.n_obj * kGroup;
         const int grid = (int)((threads + block - 1) / block);
         if (grid == 0) return hipSuccess;
-        // perturber counts of the common tables get an unrolled force loop
-        const int nb = p.eph.n_body;
-#define KETE_G8(B)                                                                        \
-    do {                                                                                  \
-        if (nb == 9) hipLaunchKernelGGL((k_nbody_g8<B, 9>), dim3(grid), dim3(B), lds, s, p);      \
-        else if (nb == 3) hipLaunchKernelGGL((k_nbody_g8<B, 3>), dim3(grid), dim3(B), lds, s, p); \
-        else hipLaunchKernelGGL((k_nbody_g8<B, 0>), dim3(grid), dim3(B), lds, s, p);              \
+        // perturber tables of the common shapes get an unrolled force loop
+        const int nb = p.eph.n_body, ngr = p.eph.n_gr;
+#define KETE_G8(B)                                                                                        \
+    do {                                                                                                  \
+        if (nb == 9 && ngr == 3) hipLaunchKernelGGL((k_nbody_g8<B, 9, 3>), dim3(grid), dim3(B), lds8, s, p); \
+        else if (nb == 3 && ngr == 2)                                                                     \
+            hipLaunchKernelGGL((k_nbody_g8<B, 3, 2>), dim3(grid), dim3(B), lds8, s, p);                   \
+        else hipLaunchKernelGGL((k_nbody_g8<B, 0, 0>), dim3(grid), dim3(B), lds8, s, p);                  \
     } while (0)
         switch (block) {
             case 64: KETE_G8(64); break;

@@ -252,19 +252,136 @@ __device__ __forceinline__ void load_node_row(const RadauConst& rc, int n, NodeR
     }
 }
 
+// Wave-wide reductions of values that are equal within each 8-lane group.
+__device__ __forceinline__ double groups_max(double x) {
+#pragma unroll
+    for (int off = kGroup; off < kWave; off <<= 1) x = fmax(x, __shfl_xor(x, off, kWave));
+    return uniform(x);
+}
+__device__ __forceinline__ double groups_min(double x) {
+#pragma unroll
+    for (int off = kGroup; off < kWave; off <<= 1) x = fmin(x, __shfl_xor(x, off, kWave));
+    return uniform(x);
+}
+
+// Perturber table of the grouped integrator: per node and slot 8 doubles
+// (x, y, z, GM, vx, vy, vz, GM/c^2).  GM values are written once per
+// launch (g8_table_init); node_ephemeris8 fills positions, and velocities
+// only for the slots that carry the Eq. A.3 term.
+constexpr int kSlot = 8;
+// Doubles per node row: 4 (4 n_body + 1) dwords, so the 8 rows read
+// together by an 8-lane group fall in distinct LDS banks.
+__host__ __device__ inline int g8_row(int n_body) { return n_body * kSlot + 2; }
+
+__device__ __forceinline__ void g8_table_init(const EphemArgs& E, int lane, double* __restrict__ e8) {
+    for (int b = 0; b < E.n_body; ++b) {
+        const int sl = body_slot(E, b);
+        for (int n = lane; n < kNodes; n += kWave) {
+            e8[n * g8_row(E.n_body) + sl * kSlot + 3] = E.gm[b];
+            e8[n * g8_row(E.n_body) + sl * kSlot + 7] = E.kgr[b];
+        }
+    }
+}
+
+// Perturber states at node times n0..8 of a step (node 0 is only needed
+// before the first step; later steps reuse the force at the previous
+// step end).  Chains with a velocity come first so lanes of one pass do
+// equal work.
+__device__ __forceinline__ void node_ephemeris8(const double* __restrict__ coefL, int bstride, const EphemArgs& E,
+                                                const RadauConst& rc, int seg_lo, int seg_hi, double t, double h,
+                                                double t_end, int n0, int lane, double* __restrict__ e8) {
+    const int nb = E.n_body, ngr = E.n_gr, deg1 = E.deg1, cps = 3 * deg1;
+    const int nn = kNodes - n0;
+    auto tau_of = [&](int n, int& k) {
+        const double tt = (n == kNodes - 1) ? t_end : t + rc.s[n] * h;
+        k = seg_index(tt, E.t_start, E.inv_seg, seg_lo, seg_hi);
+        return 2.0 * (tt - (E.t_start + (double)k * E.seg_days)) * E.inv_seg - 1.0;
+    };
+    const int n_vel = nn * ngr * 3;
+    for (int c = lane; c < n_vel; c += kWave) {
+        const int n = n0 + c / (ngr * 3);
+        const int r = c % (ngr * 3);
+        const int sl = r / 3, i = r - 3 * sl;
+        const int b = slot_body(E, sl);
+        int k;
+        const double tau = tau_of(n, k);
+        double pv, dv;
+        clenshaw(coefL + b * bstride + (k - seg_lo) * cps + i * deg1, deg1, tau, pv, dv);
+        e8[n * g8_row(nb) + sl * kSlot + i] = pv;
+        e8[n * g8_row(nb) + sl * kSlot + 4 + i] = dv * 2.0 * E.inv_seg;
+    }
+    const int npl = nb - ngr;
+    const int n_pos = nn * npl * 3;
+    for (int c = lane; c < n_pos; c += kWave) {
+        const int n = n0 + c / (npl * 3);
+        const int r = c % (npl * 3);
+        const int sl = ngr + r / 3, i = r % 3;
+        const int b = slot_body(E, sl);
+        int k;
+        const double tau = tau_of(n, k);
+        e8[n * g8_row(nb) + sl * kSlot + i] = clenshaw_value(coefL + b * bstride + (k - seg_lo) * cps + i * deg1, deg1, tau);
+    }
+    wave_lds_sync();
+}
+
+// Force of Eqs. A.1 + A.3 from the grouped table e8 (one node): slots
+// below NGR carry the Eq. A.3 term.  NB = 0 takes the counts at run time.
+template <int NB, int NGR>
+__device__ __forceinline__ void accel8(const double* __restrict__ e8, const EphemArgs& E, const double X[3],
+                                       const double V[3], double F[3]) {
+    const int nb = NB > 0 ? NB : E.n_body;
+    const int ngr = NB > 0 ? NGR : E.n_gr;
+    double ax = 0.0, ay = 0.0, az = 0.0;
+#pragma unroll
+    for (int b = 0; b < (NB > 0 ? NGR : KETE_MAX_BODIES); ++b) {
+        if (NB == 0 && b >= ngr) break;
+        const double* pb = e8 + kSlot * b;
+        const double2 pxy = *reinterpret_cast<const double2*>(pb);
+        const double2 pzg = *reinterpret_cast<const double2*>(pb + 2);
+        const double2 vxy = *reinterpret_cast<const double2*>(pb + 4);
+        const double2 vzk = *reinterpret_cast<const double2*>(pb + 6);
+        const double rx = X[0] - pxy.x, ry = X[1] - pxy.y, rz = X[2] - pzg.x;
+        const double r2 = fma(rx, rx, fma(ry, ry, rz * rz));
+        const double ir = rsqrt(r2);
+        const double ir3 = ir * ir * ir;
+        const double gm = pzg.y;
+        const double wx = V[0] - vxy.x, wy = V[1] - vxy.y, wz = V[2] - vzk.x;
+        const double w2 = fma(wx, wx, fma(wy, wy, wz * wz));
+        const double rw = fma(rx, wx, fma(ry, wy, rz * wz));
+        const double g = vzk.y * ir3;
+        const double f = fma(g, 4.0 * gm * ir - w2, -gm * ir3);
+        const double q = 4.0 * g * rw;
+        ax = fma(q, wx, ax); ay = fma(q, wy, ay); az = fma(q, wz, az);
+        ax = fma(f, rx, ax); ay = fma(f, ry, ay); az = fma(f, rz, az);
+    }
+#pragma unroll
+    for (int b = (NB > 0 ? NGR : 0); b < (NB > 0 ? NB : KETE_MAX_BODIES); ++b) {
+        if (NB == 0 && b >= nb - ngr) break;
+        const double* pb = e8 + kSlot * (NB > 0 ? b : b + ngr);
+        const double2 pxy = *reinterpret_cast<const double2*>(pb);
+        const double2 pzg = *reinterpret_cast<const double2*>(pb + 2);
+        const double rx = X[0] - pxy.x, ry = X[1] - pxy.y, rz = X[2] - pzg.x;
+        const double r2 = fma(rx, rx, fma(ry, ry, rz * rz));
+        const double ir = rsqrt(r2);
+        const double f = -pzg.y * (ir * ir * ir);
+        ax = fma(f, rx, ax); ay = fma(f, ry, ay); az = fma(f, rz, az);
+    }
+    F[0] = ax; F[1] = ay; F[2] = az;
+}
+
 // Corrector for a body spread over an 8-lane group (see above), with the
 // same stopping rule as corrector().  Each lane keeps only its own node's
 // increment dn; the other nodes' increments are read from the group's
 // lanes when the predictor sums and b6 are formed.  On return dn holds
 // the converged increment of this lane's node, b6 the highest
 // coefficient and d6 the increment of node 7 (all lanes).
-template <int NB>
-__device__ __forceinline__ int corrector_g8(const RadauConst& rc, const EphemArgs& E, const double* __restrict__ ephW,
+template <int NB, int NGR>
+__device__ __forceinline__ int corrector_g8(const RadauConst& rc, const EphemArgs& E, const double* __restrict__ e8,
                                             const NodeRow& R, int node, const double x0[3], const double v0[3],
                                             const double F0[3], double h, bool active, int max_iter, double dn[3],
                                             double b6[3], double d6[3]) {
     const double hh = h * h, sh = R.s * h;
-    const double* en = ephW + node * E.n_body * 6;
+    const double* en = e8 + node * g8_row(E.n_body);
     dn[0] = dn[1] = dn[2] = 0.0;
     b6[0] = b6[1] = b6[2] = 0.0;
     d6[0] = d6[1] = d6[2] = 0.0;
@@ -295,7 +412,7 @@ __device__ __forceinline__ int corrector_g8(const RadauConst& rc, const EphemArg
                 fm = fmax(fm, fabs(d6[c] + F0[c]));
             }
             const double lpc = (active && fm > 0.0) ? db / fm : 0.0;
-            pc = wave_max(lpc);
+            pc = groups_max(lpc);
             if (pc < 1e-16 || (it > 2 && pcl <= pc) || it >= max_iter) break;
         }
         ++it;
@@ -309,7 +426,7 @@ __device__ __forceinline__ int corrector_g8(const RadauConst& rc, const EphemArg
             V[0] = v0[0]; V[1] = v0[1]; V[2] = v0[2];
         }
         double F[3];
-        accel_n<NB>(en, E, X, V, F);
+        accel8<NB, NGR>(en, E, X, V, F);
 #pragma unroll
         for (int c = 0; c < 3; ++c) dn[c] = F[c] - F0[c];
     }
@@ -320,15 +437,19 @@ __device__ __forceinline__ int corrector_g8(const RadauConst& rc, const EphemArg
 __device__ __forceinline__ void step_end_g8(const RadauConst& rc, const double dn[3], double h, double x0[3],
                                             double v0[3], const double F0[3]) {
     double ax[3], av[3];
+    // opaque zero row offset: the constants are loaded where used instead
+    // of being held in (spilled) scalar registers for the whole kernel
+    int z;
+    asm volatile("s_mov_b32 %0, 0" : "=s"(z));
 #pragma unroll
-    for (int c = 0; c < 3; ++c) { ax[c] = rc.half_s2[8] * F0[c]; av[c] = F0[c]; }
+    for (int c = 0; c < 3; ++c) { ax[c] = rc.half_s2[8 + z] * F0[c]; av[c] = F0[c]; }
 #pragma unroll
     for (int m = 0; m < 7; ++m) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const double d = __shfl(dn[c], m, kGroup);
-            ax[c] = fma(rc.A[8][m], d, ax[c]);
-            av[c] = fma(rc.B[8][m], d, av[c]);
+            ax[c] = fma(rc.A[8 + z][m], d, ax[c]);
+            av[c] = fma(rc.B[8 + z][m], d, av[c]);
         }
     }
     const double hh = h * h;
