@@ -240,8 +240,9 @@ int kete_fov_check(const kete_ephem_t *eph, const double *x_epoch, const int32_t
                    void *workspace, size_t ws_bytes, void *stream);
 
 /* Counters of the last kete_fov_check on the calling thread: out[0]
- * candidate frames visited, out[1] exact light-time tests, out[2] objects
- * handled by the brute-force path, out[3] reserved. */
+ * (object, frame) pairs that passed the cap test, out[1] exact light-time
+ * tests, out[2] objects handled by the brute-force path, out[3] frame
+ * records scanned by the per-cell join (per wavefront). */
 void kete_fov_last_stats(int64_t out[4]);
 
 /* Light-time corrected directions (the per-pair step of kete_fov_check,

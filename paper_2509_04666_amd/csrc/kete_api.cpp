@@ -489,6 +489,7 @@ size_t kete_fov_workspace_size(int64_t n_obj, int64_t n_frames, int64_t n_batch,
     c.take<int32_t>((size_t)nkeys + 1);
     c.take<int32_t>((size_t)nkeys + 1);
     c.take<int32_t>((size_t)n_frames);
+    c.take<double>((size_t)n_frames * 8);           // frame caps in cell order
     c.take<unsigned long long>((size_t)std::max<int64_t>(pairs_cap, 1));
     c.take<unsigned long long>(8);
     c.take<int32_t>((size_t)n_frames + 1);
@@ -503,6 +504,9 @@ size_t kete_fov_workspace_size(int64_t n_obj, int64_t n_frames, int64_t n_batch,
     c.take<int32_t>((size_t)nkeys + 1);
     c.take<unsigned long long>((size_t)(n_batch * n_obj));   // wide objects
     c.take<char>(scan_scratch_bytes(nkeys));
+    c.take<int32_t>((size_t)nkeys + 1);             // join work items per key and their starts
+    c.take<int32_t>((size_t)nkeys + 1);
+    c.take<unsigned long long>((size_t)fov_item_capacity(nkeys, n_batch * n_obj));
     c.take<int64_t>((size_t)n_batch + 1);          // batch -> object layout
     c.take<int32_t>((size_t)n_batch);
     c.take<int64_t>((size_t)n_batch);
@@ -553,6 +557,7 @@ int kete_fov_check(const kete_ephem_t* eph, const double* x_epoch, const int32_t
     int32_t* cnt = c.take<int32_t>((size_t)nkeys + 1);
     P.cell_start = c.take<int32_t>((size_t)nkeys + 1);
     P.cell_frames = c.take<int32_t>((size_t)F);
+    P.cell_caps = c.take<double>((size_t)F * 8);
     P.pairs = c.take<unsigned long long>((size_t)std::max<int64_t>(pairs_cap, 1));
     unsigned long long* counters = c.take<unsigned long long>(8);
     int32_t* fcnt = c.take<int32_t>((size_t)F + 1);
@@ -568,6 +573,9 @@ int kete_fov_check(const kete_ephem_t* eph, const double* x_epoch, const int32_t
     int32_t* ocnt = c.take<int32_t>((size_t)nkeys + 1);
     P.wide = c.take<unsigned long long>((size_t)(n_batch * n_obj));
     void* oscan = c.take<char>(scan_scratch_bytes(nkeys));
+    int32_t* icnt = c.take<int32_t>((size_t)nkeys + 1);
+    int32_t* istart = c.take<int32_t>((size_t)nkeys + 1);
+    unsigned long long* items = c.take<unsigned long long>((size_t)fov_item_capacity(nkeys, n_batch * n_obj));
     int64_t* b_poff = c.take<int64_t>((size_t)n_batch + 1);
     int32_t* b_obj0 = c.take<int32_t>((size_t)n_batch);
     int64_t* b_xoff = c.take<int64_t>((size_t)n_batch);
@@ -613,9 +621,11 @@ int kete_fov_check(const kete_ephem_t* eph, const double* x_epoch, const int32_t
     P.n_wide = counters + 6;
     HIPCHK(fov_sort_objects(P, okey, ocnt, ostart, osorted, oscan, s));
     P.obj_sorted = osorted;
+    P.obj_start = ostart;
+    P.obj_count = ocnt;
     {
         TimedScope ts(kTimeFov, s);
-        HIPCHK(fov_candidates(P, opts->fov_block, s));
+        HIPCHK(fov_candidates(P, icnt, istart, items, (unsigned int*)(counters + 7), oscan, s));
         HIPCHK(fov_exact(P, s));
     }
     unsigned long long host_counters[8];
@@ -884,7 +894,8 @@ struct BatchWs {
     unsigned int* tile_counter;
     int32_t* perm;
     FovParams P;
-    int32_t *qkey, *cnt, *fcnt, *fstart, *okey, *osorted, *ostart, *ocnt;
+    int32_t *qkey, *cnt, *fcnt, *fstart, *okey, *osorted, *ostart, *ocnt, *icnt, *istart;
+    unsigned long long* items;
     unsigned long long *counters, *sorted;
     void *scan_scratch, *oscan;
     int64_t *b_poff, *b_xoff, *b_koff;
@@ -904,6 +915,7 @@ size_t batch_carve(const BatchDims& d, const kete_batch_t* bt, char* base, Batch
     w.cnt = c.take<int32_t>((size_t)d.nkeys + 1);
     P.cell_start = c.take<int32_t>((size_t)d.nkeys + 1);
     P.cell_frames = c.take<int32_t>((size_t)d.F);
+    P.cell_caps = c.take<double>((size_t)d.F * 8);
     P.pairs = c.take<unsigned long long>((size_t)std::max<int64_t>(d.pairs_cap, 1));
     w.counters = c.take<unsigned long long>(8);
     w.fcnt = c.take<int32_t>((size_t)d.F + 1);
@@ -918,6 +930,9 @@ size_t batch_carve(const BatchDims& d, const kete_batch_t* bt, char* base, Batch
     w.ocnt = c.take<int32_t>((size_t)d.nkeys + 1);
     P.wide = c.take<unsigned long long>((size_t)std::max<int64_t>(d.NP, 1));
     w.oscan = c.take<char>(scan_scratch_bytes(d.nkeys));
+    w.icnt = c.take<int32_t>((size_t)d.nkeys + 1);
+    w.istart = c.take<int32_t>((size_t)d.nkeys + 1);
+    w.items = c.take<unsigned long long>((size_t)fov_item_capacity(d.nkeys, d.NP));
     w.b_poff = c.take<int64_t>((size_t)d.B + 1);
     w.b_obj0 = c.take<int32_t>((size_t)d.B + 1);
     w.b_xoff = c.take<int64_t>((size_t)d.B + 1);
@@ -1051,8 +1066,10 @@ int kete_batch_run(const kete_ephem_t* eph, const kete_batch_t* batch, int64_t p
         HIPCHK(fov_prepare(P, w.qkey, w.cnt, w.cnt, w.scan_scratch, s));
         HIPCHK(fov_sort_objects(P, w.okey, w.ocnt, w.ostart, w.osorted, w.oscan, s));
         P.obj_sorted = w.osorted;
+        P.obj_start = w.ostart;
+        P.obj_count = w.ocnt;
         TimedScope ts(kTimeFov, s);
-        HIPCHK(fov_candidates(P, opts->fov_block, s));
+        HIPCHK(fov_candidates(P, w.icnt, w.istart, w.items, (unsigned int*)(w.counters + 7), w.oscan, s));
         HIPCHK(fov_exact(P, s));
     }
     return KETE_OK;

@@ -185,7 +185,13 @@ __global__ void k_frame_scatter(const FovParams p, const int32_t* __restrict__ q
     if (q >= p.n_frames) return;
     const int key = qkey[q];
     const int pos = p.cell_start[key] + atomicAdd(cursor + key, 1);
-    p.cell_frames[pos] = p.frame_order[q];
+    const int f = p.frame_order[q];
+    p.cell_frames[pos] = f;
+    const double* src = p.fcap + 8 * f;
+    double* dst = p.cell_caps + 8 * (int64_t)pos;
+    for (int i = 0; i < 5; ++i) dst[i] = src[i];
+    dst[5] = (double)f;
+    dst[6] = dst[7] = 0.0;
 }
 
 struct SunLds {
@@ -210,6 +216,41 @@ __device__ __forceinline__ void wave_append(unsigned long long* list, unsigned l
     base = __shfl(base, leader, 64);
     const unsigned long long idx = base + __popcll(m & lt);
     if (idx < (unsigned long long)cap) list[idx] = key;
+}
+
+// Per-wavefront staging of list appends in LDS: appends gather in `buf`
+// (128 entries) and reach the global list 64 or more at a time, so the
+// shared counter sees one atomic per flush instead of one per append.
+// Both calls must be made by the whole wavefront.
+constexpr int kBufEntries = 128;
+
+__device__ __forceinline__ void buf_flush(unsigned long long* __restrict__ buf, int& n,
+                                          unsigned long long* __restrict__ list, unsigned long long* count,
+                                          int64_t cap) {
+    if (n == 0) return;
+    const int lane = threadIdx.x & 63;
+    wave_lds_sync();
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(count, (unsigned long long)n);
+    base = __shfl(base, 0, 64);
+    for (int i = lane; i < n; i += 64) {
+        const unsigned long long idx = base + (unsigned long long)i;
+        if (idx < (unsigned long long)cap) list[idx] = buf[i];
+    }
+    wave_lds_sync();
+    n = 0;
+}
+
+__device__ __forceinline__ void buf_append(unsigned long long* __restrict__ buf, int& n, bool pred,
+                                           unsigned long long key, unsigned long long* __restrict__ list,
+                                           unsigned long long* count, int64_t cap) {
+    const unsigned long long m = __ballot(pred);
+    if (m == 0ull) return;
+    const int lane = threadIdx.x & 63;
+    const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    if (pred) buf[n + __popcll(m & lt)] = key;
+    n += __popcll(m);
+    if (n >= 64) buf_flush(buf, n, list, count, cap);
 }
 
 // Everything one (object, batch) needs to skip frames it cannot reach.
@@ -299,21 +340,34 @@ __device__ __forceinline__ bool object_bounds(const FovParams& p, int b, int64_t
 
 constexpr int kNarrowCells = 27;
 
-__device__ __forceinline__ bool is_narrow(const ObjBounds& o) { return !o.overflow && o.ncell <= kNarrowCells; }
+// Narrow: the cap's grid box lies inside the 3x3x3 neighbourhood of the
+// cell holding the direction itself, so every frame the object can reach
+// is listed in one of those 27 cells.
+__device__ __forceinline__ bool is_narrow(const ObjBounds& o, int G) {
+    if (o.overflow) return false;
+    for (int c = 0; c < 3; ++c) {
+        const int home = cell_coord(o.dh[c], G);
+        if (o.lo[c] < home - 1 || o.hi[c] > home + 1) return false;
+    }
+    return true;
+}
 
 // Cap test with the frame's own radius, then the linear-motion test with
 // its remainder bound; survivors become exact-test candidates.
-__device__ __forceinline__ bool frame_may_contain(const FovParams& p, const ObjBounds& o, int f, double tr,
-                                                  double Asun, unsigned long long& n_cand) {
-    const double* cp = p.fcap + 8 * f;
-    if (!o.overflow) {
-        const double thr = cp[3] * o.cth - cp[4] * o.sth;     // cos(R_f + theta)
-        if (dot3(cp, o.dh) < thr - 1e-12) return false;
-    }
-    ++n_cand;
+__device__ __forceinline__ bool frame_cap_hit(const ObjBounds& o, const double* __restrict__ cp) {
+    if (o.overflow) return true;
+    const double thr = cp[3] * o.cth - cp[4] * o.sth;         // cos(R_f + theta)
+    return !(dot3(cp, o.dh) < thr - 1e-12);
+}
+
+// Linear-motion test of a frame that passed the cap test.
+// Linear-motion test with its remainder bound: the object moves on
+// x + v dt within eps of its true position, so it is outside a sub-frame
+// when some normal has n . ul / |ul| <= -2 eps / |ul|.  dt is the frame
+// time minus the batch epoch, ob the observer, nrm the n_sub x 4 normals.
+__device__ __forceinline__ bool lin_may_contain(const ObjBounds& o, double dt, const double ob[3],
+                                                const double* __restrict__ nrm, int n_sub, double Asun) {
     if (!o.lin_ok) return true;
-    const double dt = p.ft[f] - tr;
-    const double* ob = p.fobs + 3 * f;
     double ul[3];
     for (int c = 0; c < 3; ++c) ul[c] = o.x[c] + o.v[c] * dt - ob[c];
     const double uln = sqrt(dot3(ul, ul));
@@ -321,8 +375,7 @@ __device__ __forceinline__ bool frame_may_contain(const FovParams& p, const ObjB
     const double eps = o.vbn * o.taumax + 0.5 * (o.a2b + Asun) * ad * ad + 1e-12;
     const double eta = 2.0 * eps / uln;
     if (!(eta < 1.0)) return true;
-    const double* nrm = p.normals + (size_t)f * p.n_sub * 12;
-    for (int s = 0; s < p.n_sub; ++s) {
+    for (int s = 0; s < n_sub; ++s) {
         bool out = false;
         for (int i = 0; i < 4; ++i) out |= dot3(nrm + 12 * s + 3 * i, ul) / uln <= -eta;
         if (!out) return true;
@@ -330,9 +383,34 @@ __device__ __forceinline__ bool frame_may_contain(const FovParams& p, const ObjB
     return false;
 }
 
-// Narrow objects: one lane per (object, batch), objects of a batch in sky
-// cell order so that the lanes of a wavefront visit the same cells.
-// Wide objects are handed to k_fov_wide.
+__device__ __forceinline__ bool frame_may_contain_lin(const FovParams& p, const ObjBounds& o, int f, double tr,
+                                                      double Asun) {
+    const double* ob = p.fobs + 3 * f;
+    const double obv[3] = {ob[0], ob[1], ob[2]};
+    return lin_may_contain(o, p.ft[f] - tr, obv, p.normals + (size_t)f * p.n_sub * 12, p.n_sub, Asun);
+}
+
+__device__ __forceinline__ bool frame_may_contain(const FovParams& p, const ObjBounds& o, int f, double tr,
+                                                  double Asun, unsigned long long& n_cand) {
+    if (!frame_cap_hit(o, p.fcap + 8 * f)) return false;
+    ++n_cand;
+    return frame_may_contain_lin(p, o, f, tr, Asun);
+}
+
+// The same for the k-th frame of the cell lists (cap record read in place).
+__device__ __forceinline__ bool cell_frame_may_contain(const FovParams& p, const ObjBounds& o, int k, double tr,
+                                                       double Asun, unsigned long long& n_cand, int& f) {
+    const double* cp = p.cell_caps + 8 * (int64_t)k;
+    if (!frame_cap_hit(o, cp)) return false;
+    f = (int)cp[5];
+    ++n_cand;
+    return frame_may_contain_lin(p, o, f, tr, Asun);
+}
+
+// Narrow objects: one wavefront per (batch, sky cell) of objects.  The
+// lanes take the cell's objects 64 at a time and scan the frames of the 27
+// neighbouring cells together: the loops are the same for every lane and
+// the frame records are broadcast loads.
 // batch of a flattened (batch, object) index: b_poff[b] <= i < b_poff[b+1]
 __device__ __forceinline__ int batch_of(const int64_t* __restrict__ poff, int n_batch, int64_t i) {
     int lo = 0, hi = n_batch;
@@ -343,37 +421,149 @@ __device__ __forceinline__ int batch_of(const int64_t* __restrict__ poff, int n_
     return lo;
 }
 
-template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_fov(const FovParams p) {
-    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    const bool in_range = i < p.n_pairs_total;
-    const int b = in_range ? batch_of(p.b_poff, p.n_batch, i) : 0;
-    const int64_t j = in_range ? p.obj_sorted[i] : 0;
-    unsigned long long n_cand = 0, n_exact = 0;
-    ObjBounds o;
-    const bool live = in_range && object_bounds(p, b, j, o);
-    const unsigned long long gobj = (unsigned long long)(p.b_obj0[b] + j);
-    if (live && !is_narrow(o)) {
-        wave_append(p.wide, p.n_wide, p.n_pairs_total, ((unsigned long long)b << 32) | (unsigned long long)j);
-    } else if (live) {
-        const double tr = p.t_ref[b];
-        const double Asun = p.btab[kBatchStride * b + 14];
+// batch holding sort key `key` (keys are batch-major)
+__device__ __forceinline__ int batch_of_key(const int64_t* __restrict__ koff, int n_batch, int64_t key) {
+    int lo = 0, hi = n_batch;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (koff[mid] <= key) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Read lane m's value (m uniform) into every lane.
+__device__ __forceinline__ double lane_value(double v, int m) {
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffll), m);
+    const int hi = __builtin_amdgcn_readlane((int)(u >> 32), m);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Work items of the join: one per 64 narrow objects of a (batch, cell).
+__global__ void k_item_count(const FovParams p, int32_t* __restrict__ icnt) {
+    const int64_t key = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (key >= p.n_keys) return;
+    const int b = batch_of_key(p.b_koff, p.n_batch, key);
+    const int G = p.b_G[b];
+    const bool narrow_cell = key - p.b_koff[b] < (int64_t)G * G * G;
+    icnt[key] = narrow_cell ? (p.obj_count[key] + kWave - 1) / kWave : 0;
+}
+
+__global__ void k_item_scatter(const FovParams p, const int32_t* __restrict__ icnt) {
+    const int64_t key = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (key >= p.n_keys) return;
+    const int n = icnt[key], s0 = p.item_start[key];
+    for (int c = 0; c < n; ++c) p.items[s0 + c] = ((unsigned long long)key << 32) | (unsigned long long)c;
+}
+
+// Persistent join: every wavefront pops work items until none is left.
+__global__ __launch_bounds__(256) void k_fov_cells(const FovParams p) {
+    const int lane = threadIdx.x & 63;
+    unsigned long long n_cand = 0, n_exact = 0, n_visit = 0;
+    const double* __restrict__ caps = p.cell_caps;
+    const bool one_sub = p.n_sub == 1;
+    const int n_items = p.item_start[p.n_keys];
+    __shared__ unsigned long long bufs[4][kBufEntries];
+    unsigned long long* buf = bufs[(threadIdx.x >> 6) & 3];
+    int nbuf = 0;
+    for (;;) {
+        int item = 0;
+        if (lane == 0) item = (int)atomicAdd(p.item_next, 1u);
+        item = __shfl(item, 0, kWave);
+        if (item >= n_items) break;
+        const unsigned long long it = p.items[item];
+        const int64_t key = (int64_t)(it >> 32);
+        const int chunk = (int)(it & 0xffffffffull);
+        const int o1 = p.obj_start[key + 1];
+        const int o0 = p.obj_start[key] + chunk * kWave;
+        const int b = batch_of_key(p.b_koff, p.n_batch, key);
         const int G = p.b_G[b];
         const int64_t base = p.b_koff[b];
-        for (int ix = o.lo[0]; ix <= o.hi[0]; ++ix)
-            for (int iy = o.lo[1]; iy <= o.hi[1]; ++iy)
-                for (int iz = o.lo[2]; iz <= o.hi[2]; ++iz) {
-                    const int64_t key = base + (ix * G + iy) * G + iz;
-                    const int a0 = p.cell_start[key], a1 = p.cell_start[key + 1];
-                    for (int k = a0; k < a1; ++k) {
-                        const int f = p.cell_frames[k];
-                        if (frame_may_contain(p, o, f, tr, Asun, n_cand)) {
-                            ++n_exact;
-                            wave_append(p.cand, p.n_cand, p.cand_cap, ((unsigned long long)f << 32) | gobj);
-                        }
+        const int cell = (int)(key - base);
+        const int ix = cell / (G * G), iy = (cell / G) % G, iz = cell % G;
+        const double tr = p.t_ref[b];
+        const double Asun = p.btab[kBatchStride * b + 14];
+        // frame ranges of the 27 neighbouring cells, one per lane, and their
+        // offsets in the concatenated neighbourhood list
+        int my_a0 = 0, my_len = 0;
+        if (lane < 27) {
+            const int cx = ix + lane / 9 - 1, cy = iy + (lane / 3) % 3 - 1, cz = iz + lane % 3 - 1;
+            if (cx >= 0 && cx < G && cy >= 0 && cy < G && cz >= 0 && cz < G) {
+                const int64_t nk = base + ((int64_t)cx * G + cy) * G + cz;
+                my_a0 = p.cell_start[nk];
+                my_len = p.cell_start[nk + 1] - my_a0;
+            }
+        }
+        int incl = my_len;
+#pragma unroll
+        for (int off = 1; off < 32; off <<= 1) {
+            const int t = __shfl_up(incl, off, kWave);
+            if (lane >= off) incl += t;
+        }
+        const int excl = incl - my_len;
+        const int total = __shfl(incl, 26, kWave);
+        if (total == 0) continue;
+        {
+            const int q = o0 + lane;
+            const bool has = q < o1;
+            const int64_t j = has ? p.obj_sorted[q] : 0;
+            ObjBounds o;
+            const bool live = has && object_bounds(p, b, j, o);
+            const unsigned long long gobj = (unsigned long long)(p.b_obj0[b] + j);
+            for (int g0 = 0; g0 < total; g0 += kWave) {
+                // lane l holds frame record g0 + l of the neighbourhood list
+                const int g = g0 + lane;
+                int nq = 0;
+                for (int t = 1; t < 27; ++t) nq = (__shfl(excl, t, kWave) <= g) ? t : nq;
+                const int rk = __shfl(my_a0, nq, kWave) + (g - __shfl(excl, nq, kWave));
+                // lane l also holds that frame's time, observer and (single
+                // sub-frame) normals for the linear test
+                double r[6] = {0.0, 0.0, 0.0, 2.0, 0.0, 0.0};
+                double rt = 0.0, ro[3] = {0.0, 0.0, 0.0}, rn[12];
+#pragma unroll
+                for (int i = 0; i < 12; ++i) rn[i] = 0.0;
+                if (g < total) {
+                    const double* cp = caps + 8 * (int64_t)rk;
+                    const double2 c01 = *reinterpret_cast<const double2*>(cp);
+                    const double2 c23 = *reinterpret_cast<const double2*>(cp + 2);
+                    const double2 c45 = *reinterpret_cast<const double2*>(cp + 4);
+                    r[0] = c01.x; r[1] = c01.y; r[2] = c23.x; r[3] = c23.y; r[4] = c45.x; r[5] = c45.y;
+                    const int f = (int)r[5];
+                    rt = p.ft[f] - tr;
+                    for (int c = 0; c < 3; ++c) ro[c] = p.fobs[3 * f + c];
+                    if (one_sub) {
+#pragma unroll
+                        for (int i = 0; i < 12; ++i) rn[i] = p.normals[(size_t)f * 12 + i];
                     }
                 }
+                const int n = min(kWave, total - g0);
+                n_visit += (unsigned long long)n;
+                for (int m = 0; m < n; ++m) {
+                    double cpm[5];
+#pragma unroll
+                    for (int i = 0; i < 5; ++i) cpm[i] = lane_value(r[i], m);
+                    const bool hit = live && frame_cap_hit(o, cpm);
+                    if (__ballot(hit) == 0ull) continue;
+                    const int f = (int)lane_value(r[5], m);
+                    const double dt = lane_value(rt, m);
+                    const double ob[3] = {lane_value(ro[0], m), lane_value(ro[1], m), lane_value(ro[2], m)};
+                    bool may;
+                    if (one_sub) {
+                        double nm[12];
+#pragma unroll
+                        for (int i = 0; i < 12; ++i) nm[i] = lane_value(rn[i], m);
+                        may = hit && lin_may_contain(o, dt, ob, nm, 1, Asun);
+                    } else {
+                        may = hit && lin_may_contain(o, dt, ob, p.normals + (size_t)f * p.n_sub * 12, p.n_sub, Asun);
+                    }
+                    if (hit) ++n_cand;
+                    if (may) ++n_exact;
+                    buf_append(buf, nbuf, may, ((unsigned long long)f << 32) | gobj, p.cand, p.n_cand, p.cand_cap);
+                }
+            }
+        }
     }
+    buf_flush(buf, nbuf, p.cand, p.n_cand, p.cand_cap);
     if (p.stats) {
         unsigned long long a = n_cand, e = n_exact;
 #pragma unroll
@@ -381,9 +571,10 @@ __global__ __launch_bounds__(BLOCK) void k_fov(const FovParams p) {
             a += __shfl_xor(a, off, 64);
             e += __shfl_xor(e, off, 64);
         }
-        if ((threadIdx.x & 63) == 0) {
+        if (lane == 0) {
             atomicAdd(p.stats + 0, a);
             atomicAdd(p.stats + 1, e);
+            atomicAdd(p.stats + 3, n_visit);
         }
     }
 }
@@ -396,6 +587,9 @@ __global__ __launch_bounds__(256) void k_fov_wide(const FovParams p) {
     const int64_t n_items = (int64_t)(nw < (unsigned long long)p.n_pairs_total ? nw : p.n_pairs_total);
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    __shared__ unsigned long long bufs[4][kBufEntries];
+    unsigned long long* buf = bufs[(threadIdx.x >> 6) & 3];
+    int nbuf = 0;
     unsigned long long n_cand = 0, n_exact = 0, n_over = 0;
     for (int64_t it = wave; it < n_items; it += n_waves) {
         const unsigned long long w = p.wide[it];
@@ -408,34 +602,43 @@ __global__ __launch_bounds__(256) void k_fov_wide(const FovParams p) {
         const double Asun = p.btab[kBatchStride * b + 14];
         if (o.overflow) {
             if (lane == 0) ++n_over;
-            for (int q = p.batch_off[b] + lane; q < p.batch_off[b + 1]; q += 64) {
-                const int f = p.frame_order[q];
-                if (frame_may_contain(p, o, f, tr, Asun, n_cand)) {
-                    ++n_exact;
-                    wave_append(p.cand, p.n_cand, p.cand_cap, ((unsigned long long)f << 32) | gobj);
-                }
+            const int q1 = p.batch_off[b + 1];
+            for (int q0 = p.batch_off[b]; q0 < q1; q0 += 64) {
+                const int q = q0 + lane;
+                const int f = q < q1 ? p.frame_order[q] : 0;
+                const bool may = q < q1 && frame_may_contain(p, o, f, tr, Asun, n_cand);
+                if (may) ++n_exact;
+                buf_append(buf, nbuf, may, ((unsigned long long)f << 32) | gobj, p.cand, p.n_cand, p.cand_cap);
             }
         } else {
             const int G = p.b_G[b];
-            const int nx = o.hi[0] - o.lo[0] + 1, ny = o.hi[1] - o.lo[1] + 1, nz = o.hi[2] - o.lo[2] + 1;
+            const int ny = o.hi[1] - o.lo[1] + 1, nz = o.hi[2] - o.lo[2] + 1;
             const int64_t base = p.b_koff[b];
-            for (int c = lane; c < o.ncell; c += 64) {
-                const int ix = o.lo[0] + c / (ny * nz);
-                const int iy = o.lo[1] + (c / nz) % ny;
-                const int iz = o.lo[2] + c % nz;
-                (void)nx;
-                const int64_t key = base + (ix * G + iy) * G + iz;
-                const int a0 = p.cell_start[key], a1 = p.cell_start[key + 1];
-                for (int k = a0; k < a1; ++k) {
-                    const int f = p.cell_frames[k];
-                    if (frame_may_contain(p, o, f, tr, Asun, n_cand)) {
-                        ++n_exact;
-                        wave_append(p.cand, p.n_cand, p.cand_cap, ((unsigned long long)f << 32) | gobj);
-                    }
+            for (int c0 = 0; c0 < o.ncell; c0 += 64) {
+                const int c = c0 + lane;
+                int a0 = 0, a1 = 0;
+                if (c < o.ncell) {
+                    const int ix = o.lo[0] + c / (ny * nz);
+                    const int iy = o.lo[1] + (c / nz) % ny;
+                    const int iz = o.lo[2] + c % nz;
+                    const int64_t key = base + (ix * G + iy) * G + iz;
+                    a0 = p.cell_start[key];
+                    a1 = p.cell_start[key + 1];
+                }
+                int len = a1 - a0;
+#pragma unroll
+                for (int off = 32; off >= 1; off >>= 1) len = max(len, __shfl_xor(len, off, 64));
+                for (int t = 0; t < len; ++t) {
+                    const int k = a0 + t;
+                    int f = 0;
+                    const bool may = k < a1 && cell_frame_may_contain(p, o, k, tr, Asun, n_cand, f);
+                    if (may) ++n_exact;
+                    buf_append(buf, nbuf, may, ((unsigned long long)f << 32) | gobj, p.cand, p.n_cand, p.cand_cap);
                 }
             }
         }
     }
+    buf_flush(buf, nbuf, p.cand, p.n_cand, p.cand_cap);
     if (p.stats) {
         unsigned long long a = n_cand, e = n_exact;
 #pragma unroll
@@ -447,7 +650,6 @@ __global__ __launch_bounds__(256) void k_fov_wide(const FovParams p) {
             atomicAdd(p.stats + 0, a);
             atomicAdd(p.stats + 1, e);
             atomicAdd(p.stats + 2, n_over);
-            atomicAdd(p.stats + 3, (unsigned long long)0);
         }
     }
 }
@@ -463,8 +665,13 @@ __global__ void k_obj_keys(const FovParams p, int32_t* __restrict__ okey, int32_
     ObjBounds o;
     const int G = p.b_G[b], G3 = G * G * G;
     int key;
-    if (object_bounds(p, b, j, o) && is_narrow(o)) key = (int)(p.b_koff[b] + cell_of(o.dh, G));
-    else key = (int)(p.b_koff[b] + G3);
+    const bool live = object_bounds(p, b, j, o);
+    if (live && is_narrow(o, G)) {
+        key = (int)(p.b_koff[b] + cell_of(o.dh, G));
+    } else {
+        key = (int)(p.b_koff[b] + G3);
+        if (live) wave_append(p.wide, p.n_wide, p.n_pairs_total, ((unsigned long long)b << 32) | (unsigned long long)j);
+    }
     okey[i] = key;
     atomicAdd(cnt + key, 1);
 }
@@ -641,15 +848,21 @@ hipError_t fill_zero(void* p, size_t bytes, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t fov_candidates(const FovParams& p, int block, hipStream_t s) {
+static int cu_count();
+
+hipError_t fov_candidates(FovParams& p, int32_t* icnt, int32_t* istart, unsigned long long* items,
+                          unsigned int* item_next, void* scan_scratch, hipStream_t s) {
     if (p.n_pairs_total == 0 || p.n_batch == 0) return hipSuccess;
-    dim3 grid((unsigned)((p.n_pairs_total + block - 1) / block));
-    switch (block) {
-        case 64: hipLaunchKernelGGL(k_fov<64>, grid, dim3(64), 0, s, p); break;
-        case 128: hipLaunchKernelGGL(k_fov<128>, grid, dim3(128), 0, s, p); break;
-        case 256: hipLaunchKernelGGL(k_fov<256>, grid, dim3(256), 0, s, p); break;
-        default: return hipErrorInvalidValue;
-    }
+    p.items = items;
+    p.item_start = istart;
+    p.item_next = item_next;
+    const unsigned gk = (unsigned)((p.n_keys + 255) / 256);
+    hipError_t e;
+    hipLaunchKernelGGL(k_item_count, dim3(gk), dim3(256), 0, s, p, icnt);
+    if ((e = exclusive_scan_i32(icnt, istart, p.n_keys, scan_scratch, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_item_scatter, dim3(gk), dim3(256), 0, s, p, (const int32_t*)icnt);
+    if ((e = fill_zero(item_next, sizeof(unsigned int), s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fov_cells, dim3((unsigned)(cu_count() * 2)), dim3(256), 0, s, p);
     return hipGetLastError();
 }
 

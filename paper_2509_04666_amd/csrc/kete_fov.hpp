@@ -27,6 +27,7 @@ struct FovParams {
     double* btab;               // [B][kBatchStride]
     int32_t* cell_start;        // [B G^3 + 1]
     int32_t* cell_frames;       // [F]
+    double* cell_caps;          // [F][8]: frame caps in cell order, slot 5 = frame index
     unsigned long long* pairs;  // [cap] packed (frame << 32 | sub << 25 | obj)
     unsigned long long* n_pairs;
     int64_t cap;
@@ -51,6 +52,11 @@ struct FovParams {
     const int64_t* b_koff;      // [B+1]
     int64_t n_keys;             // b_koff[B]
     const int32_t* obj_sorted;  // [n_pairs_total] local objects of each batch ordered by sky cell
+    const int32_t* obj_start;   // [n_keys + 1] start of each key's objects in obj_sorted
+    const int32_t* obj_count;   // [n_keys] objects per key
+    unsigned long long* items;  // work items of the per-cell join: key << 32 | object chunk
+    const int32_t* item_start;  // [n_keys + 1] exclusive scan of items per key (total at n_keys)
+    unsigned int* item_next;    // work-queue cursor
     unsigned long long* wide;   // [n_pairs_total] (batch << 32 | local obj) of objects with wide motion caps
     unsigned long long* n_wide;
     double mu, smu, c_light, lt_tol;
@@ -63,7 +69,12 @@ hipError_t fov_prepare(const FovParams& p, int32_t* qkey, int32_t* cnt, int32_t*
                        hipStream_t s);
 hipError_t fov_sort_objects(const FovParams& p, int32_t* okey, int32_t* cnt, int32_t* start, int32_t* sorted,
                             void* scan_scratch, hipStream_t s);
-hipError_t fov_candidates(const FovParams& p, int block, hipStream_t s);
+// Candidate generation.  icnt and istart are [n_keys + 1] int32 scratch
+// (istart becomes p.item_start), items holds n_keys + n_pairs_total / 64 + 1
+// entries, scan_scratch >= scan_scratch_bytes(n_keys).
+hipError_t fov_candidates(FovParams& p, int32_t* icnt, int32_t* istart, unsigned long long* items,
+                          unsigned int* item_next, void* scan_scratch, hipStream_t s);
+inline int64_t fov_item_capacity(int64_t n_keys, int64_t n_pairs_total) { return n_keys + n_pairs_total / 64 + 1; }
 hipError_t fov_exact(const FovParams& p, hipStream_t s);
 hipError_t fov_sort(const unsigned long long* keys, int64_t n, int64_t n_frames, int32_t* fcnt, int32_t* fstart,
                     unsigned long long* sorted, void* scan_scratch, int32_t* pf, int32_t* ps, int32_t* po,

@@ -372,7 +372,11 @@ def frames_survey(rng, model, n_frames, t0, span, width_deg=0.78, seq_len=12,
     apart, stepping `step_deg` along the 90-degree-elongation great circle,
     each frame rolled so that its first axis is the scan direction."""
     n_seq = -(-n_frames // seq_len)
-    t_seq = t0 + (np.arange(n_seq) + rng.uniform(0, 1, n_seq)) * (span - 1.0 / 24.0) / n_seq
+    # one telescope: sequences start at jittered times but never overlap,
+    # so the exposure list is chronological
+    gap = (span - 1.0 / 24.0) / n_seq
+    busy = min(1.0, (seq_len - 1) * cadence_s / 86400.0 / gap)
+    t_seq = t0 + (np.arange(n_seq) + rng.uniform(0, 1, n_seq) * (1.0 - busy)) * gap
     j = np.arange(seq_len)
     t = (t_seq[:, None] + j[None, :] * cadence_s / 86400.0).reshape(-1)[:n_frames]
     n = math.sqrt(GM_SUN)
