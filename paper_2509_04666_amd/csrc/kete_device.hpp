@@ -55,6 +55,30 @@ __device__ __forceinline__ void clenshaw(const double* __restrict__ c, int deg1,
     dp = fma(tau, d1, b1 - d2);
 }
 
+// The same two recurrences with the coefficient count fixed at compile
+// time (DEG1 > 0): every coefficient load is issued before the chain
+// starts.  DEG1 = 0 falls back to the runtime loops.
+template <int DEG1>
+__device__ __forceinline__ void clenshaw_n(const double* __restrict__ c, int deg1, double tau, double& p, double& dp) {
+    if constexpr (DEG1 == 0) {
+        clenshaw(c, deg1, tau, p, dp);
+    } else {
+        double cc[DEG1];
+#pragma unroll
+        for (int k = 0; k < DEG1; ++k) cc[k] = c[k];
+        double b1 = 0.0, b2 = 0.0, d1 = 0.0, d2 = 0.0;
+        const double t2 = tau + tau;
+#pragma unroll
+        for (int k = DEG1 - 1; k >= 1; --k) {
+            const double b0 = fma(t2, b1, cc[k] - b2);
+            const double d0 = fma(t2, d1, 2.0 * b1 - d2);
+            b2 = b1; b1 = b0; d2 = d1; d1 = d0;
+        }
+        p = fma(tau, b1, cc[0] - b2);
+        dp = fma(tau, d1, b1 - d2);
+    }
+}
+
 // Clenshaw recurrence for the value only.
 __device__ __forceinline__ double clenshaw_value(const double* __restrict__ c, int deg1, double tau) {
     double b1 = 0.0, b2 = 0.0;
@@ -64,6 +88,25 @@ __device__ __forceinline__ double clenshaw_value(const double* __restrict__ c, i
         b2 = b1; b1 = b0;
     }
     return fma(tau, b1, c[0] - b2);
+}
+
+template <int DEG1>
+__device__ __forceinline__ double clenshaw_value_n(const double* __restrict__ c, int deg1, double tau) {
+    if constexpr (DEG1 == 0) {
+        return clenshaw_value(c, deg1, tau);
+    } else {
+        double cc[DEG1];
+#pragma unroll
+        for (int k = 0; k < DEG1; ++k) cc[k] = c[k];
+        double b1 = 0.0, b2 = 0.0;
+        const double t2 = tau + tau;
+#pragma unroll
+        for (int k = DEG1 - 1; k >= 1; --k) {
+            const double b0 = fma(t2, b1, cc[k] - b2);
+            b2 = b1; b1 = b0;
+        }
+        return fma(tau, b1, cc[0] - b2);
+    }
 }
 
 // Position and velocity of one body from a segment table laid out as

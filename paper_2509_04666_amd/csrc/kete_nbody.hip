@@ -88,7 +88,7 @@ __global__ __launch_bounds__(BLOCK) void k_nbody(const NbodyParams p) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) { fm = fmax(fm, fabs(D[6][c] + F0[c])); bm = fmax(bm, fabs(b6p[c])); }
             const double ebl = fm > 0.0 ? bm / fm : 0.0;
-            double hl = (ebl > 0.0 && ebl < kInf) ? fabs(h) * pow(p.eps / ebl, 1.0 / 7.0) : fabs(h) / p.safety;
+            double hl = (ebl > 0.0 && ebl < kInf) ? fabs(h) * step_factor(p.eps / ebl) : fabs(h) / p.safety;
             if (!active) hl = kInf;
             if (active && hl < p.h_min) { my_status = KETE_ST_STEP_UNDERFLOW; active = false; hl = kInf; }
             const double hn = wave_min(hl);
@@ -156,8 +156,8 @@ __global__ __launch_bounds__(BLOCK) void k_nbody(const NbodyParams p) {
 // 8 objects of a wavefront share the time grid and the perturber table
 // as above; each sweep evaluates the force at all 7 nodes of an object
 // at once.  Output and counters are per object, as in k_nbody.
-template <int BLOCK, int NB, int NGR>
-__global__ __launch_bounds__(BLOCK) void k_nbody_g8(const NbodyParams p) {
+template <int BLOCK, int NB, int NGR, int DEG1>
+__global__ __launch_bounds__(BLOCK, 3) void k_nbody_g8(const NbodyParams p) {
     extern __shared__ double smem[];
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
     const int gl = lane & (kGroup - 1);               // lane within the object's group
@@ -218,7 +218,7 @@ __global__ __launch_bounds__(BLOCK) void k_nbody_g8(const NbodyParams p) {
             const double t_end = landed ? tb : t + h;
             const double hh = h * h;
             const int n0 = haveF0 ? 1 : 0;
-            node_ephemeris8(coefL, bstride, E, rc, W.seg_lo, W.seg_hi, t, h, t_end, n0, lane, e8);
+            node_ephemeris8<DEG1>(coefL, bstride, E, rc, W.seg_lo, W.seg_hi, t, h, t_end, n0, lane, e8);
             c_chain += (kNodes - n0) * E.n_gr * 3;
             c_vchain += (kNodes - n0) * (nb - E.n_gr) * 3;
             if (!haveF0) { accel8<NB, NGR>(e8, E, x0, v0, F0); haveF0 = true; }
@@ -233,7 +233,7 @@ __global__ __launch_bounds__(BLOCK) void k_nbody_g8(const NbodyParams p) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) { fm = fmax(fm, fabs(d6[c] + F0[c])); bm = fmax(bm, fabs(b6p[c])); }
             const double ebl = fm > 0.0 ? bm / fm : 0.0;
-            double hl = (ebl > 0.0 && ebl < kInf) ? fabs(h) * pow(p.eps / ebl, 1.0 / 7.0) : fabs(h) / p.safety;
+            double hl = (ebl > 0.0 && ebl < kInf) ? fabs(h) * step_factor(p.eps / ebl) : fabs(h) / p.safety;
             if (!active) hl = kInf;
             if (active && hl < p.h_min) { my_status = KETE_ST_STEP_UNDERFLOW; active = false; hl = kInf; }
             const double hn = groups_min(hl);
@@ -251,7 +251,7 @@ __global__ __launch_bounds__(BLOCK) void k_nbody_g8(const NbodyParams p) {
                             isfinite(v0[0]) && isfinite(v0[1]) && isfinite(v0[2]))) {
                 my_status = KETE_ST_NONFINITE; active = false;
             }
-            accel8<NB, NGR>(e8 + 8 * g8_row(nb), E, x0, v0, F0);
+            accel8_group(e8 + 8 * g8_row(nb), E, x0, v0, gl, F0);
             if (landed) {
                 hw = fmin(hw, hn);
             } else {
@@ -351,13 +351,14 @@ hipError_t launch_nbody(const NbodyParams& p, int block, int lanes_per_body, hip
         const int grid = (int)((threads + block - 1) / block);
         if (grid == 0) return hipSuccess;
         // perturber tables of the common shapes get an unrolled force loop
-        const int nb = p.eph.n_body, ngr = p.eph.n_gr;
-#define KETE_G8(B)                                                                                        \
-    do {                                                                                                  \
-        if (nb == 9 && ngr == 3) hipLaunchKernelGGL((k_nbody_g8<B, 9, 3>), dim3(grid), dim3(B), lds8, s, p); \
-        else if (nb == 3 && ngr == 2)                                                                     \
-            hipLaunchKernelGGL((k_nbody_g8<B, 3, 2>), dim3(grid), dim3(B), lds8, s, p);                   \
-        else hipLaunchKernelGGL((k_nbody_g8<B, 0, 0>), dim3(grid), dim3(B), lds8, s, p);                  \
+        const int nb = p.eph.n_body, ngr = p.eph.n_gr, d1 = p.eph.deg1;
+#define KETE_G8(B)                                                                                              \
+    do {                                                                                                        \
+        if (nb == 9 && ngr == 3 && d1 == 13)                                                                    \
+            hipLaunchKernelGGL((k_nbody_g8<B, 9, 3, 13>), dim3(grid), dim3(B), lds8, s, p);                     \
+        else if (nb == 3 && ngr == 2 && d1 == 13)                                                               \
+            hipLaunchKernelGGL((k_nbody_g8<B, 3, 2, 13>), dim3(grid), dim3(B), lds8, s, p);                     \
+        else hipLaunchKernelGGL((k_nbody_g8<B, 0, 0, 0>), dim3(grid), dim3(B), lds8, s, p);                     \
     } while (0)
         switch (block) {
             case 64: KETE_G8(64); break;

@@ -287,6 +287,7 @@ __device__ __forceinline__ void g8_table_init(const EphemArgs& E, int lane, doub
 // before the first step; later steps reuse the force at the previous
 // step end).  Chains with a velocity come first so lanes of one pass do
 // equal work.
+template <int DEG1>
 __device__ __forceinline__ void node_ephemeris8(const double* __restrict__ coefL, int bstride, const EphemArgs& E,
                                                 const RadauConst& rc, int seg_lo, int seg_hi, double t, double h,
                                                 double t_end, int n0, int lane, double* __restrict__ e8) {
@@ -306,7 +307,7 @@ __device__ __forceinline__ void node_ephemeris8(const double* __restrict__ coefL
         int k;
         const double tau = tau_of(n, k);
         double pv, dv;
-        clenshaw(coefL + b * bstride + (k - seg_lo) * cps + i * deg1, deg1, tau, pv, dv);
+        clenshaw_n<DEG1>(coefL + b * bstride + (k - seg_lo) * cps + i * deg1, deg1, tau, pv, dv);
         e8[n * g8_row(nb) + sl * kSlot + i] = pv;
         e8[n * g8_row(nb) + sl * kSlot + 4 + i] = dv * 2.0 * E.inv_seg;
     }
@@ -319,7 +320,8 @@ __device__ __forceinline__ void node_ephemeris8(const double* __restrict__ coefL
         const int b = slot_body(E, sl);
         int k;
         const double tau = tau_of(n, k);
-        e8[n * g8_row(nb) + sl * kSlot + i] = clenshaw_value(coefL + b * bstride + (k - seg_lo) * cps + i * deg1, deg1, tau);
+        e8[n * g8_row(nb) + sl * kSlot + i] =
+            clenshaw_value_n<DEG1>(coefL + b * bstride + (k - seg_lo) * cps + i * deg1, deg1, tau);
     }
     wave_lds_sync();
 }
@@ -367,6 +369,51 @@ __device__ __forceinline__ void accel8(const double* __restrict__ e8, const Ephe
         ax = fma(f, rx, ax); ay = fma(f, ry, ay); az = fma(f, rz, az);
     }
     F[0] = ax; F[1] = ay; F[2] = az;
+}
+
+// The same force computed by an 8-lane group together: lane k of the
+// group takes slots k, k + 8, ...; the partial sums are added across the
+// group.  Every lane of the group returns the total.
+__device__ __forceinline__ void accel8_group(const double* __restrict__ e8, const EphemArgs& E, const double X[3],
+                                             const double V[3], int gl, double F[3]) {
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    for (int sl = gl; sl < E.n_body; sl += kGroup) {
+        const double* pb = e8 + kSlot * sl;
+        const double2 pxy = *reinterpret_cast<const double2*>(pb);
+        const double2 pzg = *reinterpret_cast<const double2*>(pb + 2);
+        const double rx = X[0] - pxy.x, ry = X[1] - pxy.y, rz = X[2] - pzg.x;
+        const double r2 = fma(rx, rx, fma(ry, ry, rz * rz));
+        const double ir = rsqrt(r2);
+        const double ir3 = ir * ir * ir;
+        const double gm = pzg.y;
+        double f = -gm * ir3;
+        if (sl < E.n_gr) {
+            const double2 vxy = *reinterpret_cast<const double2*>(pb + 4);
+            const double2 vzk = *reinterpret_cast<const double2*>(pb + 6);
+            const double wx = V[0] - vxy.x, wy = V[1] - vxy.y, wz = V[2] - vzk.x;
+            const double w2 = fma(wx, wx, fma(wy, wy, wz * wz));
+            const double rw = fma(rx, wx, fma(ry, wy, rz * wz));
+            const double g = vzk.y * ir3;
+            f = fma(g, 4.0 * gm * ir - w2, f);
+            const double q = 4.0 * g * rw;
+            ax = fma(q, wx, ax); ay = fma(q, wy, ay); az = fma(q, wz, az);
+        }
+        ax = fma(f, rx, ax); ay = fma(f, ry, ay); az = fma(f, rz, az);
+    }
+#pragma unroll
+    for (int off = 1; off < kGroup; off <<= 1) {
+        ax += __shfl_xor(ax, off, kWave);
+        ay += __shfl_xor(ay, off, kWave);
+        az += __shfl_xor(az, off, kWave);
+    }
+    F[0] = ax; F[1] = ay; F[2] = az;
+}
+
+// Step-size factor (eps / e)^(1/7) of the IAS15 control, in single
+// precision: the factor only sets the next trial step.
+__device__ __forceinline__ double step_factor(double q) {
+    const float qf = (float)fmin(fmax(q, 1e-35), 1e35);
+    return (double)exp2f(log2f(qf) * (1.0f / 7.0f));
 }
 
 // Corrector for a body spread over an 8-lane group (see above), with the
@@ -529,7 +576,7 @@ __device__ __forceinline__ void integrate_window(const Params& p, const Window& 
         double fm = 0.0, bm = 0.0;
         for (int c = 0; c < 3; ++c) { fm = fmax(fm, fabs(D[6][c] + L.F0[c])); bm = fmax(bm, fabs(b6[c])); }
         const double ebl = fm > 0.0 ? bm / fm : 0.0;
-        double hl = (ebl > 0.0 && ebl < kInf) ? fabs(h) * pow(p.eps / ebl, 1.0 / 7.0) : fabs(h) / p.safety;
+        double hl = (ebl > 0.0 && ebl < kInf) ? fabs(h) * step_factor(p.eps / ebl) : fabs(h) / p.safety;
         if (!L.active) hl = kInf;
         if (L.active && hl < p.h_min) { L.status = KETE_ST_STEP_UNDERFLOW; L.active = false; hl = kInf; }
         const double hn = wave_min(hl);
