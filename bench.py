@@ -227,8 +227,8 @@ def batched_component(api, synth, torch, n_jobs, log, reps=2, tune_cache=None):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--objects", type=int, default=100_000)
     ap.add_argument("--frames", type=int, default=500_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -830,12 +830,16 @@ int batch_dims(const kete_ephem_t* eph, const kete_batch_t* bt, int64_t pairs_ca
             return fail(KETE_EINVAL, "job %d out of range", j);
         if (!(J[j].t0 >= tlo && J[j].t0 <= thi)) return fail(KETE_ERANGE, "job %d t0 outside the ephemeris", j);
     }
-    // tiles of 64 bodies
-    for (int j = 0; j < bt->n_jobs; ++j) d.n_tiles += (J[j].n_obj + 63) / 64;
+    // tiles of KETE_BATCH_TILE bodies
+    constexpr int T = KETE_BATCH_TILE;
+    int64_t n_tiles = 0;
+    for (int j = 0; j < bt->n_jobs; ++j) n_tiles += (J[j].n_obj + T - 1) / T;
+    if (n_tiles > INT32_MAX) return fail(KETE_EINVAL, "too many tiles");
+    d.n_tiles = (int32_t)n_tiles;
     if (tables) {
         d.tiles.reserve(d.n_tiles);
         for (int j = 0; j < bt->n_jobs; ++j)
-            for (int t = 0; t < (J[j].n_obj + 63) / 64; ++t) d.tiles.push_back(make_int2(j, t));
+            for (int t = 0; t < (J[j].n_obj + T - 1) / T; ++t) d.tiles.push_back(make_int2(j, t));
     }
     // batches
     if (tables) {

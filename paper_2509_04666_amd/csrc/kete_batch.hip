@@ -69,14 +69,24 @@ __device__ __forceinline__ void ensure_window(const EphemArgs& E, int a, int b, 
     lo = a; hi = b;
 }
 
-__global__ __launch_bounds__(64) void k_batch_nbody(const BatchParams p) {
+// One wavefront per block; it pops tiles of 8 bodies of one job and
+// integrates them as 8-lane groups (one lane per collocation node)
+// through the job's epochs.
+template <int NB, int NGR, int DEG1>
+__global__ __launch_bounds__(64, 3) void k_batch_g8(const BatchParams p) {
     extern __shared__ double smem[];
     const int lane = threadIdx.x;
+    const int gl = lane & (kGroup - 1);
+    const int node = gl < 7 ? gl + 1 : 7;
     const EphemArgs& E = p.eph;
     const int bstride = p.max_win_segs * 3 * E.deg1;
     double* coefL = smem;
-    double* ephW = smem + (size_t)E.n_body * bstride;
+    double* e8 = smem + (((size_t)E.n_body * bstride + 1) & ~(size_t)1);
+    g8_table_init(E, lane, e8);
+    NodeRow R;
+    load_node_row(p.rc, node, R);
     const int W = p.max_win_segs - 1;            // segment lengths per window
+    int lo = 1, hi = 0;                          // nothing staged yet
     for (;;) {
         int tile = 0;
         if (lane == 0) tile = (int)atomicAdd(p.tile_counter, 1u);
@@ -84,58 +94,52 @@ __global__ __launch_bounds__(64) void k_batch_nbody(const BatchParams p) {
         if (tile >= p.n_tiles) break;
         const int2 tj = p.tiles[tile];
         const kete_job_t job = p.jobs[tj.x];
-        const int64_t k = (int64_t)tj.y * 64 + lane;
+        const int64_t k = (int64_t)tj.y * kGroup + lane / kGroup;
         const bool valid = k < job.n_obj;
         const int64_t local = valid ? (p.n_buckets > 1 ? p.perm[job.obj_off + k] : k) : 0;
         const int64_t gobj = job.obj_off + local;
-        Lane L;
-        L.status = 0;
-        L.active = valid;
+        G8State S;
+        S.status = 0;
+        S.active = valid;
         for (int i = 0; i < 3; ++i) {
-            L.x0[i] = valid ? p.x0[6 * gobj + i] : (i == 0 ? 1.0 : 0.0);
-            L.v0[i] = valid ? p.x0[6 * gobj + 3 + i] : 0.0;
-            L.F0[i] = 0.0;
+            S.x0[i] = valid ? p.x0[6 * gobj + i] : (i == 0 ? 1.0 : 0.0);
+            S.v0[i] = valid ? p.x0[6 * gobj + 3 + i] : 0.0;
+            S.F0[i] = 0.0;
         }
         double hp = kInf;
         if (valid) {
-            const double r = sqrt(dot3(L.x0, L.x0));
+            const double r = sqrt(dot3(S.x0, S.x0));
             hp = 0.05 * sqrt(r * r * r / E.gm[0]);
         }
-        double hw = wave_min(L.active ? hp : kInf);
-        if (!(hw < kInf)) hw = p.h_init;
-        double t = job.t0;
-        bool haveF0 = false;
-        long wsteps = 0;
-        int lo = 1, hi = 0;                       // nothing staged yet
+        S.hw = groups_min(S.active ? hp : kInf);
+        if (!(S.hw < kInf)) S.hw = p.h_init;
+        S.hp_new = kInf;
+        S.t = job.t0;
+        S.haveF0 = false;
+        G8Count C;
         for (int e = 0; e < job.n_epoch; ++e) {
             const double target = p.epochs[job.epoch_off + e];
-            while (t != target) {
-                Window Wn = next_window(t, target, E.t_start, E.seg_days, E.inv_seg, E.n_seg, W);
+            while (S.t != target) {
+                const Window Wn = next_window(S.t, target, E.t_start, E.seg_days, E.inv_seg, E.n_seg, W);
                 ensure_window(E, Wn.seg_lo, Wn.seg_hi, lo, hi, coefL, bstride);
-                Wn.seg_lo = lo;
-                Wn.seg_hi = hi;
-                integrate_window(p, Wn, coefL, bstride, ephW, L, t, hw, haveF0, wsteps,
-                                 [](double, double, const double (*)[3], const double*) {});
-                t = Wn.t_b;
+                g8_integrate<NB, NGR, DEG1>(p, R, node, gl, lane, coefL, bstride, e8, lo, hi, Wn.t_b, S, C);
+                S.t = Wn.t_b;
             }
-            if (valid) {
+            if (valid && gl < 6) {
                 double* dst = p.x_out + job.xout_off + ((int64_t)e * job.n_obj + local) * 6;
-                const bool ok = L.active && L.status == 0;
-                for (int i = 0; i < 3; ++i) {
-                    dst[i] = ok ? L.x0[i] : __builtin_nan("");
-                    dst[3 + i] = ok ? L.v0[i] : __builtin_nan("");
-                }
+                const bool ok = S.active && S.status == 0;
+                dst[gl] = ok ? state_component(S.x0, S.v0, gl) : __builtin_nan("");
             }
         }
-        if (valid) p.status[gobj] = L.status;
+        if (valid && gl == 0) p.status[gobj] = S.status;
     }
 }
 
 }  // namespace
 
 size_t batch_lds_bytes(const BatchParams& p) {
-    return ((size_t)p.eph.n_body * p.max_win_segs * 3 * p.eph.deg1 + (size_t)kNodes * p.eph.n_body * 6) *
-           sizeof(double);
+    return ((((size_t)p.eph.n_body * p.max_win_segs * 3 * p.eph.deg1 + 1) & ~(size_t)1) +
+            (size_t)kNodes * g8_row(p.eph.n_body)) * sizeof(double);
 }
 
 hipError_t launch_batch(const BatchParams& p, int waves_per_cu, hipStream_t s) {
@@ -146,7 +150,12 @@ hipError_t launch_batch(const BatchParams& p, int waves_per_cu, hipStream_t s) {
     if (p.n_jobs > 0 && p.n_buckets > 1)
         hipLaunchKernelGGL(k_job_bucket, dim3((unsigned)p.n_jobs), dim3(256), 0, s, p);
     const int grid = std::max(1, std::min(ncu * waves_per_cu, p.n_tiles));
-    hipLaunchKernelGGL(k_batch_nbody, dim3(grid), dim3(64), batch_lds_bytes(p), s, p);
+    const size_t lds = batch_lds_bytes(p);
+    const int nb = p.eph.n_body, ngr = p.eph.n_gr, d1 = p.eph.deg1;
+    if (nb == 9 && ngr == 3 && d1 == 13) hipLaunchKernelGGL((k_batch_g8<9, 3, 13>), dim3(grid), dim3(64), lds, s, p);
+    else if (nb == 3 && ngr == 2 && d1 == 13)
+        hipLaunchKernelGGL((k_batch_g8<3, 2, 13>), dim3(grid), dim3(64), lds, s, p);
+    else hipLaunchKernelGGL((k_batch_g8<0, 0, 0>), dim3(grid), dim3(64), lds, s, p);
     return hipGetLastError();
 }
 

@@ -5,6 +5,9 @@
 #include "kete_fov.hpp"
 #include "kete_internal.hpp"
 
+// bodies per tile of the persistent kernel (one 8-lane group each)
+#define KETE_BATCH_TILE 8
+
 namespace kete {
 
 struct BatchParams {
@@ -13,7 +16,7 @@ struct BatchParams {
     const kete_job_t* jobs;     // [n_jobs]
     int32_t n_jobs;
     int32_t n_tiles;
-    const int2* tiles;          // [n_tiles] (job, tile of 64 bodies), longest first
+    const int2* tiles;          // [n_tiles] (job, tile of 8 bodies), longest first
     unsigned int* tile_counter;
     const double* x0;           // [bodies][6]
     const double* epochs;       // concatenated epochs of all jobs

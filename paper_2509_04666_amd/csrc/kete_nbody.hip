@@ -177,104 +177,45 @@ __global__ __launch_bounds__(BLOCK, 3) void k_nbody_g8(const NbodyParams p) {
     const long gi = ((long)blockIdx.x * BLOCK + tid) / kGroup;
     const bool valid = gi < p.n_obj;
     const int j = valid ? (p.perm ? p.perm[gi] : (int)gi) : 0;
-    bool active = valid && p.status[j] == 0;
-    int my_status = valid ? p.status[j] : 0;
-
-    double x0[3] = {1.0, 0.0, 0.0}, v0[3] = {0.0, 0.0, 0.0};
+    G8State S;
+    S.active = valid && p.status[j] == 0;
+    S.status = valid ? p.status[j] : 0;
+    S.x0[0] = 1.0; S.x0[1] = S.x0[2] = 0.0;
+    S.v0[0] = S.v0[1] = S.v0[2] = 0.0;
+    S.F0[0] = S.F0[1] = S.F0[2] = 0.0;
     double hin = kInf;
     if (valid) {
 #pragma unroll
-        for (int i = 0; i < 3; ++i) { x0[i] = p.state[6 * j + i]; v0[i] = p.state[6 * j + 3 + i]; }
+        for (int i = 0; i < 3; ++i) { S.x0[i] = p.state[6 * j + i]; S.v0[i] = p.state[6 * j + 3 + i]; }
         hin = p.h_pref[j];
     }
-    double hw = groups_min(active ? hin : kInf);
-    if (!(hw < kInf)) hw = p.h_init;
-    double hp_new = kInf;
-
-    unsigned long long c_steps = 0, c_iter = 0, c_rej = 0, c_lsteps = 0, c_liter = 0, c_chain = 0, c_vchain = 0;
-    double t = p.win[0].t_a;
-    double F0[3] = {0.0, 0.0, 0.0};
-    bool haveF0 = false;
+    S.hw = groups_min(S.active ? hin : kInf);
+    if (!(S.hw < kInf)) S.hw = p.h_init;
+    S.hp_new = kInf;
+    S.t = p.win[0].t_a;
+    S.haveF0 = false;
+    G8Count C;
 
     for (int w = 0; w < p.n_win; ++w) {
         const Window W = p.win[w];
         __syncthreads();
         stage_window(E, W.seg_lo, W.seg_hi, bstride, tid, BLOCK, coefL);
         __syncthreads();
-        const double tb = W.t_b;
-        if (__ballot(active) == 0ull) t = tb;
-        while (t != tb) {
-            const double dir = tb > t ? 1.0 : -1.0;
-            double hmag = hw;
-            if (p.h_max > 0.0 && hmag > p.h_max) hmag = p.h_max;
-            double h = dir * hmag;
-            bool landed = false;
-            if (fabs(h) >= fabs(tb - t)) { h = tb - t; landed = true; }
-            if ((long)c_steps >= p.max_steps) {
-                if (active) { my_status = KETE_ST_MAX_STEPS; active = false; }
-                t = tb;
-                break;
-            }
-            const double t_end = landed ? tb : t + h;
-            const double hh = h * h;
-            const int n0 = haveF0 ? 1 : 0;
-            node_ephemeris8<DEG1>(coefL, bstride, E, rc, W.seg_lo, W.seg_hi, t, h, t_end, n0, lane, e8);
-            c_chain += (kNodes - n0) * E.n_gr * 3;
-            c_vchain += (kNodes - n0) * (nb - E.n_gr) * 3;
-            if (!haveF0) { accel8<NB, NGR>(e8, E, x0, v0, F0); haveF0 = true; }
-
-            double dn[3], b6p[3], d6[3];
-            const int it = corrector_g8<NB, NGR>(rc, E, e8, R, node, x0, v0, F0, h, active, p.max_iter, dn, b6p, d6);
-            c_iter += it;
-            const unsigned long long n_act = __popcll(__ballot(active)) / kGroup;
-            c_liter += (unsigned long long)it * n_act;
-
-            double fm = 0.0, bm = 0.0;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) { fm = fmax(fm, fabs(d6[c] + F0[c])); bm = fmax(bm, fabs(b6p[c])); }
-            const double ebl = fm > 0.0 ? bm / fm : 0.0;
-            double hl = (ebl > 0.0 && ebl < kInf) ? fabs(h) * step_factor(p.eps / ebl) : fabs(h) / p.safety;
-            if (!active) hl = kInf;
-            if (active && hl < p.h_min) { my_status = KETE_ST_STEP_UNDERFLOW; active = false; hl = kInf; }
-            const double hn = groups_min(hl);
-            if (!(hn < kInf)) { t = tb; break; }
-            if (hn < p.safety * fabs(h)) {
-                hw = hn;
-                ++c_rej;
-                continue;
-            }
-            step_end_g8(rc, dn, h, x0, v0, F0);
-            t = t_end;
-            ++c_steps;
-            c_lsteps += n_act;
-            if (active && !(isfinite(x0[0]) && isfinite(x0[1]) && isfinite(x0[2]) &&
-                            isfinite(v0[0]) && isfinite(v0[1]) && isfinite(v0[2]))) {
-                my_status = KETE_ST_NONFINITE; active = false;
-            }
-            accel8_group(e8 + 8 * g8_row(nb), E, x0, v0, gl, F0);
-            if (landed) {
-                hw = fmin(hw, hn);
-            } else {
-                hw = fmin(hn, fabs(h) / p.safety);
-                hp_new = fmin(hp_new, fmin(hl, fabs(h) / p.safety));
-            }
-        }
+        g8_integrate<NB, NGR, DEG1>(p, R, node, gl, lane, coefL, bstride, e8, W.seg_lo, W.seg_hi, W.t_b, S, C);
         if (W.out >= 0 && valid && gl < 6) {
             // lane gl of the group writes component gl of the state
             double* dst = p.x_out + ((size_t)W.out * p.n_obj + j) * 6;
-            const bool ok = active && my_status == 0;
-            double v = gl == 0 ? x0[0] : gl == 1 ? x0[1] : gl == 2 ? x0[2] : gl == 3 ? v0[0] : gl == 4 ? v0[1] : v0[2];
-            dst[gl] = ok ? v : __builtin_nan("");
+            const bool ok = S.active && S.status == 0;
+            dst[gl] = ok ? state_component(S.x0, S.v0, gl) : __builtin_nan("");
         }
     }
-    if (valid && gl < 6) {
-        const double v = gl == 0 ? x0[0] : gl == 1 ? x0[1] : gl == 2 ? x0[2] : gl == 3 ? v0[0] : gl == 4 ? v0[1] : v0[2];
-        p.state[6 * j + gl] = v;
-    }
+    if (valid && gl < 6) p.state[6 * j + gl] = state_component(S.x0, S.v0, gl);
     if (valid && gl == 0) {
-        if (hp_new < kInf) p.h_pref[j] = hp_new;
-        p.status[j] = my_status;
+        if (S.hp_new < kInf) p.h_pref[j] = S.hp_new;
+        p.status[j] = S.status;
     }
+    const unsigned long long c_steps = C.steps, c_iter = C.iter, c_rej = C.rej, c_lsteps = C.lsteps,
+                             c_liter = C.liter, c_chain = C.chain, c_vchain = C.vchain;
     if (p.stats && lane == 0 && __ballot(valid) != 0ull) {
         atomicAdd(p.stats + 0, c_steps);
         atomicAdd(p.stats + 1, c_iter);

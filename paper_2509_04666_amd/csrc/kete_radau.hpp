@@ -507,6 +507,91 @@ __device__ __forceinline__ void step_end_g8(const RadauConst& rc, const double d
     }
 }
 
+// Stepping state of a group-integrated body (replicated in its 8 lanes).
+struct G8State {
+    double x0[3], v0[3], F0[3];
+    double t, hw, hp_new;
+    bool active, haveF0;
+    int status;
+};
+struct G8Count {
+    unsigned long long steps = 0, iter = 0, rej = 0, lsteps = 0, liter = 0, chain = 0, vchain = 0;
+};
+
+// Integrate one window [S.t, tb] whose Chebyshev segments seg_lo..seg_hi
+// are staged at coefL, with wave-shared adaptive steps (the 8 bodies of
+// the wavefront take the smallest step any of them asks for).
+template <int NB, int NGR, int DEG1, class Params>
+__device__ __forceinline__ void g8_integrate(const Params& p, const NodeRow& R, int node, int gl, int lane,
+                                             const double* __restrict__ coefL, int bstride, double* __restrict__ e8,
+                                             int seg_lo, int seg_hi, double tb, G8State& S, G8Count& C) {
+    const EphemArgs& E = p.eph;
+    const RadauConst& rc = p.rc;
+    const int nb = E.n_body;
+    if (__ballot(S.active) == 0ull) { S.t = tb; return; }
+    while (S.t != tb) {
+        const double dir = tb > S.t ? 1.0 : -1.0;
+        double hmag = S.hw;
+        if (p.h_max > 0.0 && hmag > p.h_max) hmag = p.h_max;
+        double h = dir * hmag;
+        bool landed = false;
+        if (fabs(h) >= fabs(tb - S.t)) { h = tb - S.t; landed = true; }
+        if ((long)C.steps >= p.max_steps) {
+            if (S.active) { S.status = KETE_ST_MAX_STEPS; S.active = false; }
+            S.t = tb;
+            return;
+        }
+        const double t_end = landed ? tb : S.t + h;
+        const int n0 = S.haveF0 ? 1 : 0;
+        node_ephemeris8<DEG1>(coefL, bstride, E, rc, seg_lo, seg_hi, S.t, h, t_end, n0, lane, e8);
+        C.chain += (kNodes - n0) * E.n_gr * 3;
+        C.vchain += (kNodes - n0) * (nb - E.n_gr) * 3;
+        if (!S.haveF0) { accel8<NB, NGR>(e8, E, S.x0, S.v0, S.F0); S.haveF0 = true; }
+
+        double dn[3], b6p[3], d6[3];
+        const int it = corrector_g8<NB, NGR>(rc, E, e8, R, node, S.x0, S.v0, S.F0, h, S.active, p.max_iter, dn,
+                                             b6p, d6);
+        C.iter += it;
+        const unsigned long long n_act = __popcll(__ballot(S.active)) / kGroup;
+        C.liter += (unsigned long long)it * n_act;
+
+        double fm = 0.0, bm = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) { fm = fmax(fm, fabs(d6[c] + S.F0[c])); bm = fmax(bm, fabs(b6p[c])); }
+        const double ebl = fm > 0.0 ? bm / fm : 0.0;
+        double hl = (ebl > 0.0 && ebl < kInf) ? fabs(h) * step_factor(p.eps / ebl) : fabs(h) / p.safety;
+        if (!S.active) hl = kInf;
+        if (S.active && hl < p.h_min) { S.status = KETE_ST_STEP_UNDERFLOW; S.active = false; hl = kInf; }
+        const double hn = groups_min(hl);
+        if (!(hn < kInf)) { S.t = tb; return; }
+        if (hn < p.safety * fabs(h)) {       // reject and retry from the same state
+            S.hw = hn;
+            ++C.rej;
+            continue;
+        }
+        step_end_g8(rc, dn, h, S.x0, S.v0, S.F0);
+        S.t = t_end;
+        ++C.steps;
+        C.lsteps += n_act;
+        if (S.active && !(isfinite(S.x0[0]) && isfinite(S.x0[1]) && isfinite(S.x0[2]) && isfinite(S.v0[0]) &&
+                          isfinite(S.v0[1]) && isfinite(S.v0[2]))) {
+            S.status = KETE_ST_NONFINITE; S.active = false;
+        }
+        accel8_group(e8 + 8 * g8_row(nb), E, S.x0, S.v0, gl, S.F0);
+        if (landed) {
+            S.hw = fmin(S.hw, hn);
+        } else {
+            S.hw = fmin(hn, fabs(h) / p.safety);
+            S.hp_new = fmin(S.hp_new, fmin(hl, fabs(h) / p.safety));
+        }
+    }
+}
+
+// Component gl (0..5) of a state.
+__device__ __forceinline__ double state_component(const double x0[3], const double v0[3], int gl) {
+    return gl == 0 ? x0[0] : gl == 1 ? x0[1] : gl == 2 ? x0[2] : gl == 3 ? v0[0] : gl == 4 ? v0[1] : v0[2];
+}
+
 // Collocation polynomial at fraction sig of the step (sig = 1: step end),
 // from the monomial weights alpha_m(sig) = sum_k Ap[m][k] sig^(k+2) and
 // beta_m(sig) = sum_k Bp[m][k] sig^(k+1) (m = 1..7, k = 0..7).
