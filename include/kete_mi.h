@@ -229,10 +229,12 @@ size_t kete_fov_workspace_size(int64_t n_obj, int64_t n_frames, int64_t n_batch,
  *   frame_order device [n_frames]
  *   pf, ps, po  device [pairs_cap]: frame, sub-frame, object of each pair,
  *               sorted by (frame, sub-frame, object)
- *   n_pairs     host out: number of pairs (also when it exceeds pairs_cap)
- * Synchronizes `stream` once to read the pair count.  Returns
- * KETE_ECAPACITY (with *n_pairs set, outputs unspecified) when
- * pairs_cap is too small. */
+ *   n_pairs     host out: number of pairs
+ * The workspace holds up to max(16 n_frames, 2 pairs_cap) exact-test
+ * candidates.  Synchronizes `stream` once to read the counts.  Returns
+ * KETE_ECAPACITY (outputs unspecified) when the pairs or the candidates
+ * do not fit; *n_pairs then holds a pairs_cap to retry with, large
+ * enough for both as far as they were counted. */
 int kete_fov_check(const kete_ephem_t *eph, const double *x_epoch, const int32_t *status,
                    int64_t n_obj, int64_t n_batch, const double *t_ref, const int32_t *batch_off,
                    const int32_t *frame_order, const kete_frames_t *frames, const kete_opts_t *opts,

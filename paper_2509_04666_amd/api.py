@@ -140,7 +140,7 @@ def fov_check(eph: DeviceEphemeris, x_epoch: torch.Tensor, batches: Batches, fra
     F, S = frames.t.shape[0], frames.normals.shape[1]
     cap = int(pairs_cap) if pairs_cap is not None else max(1 << 16, 4 * F)
     fc = frames.c()
-    for attempt in range(2):
+    for attempt in range(3):
         need = lib().kete_fov_workspace_size(N, F, B, S, cap, C.byref(opts))
         if need == 0:
             check(_lib.KETE_EINVAL)
@@ -153,8 +153,9 @@ def fov_check(eph: DeviceEphemeris, x_epoch: torch.Tensor, batches: Batches, fra
                                   _ptr(batches.batch_off), _ptr(batches.frame_order), C.byref(fc), C.byref(opts),
                                   _ptr(pf), _ptr(ps), _ptr(po), cap, C.byref(n_pairs), _ptr(ws), ws.numel(),
                                   _stream())
-        if rc == _lib.KETE_ECAPACITY and pairs_cap is None and attempt == 0:
+        if rc == _lib.KETE_ECAPACITY and pairs_cap is None and attempt < 2:
             cap = int(n_pairs.value)
+            ws = None
             continue
         check(rc)
         break

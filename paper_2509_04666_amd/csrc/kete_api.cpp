@@ -462,7 +462,13 @@ int kete_propagate_nbody(const kete_ephem_t* eph, const double* x0, double t0, i
 
 // Exact-test candidates kept between the two FoV kernels.
 static int64_t cand_capacity(int64_t n_frames, int64_t pairs_cap) {
-    return std::max<int64_t>(1 << 16, std::max<int64_t>(16 * n_frames, 8 * pairs_cap));
+    return std::max<int64_t>(1 << 16, std::max<int64_t>(16 * n_frames, 2 * pairs_cap));
+}
+
+// pairs_cap to retry with after a capacity failure: room for the pairs
+// found and, with one pair per candidate, for every counted candidate.
+static int64_t retry_pairs_cap(int64_t pairs, int64_t cands, int64_t pairs_cap) {
+    return std::max<int64_t>(std::max<int64_t>(pairs, cands), pairs_cap + 1);
 }
 
 static int grid_dims(const kete_opts_t* o, int64_t n_batch, int& G, double& L) {
@@ -634,10 +640,11 @@ int kete_fov_check(const kete_ephem_t* eph, const double* x_epoch, const int32_t
     for (int i = 0; i < 4; ++i) g_fov_stats[i] = host_counters[1 + i];
     const int64_t np = (int64_t)host_counters[0];
     *n_pairs = np;
-    if ((int64_t)host_counters[5] > P.cand_cap)
-        return fail(KETE_ECAPACITY, "%llu exact-test candidates exceed the workspace capacity %lld",
-                    host_counters[5], (long long)P.cand_cap);
-    if (np > pairs_cap) return fail(KETE_ECAPACITY, "%lld pairs exceed pairs_cap %lld", (long long)np, (long long)pairs_cap);
+    if ((int64_t)host_counters[5] > P.cand_cap || np > pairs_cap) {
+        *n_pairs = retry_pairs_cap(np, (int64_t)host_counters[5], pairs_cap);
+        return fail(KETE_ECAPACITY, "%lld pairs / %llu exact-test candidates exceed pairs_cap %lld / %lld",
+                    (long long)np, host_counters[5], (long long)pairs_cap, (long long)P.cand_cap);
+    }
     HIPCHK(fov_sort(P.pairs, np, F, fcnt, fstart, sorted, scan_scratch, pf, ps, po, s));
     return KETE_OK;
 }
@@ -1099,9 +1106,11 @@ int kete_batch_pairs(const kete_batch_t* batch, int64_t pairs_cap, const kete_op
     for (int i = 0; i < 4; ++i) g_fov_stats[i] = hc[1 + i];
     const int64_t np = (int64_t)hc[0];
     *n_pairs = np;
-    if ((int64_t)hc[5] > d.cand_cap)
-        return fail(KETE_ECAPACITY, "%llu exact-test candidates exceed the workspace capacity", hc[5]);
-    if (np > pairs_cap) return fail(KETE_ECAPACITY, "%lld pairs exceed pairs_cap", (long long)np);
+    if ((int64_t)hc[5] > d.cand_cap || np > pairs_cap) {
+        *n_pairs = retry_pairs_cap(np, (int64_t)hc[5], pairs_cap);
+        return fail(KETE_ECAPACITY, "%lld pairs / %llu exact-test candidates exceed pairs_cap %lld / %lld",
+                    (long long)np, hc[5], (long long)pairs_cap, (long long)d.cand_cap);
+    }
     if (np > 0 && (!pf || !ps || !po)) return fail(KETE_EINVAL, "null output pointer");
     HIPCHK(fov_sort(w.P.pairs, np, d.F, w.fcnt, w.fstart, w.sorted, w.scan_scratch, pf, ps, po, s));
     return KETE_OK;

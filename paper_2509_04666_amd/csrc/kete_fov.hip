@@ -150,6 +150,13 @@ __global__ __launch_bounds__(256) void k_batch_prep(const FovParams p) {
         o[14] = as * (1.0 + 1e-9) + 1e-15;
         o[15] = (double)lo;
         o[16] = (double)hi;
+        // Large frames: coarsen the grid so that a frame plus a typical
+        // motion cap (1.5 deg) fits in one cell, keeping most objects on
+        // the per-cell join.
+        const double Rm = atan2(o[12], cR) + 1.5 * (3.14159265358979323846 / 180.0);
+        const double L = 1.2 * 2.0 * sin(0.5 * fmin(Rm, 3.0));
+        const int G = L > 0.0 ? (int)floor(2.0 / L) : 1;
+        if (G < p.b_G[b]) p.b_G[b] = G < 1 ? 1 : G;
     }
 }
 
@@ -731,24 +738,95 @@ __global__ void k_pair_scatter(const unsigned long long* __restrict__ keys, int6
     out[fstart[f] + atomicAdd(fcur + f, 1)] = k;
 }
 
-// Each frame's pairs are few: insertion sort per frame, then unpack.
-__global__ void k_pair_segsort(unsigned long long* __restrict__ keys, const int32_t* __restrict__ fstart,
-                               int64_t n_frames, int32_t* __restrict__ pf, int32_t* __restrict__ ps,
-                               int32_t* __restrict__ po) {
+__device__ __forceinline__ void unpack_pair(unsigned long long k, int i, int32_t* __restrict__ pf,
+                                            int32_t* __restrict__ ps, int32_t* __restrict__ po) {
+    pf[i] = (int32_t)(k >> 32);
+    ps[i] = (int32_t)((k >> 25) & 0x7f);
+    po[i] = (int32_t)(k & 0x1ffffff);
+}
+
+// Ordering inside each frame's segment of the pair keys (keys are unique),
+// by segment size: up to kSortSmall by one thread (insertion sort), up to
+// kSortLds by a block in LDS (bitonic network), larger ones by a block
+// with bottom-up merge passes through global memory (merge-path
+// partitions), ping-ponging with `tmp` at the same offsets.
+constexpr int kSortSmall = 32;
+constexpr int kSortLds = 4096;
+
+__global__ void k_pair_sort_small(unsigned long long* __restrict__ keys, const int32_t* __restrict__ fstart,
+                                  int64_t n_frames, int32_t* __restrict__ pf, int32_t* __restrict__ ps,
+                                  int32_t* __restrict__ po) {
     const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= n_frames) return;
     const int a = fstart[f], e = fstart[f + 1];
+    if (e - a > kSortSmall) return;
     for (int i = a + 1; i < e; ++i) {
         const unsigned long long k = keys[i];
         int j = i - 1;
         while (j >= a && keys[j] > k) { keys[j + 1] = keys[j]; --j; }
         keys[j + 1] = k;
     }
-    for (int i = a; i < e; ++i) {
-        const unsigned long long k = keys[i];
-        pf[i] = (int32_t)(k >> 32);
-        ps[i] = (int32_t)((k >> 25) & 0x7f);
-        po[i] = (int32_t)(k & 0x1ffffff);
+    for (int i = a; i < e; ++i) unpack_pair(keys[i], i, pf, ps, po);
+}
+
+__global__ __launch_bounds__(256) void k_pair_sort_lds(const unsigned long long* __restrict__ keys,
+                                                      const int32_t* __restrict__ fstart, int64_t n_frames,
+                                                      int32_t* __restrict__ pf, int32_t* __restrict__ ps,
+                                                      int32_t* __restrict__ po) {
+    __shared__ unsigned long long sh[kSortLds];
+    for (int64_t f = blockIdx.x; f < n_frames; f += gridDim.x) {
+        const int a = fstart[f], n = fstart[f + 1] - a;
+        if (n <= kSortSmall || n > kSortLds) continue;
+        int P = 1;
+        while (P < n) P <<= 1;
+        for (int i = threadIdx.x; i < P; i += blockDim.x) sh[i] = i < n ? keys[a + i] : ~0ull;
+        __syncthreads();
+        for (int k = 2; k <= P; k <<= 1)
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int i = threadIdx.x; i < P; i += blockDim.x) {
+                    const int l = i ^ j;
+                    if (l > i) {
+                        const unsigned long long x = sh[i], y = sh[l];
+                        const bool up = (i & k) == 0;
+                        if ((x > y) == up) { sh[i] = y; sh[l] = x; }
+                    }
+                }
+                __syncthreads();
+            }
+        for (int i = threadIdx.x; i < n; i += blockDim.x) unpack_pair(sh[i], a + i, pf, ps, po);
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_pair_sort_large(unsigned long long* __restrict__ keys,
+                                                        unsigned long long* __restrict__ tmp,
+                                                        const int32_t* __restrict__ fstart, int64_t n_frames,
+                                                        int32_t* __restrict__ pf, int32_t* __restrict__ ps,
+                                                        int32_t* __restrict__ po) {
+    for (int64_t f = blockIdx.x; f < n_frames; f += gridDim.x) {
+        const int a = fstart[f], n = fstart[f + 1] - a;
+        if (n <= kSortLds) continue;
+        unsigned long long* src = keys + a;
+        unsigned long long* dst = tmp + a;
+        for (int w = 1; w < n; w <<= 1) {
+            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                const int p0 = (i / (2 * w)) * (2 * w);
+                const int a1 = min(p0 + w, n), b1 = min(p0 + 2 * w, n);
+                const int m = a1 - p0, m2 = b1 - a1, k = i - p0;
+                int lo = max(0, k - m2), hi = min(k, m);
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (src[p0 + mid] < src[a1 + k - mid - 1]) lo = mid + 1; else hi = mid;
+                }
+                const unsigned long long va = lo < m ? src[p0 + lo] : ~0ull;
+                const unsigned long long vb = k - lo < m2 ? src[a1 + k - lo] : ~0ull;
+                dst[i] = va < vb ? va : vb;
+            }
+            __syncthreads();
+            unsigned long long* t = src; src = dst; dst = t;
+        }
+        for (int i = threadIdx.x; i < n; i += blockDim.x) unpack_pair(src[i], a + i, pf, ps, po);
+        __syncthreads();
     }
 }
 
@@ -878,9 +956,10 @@ hipError_t fov_exact(const FovParams& p, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t fov_sort(const unsigned long long* keys, int64_t n, int64_t n_frames, int32_t* fcnt, int32_t* fstart,
+hipError_t fov_sort(unsigned long long* keys, int64_t n, int64_t n_frames, int32_t* fcnt, int32_t* fstart,
                     unsigned long long* sorted, void* scan_scratch, int32_t* pf, int32_t* ps, int32_t* po,
                     hipStream_t s) {
+    unsigned long long* tmp = keys;            // free once the keys are scattered by frame
     hipError_t e;
     if ((e = fill_zero(fcnt, (size_t)(n_frames + 1) * sizeof(int32_t), s)) != hipSuccess) return e;
     if (n > 0) hipLaunchKernelGGL(k_pair_hist, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, keys, n, fcnt);
@@ -888,9 +967,15 @@ hipError_t fov_sort(const unsigned long long* keys, int64_t n, int64_t n_frames,
     if ((e = fill_zero(fcnt, (size_t)n_frames * sizeof(int32_t), s)) != hipSuccess) return e;
     if (n > 0) hipLaunchKernelGGL(k_pair_scatter, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, keys, n,
                                   (const int32_t*)fstart, fcnt, sorted);
-    if (n_frames > 0)
-        hipLaunchKernelGGL(k_pair_segsort, dim3((unsigned)((n_frames + 255) / 256)), dim3(256), 0, s, sorted,
+    if (n_frames > 0) {
+        const unsigned gb = (unsigned)std::min<int64_t>(n_frames, (int64_t)cu_count() * 16);
+        hipLaunchKernelGGL(k_pair_sort_small, dim3((unsigned)((n_frames + 255) / 256)), dim3(256), 0, s, sorted,
                            (const int32_t*)fstart, n_frames, pf, ps, po);
+        hipLaunchKernelGGL(k_pair_sort_lds, dim3(gb), dim3(256), 0, s, (const unsigned long long*)sorted,
+                           (const int32_t*)fstart, n_frames, pf, ps, po);
+        hipLaunchKernelGGL(k_pair_sort_large, dim3(gb), dim3(256), 0, s, sorted, tmp, (const int32_t*)fstart,
+                           n_frames, pf, ps, po);
+    }
     return hipGetLastError();
 }
 

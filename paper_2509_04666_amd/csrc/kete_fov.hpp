@@ -48,7 +48,7 @@ struct FovParams {
     // Sky grid of batch b: G_b cells per axis over [-1, 1]^3 (G_b = 1 puts
     // every frame in one cell); its keys start at b_koff[b] and number
     // G_b^3 + 1 (the last one collects objects with wide motion caps).
-    const int32_t* b_G;         // [B]
+    int32_t* b_G;               // [B] sky-grid size per batch (lowered for large frames)
     const int64_t* b_koff;      // [B+1]
     int64_t n_keys;             // b_koff[B]
     const int32_t* obj_sorted;  // [n_pairs_total] local objects of each batch ordered by sky cell
@@ -76,7 +76,7 @@ hipError_t fov_candidates(FovParams& p, int32_t* icnt, int32_t* istart, unsigned
                           unsigned int* item_next, void* scan_scratch, hipStream_t s);
 inline int64_t fov_item_capacity(int64_t n_keys, int64_t n_pairs_total) { return n_keys + n_pairs_total / 64 + 1; }
 hipError_t fov_exact(const FovParams& p, hipStream_t s);
-hipError_t fov_sort(const unsigned long long* keys, int64_t n, int64_t n_frames, int32_t* fcnt, int32_t* fstart,
+hipError_t fov_sort(unsigned long long* keys, int64_t n, int64_t n_frames, int32_t* fcnt, int32_t* fstart,
                     unsigned long long* sorted, void* scan_scratch, int32_t* pf, int32_t* ps, int32_t* po,
                     hipStream_t s);
 hipError_t launch_directions(const FovParams& p, const double* x_ref, double t_ref, const double* t_obs,

@@ -26,6 +26,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import os
 from typing import Dict, List, Optional
 
 import numpy as np
@@ -305,6 +306,8 @@ def rect_normals(center, u, w, half_u, half_w):
 
 @dataclasses.dataclass
 class Frames:
+    """Frames with per-sub-frame geometry; center .. half_w may be None for
+    large footprint sets, where only the normals are kept."""
     t: np.ndarray          # [F]
     obs: np.ndarray        # [F, 3] barycentric observer position
     center: np.ndarray     # [F, S, 3] sub-frame centres
@@ -321,13 +324,16 @@ class Frames:
 
     def subset(self, idx):
         idx = np.asarray(idx)
-        return Frames(self.t[idx], self.obs[idx], self.center[idx], self.u[idx], self.w[idx],
-                      self.half_u[idx], self.half_w[idx], self.normals[idx])
+        g = lambda a: None if a is None else a[idx]
+        return Frames(self.t[idx], self.obs[idx], g(self.center), g(self.u), g(self.w),
+                      g(self.half_u), g(self.half_w), self.normals[idx])
 
     @staticmethod
     def concat(parts):
-        return Frames(*[np.concatenate([getattr(p, f.name) for p in parts])
-                        for f in dataclasses.fields(Frames)])
+        def cat(name):
+            arrs = [getattr(p, name) for p in parts]
+            return None if any(a is None for a in arrs) else np.concatenate(arrs)
+        return Frames(*[cat(f.name) for f in dataclasses.fields(Frames)])
 
 
 def _frames_from_pointing(t, obs, center, roll, half_u, half_w):
@@ -428,6 +434,116 @@ def frames_targeted(rng, model, states_el, t0, span, n_frames, width_deg=1.5,
     center /= np.linalg.norm(center, axis=1, keepdims=True)
     roll = rng.uniform(0, 2 * np.pi, n_frames)
     return _frames_from_pointing(t, obs, center, roll, h, h)
+
+
+R_EARTH_AU = 6378.137 / AU_KM
+
+
+def equatorial_to_ecliptic(v: np.ndarray) -> np.ndarray:
+    ce, se = math.cos(OBLIQUITY_J2000_RAD), math.sin(OBLIQUITY_J2000_RAD)
+    out = np.empty_like(v)
+    out[..., 0] = v[..., 0]
+    out[..., 1] = ce * v[..., 1] + se * v[..., 2]
+    out[..., 2] = -se * v[..., 1] + ce * v[..., 2]
+    return out
+
+
+def ground_sites(t: np.ndarray, lon: np.ndarray, lat: float) -> np.ndarray:
+    """Equatorial unit vectors of sites at east longitude `lon` and latitude
+    `lat` (radians) at times t, the Earth turning by the Earth Rotation
+    Angle (time scales not distinguished)."""
+    era = 2.0 * np.pi * (0.7790572732640 + 1.00273781191135448 * t)
+    a = era + lon
+    return np.stack([math.cos(lat) * np.cos(a), math.cos(lat) * np.sin(a), np.full_like(a, math.sin(lat))], -1)
+
+
+def frames_ground(rng, model, n_frames, t0, span, n_sites=6, lat_deg=33.0, exposure_s=30.0, night_h=8.0,
+                  foot_u_deg=7.0, foot_w_deg=7.3, grid=8, sub_deg=0.87, min_alt_deg=30.0,
+                  keep_geometry=False, chunk=65536):
+    """Ground-survey footprints: n_sites sites at latitude lat_deg, spread
+    evenly in longitude, each exposing every exposure_s seconds through an
+    8 h block centred on local midnight; each exposure points uniformly in
+    solid angle above min_alt_deg and is a foot_u x foot_w degree footprint
+    made of grid x grid square sub-frames of sub_deg degrees on the
+    footprint's gnomonic plane.  The first n_frames exposures in time order
+    are kept.  Only the normals of the sub-frames are stored unless
+    keep_geometry is set."""
+    lons = 2.0 * np.pi * np.arange(n_sites) / n_sites
+    per_night = int(round(night_h * 3600.0 / exposure_s))
+    n_days = int(math.ceil(span)) + 1
+    ts, ls = [], []
+    for s_i, lon in enumerate(lons):
+        # local midnight: t = n + 1/2 - lon / 2 pi (J2000 at noon)
+        mid = np.arange(-1, n_days + 1) + 0.5 - lon / (2.0 * np.pi)
+        tt = (mid[:, None] + ((np.arange(per_night) + 0.5) * exposure_s / 86400.0 - night_h / 48.0)[None, :]).ravel()
+        tt = tt[(tt >= t0) & (tt < t0 + span)]
+        ts.append(tt)
+        ls.append(np.full(tt.size, lon))
+    t = np.concatenate(ts)
+    lon = np.concatenate(ls)
+    order = np.argsort(t, kind="stable")[:n_frames]
+    t, lon = t[order], lon[order]
+    F = t.size
+    lat = math.radians(lat_deg)
+    zen_eq = ground_sites(t, lon, lat)
+    ie = PLANET_NAMES.index("earth") + 1
+    earth = model.bary(t)[:, ie, :3]
+    obs = earth + R_EARTH_AU * equatorial_to_ecliptic(zen_eq)
+    # pointing: altitude with uniform sin, azimuth uniform
+    salt = rng.uniform(math.sin(math.radians(min_alt_deg)), 1.0, F)
+    calt = np.sqrt(1.0 - salt * salt)
+    az = rng.uniform(0.0, 2.0 * np.pi, F)
+    east_eq = np.stack([-zen_eq[:, 1], zen_eq[:, 0], np.zeros(F)], -1)
+    east_eq /= np.linalg.norm(east_eq, axis=-1, keepdims=True)
+    north_eq = np.cross(zen_eq, east_eq)
+    d_eq = salt[:, None] * zen_eq + calt[:, None] * (np.cos(az)[:, None] * north_eq + np.sin(az)[:, None] * east_eq)
+    center = equatorial_to_ecliptic(d_eq)
+    center /= np.linalg.norm(center, axis=-1, keepdims=True)
+    fu, fw = tangent_basis(center)
+    S = grid * grid
+    h = math.radians(sub_deg / 2.0)
+    xi = np.tan(math.radians(foot_u_deg) / grid) * (np.arange(grid) - (grid - 1) / 2.0)
+    eta = np.tan(math.radians(foot_w_deg) / grid) * (np.arange(grid) - (grid - 1) / 2.0)
+    gx, gy = np.meshgrid(xi, eta, indexing="ij")
+    gx, gy = gx.ravel(), gy.ravel()
+    normals = np.empty((F, S, 4, 3))
+    geo = None
+    if keep_geometry:
+        geo = [np.empty((F, S, 3)), np.empty((F, S, 3)), np.empty((F, S, 3))]
+    def fill(a):
+        b = min(F, a + chunk)
+        c = center[a:b, None, :] + gx[None, :, None] * fu[a:b, None, :] + gy[None, :, None] * fw[a:b, None, :]
+        c /= np.linalg.norm(c, axis=-1, keepdims=True)
+        u = fu[a:b, None, :] - np.sum(fu[a:b, None, :] * c, -1, keepdims=True) * c
+        u /= np.linalg.norm(u, axis=-1, keepdims=True)
+        w = np.cross(c, u)
+        hh = np.full(c.shape[:-1], h)
+        normals[a:b] = rect_normals(c, u, w, hh, hh)
+        if keep_geometry:
+            geo[0][a:b], geo[1][a:b], geo[2][a:b] = c, u, w
+
+    # disjoint slices, numpy releases the GIL: fill them on a few threads
+    import concurrent.futures as cf
+    with cf.ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+        list(ex.map(fill, range(0, F, chunk)))
+    if keep_geometry:
+        hu = np.full((F, S), h)
+        return Frames(t, obs, geo[0], geo[1], geo[2], hu, hu.copy(), normals)
+    return Frames(t, obs, None, None, None, None, None, normals)
+
+
+def footprint_case(seed: int = 3, n_obj: int = 750_000, n_frames: int = 2_000_000, span: float = 365.25,
+                   neo_frac: float = 0.05, keep_geometry: bool = False) -> PropagationCase:
+    """750,000 bodies (main belt plus 5% NEO-like), all 8 planets, one
+    year, 2,000,000 ground footprints of 7 x 7.3 degrees in 8 x 8
+    sub-frames of 0.87 degrees from six sites at latitude 33 degrees."""
+    rng = np.random.default_rng(seed)
+    model = PlanetModel.make()
+    n_seg = int(math.ceil((span + 24.0) / SEG_DAYS))
+    eph = make_ephemeris(model, -8.0, n_seg)
+    x0, el, is_neo = make_population(rng, model, n_obj, neo_frac, 0.0)
+    fr = frames_ground(rng, model, n_frames, 0.0, span, keep_geometry=keep_geometry) if n_frames else None
+    return PropagationCase("footprint", eph, model, x0, el, is_neo, 0.0, span, fr, seed)
 
 
 def ecliptic_to_equatorial(v: np.ndarray) -> np.ndarray:
