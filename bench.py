@@ -55,6 +55,26 @@ def integrator_flops(stats, n_body: int, n_gr: int, deg1: int) -> float:
             + vchains * CLENSHAW_VALUE_FLOPS(deg1))
 
 
+def measured_traffic(path=os.path.join(ROOT, "profiles", "traffic_k_nbody_g8_survey.md")):
+    """HBM bytes per integrator launch from the committed counter summary,
+    or None when the summary is missing or the kernel sources changed
+    since it was taken."""
+    import hashlib
+    import re
+    try:
+        txt = open(path).read()
+        val = float(re.search(r"^traffic_bytes_per_launch: (\S+)$", txt, re.M).group(1))
+        sha = re.search(r"^sources_sha1: (\S+)$", txt, re.M).group(1)
+        files = re.search(r"^sources: (.+)$", txt, re.M).group(1).split()
+    except (OSError, AttributeError, ValueError):
+        return None
+    h = hashlib.sha1()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_2509_04666_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return val if h.hexdigest() == sha else None
+
+
 def workload_name(case, F):
     return ("survey: %d bodies (95%% main belt, 5%% NEO-like), Sun + 8 planets as 8-day degree-12 "
             "Chebyshev segments, %.2f days, %d frames of 0.78 deg in 11 s sequences of 12" %
@@ -237,6 +257,8 @@ def main():
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2509_04666_amd", "tuning.json"))
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="copy a buffer of this size once before timing (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported (the objects are independent "
@@ -280,6 +302,14 @@ def main():
                                         workspace=ws_fov, return_stats=True)
         return pf.numel(), fst, status
 
+    if args.copy_calibration_mib > 0:
+        # a plain device copy of known size, for scaling the HBM byte counters
+        nb = args.copy_calibration_mib << 20
+        src = torch.ones(nb // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -312,12 +342,14 @@ def main():
     integ_ms_step = ms[0] / args.steps
     fov_ms_step = ms[1] / args.steps
     if integ_ms_step >= fov_ms_step:
-        roof = {"kernel": "k_nbody (integrator)", "bound": "alu", "achieved": achieved_tf, "peak": FP64_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved_tf / FP64_PEAK_TFLOPS, "traffic": None,
+        roof = {"kernel": "k_nbody_g8 (integrator)", "bound": "alu", "achieved": achieved_tf,
+                "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved_tf / FP64_PEAK_TFLOPS,
+                "traffic": measured_traffic(),
                 "launches_per_step": int(cnt[0] // args.steps), "avg_launch_ms": t_launch_nb * 1e3,
                 "algorithmic_flops_per_launch": flops}
     else:
-        roof = {"kernel": "k_fov (candidates)", "bound": "hbm", "achieved": fov_gbs, "peak": HBM_PEAK_GBS,
+        roof = {"kernel": "k_fov_cells + k_fov_wide (candidates)", "bound": "hbm", "achieved": fov_gbs,
+                "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": fov_gbs / HBM_PEAK_GBS, "traffic": None,
                 "launches_per_step": int(cnt[1] // args.steps), "avg_launch_ms": t_launch_fov * 1e3,
                 "algorithmic_bytes_per_launch": fov_bytes}
