@@ -157,6 +157,7 @@ def adjoint_component(api, synth, torch, n_obj, log, reps=3):
     return {
         "workload": f"{n_obj} bodies x 20 observations over 60 days, Sun + 8 planets, checkpoints every 5 days",
         "forward_ms": t_f * 1e3, "backward_ms": t_b * 1e3, "backward_over_forward": t_b / t_f,
+        "gradient_over_forward": (t_f + t_b) / t_f,
         "forward_object_days_per_s": n_obj * 60.0 / t_f, "failed_objects": n_fail,
         "grad_finite": bool(torch.isfinite(grad).all().item()),
     }

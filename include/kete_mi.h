@@ -270,7 +270,7 @@ int kete_ephem_eval(const kete_ephem_t *eph, const double *t, const double *t_ho
 
 /* Bytes of workspace needed by kete_propagate_adjoint (the same
  * workspace must be passed to the forward and the backward call). */
-size_t kete_adjoint_workspace_size(int64_t n_obj, double t0, double t_end, double ckpt_days,
+size_t kete_adjoint_workspace_size(int64_t n_obj, int32_t k_obs, double t0, double t_end, double ckpt_days,
                                    const kete_opts_t *opts);
 
 /* Sky positions of observations and their gradient with respect to the

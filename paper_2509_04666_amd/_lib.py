@@ -85,7 +85,7 @@ SIGNATURES = {
                                             C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.POINTER(OptsT),
                                             C.c_void_p]),
     "kete_ephem_eval": (C.c_int, [C.POINTER(EphemT), C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
-    "kete_adjoint_workspace_size": (C.c_size_t, [C.c_int64, C.c_double, C.c_double, C.c_double, C.POINTER(OptsT)]),
+    "kete_adjoint_workspace_size": (C.c_size_t, [C.c_int64, C.c_int32, C.c_double, C.c_double, C.c_double, C.POINTER(OptsT)]),
     "kete_propagate_adjoint": (C.c_int, [C.POINTER(EphemT), C.c_int32, C.c_void_p, C.c_double, C.c_double,
                                          C.c_int64, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
                                          C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(OptsT), C.c_void_p,

@@ -213,7 +213,7 @@ class AdjointContext:
         self.obs_pos = obs_pos.contiguous()
         self.opts = opts or default_opts()
         self.n_obj, self.k_obs = self.t_obs.shape
-        need = lib().kete_adjoint_workspace_size(self.n_obj, self.t0, self.t_end, self.ckpt_days,
+        need = lib().kete_adjoint_workspace_size(self.n_obj, self.k_obs, self.t0, self.t_end, self.ckpt_days,
                                                  C.byref(self.opts))
         if need == 0:
             check(_lib.KETE_EINVAL)

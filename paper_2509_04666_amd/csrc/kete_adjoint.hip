@@ -167,299 +167,448 @@ __device__ void hop_vjp(const AdjParams& p, const SunGlobal& sun, double t_obs, 
 }
 
 // ---------------------------------------------------------------- forward
-__device__ __forceinline__ void save_ckpt(const AdjParams& p, int c, int j, const Lane& L, double hw) {
+// Both passes integrate each object as an 8-lane group (one lane per
+// collocation node, 8 objects per wavefront, wave-shared steps) with the
+// step loop of the propagation kernels.
+
+// Checkpoint c of object j: state, the step size to resume with, and a
+// failure flag; lanes 0..7 of the group write one double each.
+__device__ __forceinline__ void save_ckpt_g8(const AdjParams& p, int c, int j, int gl, const G8State& S) {
     double* ck = p.ckpt + ((size_t)c * p.n_obj + j) * kCkptDoubles;
-    for (int i = 0; i < 3; ++i) { ck[i] = L.x0[i]; ck[3 + i] = L.v0[i]; }
-    ck[6] = hw;
-    ck[7] = L.active ? 0.0 : (double)(L.status ? L.status : 1);
+    const double v = gl < 6 ? state_component(S.x0, S.v0, gl)
+                            : gl == 6 ? S.hw : (S.active ? 0.0 : (double)(S.status ? S.status : 1));
+    ck[gl] = v;
 }
 
-__global__ __launch_bounds__(64) void k_adjoint_fwd(const AdjParams p) {
+// Increments of all 7 nodes of this lane's group.
+__device__ __forceinline__ void gather_d(const double dn[3], double D[7][3]) {
+#pragma unroll
+    for (int m = 0; m < 7; ++m) {
+        D[m][0] = __shfl(dn[0], m, kGroup);
+        D[m][1] = __shfl(dn[1], m, kGroup);
+        D[m][2] = __shfl(dn[2], m, kGroup);
+    }
+}
+
+__device__ __forceinline__ void init_lane_state(const AdjParams& p, bool valid, int j, G8State& S) {
+    S.status = 0;
+    S.active = valid;
+    for (int i = 0; i < 3; ++i) {
+        S.x0[i] = valid ? p.x0[6 * j + i] : (i == 0 ? 1.0 : 0.0);
+        S.v0[i] = valid ? p.x0[6 * j + 3 + i] : 0.0;
+        S.F0[i] = 0.0;
+    }
+    S.hp_new = kInf;
+    S.haveF0 = false;
+}
+
+template <int NB, int NGR, int DEG1>
+__global__ __launch_bounds__(64, 3) void k_adjoint_fwd(const AdjParams p) {
     extern __shared__ double smem[];
     const int lane = threadIdx.x;
+    const int gl = lane & (kGroup - 1);
+    const int node = gl < 7 ? gl + 1 : 7;
     const EphemArgs& E = p.eph;
     const int bstride = p.max_win_segs * 3 * E.deg1;
     double* coefL = smem;
-    double* ephW = smem + (size_t)E.n_body * bstride;
-    const long gi = (long)blockIdx.x * 64 + lane;
+    double* e8 = smem + (((size_t)E.n_body * bstride + 1) & ~(size_t)1);
+    g8_table_init(E, lane, e8);
+    NodeRow R;
+    load_node_row(p.rc, node, R);
+    const long gi = ((long)blockIdx.x * 64 + lane) / kGroup;
     const bool valid = gi < p.n_obj;
     const int j = valid ? p.perm[gi] : 0;
-    const SunGlobal sun{E};
-    Lane L;
-    L.status = 0;
-    L.active = valid;
-    for (int i = 0; i < 3; ++i) { L.x0[i] = valid ? p.x0[6 * j + i] : (i == 0 ? 1.0 : 0.0); L.v0[i] = valid ? p.x0[6 * j + 3 + i] : 0.0; L.F0[i] = 0.0; }
-    double hw = wave_min(L.active ? p.h_pref[j] : kInf);
-    if (!(hw < kInf)) hw = p.h_init;
-    double t = p.t0;
-    bool haveF0 = false;
-    long wsteps = 0;
+    G8State S;
+    init_lane_state(p, valid, j, S);
+    S.hw = groups_min(valid ? p.h_pref[j] : kInf);
+    if (!(S.hw < kInf)) S.hw = p.h_init;
+    S.t = p.t0;
+    G8Count C;
     const int K = p.k_obs;
     int kobs = 0;
     const double* tob = p.t_obs + (size_t)j * K;
-    auto sky_of = [&](int k, const double X[3], const double V[3]) {
-        double d[3], tau, ve[3], r0[3], v0[3], chi;
-        hop(p, sun, tob[k], X, V, p.obs_pos + ((size_t)j * K + k) * 3, d, tau, ve, r0, v0, chi);
-        double ra, dec, J[6];
-        radec(d, p.cos_eps, p.sin_eps, ra, dec, J);
-        p.sky_out[((size_t)j * K + k) * 2] = ra;
-        p.sky_out[((size_t)j * K + k) * 2 + 1] = dec;
+    auto store_obs = [&](int k, const double X[3], const double V[3]) {
+        if (gl < 6) p.obs_state[((size_t)j * K + k) * 6 + gl] = state_component(X, V, gl);
     };
     // observations at the start epoch
-    if (L.active) while (kobs < K && tob[kobs] <= t) { sky_of(kobs, L.x0, L.v0); ++kobs; }
-    if (valid) save_ckpt(p, 0, j, L, hw);
+    if (valid) while (kobs < K && tob[kobs] <= S.t) { store_obs(kobs, S.x0, S.v0); ++kobs; }
+    auto visit = [&](double ts, double h, const double dn[3], const G8State& St) {
+        const double te = ts + h;
+        auto pending = [&]() {
+            return valid && St.active && kobs < K && (h > 0 ? tob[kobs] <= te : tob[kobs] >= te);
+        };
+        bool pend = pending();
+        if (__ballot(pend) == 0ull) return;
+        double D[7][3];
+        gather_d(dn, D);
+        while (__ballot(pend) != 0ull) {
+            if (pend) {
+                double X[3], V[3];
+                dense_state(p.rc, St.x0, St.v0, St.F0, D, h, (tob[kobs] - ts) / h, X, V);
+                store_obs(kobs, X, V);
+                ++kobs;
+            }
+            pend = pending();
+        }
+    };
+    if (valid) save_ckpt_g8(p, 0, j, gl, S);
     for (int c = 0; c < p.n_ckpt; ++c) {
         for (int w = p.seg_win[c]; w < p.seg_win[c + 1]; ++w) {
             const Window W = p.win[w];
             __syncthreads();
             stage_window(E, W.seg_lo, W.seg_hi, bstride, lane, 64, coefL);
             __syncthreads();
-            integrate_window(p, W, coefL, bstride, ephW, L, t, hw, haveF0, wsteps,
-                             [&](double ts, double h, const double D[7][3], const double*) {
-                                 if (!L.active) return;
-                                 const double te = ts + h;
-                                 while (kobs < K && (h > 0 ? tob[kobs] <= te : tob[kobs] >= te)) {
-                                     double X[3], V[3];
-                                     dense_state(p.rc, L.x0, L.v0, L.F0, D, h, (tob[kobs] - ts) / h, X, V);
-                                     sky_of(kobs, X, V);
-                                     ++kobs;
-                                 }
-                             });
+            g8_integrate<NB, NGR, DEG1>(p, R, node, gl, lane, coefL, bstride, e8, W.seg_lo, W.seg_hi, W.t_b, S, C,
+                                        visit);
         }
-        if (valid) save_ckpt(p, c + 1, j, L, hw);
+        if (valid) save_ckpt_g8(p, c + 1, j, gl, S);
     }
-    if (valid) {
-        p.status[j] = L.status;
-        if (L.status)
-            for (int k = 0; k < K; ++k) { p.sky_out[((size_t)j * K + k) * 2] = __builtin_nan(""); p.sky_out[((size_t)j * K + k) * 2 + 1] = __builtin_nan(""); }
-    }
+    if (valid && gl == 0) p.status[j] = S.status;
+}
+
+// Sky position of every observation from its stored state (forward), one
+// lane per (object, observation); failed objects get NaN.
+__global__ __launch_bounds__(256) void k_obs_sky(const AdjParams p) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)p.n_obj * p.k_obs) return;
+    const int64_t j = i / p.k_obs;
+    double* out = p.sky_out + 2 * i;
+    if (p.status[j] != 0) { out[0] = out[1] = __builtin_nan(""); return; }
+    const SunGlobal sun{p.eph};
+    const double* st = p.obs_state + 6 * i;
+    double d[3], tau, ve[3], r0[3], v0[3], chi;
+    hop(p, sun, p.t_obs[i], st, st + 3, p.obs_pos + 3 * i, d, tau, ve, r0, v0, chi);
+    double ra, dec, J[6];
+    radec(d, p.cos_eps, p.sin_eps, ra, dec, J);
+    out[0] = ra;
+    out[1] = dec;
+}
+
+// dL/d(state) of every observation (backward), one lane per observation.
+__global__ __launch_bounds__(256) void k_obs_vjp(const AdjParams p) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)p.n_obj * p.k_obs) return;
+    const int64_t j = i / p.k_obs;
+    double* g = p.obs_grad + 6 * i;
+    if (p.status[j] != 0) { for (int c = 0; c < 6; ++c) g[c] = 0.0; return; }
+    const SunGlobal sun{p.eph};
+    const double* st = p.obs_state + 6 * i;
+    double lX[3], lV[3];
+    hop_vjp(p, sun, p.t_obs[i], st, st + 3, p.obs_pos + 3 * i, p.dL_dsky[2 * i], p.dL_dsky[2 * i + 1], lX, lV);
+    for (int c = 0; c < 3; ++c) { g[c] = lX[c]; g[3 + c] = lV[c]; }
 }
 
 // ---------------------------------------------------------------- backward
-__global__ __launch_bounds__(64) void k_adjoint_bwd(const AdjParams p) {
+// Constants of the reverse sweep held by lane gl of a group.  Lane m - 1
+// (m = 1..7) owns stage m: cA[n-1] = A_m(s_n), cB[n-1] = B_m(s_n) and the
+// step-end weights gA = A_m(1), gB = B_m(1); lane 7 owns the step start:
+// s_n^2/2 - sum_m A_m(s_n), s_n - sum_m B_m(s_n), and the same at s = 1.
+struct AdjCols {
+    double cA[7], cB[7], gA, gB;
+};
+
+__device__ __forceinline__ void load_adj_cols(const RadauConst& rc, int gl, AdjCols& c) {
+#pragma unroll
+    for (int n = 1; n <= 8; ++n) {
+        double sA = 0.0, sB = 0.0, a = 0.0, b = 0.0;
+#pragma unroll
+        for (int m = 0; m < 7; ++m) {
+            sA += rc.A[n][m];
+            sB += rc.B[n][m];
+            a = (gl == m) ? rc.A[n][m] : a;
+            b = (gl == m) ? rc.B[n][m] : b;
+        }
+        if (gl == 7) { a = rc.half_s2[n] - sA; b = rc.s[n] - sB; }
+        if (n < 8) { c.cA[n - 1] = a; c.cB[n - 1] = b; }
+        else { c.gA = a; c.gB = b; }
+    }
+}
+
+template <int NB, int NGR, int DEG1>
+__global__ __launch_bounds__(64, 2) void k_adjoint_bwd(const AdjParams p) {
     extern __shared__ double smem[];
     const int lane = threadIdx.x;
+    const int gl = lane & (kGroup - 1);
+    const int node = gl < 7 ? gl + 1 : 7;
+    const int jnode = gl < 7 ? gl + 1 : 0;          // node whose Jacobians this lane keeps
     const EphemArgs& E = p.eph;
     const RadauConst& rc = p.rc;
     const int bstride = p.max_win_segs * 3 * E.deg1;
     double* coefL = smem;
-    double* ephW = smem + (size_t)E.n_body * bstride;
-    const long gi_raw = (long)blockIdx.x * 64 + lane;
+    double* e8 = smem + (((size_t)E.n_body * bstride + 1) & ~(size_t)1);
+    // exchange slots of the reverse sweep: [group][node lane][6] (W, U)
+    double* xw = e8 + (size_t)kNodes * g8_row(E.n_body) + (lane / kGroup) * kGroup * 6;
+    g8_table_init(E, lane, e8);
+    // per-node constants of the 8 lanes of a group, shared through LDS to
+    // keep registers for the sweeps
+    __shared__ NodeRow rows[kGroup];
+    __shared__ AdjCols cols[kGroup];
+    __shared__ double drow[kGroup][18];      // own dense-output row (see below)
+    if (lane < kGroup) {
+        NodeRow r;
+        load_node_row(rc, lane < 7 ? lane + 1 : 7, r);
+        rows[lane] = r;
+        AdjCols q;
+        load_adj_cols(rc, lane, q);
+        cols[lane] = q;
+        // alpha(sig) = sum_k drow[k] sig^(k+2) + drow[16] sig^2, beta(sig) = sum_k drow[8+k] sig^(k+1) + drow[17] sig:
+        // stage m = lane + 1 for lanes 0..6, minus the sum over stages for lane 7
+        for (int k = 0; k < 8; ++k) {
+            double a = 0.0, b = 0.0, sa = 0.0, sb = 0.0;
+            for (int m = 0; m < 7; ++m) {
+                sa += rc.Ap[m][k]; sb += rc.Bp[m][k];
+                if (m == lane) { a = rc.Ap[m][k]; b = rc.Bp[m][k]; }
+            }
+            drow[lane][k] = lane < 7 ? a : -sa;
+            drow[lane][8 + k] = lane < 7 ? b : -sb;
+        }
+        drow[lane][16] = lane < 7 ? 0.0 : 0.5;
+        drow[lane][17] = lane < 7 ? 0.0 : 1.0;
+    }
+    __syncthreads();
+    const NodeRow& R = rows[gl];
+    const AdjCols& Q = cols[gl];
+    const double* dr = drow[gl];
+    const long gi_raw = ((long)blockIdx.x * 64 + lane) / kGroup;
     const bool valid = gi_raw < p.n_obj;
-    const size_t gi = valid ? (size_t)gi_raw : 0;     // scratch slot (invalid lanes read slot 0, never write)
+    const size_t gi = valid ? (size_t)gi_raw : 0;   // scratch slot (invalid groups read slot 0, never write)
     const int j = valid ? p.perm[gi] : 0;
     const size_t N = p.n_obj;
-    const SunGlobal sun{E};
     const int K = p.k_obs;
     const double* tob = p.t_obs + (size_t)j * K;
-    const double* gsky = p.dL_dsky + (size_t)j * K * 2;
     const bool ok_final = valid && p.status[j] == 0;
     double lx[3] = {0.0, 0.0, 0.0}, lv[3] = {0.0, 0.0, 0.0};
     int kb = K - 1;
     bool overflow_steps = false;
 
     for (int c = p.n_ckpt - 1; c >= 0; --c) {
-        // ---- recompute segment c, storing steps and node Jacobians
-        Lane L;
+        // ---- recompute segment c, storing the steps and the node Jacobians
+        G8State S;
+        init_lane_state(p, false, j, S);
         double hw = 0.0;
         if (valid) {
             const double* ck = p.ckpt + ((size_t)c * N + j) * kCkptDoubles;
-            for (int i = 0; i < 3; ++i) { L.x0[i] = ck[i]; L.v0[i] = ck[3 + i]; L.F0[i] = 0.0; }
+            #pragma unroll
+            for (int i = 0; i < 3; ++i) { S.x0[i] = ck[i]; S.v0[i] = ck[3 + i]; }
             hw = ck[6];
-            L.active = ck[7] == 0.0;
-            L.status = 0;
-        } else {
-            for (int i = 0; i < 3; ++i) { L.x0[i] = (i == 0 ? 1.0 : 0.0); L.v0[i] = 0.0; L.F0[i] = 0.0; }
-            L.active = false;
-            L.status = 0;
+            S.active = ck[7] == 0.0;
         }
-        hw = wave_max(valid ? hw : 0.0);     // the same value in every valid lane
-        double t = p.win[p.seg_win[c]].t_a;
-        bool haveF0 = false;
-        long wsteps = 0;
+        S.hw = groups_max(valid ? hw : 0.0);        // the same value in every valid group
+        S.t = p.win[p.seg_win[c]].t_a;
+        G8Count Cn;
         int ns = 0;
+        auto store = [&](double ts, double h, const double dn[3], const G8State& St) {
+            if (ns >= p.s_max) { overflow_steps = true; return; }
+            double D[7][3];
+            gather_d(dn, D);
+            if (valid) {
+                double* sp = p.steps + (size_t)ns * kStepDoubles * N;
+                if (gl < 6) sp[(2 + gl) * N + gi] = state_component(St.x0, St.v0, gl);
+                if (gl == 6) sp[gi] = ts;
+                if (gl == 7) sp[N + gi] = h;
+                if (gl < 3) sp[(8 + gl) * N + gi] = St.F0[gl];
+                if (gl < 7)
+                    #pragma unroll
+                    for (int i = 0; i < 3; ++i) sp[(11 + 3 * gl + i) * N + gi] = dn[i];
+                // state at this lane's Jacobian node
+                double X[3], V[3];
+                const double hh = h * h;
+                #pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    if (jnode == 0) { X[i] = St.x0[i]; V[i] = St.v0[i]; continue; }
+                    double ax = R.hs2 * St.F0[i], av = R.s * St.F0[i];
+                    #pragma unroll
+                    for (int m = 0; m < 7; ++m) { ax = fma(R.A[m], D[m][i], ax); av = fma(R.B[m], D[m][i], av); }
+                    X[i] = fma(hh, ax, fma(R.s * h, St.v0[i], St.x0[i]));
+                    V[i] = fma(h, av, St.v0[i]);
+                }
+                double Jx[9], Jv[9];
+                accel_jac8(e8 + jnode * g8_row(E.n_body), E, X, V, Jx, Jv);
+                double* jp = p.jac + (size_t)ns * 8 * kJacDoubles * N;
+                #pragma unroll
+                for (int q = 0; q < 9; ++q) {
+                    jp[((size_t)jnode * kJacDoubles + q) * N + gi] = Jx[q];
+                    jp[((size_t)jnode * kJacDoubles + 9 + q) * N + gi] = Jv[q];
+                }
+            }
+            ++ns;
+        };
         for (int w = p.seg_win[c]; w < p.seg_win[c + 1]; ++w) {
             const Window W = p.win[w];
             __syncthreads();
             stage_window(E, W.seg_lo, W.seg_hi, bstride, lane, 64, coefL);
             __syncthreads();
-            integrate_window(p, W, coefL, bstride, ephW, L, t, hw, haveF0, wsteps,
-                             [&](double ts, double h, const double D[7][3], const double* eph) {
-                                 if (ns >= p.s_max) { overflow_steps = true; return; }
-                                 if (!valid) { ++ns; return; }
-                                 double* sp = p.steps + (size_t)ns * kStepDoubles * N;
-                                 sp[0 * N + gi] = ts;
-                                 sp[1 * N + gi] = h;
-                                 for (int i = 0; i < 3; ++i) {
-                                     sp[(2 + i) * N + gi] = L.x0[i];
-                                     sp[(5 + i) * N + gi] = L.v0[i];
-                                     sp[(8 + i) * N + gi] = L.F0[i];
-                                 }
-                                 for (int m = 0; m < 7; ++m)
-                                     for (int i = 0; i < 3; ++i) sp[(11 + 3 * m + i) * N + gi] = D[m][i];
-                                 double* jp = p.jac + (size_t)ns * 8 * kJacDoubles * N;
-                                 const double hh = h * h;
-                                 for (int n = 0; n < 8; ++n) {
-                                     double X[3], V[3];
-                                     if (n == 0) {
-                                         for (int i = 0; i < 3; ++i) { X[i] = L.x0[i]; V[i] = L.v0[i]; }
-                                     } else {
-                                         for (int i = 0; i < 3; ++i) {
-                                             double ax = rc.half_s2[n] * L.F0[i], av = rc.s[n] * L.F0[i];
-                                             for (int m = 0; m < 7; ++m) {
-                                                 ax = fma(rc.A[n][m], D[m][i], ax);
-                                                 av = fma(rc.B[n][m], D[m][i], av);
-                                             }
-                                             X[i] = fma(hh, ax, fma(rc.s[n] * h, L.v0[i], L.x0[i]));
-                                             V[i] = fma(h, av, L.v0[i]);
-                                         }
-                                     }
-                                     double Jx[9], Jv[9];
-                                     accel_jac(eph + n * E.n_body * 6, E, X, V, Jx, Jv);
-                                     for (int q = 0; q < 9; ++q) {
-                                         jp[((size_t)n * kJacDoubles + q) * N + gi] = Jx[q];
-                                         jp[((size_t)n * kJacDoubles + 9 + q) * N + gi] = Jv[q];
-                                     }
-                                 }
-                                 ++ns;
-                             });
+            g8_integrate<NB, NGR, DEG1>(p, R, node, gl, lane, coefL, bstride, e8, W.seg_lo, W.seg_hi, W.t_b, S, Cn,
+                                        store, true);
         }
+        if (ns > p.s_max) ns = p.s_max;
         // ---- reverse sweep over the stored steps
-        for (int s = ns - 1; s >= 0; --s) {
-            const double* sp = p.steps + (size_t)s * kStepDoubles * N;
-            const double ts = valid ? sp[gi] : 0.0;
+        for (int st = ns - 1; st >= 0; --st) {
+            const double* sp = p.steps + (size_t)st * kStepDoubles * N;
+            const double ts = sp[gi];
             const double h = valid ? sp[N + gi] : 1.0;
-            double x0[3], v0[3], F0[3], D[7][3];
-            for (int i = 0; i < 3; ++i) {
-                x0[i] = valid ? sp[(2 + i) * N + gi] : 0.0;
-                v0[i] = valid ? sp[(5 + i) * N + gi] : 0.0;
-                F0[i] = valid ? sp[(8 + i) * N + gi] : 0.0;
-            }
-            for (int m = 0; m < 7; ++m)
-                for (int i = 0; i < 3; ++i) D[m][i] = valid ? sp[(11 + 3 * m + i) * N + gi] : 0.0;
             const double hh = h * h;
             // output cotangents: the step end and the observations inside
-            double G[8][3];
-            double sA = 0.0, sB = 0.0;
-            for (int m = 0; m < 7; ++m) { sA += rc.A[8][m]; sB += rc.B[8][m]; }
+            double G[3], gx0[3], gv0[3];
+            #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                G[0][i] = hh * (rc.half_s2[8] - sA) * lx[i] + h * (1.0 - sB) * lv[i];
-                for (int m = 0; m < 7; ++m) G[m + 1][i] = hh * rc.A[8][m] * lx[i] + h * rc.B[8][m] * lv[i];
+                G[i] = hh * Q.gA * lx[i] + h * Q.gB * lv[i];
+                gx0[i] = lx[i];
+                gv0[i] = h * lx[i] + lv[i];
             }
-            double gx0[3], gv0[3];
-            for (int i = 0; i < 3; ++i) { gx0[i] = lx[i]; gv0[i] = h * lx[i] + lv[i]; }
-            if (ok_final) {
-                while (kb >= 0 && (h > 0 ? tob[kb] > ts : tob[kb] < ts)) {
+            auto pending = [&]() { return ok_final && kb >= 0 && (h > 0 ? tob[kb] > ts : tob[kb] < ts); };
+            bool pend = pending();
+            while (__ballot(pend) != 0ull) {
+                if (pend) {
                     const double sig = (tob[kb] - ts) / h;
-                    double X[3], V[3];
-                    dense_state(rc, x0, v0, F0, D, h, sig, X, V);
-                    double lX[3], lV[3];
-                    hop_vjp(p, sun, tob[kb], X, V, p.obs_pos + ((size_t)j * K + kb) * 3, gsky[2 * kb], gsky[2 * kb + 1],
-                            lX, lV);
-                    double al[7], be[7];
-                    dense_weights(rc, sig, al, be);
-                    double sa = 0.0, sb = 0.0;
-                    for (int m = 0; m < 7; ++m) { sa += al[m]; sb += be[m]; }
+                    const double* og = p.obs_grad + ((size_t)j * K + kb) * 6;
+                    const double lX[3] = {og[0], og[1], og[2]}, lV[3] = {og[3], og[4], og[5]};
+                    // this lane's dense-output weights at sig
+                    double a = dr[7], b = dr[15];
+                    #pragma unroll
+                    for (int k = 6; k >= 0; --k) { a = fma(a, sig, dr[k]); b = fma(b, sig, dr[8 + k]); }
+                    a = (a + dr[16]) * sig * sig;
+                    b = (b + dr[17]) * sig;
+                    #pragma unroll
                     for (int i = 0; i < 3; ++i) {
-                        G[0][i] += hh * (0.5 * sig * sig - sa) * lX[i] + h * (sig - sb) * lV[i];
-                        for (int m = 0; m < 7; ++m) G[m + 1][i] += hh * al[m] * lX[i] + h * be[m] * lV[i];
+                        G[i] += hh * a * lX[i] + h * b * lV[i];
                         gx0[i] += lX[i];
                         gv0[i] += sig * h * lX[i] + lV[i];
                     }
                     --kb;
                 }
+                pend = pending();
             }
-            // stage cotangents: mu_m = G_m + sum_n [h^2 alpha_m(s_n) Jx_n^T mu_n + h beta_m(s_n) Jv_n^T mu_n]
-            const double* jp = p.jac + (size_t)s * 8 * kJacDoubles * N;
-            double mu[7][3];
-            for (int m = 0; m < 7; ++m) for (int i = 0; i < 3; ++i) mu[m][i] = G[m + 1][i];
-            double wsum[3], usum[3], m0[3];
+            // this lane's Jacobians
+            const double* jp = p.jac + (size_t)st * 8 * kJacDoubles * N;
+            double Jx[9], Jv[9];
+            #pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                Jx[q] = valid ? jp[((size_t)jnode * kJacDoubles + q) * N + gi] : 0.0;
+                Jv[q] = valid ? jp[((size_t)jnode * kJacDoubles + 9 + q) * N + gi] : 0.0;
+            }
+            // stage cotangents: mu_m = G_m + sum_n [h^2 A_m(s_n) Jx_n^T mu_n + h B_m(s_n) Jv_n^T mu_n],
+            // lane m - 1 holding mu_m; lane 7 accumulates the step-start term m0
+            double mu[3] = {G[0], G[1], G[2]};
+            double wsum[3], usum[3], m0[3] = {0.0, 0.0, 0.0};
             double pc = 1e300, pcl;
             int it = 0;
             do {
                 pcl = pc;
                 ++it;
-                double nm[7][3];
-                for (int m = 0; m < 7; ++m) for (int i = 0; i < 3; ++i) nm[m][i] = G[m + 1][i];
-                for (int i = 0; i < 3; ++i) { wsum[i] = 0.0; usum[i] = 0.0; m0[i] = G[0][i]; }
-                for (int n = 1; n <= 7; ++n) {
-                    double wn[3], un[3];
+                double W[3] = {0.0, 0.0, 0.0}, U[3] = {0.0, 0.0, 0.0};
+                if (gl < 7) {
+                    #pragma unroll
                     for (int c2 = 0; c2 < 3; ++c2) {
                         double a = 0.0, b = 0.0;
-                        for (int r = 0; r < 3; ++r) {
-                            a = fma(jp[((size_t)n * kJacDoubles + 3 * r + c2) * N + gi], mu[n - 1][r], a);
-                            b = fma(jp[((size_t)n * kJacDoubles + 9 + 3 * r + c2) * N + gi], mu[n - 1][r], b);
-                        }
-                        wn[c2] = a; un[c2] = b;
+                        #pragma unroll
+                        for (int r = 0; r < 3; ++r) { a = fma(Jx[3 * r + c2], mu[r], a); b = fma(Jv[3 * r + c2], mu[r], b); }
+                        W[c2] = a; U[c2] = b;
                     }
-                    double sAn = 0.0, sBn = 0.0;
-                    for (int m = 0; m < 7; ++m) { sAn += rc.A[n][m]; sBn += rc.B[n][m]; }
+                }
+                *reinterpret_cast<double2*>(xw + 6 * gl) = make_double2(W[0], W[1]);
+                *reinterpret_cast<double2*>(xw + 6 * gl + 2) = make_double2(W[2], U[0]);
+                *reinterpret_cast<double2*>(xw + 6 * gl + 4) = make_double2(U[1], U[2]);
+                wave_lds_sync();
+                double nm[3] = {G[0], G[1], G[2]};
+                #pragma unroll
+                for (int i = 0; i < 3; ++i) { wsum[i] = 0.0; usum[i] = 0.0; }
+                #pragma unroll
+                for (int n = 1; n <= 7; ++n) {
+                    const double* x = xw + 6 * (n - 1);
+                    const double2 w01 = *reinterpret_cast<const double2*>(x);
+                    const double2 w2u0 = *reinterpret_cast<const double2*>(x + 2);
+                    const double2 u12 = *reinterpret_cast<const double2*>(x + 4);
+                    const double wn[3] = {w01.x, w01.y, w2u0.x}, un[3] = {w2u0.y, u12.x, u12.y};
+                    #pragma unroll
                     for (int i = 0; i < 3; ++i) {
-                        for (int m = 0; m < 7; ++m) nm[m][i] += hh * rc.A[n][m] * wn[i] + h * rc.B[n][m] * un[i];
-                        m0[i] += hh * (rc.half_s2[n] - sAn) * wn[i] + h * (rc.s[n] - sBn) * un[i];
+                        nm[i] += hh * Q.cA[n - 1] * wn[i] + h * Q.cB[n - 1] * un[i];
                         wsum[i] += wn[i];
                         usum[i] += rc.s[n] * h * wn[i] + un[i];
                     }
                 }
+                wave_lds_sync();
                 double dm = 0.0, mm = 0.0;
-                for (int m = 0; m < 7; ++m)
+                if (gl < 7) {
+                    #pragma unroll
                     for (int i = 0; i < 3; ++i) {
-                        dm = fmax(dm, fabs(nm[m][i] - mu[m][i]));
-                        mm = fmax(mm, fabs(nm[m][i]));
-                        mu[m][i] = nm[m][i];
+                        dm = fmax(dm, fabs(nm[i] - mu[i]));
+                        mm = fmax(mm, fabs(nm[i]));
+                        mu[i] = nm[i];
                     }
-                pc = wave_max((ok_final && mm > 0.0) ? dm / mm : 0.0);
+                } else {
+                    #pragma unroll
+                    for (int i = 0; i < 3; ++i) m0[i] = nm[i];
+                }
+#pragma unroll
+                for (int off = 1; off < kGroup; off <<= 1) {
+                    dm = fmax(dm, __shfl_xor(dm, off, kWave));
+                    mm = fmax(mm, __shfl_xor(mm, off, kWave));
+                }
+                pc = groups_max((ok_final && mm > 0.0) ? dm / mm : 0.0);
             } while (!(pc < 1e-16) && !(it > 2 && pcl <= pc) && it < 2 * p.max_iter);
-            // wsum/usum/m0 hold the sums of the last sweep, whose mu differs
-            // from the converged one by the last change only
-            double J0x[9], J0v[9];
-            for (int q = 0; q < 9; ++q) {
-                J0x[q] = jp[(size_t)q * N + gi];
-                J0v[q] = jp[(size_t)(9 + q) * N + gi];
-            }
+            // step-start Jacobians (lane 7) applied to m0, shared with the group
+            double a0[3], b0[3];
+            #pragma unroll
             for (int i = 0; i < 3; ++i) {
                 double a = 0.0, b = 0.0;
-                for (int r = 0; r < 3; ++r) { a = fma(J0x[3 * r + i], m0[r], a); b = fma(J0v[3 * r + i], m0[r], b); }
-                lx[i] = gx0[i] + wsum[i] + a;
-                lv[i] = gv0[i] + usum[i] + b;
+                #pragma unroll
+                for (int r = 0; r < 3; ++r) { a = fma(Jx[3 * r + i], m0[r], a); b = fma(Jv[3 * r + i], m0[r], b); }
+                a0[i] = __shfl(a, 7, kGroup);
+                b0[i] = __shfl(b, 7, kGroup);
+            }
+            #pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                lx[i] = gx0[i] + wsum[i] + a0[i];
+                lv[i] = gv0[i] + usum[i] + b0[i];
             }
         }
     }
     // observations at the start epoch
     if (ok_final) {
         while (kb >= 0) {
-            double lX[3], lV[3];
-            const double xs[3] = {p.x0[6 * j], p.x0[6 * j + 1], p.x0[6 * j + 2]};
-            const double vs[3] = {p.x0[6 * j + 3], p.x0[6 * j + 4], p.x0[6 * j + 5]};
-            hop_vjp(p, sun, tob[kb], xs, vs, p.obs_pos + ((size_t)j * K + kb) * 3, gsky[2 * kb], gsky[2 * kb + 1], lX, lV);
-            for (int i = 0; i < 3; ++i) { lx[i] += lX[i]; lv[i] += lV[i]; }
+            const double* og = p.obs_grad + ((size_t)j * K + kb) * 6;
+            #pragma unroll
+            for (int i = 0; i < 3; ++i) { lx[i] += og[i]; lv[i] += og[3 + i]; }
             --kb;
         }
     }
     if (valid) {
         const bool good = ok_final && !overflow_steps;
-        for (int i = 0; i < 3; ++i) {
-            p.grad[6 * j + i] = good ? lx[i] : 0.0;
-            p.grad[6 * j + 3 + i] = good ? lv[i] : 0.0;
-        }
-        if (overflow_steps && p.status[j] == 0) p.status[j] = KETE_ST_MAX_STEPS;
+        if (gl < 6) p.grad[6 * j + gl] = good ? state_component(lx, lv, gl) : 0.0;
+        if (gl == 0 && overflow_steps && p.status[j] == 0) p.status[j] = KETE_ST_MAX_STEPS;
     }
 }
 
 }  // namespace
 
 size_t adjoint_lds_bytes(const AdjParams& p) {
-    return ((size_t)p.eph.n_body * p.max_win_segs * 3 * p.eph.deg1 + (size_t)kNodes * p.eph.n_body * 6) *
-           sizeof(double);
+    return ((((size_t)p.eph.n_body * p.max_win_segs * 3 * p.eph.deg1 + 1) & ~(size_t)1) +
+            (size_t)kNodes * g8_row(p.eph.n_body) + (size_t)kWave * 6) * sizeof(double);
 }
 
 hipError_t launch_adjoint(const AdjParams& p, int mode, hipStream_t s) {
-    const int grid = (int)((p.n_obj + 63) / 64);
+    const int grid = (int)(((int64_t)p.n_obj * kGroup + 63) / 64);
     if (grid == 0) return hipSuccess;
-    if (mode == KETE_ADJ_FWD)
-        hipLaunchKernelGGL(k_adjoint_fwd, dim3(grid), dim3(64), adjoint_lds_bytes(p), s, p);
-    else
-        hipLaunchKernelGGL(k_adjoint_bwd, dim3(grid), dim3(64), adjoint_lds_bytes(p), s, p);
+    const int64_t n_o = (int64_t)p.n_obj * p.k_obs;
+    const unsigned go = (unsigned)((n_o + 255) / 256);
+    const size_t lds = adjoint_lds_bytes(p);
+    const int nb = p.eph.n_body, ngr = p.eph.n_gr, d1 = p.eph.deg1;
+#define KETE_ADJ(K)                                                                                     \
+    do {                                                                                                \
+        if (nb == 9 && ngr == 3 && d1 == 13) hipLaunchKernelGGL((K<9, 3, 13>), dim3(grid), dim3(64), lds, s, p); \
+        else if (nb == 3 && ngr == 2 && d1 == 13)                                                       \
+            hipLaunchKernelGGL((K<3, 2, 13>), dim3(grid), dim3(64), lds, s, p);                         \
+        else hipLaunchKernelGGL((K<0, 0, 0>), dim3(grid), dim3(64), lds, s, p);                         \
+    } while (0)
+    if (mode == KETE_ADJ_FWD) {
+        KETE_ADJ(k_adjoint_fwd);
+        if (n_o > 0) hipLaunchKernelGGL(k_obs_sky, dim3(go), dim3(256), 0, s, p);
+    } else {
+        if (n_o > 0) hipLaunchKernelGGL(k_obs_vjp, dim3(go), dim3(256), 0, s, p);
+        KETE_ADJ(k_adjoint_bwd);
+    }
+#undef KETE_ADJ
     return hipGetLastError();
 }
 

@@ -28,6 +28,8 @@ struct AdjParams {
     const int32_t* seg_win;     // [C+1]: first window of each checkpoint segment
     int32_t n_win;
     int32_t n_ckpt;             // C segments
+    double* obs_state;          // [N][K][6] states at the observation times (forward)
+    double* obs_grad;           // [N][K][6] dL/d(state) at the observation times (backward)
     double* steps;              // [s_max][32][N]
     double* jac;                // [s_max][8][18][N]
     int32_t s_max;

@@ -672,10 +672,11 @@ static int adj_steps(const kete_opts_t* o) { return o->adj_seg_steps > 0 ? std::
 // Windows of the adjoint plan: at most 64 per checkpoint segment.
 static int64_t adjoint_max_windows(int64_t n_ckpt) { return 64 * (n_ckpt + 1) + 16; }
 
-size_t kete_adjoint_workspace_size(int64_t n_obj, double t0, double t_end, double ckpt_days, const kete_opts_t* opts) {
+size_t kete_adjoint_workspace_size(int64_t n_obj, int32_t k_obs, double t0, double t_end, double ckpt_days,
+                                   const kete_opts_t* opts) {
     kete_opts_t d;
     if (!opts) { kete_default_opts(&d); opts = &d; }
-    if (!(t_end > t0) || !(ckpt_days > 0) || n_obj < 0) return 0;
+    if (!(t_end > t0) || !(ckpt_days > 0) || n_obj < 0 || k_obs < 0) return 0;
     const int64_t C = (int64_t)std::ceil((t_end - t0) / ckpt_days - 1e-12);
     const int nbk = std::max(1, opts->n_buckets);
     Carver c{nullptr};
@@ -685,6 +686,8 @@ size_t kete_adjoint_workspace_size(int64_t n_obj, double t0, double t_end, doubl
     c.take<int32_t>((size_t)C + 1);
     c.take<double>((size_t)(C + 1) * n_obj * kCkptDoubles);
     c.take<double>((size_t)adj_steps(opts) * adjoint_step_doubles() * n_obj);
+    c.take<double>((size_t)n_obj * std::max(0, k_obs) * 6);    // observation states
+    c.take<double>((size_t)n_obj * std::max(0, k_obs) * 6);    // observation cotangents
     c.take<int32_t>(bucket_scratch_ints(n_obj, nbk));
     return c.off;
 }
@@ -715,7 +718,7 @@ int kete_propagate_adjoint(const kete_ephem_t* eph, int32_t mode, const double* 
     const int64_t C = (int64_t)seg_win.size() - 1;
     const int nbk = std::min(std::max(1, opts->n_buckets), 32);
     if (!workspace) return fail(KETE_EWORKSPACE, "workspace is null");
-    const size_t need = kete_adjoint_workspace_size(n_obj, t0, t_end, ckpt_days, opts);
+    const size_t need = kete_adjoint_workspace_size(n_obj, k_obs, t0, t_end, ckpt_days, opts);
     if (ws_bytes < need) return fail(KETE_EWORKSPACE, "workspace %zu bytes < %zu required", ws_bytes, need);
     Carver c{(char*)workspace};
     int32_t* perm = c.take<int32_t>((size_t)n_obj);
@@ -726,6 +729,8 @@ int kete_propagate_adjoint(const kete_ephem_t* eph, int32_t mode, const double* 
     int32_t* dseg = c.take<int32_t>((size_t)C + 1);
     double* ckpt = c.take<double>((size_t)(C + 1) * n_obj * kCkptDoubles);
     double* scratch = c.take<double>((size_t)adj_steps(opts) * adjoint_step_doubles() * n_obj);
+    double* obs_state = c.take<double>((size_t)n_obj * k_obs * 6);
+    double* obs_grad = c.take<double>((size_t)n_obj * k_obs * 6);
     int32_t* bscratch = c.take<int32_t>(bucket_scratch_ints(n_obj, nbk));
 
     hipStream_t s = (hipStream_t)stream;
@@ -754,6 +759,8 @@ int kete_propagate_adjoint(const kete_ephem_t* eph, int32_t mode, const double* 
     P.seg_win = dseg;
     P.n_win = (int32_t)win.size();
     P.n_ckpt = (int32_t)C;
+    P.obs_state = obs_state;
+    P.obs_grad = obs_grad;
     P.steps = scratch;
     P.jac = scratch + (size_t)adj_steps(opts) * 32 * n_obj;
     P.s_max = adj_steps(opts);

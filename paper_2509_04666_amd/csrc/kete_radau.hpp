@@ -409,6 +409,43 @@ __device__ __forceinline__ void accel8_group(const double* __restrict__ e8, cons
     F[0] = ax; F[1] = ay; F[2] = az;
 }
 
+// Jacobians Jx = da/dx, Jv = da/dv (row-major 3x3) from the grouped
+// table e8 (one node); same force as accel_jac.
+__device__ __forceinline__ void accel_jac8(const double* __restrict__ e8, const EphemArgs& E, const double X[3],
+                                           const double V[3], double Jx[9], double Jv[9]) {
+    for (int i = 0; i < 9; ++i) { Jx[i] = 0.0; Jv[i] = 0.0; }
+    for (int sl = 0; sl < E.n_body; ++sl) {
+        const double* pb = e8 + kSlot * sl;
+        const double r[3] = {X[0] - pb[0], X[1] - pb[1], X[2] - pb[2]};
+        const double r2 = dot3(r, r);
+        const double ir = rsqrt(r2);
+        const double ir2 = ir * ir, ir3 = ir2 * ir, ir5 = ir3 * ir2;
+        const double gm = pb[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                Jx[3 * i + j] += gm * (3.0 * r[i] * r[j] * ir5 - (i == j ? ir3 : 0.0));
+        if (sl < E.n_gr) {
+            const double k = pb[7];
+            const double w[3] = {V[0] - pb[4], V[1] - pb[5], V[2] - pb[6]};
+            const double w2 = dot3(w, w), rw = dot3(r, w);
+            const double s1 = 4.0 * gm * ir - w2;
+            const double P[3] = {s1 * r[0] + 4.0 * rw * w[0], s1 * r[1] + 4.0 * rw * w[1], s1 * r[2] + 4.0 * rw * w[2]};
+            const double ir6 = ir3 * ir3;
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    const double d = (i == j) ? 1.0 : 0.0;
+                    Jx[3 * i + j] += k * (-3.0 * P[i] * r[j] * ir5 - 4.0 * gm * r[i] * r[j] * ir6 + s1 * d * ir3 +
+                                          4.0 * w[i] * w[j] * ir3);
+                    Jv[3 * i + j] += k * ir3 * (-2.0 * r[i] * w[j] + 4.0 * w[i] * r[j] + 4.0 * rw * d);
+                }
+        }
+    }
+}
+
 // Step-size factor (eps / e)^(1/7) of the IAS15 control, in single
 // precision: the factor only sets the next trial step.
 __device__ __forceinline__ double step_factor(double q) {
@@ -521,10 +558,20 @@ struct G8Count {
 // Integrate one window [S.t, tb] whose Chebyshev segments seg_lo..seg_hi
 // are staged at coefL, with wave-shared adaptive steps (the 8 bodies of
 // the wavefront take the smallest step any of them asks for).
-template <int NB, int NGR, int DEG1, class Params>
+struct G8NoVisit {
+    template <class... A>
+    __device__ __forceinline__ void operator()(A&&...) const {}
+};
+
+// visit(ts, h, dn, S) is called by every lane after each accepted step,
+// before S moves to the step end (dn: this lane's converged increment,
+// e8: the step's perturber table).  With need_node0 the table also holds
+// node 0 (the step start) on every step.
+template <int NB, int NGR, int DEG1, class Params, class Visit = G8NoVisit>
 __device__ __forceinline__ void g8_integrate(const Params& p, const NodeRow& R, int node, int gl, int lane,
                                              const double* __restrict__ coefL, int bstride, double* __restrict__ e8,
-                                             int seg_lo, int seg_hi, double tb, G8State& S, G8Count& C) {
+                                             int seg_lo, int seg_hi, double tb, G8State& S, G8Count& C,
+                                             Visit&& visit = Visit(), bool need_node0 = false) {
     const EphemArgs& E = p.eph;
     const RadauConst& rc = p.rc;
     const int nb = E.n_body;
@@ -542,7 +589,7 @@ __device__ __forceinline__ void g8_integrate(const Params& p, const NodeRow& R, 
             return;
         }
         const double t_end = landed ? tb : S.t + h;
-        const int n0 = S.haveF0 ? 1 : 0;
+        const int n0 = (S.haveF0 && !need_node0) ? 1 : 0;
         node_ephemeris8<DEG1>(coefL, bstride, E, rc, seg_lo, seg_hi, S.t, h, t_end, n0, lane, e8);
         C.chain += (kNodes - n0) * E.n_gr * 3;
         C.vchain += (kNodes - n0) * (nb - E.n_gr) * 3;
@@ -569,6 +616,7 @@ __device__ __forceinline__ void g8_integrate(const Params& p, const NodeRow& R, 
             ++C.rej;
             continue;
         }
+        visit(S.t, h, dn, S);
         step_end_g8(rc, dn, h, S.x0, S.v0, S.F0);
         S.t = t_end;
         ++C.steps;
@@ -596,11 +644,15 @@ __device__ __forceinline__ double state_component(const double x0[3], const doub
 // from the monomial weights alpha_m(sig) = sum_k Ap[m][k] sig^(k+2) and
 // beta_m(sig) = sum_k Bp[m][k] sig^(k+1) (m = 1..7, k = 0..7).
 __device__ __forceinline__ void dense_weights(const RadauConst& rc, double sig, double al[7], double be[7]) {
+    // opaque zero row offset: the 112 constants are loaded where used
+    // rather than held in registers across the caller's loops
+    int z;
+    asm volatile("s_mov_b32 %0, 0" : "=s"(z));
 #pragma unroll
     for (int m = 0; m < 7; ++m) {
-        double a = rc.Ap[m][7], b = rc.Bp[m][7];
+        double a = rc.Ap[m + z][7], b = rc.Bp[m + z][7];
 #pragma unroll
-        for (int k = 6; k >= 0; --k) { a = fma(a, sig, rc.Ap[m][k]); b = fma(b, sig, rc.Bp[m][k]); }
+        for (int k = 6; k >= 0; --k) { a = fma(a, sig, rc.Ap[m + z][k]); b = fma(b, sig, rc.Bp[m + z][k]); }
         al[m] = a * sig * sig;
         be[m] = b * sig;
     }
