@@ -180,15 +180,6 @@ __device__ __forceinline__ void save_ckpt_g8(const AdjParams& p, int c, int j, i
     ck[gl] = v;
 }
 
-// Increments of all 7 nodes of this lane's group.
-__device__ __forceinline__ void gather_d(const double dn[3], double D[7][3]) {
-#pragma unroll
-    for (int m = 0; m < 7; ++m) {
-        D[m][0] = __shfl(dn[0], m, kGroup);
-        D[m][1] = __shfl(dn[1], m, kGroup);
-        D[m][2] = __shfl(dn[2], m, kGroup);
-    }
-}
 
 __device__ __forceinline__ void init_lane_state(const AdjParams& p, bool valid, int j, G8State& S) {
     S.status = 0;
@@ -240,7 +231,7 @@ __global__ __launch_bounds__(64, 3) void k_adjoint_fwd(const AdjParams p) {
         bool pend = pending();
         if (__ballot(pend) == 0ull) return;
         double D[7][3];
-        gather_d(dn, D);
+        g8_exchange(g8_xch(e8, E.n_body, lane), gl, dn, D);
         while (__ballot(pend) != 0ull) {
             if (pend) {
                 double X[3], V[3];
@@ -337,7 +328,7 @@ __global__ __launch_bounds__(64, 2) void k_adjoint_bwd(const AdjParams p) {
     double* coefL = smem;
     double* e8 = smem + (((size_t)E.n_body * bstride + 1) & ~(size_t)1);
     // exchange slots of the reverse sweep: [group][node lane][6] (W, U)
-    double* xw = e8 + (size_t)kNodes * g8_row(E.n_body) + (lane / kGroup) * kGroup * 6;
+    double* xw = e8 + (size_t)g8_wave_doubles(E.n_body) + (lane / kGroup) * kGroup * 6;
     g8_table_init(E, lane, e8);
     // per-node constants of the 8 lanes of a group, shared through LDS to
     // keep registers for the sweeps
@@ -400,7 +391,7 @@ __global__ __launch_bounds__(64, 2) void k_adjoint_bwd(const AdjParams p) {
         auto store = [&](double ts, double h, const double dn[3], const G8State& St) {
             if (ns >= p.s_max) { overflow_steps = true; return; }
             double D[7][3];
-            gather_d(dn, D);
+            g8_exchange(g8_xch(e8, E.n_body, lane), gl, dn, D);
             if (valid) {
                 double* sp = p.steps + (size_t)ns * kStepDoubles * N;
                 if (gl < 6) sp[(2 + gl) * N + gi] = state_component(St.x0, St.v0, gl);
@@ -584,7 +575,7 @@ __global__ __launch_bounds__(64, 2) void k_adjoint_bwd(const AdjParams p) {
 
 size_t adjoint_lds_bytes(const AdjParams& p) {
     return ((((size_t)p.eph.n_body * p.max_win_segs * 3 * p.eph.deg1 + 1) & ~(size_t)1) +
-            (size_t)kNodes * g8_row(p.eph.n_body) + (size_t)kWave * 6) * sizeof(double);
+            (size_t)g8_wave_doubles(p.eph.n_body) + (size_t)kWave * 6) * sizeof(double);
 }
 
 hipError_t launch_adjoint(const AdjParams& p, int mode, hipStream_t s) {

@@ -139,7 +139,7 @@ __global__ __launch_bounds__(64, 3) void k_batch_g8(const BatchParams p) {
 
 size_t batch_lds_bytes(const BatchParams& p) {
     return ((((size_t)p.eph.n_body * p.max_win_segs * 3 * p.eph.deg1 + 1) & ~(size_t)1) +
-            (size_t)kNodes * g8_row(p.eph.n_body)) * sizeof(double);
+            (size_t)g8_wave_doubles(p.eph.n_body)) * sizeof(double);
 }
 
 hipError_t launch_batch(const BatchParams& p, int waves_per_cu, hipStream_t s) {

@@ -63,13 +63,17 @@ __device__ __forceinline__ void clenshaw_n(const double* __restrict__ c, int deg
     if constexpr (DEG1 == 0) {
         clenshaw(c, deg1, tau, p, dp);
     } else {
+        static_assert(DEG1 >= 3, "compile-time chains need degree 2 or more");
         double cc[DEG1];
 #pragma unroll
         for (int k = 0; k < DEG1; ++k) cc[k] = c[k];
-        double b1 = 0.0, b2 = 0.0, d1 = 0.0, d2 = 0.0;
         const double t2 = tau + tau;
+        // the first two steps from zero start values, written out: the same
+        // numbers without the multiplications by zero
+        double b2 = cc[DEG1 - 1], b1 = fma(t2, b2, cc[DEG1 - 2]);
+        double d2 = 0.0, d1 = 2.0 * b2;
 #pragma unroll
-        for (int k = DEG1 - 1; k >= 1; --k) {
+        for (int k = DEG1 - 3; k >= 1; --k) {
             const double b0 = fma(t2, b1, cc[k] - b2);
             const double d0 = fma(t2, d1, 2.0 * b1 - d2);
             b2 = b1; b1 = b0; d2 = d1; d1 = d0;
@@ -95,13 +99,14 @@ __device__ __forceinline__ double clenshaw_value_n(const double* __restrict__ c,
     if constexpr (DEG1 == 0) {
         return clenshaw_value(c, deg1, tau);
     } else {
+        static_assert(DEG1 >= 3, "compile-time chains need degree 2 or more");
         double cc[DEG1];
 #pragma unroll
         for (int k = 0; k < DEG1; ++k) cc[k] = c[k];
-        double b1 = 0.0, b2 = 0.0;
         const double t2 = tau + tau;
+        double b2 = cc[DEG1 - 1], b1 = fma(t2, b2, cc[DEG1 - 2]);
 #pragma unroll
-        for (int k = DEG1 - 1; k >= 1; --k) {
+        for (int k = DEG1 - 3; k >= 1; --k) {
             const double b0 = fma(t2, b1, cc[k] - b2);
             b2 = b1; b1 = b0;
         }

@@ -169,10 +169,18 @@ __global__ __launch_bounds__(BLOCK, 3) void k_nbody_g8(const NbodyParams p) {
     const int bstride = p.max_win_segs * cps;
     double* coefL = smem;
     // the table is read with 16-byte loads: start it on a 16-byte boundary
-    double* e8 = smem + (((size_t)nb * bstride + 1) & ~(size_t)1) + (size_t)wid * kNodes * g8_row(nb);
+    double* e8 = smem + (((size_t)nb * bstride + 1) & ~(size_t)1) + (size_t)wid * g8_wave_doubles(nb);
     g8_table_init(E, lane, e8);
-    NodeRow R;
-    load_node_row(rc, node, R);
+    // per-node constants of the 8 lanes of a group, read from LDS in the
+    // sweeps to keep registers for more wavefronts per SIMD
+    __shared__ NodeRow rows[kGroup];
+    if (tid < kGroup) {
+        NodeRow r;
+        load_node_row(rc, tid < 7 ? tid + 1 : 7, r);
+        rows[tid] = r;
+    }
+    __syncthreads();
+    const NodeRow& R = rows[gl];
 
     const long gi = ((long)blockIdx.x * BLOCK + tid) / kGroup;
     const bool valid = gi < p.n_obj;
@@ -287,7 +295,7 @@ hipError_t launch_nbody(const NbodyParams& p, int block, int lanes_per_body, hip
                         (size_t)(block / kWave) * kNodes * p.eph.n_body * 6) * sizeof(double);
     if (lanes_per_body == kGroup) {
         const size_t lds8 = ((((size_t)p.eph.n_body * p.max_win_segs * 3 * p.eph.deg1 + 1) & ~(size_t)1) +
-                             (size_t)(block / kWave) * kNodes * g8_row(p.eph.n_body)) * sizeof(double);
+                             (size_t)(block / kWave) * g8_wave_doubles(p.eph.n_body)) * sizeof(double);
         const long threads = (long)p.n_obj * kGroup;
         const int grid = (int)((threads + block - 1) / block);
         if (grid == 0) return hipSuccess;

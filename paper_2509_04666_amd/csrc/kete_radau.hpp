@@ -231,6 +231,7 @@ constexpr int kGroup = 8;
 // Constants of one node, held in registers by the lane that owns it.
 struct NodeRow {
     double s, hs2, A[7], B[7];
+    double pad_[2];       // 144-byte rows: the 8 rows start in distinct LDS banks
 };
 
 // Row n (lane-varying, 1..7) selected from uniform constants without any
@@ -273,6 +274,37 @@ constexpr int kSlot = 8;
 // together by an 8-lane group fall in distinct LDS banks.
 __host__ __device__ inline int g8_row(int n_body) { return n_body * kSlot + 2; }
 
+// Increment exchange of the grouped corrector, after the wave's node
+// table: per 8-lane group three rows (x, y, z) of 8 doubles, lane k
+// writing column k, padded to 26 doubles so that the 16-byte reads of the
+// 8 groups of a wavefront fall in distinct LDS banks.
+constexpr int kXchGroup = 26;
+// Doubles of LDS per wavefront: node table plus exchange rows.
+__host__ __device__ inline int g8_wave_doubles(int n_body) { return kNodes * g8_row(n_body) + kGroup * kXchGroup; }
+__device__ __forceinline__ double* g8_xch(double* e8, int n_body, int lane) {
+    return e8 + kNodes * g8_row(n_body) + (lane / kGroup) * kXchGroup;
+}
+
+// Publish this lane's increment dn (node gl + 1) and read the increments
+// D[m] of nodes m + 1 = 1..7 of the group.  Every lane of the wavefront
+// takes part.
+__device__ __forceinline__ void g8_exchange(double* __restrict__ xg, int gl, const double dn[3], double D[7][3]) {
+    wave_lds_sync();                        // earlier reads of the rows are done
+    xg[gl] = dn[0];
+    xg[8 + gl] = dn[1];
+    xg[16 + gl] = dn[2];
+    wave_lds_sync();
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double2 v = *reinterpret_cast<const double2*>(xg + 8 * c + 2 * k);
+            D[2 * k][c] = v.x;
+            if (2 * k + 1 < 7) D[2 * k + 1][c] = v.y;
+        }
+    }
+}
+
 __device__ __forceinline__ void g8_table_init(const EphemArgs& E, int lane, double* __restrict__ e8) {
     for (int b = 0; b < E.n_body; ++b) {
         const int sl = body_slot(E, b);
@@ -283,47 +315,63 @@ __device__ __forceinline__ void g8_table_init(const EphemArgs& E, int lane, doub
     }
 }
 
-// Perturber states at node times n0..8 of a step (node 0 is only needed
-// before the first step; later steps reuse the force at the previous
-// step end).  Chains with a velocity come first so lanes of one pass do
-// equal work.
-template <int DEG1>
+// Perturber states at the node times of a step.  Lane k of each 8-lane
+// group takes node (k & 7) + 1 (node 8 is the step end) and finds that
+// node's segment and tau once; the 3 n_body coordinates are spread over
+// the 8 groups (group g takes coordinates g, g + 8, ...).  Coordinates of
+// the slots with the Eq. A.3 term come first and also get the velocity
+// (derivative chain); a pass holding any of them evaluates derivatives in
+// every lane so the wavefront does not diverge.  Node 0 (the step start,
+// needed before the first step or when the caller asks) takes one more
+// pass with coordinate = lane.  s_lane: node fraction of node (k & 7) + 1
+// for k & 7 < 7.
+template <int NB, int NGR, int DEG1>
 __device__ __forceinline__ void node_ephemeris8(const double* __restrict__ coefL, int bstride, const EphemArgs& E,
-                                                const RadauConst& rc, int seg_lo, int seg_hi, double t, double h,
-                                                double t_end, int n0, int lane, double* __restrict__ e8) {
-    const int nb = E.n_body, ngr = E.n_gr, deg1 = E.deg1, cps = 3 * deg1;
-    const int nn = kNodes - n0;
-    auto tau_of = [&](int n, int& k) {
-        const double tt = (n == kNodes - 1) ? t_end : t + rc.s[n] * h;
-        k = seg_index(tt, E.t_start, E.inv_seg, seg_lo, seg_hi);
-        return 2.0 * (tt - (E.t_start + (double)k * E.seg_days)) * E.inv_seg - 1.0;
+                                                double s_lane, int seg_lo, int seg_hi, double t, double h,
+                                                double t_end, bool node0, int lane, double* __restrict__ e8) {
+    const int nb = NB > 0 ? NB : E.n_body;
+    const int ngr = NB > 0 ? NGR : E.n_gr;
+    const int deg1 = DEG1 > 0 ? DEG1 : E.deg1;
+    const int cps = 3 * deg1, nc = 3 * nb, ngc = 3 * ngr;
+    const double sc = 2.0 * E.inv_seg;
+    auto chains = [&](int n, double tt, int c0, int cstep, int npass) {
+        const int k = seg_index(tt, E.t_start, E.inv_seg, seg_lo, seg_hi);
+        const double tau = 2.0 * (tt - (E.t_start + (double)k * E.seg_days)) * E.inv_seg - 1.0;
+        const double* cb = coefL + (k - seg_lo) * cps;
+        double* row = e8 + n * g8_row(nb);
+        // one chain in flight per lane: the coefficient loads of several
+        // unrolled passes would crowd out the integrator state
+#pragma unroll 1
+        for (int j = 0; j < npass; ++j) {
+            const int c = c0 + cstep * j;
+            if (c >= nc) continue;
+            const int sl = c / 3, i = c - 3 * sl;
+            const double* cp = cb + slot_body(E, sl) * bstride + i * deg1;
+            if (cstep * j < ngc) {                 // wave-uniform: the pass holds derivative chains
+                double pv, dv;
+                clenshaw_n<DEG1>(cp, deg1, tau, pv, dv);
+                row[sl * kSlot + i] = pv;
+                if (c < ngc) row[sl * kSlot + 4 + i] = dv * sc;
+            } else {
+                row[sl * kSlot + i] = clenshaw_value_n<DEG1>(cp, deg1, tau);
+            }
+        }
     };
-    const int n_vel = nn * ngr * 3;
-    for (int c = lane; c < n_vel; c += kWave) {
-        const int n = n0 + c / (ngr * 3);
-        const int r = c % (ngr * 3);
-        const int sl = r / 3, i = r - 3 * sl;
-        const int b = slot_body(E, sl);
-        int k;
-        const double tau = tau_of(n, k);
-        double pv, dv;
-        clenshaw_n<DEG1>(coefL + b * bstride + (k - seg_lo) * cps + i * deg1, deg1, tau, pv, dv);
-        e8[n * g8_row(nb) + sl * kSlot + i] = pv;
-        e8[n * g8_row(nb) + sl * kSlot + 4 + i] = dv * 2.0 * E.inv_seg;
-    }
-    const int npl = nb - ngr;
-    const int n_pos = nn * npl * 3;
-    for (int c = lane; c < n_pos; c += kWave) {
-        const int n = n0 + c / (npl * 3);
-        const int r = c % (npl * 3);
-        const int sl = ngr + r / 3, i = r % 3;
-        const int b = slot_body(E, sl);
-        int k;
-        const double tau = tau_of(n, k);
-        e8[n * g8_row(nb) + sl * kSlot + i] =
-            clenshaw_value_n<DEG1>(coefL + b * bstride + (k - seg_lo) * cps + i * deg1, deg1, tau);
-    }
+    const int gl = lane & (kGroup - 1);
+    chains(gl + 1, gl == kGroup - 1 ? t_end : t + s_lane * h, lane / kGroup, kGroup, (nc + kGroup - 1) / kGroup);
+    if (node0) chains(0, t, lane, kWave, 1);
     wave_lds_sync();
+}
+
+// 1/sqrt(x) for a positive normal x: the hardware estimate y0 times the
+// series (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8 + O(e^3), e = 1 - x y0^2.  The
+// truncation leaves a relative error of about 5e^3/16, below an ulp when
+// the estimate is good to 2^-19.  No special-value handling: a zero or
+// non-finite x gives a non-finite result, reported as a failed body.
+__device__ __forceinline__ double rsqrt_pos(double x) {
+    const double y0 = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * y0, y0, 1.0);
+    return fma(y0 * e, fma(e, 0.375, 0.5), y0);
 }
 
 // Force of Eqs. A.1 + A.3 from the grouped table e8 (one node): slots
@@ -344,7 +392,7 @@ __device__ __forceinline__ void accel8(const double* __restrict__ e8, const Ephe
         const double2 vzk = *reinterpret_cast<const double2*>(pb + 6);
         const double rx = X[0] - pxy.x, ry = X[1] - pxy.y, rz = X[2] - pzg.x;
         const double r2 = fma(rx, rx, fma(ry, ry, rz * rz));
-        const double ir = rsqrt(r2);
+        const double ir = rsqrt_pos(r2);
         const double ir3 = ir * ir * ir;
         const double gm = pzg.y;
         const double wx = V[0] - vxy.x, wy = V[1] - vxy.y, wz = V[2] - vzk.x;
@@ -364,7 +412,7 @@ __device__ __forceinline__ void accel8(const double* __restrict__ e8, const Ephe
         const double2 pzg = *reinterpret_cast<const double2*>(pb + 2);
         const double rx = X[0] - pxy.x, ry = X[1] - pxy.y, rz = X[2] - pzg.x;
         const double r2 = fma(rx, rx, fma(ry, ry, rz * rz));
-        const double ir = rsqrt(r2);
+        const double ir = rsqrt_pos(r2);
         const double f = -pzg.y * (ir * ir * ir);
         ax = fma(f, rx, ax); ay = fma(f, ry, ay); az = fma(f, rz, az);
     }
@@ -383,7 +431,7 @@ __device__ __forceinline__ void accel8_group(const double* __restrict__ e8, cons
         const double2 pzg = *reinterpret_cast<const double2*>(pb + 2);
         const double rx = X[0] - pxy.x, ry = X[1] - pxy.y, rz = X[2] - pzg.x;
         const double r2 = fma(rx, rx, fma(ry, ry, rz * rz));
-        const double ir = rsqrt(r2);
+        const double ir = rsqrt_pos(r2);
         const double ir3 = ir * ir * ir;
         const double gm = pzg.y;
         double f = -gm * ir3;
@@ -461,7 +509,8 @@ __device__ __forceinline__ double step_factor(double q) {
 // coefficient and d6 the increment of node 7 (all lanes).
 template <int NB, int NGR>
 __device__ __forceinline__ int corrector_g8(const RadauConst& rc, const EphemArgs& E, const double* __restrict__ e8,
-                                            const NodeRow& R, int node, const double x0[3], const double v0[3],
+                                            double* __restrict__ xg, int gl, const NodeRow& R, int node,
+                                            const double x0[3], const double v0[3],
                                             const double F0[3], double h, bool active, int max_iter, double dn[3],
                                             double b6[3], double d6[3]) {
     const double hh = h * h, sh = R.s * h;
@@ -476,11 +525,13 @@ __device__ __forceinline__ int corrector_g8(const RadauConst& rc, const EphemArg
 #pragma unroll
         for (int c = 0; c < 3; ++c) { ax[c] = R.hs2 * F0[c]; av[c] = R.s * F0[c]; bb[c] = 0.0; }
         if (it > 0) {
+            double D[7][3];
+            g8_exchange(xg, gl, dn, D);
 #pragma unroll
             for (int m = 0; m < 7; ++m) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    const double d = __shfl(dn[c], m, kGroup);
+                    const double d = D[m][c];
                     ax[c] = fma(R.A[m], d, ax[c]);
                     av[c] = fma(R.B[m], d, av[c]);
                     bb[c] = fma(rc.E6[m], d, bb[c]);
@@ -495,7 +546,8 @@ __device__ __forceinline__ int corrector_g8(const RadauConst& rc, const EphemArg
                 b6[c] = bb[c];
                 fm = fmax(fm, fabs(d6[c] + F0[c]));
             }
-            const double lpc = (active && fm > 0.0) ? db / fm : 0.0;
+            // the ratio only steers the stopping rule: the reciprocal estimate suffices
+            const double lpc = (active && fm > 0.0) ? db * __builtin_amdgcn_rcp(fm) : 0.0;
             pc = groups_max(lpc);
             if (pc < 1e-16 || (it > 2 && pcl <= pc) || it >= max_iter) break;
         }
@@ -503,7 +555,7 @@ __device__ __forceinline__ int corrector_g8(const RadauConst& rc, const EphemArg
         double X[3], V[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) X[c] = fma(hh, ax[c], fma(sh, v0[c], x0[c]));
-        if (E.has_gr) {
+        if (NB > 0 ? NGR > 0 : E.has_gr) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) V[c] = fma(h, av[c], v0[c]);
         } else {
@@ -518,9 +570,11 @@ __device__ __forceinline__ int corrector_g8(const RadauConst& rc, const EphemArg
 }
 
 // Step end of a group-integrated body from the converged increments.
-__device__ __forceinline__ void step_end_g8(const RadauConst& rc, const double dn[3], double h, double x0[3],
-                                            double v0[3], const double F0[3]) {
+__device__ __forceinline__ void step_end_g8(const RadauConst& rc, double* __restrict__ xg, int gl, const double dn[3],
+                                            double h, double x0[3], double v0[3], const double F0[3]) {
     double ax[3], av[3];
+    double D[7][3];
+    g8_exchange(xg, gl, dn, D);
     // opaque zero row offset: the constants are loaded where used instead
     // of being held in (spilled) scalar registers for the whole kernel
     int z;
@@ -531,7 +585,7 @@ __device__ __forceinline__ void step_end_g8(const RadauConst& rc, const double d
     for (int m = 0; m < 7; ++m) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const double d = __shfl(dn[c], m, kGroup);
+            const double d = D[m][c];
             ax[c] = fma(rc.A[8 + z][m], d, ax[c]);
             av[c] = fma(rc.B[8 + z][m], d, av[c]);
         }
@@ -575,6 +629,7 @@ __device__ __forceinline__ void g8_integrate(const Params& p, const NodeRow& R, 
     const EphemArgs& E = p.eph;
     const RadauConst& rc = p.rc;
     const int nb = E.n_body;
+    double* xg = g8_xch(e8, nb, lane);
     if (__ballot(S.active) == 0ull) { S.t = tb; return; }
     while (S.t != tb) {
         const double dir = tb > S.t ? 1.0 : -1.0;
@@ -590,14 +645,14 @@ __device__ __forceinline__ void g8_integrate(const Params& p, const NodeRow& R, 
         }
         const double t_end = landed ? tb : S.t + h;
         const int n0 = (S.haveF0 && !need_node0) ? 1 : 0;
-        node_ephemeris8<DEG1>(coefL, bstride, E, rc, seg_lo, seg_hi, S.t, h, t_end, n0, lane, e8);
+        node_ephemeris8<NB, NGR, DEG1>(coefL, bstride, E, R.s, seg_lo, seg_hi, S.t, h, t_end, n0 == 0, lane, e8);
         C.chain += (kNodes - n0) * E.n_gr * 3;
         C.vchain += (kNodes - n0) * (nb - E.n_gr) * 3;
         if (!S.haveF0) { accel8<NB, NGR>(e8, E, S.x0, S.v0, S.F0); S.haveF0 = true; }
 
         double dn[3], b6p[3], d6[3];
-        const int it = corrector_g8<NB, NGR>(rc, E, e8, R, node, S.x0, S.v0, S.F0, h, S.active, p.max_iter, dn,
-                                             b6p, d6);
+        const int it = corrector_g8<NB, NGR>(rc, E, e8, xg, gl, R, node, S.x0, S.v0, S.F0, h, S.active, p.max_iter,
+                                             dn, b6p, d6);
         C.iter += it;
         const unsigned long long n_act = __popcll(__ballot(S.active)) / kGroup;
         C.liter += (unsigned long long)it * n_act;
@@ -617,7 +672,7 @@ __device__ __forceinline__ void g8_integrate(const Params& p, const NodeRow& R, 
             continue;
         }
         visit(S.t, h, dn, S);
-        step_end_g8(rc, dn, h, S.x0, S.v0, S.F0);
+        step_end_g8(rc, xg, gl, dn, h, S.x0, S.v0, S.F0);
         S.t = t_end;
         ++C.steps;
         C.lsteps += n_act;
