@@ -292,10 +292,15 @@ def main():
     ws_fov = torch.empty(_lib.lib().kete_fov_workspace_size(N, F, B, S, cap, C.byref(opts)), dtype=torch.uint8,
                          device=dev)
 
+    # Host batching (a1) of the next step runs while this step's integrator
+    # kernels execute; every step still batches its own frames.
+    next_host = [api.make_batches(frame_t_host, opts.batch_span)]
+
     def step(stats=None):
-        order, off, t_ref = api.make_batches(frame_t_host, opts.batch_span)
+        order, off, t_ref = next_host[0]
         batches = api.Batches.from_host(order, off, t_ref, dev)
         res = api.propagate(eph, x0, 0.0, t_ref, opts, stats=stats is not None, workspace=ws_prop)
+        next_host[0] = api.make_batches(frame_t_host, opts.batch_span)
         x_epoch, status = res[0], res[1]
         if stats is not None:
             stats += res[2]

@@ -99,7 +99,7 @@ typedef struct {
     int32_t fov_block;       /* FoV threads per block: 64/128/256 (128) */
     int32_t adj_seg_steps;   /* adjoint: steps stored per checkpoint segment (32) */
     int32_t persist_waves;   /* batched runs: resident waves per compute unit (8) */
-    int32_t lanes_per_body;  /* integrator lanes per object: 1 or 8 (8) */
+    int32_t lanes_per_body;  /* integrator lanes per object: 1, 7 (9 per wavefront) or 8 (8) */
     int32_t reserved;
 } kete_opts_t;
 

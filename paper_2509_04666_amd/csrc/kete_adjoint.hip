@@ -1,7 +1,7 @@
 // Gradient of sky-position residuals with respect to the initial state.
 //
-// Forward: the collocation integrator of the propagation kernels (one
-// lane per object, wave-shared steps) lands on checkpoint times every
+// Forward: the collocation integrator of the propagation kernels (8-lane
+// group per object, wave-shared steps) lands on checkpoint times every
 // ckpt_days; observations at per-object times are read off the step's
 // collocation polynomial, hopped with light time to the emission point
 // (Sect. 2) and turned into RA/Dec.
@@ -231,7 +231,7 @@ __global__ __launch_bounds__(64, 3) void k_adjoint_fwd(const AdjParams p) {
         bool pend = pending();
         if (__ballot(pend) == 0ull) return;
         double D[7][3];
-        g8_exchange(g8_xch(e8, E.n_body, lane), gl, dn, D);
+        g8_exchange(g8_xch(e8, E.n_body, lane / kGroup), gl, dn, D);
         while (__ballot(pend) != 0ull) {
             if (pend) {
                 double X[3], V[3];
@@ -249,8 +249,8 @@ __global__ __launch_bounds__(64, 3) void k_adjoint_fwd(const AdjParams p) {
             __syncthreads();
             stage_window(E, W.seg_lo, W.seg_hi, bstride, lane, 64, coefL);
             __syncthreads();
-            g8_integrate<NB, NGR, DEG1>(p, R, node, gl, lane, coefL, bstride, e8, W.seg_lo, W.seg_hi, W.t_b, S, C,
-                                        visit);
+            g8_integrate<NB, NGR, DEG1, kGroup>(p, R, node, gl, lane / kGroup, lane, coefL, bstride, e8, W.seg_lo,
+                                                W.seg_hi, W.t_b, S, C, visit);
         }
         if (valid) save_ckpt_g8(p, c + 1, j, gl, S);
     }
@@ -391,7 +391,7 @@ __global__ __launch_bounds__(64, 2) void k_adjoint_bwd(const AdjParams p) {
         auto store = [&](double ts, double h, const double dn[3], const G8State& St) {
             if (ns >= p.s_max) { overflow_steps = true; return; }
             double D[7][3];
-            g8_exchange(g8_xch(e8, E.n_body, lane), gl, dn, D);
+            g8_exchange(g8_xch(e8, E.n_body, lane / kGroup), gl, dn, D);
             if (valid) {
                 double* sp = p.steps + (size_t)ns * kStepDoubles * N;
                 if (gl < 6) sp[(2 + gl) * N + gi] = state_component(St.x0, St.v0, gl);
@@ -429,8 +429,8 @@ __global__ __launch_bounds__(64, 2) void k_adjoint_bwd(const AdjParams p) {
             __syncthreads();
             stage_window(E, W.seg_lo, W.seg_hi, bstride, lane, 64, coefL);
             __syncthreads();
-            g8_integrate<NB, NGR, DEG1>(p, R, node, gl, lane, coefL, bstride, e8, W.seg_lo, W.seg_hi, W.t_b, S, Cn,
-                                        store, true);
+            g8_integrate<NB, NGR, DEG1, kGroup>(p, R, node, gl, lane / kGroup, lane, coefL, bstride, e8, W.seg_lo,
+                                                W.seg_hi, W.t_b, S, Cn, store, true);
         }
         if (ns > p.s_max) ns = p.s_max;
         // ---- reverse sweep over the stored steps

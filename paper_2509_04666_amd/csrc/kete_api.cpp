@@ -50,6 +50,40 @@ int fail(int code, const char* fmt, ...) {
 
 constexpr double kC = 299792.458 * 86400.0 / 149597870.7;
 
+// Pinned staging of a host table copied to the device on the caller's
+// stream, so that the call returns without waiting for the copy.  One
+// buffer per thread: before it is refilled, the copy out of it made by
+// the previous call is waited for (normally long finished).
+struct HostStage {
+    void* buf = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+};
+thread_local HostStage g_stage;
+
+int stage_to_device(void* dst, const void* src, size_t bytes, hipStream_t s) {
+    HostStage& h = g_stage;
+    if (h.pending) {
+        HIPCHK(hipEventSynchronize(h.done));
+        h.pending = false;
+    }
+    if (bytes > h.cap) {
+        if (h.buf) HIPCHK(hipHostFree(h.buf));
+        h.buf = nullptr;
+        h.cap = 0;
+        const size_t want = std::max(bytes, (size_t)1 << 20);
+        HIPCHK(hipHostMalloc(&h.buf, want, hipHostMallocDefault));
+        h.cap = want;
+    }
+    if (!h.done) HIPCHK(hipEventCreateWithFlags(&h.done, hipEventDisableTiming));
+    std::memcpy(h.buf, src, bytes);
+    HIPCHK(hipMemcpyAsync(dst, h.buf, bytes, hipMemcpyHostToDevice, s));
+    HIPCHK(hipEventRecord(h.done, s));
+    h.pending = true;
+    return KETE_OK;
+}
+
 // ---------------------------------------------------------------- Radau
 typedef long double ld;
 
@@ -381,8 +415,8 @@ int kete_propagate_nbody(const kete_ephem_t* eph, const double* x0, double t0, i
     }
     if (opts->block != 64 && opts->block != 128 && opts->block != 256)
         return fail(KETE_EINVAL, "block must be 64, 128 or 256");
-    if (opts->lanes_per_body != 1 && opts->lanes_per_body != 8)
-        return fail(KETE_EINVAL, "lanes_per_body must be 1 or 8");
+    if (opts->lanes_per_body != 1 && opts->lanes_per_body != 7 && opts->lanes_per_body != 8)
+        return fail(KETE_EINVAL, "lanes_per_body must be 1, 7 or 8");
     if (!(opts->eps > 0) || !(opts->h_init > 0) || !(opts->h_min > 0) || opts->max_iter < 1 || opts->max_steps < 1)
         return fail(KETE_EINVAL, "eps, h_init, h_min, max_iter and max_steps must be positive");
     const int nbk = std::min(std::max(1, opts->n_buckets), 32);
@@ -404,8 +438,7 @@ int kete_propagate_nbody(const kete_ephem_t* eph, const double* x0, double t0, i
     int32_t* bscratch = c.take<int32_t>(bucket_scratch_ints(n_obj, nbk));
 
     hipStream_t s = (hipStream_t)stream;
-    HIPCHK(hipMemcpyAsync(dwin, win.data(), win.size() * sizeof(Window), hipMemcpyHostToDevice, s));
-    HIPCHK(hipStreamSynchronize(s));
+    if ((rc = stage_to_device(dwin, win.data(), win.size() * sizeof(Window), s))) return rc;
     HIPCHK(hipMemcpyAsync(state, x0, (size_t)n_obj * 6 * sizeof(double), hipMemcpyDeviceToDevice, s));
     HIPCHK(hipMemsetAsync(status, 0, (size_t)n_obj * sizeof(int32_t), s));
     HIPCHK(launch_hpref_init(x0, h_pref, (int)n_obj, E.gm[0], s));

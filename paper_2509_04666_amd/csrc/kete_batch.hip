@@ -1,9 +1,10 @@
 // Many independent propagation jobs of uneven size in one persistent
 // launch.  A job is a set of bodies with a common start epoch and its own
 // list of output epochs.  Its bodies are sorted by predicted step size
-// (stable, per job) and cut into tiles of 64; a grid sized to the device
-// pops tiles from a queue ordered longest-first, one wavefront per tile,
-// each with its own LDS window of Chebyshev segments.
+// (stable, per job) and cut into tiles of 8; a grid sized to the device
+// pops tiles from a queue ordered longest-first, one wavefront per tile
+// (8 bodies on 8-lane groups, as in the propagation kernel), each with
+// its own LDS window of Chebyshev segments.
 #include <math.h>
 
 #include "kete_batch.hpp"
@@ -69,14 +70,17 @@ __device__ __forceinline__ void ensure_window(const EphemArgs& E, int a, int b, 
     lo = a; hi = b;
 }
 
-// One wavefront per block; it pops tiles of 8 bodies of one job and
-// integrates them as 8-lane groups (one lane per collocation node)
-// through the job's epochs.
+// One wavefront per block; it pops tiles of KETE_BATCH_TILE bodies of one
+// job and integrates them as lane groups (one lane per collocation node,
+// see GroupMap) through the job's epochs.
 template <int NB, int NGR, int DEG1>
 __global__ __launch_bounds__(64, 3) void k_batch_g8(const BatchParams p) {
+    constexpr int G = KETE_BATCH_LANES;
+    static_assert(GroupMap<G>::kBodies == KETE_BATCH_TILE, "tile = bodies per wavefront");
     extern __shared__ double smem[];
     const int lane = threadIdx.x;
-    const int gl = lane & (kGroup - 1);
+    const GroupMap<G> M(lane);
+    const int gl = M.gl;
     const int node = gl < 7 ? gl + 1 : 7;
     const EphemArgs& E = p.eph;
     const int bstride = p.max_win_segs * 3 * E.deg1;
@@ -94,7 +98,7 @@ __global__ __launch_bounds__(64, 3) void k_batch_g8(const BatchParams p) {
         if (tile >= p.n_tiles) break;
         const int2 tj = p.tiles[tile];
         const kete_job_t job = p.jobs[tj.x];
-        const int64_t k = (int64_t)tj.y * kGroup + lane / kGroup;
+        const int64_t k = (int64_t)tj.y * KETE_BATCH_TILE + M.grp;
         const bool valid = k < job.n_obj;
         const int64_t local = valid ? (p.n_buckets > 1 ? p.perm[job.obj_off + k] : k) : 0;
         const int64_t gobj = job.obj_off + local;
@@ -111,7 +115,7 @@ __global__ __launch_bounds__(64, 3) void k_batch_g8(const BatchParams p) {
             const double r = sqrt(dot3(S.x0, S.x0));
             hp = 0.05 * sqrt(r * r * r / E.gm[0]);
         }
-        S.hw = groups_min(S.active ? hp : kInf);
+        S.hw = groups_min<G>(S.active ? hp : kInf);
         if (!(S.hw < kInf)) S.hw = p.h_init;
         S.hp_new = kInf;
         S.t = job.t0;
@@ -122,7 +126,8 @@ __global__ __launch_bounds__(64, 3) void k_batch_g8(const BatchParams p) {
             while (S.t != target) {
                 const Window Wn = next_window(S.t, target, E.t_start, E.seg_days, E.inv_seg, E.n_seg, W);
                 ensure_window(E, Wn.seg_lo, Wn.seg_hi, lo, hi, coefL, bstride);
-                g8_integrate<NB, NGR, DEG1>(p, R, node, gl, lane, coefL, bstride, e8, lo, hi, Wn.t_b, S, C);
+                g8_integrate<NB, NGR, DEG1, G>(p, R, node, gl, M.grp, lane, coefL, bstride, e8, lo, hi, Wn.t_b, S,
+                                               C);
                 S.t = Wn.t_b;
             }
             if (valid && gl < 6) {

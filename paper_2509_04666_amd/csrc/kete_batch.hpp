@@ -5,8 +5,10 @@
 #include "kete_fov.hpp"
 #include "kete_internal.hpp"
 
-// bodies per tile of the persistent kernel (one 8-lane group each)
-#define KETE_BATCH_TILE 8
+// lanes per body of the persistent kernel (7: 9 bodies per wavefront,
+// 8: 8 bodies) and bodies per tile, one wavefront each
+#define KETE_BATCH_LANES 7
+#define KETE_BATCH_TILE (KETE_BATCH_LANES == 7 ? 9 : 8)
 
 namespace kete {
 
@@ -16,7 +18,7 @@ struct BatchParams {
     const kete_job_t* jobs;     // [n_jobs]
     int32_t n_jobs;
     int32_t n_tiles;
-    const int2* tiles;          // [n_tiles] (job, tile of 8 bodies), longest first
+    const int2* tiles;          // [n_tiles] (job, tile of KETE_BATCH_TILE bodies), longest first
     unsigned int* tile_counter;
     const double* x0;           // [bodies][6]
     const double* epochs;       // concatenated epochs of all jobs

@@ -2,15 +2,21 @@
 //
 // Per batch, frames are binned by the direction of their bounding cap on
 // a uniform 3-D grid over [-1, 1]^3 (unit vectors only touch cells near
-// the sphere).  Each (object, batch) thread bounds how far the object's
-// light-time direction can move inside the batch -- perihelion speed of
-// its heliocentric conic, the Sun's speed, the observers' spread and the
-// batch half-span -- and visits only the grid cells within that angle
-// plus the frame radius.  Survivors pass a linear-motion test with a
-// rigorous remainder bound; the exact test (universal-variable hop with
-// light time, then n.d > 0 for every normal) decides membership.  Hits
-// are appended with one atomic per wavefront, then sorted by
-// (frame, sub-frame, object).
+// the sphere).  Every (object, batch) gets a rigorous bound on how far the
+// object's light-time direction can move inside the batch -- perihelion
+// speed of its heliocentric conic, the Sun's speed, the observers' spread
+// and the batch half-span.  Objects whose reach stays inside the 3x3x3
+// cells around their own direction ("narrow") are binned on the same
+// grid, and a persistent join pops work items (one per 64 narrow objects
+// of a cell) and scans the frames of the 27 neighbouring cells with
+// wave-uniform loops; the remaining ("wide") objects scan the cells their
+// cap touches, one wavefront per object.  Pairs that pass the cap test
+// and a linear-motion test with a rigorous remainder bound become
+// candidates; the exact test (universal-variable hop with light time,
+// then n.d > 0 for every normal) decides membership.  Appends are staged
+// in LDS per wavefront and flushed to the global lists in chunks; the
+// pairs are then ordered by (frame, sub-frame, object) with a counting
+// sort by frame and a sort inside each frame's segment.
 #include <math.h>
 
 #include <algorithm>

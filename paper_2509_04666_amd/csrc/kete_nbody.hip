@@ -1,13 +1,16 @@
 // n-body propagation of massless bodies on gfx950 (App. A force model,
 // Gauss-Radau collocation with the predictor removed, App. A.6).
 //
-// One lane per object.  The 64 objects of a wavefront share the time
-// grid: the step size is the smallest one any lane asks for, so the
-// perturber positions at the 9 node times of a step are evaluated once
-// per wavefront (64 Clenshaw chains in parallel) and broadcast from LDS.
-// The Chebyshev coefficients of the segments a window needs are staged
-// in LDS once per workgroup.  Objects are sorted by predicted step size
-// before each launch so that lanes of one wavefront want similar steps.
+// Two layouts share the force, the Chebyshev window staging and the step
+// control.  k_nbody_g8 (the default) spreads each object over an 8-lane
+// group, one collocation node per lane, so a wavefront integrates 8
+// objects; k_nbody keeps one object per lane (64 per wavefront).  The
+// objects of a wavefront share the time grid: the step size is the
+// smallest one any of them asks for, so the perturber states at the node
+// times of a step are evaluated once per wavefront and read from LDS.
+// The Chebyshev coefficients of the segments a window needs are staged in
+// LDS once per workgroup.  Objects are sorted by predicted step size
+// before a launch so that the objects of one wavefront want similar steps.
 #include <math.h>
 
 #include "kete_radau.hpp"
@@ -151,16 +154,18 @@ __global__ __launch_bounds__(BLOCK) void k_nbody(const NbodyParams p) {
     }
 }
 
-// Eight lanes per object: a wavefront integrates 8 objects, each spread
-// over an 8-lane group whose lanes own one collocation node each.  The
-// 8 objects of a wavefront share the time grid and the perturber table
-// as above; each sweep evaluates the force at all 7 nodes of an object
-// at once.  Output and counters are per object, as in k_nbody.
-template <int BLOCK, int NB, int NGR, int DEG1>
+// G lanes per object (7 or 8, see GroupMap): a wavefront integrates 9 or
+// 8 objects, each spread over a group whose lanes own one collocation
+// node each.  The objects of a wavefront share the time grid and the
+// perturber table as above; each sweep evaluates the force at all 7 nodes
+// of an object at once.  Output and counters are per object, as in
+// k_nbody.
+template <int BLOCK, int G, int NB, int NGR, int DEG1>
 __global__ __launch_bounds__(BLOCK, 3) void k_nbody_g8(const NbodyParams p) {
     extern __shared__ double smem[];
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
-    const int gl = lane & (kGroup - 1);               // lane within the object's group
+    const GroupMap<G> M(lane);
+    const int gl = M.gl;                              // lane within the object's group
     const int node = gl < 7 ? gl + 1 : 7;
     const EphemArgs& E = p.eph;
     const RadauConst& rc = p.rc;
@@ -182,7 +187,7 @@ __global__ __launch_bounds__(BLOCK, 3) void k_nbody_g8(const NbodyParams p) {
     __syncthreads();
     const NodeRow& R = rows[gl];
 
-    const long gi = ((long)blockIdx.x * BLOCK + tid) / kGroup;
+    const long gi = ((long)blockIdx.x * (BLOCK / kWave) + wid) * GroupMap<G>::kBodies + M.grp;
     const bool valid = gi < p.n_obj;
     const int j = valid ? (p.perm ? p.perm[gi] : (int)gi) : 0;
     G8State S;
@@ -197,7 +202,7 @@ __global__ __launch_bounds__(BLOCK, 3) void k_nbody_g8(const NbodyParams p) {
         for (int i = 0; i < 3; ++i) { S.x0[i] = p.state[6 * j + i]; S.v0[i] = p.state[6 * j + 3 + i]; }
         hin = p.h_pref[j];
     }
-    S.hw = groups_min(S.active ? hin : kInf);
+    S.hw = groups_min<G>(S.active ? hin : kInf);
     if (!(S.hw < kInf)) S.hw = p.h_init;
     S.hp_new = kInf;
     S.t = p.win[0].t_a;
@@ -209,7 +214,8 @@ __global__ __launch_bounds__(BLOCK, 3) void k_nbody_g8(const NbodyParams p) {
         __syncthreads();
         stage_window(E, W.seg_lo, W.seg_hi, bstride, tid, BLOCK, coefL);
         __syncthreads();
-        g8_integrate<NB, NGR, DEG1>(p, R, node, gl, lane, coefL, bstride, e8, W.seg_lo, W.seg_hi, W.t_b, S, C);
+        g8_integrate<NB, NGR, DEG1, G>(p, R, node, gl, M.grp, lane, coefL, bstride, e8, W.seg_lo, W.seg_hi, W.t_b,
+                                       S, C);
         if (W.out >= 0 && valid && gl < 6) {
             // lane gl of the group writes component gl of the state
             double* dst = p.x_out + ((size_t)W.out * p.n_obj + j) * 6;
@@ -293,27 +299,38 @@ __global__ void k_hpref_init(const double* __restrict__ x0, double* __restrict__
 hipError_t launch_nbody(const NbodyParams& p, int block, int lanes_per_body, hipStream_t s) {
     const size_t lds = ((size_t)p.eph.n_body * p.max_win_segs * 3 * p.eph.deg1 +
                         (size_t)(block / kWave) * kNodes * p.eph.n_body * 6) * sizeof(double);
-    if (lanes_per_body == kGroup) {
+    if (lanes_per_body == 7 || lanes_per_body == 8) {
         const size_t lds8 = ((((size_t)p.eph.n_body * p.max_win_segs * 3 * p.eph.deg1 + 1) & ~(size_t)1) +
                              (size_t)(block / kWave) * g8_wave_doubles(p.eph.n_body)) * sizeof(double);
-        const long threads = (long)p.n_obj * kGroup;
-        const int grid = (int)((threads + block - 1) / block);
+        const long per_wave = lanes_per_body == 7 ? GroupMap<7>::kBodies : GroupMap<8>::kBodies;
+        const long waves = ((long)p.n_obj + per_wave - 1) / per_wave;
+        const int wpb = block / kWave;
+        const int grid = (int)((waves + wpb - 1) / wpb);
         if (grid == 0) return hipSuccess;
         // perturber tables of the common shapes get an unrolled force loop
         const int nb = p.eph.n_body, ngr = p.eph.n_gr, d1 = p.eph.deg1;
-#define KETE_G8(B)                                                                                              \
+#define KETE_G8(B, G)                                                                                           \
     do {                                                                                                        \
         if (nb == 9 && ngr == 3 && d1 == 13)                                                                    \
-            hipLaunchKernelGGL((k_nbody_g8<B, 9, 3, 13>), dim3(grid), dim3(B), lds8, s, p);                     \
+            hipLaunchKernelGGL((k_nbody_g8<B, G, 9, 3, 13>), dim3(grid), dim3(B), lds8, s, p);                  \
         else if (nb == 3 && ngr == 2 && d1 == 13)                                                               \
-            hipLaunchKernelGGL((k_nbody_g8<B, 3, 2, 13>), dim3(grid), dim3(B), lds8, s, p);                     \
-        else hipLaunchKernelGGL((k_nbody_g8<B, 0, 0, 0>), dim3(grid), dim3(B), lds8, s, p);                     \
+            hipLaunchKernelGGL((k_nbody_g8<B, G, 3, 2, 13>), dim3(grid), dim3(B), lds8, s, p);                  \
+        else hipLaunchKernelGGL((k_nbody_g8<B, G, 0, 0, 0>), dim3(grid), dim3(B), lds8, s, p);                  \
     } while (0)
-        switch (block) {
-            case 64: KETE_G8(64); break;
-            case 128: KETE_G8(128); break;
-            case 256: KETE_G8(256); break;
-            default: return hipErrorInvalidValue;
+        if (lanes_per_body == 7) {
+            switch (block) {
+                case 64: KETE_G8(64, 7); break;
+                case 128: KETE_G8(128, 7); break;
+                case 256: KETE_G8(256, 7); break;
+                default: return hipErrorInvalidValue;
+            }
+        } else {
+            switch (block) {
+                case 64: KETE_G8(64, 8); break;
+                case 128: KETE_G8(128, 8); break;
+                case 256: KETE_G8(256, 8); break;
+                default: return hipErrorInvalidValue;
+            }
         }
 #undef KETE_G8
         return hipGetLastError();

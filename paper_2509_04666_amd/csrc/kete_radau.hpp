@@ -228,6 +228,28 @@ __device__ __forceinline__ int corrector(const RadauConst& rc, const EphemArgs& 
 // solution).
 constexpr int kGroup = 8;
 
+// Lanes of a wavefront by body.  With G = 8 a wavefront holds 8 bodies,
+// lanes 8g..8g+7 for body g.  With G = 7 it holds 9: lanes 7g..7g+6 for
+// body g, and lane 63 joins body 8 as its eighth lane.  In both layouts
+// lane gl = 7 of a group repeats node 7, so every node has exactly one
+// owning lane and the code below needs no other distinction.
+template <int G>
+struct GroupMap {
+    static_assert(G == 7 || G == 8, "7 or 8 lanes per body");
+    static constexpr int kBodies = G == 8 ? 8 : 9;   // bodies per wavefront
+    int grp, gl;
+    __device__ __forceinline__ explicit GroupMap(int lane) {
+        if constexpr (G == 8) {
+            grp = lane >> 3;
+            gl = lane & 7;
+        } else {
+            grp = lane < 63 ? lane / 7 : 8;
+            gl = lane - 7 * grp;
+        }
+    }
+};
+constexpr int kMaxGroups = 9;
+
 // Constants of one node, held in registers by the lane that owns it.
 struct NodeRow {
     double s, hs2, A[7], B[7];
@@ -253,15 +275,18 @@ __device__ __forceinline__ void load_node_row(const RadauConst& rc, int n, NodeR
     }
 }
 
-// Wave-wide reductions of values that are equal within each 8-lane group.
+// Wave-wide reductions of values that are equal within each group: with
+// aligned 8-lane groups three exchange steps suffice, otherwise all six.
+template <int G = kGroup>
 __device__ __forceinline__ double groups_max(double x) {
 #pragma unroll
-    for (int off = kGroup; off < kWave; off <<= 1) x = fmax(x, __shfl_xor(x, off, kWave));
+    for (int off = (G == 8 ? 8 : 1); off < kWave; off <<= 1) x = fmax(x, __shfl_xor(x, off, kWave));
     return uniform(x);
 }
+template <int G = kGroup>
 __device__ __forceinline__ double groups_min(double x) {
 #pragma unroll
-    for (int off = kGroup; off < kWave; off <<= 1) x = fmin(x, __shfl_xor(x, off, kWave));
+    for (int off = (G == 8 ? 8 : 1); off < kWave; off <<= 1) x = fmin(x, __shfl_xor(x, off, kWave));
     return uniform(x);
 }
 
@@ -274,15 +299,17 @@ constexpr int kSlot = 8;
 // together by an 8-lane group fall in distinct LDS banks.
 __host__ __device__ inline int g8_row(int n_body) { return n_body * kSlot + 2; }
 
-// Increment exchange of the grouped corrector, after the wave's node
-// table: per 8-lane group three rows (x, y, z) of 8 doubles, lane k
-// writing column k, padded to 26 doubles so that the 16-byte reads of the
-// 8 groups of a wavefront fall in distinct LDS banks.
+// Exchange rows of the grouped corrector, after the wave's node table:
+// per group three rows (x, y, z) of 8 doubles, lane gl writing column gl,
+// padded to 26 doubles so that the 16-byte reads of the groups of a
+// wavefront fall in distinct LDS banks.
 constexpr int kXchGroup = 26;
 // Doubles of LDS per wavefront: node table plus exchange rows.
-__host__ __device__ inline int g8_wave_doubles(int n_body) { return kNodes * g8_row(n_body) + kGroup * kXchGroup; }
-__device__ __forceinline__ double* g8_xch(double* e8, int n_body, int lane) {
-    return e8 + kNodes * g8_row(n_body) + (lane / kGroup) * kXchGroup;
+__host__ __device__ inline int g8_wave_doubles(int n_body) {
+    return kNodes * g8_row(n_body) + kMaxGroups * kXchGroup;
+}
+__device__ __forceinline__ double* g8_xch(double* e8, int n_body, int grp) {
+    return e8 + kNodes * g8_row(n_body) + grp * kXchGroup;
 }
 
 // Publish this lane's increment dn (node gl + 1) and read the increments
@@ -419,13 +446,14 @@ __device__ __forceinline__ void accel8(const double* __restrict__ e8, const Ephe
     F[0] = ax; F[1] = ay; F[2] = az;
 }
 
-// The same force computed by an 8-lane group together: lane k of the
-// group takes slots k, k + 8, ...; the partial sums are added across the
-// group.  Every lane of the group returns the total.
+// The same force computed by a group together: node lane gl < 7 takes
+// slots gl, gl + 7, ...; the partial sums meet in the group's exchange
+// rows xg and every lane adds them in the same order, so all lanes of the
+// group return the same total.  The whole wavefront takes part.
 __device__ __forceinline__ void accel8_group(const double* __restrict__ e8, const EphemArgs& E, const double X[3],
-                                             const double V[3], int gl, double F[3]) {
+                                             const double V[3], int gl, double* __restrict__ xg, double F[3]) {
     double ax = 0.0, ay = 0.0, az = 0.0;
-    for (int sl = gl; sl < E.n_body; sl += kGroup) {
+    for (int sl = gl; gl < 7 && sl < E.n_body; sl += 7) {
         const double* pb = e8 + kSlot * sl;
         const double2 pxy = *reinterpret_cast<const double2*>(pb);
         const double2 pzg = *reinterpret_cast<const double2*>(pb + 2);
@@ -448,13 +476,16 @@ __device__ __forceinline__ void accel8_group(const double* __restrict__ e8, cons
         }
         ax = fma(f, rx, ax); ay = fma(f, ry, ay); az = fma(f, rz, az);
     }
+    const double part[3] = {ax, ay, az};
+    double D[7][3];
+    g8_exchange(xg, gl, part, D);
 #pragma unroll
-    for (int off = 1; off < kGroup; off <<= 1) {
-        ax += __shfl_xor(ax, off, kWave);
-        ay += __shfl_xor(ay, off, kWave);
-        az += __shfl_xor(az, off, kWave);
+    for (int c = 0; c < 3; ++c) {
+        double f = D[0][c];
+#pragma unroll
+        for (int m = 1; m < 7; ++m) f += D[m][c];
+        F[c] = f;
     }
-    F[0] = ax; F[1] = ay; F[2] = az;
 }
 
 // Jacobians Jx = da/dx, Jv = da/dv (row-major 3x3) from the grouped
@@ -507,7 +538,7 @@ __device__ __forceinline__ double step_factor(double q) {
 // lanes when the predictor sums and b6 are formed.  On return dn holds
 // the converged increment of this lane's node, b6 the highest
 // coefficient and d6 the increment of node 7 (all lanes).
-template <int NB, int NGR>
+template <int NB, int NGR, int G>
 __device__ __forceinline__ int corrector_g8(const RadauConst& rc, const EphemArgs& E, const double* __restrict__ e8,
                                             double* __restrict__ xg, int gl, const NodeRow& R, int node,
                                             const double x0[3], const double v0[3],
@@ -548,7 +579,7 @@ __device__ __forceinline__ int corrector_g8(const RadauConst& rc, const EphemArg
             }
             // the ratio only steers the stopping rule: the reciprocal estimate suffices
             const double lpc = (active && fm > 0.0) ? db * __builtin_amdgcn_rcp(fm) : 0.0;
-            pc = groups_max(lpc);
+            pc = groups_max<G>(lpc);
             if (pc < 1e-16 || (it > 2 && pcl <= pc) || it >= max_iter) break;
         }
         ++it;
@@ -621,15 +652,15 @@ struct G8NoVisit {
 // before S moves to the step end (dn: this lane's converged increment,
 // e8: the step's perturber table).  With need_node0 the table also holds
 // node 0 (the step start) on every step.
-template <int NB, int NGR, int DEG1, class Params, class Visit = G8NoVisit>
-__device__ __forceinline__ void g8_integrate(const Params& p, const NodeRow& R, int node, int gl, int lane,
+template <int NB, int NGR, int DEG1, int G, class Params, class Visit = G8NoVisit>
+__device__ __forceinline__ void g8_integrate(const Params& p, const NodeRow& R, int node, int gl, int grp, int lane,
                                              const double* __restrict__ coefL, int bstride, double* __restrict__ e8,
                                              int seg_lo, int seg_hi, double tb, G8State& S, G8Count& C,
                                              Visit&& visit = Visit(), bool need_node0 = false) {
     const EphemArgs& E = p.eph;
     const RadauConst& rc = p.rc;
     const int nb = E.n_body;
-    double* xg = g8_xch(e8, nb, lane);
+    double* xg = g8_xch(e8, nb, grp);
     if (__ballot(S.active) == 0ull) { S.t = tb; return; }
     while (S.t != tb) {
         const double dir = tb > S.t ? 1.0 : -1.0;
@@ -651,10 +682,10 @@ __device__ __forceinline__ void g8_integrate(const Params& p, const NodeRow& R, 
         if (!S.haveF0) { accel8<NB, NGR>(e8, E, S.x0, S.v0, S.F0); S.haveF0 = true; }
 
         double dn[3], b6p[3], d6[3];
-        const int it = corrector_g8<NB, NGR>(rc, E, e8, xg, gl, R, node, S.x0, S.v0, S.F0, h, S.active, p.max_iter,
+        const int it = corrector_g8<NB, NGR, G>(rc, E, e8, xg, gl, R, node, S.x0, S.v0, S.F0, h, S.active, p.max_iter,
                                              dn, b6p, d6);
         C.iter += it;
-        const unsigned long long n_act = __popcll(__ballot(S.active)) / kGroup;
+        const unsigned long long n_act = __popcll(__ballot(S.active && gl == 0));
         C.liter += (unsigned long long)it * n_act;
 
         double fm = 0.0, bm = 0.0;
@@ -664,7 +695,7 @@ __device__ __forceinline__ void g8_integrate(const Params& p, const NodeRow& R, 
         double hl = (ebl > 0.0 && ebl < kInf) ? fabs(h) * step_factor(p.eps / ebl) : fabs(h) / p.safety;
         if (!S.active) hl = kInf;
         if (S.active && hl < p.h_min) { S.status = KETE_ST_STEP_UNDERFLOW; S.active = false; hl = kInf; }
-        const double hn = groups_min(hl);
+        const double hn = groups_min<G>(hl);
         if (!(hn < kInf)) { S.t = tb; return; }
         if (hn < p.safety * fabs(h)) {       // reject and retry from the same state
             S.hw = hn;
@@ -680,7 +711,7 @@ __device__ __forceinline__ void g8_integrate(const Params& p, const NodeRow& R, 
                           isfinite(S.v0[1]) && isfinite(S.v0[2]))) {
             S.status = KETE_ST_NONFINITE; S.active = false;
         }
-        accel8_group(e8 + 8 * g8_row(nb), E, S.x0, S.v0, gl, S.F0);
+        accel8_group(e8 + 8 * g8_row(nb), E, S.x0, S.v0, gl, xg, S.F0);
         if (landed) {
             S.hw = fmin(S.hw, hn);
         } else {

@@ -151,7 +151,8 @@ def test_propagate_configuration_invariance(torch_cuda):
     ref2, _ = api.propagate(eph, x0, 0.0, t_out, api.default_opts())
     assert torch.equal(ref, ref2), "propagation is not deterministic"
     for kw in (dict(n_buckets=1), dict(block=64), dict(block=128, n_buckets=4), dict(rebucket_epochs=1),
-               dict(window_segs=1), dict(rebucket_epochs=0)):
+               dict(window_segs=1), dict(rebucket_epochs=0), dict(rebucket_epochs=16), dict(lanes_per_body=7),
+               dict(lanes_per_body=8), dict(lanes_per_body=7, block=256), dict(lanes_per_body=1)):
         x, s = api.propagate(eph, x0, 0.0, t_out, api.default_opts(**kw))
         d = (x - ref).abs().max().item()
         _say(f"config {kw}: max |dx| vs default {d:.3e}")
@@ -163,9 +164,11 @@ def test_propagate_ragged_sizes(torch_cuda, orc):
     torch, api = torch_cuda
     case = synth.survey_case(n_obj=130, n_frames=0, neo_frac=0.3)
     t_out = [2.0, 9.5]
-    for n in (1, 63, 65, 130):
-        xg, sg, xo, so = _propagate_both(torch, api, orc, case.ephem, case.x0[:n], 0.0, t_out)
-        assert np.max(np.abs(xg - xo)) < 1e-12, n
+    for lanes in (7, 8, 1):
+        for n in (1, 8, 9, 10, 17, 63, 65, 130):
+            xg, sg, xo, so = _propagate_both(torch, api, orc, case.ephem, case.x0[:n], 0.0, t_out,
+                                             lanes_per_body=lanes)
+            assert np.max(np.abs(xg - xo)) < 1e-12, (lanes, n)
     eph = api.DeviceEphemeris.from_synth(case.ephem)
     x, s = api.propagate(eph, torch.zeros((0, 6), dtype=torch.float64, device="cuda"), 0.0, t_out)
     assert x.shape == (2, 0, 6)
