@@ -92,14 +92,14 @@ typedef struct {
     int32_t max_steps;       /* per object per call (2,000,000) */
     int32_t max_iter;        /* corrector iterations per step (12) */
     int32_t n_buckets;       /* step-size buckets (octaves of the predicted step), 1 = none (16) */
-    int32_t block;           /* integrator threads per block: 64/128/256 (64) */
-    int32_t rebucket_epochs; /* epochs per integrator launch, 0 = all (16) */
+    int32_t block;           /* integrator threads per block: 64/128/256 (128) */
+    int32_t rebucket_epochs; /* epochs per integrator launch, 0 = all (0) */
     int32_t window_segs;     /* Chebyshev segments per staged window (2) */
     int32_t lt_iter;         /* light-time iterations (10) */
     int32_t fov_block;       /* FoV threads per block: 64/128/256 (128) */
     int32_t adj_seg_steps;   /* adjoint: steps stored per checkpoint segment (32) */
     int32_t persist_waves;   /* batched runs: resident waves per compute unit (8) */
-    int32_t lanes_per_body;  /* integrator lanes per object: 1, 7 (9 per wavefront) or 8 (8) */
+    int32_t lanes_per_body;  /* integrator lanes per object: 1, 7 (9 per wavefront) or 8 (7) */
     int32_t reserved;
 } kete_opts_t;
 

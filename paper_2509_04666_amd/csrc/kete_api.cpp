@@ -328,11 +328,11 @@ void kete_default_opts(kete_opts_t* o) {
     o->max_steps = 2000000;
     o->max_iter = 12;
     o->n_buckets = 16;
-    o->block = 64;
-    o->rebucket_epochs = 16;
+    o->block = 128;
+    o->rebucket_epochs = 0;
     o->window_segs = 2;
     o->persist_waves = 8;
-    o->lanes_per_body = 8;
+    o->lanes_per_body = 7;
     o->lt_iter = 10;
     o->fov_block = 128;
     o->adj_seg_steps = 32;

@@ -350,11 +350,11 @@ __device__ __forceinline__ void g8_table_init(const EphemArgs& E, int lane, doub
 // (derivative chain); a pass holding any of them evaluates derivatives in
 // every lane so the wavefront does not diverge.  Node 0 (the step start,
 // needed before the first step or when the caller asks) takes one more
-// pass with coordinate = lane.  s_lane: node fraction of node (k & 7) + 1
-// for k & 7 < 7.
+// pass with coordinate = lane.  The node of a lane here follows lane & 7
+// whatever the lane's body group.
 template <int NB, int NGR, int DEG1>
 __device__ __forceinline__ void node_ephemeris8(const double* __restrict__ coefL, int bstride, const EphemArgs& E,
-                                                double s_lane, int seg_lo, int seg_hi, double t, double h,
+                                                const RadauConst& rc, int seg_lo, int seg_hi, double t, double h,
                                                 double t_end, bool node0, int lane, double* __restrict__ e8) {
     const int nb = NB > 0 ? NB : E.n_body;
     const int ngr = NB > 0 ? NGR : E.n_gr;
@@ -384,8 +384,8 @@ __device__ __forceinline__ void node_ephemeris8(const double* __restrict__ coefL
             }
         }
     };
-    const int gl = lane & (kGroup - 1);
-    chains(gl + 1, gl == kGroup - 1 ? t_end : t + s_lane * h, lane / kGroup, kGroup, (nc + kGroup - 1) / kGroup);
+    const int nl = lane & (kGroup - 1);
+    chains(nl + 1, nl == kGroup - 1 ? t_end : t + rc.s[nl + 1] * h, lane / kGroup, kGroup, (nc + kGroup - 1) / kGroup);
     if (node0) chains(0, t, lane, kWave, 1);
     wave_lds_sync();
 }
@@ -676,7 +676,7 @@ __device__ __forceinline__ void g8_integrate(const Params& p, const NodeRow& R, 
         }
         const double t_end = landed ? tb : S.t + h;
         const int n0 = (S.haveF0 && !need_node0) ? 1 : 0;
-        node_ephemeris8<NB, NGR, DEG1>(coefL, bstride, E, R.s, seg_lo, seg_hi, S.t, h, t_end, n0 == 0, lane, e8);
+        node_ephemeris8<NB, NGR, DEG1>(coefL, bstride, E, rc, seg_lo, seg_hi, S.t, h, t_end, n0 == 0, lane, e8);
         C.chain += (kNodes - n0) * E.n_gr * 3;
         C.vchain += (kNodes - n0) * (nb - E.n_gr) * 3;
         if (!S.haveF0) { accel8<NB, NGR>(e8, E, S.x0, S.v0, S.F0); S.haveF0 = true; }
