@@ -470,11 +470,10 @@ __global__ void k_item_scatter(const FovParams p, const int32_t* __restrict__ ic
 }
 
 // Persistent join: every wavefront pops work items until none is left.
-__global__ __launch_bounds__(256) void k_fov_cells(const FovParams p) {
+__global__ __launch_bounds__(256, 3) void k_fov_cells(const FovParams p) {
     const int lane = threadIdx.x & 63;
     unsigned long long n_cand = 0, n_exact = 0, n_visit = 0;
     const double* __restrict__ caps = p.cell_caps;
-    const bool one_sub = p.n_sub == 1;
     const int n_items = p.item_start[p.n_keys];
     __shared__ unsigned long long bufs[4][kBufEntries];
     unsigned long long* buf = bufs[(threadIdx.x >> 6) & 3];
@@ -529,25 +528,13 @@ __global__ __launch_bounds__(256) void k_fov_cells(const FovParams p) {
                 int nq = 0;
                 for (int t = 1; t < 27; ++t) nq = (__shfl(excl, t, kWave) <= g) ? t : nq;
                 const int rk = __shfl(my_a0, nq, kWave) + (g - __shfl(excl, nq, kWave));
-                // lane l also holds that frame's time, observer and (single
-                // sub-frame) normals for the linear test
                 double r[6] = {0.0, 0.0, 0.0, 2.0, 0.0, 0.0};
-                double rt = 0.0, ro[3] = {0.0, 0.0, 0.0}, rn[12];
-#pragma unroll
-                for (int i = 0; i < 12; ++i) rn[i] = 0.0;
                 if (g < total) {
                     const double* cp = caps + 8 * (int64_t)rk;
                     const double2 c01 = *reinterpret_cast<const double2*>(cp);
                     const double2 c23 = *reinterpret_cast<const double2*>(cp + 2);
                     const double2 c45 = *reinterpret_cast<const double2*>(cp + 4);
                     r[0] = c01.x; r[1] = c01.y; r[2] = c23.x; r[3] = c23.y; r[4] = c45.x; r[5] = c45.y;
-                    const int f = (int)r[5];
-                    rt = p.ft[f] - tr;
-                    for (int c = 0; c < 3; ++c) ro[c] = p.fobs[3 * f + c];
-                    if (one_sub) {
-#pragma unroll
-                        for (int i = 0; i < 12; ++i) rn[i] = p.normals[(size_t)f * 12 + i];
-                    }
                 }
                 const int n = min(kWave, total - g0);
                 n_visit += (unsigned long long)n;
@@ -557,18 +544,13 @@ __global__ __launch_bounds__(256) void k_fov_cells(const FovParams p) {
                     for (int i = 0; i < 5; ++i) cpm[i] = lane_value(r[i], m);
                     const bool hit = live && frame_cap_hit(o, cpm);
                     if (__ballot(hit) == 0ull) continue;
-                    const int f = (int)lane_value(r[5], m);
-                    const double dt = lane_value(rt, m);
-                    const double ob[3] = {lane_value(ro[0], m), lane_value(ro[1], m), lane_value(ro[2], m)};
-                    bool may;
-                    if (one_sub) {
-                        double nm[12];
-#pragma unroll
-                        for (int i = 0; i < 12; ++i) nm[i] = lane_value(rn[i], m);
-                        may = hit && lin_may_contain(o, dt, ob, nm, 1, Asun);
-                    } else {
-                        may = hit && lin_may_contain(o, dt, ob, p.normals + (size_t)f * p.n_sub * 12, p.n_sub, Asun);
-                    }
+                    // a frame some lane may see: its time, observer and
+                    // normals are read at a wave-uniform address
+                    const int f = __builtin_amdgcn_readfirstlane((int)lane_value(r[5], m));
+                    const double dt = p.ft[f] - tr;
+                    const double ob[3] = {p.fobs[3 * f], p.fobs[3 * f + 1], p.fobs[3 * f + 2]};
+                    const bool may = hit && lin_may_contain(o, dt, ob, p.normals + (size_t)f * p.n_sub * 12, p.n_sub,
+                                                            Asun);
                     if (hit) ++n_cand;
                     if (may) ++n_exact;
                     buf_append(buf, nbuf, may, ((unsigned long long)f << 32) | gobj, p.cand, p.n_cand, p.cand_cap);
@@ -592,10 +574,16 @@ __global__ __launch_bounds__(256) void k_fov_cells(const FovParams p) {
     }
 }
 
-// Wide objects: one wavefront per (object, batch); its lanes split the
-// object's grid cells, or every frame of the batch when no cap applies.
+// Wide objects: one wavefront per (object, batch).  Without a usable cap
+// its lanes split every frame of the batch; otherwise they take the cap's
+// grid cells 64 at a time, and the frame records of those cells are dealt
+// out 64 at a time across the lanes (a prefix sum of the cell lengths,
+// then a binary search per lane), so empty and short cells cost nothing.
 __global__ __launch_bounds__(256) void k_fov_wide(const FovParams p) {
     const int lane = threadIdx.x & 63;
+    __shared__ int s_incl[4][kWave], s_base[4][kWave];
+    int* incl_w = s_incl[(threadIdx.x >> 6) & 3];
+    int* base_w = s_base[(threadIdx.x >> 6) & 3];
     const unsigned long long nw = *p.n_wide;
     const int64_t n_items = (int64_t)(nw < (unsigned long long)p.n_pairs_total ? nw : p.n_pairs_total);
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -629,22 +617,36 @@ __global__ __launch_bounds__(256) void k_fov_wide(const FovParams p) {
             const int64_t base = p.b_koff[b];
             for (int c0 = 0; c0 < o.ncell; c0 += 64) {
                 const int c = c0 + lane;
-                int a0 = 0, a1 = 0;
+                int a0 = 0, len = 0;
                 if (c < o.ncell) {
                     const int ix = o.lo[0] + c / (ny * nz);
                     const int iy = o.lo[1] + (c / nz) % ny;
                     const int iz = o.lo[2] + c % nz;
                     const int64_t key = base + (ix * G + iy) * G + iz;
                     a0 = p.cell_start[key];
-                    a1 = p.cell_start[key + 1];
+                    len = p.cell_start[key + 1] - a0;
                 }
-                int len = a1 - a0;
+                int incl = len;
 #pragma unroll
-                for (int off = 32; off >= 1; off >>= 1) len = max(len, __shfl_xor(len, off, 64));
-                for (int t = 0; t < len; ++t) {
-                    const int k = a0 + t;
+                for (int off = 1; off < kWave; off <<= 1) {
+                    const int t = __shfl_up(incl, off, kWave);
+                    if (lane >= off) incl += t;
+                }
+                const int total = __shfl(incl, kWave - 1, kWave);
+                if (total == 0) continue;
+                wave_lds_sync();                 // the previous chunk's searches are done
+                incl_w[lane] = incl;
+                base_w[lane] = a0 - (incl - len); // record of position t in this cell: base + t
+                wave_lds_sync();
+                for (int t0 = 0; t0 < total; t0 += kWave) {
+                    const int t = t0 + lane;
+                    // cell of position t: the first lane whose inclusive sum exceeds t
+                    int i = 0;
+#pragma unroll
+                    for (int step = kWave / 2; step > 0; step >>= 1)
+                        if (incl_w[i + step - 1] <= t) i += step;
                     int f = 0;
-                    const bool may = k < a1 && cell_frame_may_contain(p, o, k, tr, Asun, n_cand, f);
+                    const bool may = t < total && cell_frame_may_contain(p, o, base_w[i] + t, tr, Asun, n_cand, f);
                     if (may) ++n_exact;
                     buf_append(buf, nbuf, may, ((unsigned long long)f << 32) | gobj, p.cand, p.n_cand, p.cand_cap);
                 }
