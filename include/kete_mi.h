@@ -87,7 +87,7 @@ typedef struct {
     double h_max;            /* largest step, 0 = unlimited */
     double c_light;          /* speed of light in au/day (173.144632674...) */
     double batch_span;       /* frame batch span in days (3.0, Sect. 2) */
-    double cell_chord;       /* FoV sky-grid cell size (chord units; 0 = auto) */
+    double cell_chord;       /* FoV sky-grid cell size (chord units; 0 = auto: 0.10) */
     double lt_tol;           /* light-time convergence in days (1e-15) */
     int32_t max_steps;       /* per object per call (2,000,000) */
     int32_t max_iter;        /* corrector iterations per step (12) */
@@ -334,7 +334,7 @@ int kete_batch_graph_destroy(void *graph);
 /* Autotuner for batched runs: coordinate descent, starting from `base`
  * (NULL = defaults), over n_buckets {1,4,8,16}, persist_waves {2,4,8,12},
  * window_segs {1,2,4}, fov_block {64,128,256} and cell_chord
- * {0.04,0.08,0.16}, in that order; each candidate is planned, run once to
+ * {0.05,0.10,0.16}, in that order; each candidate is planned, run once to
  * warm up and timed with HIP events over `reps` (1..100) runs of
  * kete_batch_run on `stream`.  Candidates whose workspace exceeds
  * ws_bytes are skipped.  progress (may be NULL) is called with user after

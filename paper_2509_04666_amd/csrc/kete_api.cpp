@@ -505,7 +505,7 @@ static int64_t retry_pairs_cap(int64_t pairs, int64_t cands, int64_t pairs_cap) 
 }
 
 static int grid_dims(const kete_opts_t* o, int64_t n_batch, int& G, double& L) {
-    L = o->cell_chord > 0 ? o->cell_chord : 0.08;
+    L = o->cell_chord > 0 ? o->cell_chord : 0.10;
     G = (int)std::ceil(2.0 / L - 1e-9);
     if (G < 1) G = 1;
     if (G > 128) return fail(KETE_EINVAL, "cell_chord too small (grid > 128 cells per axis)");
@@ -865,7 +865,7 @@ int batch_dims(const kete_ephem_t* eph, const kete_batch_t* bt, int64_t pairs_ca
     if (d.n_sub < 1 || d.n_sub > KETE_MAX_SUB) return fail(KETE_EINVAL, "n_sub outside 1..%d", KETE_MAX_SUB);
     if (d.B > 0 && (!bt->batch_job_host || !bt->batch_epoch_host || !bt->batch_off_host))
         return fail(KETE_EINVAL, "null batch host tables");
-    const double L = o->cell_chord > 0 ? o->cell_chord : 0.08;
+    const double L = o->cell_chord > 0 ? o->cell_chord : 0.10;
     const int Gbig = (int)std::ceil(2.0 / L - 1e-9);
     if (Gbig > 128) return fail(KETE_EINVAL, "cell_chord too small");
     // jobs
@@ -1252,7 +1252,7 @@ int kete_batch_autotune(const kete_ephem_t* eph, const kete_batch_t* batch, int6
         {1, {2, 4, 8, 12}, 4},             // persist_waves
         {2, {1, 2, 4}, 3},                 // window_segs
         {3, {64, 128, 256}, 3},            // fov_block
-        {4, {0.04, 0.08, 0.16}, 3},        // cell_chord
+        {4, {0.05, 0.10, 0.16}, 3},        // cell_chord
     };
     auto with = [](kete_opts_t o, int which, double v) {
         switch (which) {
