@@ -315,79 +315,60 @@ __device__ __forceinline__ void load_adj_cols(const RadauConst& rc, int gl, AdjC
     }
 }
 
-template <int NB, int NGR, int DEG1>
-__global__ __launch_bounds__(64, 2) void k_adjoint_bwd(const AdjParams p) {
+// Per-node constants of the 8 lanes of a group (LDS rows, indexed by gl).
+__device__ __forceinline__ void fill_node_rows(const RadauConst& rc, int tid, NodeRow* rows) {
+    if (tid < kGroup) {
+        NodeRow r;
+        load_node_row(rc, tid < 7 ? tid + 1 : 7, r);
+        rows[tid] = r;
+    }
+}
+
+// Backward, first half for checkpoint segment c: recompute the segment from
+// its checkpoint with the forward's grouping and step sequence, storing
+// each step's data and this lane's node Jacobians (lane 7: node 0).  The
+// step count (plus kSegOverflow when the step store was too small) goes to
+// seg_ns[wave].
+constexpr int kSegOverflow = 1 << 30;
+static_assert(kAdjLanes == kGroup, "adjoint wavefronts hold 8 objects");
+
+template <int BLOCK, int NB, int NGR, int DEG1>
+__global__ __launch_bounds__(BLOCK, 2) void k_adj_recompute(const AdjParams p, const int c) {
     extern __shared__ double smem[];
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
     const int gl = lane & (kGroup - 1);
     const int node = gl < 7 ? gl + 1 : 7;
     const int jnode = gl < 7 ? gl + 1 : 0;          // node whose Jacobians this lane keeps
     const EphemArgs& E = p.eph;
-    const RadauConst& rc = p.rc;
     const int bstride = p.max_win_segs * 3 * E.deg1;
     double* coefL = smem;
-    double* e8 = smem + (((size_t)E.n_body * bstride + 1) & ~(size_t)1);
-    // exchange slots of the reverse sweep: [group][node lane][6] (W, U)
-    double* xw = e8 + (size_t)g8_wave_doubles(E.n_body) + (lane / kGroup) * kGroup * 6;
+    double* e8 = smem + (((size_t)E.n_body * bstride + 1) & ~(size_t)1) + (size_t)wid * g8_wave_doubles(E.n_body);
     g8_table_init(E, lane, e8);
-    // per-node constants of the 8 lanes of a group, shared through LDS to
-    // keep registers for the sweeps
     __shared__ NodeRow rows[kGroup];
-    __shared__ AdjCols cols[kGroup];
-    __shared__ double drow[kGroup][18];      // own dense-output row (see below)
-    if (lane < kGroup) {
-        NodeRow r;
-        load_node_row(rc, lane < 7 ? lane + 1 : 7, r);
-        rows[lane] = r;
-        AdjCols q;
-        load_adj_cols(rc, lane, q);
-        cols[lane] = q;
-        // alpha(sig) = sum_k drow[k] sig^(k+2) + drow[16] sig^2, beta(sig) = sum_k drow[8+k] sig^(k+1) + drow[17] sig:
-        // stage m = lane + 1 for lanes 0..6, minus the sum over stages for lane 7
-        for (int k = 0; k < 8; ++k) {
-            double a = 0.0, b = 0.0, sa = 0.0, sb = 0.0;
-            for (int m = 0; m < 7; ++m) {
-                sa += rc.Ap[m][k]; sb += rc.Bp[m][k];
-                if (m == lane) { a = rc.Ap[m][k]; b = rc.Bp[m][k]; }
-            }
-            drow[lane][k] = lane < 7 ? a : -sa;
-            drow[lane][8 + k] = lane < 7 ? b : -sb;
-        }
-        drow[lane][16] = lane < 7 ? 0.0 : 0.5;
-        drow[lane][17] = lane < 7 ? 0.0 : 1.0;
-    }
+    fill_node_rows(p.rc, tid, rows);
     __syncthreads();
     const NodeRow& R = rows[gl];
-    const AdjCols& Q = cols[gl];
-    const double* dr = drow[gl];
-    const long gi_raw = ((long)blockIdx.x * 64 + lane) / kGroup;
+    const long wave = (long)blockIdx.x * (BLOCK / kWave) + wid;
+    const long gi_raw = wave * kGroup + lane / kGroup;
     const bool valid = gi_raw < p.n_obj;
     const size_t gi = valid ? (size_t)gi_raw : 0;   // scratch slot (invalid groups read slot 0, never write)
     const int j = valid ? p.perm[gi] : 0;
     const size_t N = p.n_obj;
-    const int K = p.k_obs;
-    const double* tob = p.t_obs + (size_t)j * K;
-    const bool ok_final = valid && p.status[j] == 0;
-    double lx[3] = {0.0, 0.0, 0.0}, lv[3] = {0.0, 0.0, 0.0};
-    int kb = K - 1;
     bool overflow_steps = false;
-
-    for (int c = p.n_ckpt - 1; c >= 0; --c) {
-        // ---- recompute segment c, storing the steps and the node Jacobians
-        G8State S;
-        init_lane_state(p, false, j, S);
-        double hw = 0.0;
-        if (valid) {
-            const double* ck = p.ckpt + ((size_t)c * N + j) * kCkptDoubles;
-            #pragma unroll
-            for (int i = 0; i < 3; ++i) { S.x0[i] = ck[i]; S.v0[i] = ck[3 + i]; }
-            hw = ck[6];
-            S.active = ck[7] == 0.0;
-        }
-        S.hw = groups_max(valid ? hw : 0.0);        // the same value in every valid group
-        S.t = p.win[p.seg_win[c]].t_a;
-        G8Count Cn;
-        int ns = 0;
+    G8State S;
+    init_lane_state(p, false, j, S);
+    double hw = 0.0;
+    if (valid) {
+        const double* ck = p.ckpt + ((size_t)c * N + j) * kCkptDoubles;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) { S.x0[i] = ck[i]; S.v0[i] = ck[3 + i]; }
+        hw = ck[6];
+        S.active = ck[7] == 0.0;
+    }
+    S.hw = groups_max(valid ? hw : 0.0);        // the same value in every valid group
+    S.t = p.win[p.seg_win[c]].t_a;
+    G8Count Cn;
+    int ns = 0;
         auto store = [&](double ts, double h, const double dn[3], const G8State& St) {
             if (ns >= p.s_max) { overflow_steps = true; return; }
             double D[7][3];
@@ -424,136 +405,202 @@ __global__ __launch_bounds__(64, 2) void k_adjoint_bwd(const AdjParams p) {
             }
             ++ns;
         };
-        for (int w = p.seg_win[c]; w < p.seg_win[c + 1]; ++w) {
-            const Window W = p.win[w];
-            __syncthreads();
-            stage_window(E, W.seg_lo, W.seg_hi, bstride, lane, 64, coefL);
-            __syncthreads();
-            g8_integrate<NB, NGR, DEG1, kGroup>(p, R, node, gl, lane / kGroup, lane, coefL, bstride, e8, W.seg_lo,
-                                                W.seg_hi, W.t_b, S, Cn, store, true);
+    for (int w = p.seg_win[c]; w < p.seg_win[c + 1]; ++w) {
+        const Window W = p.win[w];
+        __syncthreads();
+        stage_window(E, W.seg_lo, W.seg_hi, bstride, tid, BLOCK, coefL);
+        __syncthreads();
+        g8_integrate<NB, NGR, DEG1, kGroup>(p, R, node, gl, lane / kGroup, lane, coefL, bstride, e8, W.seg_lo,
+                                            W.seg_hi, W.t_b, S, Cn, store, true);
+    }
+    if (lane == 0 && wave * kGroup < p.n_obj) p.seg_ns[wave] = min(ns, p.s_max) | (overflow_steps ? kSegOverflow : 0);
+}
+
+// Backward, second half for checkpoint segment c: the reverse sweep over
+// the stored steps, one 8-lane group per object (lane m - 1 holds the
+// stage cotangent mu_m, lane 7 the step-start term), carrying the state
+// cotangent (lx, lv), the next observation and the overflow flag from
+// segment c + 1 in adj_state; segment 0 adds the observations at the start
+// epoch and writes the gradient.
+__global__ __launch_bounds__(64) void k_adj_sweep(const AdjParams p, const int c) {
+    const int lane = threadIdx.x;
+    const int gl = lane & (kGroup - 1);
+    const int jnode = gl < 7 ? gl + 1 : 0;
+    const RadauConst& rc = p.rc;
+    // exchange slots of the reverse sweep: [group][node lane][6] (W, U)
+    __shared__ double xw_all[kWave * 6];
+    double* xw = xw_all + (lane / kGroup) * kGroup * 6;
+    __shared__ AdjCols cols[kGroup];
+    __shared__ double drow[kGroup][18];      // own dense-output row (see below)
+    if (lane < kGroup) {
+        AdjCols q;
+        load_adj_cols(rc, lane, q);
+        cols[lane] = q;
+        // alpha(sig) = sum_k drow[k] sig^(k+2) + drow[16] sig^2, beta(sig) = sum_k drow[8+k] sig^(k+1) + drow[17] sig:
+        // stage m = lane + 1 for lanes 0..6, minus the sum over stages for lane 7
+        for (int k = 0; k < 8; ++k) {
+            double a = 0.0, b = 0.0, sa = 0.0, sb = 0.0;
+            for (int m = 0; m < 7; ++m) {
+                sa += rc.Ap[m][k]; sb += rc.Bp[m][k];
+                if (m == lane) { a = rc.Ap[m][k]; b = rc.Bp[m][k]; }
+            }
+            drow[lane][k] = lane < 7 ? a : -sa;
+            drow[lane][8 + k] = lane < 7 ? b : -sb;
         }
-        if (ns > p.s_max) ns = p.s_max;
-        // ---- reverse sweep over the stored steps
-        for (int st = ns - 1; st >= 0; --st) {
-            const double* sp = p.steps + (size_t)st * kStepDoubles * N;
-            const double ts = sp[gi];
-            const double h = valid ? sp[N + gi] : 1.0;
-            const double hh = h * h;
-            // output cotangents: the step end and the observations inside
-            double G[3], gx0[3], gv0[3];
-            #pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                G[i] = hh * Q.gA * lx[i] + h * Q.gB * lv[i];
-                gx0[i] = lx[i];
-                gv0[i] = h * lx[i] + lv[i];
-            }
-            auto pending = [&]() { return ok_final && kb >= 0 && (h > 0 ? tob[kb] > ts : tob[kb] < ts); };
-            bool pend = pending();
-            while (__ballot(pend) != 0ull) {
-                if (pend) {
-                    const double sig = (tob[kb] - ts) / h;
-                    const double* og = p.obs_grad + ((size_t)j * K + kb) * 6;
-                    const double lX[3] = {og[0], og[1], og[2]}, lV[3] = {og[3], og[4], og[5]};
-                    // this lane's dense-output weights at sig
-                    double a = dr[7], b = dr[15];
-                    #pragma unroll
-                    for (int k = 6; k >= 0; --k) { a = fma(a, sig, dr[k]); b = fma(b, sig, dr[8 + k]); }
-                    a = (a + dr[16]) * sig * sig;
-                    b = (b + dr[17]) * sig;
-                    #pragma unroll
-                    for (int i = 0; i < 3; ++i) {
-                        G[i] += hh * a * lX[i] + h * b * lV[i];
-                        gx0[i] += lX[i];
-                        gv0[i] += sig * h * lX[i] + lV[i];
-                    }
-                    --kb;
-                }
-                pend = pending();
-            }
-            // this lane's Jacobians
-            const double* jp = p.jac + (size_t)st * 8 * kJacDoubles * N;
-            double Jx[9], Jv[9];
-            #pragma unroll
-            for (int q = 0; q < 9; ++q) {
-                Jx[q] = valid ? jp[((size_t)jnode * kJacDoubles + q) * N + gi] : 0.0;
-                Jv[q] = valid ? jp[((size_t)jnode * kJacDoubles + 9 + q) * N + gi] : 0.0;
-            }
-            // stage cotangents: mu_m = G_m + sum_n [h^2 A_m(s_n) Jx_n^T mu_n + h B_m(s_n) Jv_n^T mu_n],
-            // lane m - 1 holding mu_m; lane 7 accumulates the step-start term m0
-            double mu[3] = {G[0], G[1], G[2]};
-            double wsum[3], usum[3], m0[3] = {0.0, 0.0, 0.0};
-            double pc = 1e300, pcl;
-            int it = 0;
-            do {
-                pcl = pc;
-                ++it;
-                double W[3] = {0.0, 0.0, 0.0}, U[3] = {0.0, 0.0, 0.0};
-                if (gl < 7) {
-                    #pragma unroll
-                    for (int c2 = 0; c2 < 3; ++c2) {
-                        double a = 0.0, b = 0.0;
-                        #pragma unroll
-                        for (int r = 0; r < 3; ++r) { a = fma(Jx[3 * r + c2], mu[r], a); b = fma(Jv[3 * r + c2], mu[r], b); }
-                        W[c2] = a; U[c2] = b;
-                    }
-                }
-                *reinterpret_cast<double2*>(xw + 6 * gl) = make_double2(W[0], W[1]);
-                *reinterpret_cast<double2*>(xw + 6 * gl + 2) = make_double2(W[2], U[0]);
-                *reinterpret_cast<double2*>(xw + 6 * gl + 4) = make_double2(U[1], U[2]);
-                wave_lds_sync();
-                double nm[3] = {G[0], G[1], G[2]};
-                #pragma unroll
-                for (int i = 0; i < 3; ++i) { wsum[i] = 0.0; usum[i] = 0.0; }
-                #pragma unroll
-                for (int n = 1; n <= 7; ++n) {
-                    const double* x = xw + 6 * (n - 1);
-                    const double2 w01 = *reinterpret_cast<const double2*>(x);
-                    const double2 w2u0 = *reinterpret_cast<const double2*>(x + 2);
-                    const double2 u12 = *reinterpret_cast<const double2*>(x + 4);
-                    const double wn[3] = {w01.x, w01.y, w2u0.x}, un[3] = {w2u0.y, u12.x, u12.y};
-                    #pragma unroll
-                    for (int i = 0; i < 3; ++i) {
-                        nm[i] += hh * Q.cA[n - 1] * wn[i] + h * Q.cB[n - 1] * un[i];
-                        wsum[i] += wn[i];
-                        usum[i] += rc.s[n] * h * wn[i] + un[i];
-                    }
-                }
-                wave_lds_sync();
-                double dm = 0.0, mm = 0.0;
-                if (gl < 7) {
-                    #pragma unroll
-                    for (int i = 0; i < 3; ++i) {
-                        dm = fmax(dm, fabs(nm[i] - mu[i]));
-                        mm = fmax(mm, fabs(nm[i]));
-                        mu[i] = nm[i];
-                    }
-                } else {
-                    #pragma unroll
-                    for (int i = 0; i < 3; ++i) m0[i] = nm[i];
-                }
+        drow[lane][16] = lane < 7 ? 0.0 : 0.5;
+        drow[lane][17] = lane < 7 ? 0.0 : 1.0;
+    }
+    __syncthreads();
+    const AdjCols& Q = cols[gl];
+    const double* dr = drow[gl];
+    const long wave = blockIdx.x;
+    const long gi_raw = wave * kGroup + lane / kGroup;
+    const bool valid = gi_raw < p.n_obj;
+    const size_t gi = valid ? (size_t)gi_raw : 0;
+    const int j = valid ? p.perm[gi] : 0;
+    const size_t N = p.n_obj;
+    const int K = p.k_obs;
+    const double* tob = p.t_obs + (size_t)j * K;
+    const bool ok_final = valid && p.status[j] == 0;
+    double lx[3] = {0.0, 0.0, 0.0}, lv[3] = {0.0, 0.0, 0.0};
+    int kb = K - 1;
+    bool overflow_steps = false;
+    double* as = p.adj_state + (size_t)j * kAdjStateDoubles;
+    if (c < p.n_ckpt - 1 && valid) {
 #pragma unroll
-                for (int off = 1; off < kGroup; off <<= 1) {
-                    dm = fmax(dm, __shfl_xor(dm, off, kWave));
-                    mm = fmax(mm, __shfl_xor(mm, off, kWave));
-                }
-                pc = groups_max((ok_final && mm > 0.0) ? dm / mm : 0.0);
-            } while (!(pc < 1e-16) && !(it > 2 && pcl <= pc) && it < 2 * p.max_iter);
-            // step-start Jacobians (lane 7) applied to m0, shared with the group
-            double a0[3], b0[3];
-            #pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                double a = 0.0, b = 0.0;
-                #pragma unroll
-                for (int r = 0; r < 3; ++r) { a = fma(Jx[3 * r + i], m0[r], a); b = fma(Jv[3 * r + i], m0[r], b); }
-                a0[i] = __shfl(a, 7, kGroup);
-                b0[i] = __shfl(b, 7, kGroup);
-            }
-            #pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                lx[i] = gx0[i] + wsum[i] + a0[i];
-                lv[i] = gv0[i] + usum[i] + b0[i];
-            }
+        for (int i = 0; i < 3; ++i) { lx[i] = as[i]; lv[i] = as[3 + i]; }
+        kb = (int)as[6];
+        overflow_steps = as[7] != 0.0;
+    }
+    const int sn = p.seg_ns[wave];
+    const int ns = sn & (kSegOverflow - 1);
+    overflow_steps = overflow_steps || (sn & kSegOverflow) != 0;
+    for (int st = ns - 1; st >= 0; --st) {
+        const double* sp = p.steps + (size_t)st * kStepDoubles * N;
+        const double ts = sp[gi];
+        const double h = valid ? sp[N + gi] : 1.0;
+        const double hh = h * h;
+        // output cotangents: the step end and the observations inside
+        double G[3], gx0[3], gv0[3];
+        #pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            G[i] = hh * Q.gA * lx[i] + h * Q.gB * lv[i];
+            gx0[i] = lx[i];
+            gv0[i] = h * lx[i] + lv[i];
         }
+        auto pending = [&]() { return ok_final && kb >= 0 && (h > 0 ? tob[kb] > ts : tob[kb] < ts); };
+        bool pend = pending();
+        while (__ballot(pend) != 0ull) {
+            if (pend) {
+                const double sig = (tob[kb] - ts) / h;
+                const double* og = p.obs_grad + ((size_t)j * K + kb) * 6;
+                const double lX[3] = {og[0], og[1], og[2]}, lV[3] = {og[3], og[4], og[5]};
+                // this lane's dense-output weights at sig
+                double a = dr[7], b = dr[15];
+                #pragma unroll
+                for (int k = 6; k >= 0; --k) { a = fma(a, sig, dr[k]); b = fma(b, sig, dr[8 + k]); }
+                a = (a + dr[16]) * sig * sig;
+                b = (b + dr[17]) * sig;
+                #pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    G[i] += hh * a * lX[i] + h * b * lV[i];
+                    gx0[i] += lX[i];
+                    gv0[i] += sig * h * lX[i] + lV[i];
+                }
+                --kb;
+            }
+            pend = pending();
+        }
+        // this lane's Jacobians
+        const double* jp = p.jac + (size_t)st * 8 * kJacDoubles * N;
+        double Jx[9], Jv[9];
+        #pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            Jx[q] = valid ? jp[((size_t)jnode * kJacDoubles + q) * N + gi] : 0.0;
+            Jv[q] = valid ? jp[((size_t)jnode * kJacDoubles + 9 + q) * N + gi] : 0.0;
+        }
+        // stage cotangents: mu_m = G_m + sum_n [h^2 A_m(s_n) Jx_n^T mu_n + h B_m(s_n) Jv_n^T mu_n],
+        // lane m - 1 holding mu_m; lane 7 accumulates the step-start term m0
+        double mu[3] = {G[0], G[1], G[2]};
+        double wsum[3], usum[3], m0[3] = {0.0, 0.0, 0.0};
+        double pc = 1e300, pcl;
+        int it = 0;
+        do {
+            pcl = pc;
+            ++it;
+            double W[3] = {0.0, 0.0, 0.0}, U[3] = {0.0, 0.0, 0.0};
+            if (gl < 7) {
+                #pragma unroll
+                for (int c2 = 0; c2 < 3; ++c2) {
+                    double a = 0.0, b = 0.0;
+                    #pragma unroll
+                    for (int r = 0; r < 3; ++r) { a = fma(Jx[3 * r + c2], mu[r], a); b = fma(Jv[3 * r + c2], mu[r], b); }
+                    W[c2] = a; U[c2] = b;
+                }
+            }
+            *reinterpret_cast<double2*>(xw + 6 * gl) = make_double2(W[0], W[1]);
+            *reinterpret_cast<double2*>(xw + 6 * gl + 2) = make_double2(W[2], U[0]);
+            *reinterpret_cast<double2*>(xw + 6 * gl + 4) = make_double2(U[1], U[2]);
+            wave_lds_sync();
+            double nm[3] = {G[0], G[1], G[2]};
+            #pragma unroll
+            for (int i = 0; i < 3; ++i) { wsum[i] = 0.0; usum[i] = 0.0; }
+            #pragma unroll
+            for (int n = 1; n <= 7; ++n) {
+                const double* x = xw + 6 * (n - 1);
+                const double2 w01 = *reinterpret_cast<const double2*>(x);
+                const double2 w2u0 = *reinterpret_cast<const double2*>(x + 2);
+                const double2 u12 = *reinterpret_cast<const double2*>(x + 4);
+                const double wn[3] = {w01.x, w01.y, w2u0.x}, un[3] = {w2u0.y, u12.x, u12.y};
+                #pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    nm[i] += hh * Q.cA[n - 1] * wn[i] + h * Q.cB[n - 1] * un[i];
+                    wsum[i] += wn[i];
+                    usum[i] += rc.s[n] * h * wn[i] + un[i];
+                }
+            }
+            wave_lds_sync();
+            double dm = 0.0, mm = 0.0;
+            if (gl < 7) {
+                #pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    dm = fmax(dm, fabs(nm[i] - mu[i]));
+                    mm = fmax(mm, fabs(nm[i]));
+                    mu[i] = nm[i];
+                }
+            } else {
+                #pragma unroll
+                for (int i = 0; i < 3; ++i) m0[i] = nm[i];
+            }
+#pragma unroll
+            for (int off = 1; off < kGroup; off <<= 1) {
+                dm = fmax(dm, __shfl_xor(dm, off, kWave));
+                mm = fmax(mm, __shfl_xor(mm, off, kWave));
+            }
+            pc = groups_max((ok_final && mm > 0.0) ? dm / mm : 0.0);
+        } while (!(pc < 1e-16) && !(it > 2 && pcl <= pc) && it < 2 * p.max_iter);
+        // step-start Jacobians (lane 7) applied to m0, shared with the group
+        double a0[3], b0[3];
+        #pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            double a = 0.0, b = 0.0;
+            #pragma unroll
+            for (int r = 0; r < 3; ++r) { a = fma(Jx[3 * r + i], m0[r], a); b = fma(Jv[3 * r + i], m0[r], b); }
+            a0[i] = __shfl(a, 7, kGroup);
+            b0[i] = __shfl(b, 7, kGroup);
+        }
+        #pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            lx[i] = gx0[i] + wsum[i] + a0[i];
+            lv[i] = gv0[i] + usum[i] + b0[i];
+        }
+    }
+    if (c > 0) {
+        if (valid) {
+            const double v = gl < 6 ? state_component(lx, lv, gl) : gl == 6 ? (double)kb : (overflow_steps ? 1.0 : 0.0);
+            as[gl] = v;
+        }
+        return;
     }
     // observations at the start epoch
     if (ok_final) {
@@ -575,31 +622,42 @@ __global__ __launch_bounds__(64, 2) void k_adjoint_bwd(const AdjParams p) {
 
 size_t adjoint_lds_bytes(const AdjParams& p) {
     return ((((size_t)p.eph.n_body * p.max_win_segs * 3 * p.eph.deg1 + 1) & ~(size_t)1) +
-            (size_t)g8_wave_doubles(p.eph.n_body) + (size_t)kWave * 6) * sizeof(double);
+            (size_t)g8_wave_doubles(p.eph.n_body)) * sizeof(double);
 }
 
+// The backward recompute runs kAdjBlock threads per block: its wavefronts
+// share the staged Chebyshev window.
+constexpr int kAdjBlock = 128;
+
 hipError_t launch_adjoint(const AdjParams& p, int mode, hipStream_t s) {
-    const int grid = (int)(((int64_t)p.n_obj * kGroup + 63) / 64);
+    const int64_t waves = ((int64_t)p.n_obj + kGroup - 1) / kGroup;
+    const int grid = (int)waves;
     if (grid == 0) return hipSuccess;
     const int64_t n_o = (int64_t)p.n_obj * p.k_obs;
     const unsigned go = (unsigned)((n_o + 255) / 256);
     const size_t lds = adjoint_lds_bytes(p);
     const int nb = p.eph.n_body, ngr = p.eph.n_gr, d1 = p.eph.deg1;
-#define KETE_ADJ(K)                                                                                     \
-    do {                                                                                                \
-        if (nb == 9 && ngr == 3 && d1 == 13) hipLaunchKernelGGL((K<9, 3, 13>), dim3(grid), dim3(64), lds, s, p); \
-        else if (nb == 3 && ngr == 2 && d1 == 13)                                                       \
-            hipLaunchKernelGGL((K<3, 2, 13>), dim3(grid), dim3(64), lds, s, p);                         \
-        else hipLaunchKernelGGL((K<0, 0, 0>), dim3(grid), dim3(64), lds, s, p);                         \
-    } while (0)
     if (mode == KETE_ADJ_FWD) {
-        KETE_ADJ(k_adjoint_fwd);
+        if (nb == 9 && ngr == 3 && d1 == 13) hipLaunchKernelGGL((k_adjoint_fwd<9, 3, 13>), dim3(grid), dim3(64), lds, s, p);
+        else if (nb == 3 && ngr == 2 && d1 == 13)
+            hipLaunchKernelGGL((k_adjoint_fwd<3, 2, 13>), dim3(grid), dim3(64), lds, s, p);
+        else hipLaunchKernelGGL((k_adjoint_fwd<0, 0, 0>), dim3(grid), dim3(64), lds, s, p);
         if (n_o > 0) hipLaunchKernelGGL(k_obs_sky, dim3(go), dim3(256), 0, s, p);
-    } else {
-        if (n_o > 0) hipLaunchKernelGGL(k_obs_vjp, dim3(go), dim3(256), 0, s, p);
-        KETE_ADJ(k_adjoint_bwd);
+        return hipGetLastError();
     }
-#undef KETE_ADJ
+    if (n_o > 0) hipLaunchKernelGGL(k_obs_vjp, dim3(go), dim3(256), 0, s, p);
+    constexpr int wpb = kAdjBlock / kWave;
+    const int rgrid = (int)((waves + wpb - 1) / wpb);
+    const size_t rlds = ((((size_t)nb * p.max_win_segs * 3 * d1 + 1) & ~(size_t)1) +
+                         (size_t)wpb * g8_wave_doubles(nb)) * sizeof(double);
+    for (int c = p.n_ckpt - 1; c >= 0; --c) {
+        if (nb == 9 && ngr == 3 && d1 == 13)
+            hipLaunchKernelGGL((k_adj_recompute<kAdjBlock, 9, 3, 13>), dim3(rgrid), dim3(kAdjBlock), rlds, s, p, c);
+        else if (nb == 3 && ngr == 2 && d1 == 13)
+            hipLaunchKernelGGL((k_adj_recompute<kAdjBlock, 3, 2, 13>), dim3(rgrid), dim3(kAdjBlock), rlds, s, p, c);
+        else hipLaunchKernelGGL((k_adj_recompute<kAdjBlock, 0, 0, 0>), dim3(rgrid), dim3(kAdjBlock), rlds, s, p, c);
+        hipLaunchKernelGGL(k_adj_sweep, dim3(grid), dim3(64), 0, s, p, c);
+    }
     return hipGetLastError();
 }
 

@@ -7,6 +7,8 @@
 namespace kete {
 
 constexpr int kCkptDoubles = 8;     // x[3], v[3], wave step, failed flag
+constexpr int kAdjStateDoubles = 8; // lx[3], lv[3], next observation, overflow flag
+constexpr int kAdjLanes = 8;         // lanes per object in the adjoint kernels (8 objects per wavefront)
 
 struct AdjParams {
     EphemArgs eph;
@@ -32,6 +34,8 @@ struct AdjParams {
     double* obs_grad;           // [N][K][6] dL/d(state) at the observation times (backward)
     double* steps;              // [s_max][32][N]
     double* jac;                // [s_max][8][18][N]
+    double* adj_state;          // [N][kAdjStateDoubles] carried between backward segments
+    int32_t* seg_ns;            // [ceil(N / 8)] steps stored per wavefront in the current segment
     int32_t s_max;
     int32_t max_win_segs;
     int32_t max_iter;

@@ -722,6 +722,8 @@ size_t kete_adjoint_workspace_size(int64_t n_obj, int32_t k_obs, double t0, doub
     c.take<double>((size_t)n_obj * std::max(0, k_obs) * 6);    // observation states
     c.take<double>((size_t)n_obj * std::max(0, k_obs) * 6);    // observation cotangents
     c.take<int32_t>(bucket_scratch_ints(n_obj, nbk));
+    c.take<double>((size_t)n_obj * kAdjStateDoubles);                 // carried backward state
+    c.take<int32_t>((size_t)(n_obj + kAdjLanes - 1) / kAdjLanes);           // steps per wavefront
     return c.off;
 }
 
@@ -765,6 +767,8 @@ int kete_propagate_adjoint(const kete_ephem_t* eph, int32_t mode, const double* 
     double* obs_state = c.take<double>((size_t)n_obj * k_obs * 6);
     double* obs_grad = c.take<double>((size_t)n_obj * k_obs * 6);
     int32_t* bscratch = c.take<int32_t>(bucket_scratch_ints(n_obj, nbk));
+    double* adj_state = c.take<double>((size_t)n_obj * kAdjStateDoubles);
+    int32_t* seg_ns = c.take<int32_t>((size_t)(n_obj + kAdjLanes - 1) / kAdjLanes);
 
     hipStream_t s = (hipStream_t)stream;
     HIPCHK(hipMemcpyAsync(dwin, win.data(), win.size() * sizeof(Window), hipMemcpyHostToDevice, s));
@@ -797,6 +801,8 @@ int kete_propagate_adjoint(const kete_ephem_t* eph, int32_t mode, const double* 
     P.steps = scratch;
     P.jac = scratch + (size_t)adj_steps(opts) * 32 * n_obj;
     P.s_max = adj_steps(opts);
+    P.adj_state = adj_state;
+    P.seg_ns = seg_ns;
     P.max_win_segs = std::max(1, opts->window_segs) + 1;
     P.max_iter = opts->max_iter;
     P.max_steps = opts->max_steps;
