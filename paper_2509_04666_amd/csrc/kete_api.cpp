@@ -538,6 +538,7 @@ size_t kete_fov_workspace_size(int64_t n_obj, int64_t n_frames, int64_t n_batch,
     c.take<unsigned long long>((size_t)cand_capacity(n_frames, pairs_cap));
     c.take<int32_t>((size_t)n_frames);
     c.take<int32_t>((size_t)(n_batch * n_obj));     // object cell keys
+    c.take<int32_t>((size_t)(n_batch * n_obj));     // object ranks inside their cell
     c.take<int32_t>((size_t)(n_batch * n_obj));     // objects sorted by cell
     c.take<int32_t>((size_t)nkeys + 1);             // object cell starts and counts
     c.take<int32_t>((size_t)nkeys + 1);
@@ -607,6 +608,7 @@ int kete_fov_check(const kete_ephem_t* eph, const double* x_epoch, const int32_t
     P.cand = c.take<unsigned long long>((size_t)P.cand_cap);
     P.frame_batch = c.take<int32_t>((size_t)F);
     int32_t* okey = c.take<int32_t>((size_t)(n_batch * n_obj));
+    int32_t* orank = c.take<int32_t>((size_t)(n_batch * n_obj));
     int32_t* osorted = c.take<int32_t>((size_t)(n_batch * n_obj));
     int32_t* ostart = c.take<int32_t>((size_t)nkeys + 1);
     int32_t* ocnt = c.take<int32_t>((size_t)nkeys + 1);
@@ -658,7 +660,7 @@ int kete_fov_check(const kete_ephem_t* eph, const double* x_epoch, const int32_t
     HIPCHK(fov_single_job_layout(b_poff, b_obj0, b_xoff, b_G, b_koff, n_batch, n_obj, G, s));
     HIPCHK(fov_prepare(P, qkey, cnt, cnt, scan_scratch, s));
     P.n_wide = counters + 6;
-    HIPCHK(fov_sort_objects(P, okey, ocnt, ostart, osorted, oscan, s));
+    HIPCHK(fov_sort_objects(P, okey, orank, ocnt, ostart, osorted, oscan, s));
     P.obj_sorted = osorted;
     P.obj_start = ostart;
     P.obj_count = ocnt;
@@ -951,7 +953,7 @@ struct BatchWs {
     unsigned int* tile_counter;
     int32_t* perm;
     FovParams P;
-    int32_t *qkey, *cnt, *fcnt, *fstart, *okey, *osorted, *ostart, *ocnt, *icnt, *istart;
+    int32_t *qkey, *cnt, *fcnt, *fstart, *okey, *orank, *osorted, *ostart, *ocnt, *icnt, *istart;
     unsigned long long* items;
     unsigned long long *counters, *sorted;
     void *scan_scratch, *oscan;
@@ -982,6 +984,7 @@ size_t batch_carve(const BatchDims& d, const kete_batch_t* bt, char* base, Batch
     P.cand = c.take<unsigned long long>((size_t)d.cand_cap);
     P.frame_batch = c.take<int32_t>((size_t)d.F);
     w.okey = c.take<int32_t>((size_t)d.NP);
+    w.orank = c.take<int32_t>((size_t)d.NP);
     w.osorted = c.take<int32_t>((size_t)d.NP);
     w.ostart = c.take<int32_t>((size_t)d.nkeys + 1);
     w.ocnt = c.take<int32_t>((size_t)d.nkeys + 1);
@@ -1121,7 +1124,7 @@ int kete_batch_run(const kete_ephem_t* eph, const kete_batch_t* batch, int64_t p
     HIPCHK(fill_zero(w.counters, 8 * sizeof(unsigned long long), s));
     if (dc.B > 0 && dc.F > 0 && dc.NP > 0) {
         HIPCHK(fov_prepare(P, w.qkey, w.cnt, w.cnt, w.scan_scratch, s));
-        HIPCHK(fov_sort_objects(P, w.okey, w.ocnt, w.ostart, w.osorted, w.oscan, s));
+        HIPCHK(fov_sort_objects(P, w.okey, w.orank, w.ocnt, w.ostart, w.osorted, w.oscan, s));
         P.obj_sorted = w.osorted;
         P.obj_start = w.ostart;
         P.obj_count = w.ocnt;

@@ -672,7 +672,8 @@ __global__ __launch_bounds__(256) void k_fov_wide(const FovParams p) {
 // Sky cell of every (object, batch): direction from the batch's mean
 // observer, on the frame grid; wide and failed objects sort after the
 // narrow ones of their batch.
-__global__ void k_obj_keys(const FovParams p, int32_t* __restrict__ okey, int32_t* __restrict__ cnt) {
+__global__ void k_obj_keys(const FovParams p, int32_t* __restrict__ okey, int32_t* __restrict__ orank,
+                           int32_t* __restrict__ cnt) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= p.n_pairs_total) return;
     const int b = batch_of(p.b_poff, p.n_batch, i);
@@ -688,17 +689,19 @@ __global__ void k_obj_keys(const FovParams p, int32_t* __restrict__ okey, int32_
         if (live) wave_append(p.wide, p.n_wide, p.n_pairs_total, ((unsigned long long)b << 32) | (unsigned long long)j);
     }
     okey[i] = key;
-    atomicAdd(cnt + key, 1);
+    orank[i] = atomicAdd(cnt + key, 1);
 }
 
-__global__ void k_obj_scatter(const FovParams p, const int32_t* __restrict__ okey, const int32_t* __restrict__ start,
-                              int32_t* __restrict__ cursor, int32_t* __restrict__ sorted) {
+// Objects into their cell's slots, at the rank the key pass drew (the order
+// inside a cell is arbitrary: the pairs are sorted at the end).
+__global__ void k_obj_scatter(const FovParams p, const int32_t* __restrict__ okey, const int32_t* __restrict__ orank,
+                              const int32_t* __restrict__ start, int32_t* __restrict__ sorted) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= p.n_pairs_total) return;
     const int key = okey[i];
     const int b = batch_of(p.b_poff, p.n_batch, i);
     // keys are batch-major, so batch b occupies [b_poff[b], b_poff[b+1])
-    sorted[start[key] + atomicAdd(cursor + key, 1)] = (int32_t)(i - p.b_poff[b]);
+    sorted[start[key] + orank[i]] = (int32_t)(i - p.b_poff[b]);
 }
 
 // Exact test of every candidate (one lane per candidate, grid-stride).
@@ -903,19 +906,18 @@ hipError_t fov_prepare(const FovParams& p, int32_t* qkey, int32_t* cnt, int32_t*
     return hipGetLastError();
 }
 
-hipError_t fov_sort_objects(const FovParams& p, int32_t* okey, int32_t* cnt, int32_t* start, int32_t* sorted,
-                            void* scan_scratch, hipStream_t s) {
+hipError_t fov_sort_objects(const FovParams& p, int32_t* okey, int32_t* orank, int32_t* cnt, int32_t* start,
+                            int32_t* sorted, void* scan_scratch, hipStream_t s) {
     const int64_t n = p.n_pairs_total;
     const int64_t nkeys = p.n_keys;
     if (n == 0) return hipSuccess;
     hipError_t e;
     if ((e = fill_zero(cnt, (size_t)(nkeys + 1) * sizeof(int32_t), s)) != hipSuccess) return e;
     const unsigned g = (unsigned)((n + 255) / 256);
-    hipLaunchKernelGGL(k_obj_keys, dim3(g), dim3(256), 0, s, p, okey, cnt);
+    hipLaunchKernelGGL(k_obj_keys, dim3(g), dim3(256), 0, s, p, okey, orank, cnt);
     if ((e = exclusive_scan_i32(cnt, start, nkeys, scan_scratch, s)) != hipSuccess) return e;
-    if ((e = fill_zero(cnt, (size_t)nkeys * sizeof(int32_t), s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_obj_scatter, dim3(g), dim3(256), 0, s, p, (const int32_t*)okey, (const int32_t*)start, cnt,
-                       sorted);
+    hipLaunchKernelGGL(k_obj_scatter, dim3(g), dim3(256), 0, s, p, (const int32_t*)okey, (const int32_t*)orank,
+                       (const int32_t*)start, sorted);
     return hipGetLastError();
 }
 

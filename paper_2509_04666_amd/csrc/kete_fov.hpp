@@ -67,7 +67,8 @@ struct FovParams {
 
 hipError_t fov_prepare(const FovParams& p, int32_t* qkey, int32_t* cnt, int32_t* cursor, void* scan_scratch,
                        hipStream_t s);
-hipError_t fov_sort_objects(const FovParams& p, int32_t* okey, int32_t* cnt, int32_t* start, int32_t* sorted,
+hipError_t fov_sort_objects(const FovParams& p, int32_t* okey, int32_t* orank, int32_t* cnt, int32_t* start,
+                            int32_t* sorted,
                             void* scan_scratch, hipStream_t s);
 // Candidate generation.  icnt and istart are [n_keys + 1] int32 scratch
 // (istart becomes p.item_start), items holds n_keys + n_pairs_total / 64 + 1
