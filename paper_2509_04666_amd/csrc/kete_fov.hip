@@ -373,24 +373,23 @@ __device__ __forceinline__ bool frame_cap_hit(const ObjBounds& o, const double* 
     return !(dot3(cp, o.dh) < thr - 1e-12);
 }
 
-// Linear-motion test of a frame that passed the cap test.
-// Linear-motion test with its remainder bound: the object moves on
-// x + v dt within eps of its true position, so it is outside a sub-frame
-// when some normal has n . ul / |ul| <= -2 eps / |ul|.  dt is the frame
-// time minus the batch epoch, ob the observer, nrm the n_sub x 4 normals.
+// Linear-motion test of a frame that passed the cap test, with its
+// remainder bound: the object moves on x + v dt within eps of its true
+// position, so it is outside a sub-frame when some unit normal has
+// n . ul <= -2 eps (the true direction's dot product is then negative);
+// the test is void when 2 eps reaches |ul|.  dt is the frame time minus
+// the batch epoch, ob the observer, nrm the n_sub x 4 normals.
 __device__ __forceinline__ bool lin_may_contain(const ObjBounds& o, double dt, const double ob[3],
                                                 const double* __restrict__ nrm, int n_sub, double Asun) {
     if (!o.lin_ok) return true;
     double ul[3];
     for (int c = 0; c < 3; ++c) ul[c] = o.x[c] + o.v[c] * dt - ob[c];
-    const double uln = sqrt(dot3(ul, ul));
     const double ad = fabs(dt) + o.taumax;
-    const double eps = o.vbn * o.taumax + 0.5 * (o.a2b + Asun) * ad * ad + 1e-12;
-    const double eta = 2.0 * eps / uln;
-    if (!(eta < 1.0)) return true;
+    const double e2 = 2.0 * (o.vbn * o.taumax + 0.5 * (o.a2b + Asun) * ad * ad + 1e-12);
+    if (!(e2 * e2 < dot3(ul, ul))) return true;
     for (int s = 0; s < n_sub; ++s) {
         bool out = false;
-        for (int i = 0; i < 4; ++i) out |= dot3(nrm + 12 * s + 3 * i, ul) / uln <= -eta;
+        for (int i = 0; i < 4; ++i) out |= dot3(nrm + 12 * s + 3 * i, ul) <= -e2;
         if (!out) return true;
     }
     return false;
