@@ -468,14 +468,41 @@ __global__ void k_item_scatter(const FovParams p, const int32_t* __restrict__ ic
     for (int c = 0; c < n; ++c) p.items[s0 + c] = ((unsigned long long)key << 32) | (unsigned long long)c;
 }
 
+// A frame's cap record (centre, cos and sin of the radius, frame index) as
+// three 16-byte LDS words.
+struct __align__(16) double6 {
+    double a, b, c, d, e, f;
+};
+
+// Linear-motion data of one object of a join item, kept in LDS so that
+// any lane can run the linear test of any (object, frame) pair.
+struct ObjLin {
+    double x[3], v[3];
+    double taumax, vbn, a2b;
+    unsigned long long gobj;    // global object index; bit 63 set: no linear test
+};
+constexpr int kLinQueue = 2 * kWave;
+
 // Persistent join: every wavefront pops work items until none is left.
+// An item is up to 64 narrow objects of one (batch, cell), one per lane;
+// the frame records of the 27 neighbouring cells are read 64 at a time,
+// one per lane, and broadcast for the cap test.  (object, frame) pairs
+// that pass it are queued in LDS and take the linear-motion test 64 at a
+// time, one pair per lane.
 __global__ __launch_bounds__(256, 3) void k_fov_cells(const FovParams p) {
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63, wv = (threadIdx.x >> 6) & 3;
     unsigned long long n_cand = 0, n_exact = 0, n_visit = 0;
     const double* __restrict__ caps = p.cell_caps;
     const int n_items = p.item_start[p.n_keys];
     __shared__ unsigned long long bufs[4][kBufEntries];
-    unsigned long long* buf = bufs[(threadIdx.x >> 6) & 3];
+    __shared__ ObjLin objs_all[4][kWave];
+    __shared__ unsigned long long queue_all[4][kLinQueue];
+    __shared__ double6 fcap_all[4][kWave];
+    unsigned long long* buf = bufs[wv];
+    double6* fcap = fcap_all[wv];
+    ObjLin* objs = objs_all[wv];
+    unsigned long long* queue = queue_all[wv];
+    const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     int nbuf = 0;
     for (;;) {
         int item = 0;
@@ -514,47 +541,90 @@ __global__ __launch_bounds__(256, 3) void k_fov_cells(const FovParams p) {
         const int excl = incl - my_len;
         const int total = __shfl(incl, 26, kWave);
         if (total == 0) continue;
+        const int q = o0 + lane;
+        const bool has = q < o1;
+        const int64_t j = has ? p.obj_sorted[q] : 0;
+        ObjBounds o;
+        const bool live = has && object_bounds(p, b, j, o);
+        wave_lds_sync();                      // the previous item's queue and objects are done
         {
-            const int q = o0 + lane;
-            const bool has = q < o1;
-            const int64_t j = has ? p.obj_sorted[q] : 0;
-            ObjBounds o;
-            const bool live = has && object_bounds(p, b, j, o);
-            const unsigned long long gobj = (unsigned long long)(p.b_obj0[b] + j);
-            for (int g0 = 0; g0 < total; g0 += kWave) {
-                // lane l holds frame record g0 + l of the neighbourhood list
-                const int g = g0 + lane;
-                int nq = 0;
-                for (int t = 1; t < 27; ++t) nq = (__shfl(excl, t, kWave) <= g) ? t : nq;
-                const int rk = __shfl(my_a0, nq, kWave) + (g - __shfl(excl, nq, kWave));
-                double r[6] = {0.0, 0.0, 0.0, 2.0, 0.0, 0.0};
-                if (g < total) {
-                    const double* cp = caps + 8 * (int64_t)rk;
-                    const double2 c01 = *reinterpret_cast<const double2*>(cp);
-                    const double2 c23 = *reinterpret_cast<const double2*>(cp + 2);
-                    const double2 c45 = *reinterpret_cast<const double2*>(cp + 4);
-                    r[0] = c01.x; r[1] = c01.y; r[2] = c23.x; r[3] = c23.y; r[4] = c45.x; r[5] = c45.y;
-                }
-                const int n = min(kWave, total - g0);
-                n_visit += (unsigned long long)n;
-                for (int m = 0; m < n; ++m) {
-                    double cpm[5];
+            ObjLin& ol = objs[lane];
 #pragma unroll
-                    for (int i = 0; i < 5; ++i) cpm[i] = lane_value(r[i], m);
-                    const bool hit = live && frame_cap_hit(o, cpm);
-                    if (__ballot(hit) == 0ull) continue;
-                    // a frame some lane may see: its time, observer and
-                    // normals are read at a wave-uniform address
-                    const int f = __builtin_amdgcn_readfirstlane((int)lane_value(r[5], m));
-                    const double dt = p.ft[f] - tr;
+            for (int c = 0; c < 3; ++c) { ol.x[c] = o.x[c]; ol.v[c] = o.v[c]; }
+            ol.taumax = o.taumax; ol.vbn = o.vbn; ol.a2b = o.a2b;
+            ol.gobj = (unsigned long long)(p.b_obj0[b] + j) | (o.lin_ok ? 0ull : (1ull << 63));
+        }
+        wave_lds_sync();
+        int nq = 0;                           // queued (object, frame) pairs, wave-uniform
+        // linear test of the first n queued pairs, one per lane
+        auto drain = [&](int n) {
+            bool may = false;
+            int f = 0;
+            unsigned long long gobj = 0;
+            if (lane < n) {
+                const unsigned long long e = queue[lane];
+                const ObjLin& ol = objs[e & 63];
+                f = (int)(e >> 8);
+                gobj = ol.gobj & ~(1ull << 63);
+                if (ol.gobj >> 63) {
+                    may = true;
+                } else {
+                    ObjBounds lo;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) { lo.x[c] = ol.x[c]; lo.v[c] = ol.v[c]; }
+                    lo.taumax = ol.taumax; lo.vbn = ol.vbn; lo.a2b = ol.a2b; lo.lin_ok = true;
                     const double ob[3] = {p.fobs[3 * f], p.fobs[3 * f + 1], p.fobs[3 * f + 2]};
-                    const bool may = hit && lin_may_contain(o, dt, ob, p.normals + (size_t)f * p.n_sub * 12, p.n_sub,
-                                                            Asun);
-                    if (hit) ++n_cand;
-                    if (may) ++n_exact;
-                    buf_append(buf, nbuf, may, ((unsigned long long)f << 32) | gobj, p.cand, p.n_cand, p.cand_cap);
+                    may = lin_may_contain(lo, p.ft[f] - tr, ob, p.normals + (size_t)f * p.n_sub * 12, p.n_sub, Asun);
                 }
             }
+            if (may) ++n_exact;
+            buf_append(buf, nbuf, may, ((unsigned long long)f << 32) | gobj, p.cand, p.n_cand, p.cand_cap);
+        };
+        for (int g0 = 0; g0 < total; g0 += kWave) {
+            // lane l holds frame record g0 + l of the neighbourhood list
+            const int g = g0 + lane;
+            int nc = 0;
+            for (int t = 1; t < 27; ++t) nc = (__shfl(excl, t, kWave) <= g) ? t : nc;
+            const int rk = __shfl(my_a0, nc, kWave) + (g - __shfl(excl, nc, kWave));
+            // the chunk's cap records go to LDS and are read back as broadcasts
+            double6 rec = {0.0, 0.0, 0.0, 2.0, 0.0, 0.0};
+            if (g < total) {
+                const double* cp = caps + 8 * (int64_t)rk;
+                const double2 c01 = *reinterpret_cast<const double2*>(cp);
+                const double2 c23 = *reinterpret_cast<const double2*>(cp + 2);
+                const double2 c45 = *reinterpret_cast<const double2*>(cp + 4);
+                rec = {c01.x, c01.y, c23.x, c23.y, c45.x, c45.y};
+            }
+            wave_lds_sync();                  // the previous chunk's records are read
+            fcap[lane] = rec;
+            wave_lds_sync();
+            const int n = min(kWave, total - g0);
+            n_visit += (unsigned long long)n;
+            for (int m = 0; m < n; ++m) {
+                const double6 cm = fcap[m];
+                const double cpm[5] = {cm.a, cm.b, cm.c, cm.d, cm.e};
+                const bool hit = live && frame_cap_hit(o, cpm);
+                const unsigned long long mask = __ballot(hit);
+                if (mask == 0ull) continue;
+                if (hit) ++n_cand;
+                const unsigned long long f = (unsigned long long)(unsigned int)(int)cm.f;
+                if (hit) queue[nq + __popcll(mask & lt)] = (f << 8) | (unsigned long long)lane;
+                nq += __popcll(mask);
+                if (nq >= kWave) {
+                    wave_lds_sync();
+                    drain(kWave);
+                    // move the overflow to the front (fewer than 64 entries)
+                    const unsigned long long rest = lane < nq - kWave ? queue[kWave + lane] : 0ull;
+                    wave_lds_sync();
+                    if (lane < nq - kWave) queue[lane] = rest;
+                    nq -= kWave;
+                    wave_lds_sync();
+                }
+            }
+        }
+        if (nq > 0) {
+            wave_lds_sync();
+            drain(nq);
         }
     }
     buf_flush(buf, nbuf, p.cand, p.n_cand, p.cand_cap);
