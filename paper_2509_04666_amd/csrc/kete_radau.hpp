@@ -275,20 +275,60 @@ __device__ __forceinline__ void load_node_row(const RadauConst& rc, int n, NodeR
     }
 }
 
-// Wave-wide reductions of values that are equal within each group: with
-// aligned 8-lane groups three exchange steps suffice, otherwise all six.
-template <int G = kGroup>
-__device__ __forceinline__ double groups_max(double x) {
-#pragma unroll
-    for (int off = (G == 8 ? 8 : 1); off < kWave; off <<= 1) x = fmax(x, __shfl_xor(x, off, kWave));
+// Wave-wide reductions of values that are equal within each group, as a
+// butterfly of lane permutations that stay in the vector unit: DPP quad
+// permutes (lanes xor 1, xor 2), the half-row and row mirrors (lane i with
+// 7 - i, with 15 - i) and the row-pair and half-wave swaps (xor 16, xor
+// 32).  Aligned 8-lane groups need only the last three steps.
+struct PermDouble {
+    unsigned lo, hi;
+};
+__device__ __forceinline__ PermDouble split_double(double x) {
+    const unsigned long long u = __double_as_longlong(x);
+    return PermDouble{(unsigned)u, (unsigned)(u >> 32)};
+}
+__device__ __forceinline__ double join_double(unsigned lo, unsigned hi) {
+    return __longlong_as_double(((long long)hi << 32) | lo);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_double(double x) {
+    const PermDouble d = split_double(x);
+    return join_double((unsigned)__builtin_amdgcn_update_dpp(0, (int)d.lo, CTRL, 0xF, 0xF, false),
+                       (unsigned)__builtin_amdgcn_update_dpp(0, (int)d.hi, CTRL, 0xF, 0xF, false));
+}
+// the other operand of a max/min step across rows (xor 16) and halves (xor 32)
+__device__ __forceinline__ double swap16_double(double x) {
+    const PermDouble d = split_double(x);
+    const auto lo = __builtin_amdgcn_permlane16_swap(d.lo, d.lo, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(d.hi, d.hi, false, false);
+    // both results hold each lane's own value in one and its xor-16 partner in the other
+    const double a = join_double(lo[0], hi[0]), b = join_double(lo[1], hi[1]);
+    return ((threadIdx.x >> 4) & 1) ? a : b;
+}
+__device__ __forceinline__ double swap32_double(double x) {
+    const PermDouble d = split_double(x);
+    const auto lo = __builtin_amdgcn_permlane32_swap(d.lo, d.lo, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(d.hi, d.hi, false, false);
+    const double a = join_double(lo[0], hi[0]), b = join_double(lo[1], hi[1]);
+    return ((threadIdx.x >> 5) & 1) ? a : b;
+}
+template <int G = kGroup, bool MAX = true>
+__device__ __forceinline__ double groups_reduce(double x) {
+    auto op = [](double a, double b) { return MAX ? fmax(a, b) : fmin(a, b); };
+    if constexpr (G != 8) {
+        x = op(x, dpp_double<0xB1>(x));      // lane xor 1
+        x = op(x, dpp_double<0x4E>(x));      // lane xor 2
+        x = op(x, dpp_double<0x141>(x));     // 7 - lane within 8
+    }
+    x = op(x, dpp_double<0x140>(x));         // 15 - lane within 16
+    x = op(x, swap16_double(x));
+    x = op(x, swap32_double(x));
     return uniform(x);
 }
 template <int G = kGroup>
-__device__ __forceinline__ double groups_min(double x) {
-#pragma unroll
-    for (int off = (G == 8 ? 8 : 1); off < kWave; off <<= 1) x = fmin(x, __shfl_xor(x, off, kWave));
-    return uniform(x);
-}
+__device__ __forceinline__ double groups_max(double x) { return groups_reduce<G, true>(x); }
+template <int G = kGroup>
+__device__ __forceinline__ double groups_min(double x) { return groups_reduce<G, false>(x); }
 
 // Perturber table of the grouped integrator: per node and slot 8 doubles
 // (x, y, z, GM, vx, vy, vz, GM/c^2).  GM values are written once per
