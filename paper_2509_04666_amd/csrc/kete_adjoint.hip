@@ -395,7 +395,7 @@ __global__ __launch_bounds__(BLOCK, 2) void k_adj_recompute(const AdjParams p, c
                     V[i] = fma(h, av, St.v0[i]);
                 }
                 double Jx[9], Jv[9];
-                accel_jac8(e8 + jnode * g8_row(E.n_body), E, X, V, Jx, Jv);
+                accel_jac8<NB, NGR>(e8 + jnode * g8_row(E.n_body), E, X, V, Jx, Jv);
                 double* jp = p.jac + (size_t)ns * 8 * kJacDoubles * N;
                 #pragma unroll
                 for (int q = 0; q < 9; ++q) {
@@ -577,7 +577,8 @@ __global__ __launch_bounds__(64) void k_adj_sweep(const AdjParams p, const int c
                 dm = fmax(dm, __shfl_xor(dm, off, kWave));
                 mm = fmax(mm, __shfl_xor(mm, off, kWave));
             }
-            pc = groups_max((ok_final && mm > 0.0) ? dm / mm : 0.0);
+            // the ratio only steers the stopping rule: the reciprocal estimate suffices
+            pc = groups_max((ok_final && mm > 0.0) ? dm * __builtin_amdgcn_rcp(mm) : 0.0);
         } while (!(pc < 1e-16) && !(it > 2 && pcl <= pc) && it < 2 * p.max_iter);
         // step-start Jacobians (lane 7) applied to m0, shared with the group
         double a0[3], b0[3];

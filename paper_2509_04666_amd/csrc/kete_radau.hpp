@@ -529,40 +529,71 @@ __device__ __forceinline__ void accel8_group(const double* __restrict__ e8, cons
 }
 
 // Jacobians Jx = da/dx, Jv = da/dv (row-major 3x3) from the grouped
-// table e8 (one node); same force as accel_jac.
+// table e8 (one node); same force as accel_jac.  The Newtonian part is
+// symmetric and accumulated once per pair (i <= j); the Eq. A.3 part,
+// with P = s1 r + 4 (r.w) w and s1 = 4 mu / r - w^2, is
+//   Jx += k [(-3 P / r^5 - 4 mu r / r^6) r^T + 4 w w^T / r^3 + s1 I / r^3]
+//   Jv += k / r^3 [-2 r w^T + 4 w r^T + 4 (r.w) I].
+// NB = 0 takes the counts at run time.
+template <int NB, int NGR>
 __device__ __forceinline__ void accel_jac8(const double* __restrict__ e8, const EphemArgs& E, const double X[3],
                                            const double V[3], double Jx[9], double Jv[9]) {
+    const int nb = NB > 0 ? NB : E.n_body;
+    const int ngr = NB > 0 ? NGR : E.n_gr;
+    double S[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // xx xy xz yy yz zz
+    double dg = 0.0;
+#pragma unroll
     for (int i = 0; i < 9; ++i) { Jx[i] = 0.0; Jv[i] = 0.0; }
-    for (int sl = 0; sl < E.n_body; ++sl) {
+#pragma unroll
+    for (int sl = 0; sl < (NB > 0 ? NB : KETE_MAX_BODIES); ++sl) {
+        if (NB == 0 && sl >= nb) break;
         const double* pb = e8 + kSlot * sl;
-        const double r[3] = {X[0] - pb[0], X[1] - pb[1], X[2] - pb[2]};
-        const double r2 = dot3(r, r);
-        const double ir = rsqrt(r2);
+        const double2 pxy = *reinterpret_cast<const double2*>(pb);
+        const double2 pzg = *reinterpret_cast<const double2*>(pb + 2);
+        const double r[3] = {X[0] - pxy.x, X[1] - pxy.y, X[2] - pzg.x};
+        const double r2 = fma(r[0], r[0], fma(r[1], r[1], r[2] * r[2]));
+        const double ir = rsqrt_pos(r2);
         const double ir2 = ir * ir, ir3 = ir2 * ir, ir5 = ir3 * ir2;
-        const double gm = pb[3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j)
-                Jx[3 * i + j] += gm * (3.0 * r[i] * r[j] * ir5 - (i == j ? ir3 : 0.0));
-        if (sl < E.n_gr) {
-            const double k = pb[7];
-            const double w[3] = {V[0] - pb[4], V[1] - pb[5], V[2] - pb[6]};
-            const double w2 = dot3(w, w), rw = dot3(r, w);
+        const double gm = pzg.y;
+        const double sN = 3.0 * gm * ir5;
+        const double a[3] = {sN * r[0], sN * r[1], sN * r[2]};
+        S[0] = fma(a[0], r[0], S[0]); S[1] = fma(a[0], r[1], S[1]); S[2] = fma(a[0], r[2], S[2]);
+        S[3] = fma(a[1], r[1], S[3]); S[4] = fma(a[1], r[2], S[4]); S[5] = fma(a[2], r[2], S[5]);
+        dg = fma(-gm, ir3, dg);
+        if (sl < ngr) {
+            const double2 vxy = *reinterpret_cast<const double2*>(pb + 4);
+            const double2 vzk = *reinterpret_cast<const double2*>(pb + 6);
+            const double k = vzk.y;
+            const double w[3] = {V[0] - vxy.x, V[1] - vxy.y, V[2] - vzk.x};
+            const double w2 = fma(w[0], w[0], fma(w[1], w[1], w[2] * w[2]));
+            const double rw = fma(r[0], w[0], fma(r[1], w[1], r[2] * w[2]));
             const double s1 = 4.0 * gm * ir - w2;
-            const double P[3] = {s1 * r[0] + 4.0 * rw * w[0], s1 * r[1] + 4.0 * rw * w[1], s1 * r[2] + 4.0 * rw * w[2]};
-            const double ir6 = ir3 * ir3;
+            const double kr3 = k * ir3;
+            const double c1 = -3.0 * k * ir5, c2 = -4.0 * k * gm * ir3 * ir3, c4 = 4.0 * kr3;
+            double u[3], v[3], pr[3], qw[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const double P = fma(s1, r[i], 4.0 * rw * w[i]);
+                u[i] = fma(c1, P, c2 * r[i]);
+                v[i] = c4 * w[i];
+                pr[i] = -2.0 * kr3 * r[i];
+                qw[i] = c4 * w[i];
+            }
 #pragma unroll
             for (int i = 0; i < 3; ++i)
 #pragma unroll
                 for (int j = 0; j < 3; ++j) {
-                    const double d = (i == j) ? 1.0 : 0.0;
-                    Jx[3 * i + j] += k * (-3.0 * P[i] * r[j] * ir5 - 4.0 * gm * r[i] * r[j] * ir6 + s1 * d * ir3 +
-                                          4.0 * w[i] * w[j] * ir3);
-                    Jv[3 * i + j] += k * ir3 * (-2.0 * r[i] * w[j] + 4.0 * w[i] * r[j] + 4.0 * rw * d);
+                    Jx[3 * i + j] = fma(u[i], r[j], fma(v[i], w[j], Jx[3 * i + j]));
+                    Jv[3 * i + j] = fma(pr[i], w[j], fma(qw[i], r[j], Jv[3 * i + j]));
                 }
+            const double dx = kr3 * s1, dv = c4 * rw;
+            Jx[0] += dx; Jx[4] += dx; Jx[8] += dx;
+            Jv[0] += dv; Jv[4] += dv; Jv[8] += dv;
         }
     }
+    Jx[0] += S[0] + dg; Jx[1] += S[1]; Jx[2] += S[2];
+    Jx[3] += S[1]; Jx[4] += S[3] + dg; Jx[5] += S[4];
+    Jx[6] += S[2]; Jx[7] += S[4]; Jx[8] += S[5] + dg;
 }
 
 // Step-size factor (eps / e)^(1/7) of the IAS15 control, in single
