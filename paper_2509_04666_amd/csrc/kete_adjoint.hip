@@ -171,13 +171,17 @@ __device__ void hop_vjp(const AdjParams& p, const SunGlobal& sun, double t_obs, 
 // collocation node, 8 objects per wavefront, wave-shared steps) with the
 // step loop of the propagation kernels.
 
-// Checkpoint c of object j: state, the step size to resume with, and a
-// failure flag; lanes 0..7 of the group write one double each.
+// Checkpoint c of object j: state, the step size to resume with, a
+// failure flag and the force at the state (with whether it was evaluated
+// yet), so that a recompute repeats the forward's steps exactly; lanes
+// 0..7 of the group write the first eight values, lanes 0..3 the rest.
 __device__ __forceinline__ void save_ckpt_g8(const AdjParams& p, int c, int j, int gl, const G8State& S) {
     double* ck = p.ckpt + ((size_t)c * p.n_obj + j) * kCkptDoubles;
     const double v = gl < 6 ? state_component(S.x0, S.v0, gl)
                             : gl == 6 ? S.hw : (S.active ? 0.0 : (double)(S.status ? S.status : 1));
     ck[gl] = v;
+    const double f = gl == 0 ? S.F0[0] : gl == 1 ? S.F0[1] : gl == 2 ? S.F0[2] : (S.haveF0 ? 1.0 : 0.0);
+    if (gl < 4) ck[8 + gl] = f;
 }
 
 
@@ -297,6 +301,9 @@ __global__ __launch_bounds__(256) void k_obs_vjp(const AdjParams p) {
 struct AdjCols {
     double cA[7], cB[7], gA, gB;
 };
+constexpr int kAdjColDoubles = 16;
+static_assert(sizeof(AdjCols) == kAdjColDoubles * sizeof(double), "AdjCols is 16 doubles");
+static_assert(kAdjTabDoubles == kGroup * (kAdjColDoubles + 18), "table size");
 
 __device__ __forceinline__ void load_adj_cols(const RadauConst& rc, int gl, AdjCols& c) {
 #pragma unroll
@@ -358,14 +365,17 @@ __global__ __launch_bounds__(BLOCK, 2) void k_adj_recompute(const AdjParams p, c
     G8State S;
     init_lane_state(p, false, j, S);
     double hw = 0.0;
+    bool have_f0 = false;
     if (valid) {
         const double* ck = p.ckpt + ((size_t)c * N + j) * kCkptDoubles;
 #pragma unroll
-        for (int i = 0; i < 3; ++i) { S.x0[i] = ck[i]; S.v0[i] = ck[3 + i]; }
+        for (int i = 0; i < 3; ++i) { S.x0[i] = ck[i]; S.v0[i] = ck[3 + i]; S.F0[i] = ck[8 + i]; }
         hw = ck[6];
         S.active = ck[7] == 0.0;
+        have_f0 = ck[11] != 0.0;
     }
     S.hw = groups_max(valid ? hw : 0.0);        // the same value in every valid group
+    S.haveF0 = __ballot(have_f0) != 0ull;       // as in the forward at this checkpoint
     S.t = p.win[p.seg_win[c]].t_a;
     G8Count Cn;
     int ns = 0;
@@ -416,6 +426,35 @@ __global__ __launch_bounds__(BLOCK, 2) void k_adj_recompute(const AdjParams p, c
     if (lane == 0 && wave * kGroup < p.n_obj) p.seg_ns[wave] = min(ns, p.s_max) | (overflow_steps ? kSegOverflow : 0);
 }
 
+// Constant rows of the reverse sweep, for the 8 lanes of a group: the
+// stage columns (AdjCols) and the dense-output rows alpha(sig) =
+// sum_k dr[k] sig^(k+2) + dr[16] sig^2, beta(sig) = sum_k dr[8+k] sig^(k+1)
+// + dr[17] sig of stage m = lane + 1 (lanes 0..6), and minus the sum over
+// the stages for lane 7.  One block of 64 threads.
+__global__ void k_adj_tables(const AdjParams p) {
+    const int lane = threadIdx.x;
+    if (lane >= kGroup) return;
+    const RadauConst& rc = p.rc;
+    AdjCols q;
+    load_adj_cols(rc, lane, q);
+    double* col = p.adj_tab + lane * kAdjColDoubles;
+    for (int n = 0; n < 7; ++n) { col[n] = q.cA[n]; col[7 + n] = q.cB[n]; }
+    col[14] = q.gA;
+    col[15] = q.gB;
+    double* dr = p.adj_tab + kGroup * kAdjColDoubles + lane * 18;
+    for (int k = 0; k < 8; ++k) {
+        double a = 0.0, b = 0.0, sa = 0.0, sb = 0.0;
+        for (int m = 0; m < 7; ++m) {
+            sa += rc.Ap[m][k]; sb += rc.Bp[m][k];
+            if (m == lane) { a = rc.Ap[m][k]; b = rc.Bp[m][k]; }
+        }
+        dr[k] = lane < 7 ? a : -sa;
+        dr[8 + k] = lane < 7 ? b : -sb;
+    }
+    dr[16] = lane < 7 ? 0.0 : 0.5;
+    dr[17] = lane < 7 ? 0.0 : 1.0;
+}
+
 // Backward, second half for checkpoint segment c: the reverse sweep over
 // the stored steps, one 8-lane group per object (lane m - 1 holds the
 // stage cotangent mu_m, lane 7 the step-start term), carrying the state
@@ -432,23 +471,12 @@ __global__ __launch_bounds__(64) void k_adj_sweep(const AdjParams p, const int c
     double* xw = xw_all + (lane / kGroup) * kGroup * 6;
     __shared__ AdjCols cols[kGroup];
     __shared__ double drow[kGroup][18];      // own dense-output row (see below)
-    if (lane < kGroup) {
-        AdjCols q;
-        load_adj_cols(rc, lane, q);
-        cols[lane] = q;
-        // alpha(sig) = sum_k drow[k] sig^(k+2) + drow[16] sig^2, beta(sig) = sum_k drow[8+k] sig^(k+1) + drow[17] sig:
-        // stage m = lane + 1 for lanes 0..6, minus the sum over stages for lane 7
-        for (int k = 0; k < 8; ++k) {
-            double a = 0.0, b = 0.0, sa = 0.0, sb = 0.0;
-            for (int m = 0; m < 7; ++m) {
-                sa += rc.Ap[m][k]; sb += rc.Bp[m][k];
-                if (m == lane) { a = rc.Ap[m][k]; b = rc.Bp[m][k]; }
-            }
-            drow[lane][k] = lane < 7 ? a : -sa;
-            drow[lane][8 + k] = lane < 7 ? b : -sb;
-        }
-        drow[lane][16] = lane < 7 ? 0.0 : 0.5;
-        drow[lane][17] = lane < 7 ? 0.0 : 1.0;
+    {
+        // the constant rows, computed once per call by k_adj_tables
+        const double* src = p.adj_tab;
+        double* dst = &cols[0].cA[0];
+        for (int i = lane; i < kAdjTabDoubles; i += kWave)
+            (i < kGroup * kAdjColDoubles ? dst[i] : drow[0][i - kGroup * kAdjColDoubles]) = src[i];
     }
     __syncthreads();
     const AdjCols& Q = cols[gl];
@@ -647,6 +675,7 @@ hipError_t launch_adjoint(const AdjParams& p, int mode, hipStream_t s) {
         return hipGetLastError();
     }
     if (n_o > 0) hipLaunchKernelGGL(k_obs_vjp, dim3(go), dim3(256), 0, s, p);
+    hipLaunchKernelGGL(k_adj_tables, dim3(1), dim3(64), 0, s, p);
     constexpr int wpb = kAdjBlock / kWave;
     const int rgrid = (int)((waves + wpb - 1) / wpb);
     const size_t rlds = ((((size_t)nb * p.max_win_segs * 3 * d1 + 1) & ~(size_t)1) +

@@ -6,9 +6,10 @@
 
 namespace kete {
 
-constexpr int kCkptDoubles = 8;     // x[3], v[3], wave step, failed flag
+constexpr int kCkptDoubles = 12;    // x[3], v[3], wave step, failed flag, force F0[3], F0 valid
 constexpr int kAdjStateDoubles = 8; // lx[3], lv[3], next observation, overflow flag
 constexpr int kAdjLanes = 8;         // lanes per object in the adjoint kernels (8 objects per wavefront)
+constexpr int kAdjTabDoubles = 8 * (16 + 18);   // constant rows of the reverse sweep
 
 struct AdjParams {
     EphemArgs eph;
@@ -36,6 +37,7 @@ struct AdjParams {
     double* jac;                // [s_max][8][18][N]
     double* adj_state;          // [N][kAdjStateDoubles] carried between backward segments
     int32_t* seg_ns;            // [ceil(N / 8)] steps stored per wavefront in the current segment
+    double* adj_tab;            // [kAdjTabDoubles] constant rows of the reverse sweep
     int32_t s_max;
     int32_t max_win_segs;
     int32_t max_iter;

@@ -726,6 +726,7 @@ size_t kete_adjoint_workspace_size(int64_t n_obj, int32_t k_obs, double t0, doub
     c.take<int32_t>(bucket_scratch_ints(n_obj, nbk));
     c.take<double>((size_t)n_obj * kAdjStateDoubles);                 // carried backward state
     c.take<int32_t>((size_t)(n_obj + kAdjLanes - 1) / kAdjLanes);           // steps per wavefront
+    c.take<double>((size_t)kAdjTabDoubles);                           // reverse-sweep constants
     return c.off;
 }
 
@@ -771,6 +772,7 @@ int kete_propagate_adjoint(const kete_ephem_t* eph, int32_t mode, const double* 
     int32_t* bscratch = c.take<int32_t>(bucket_scratch_ints(n_obj, nbk));
     double* adj_state = c.take<double>((size_t)n_obj * kAdjStateDoubles);
     int32_t* seg_ns = c.take<int32_t>((size_t)(n_obj + kAdjLanes - 1) / kAdjLanes);
+    double* adj_tab = c.take<double>((size_t)kAdjTabDoubles);
 
     hipStream_t s = (hipStream_t)stream;
     HIPCHK(hipMemcpyAsync(dwin, win.data(), win.size() * sizeof(Window), hipMemcpyHostToDevice, s));
@@ -805,6 +807,7 @@ int kete_propagate_adjoint(const kete_ephem_t* eph, int32_t mode, const double* 
     P.s_max = adj_steps(opts);
     P.adj_state = adj_state;
     P.seg_ns = seg_ns;
+    P.adj_tab = adj_tab;
     P.max_win_segs = std::max(1, opts->window_segs) + 1;
     P.max_iter = opts->max_iter;
     P.max_steps = opts->max_steps;

@@ -705,6 +705,7 @@ struct G8State {
     double x0[3], v0[3], F0[3];
     double t, hw, hp_new;
     bool active, haveF0;
+    bool row0 = false;          // table row 0 holds the perturbers at t (node 0)
     int status;
 };
 struct G8Count {
@@ -746,8 +747,11 @@ __device__ __forceinline__ void g8_integrate(const Params& p, const NodeRow& R, 
             return;
         }
         const double t_end = landed ? tb : S.t + h;
-        const int n0 = (S.haveF0 && !need_node0) ? 1 : 0;
+        // node 0 is evaluated before the first step; with need_node0 it is
+        // afterwards the previous step's end row, copied when that step is accepted
+        const int n0 = (S.haveF0 && (!need_node0 || S.row0)) ? 1 : 0;
         node_ephemeris8<NB, NGR, DEG1>(coefL, bstride, E, rc, seg_lo, seg_hi, S.t, h, t_end, n0 == 0, lane, e8);
+        S.row0 = true;
         C.chain += (kNodes - n0) * E.n_gr * 3;
         C.vchain += (kNodes - n0) * (nb - E.n_gr) * 3;
         if (!S.haveF0) { accel8<NB, NGR>(e8, E, S.x0, S.v0, S.F0); S.haveF0 = true; }
@@ -783,6 +787,11 @@ __device__ __forceinline__ void g8_integrate(const Params& p, const NodeRow& R, 
             S.status = KETE_ST_NONFINITE; S.active = false;
         }
         accel8_group(e8 + 8 * g8_row(nb), E, S.x0, S.v0, gl, xg, S.F0);
+        if (need_node0) {
+            wave_lds_sync();
+            for (int i = lane; i < g8_row(nb); i += kWave) e8[i] = e8[8 * g8_row(nb) + i];
+            wave_lds_sync();
+        }
         if (landed) {
             S.hw = fmin(S.hw, hn);
         } else {
