@@ -23,9 +23,6 @@
 namespace kete {
 namespace {
 
-constexpr int kStepDoubles = 32;     // t, h, x0[3], v0[3], F0[3], D[7][3]
-constexpr int kJacDoubles = 18;      // Jx (9) + Jv (9) per node
-
 // ---------------------------------------------------------------- duals
 struct D6 {
     double v, d[6];
@@ -385,13 +382,8 @@ __global__ __launch_bounds__(BLOCK, 2) void k_adj_recompute(const AdjParams p, c
             g8_exchange(g8_xch(e8, E.n_body, lane / kGroup), gl, dn, D);
             if (valid) {
                 double* sp = p.steps + (size_t)ns * kStepDoubles * N;
-                if (gl < 6) sp[(2 + gl) * N + gi] = state_component(St.x0, St.v0, gl);
                 if (gl == 6) sp[gi] = ts;
                 if (gl == 7) sp[N + gi] = h;
-                if (gl < 3) sp[(8 + gl) * N + gi] = St.F0[gl];
-                if (gl < 7)
-                    #pragma unroll
-                    for (int i = 0; i < 3; ++i) sp[(11 + 3 * gl + i) * N + gi] = dn[i];
                 // state at this lane's Jacobian node
                 double X[3], V[3];
                 const double hh = h * h;
@@ -691,6 +683,5 @@ hipError_t launch_adjoint(const AdjParams& p, int mode, hipStream_t s) {
     return hipGetLastError();
 }
 
-size_t adjoint_step_doubles() { return kStepDoubles + 8 * kJacDoubles; }
 
 }  // namespace kete

@@ -10,6 +10,9 @@ constexpr int kCkptDoubles = 12;    // x[3], v[3], wave step, failed flag, force
 constexpr int kAdjStateDoubles = 8; // lx[3], lv[3], next observation, overflow flag
 constexpr int kAdjLanes = 8;         // lanes per object in the adjoint kernels (8 objects per wavefront)
 constexpr int kAdjTabDoubles = 8 * (16 + 18);   // constant rows of the reverse sweep
+constexpr int kStepDoubles = 2;      // per stored step and object: start time, step size
+constexpr int kJacDoubles = 18;      // per stored step, node and object: Jx (9), Jv (9)
+constexpr int kStepRecDoubles = kStepDoubles + 8 * kJacDoubles;   // step store per step and object
 
 struct AdjParams {
     EphemArgs eph;
@@ -33,8 +36,8 @@ struct AdjParams {
     int32_t n_ckpt;             // C segments
     double* obs_state;          // [N][K][6] states at the observation times (forward)
     double* obs_grad;           // [N][K][6] dL/d(state) at the observation times (backward)
-    double* steps;              // [s_max][32][N]
-    double* jac;                // [s_max][8][18][N]
+    double* steps;              // [s_max][kStepDoubles][N]
+    double* jac;                // [s_max][8][kJacDoubles][N]
     double* adj_state;          // [N][kAdjStateDoubles] carried between backward segments
     int32_t* seg_ns;            // [ceil(N / 8)] steps stored per wavefront in the current segment
     double* adj_tab;            // [kAdjTabDoubles] constant rows of the reverse sweep
@@ -50,6 +53,5 @@ struct AdjParams {
 
 size_t adjoint_lds_bytes(const AdjParams& p);
 hipError_t launch_adjoint(const AdjParams& p, int mode, hipStream_t s);
-size_t adjoint_step_doubles();
 
 }  // namespace kete

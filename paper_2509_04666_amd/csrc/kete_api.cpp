@@ -720,7 +720,7 @@ size_t kete_adjoint_workspace_size(int64_t n_obj, int32_t k_obs, double t0, doub
     c.take<Window>((size_t)adjoint_max_windows(C));
     c.take<int32_t>((size_t)C + 1);
     c.take<double>((size_t)(C + 1) * n_obj * kCkptDoubles);
-    c.take<double>((size_t)adj_steps(opts) * adjoint_step_doubles() * n_obj);
+    c.take<double>((size_t)adj_steps(opts) * kStepRecDoubles * n_obj);
     c.take<double>((size_t)n_obj * std::max(0, k_obs) * 6);    // observation states
     c.take<double>((size_t)n_obj * std::max(0, k_obs) * 6);    // observation cotangents
     c.take<int32_t>(bucket_scratch_ints(n_obj, nbk));
@@ -766,7 +766,7 @@ int kete_propagate_adjoint(const kete_ephem_t* eph, int32_t mode, const double* 
     Window* dwin = c.take<Window>(max_win);
     int32_t* dseg = c.take<int32_t>((size_t)C + 1);
     double* ckpt = c.take<double>((size_t)(C + 1) * n_obj * kCkptDoubles);
-    double* scratch = c.take<double>((size_t)adj_steps(opts) * adjoint_step_doubles() * n_obj);
+    double* scratch = c.take<double>((size_t)adj_steps(opts) * kStepRecDoubles * n_obj);
     double* obs_state = c.take<double>((size_t)n_obj * k_obs * 6);
     double* obs_grad = c.take<double>((size_t)n_obj * k_obs * 6);
     int32_t* bscratch = c.take<int32_t>(bucket_scratch_ints(n_obj, nbk));
@@ -803,7 +803,7 @@ int kete_propagate_adjoint(const kete_ephem_t* eph, int32_t mode, const double* 
     P.obs_state = obs_state;
     P.obs_grad = obs_grad;
     P.steps = scratch;
-    P.jac = scratch + (size_t)adj_steps(opts) * 32 * n_obj;
+    P.jac = scratch + (size_t)adj_steps(opts) * kStepDoubles * n_obj;
     P.s_max = adj_steps(opts);
     P.adj_state = adj_state;
     P.seg_ns = seg_ns;
