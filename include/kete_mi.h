@@ -282,7 +282,8 @@ size_t kete_adjoint_workspace_size(int64_t n_obj, int32_t k_obs, double t0, doub
  * and RA/Dec (radians) in the equatorial J2000 frame (ecliptic rotated by
  * the obliquity 84381.448").
  *   mode KETE_ADJ_FWD: writes sky_out [N][K][2] and status [N], and stores
- *     checkpoints every ckpt_days in the workspace;
+ *     checkpoints every ckpt_days and each observation's light time in the
+ *     workspace;
  *   mode KETE_ADJ_BWD: given dL_dsky [N][K][2] (device) for the same
  *     inputs and workspace, writes grad_x0 [N][6] = dL/dx0: the discrete
  *     adjoint of the forward computation, recomputing each checkpoint

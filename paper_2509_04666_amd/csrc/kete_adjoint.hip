@@ -130,21 +130,34 @@ __device__ __forceinline__ int hop(const AdjParams& p, const SunGlobal& sun, dou
     double S[3], Sd[3];
     sun.eval(t_obs, S, Sd);
     for (int i = 0; i < 3; ++i) { r0[i] = xs[i] - S[i]; v0[i] = vs[i] - Sd[i]; }
-    const int st = lighttime(sun, p.eph.gm[0], p.smu, p.c_light, p.lt_tol, p.lt_iter, t_obs, r0, v0, t_obs, o, d,
-                             tau, ve);
-    // universal anomaly of the final hop (warm-started solve)
-    double r[3], v[3];
-    chi = __builtin_nan("");
+    return lighttime(sun, p.eph.gm[0], p.smu, p.c_light, p.lt_tol, p.lt_iter, t_obs, r0, v0, t_obs, o, d, tau, ve,
+                     &chi);
+}
+
+// The same hop from the light time and universal anomaly the forward
+// converged to: one warm-started Kepler evaluation, no light-time loop.
+__device__ __forceinline__ void hop_known(const AdjParams& p, const SunGlobal& sun, double t_obs, const double xs[3],
+                                          const double vs[3], const double o[3], double tau, double& chi,
+                                          double d[3], double ve[3], double r0[3], double v0[3]) {
+    double S[3], Sd[3], r[3], v[3], Se[3], Sde[3];
+    sun.eval(t_obs, S, Sd);
+    for (int i = 0; i < 3; ++i) { r0[i] = xs[i] - S[i]; v0[i] = vs[i] - Sd[i]; }
     kepler_uv(p.eph.gm[0], p.smu, r0, v0, -tau, chi, r, v);
-    return st;
+    sun.eval(t_obs - tau, Se, Sde);
+    for (int i = 0; i < 3; ++i) {
+        d[i] = Se[i] + r[i] - o[i];
+        ve[i] = Sde[i] + v[i];
+    }
 }
 
 // dL/d(x, v) at t_obs from dL/d(ra, dec) through the sky projection and
-// the light-time hop (implicit tau: dx_e = P dz - v_e (u . dx_e) / c).
+// the light-time hop (implicit tau: dx_e = P dz - v_e (u . dx_e) / c),
+// given the forward's light time and universal anomaly.
 __device__ void hop_vjp(const AdjParams& p, const SunGlobal& sun, double t_obs, const double xs[3], const double vs[3],
-                        const double o[3], double gra, double gdec, double lx[3], double lv[3]) {
-    double d[3], tau, ve[3], r0[3], v0[3], chi;
-    hop(p, sun, t_obs, xs, vs, o, d, tau, ve, r0, v0, chi);
+                        const double o[3], double tau, double chi, double gra, double gdec, double lx[3],
+                        double lv[3]) {
+    double d[3], ve[3], r0[3], v0[3];
+    hop_known(p, sun, t_obs, xs, vs, o, tau, chi, d, ve, r0, v0);
     double ra, dec, J[6];
     radec(d, p.cos_eps, p.sin_eps, ra, dec, J);
     double gd[3];
@@ -274,6 +287,8 @@ __global__ __launch_bounds__(256) void k_obs_sky(const AdjParams p) {
     radec(d, p.cos_eps, p.sin_eps, ra, dec, J);
     out[0] = ra;
     out[1] = dec;
+    p.obs_hop[2 * i] = tau;
+    p.obs_hop[2 * i + 1] = chi;
 }
 
 // dL/d(state) of every observation (backward), one lane per observation.
@@ -286,7 +301,8 @@ __global__ __launch_bounds__(256) void k_obs_vjp(const AdjParams p) {
     const SunGlobal sun{p.eph};
     const double* st = p.obs_state + 6 * i;
     double lX[3], lV[3];
-    hop_vjp(p, sun, p.t_obs[i], st, st + 3, p.obs_pos + 3 * i, p.dL_dsky[2 * i], p.dL_dsky[2 * i + 1], lX, lV);
+    hop_vjp(p, sun, p.t_obs[i], st, st + 3, p.obs_pos + 3 * i, p.obs_hop[2 * i], p.obs_hop[2 * i + 1],
+            p.dL_dsky[2 * i], p.dL_dsky[2 * i + 1], lX, lV);
     for (int c = 0; c < 3; ++c) { g[c] = lX[c]; g[3 + c] = lV[c]; }
 }
 
@@ -401,8 +417,8 @@ __global__ __launch_bounds__(BLOCK, 2) void k_adj_recompute(const AdjParams p, c
                 double* jp = p.jac + (size_t)ns * 8 * kJacDoubles * N;
                 #pragma unroll
                 for (int q = 0; q < 9; ++q) {
-                    jp[((size_t)jnode * kJacDoubles + q) * N + gi] = Jx[q];
-                    jp[((size_t)jnode * kJacDoubles + 9 + q) * N + gi] = Jv[q];
+                    jp[((size_t)q * N + gi) * 8 + jnode] = Jx[q];
+                    jp[((size_t)(9 + q) * N + gi) * 8 + jnode] = Jv[q];
                 }
             }
             ++ns;
@@ -536,8 +552,8 @@ __global__ __launch_bounds__(64) void k_adj_sweep(const AdjParams p, const int c
         double Jx[9], Jv[9];
         #pragma unroll
         for (int q = 0; q < 9; ++q) {
-            Jx[q] = valid ? jp[((size_t)jnode * kJacDoubles + q) * N + gi] : 0.0;
-            Jv[q] = valid ? jp[((size_t)jnode * kJacDoubles + 9 + q) * N + gi] : 0.0;
+            Jx[q] = valid ? jp[((size_t)q * N + gi) * 8 + jnode] : 0.0;
+            Jv[q] = valid ? jp[((size_t)(9 + q) * N + gi) * 8 + jnode] : 0.0;
         }
         // stage cotangents: mu_m = G_m + sum_n [h^2 A_m(s_n) Jx_n^T mu_n + h B_m(s_n) Jv_n^T mu_n],
         // lane m - 1 holding mu_m; lane 7 accumulates the step-start term m0

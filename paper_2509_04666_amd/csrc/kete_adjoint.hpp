@@ -36,8 +36,9 @@ struct AdjParams {
     int32_t n_ckpt;             // C segments
     double* obs_state;          // [N][K][6] states at the observation times (forward)
     double* obs_grad;           // [N][K][6] dL/d(state) at the observation times (backward)
+    double* obs_hop;            // [N][K][2] light time and final universal anomaly (forward)
     double* steps;              // [s_max][kStepDoubles][N]
-    double* jac;                // [s_max][8][kJacDoubles][N]
+    double* jac;                // [s_max][kJacDoubles][N][8 nodes]: one object's nodes side by side
     double* adj_state;          // [N][kAdjStateDoubles] carried between backward segments
     int32_t* seg_ns;            // [ceil(N / 8)] steps stored per wavefront in the current segment
     double* adj_tab;            // [kAdjTabDoubles] constant rows of the reverse sweep

@@ -723,6 +723,7 @@ size_t kete_adjoint_workspace_size(int64_t n_obj, int32_t k_obs, double t0, doub
     c.take<double>((size_t)adj_steps(opts) * kStepRecDoubles * n_obj);
     c.take<double>((size_t)n_obj * std::max(0, k_obs) * 6);    // observation states
     c.take<double>((size_t)n_obj * std::max(0, k_obs) * 6);    // observation cotangents
+    c.take<double>((size_t)n_obj * std::max(0, k_obs) * 2);    // light times and anomalies
     c.take<int32_t>(bucket_scratch_ints(n_obj, nbk));
     c.take<double>((size_t)n_obj * kAdjStateDoubles);                 // carried backward state
     c.take<int32_t>((size_t)(n_obj + kAdjLanes - 1) / kAdjLanes);           // steps per wavefront
@@ -769,6 +770,7 @@ int kete_propagate_adjoint(const kete_ephem_t* eph, int32_t mode, const double* 
     double* scratch = c.take<double>((size_t)adj_steps(opts) * kStepRecDoubles * n_obj);
     double* obs_state = c.take<double>((size_t)n_obj * k_obs * 6);
     double* obs_grad = c.take<double>((size_t)n_obj * k_obs * 6);
+    double* obs_hop = c.take<double>((size_t)n_obj * k_obs * 2);
     int32_t* bscratch = c.take<int32_t>(bucket_scratch_ints(n_obj, nbk));
     double* adj_state = c.take<double>((size_t)n_obj * kAdjStateDoubles);
     int32_t* seg_ns = c.take<int32_t>((size_t)(n_obj + kAdjLanes - 1) / kAdjLanes);
@@ -802,6 +804,7 @@ int kete_propagate_adjoint(const kete_ephem_t* eph, int32_t mode, const double* 
     P.n_ckpt = (int32_t)C;
     P.obs_state = obs_state;
     P.obs_grad = obs_grad;
+    P.obs_hop = obs_hop;
     P.steps = scratch;
     P.jac = scratch + (size_t)adj_steps(opts) * kStepDoubles * n_obj;
     P.s_max = adj_steps(opts);

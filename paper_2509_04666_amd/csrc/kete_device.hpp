@@ -222,7 +222,8 @@ template <class SunT>
 __device__ __forceinline__ int lighttime(const SunT& sun, double mu, double smu, double c_light,
                                          double lt_tol, int lt_iter, double t_ref,
                                          const double r0[3], const double v0[3], double t_obs,
-                                         const double o[3], double d[3], double& tau, double ve[3]) {
+                                         const double o[3], double d[3], double& tau, double ve[3],
+                                         double* chi_out = nullptr) {
     double Se[3], Sde[3], r[3], v[3];
     double chi = __builtin_nan("");
     // first guess: straight line from the epoch state
@@ -245,6 +246,7 @@ __device__ __forceinline__ int lighttime(const SunT& sun, double mu, double smu,
         d[i] = Se[i] + r[i] - o[i];
         ve[i] = Sde[i] + v[i];
     }
+    if (chi_out) *chi_out = chi;
     return st;
 }
 
