@@ -35,6 +35,9 @@ HBM_PEAK_GBS = 8000.0
 # Algorithmic flop weights (FMA = 2, add/sub/mul = 1, rsqrt/sqrt/div = 1).
 CLENSHAW_CHAIN_FLOPS = lambda deg1: 7 * (deg1 - 1) + 12     # value and derivative
 CLENSHAW_VALUE_FLOPS = lambda deg1: 3 * (deg1 - 1) + 9      # value only
+# Extrapolated corrector start, per body-step: 7 nodes x (sig 2, 7 differences,
+# 7 prefix products, 7 x (weight 4, three FMAs 6) + 7 suffix products), and q.
+PREDICT_FLOPS = 7 * (2 + 7 + 7 + 7 * 10 + 7) + 1
 
 
 def node_flops(n_body: int, n_gr: int) -> int:
@@ -47,12 +50,14 @@ def node_flops(n_body: int, n_gr: int) -> int:
 def integrator_flops(stats, n_body: int, n_gr: int, deg1: int) -> float:
     """Algorithmic FP64 flops from the kernel's own counters:
     stats = [wave steps, wave iterations, rejections, body-steps,
-    body-sweeps, Clenshaw chains with derivative, value-only chains]."""
+    body-sweeps, Clenshaw chains with derivative, value-only chains,
+    body-steps started from an extrapolated corrector]."""
     lane_steps, lane_iter, chains, vchains = float(stats[3]), float(stats[4]), float(stats[5]), float(stats[6])
+    pred = float(stats[7]) if len(stats) > 7 else 0.0
     per_iter = 7 * node_flops(n_body, n_gr) + 3 * 14 + 12
     per_step = 3 * (1 + 28 + 4 + 2) + (18 * n_body + 27 * n_gr) + 10
     return (lane_iter * per_iter + lane_steps * per_step + chains * CLENSHAW_CHAIN_FLOPS(deg1)
-            + vchains * CLENSHAW_VALUE_FLOPS(deg1))
+            + vchains * CLENSHAW_VALUE_FLOPS(deg1) + pred * PREDICT_FLOPS)
 
 
 def measured_traffic(path=os.path.join(ROOT, "profiles", "traffic_k_nbody_g8_survey.md")):
@@ -381,7 +386,7 @@ def main():
             "fov_tests_per_s_bruteforce_equiv": N * F * S / (fov_ms_step / 1e3) if fov_ms_step > 0 else None,
             "pairs": n_pairs, "fov_candidates": int(fst[0]), "fov_exact_tests": int(fst[1]),
             "fov_bruteforce_objects": int(fst[2]), "failed_objects": n_fail,
-            "integrator_counters": st[:7].tolist(),
+            "integrator_counters": st[:8].tolist(),
         },
     }
     if not args.no_adjoint:

@@ -100,7 +100,9 @@ typedef struct {
     int32_t adj_seg_steps;   /* adjoint: steps stored per checkpoint segment (32) */
     int32_t persist_waves;   /* batched runs: resident waves per compute unit (8) */
     int32_t lanes_per_body;  /* integrator lanes per object: 1, 7 (9 per wavefront) or 8 (7) */
-    int32_t reserved;
+    int32_t zero_start;      /* 1: every corrector starts from zero increments, as in App. A.6;
+                                0: grouped integrators start from the previous step's
+                                collocation polynomial extrapolated (0) */
 } kete_opts_t;
 
 /* Frames (Sect. 3.1): an instantaneous observation at time t from the
@@ -201,7 +203,8 @@ size_t kete_propagate_workspace_size(int64_t n_obj, int64_t n_out, const kete_op
  *   status  device [n_obj]  (KETE_ST_*)
  *   stats   device [8] int64 or NULL: accumulated counters
  *           {wave steps, wave iterations, rejections, lane-steps,
- *            lane-iterations, ephemeris chains, 0, 0}
+ *            lane-iterations, Chebyshev chains with derivative, value-only
+ *            chains, lane-steps started from an extrapolated corrector}
  * Errors: KETE_EINVAL, KETE_ERANGE (t0 or an epoch outside the ephemeris),
  * KETE_EWORKSPACE, KETE_EDEVICE. */
 int kete_propagate_nbody(const kete_ephem_t *eph, const double *x0, double t0, int64_t n_obj,

@@ -169,6 +169,12 @@ RadauConst build_radau() {
         }
     }
     for (int m = 1; m < 8; ++m) {
+        ld den = 1;
+        for (int k = 0; k < 8; ++k) if (k != m) den *= S[m] - S[k];
+        rc.Lden[m - 1] = (double)(1 / den);
+        rc.L1[m - 1] = (double)ell(m, 1);
+    }
+    for (int m = 1; m < 8; ++m) {
         ld p = 1;
         for (int k = 0; k < 8; ++k) if (k != m) p *= (S[m] - S[k]);
         rc.E6[m - 1] = (double)(1.0L / p);
@@ -455,6 +461,7 @@ int kete_propagate_nbody(const kete_ephem_t* eph, const double* x0, double t0, i
     P.n_obj = (int32_t)n_obj;
     P.max_iter = opts->max_iter;
     P.max_steps = opts->max_steps;
+    P.zero_start = opts->zero_start != 0;
     P.max_win_segs = wsegs + 1;
     P.eps = opts->eps;
     P.h_min = opts->h_min;
@@ -1083,6 +1090,7 @@ int kete_batch_run(const kete_ephem_t* eph, const kete_batch_t* batch, int64_t p
     B.max_win_segs = std::max(1, opts->window_segs) + 1;
     B.max_iter = opts->max_iter;
     B.max_steps = opts->max_steps;
+    B.zero_start = opts->zero_start != 0;
     B.eps = opts->eps;
     B.h_min = opts->h_min;
     B.h_max = opts->h_max;

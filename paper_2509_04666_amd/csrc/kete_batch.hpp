@@ -29,6 +29,8 @@ struct BatchParams {
     int32_t max_win_segs;
     int32_t max_iter;
     int32_t max_steps;
+    int32_t zero_start;         // corrector starts from zero increments (no extrapolation)
+    int32_t pad_;
     double eps, h_min, h_max, h_init, safety;
 };
 

@@ -27,6 +27,10 @@ struct RadauConst {
     //   A_m(sig) = sum_k Ap[m][k] sig^(k+2),  B_m(sig) = sum_k Bp[m][k] sig^(k+1)
     double Ap[7][8];
     double Bp[7][8];
+    // Lagrange basis l_m on the nodes 0, s_1..s_7 (m = 1..7): 1 / prod_{k != m} (s_m - s_k)
+    // and l_m(1), to extrapolate a step's increments into the next step
+    double Lden[7];
+    double L1[7];
 };
 
 // One staged ephemeris window of the integration: [t_a, t_b] lies within
@@ -97,6 +101,8 @@ struct NbodyParams {
     int32_t max_steps;
     int32_t max_win_segs;   // LDS capacity in segments
     int32_t first_launch;
+    int32_t zero_start;     // corrector starts from zero increments (no extrapolation)
+    int32_t pad_;
     double eps, h_min, h_max, h_init, safety;
 };
 

@@ -214,7 +214,7 @@ __global__ __launch_bounds__(BLOCK, 3) void k_nbody_g8(const NbodyParams p) {
         __syncthreads();
         stage_window(E, W.seg_lo, W.seg_hi, bstride, tid, BLOCK, coefL);
         __syncthreads();
-        g8_integrate<NB, NGR, DEG1, G>(p, R, node, gl, M.grp, lane, coefL, bstride, e8, W.seg_lo, W.seg_hi, W.t_b,
+        g8_integrate<NB, NGR, DEG1, G, true>(p, R, node, gl, M.grp, lane, coefL, bstride, e8, W.seg_lo, W.seg_hi, W.t_b,
                                        S, C);
         if (W.out >= 0 && valid && gl < 6) {
             // lane gl of the group writes component gl of the state
@@ -229,7 +229,7 @@ __global__ __launch_bounds__(BLOCK, 3) void k_nbody_g8(const NbodyParams p) {
         p.status[j] = S.status;
     }
     const unsigned long long c_steps = C.steps, c_iter = C.iter, c_rej = C.rej, c_lsteps = C.lsteps,
-                             c_liter = C.liter, c_chain = C.chain, c_vchain = C.vchain;
+                             c_liter = C.liter, c_chain = C.chain, c_vchain = C.vchain, c_lpred = C.lpred;
     if (p.stats && lane == 0 && __ballot(valid) != 0ull) {
         atomicAdd(p.stats + 0, c_steps);
         atomicAdd(p.stats + 1, c_iter);
@@ -238,6 +238,7 @@ __global__ __launch_bounds__(BLOCK, 3) void k_nbody_g8(const NbodyParams p) {
         atomicAdd(p.stats + 4, c_liter);
         atomicAdd(p.stats + 5, c_chain);
         atomicAdd(p.stats + 6, c_vchain);
+        atomicAdd(p.stats + 7, c_lpred);
     }
 }
 

@@ -603,21 +603,59 @@ __device__ __forceinline__ double step_factor(double q) {
     return (double)exp2f(log2f(qf) * (1.0f / 7.0f));
 }
 
+// Starting increment of this lane's node for a step q times the previous
+// accepted one: that step's collocation polynomial of the force
+// increments (values Dp at its nodes, 0 at its start) evaluated at the new
+// node's time sig = 1 + q s_n of the old step, less its value at sig = 1.
+// The Lagrange basis of the 8 nodes is formed from prefix and suffix
+// products of (sig - s_k).
+__device__ __forceinline__ void extrapolate_increment(const RadauConst& rc, double* __restrict__ xg, int gl,
+                                                      const NodeRow& R, const double Dp[3], double q, double dn[3]) {
+    // opaque zero offset: the constants are loaded here, not kept in
+    // scalar registers across the step loop
+    int z;
+    asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+    double D[7][3];
+    g8_exchange(xg, gl, Dp, D);
+    const double sig = fma(q, R.s, 1.0);
+    double dk[8], pre[8];
+    dk[0] = sig;
+#pragma unroll
+    for (int k = 1; k < 8; ++k) dk[k] = sig - rc.s[k + z];
+    pre[0] = 1.0;
+#pragma unroll
+    for (int k = 1; k < 8; ++k) pre[k] = pre[k - 1] * dk[k - 1];
+    double suf = 1.0;
+    dn[0] = dn[1] = dn[2] = 0.0;
+#pragma unroll
+    for (int m = 7; m >= 1; --m) {
+        const double w = fma(pre[m] * suf, rc.Lden[m - 1 + z], -rc.L1[m - 1 + z]);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) dn[c] = fma(w, D[m - 1][c], dn[c]);
+        suf *= dk[m];
+    }
+}
+
 // Corrector for a body spread over an 8-lane group (see above), with the
 // same stopping rule as corrector().  Each lane keeps only its own node's
 // increment dn; the other nodes' increments are read from the group's
-// lanes when the predictor sums and b6 are formed.  On return dn holds
-// the converged increment of this lane's node, b6 the highest
-// coefficient and d6 the increment of node 7 (all lanes).
+// lanes when the predictor sums and b6 are formed.  With q > 0 the
+// iteration starts from the previous step's increments Dp extrapolated
+// (extrapolate_increment), otherwise from zero.  On return dn holds the
+// converged increment of this lane's node, b6 the highest coefficient and
+// d6 the increment of node 7 (all lanes).
 template <int NB, int NGR, int G>
 __device__ __forceinline__ int corrector_g8(const RadauConst& rc, const EphemArgs& E, const double* __restrict__ e8,
                                             double* __restrict__ xg, int gl, const NodeRow& R, int node,
                                             const double x0[3], const double v0[3],
                                             const double F0[3], double h, bool active, int max_iter, double dn[3],
-                                            double b6[3], double d6[3]) {
+                                            double b6[3], double d6[3], const double* Dp = nullptr,
+                                            double q = 0.0) {
     const double hh = h * h, sh = R.s * h;
     const double* en = e8 + node * g8_row(E.n_body);
-    dn[0] = dn[1] = dn[2] = 0.0;
+    const bool started = q > 0.0;           // wave-uniform
+    if (started) extrapolate_increment(rc, xg, gl, R, Dp, q, dn);
+    else dn[0] = dn[1] = dn[2] = 0.0;
     b6[0] = b6[1] = b6[2] = 0.0;
     d6[0] = d6[1] = d6[2] = 0.0;
     double pc = 1e300;
@@ -626,7 +664,7 @@ __device__ __forceinline__ int corrector_g8(const RadauConst& rc, const EphemArg
         double ax[3], av[3], bb[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) { ax[c] = R.hs2 * F0[c]; av[c] = R.s * F0[c]; bb[c] = 0.0; }
-        if (it > 0) {
+        if (it > 0 || started) {
             double D[7][3];
             g8_exchange(xg, gl, dn, D);
 #pragma unroll
@@ -651,7 +689,7 @@ __device__ __forceinline__ int corrector_g8(const RadauConst& rc, const EphemArg
             // the ratio only steers the stopping rule: the reciprocal estimate suffices
             const double lpc = (active && fm > 0.0) ? db * __builtin_amdgcn_rcp(fm) : 0.0;
             pc = groups_max<G>(lpc);
-            if (pc < 1e-16 || (it > 2 && pcl <= pc) || it >= max_iter) break;
+            if (it > 0 && (pc < 1e-16 || (it > 2 && pcl <= pc) || it >= max_iter)) break;
         }
         ++it;
         double X[3], V[3];
@@ -703,14 +741,20 @@ __device__ __forceinline__ void step_end_g8(const RadauConst& rc, double* __rest
 // Stepping state of a group-integrated body (replicated in its 8 lanes).
 struct G8State {
     double x0[3], v0[3], F0[3];
+    double Dp[3] = {0.0, 0.0, 0.0};   // this lane's increment in the last accepted step
+    double hprev = 0.0;               // that step (0: none yet)
     double t, hw, hp_new;
     bool active, haveF0;
     bool row0 = false;          // table row 0 holds the perturbers at t (node 0)
     int status;
 };
 struct G8Count {
-    unsigned long long steps = 0, iter = 0, rej = 0, lsteps = 0, liter = 0, chain = 0, vchain = 0;
+    unsigned long long steps = 0, iter = 0, rej = 0, lsteps = 0, liter = 0, chain = 0, vchain = 0, lpred = 0;
 };
+
+// Largest ratio of a step to the previous accepted one for which the
+// corrector starts from the extrapolated increments.
+constexpr double kPredMaxRatio = 3.0;
 
 // Integrate one window [S.t, tb] whose Chebyshev segments seg_lo..seg_hi
 // are staged at coefL, with wave-shared adaptive steps (the 8 bodies of
@@ -724,7 +768,7 @@ struct G8NoVisit {
 // before S moves to the step end (dn: this lane's converged increment,
 // e8: the step's perturber table).  With need_node0 the table also holds
 // node 0 (the step start) on every step.
-template <int NB, int NGR, int DEG1, int G, class Params, class Visit = G8NoVisit>
+template <int NB, int NGR, int DEG1, int G, bool PRED = false, class Params, class Visit = G8NoVisit>
 __device__ __forceinline__ void g8_integrate(const Params& p, const NodeRow& R, int node, int gl, int grp, int lane,
                                              const double* __restrict__ coefL, int bstride, double* __restrict__ e8,
                                              int seg_lo, int seg_hi, double tb, G8State& S, G8Count& C,
@@ -756,12 +800,18 @@ __device__ __forceinline__ void g8_integrate(const Params& p, const NodeRow& R, 
         C.vchain += (kNodes - n0) * (nb - E.n_gr) * 3;
         if (!S.haveF0) { accel8<NB, NGR>(e8, E, S.x0, S.v0, S.F0); S.haveF0 = true; }
 
+        double q = 0.0;                       // wave-uniform, like h and S.hprev
+        if constexpr (PRED) {
+            if (!p.zero_start && S.hprev != 0.0) q = h / S.hprev;
+            if (!(q <= kPredMaxRatio)) q = 0.0;
+        }
         double dn[3], b6p[3], d6[3];
         const int it = corrector_g8<NB, NGR, G>(rc, E, e8, xg, gl, R, node, S.x0, S.v0, S.F0, h, S.active, p.max_iter,
-                                             dn, b6p, d6);
+                                             dn, b6p, d6, S.Dp, q);
         C.iter += it;
         const unsigned long long n_act = __popcll(__ballot(S.active && gl == 0));
         C.liter += (unsigned long long)it * n_act;
+        if (q > 0.0) C.lpred += n_act;
 
         double fm = 0.0, bm = 0.0;
 #pragma unroll
@@ -778,6 +828,11 @@ __device__ __forceinline__ void g8_integrate(const Params& p, const NodeRow& R, 
             continue;
         }
         visit(S.t, h, dn, S);
+        if constexpr (PRED) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) S.Dp[c] = dn[c];
+            S.hprev = h;
+        }
         step_end_g8(rc, xg, gl, dn, h, S.x0, S.v0, S.F0);
         S.t = t_end;
         ++C.steps;

@@ -152,12 +152,40 @@ def test_propagate_configuration_invariance(torch_cuda):
     assert torch.equal(ref, ref2), "propagation is not deterministic"
     for kw in (dict(n_buckets=1), dict(block=64), dict(block=128, n_buckets=4), dict(rebucket_epochs=1),
                dict(window_segs=1), dict(rebucket_epochs=0), dict(rebucket_epochs=16), dict(lanes_per_body=7),
-               dict(lanes_per_body=8), dict(lanes_per_body=7, block=256), dict(lanes_per_body=1)):
+               dict(lanes_per_body=8), dict(lanes_per_body=7, block=256), dict(lanes_per_body=1),
+               dict(zero_start=1), dict(zero_start=1, lanes_per_body=8)):
         x, s = api.propagate(eph, x0, 0.0, t_out, api.default_opts(**kw))
         d = (x - ref).abs().max().item()
         _say(f"config {kw}: max |dx| vs default {d:.3e}")
         assert d < 1e-11
         assert torch.equal(s, st)
+
+
+def test_extrapolated_corrector_start(torch_cuda, orc):
+    """The grouped integrators start each corrector from the previous
+    step's increments extrapolated: nearly every step after the first is
+    counted as predicted, the corrector needs fewer sweeps than from zero,
+    and both starts agree with the oracle (which starts from zero)."""
+    torch, api = torch_cuda
+    case = synth.survey_case(n_obj=600, n_frames=0, neo_frac=0.2)
+    eph = api.DeviceEphemeris.from_synth(case.ephem)
+    x0 = _dev_x(torch, case.x0)
+    t_out = np.arange(3.0, 121.0, 3.0)
+    xp, sp, stp = api.propagate(eph, x0, 0.0, t_out, api.default_opts(), stats=True)
+    xz, sz, stz = api.propagate(eph, x0, 0.0, t_out, api.default_opts(zero_start=1), stats=True)
+    stp, stz = stp.cpu().numpy(), stz.cpu().numpy()
+    sweeps_p, sweeps_z = stp[4] / stp[3], stz[4] / stz[3]
+    _say(f"sweeps per body-step: extrapolated start {sweeps_p:.2f}, zero start {sweeps_z:.2f}; "
+         f"predicted steps {stp[7] / stp[3]:.3f}")
+    assert stz[7] == 0
+    assert stp[7] > 0.9 * stp[3]
+    assert sweeps_p < 0.8 * sweeps_z
+    assert torch.equal(sp, sz)
+    sel = np.arange(0, 600, 25)
+    xo, so, _ = orc.propagate(case.ephem, case.x0[sel], 0.0, t_out)
+    for x in (xp, xz):
+        xs = x[:, torch.as_tensor(sel, device="cuda")].cpu().numpy()
+        assert np.max(np.abs(xs[..., :3] - xo[..., :3])) < 1e-10
 
 
 def test_propagate_ragged_sizes(torch_cuda, orc):
