@@ -740,25 +740,49 @@ __global__ __launch_bounds__(256) void k_fov_wide(const FovParams p) {
 
 // Sky cell of every (object, batch): direction from the batch's mean
 // observer, on the frame grid; wide and failed objects sort after the
-// narrow ones of their batch.
-__global__ void k_obj_keys(const FovParams p, int32_t* __restrict__ okey, int32_t* __restrict__ orank,
-                           int32_t* __restrict__ cnt) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= p.n_pairs_total) return;
-    const int b = batch_of(p.b_poff, p.n_batch, i);
-    const int64_t j = i - p.b_poff[b];
-    ObjBounds o;
-    const int G = p.b_G[b], G3 = G * G * G;
-    int key;
-    const bool live = object_bounds(p, b, j, o);
-    if (live && is_narrow(o, G)) {
-        key = (int)(p.b_koff[b] + cell_of(o.dh, G));
-    } else {
-        key = (int)(p.b_koff[b] + G3);
-        if (live) wave_append(p.wide, p.n_wide, p.n_pairs_total, ((unsigned long long)b << 32) | (unsigned long long)j);
+// narrow ones of their batch.  The rank inside the cell comes from a
+// block-local count (an LDS hash table of the block's keys) plus one
+// global atomic per distinct key of the block, so objects sharing a cell
+// do not queue on its global counter one by one.
+constexpr int kKeyBlock = 256;
+constexpr int kKeySlots = 2 * kKeyBlock;     // at most half full: probing always ends
+__global__ __launch_bounds__(kKeyBlock) void k_obj_keys(const FovParams p, int32_t* __restrict__ okey,
+                                                        int32_t* __restrict__ orank, int32_t* __restrict__ cnt) {
+    __shared__ int32_t hkey[kKeySlots], hcnt[kKeySlots], hbase[kKeySlots];
+    const int tid = threadIdx.x;
+    for (int k = tid; k < kKeySlots; k += kKeyBlock) { hkey[k] = -1; hcnt[k] = 0; }
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * kKeyBlock + tid;
+    const bool valid = i < p.n_pairs_total;
+    int slot = 0, lrank = 0;
+    if (valid) {
+        const int b = batch_of(p.b_poff, p.n_batch, i);
+        const int64_t j = i - p.b_poff[b];
+        ObjBounds o;
+        const int G = p.b_G[b], G3 = G * G * G;
+        int key;
+        const bool live = object_bounds(p, b, j, o);
+        if (live && is_narrow(o, G)) {
+            key = (int)(p.b_koff[b] + cell_of(o.dh, G));
+        } else {
+            key = (int)(p.b_koff[b] + G3);
+            if (live)
+                wave_append(p.wide, p.n_wide, p.n_pairs_total, ((unsigned long long)b << 32) | (unsigned long long)j);
+        }
+        okey[i] = key;
+        slot = (int)(((unsigned)key * 2654435761u) >> 23) & (kKeySlots - 1);
+        for (;;) {
+            const int prev = atomicCAS(&hkey[slot], -1, key);
+            if (prev == -1 || prev == key) break;
+            slot = (slot + 1) & (kKeySlots - 1);
+        }
+        lrank = atomicAdd(&hcnt[slot], 1);
     }
-    okey[i] = key;
-    orank[i] = atomicAdd(cnt + key, 1);
+    __syncthreads();
+    for (int k = tid; k < kKeySlots; k += kKeyBlock)
+        if (hkey[k] >= 0) hbase[k] = atomicAdd(cnt + hkey[k], hcnt[k]);
+    __syncthreads();
+    if (valid) orank[i] = hbase[slot] + lrank;
 }
 
 // Objects into their cell's slots, at the rank the key pass drew (the order
@@ -983,7 +1007,8 @@ hipError_t fov_sort_objects(const FovParams& p, int32_t* okey, int32_t* orank, i
     hipError_t e;
     if ((e = fill_zero(cnt, (size_t)(nkeys + 1) * sizeof(int32_t), s)) != hipSuccess) return e;
     const unsigned g = (unsigned)((n + 255) / 256);
-    hipLaunchKernelGGL(k_obj_keys, dim3(g), dim3(256), 0, s, p, okey, orank, cnt);
+    hipLaunchKernelGGL(k_obj_keys, dim3((unsigned)((n + kKeyBlock - 1) / kKeyBlock)), dim3(kKeyBlock), 0, s, p, okey,
+                       orank, cnt);
     if ((e = exclusive_scan_i32(cnt, start, nkeys, scan_scratch, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_obj_scatter, dim3(g), dim3(256), 0, s, p, (const int32_t*)okey, (const int32_t*)orank,
                        (const int32_t*)start, sorted);
