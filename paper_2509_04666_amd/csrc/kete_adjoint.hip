@@ -182,9 +182,12 @@ __device__ void hop_vjp(const AdjParams& p, const SunGlobal& sun, double t_obs, 
 // step loop of the propagation kernels.
 
 // Checkpoint c of object j: state, the step size to resume with, a
-// failure flag and the force at the state (with whether it was evaluated
-// yet), so that a recompute repeats the forward's steps exactly; lanes
-// 0..7 of the group write the first eight values, lanes 0..3 the rest.
+// failure flag, the force at the state (with whether it was evaluated
+// yet), and the last accepted step with its node increments, so that a
+// recompute repeats the forward's steps exactly (extrapolated corrector
+// starts included).  Lanes 0..7 of the group write the first eight
+// values, lanes 0..3 the force, lanes 0..6 their node's increment and
+// lane 7 the step.
 __device__ __forceinline__ void save_ckpt_g8(const AdjParams& p, int c, int j, int gl, const G8State& S) {
     double* ck = p.ckpt + ((size_t)c * p.n_obj + j) * kCkptDoubles;
     const double v = gl < 6 ? state_component(S.x0, S.v0, gl)
@@ -192,6 +195,12 @@ __device__ __forceinline__ void save_ckpt_g8(const AdjParams& p, int c, int j, i
     ck[gl] = v;
     const double f = gl == 0 ? S.F0[0] : gl == 1 ? S.F0[1] : gl == 2 ? S.F0[2] : (S.haveF0 ? 1.0 : 0.0);
     if (gl < 4) ck[8 + gl] = f;
+    if (gl < 7) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) ck[12 + 3 * gl + i] = S.Dp[i];
+    } else {
+        ck[33] = S.hprev;
+    }
 }
 
 
@@ -263,8 +272,8 @@ __global__ __launch_bounds__(64, 3) void k_adjoint_fwd(const AdjParams p) {
             __syncthreads();
             stage_window(E, W.seg_lo, W.seg_hi, bstride, lane, 64, coefL);
             __syncthreads();
-            g8_integrate<NB, NGR, DEG1, kGroup>(p, R, node, gl, lane / kGroup, lane, coefL, bstride, e8, W.seg_lo,
-                                                W.seg_hi, W.t_b, S, C, visit);
+            g8_integrate<NB, NGR, DEG1, kGroup, kStartExtrapolateHeld>(p, R, node, gl, lane / kGroup, lane, coefL, bstride, e8,
+                                                      W.seg_lo, W.seg_hi, W.t_b, S, C, visit);
         }
         if (valid) save_ckpt_g8(p, c + 1, j, gl, S);
     }
@@ -377,17 +386,22 @@ __global__ __launch_bounds__(BLOCK, 2) void k_adj_recompute(const AdjParams p, c
     bool overflow_steps = false;
     G8State S;
     init_lane_state(p, false, j, S);
-    double hw = 0.0;
+    double hw = 0.0, hprev = -kInf;
     bool have_f0 = false;
     if (valid) {
         const double* ck = p.ckpt + ((size_t)c * N + j) * kCkptDoubles;
 #pragma unroll
-        for (int i = 0; i < 3; ++i) { S.x0[i] = ck[i]; S.v0[i] = ck[3 + i]; S.F0[i] = ck[8 + i]; }
+        for (int i = 0; i < 3; ++i) {
+            S.x0[i] = ck[i]; S.v0[i] = ck[3 + i]; S.F0[i] = ck[8 + i];
+            S.Dp[i] = gl < 7 ? ck[12 + 3 * gl + i] : 0.0;
+        }
         hw = ck[6];
         S.active = ck[7] == 0.0;
         have_f0 = ck[11] != 0.0;
+        hprev = ck[33];
     }
     S.hw = groups_max(valid ? hw : 0.0);        // the same value in every valid group
+    S.hprev = groups_max(hprev);                // likewise (invalid groups give -inf)
     S.haveF0 = __ballot(have_f0) != 0ull;       // as in the forward at this checkpoint
     S.t = p.win[p.seg_win[c]].t_a;
     G8Count Cn;
@@ -428,8 +442,8 @@ __global__ __launch_bounds__(BLOCK, 2) void k_adj_recompute(const AdjParams p, c
         __syncthreads();
         stage_window(E, W.seg_lo, W.seg_hi, bstride, tid, BLOCK, coefL);
         __syncthreads();
-        g8_integrate<NB, NGR, DEG1, kGroup>(p, R, node, gl, lane / kGroup, lane, coefL, bstride, e8, W.seg_lo,
-                                            W.seg_hi, W.t_b, S, Cn, store, true);
+        g8_integrate<NB, NGR, DEG1, kGroup, kStartExtrapolateHeld>(p, R, node, gl, lane / kGroup, lane, coefL, bstride, e8, W.seg_lo,
+                                                  W.seg_hi, W.t_b, S, Cn, store, true);
     }
     if (lane == 0 && wave * kGroup < p.n_obj) p.seg_ns[wave] = min(ns, p.s_max) | (overflow_steps ? kSegOverflow : 0);
 }

@@ -6,7 +6,9 @@
 
 namespace kete {
 
-constexpr int kCkptDoubles = 12;    // x[3], v[3], wave step, failed flag, force F0[3], F0 valid
+// x[3], v[3], wave step, failed flag, force F0[3], F0 valid, the last accepted step's increments
+// at nodes 1..7 [7][3] and that step (0: none), 2 spare
+constexpr int kCkptDoubles = 36;
 constexpr int kAdjStateDoubles = 8; // lx[3], lv[3], next observation, overflow flag
 constexpr int kAdjLanes = 8;         // lanes per object in the adjoint kernels (8 objects per wavefront)
 constexpr int kAdjTabDoubles = 8 * (16 + 18);   // constant rows of the reverse sweep
@@ -49,7 +51,7 @@ struct AdjParams {
     double eps, h_min, h_max, h_init, safety;
     double smu, c_light, lt_tol, cos_eps, sin_eps;
     int32_t lt_iter;
-    int32_t pad;
+    int32_t zero_start;         // correctors start from zero increments (no extrapolation)
 };
 
 size_t adjoint_lds_bytes(const AdjParams& p);

@@ -821,6 +821,7 @@ int kete_propagate_adjoint(const kete_ephem_t* eph, int32_t mode, const double* 
     P.max_win_segs = std::max(1, opts->window_segs) + 1;
     P.max_iter = opts->max_iter;
     P.max_steps = opts->max_steps;
+    P.zero_start = opts->zero_start != 0;
     P.eps = opts->eps;
     P.h_min = opts->h_min;
     P.h_max = opts->h_max;

@@ -126,7 +126,7 @@ __global__ __launch_bounds__(64, 3) void k_batch_g8(const BatchParams p) {
             while (S.t != target) {
                 const Window Wn = next_window(S.t, target, E.t_start, E.seg_days, E.inv_seg, E.n_seg, W);
                 ensure_window(E, Wn.seg_lo, Wn.seg_hi, lo, hi, coefL, bstride);
-                g8_integrate<NB, NGR, DEG1, G, true>(p, R, node, gl, M.grp, lane, coefL, bstride, e8, lo, hi, Wn.t_b, S,
+                g8_integrate<NB, NGR, DEG1, G, kStartExtrapolate>(p, R, node, gl, M.grp, lane, coefL, bstride, e8, lo, hi, Wn.t_b, S,
                                                C);
                 S.t = Wn.t_b;
             }

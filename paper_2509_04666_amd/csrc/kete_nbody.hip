@@ -214,7 +214,7 @@ __global__ __launch_bounds__(BLOCK, 3) void k_nbody_g8(const NbodyParams p) {
         __syncthreads();
         stage_window(E, W.seg_lo, W.seg_hi, bstride, tid, BLOCK, coefL);
         __syncthreads();
-        g8_integrate<NB, NGR, DEG1, G, true>(p, R, node, gl, M.grp, lane, coefL, bstride, e8, W.seg_lo, W.seg_hi, W.t_b,
+        g8_integrate<NB, NGR, DEG1, G, kStartExtrapolate>(p, R, node, gl, M.grp, lane, coefL, bstride, e8, W.seg_lo, W.seg_hi, W.t_b,
                                        S, C);
         if (W.out >= 0 && valid && gl < 6) {
             // lane gl of the group writes component gl of the state

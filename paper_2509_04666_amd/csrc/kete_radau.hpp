@@ -608,13 +608,14 @@ __device__ __forceinline__ double step_factor(double q) {
 // increments (values Dp at its nodes, 0 at its start) evaluated at the new
 // node's time sig = 1 + q s_n of the old step, less its value at sig = 1.
 // The Lagrange basis of the 8 nodes is formed from prefix and suffix
-// products of (sig - s_k).
+// products of (sig - s_k).  With RELOAD the constants are read through an
+// opaque zero offset, so they are loaded here rather than kept in scalar
+// registers across the step loop.
+template <bool RELOAD>
 __device__ __forceinline__ void extrapolate_increment(const RadauConst& rc, double* __restrict__ xg, int gl,
                                                       const NodeRow& R, const double Dp[3], double q, double dn[3]) {
-    // opaque zero offset: the constants are loaded here, not kept in
-    // scalar registers across the step loop
-    int z;
-    asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+    int z = 0;
+    if constexpr (RELOAD) asm volatile("s_mov_b32 %0, 0" : "=s"(z));
     double D[7][3];
     g8_exchange(xg, gl, Dp, D);
     const double sig = fma(q, R.s, 1.0);
@@ -644,7 +645,7 @@ __device__ __forceinline__ void extrapolate_increment(const RadauConst& rc, doub
 // (extrapolate_increment), otherwise from zero.  On return dn holds the
 // converged increment of this lane's node, b6 the highest coefficient and
 // d6 the increment of node 7 (all lanes).
-template <int NB, int NGR, int G>
+template <int NB, int NGR, int G, bool RELOAD = true>
 __device__ __forceinline__ int corrector_g8(const RadauConst& rc, const EphemArgs& E, const double* __restrict__ e8,
                                             double* __restrict__ xg, int gl, const NodeRow& R, int node,
                                             const double x0[3], const double v0[3],
@@ -654,7 +655,7 @@ __device__ __forceinline__ int corrector_g8(const RadauConst& rc, const EphemArg
     const double hh = h * h, sh = R.s * h;
     const double* en = e8 + node * g8_row(E.n_body);
     const bool started = q > 0.0;           // wave-uniform
-    if (started) extrapolate_increment(rc, xg, gl, R, Dp, q, dn);
+    if (started) extrapolate_increment<RELOAD>(rc, xg, gl, R, Dp, q, dn);
     else dn[0] = dn[1] = dn[2] = 0.0;
     b6[0] = b6[1] = b6[2] = 0.0;
     d6[0] = d6[1] = d6[2] = 0.0;
@@ -756,6 +757,11 @@ struct G8Count {
 // corrector starts from the extrapolated increments.
 constexpr double kPredMaxRatio = 3.0;
 
+// Corrector start of g8_integrate: always from zero, or extrapolated from
+// the previous step (constants reloaded at each use, or held in registers
+// where the kernel has room).
+enum G8Start { kStartZero = 0, kStartExtrapolate = 1, kStartExtrapolateHeld = 2 };
+
 // Integrate one window [S.t, tb] whose Chebyshev segments seg_lo..seg_hi
 // are staged at coefL, with wave-shared adaptive steps (the 8 bodies of
 // the wavefront take the smallest step any of them asks for).
@@ -768,7 +774,7 @@ struct G8NoVisit {
 // before S moves to the step end (dn: this lane's converged increment,
 // e8: the step's perturber table).  With need_node0 the table also holds
 // node 0 (the step start) on every step.
-template <int NB, int NGR, int DEG1, int G, bool PRED = false, class Params, class Visit = G8NoVisit>
+template <int NB, int NGR, int DEG1, int G, int START = kStartZero, class Params, class Visit = G8NoVisit>
 __device__ __forceinline__ void g8_integrate(const Params& p, const NodeRow& R, int node, int gl, int grp, int lane,
                                              const double* __restrict__ coefL, int bstride, double* __restrict__ e8,
                                              int seg_lo, int seg_hi, double tb, G8State& S, G8Count& C,
@@ -801,13 +807,14 @@ __device__ __forceinline__ void g8_integrate(const Params& p, const NodeRow& R, 
         if (!S.haveF0) { accel8<NB, NGR>(e8, E, S.x0, S.v0, S.F0); S.haveF0 = true; }
 
         double q = 0.0;                       // wave-uniform, like h and S.hprev
-        if constexpr (PRED) {
+        if constexpr (START != kStartZero) {
             if (!p.zero_start && S.hprev != 0.0) q = h / S.hprev;
             if (!(q <= kPredMaxRatio)) q = 0.0;
         }
         double dn[3], b6p[3], d6[3];
-        const int it = corrector_g8<NB, NGR, G>(rc, E, e8, xg, gl, R, node, S.x0, S.v0, S.F0, h, S.active, p.max_iter,
-                                             dn, b6p, d6, S.Dp, q);
+        const int it = corrector_g8<NB, NGR, G, START != kStartExtrapolateHeld>(rc, E, e8, xg, gl, R, node, S.x0, S.v0,
+                                                                                S.F0, h, S.active, p.max_iter, dn, b6p,
+                                                                                d6, S.Dp, q);
         C.iter += it;
         const unsigned long long n_act = __popcll(__ballot(S.active && gl == 0));
         C.liter += (unsigned long long)it * n_act;
@@ -828,7 +835,7 @@ __device__ __forceinline__ void g8_integrate(const Params& p, const NodeRow& R, 
             continue;
         }
         visit(S.t, h, dn, S);
-        if constexpr (PRED) {
+        if constexpr (START != kStartZero) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) S.Dp[c] = dn[c];
             S.hprev = h;
