@@ -38,6 +38,10 @@ CLENSHAW_VALUE_FLOPS = lambda deg1: 3 * (deg1 - 1) + 9      # value only
 # Extrapolated corrector start, per body-step: 7 nodes x (sig 2, 7 differences,
 # 7 prefix products, 7 x (weight 4, three FMAs 6) + 7 suffix products), and q.
 PREDICT_FLOPS = 7 * (2 + 7 + 7 + 7 * 10 + 7) + 1
+# Epoch read off a step's collocation polynomial, per body: 6 components x
+# (7 FMAs + 4), plus the wavefront's 14 weight polynomials (8 FMAs and a
+# product each) shared by its 9 bodies.
+DENSE_FLOPS = 6 * (7 * 2 + 4) + (14 * 17 + 8) // 9
 
 
 def node_flops(n_body: int, n_gr: int) -> int:
@@ -286,6 +290,8 @@ def main():
     x0 = torch.as_tensor(case.x0).to(dev)
     frame_t_host = np.ascontiguousarray(fr.t)
     opts = api.default_opts()
+    # one launch per call that reads every epoch but the last off the step polynomials
+    dense_epochs_read = not opts.land_epochs and opts.lanes_per_body != 1 and opts.rebucket_epochs == 0
     n_gr = int(np.sum(case.ephem.flags & 1))
     log(f"setup {time.perf_counter() - t_setup:.1f} s: N={N} F={F}")
 
@@ -350,7 +356,10 @@ def main():
     obj_days = N * case.span
     value = obj_days / (ms_step / 1e3)
     # integrator roofline (FP64 vector ALU)
-    flops = integrator_flops(st, case.ephem.n_body, n_gr, case.ephem.degree + 1) / max(cnt[0], 1)
+    # every epoch but the last of a launch is read off the step polynomials
+    dense_epochs = (B - 1) * N if dense_epochs_read else 0
+    flops = (integrator_flops(st, case.ephem.n_body, n_gr, case.ephem.degree + 1) / max(cnt[0], 1)
+             + dense_epochs * DENSE_FLOPS)
     t_launch_nb = ms[0] / max(cnt[0], 1) / 1e3
     achieved_tf = flops / t_launch_nb / 1e12
     # FoV candidate kernel: compulsory HBM bytes (states per batch, frames, pair keys)

@@ -92,9 +92,13 @@ typedef struct {
     int32_t max_steps;       /* per object per call (2,000,000) */
     int32_t max_iter;        /* corrector iterations per step (12) */
     int32_t n_buckets;       /* step-size buckets (octaves of the predicted step), 1 = none (16) */
-    int32_t block;           /* integrator threads per block: 64/128/256 (128) */
+    int32_t block;           /* integrator threads per block: 64/128/256, 0 = auto (0: 256 for the
+                                grouped integrators reading epochs off the step polynomials,
+                                else 128) */
     int32_t rebucket_epochs; /* epochs per integrator launch, 0 = all (0) */
-    int32_t window_segs;     /* Chebyshev segments per staged window (2) */
+    int32_t window_segs;     /* Chebyshev segments per staged window, 0 = auto (0: for the grouped
+                                integrators reading epochs off the step polynomials the most, up
+                                to 6, with which three blocks share a compute unit's LDS; else 2) */
     int32_t lt_iter;         /* light-time iterations (10) */
     int32_t fov_block;       /* FoV threads per block: 64/128/256 (128) */
     int32_t adj_seg_steps;   /* adjoint: steps stored per checkpoint segment (32) */
@@ -103,6 +107,11 @@ typedef struct {
     int32_t zero_start;      /* 1: every corrector starts from zero increments, as in App. A.6;
                                 0: grouped integrators start from the previous step's
                                 collocation polynomial extrapolated (0) */
+    int32_t land_epochs;     /* 1: the integration lands on every output epoch (Sect. 2);
+                                0: grouped integrators land only on the last epoch of each
+                                launch and read the others off the collocation polynomial
+                                of the step that spans them (0) */
+    int32_t reserved;
 } kete_opts_t;
 
 /* Frames (Sect. 3.1): an instantaneous observation at time t from the

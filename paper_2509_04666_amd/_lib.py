@@ -40,7 +40,8 @@ class OptsT(C.Structure):
                 ("n_buckets", C.c_int32), ("block", C.c_int32), ("rebucket_epochs", C.c_int32),
                 ("window_segs", C.c_int32), ("lt_iter", C.c_int32), ("fov_block", C.c_int32),
                 ("adj_seg_steps", C.c_int32), ("persist_waves", C.c_int32),
-                ("lanes_per_body", C.c_int32), ("zero_start", C.c_int32)]
+                ("lanes_per_body", C.c_int32), ("zero_start", C.c_int32),
+                ("land_epochs", C.c_int32), ("reserved", C.c_int32)]
 
 
 class FramesT(C.Structure):

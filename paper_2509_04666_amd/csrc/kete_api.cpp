@@ -334,9 +334,9 @@ void kete_default_opts(kete_opts_t* o) {
     o->max_steps = 2000000;
     o->max_iter = 12;
     o->n_buckets = 16;
-    o->block = 128;
+    o->block = 0;
     o->rebucket_epochs = 0;
-    o->window_segs = 2;
+    o->window_segs = 0;
     o->persist_waves = 8;
     o->lanes_per_body = 7;
     o->lt_iter = 10;
@@ -372,6 +372,41 @@ int kete_make_batches(const double* t, int64_t n_frames, double span, int32_t* f
     return KETE_OK;
 }
 
+// window_segs, with 0 (auto) taken as dflt.
+static int segs_or(const kete_opts_t* o, int dflt) { return o->window_segs > 0 ? o->window_segs : dflt; }
+
+// Launch shape of the integrator where block or window_segs is 0 (auto).
+// With epochs read off the step polynomials, steps run until a window ends,
+// so windows are long: the longest (up to 6 segments) with which three
+// blocks of 256 threads share a compute unit's 160 KB of LDS, else smaller
+// blocks.  With landing on every epoch: 128 threads, 2 segments.
+static void auto_integrator_shape(const kete_ephem_t* eph, bool dense, int& block, int& wsegs) {
+    constexpr size_t kBlockLds = 53248;
+    if (!dense) {
+        if (block == 0) block = 128;
+        if (wsegs <= 0) wsegs = 2;
+        return;
+    }
+    for (int b : {256, 128, 64}) {
+        if (block != 0 && b != block) continue;
+        if (wsegs > 0) { block = b; return; }
+        for (int w = 6; w >= 1; --w)
+            if (nbody_g8_lds_bytes(eph->n_body, eph->degree + 1, w + 1, b) <= kBlockLds) {
+                block = b;
+                wsegs = w;
+                return;
+            }
+    }
+    if (block == 0) block = 64;
+    if (wsegs <= 0) wsegs = 1;
+}
+
+// The output epochs and the dense-output rows travel in front of the window
+// plan (one staged copy).
+static size_t epoch_table_bytes(int64_t n_out) {
+    return ((((size_t)n_out + kDenseCoefDoubles) * sizeof(double)) + 31) & ~(size_t)31;
+}
+
 size_t kete_propagate_workspace_size(int64_t n_obj, int64_t n_out, const kete_opts_t* opts) {
     kete_opts_t d;
     if (!opts) { kete_default_opts(&d); opts = &d; }
@@ -385,7 +420,7 @@ size_t kete_propagate_workspace_size(int64_t n_obj, int64_t n_out, const kete_op
     c.take<double>((size_t)n_obj * 6);
     c.take<double>((size_t)n_obj);
     c.take<int32_t>((size_t)n_obj);
-    c.take<Window>((size_t)max_win);
+    c.take<char>(epoch_table_bytes(n_out) + (size_t)max_win * sizeof(Window));
     c.take<int32_t>(bucket_scratch_ints(n_obj, nbk));
     return c.off;
 }
@@ -406,7 +441,8 @@ int kete_propagate_nbody(const kete_ephem_t* eph, const double* x0, double t0, i
     if (!std::isfinite(t0)) return fail(KETE_EINVAL, "t0 not finite");
     const double tlo = eph->t_start, thi = t_end_of(eph);
     if (!(t0 >= tlo && t0 <= thi)) return fail(KETE_ERANGE, "t0 %.9g outside ephemeris [%.9g, %.9g]", t0, tlo, thi);
-    const bool fwd = t_out[0] > t0;
+    // direction from the first epoch after the start (the first may equal t0)
+    const bool fwd = (n_out > 1 && t_out[0] == t0) ? t_out[1] > t0 : t_out[0] > t0;
     double prev = t0;
     for (int64_t k = 0; k < n_out; ++k) {
         if (!std::isfinite(t_out[k])) return fail(KETE_EINVAL, "t_out[%lld] not finite", (long long)k);
@@ -414,22 +450,47 @@ int kete_propagate_nbody(const kete_ephem_t* eph, const double* x0, double t0, i
             return fail(KETE_ERANGE, "t_out[%lld] = %.9g outside ephemeris [%.9g, %.9g]", (long long)k, t_out[k], tlo, thi);
         if (k > 0 && (fwd ? !(t_out[k] > prev) : !(t_out[k] < prev)))
             return fail(KETE_EINVAL, "t_out must be strictly monotone and on one side of t0");
-        if (k == 0 && t_out[0] == t0 && n_out > 1) {
-            // allowed: the first epoch may equal t0
-        }
         prev = t_out[k];
     }
-    if (opts->block != 64 && opts->block != 128 && opts->block != 256)
-        return fail(KETE_EINVAL, "block must be 64, 128 or 256");
+    if (opts->block != 0 && opts->block != 64 && opts->block != 128 && opts->block != 256)
+        return fail(KETE_EINVAL, "block must be 0 (auto), 64, 128 or 256");
     if (opts->lanes_per_body != 1 && opts->lanes_per_body != 7 && opts->lanes_per_body != 8)
         return fail(KETE_EINVAL, "lanes_per_body must be 1, 7 or 8");
     if (!(opts->eps > 0) || !(opts->h_init > 0) || !(opts->h_min > 0) || opts->max_iter < 1 || opts->max_steps < 1)
         return fail(KETE_EINVAL, "eps, h_init, h_min, max_iter and max_steps must be positive");
     const int nbk = std::min(std::max(1, opts->n_buckets), 32);
-    const int wsegs = std::max(1, opts->window_segs);
+    const bool dense = !opts->land_epochs && opts->lanes_per_body != 1;
+    int block = opts->block, wsegs = opts->window_segs;
+    auto_integrator_shape(eph, dense, block, wsegs);
 
+    // Launches cover runs of rebucket_epochs epochs.  With landing on every
+    // epoch each epoch ends a window; otherwise only a launch's last epoch
+    // does and the kernel reads the others off the step polynomials.
+    const int64_t R = opts->rebucket_epochs > 0 ? opts->rebucket_epochs : n_out;
     std::vector<int> epoch_win;
-    std::vector<Window> win = plan_windows(eph, t0, t_out, n_out, wsegs, epoch_win);
+    std::vector<Window> win;
+    if (!dense) {
+        win = plan_windows(eph, t0, t_out, n_out, wsegs, epoch_win);
+    } else {
+        epoch_win.assign(n_out, -1);
+        const double inv = 1.0 / eph->seg_days;
+        double t = t0;
+        for (int64_t e0 = 0; e0 < n_out; e0 += R) {
+            const int64_t e1 = std::min(n_out, e0 + R) - 1;
+            const double target = t_out[e1];
+            if (t == target) {
+                Window W{t, t, seg_of(eph, t), seg_of(eph, t), (int32_t)e1, 0};
+                win.push_back(W);
+            }
+            while (t != target) {
+                Window W = next_window(t, target, eph->t_start, eph->seg_days, inv, eph->n_seg, wsegs);
+                W.out = (W.t_b == target) ? (int32_t)e1 : -1;
+                win.push_back(W);
+                t = W.t_b;
+            }
+            epoch_win[e1] = (int)win.size() - 1;
+        }
+    }
     const int64_t max_win = 4 * (n_out + 1) + 65536;
     if ((int64_t)win.size() > max_win) return fail(KETE_EINVAL, "too many integration windows (%zu)", win.size());
 
@@ -440,11 +501,22 @@ int kete_propagate_nbody(const kete_ephem_t* eph, const double* x0, double t0, i
     double* state = c.take<double>((size_t)n_obj * 6);
     double* h_pref = c.take<double>((size_t)n_obj);
     int32_t* perm = c.take<int32_t>((size_t)n_obj);
-    Window* dwin = c.take<Window>((size_t)max_win);
+    char* plan = c.take<char>(epoch_table_bytes(n_out) + (size_t)max_win * sizeof(Window));
+    double* dcoef = (double*)plan;
+    double* dt_out = dcoef + kDenseCoefDoubles;
+    Window* dwin = (Window*)(plan + epoch_table_bytes(n_out));
     int32_t* bscratch = c.take<int32_t>(bucket_scratch_ints(n_obj, nbk));
 
     hipStream_t s = (hipStream_t)stream;
-    if ((rc = stage_to_device(dwin, win.data(), win.size() * sizeof(Window), s))) return rc;
+    {
+        std::vector<char> host(epoch_table_bytes(n_out) + win.size() * sizeof(Window));
+        const RadauConst& rcst = radau_const();
+        std::memcpy(host.data(), &rcst.Ap[0][0], 56 * sizeof(double));
+        std::memcpy(host.data() + 56 * sizeof(double), &rcst.Bp[0][0], 56 * sizeof(double));
+        std::memcpy(host.data() + kDenseCoefDoubles * sizeof(double), t_out, (size_t)n_out * sizeof(double));
+        std::memcpy(host.data() + epoch_table_bytes(n_out), win.data(), win.size() * sizeof(Window));
+        if ((rc = stage_to_device(plan, host.data(), host.size(), s))) return rc;
+    }
     HIPCHK(hipMemcpyAsync(state, x0, (size_t)n_obj * 6 * sizeof(double), hipMemcpyDeviceToDevice, s));
     HIPCHK(hipMemsetAsync(status, 0, (size_t)n_obj * sizeof(int32_t), s));
     HIPCHK(launch_hpref_init(x0, h_pref, (int)n_obj, E.gm[0], s));
@@ -457,6 +529,8 @@ int kete_propagate_nbody(const kete_ephem_t* eph, const double* x0, double t0, i
     P.h_pref = h_pref;
     P.status = status;
     P.x_out = x_out;
+    P.t_out = dt_out;
+    P.dense_coef = dcoef;
     P.stats = (unsigned long long*)stats;
     P.n_obj = (int32_t)n_obj;
     P.max_iter = opts->max_iter;
@@ -469,11 +543,12 @@ int kete_propagate_nbody(const kete_ephem_t* eph, const double* x0, double t0, i
     P.h_init = opts->h_init;
     P.safety = 0.25;
 
-    const int64_t R = opts->rebucket_epochs > 0 ? opts->rebucket_epochs : n_out;
     int first = 0;
     for (int64_t e0 = 0; e0 < n_out; e0 += R) {
         const int64_t e1 = std::min(n_out, e0 + R) - 1;
         const int last = epoch_win[e1];
+        P.e_first = dense ? (int32_t)e0 : (int32_t)e1;
+        P.e_land = (int32_t)e1;
         if (nbk > 1) {
             BucketParams B;
             B.h_pref = h_pref;
@@ -493,7 +568,7 @@ int kete_propagate_nbody(const kete_ephem_t* eph, const double* x0, double t0, i
         P.first_launch = (e0 == 0);
         {
             TimedScope ts(kTimeNbody, s);
-            HIPCHK(launch_nbody(P, opts->block, opts->lanes_per_body, s));
+            HIPCHK(launch_nbody(P, block, opts->lanes_per_body, s));
         }
         first = last + 1;
     }
@@ -754,7 +829,7 @@ int kete_propagate_adjoint(const kete_ephem_t* eph, int32_t mode, const double* 
     if (n_obj < 0 || n_obj > KETE_MAX_OBJ || k_obs < 0) return fail(KETE_EINVAL, "bad sizes");
     std::vector<Window> win;
     std::vector<int32_t> seg_win;
-    if ((rc = adjoint_plan(eph, t0, t_end, ckpt_days, std::max(1, opts->window_segs), win, seg_win))) return rc;
+    if ((rc = adjoint_plan(eph, t0, t_end, ckpt_days, segs_or(opts, 2), win, seg_win))) return rc;
     if (n_obj == 0) return KETE_OK;
     if (!x0 || !status || (k_obs > 0 && (!t_obs || !obs_pos))) return fail(KETE_EINVAL, "null pointer");
     if (mode == KETE_ADJ_FWD && k_obs > 0 && !sky_out) return fail(KETE_EINVAL, "sky_out is null");
@@ -818,7 +893,7 @@ int kete_propagate_adjoint(const kete_ephem_t* eph, int32_t mode, const double* 
     P.adj_state = adj_state;
     P.seg_ns = seg_ns;
     P.adj_tab = adj_tab;
-    P.max_win_segs = std::max(1, opts->window_segs) + 1;
+    P.max_win_segs = segs_or(opts, 2) + 1;
     P.max_iter = opts->max_iter;
     P.max_steps = opts->max_steps;
     P.zero_start = opts->zero_start != 0;
@@ -1088,7 +1163,7 @@ int kete_batch_run(const kete_ephem_t* eph, const kete_batch_t* batch, int64_t p
     B.status = status;
     B.perm = w.perm;
     B.n_buckets = std::min(std::max(1, opts->n_buckets), 32);
-    B.max_win_segs = std::max(1, opts->window_segs) + 1;
+    B.max_win_segs = segs_or(opts, 2) + 1;
     B.max_iter = opts->max_iter;
     B.max_steps = opts->max_steps;
     B.zero_start = opts->zero_start != 0;

@@ -32,6 +32,8 @@ struct RadauConst {
     double Lden[7];
     double L1[7];
 };
+// Ap then Bp, as copied next to the output epochs for the dense-output kernels
+constexpr int kDenseCoefDoubles = 2 * 7 * 8;
 
 // One staged ephemeris window of the integration: [t_a, t_b] lies within
 // Chebyshev segments [seg_lo, seg_hi]; out >= 0 marks an output epoch.
@@ -95,6 +97,10 @@ struct NbodyParams {
     double* x_out;          // [E][N][6]
     unsigned long long* stats;  // [8] or null
     const Window* win;      // windows of this launch
+    const double* t_out;    // [E] output epochs (device)
+    const double* dense_coef;   // [2][7][8] the monomial rows Ap, Bp of RadauConst (device)
+    int32_t e_first;        // epochs e_first .. e_land - 1 are read off the step polynomials,
+    int32_t e_land;         // epoch e_land ends the launch's last window (no dense epochs: e_first = e_land)
     int32_t n_win;
     int32_t n_obj;
     int32_t max_iter;
@@ -110,6 +116,8 @@ const RadauConst& radau_const();
 
 // lanes_per_body: 1 (one lane per object) or 8 (an 8-lane group per object).
 hipError_t launch_nbody(const NbodyParams& p, int block, int lanes_per_body, hipStream_t s);
+// LDS of one block of the grouped integrator (dynamic and static).
+size_t nbody_g8_lds_bytes(int n_body, int deg1, int max_win_segs, int block);
 
 // Stable counting sort of objects into step-size buckets.
 struct BucketParams {

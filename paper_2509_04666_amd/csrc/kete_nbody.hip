@@ -184,6 +184,11 @@ __global__ __launch_bounds__(BLOCK, 3) void k_nbody_g8(const NbodyParams p) {
         load_node_row(rc, tid < 7 ? tid + 1 : 7, r);
         rows[tid] = r;
     }
+    // dense-output rows, read from LDS at the epochs inside a step
+    __shared__ double dcoef[kDenseCoefDoubles];
+    __shared__ double dwts[BLOCK / kWave][16];      // per wavefront: the 14 weights of an epoch
+    if (p.e_first < p.e_land)
+        for (int i = tid; i < kDenseCoefDoubles; i += BLOCK) dcoef[i] = p.dense_coef[i];
     __syncthreads();
     const NodeRow& R = rows[gl];
 
@@ -209,13 +214,47 @@ __global__ __launch_bounds__(BLOCK, 3) void k_nbody_g8(const NbodyParams p) {
     S.haveF0 = false;
     G8Count C;
 
+    // Epochs e_first .. e_land - 1 come off the collocation polynomial of
+    // the accepted step that spans them (the cursor is wave-uniform: the
+    // wavefront's objects share every step).
+    double* xg = g8_xch(e8, nb, M.grp);
+    int e_next = p.e_first;
+    auto put = [&](int e, double v, bool ok) {      // lane gl writes component gl
+        if (valid && gl < 6) p.x_out[((size_t)e * p.n_obj + j) * 6 + gl] = ok ? v : __builtin_nan("");
+    };
+    while (e_next < p.e_land && p.t_out[e_next] == S.t) {       // epochs at the start time
+        put(e_next, state_component(S.x0, S.v0, gl < 6 ? gl : 5), S.active && S.status == 0);
+        ++e_next;
+    }
+    auto dense_out = [&](double ts, double h, const double dn[3], const G8State& St) {
+        if (e_next >= p.e_land) return;
+        const double te = ts + h;
+        double tk = p.t_out[e_next];
+        if (!(h > 0.0 ? tk <= te : tk >= te)) return;
+        wave_lds_sync();                    // earlier reads of the exchange rows are done
+        xg[gl] = dn[0];
+        xg[8 + gl] = dn[1];
+        xg[16 + gl] = dn[2];
+        wave_lds_sync();
+        for (;;) {
+            const double sig = (tk - ts) / h;
+            dense_weights_wave(dcoef, sig, lane, dwts[wid]);
+            double X[3], V[3];
+            dense_state_wave(dwts[wid], xg, St.x0, St.v0, St.F0, h, sig, X, V);
+            put(e_next, state_component(X, V, gl < 6 ? gl : 5), St.active && St.status == 0);
+            if (++e_next >= p.e_land) break;
+            tk = p.t_out[e_next];
+            if (!(h > 0.0 ? tk <= te : tk >= te)) break;
+        }
+    };
+
     for (int w = 0; w < p.n_win; ++w) {
         const Window W = p.win[w];
         __syncthreads();
         stage_window(E, W.seg_lo, W.seg_hi, bstride, tid, BLOCK, coefL);
         __syncthreads();
-        g8_integrate<NB, NGR, DEG1, G, kStartExtrapolate>(p, R, node, gl, M.grp, lane, coefL, bstride, e8, W.seg_lo, W.seg_hi, W.t_b,
-                                       S, C);
+        g8_integrate<NB, NGR, DEG1, G, kStartExtrapolate>(p, R, node, gl, M.grp, lane, coefL, bstride, e8, W.seg_lo,
+                                                          W.seg_hi, W.t_b, S, C, dense_out);
         if (W.out >= 0 && valid && gl < 6) {
             // lane gl of the group writes component gl of the state
             double* dst = p.x_out + ((size_t)W.out * p.n_obj + j) * 6;
@@ -296,6 +335,12 @@ __global__ void k_hpref_init(const double* __restrict__ x0, double* __restrict__
 }
 
 }  // namespace
+
+size_t nbody_g8_lds_bytes(int n_body, int deg1, int max_win_segs, int block) {
+    return ((((size_t)n_body * max_win_segs * 3 * deg1 + 1) & ~(size_t)1) +
+            (size_t)(block / kWave) * g8_wave_doubles(n_body)) * sizeof(double) +
+           sizeof(NodeRow) * kGroup + kDenseCoefDoubles * sizeof(double);
+}
 
 hipError_t launch_nbody(const NbodyParams& p, int block, int lanes_per_body, hipStream_t s) {
     const size_t lds = ((size_t)p.eph.n_body * p.max_win_segs * 3 * p.eph.deg1 +

@@ -902,6 +902,51 @@ __device__ __forceinline__ void dense_state(const RadauConst& rc, const double x
     }
 }
 
+// Dense output at fraction sig of a step, in two parts.  The 14 weights
+// alpha_m(sig) = sum_k Ap[m][k] sig^(k+2) and beta_m(sig) = sum_k Bp[m][k]
+// sig^(k+1) are the same for every object of a wavefront (they share the
+// step), so lanes 0..13 evaluate one each from the monomial rows in LDS
+// (cw: Ap[7][8] then Bp[7][8]) into the wavefront's slots wt[14]; then
+// each lane forms its object's state from the weights and the step's node
+// increments in the group's exchange rows xg (component c
+// of node m + 1 at xg[8 c + m]) in dense_state_wave.  The first call is
+// made by the whole wavefront.
+__device__ __forceinline__ void dense_weights_wave(const double* __restrict__ cw, double sig, int lane,
+                                                   double* __restrict__ wt) {
+    wave_lds_sync();                        // earlier reads of wt are done
+    if (lane < 14) {
+        const double* pm = cw + 8 * lane;
+        double w = pm[7];
+#pragma unroll
+        for (int k = 6; k >= 0; --k) w = fma(w, sig, pm[k]);
+        wt[lane] = w * (lane < 7 ? sig * sig : sig);
+    }
+    wave_lds_sync();
+}
+__device__ __forceinline__ void dense_state_wave(const double* __restrict__ wt, const double* __restrict__ xg,
+                                                 const double x0[3], const double v0[3], const double F0[3],
+                                                 double h, double sig, double X[3], double V[3]) {
+    double ax[3], av[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) { ax[c] = 0.5 * sig * sig * F0[c]; av[c] = sig * F0[c]; }
+#pragma unroll 1
+    for (int m = 0; m < 7; ++m) {
+        const double a = wt[m], b = wt[7 + m];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double d = xg[8 * c + m];
+            ax[c] = fma(a, d, ax[c]);
+            av[c] = fma(b, d, av[c]);
+        }
+    }
+    const double hh = h * h;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        X[c] = fma(hh, ax[c], fma(sig * h, v0[c], x0[c]));
+        V[c] = fma(h, av[c], v0[c]);
+    }
+}
+
 // Shared stepping state of one lane.
 struct Lane {
     double x0[3], v0[3], F0[3];

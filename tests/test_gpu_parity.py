@@ -188,6 +188,36 @@ def test_extrapolated_corrector_start(torch_cuda, orc):
         assert np.max(np.abs(xs[..., :3] - xo[..., :3])) < 1e-10
 
 
+def test_dense_epochs_match_landing(torch_cuda, orc):
+    """Epochs read off the step polynomials (the default) against landing on
+    every epoch and against the oracle, which lands: an epoch equal to the
+    start, epochs a fraction of a step apart, backward integration and runs
+    split over several launches."""
+    torch, api = torch_cuda
+    case = synth.survey_case(n_obj=300, n_frames=0, neo_frac=0.2)
+    eph = api.DeviceEphemeris.from_synth(case.ephem)
+    x0 = _dev_x(torch, case.x0)
+    sel = np.arange(0, 300, 7)
+    for t0, t_out in ((0.0, [0.0, 0.7, 3.1, 3.2, 10.0, 17.5, 40.0, 61.25]), (30.0, [29.5, 21.0, 20.9, 2.0])):
+        xd, sd, std = api.propagate(eph, x0, t0, t_out, api.default_opts(), stats=True)
+        xl, sl, stl = api.propagate(eph, x0, t0, t_out, api.default_opts(land_epochs=1), stats=True)
+        xr, sr = api.propagate(eph, x0, t0, t_out, api.default_opts(rebucket_epochs=3))
+        assert torch.equal(sd, sl) and torch.equal(sd, sr)
+        ok = (sd == 0).cpu().numpy()
+        d_land = (xd - xl)[:, torch.as_tensor(ok, device="cuda")].abs().max().item()
+        d_split = (xd - xr)[:, torch.as_tensor(ok, device="cuda")].abs().max().item()
+        xo, so, _ = orc.propagate(case.ephem, case.x0[sel], t0, t_out)
+        xs = xd[:, torch.as_tensor(sel, device="cuda")].cpu().numpy()
+        d_orc = np.abs(xs[:, so == 0, :3] - xo[:, so == 0, :3]).max()
+        _say(f"t0 {t0}: dense vs landing {d_land:.2e}, vs split launches {d_split:.2e}, vs oracle {d_orc:.2e} au; "
+             f"body-steps {std.cpu().numpy()[3]} vs {stl.cpu().numpy()[3]} landing")
+        assert d_land < 1e-11 and d_split < 1e-11 and d_orc < 1e-11
+        assert std.cpu().numpy()[3] < stl.cpu().numpy()[3]
+        # the epoch at the start time is the initial state itself
+        if t_out[0] == t0:
+            assert torch.equal(xd[0], x0)
+
+
 def test_propagate_ragged_sizes(torch_cuda, orc):
     torch, api = torch_cuda
     case = synth.survey_case(n_obj=130, n_frames=0, neo_frac=0.3)
