@@ -36,8 +36,9 @@ HBM_PEAK_GBS = 8000.0
 CLENSHAW_CHAIN_FLOPS = lambda deg1: 7 * (deg1 - 1) + 12     # value and derivative
 CLENSHAW_VALUE_FLOPS = lambda deg1: 3 * (deg1 - 1) + 9      # value only
 # Extrapolated corrector start, per body-step: 7 nodes x (sig 2, 7 differences,
-# 7 prefix products, 7 x (weight 4, three FMAs 6) + 7 suffix products), and q.
-PREDICT_FLOPS = 7 * (2 + 7 + 7 + 7 * 10 + 7) + 1
+# 7 prefix products, 7 x (basis product 1, weight FMA 2, three FMAs 6, suffix
+# product 1)), and q.
+PREDICT_FLOPS = 7 * (2 + 7 + 7 + 7 * 10) + 1
 # Epoch read off a step's collocation polynomial, per body: 6 components x
 # (7 FMAs + 4), plus the wavefront's 14 weight polynomials (8 FMAs and a
 # product each) shared by its 9 bodies.
