@@ -1040,6 +1040,7 @@ int batch_dims(const kete_ephem_t* eph, const kete_batch_t* bt, int64_t pairs_ca
 struct BatchWs {
     int2* tiles;
     unsigned int* tile_counter;
+    double* dense_coef;
     int32_t* perm;
     FovParams P;
     int32_t *qkey, *cnt, *fcnt, *fstart, *okey, *orank, *osorted, *ostart, *ocnt, *icnt, *istart;
@@ -1054,6 +1055,7 @@ size_t batch_carve(const BatchDims& d, const kete_batch_t* bt, char* base, Batch
     Carver c{base};
     w.tiles = c.take<int2>((size_t)std::max(d.n_tiles, 1));
     w.tile_counter = c.take<unsigned int>(64);
+    w.dense_coef = c.take<double>(kDenseCoefDoubles);
     w.perm = c.take<int32_t>((size_t)std::max<int64_t>(bt->n_bodies, 1));
     FovParams& P = w.P;
     std::memset(&P, 0, sizeof(P));
@@ -1167,6 +1169,8 @@ int kete_batch_run(const kete_ephem_t* eph, const kete_batch_t* batch, int64_t p
     B.max_iter = opts->max_iter;
     B.max_steps = opts->max_steps;
     B.zero_start = opts->zero_start != 0;
+    B.land_epochs = opts->land_epochs != 0;
+    B.dense_coef = w.dense_coef;
     B.eps = opts->eps;
     B.h_min = opts->h_min;
     B.h_max = opts->h_max;

@@ -89,6 +89,11 @@ __global__ __launch_bounds__(64, 3) void k_batch_g8(const BatchParams p) {
     g8_table_init(E, lane, e8);
     NodeRow R;
     load_node_row(p.rc, node, R);
+    // dense-output rows and the wavefront's weight slots
+    __shared__ double dcoef[kDenseCoefDoubles];
+    __shared__ double dwts[16];
+    for (int i = lane; i < kDenseCoefDoubles; i += 64) dcoef[i] = p.dense_coef[i];
+    __syncthreads();
     const int W = p.max_win_segs - 1;            // segment lengths per window
     int lo = 1, hi = 0;                          // nothing staged yet
     for (;;) {
@@ -121,20 +126,60 @@ __global__ __launch_bounds__(64, 3) void k_batch_g8(const BatchParams p) {
         S.t = job.t0;
         S.haveF0 = false;
         G8Count C;
-        for (int e = 0; e < job.n_epoch; ++e) {
-            const double target = p.epochs[job.epoch_off + e];
+        const double* ep = p.epochs + job.epoch_off;
+        double* xg = g8_xch(e8, E.n_body, M.grp);
+        auto put = [&](int e, double v, bool ok) {       // lane gl writes component gl
+            if (valid && gl < 6)
+                p.x_out[job.xout_off + ((int64_t)e * job.n_obj + local) * 6 + gl] = ok ? v : __builtin_nan("");
+        };
+        // The epochs run away from t0 (later ones ascending, then earlier
+        // ones descending).  Each run of epochs in one direction lands on
+        // its last epoch; the others come off the collocation polynomial
+        // of the step that spans them (unless every epoch is landed on).
+        int e = 0;
+        while (e < job.n_epoch) {
+            if (ep[e] == S.t) {
+                put(e, state_component(S.x0, S.v0, gl < 6 ? gl : 5), S.active && S.status == 0);
+                ++e;
+                continue;
+            }
+            const bool fwd = ep[e] > S.t;
+            int e_end = e;
+            if (!p.land_epochs)
+                while (e_end + 1 < job.n_epoch && (fwd ? ep[e_end + 1] > ep[e_end] : ep[e_end + 1] < ep[e_end]))
+                    ++e_end;
+            const double target = ep[e_end];
+            int e_next = e;                              // wave-uniform cursor over e .. e_end - 1
+            auto dense_out = [&](double ts, double h, const double dn[3], const G8State& St) {
+                if (e_next >= e_end) return;
+                const double te = ts + h;
+                double tk = ep[e_next];
+                if (!(h > 0.0 ? tk <= te : tk >= te)) return;
+                wave_lds_sync();                        // earlier reads of the exchange rows are done
+                xg[gl] = dn[0];
+                xg[8 + gl] = dn[1];
+                xg[16 + gl] = dn[2];
+                wave_lds_sync();
+                for (;;) {
+                    const double sig = (tk - ts) / h;
+                    dense_weights_wave(dcoef, sig, lane, dwts);
+                    double X[3], V[3];
+                    dense_state_wave(dwts, xg, St.x0, St.v0, St.F0, h, sig, X, V);
+                    put(e_next, state_component(X, V, gl < 6 ? gl : 5), St.active && St.status == 0);
+                    if (++e_next >= e_end) break;
+                    tk = ep[e_next];
+                    if (!(h > 0.0 ? tk <= te : tk >= te)) break;
+                }
+            };
             while (S.t != target) {
                 const Window Wn = next_window(S.t, target, E.t_start, E.seg_days, E.inv_seg, E.n_seg, W);
                 ensure_window(E, Wn.seg_lo, Wn.seg_hi, lo, hi, coefL, bstride);
-                g8_integrate<NB, NGR, DEG1, G, kStartExtrapolate>(p, R, node, gl, M.grp, lane, coefL, bstride, e8, lo, hi, Wn.t_b, S,
-                                               C);
+                g8_integrate<NB, NGR, DEG1, G, kStartExtrapolate>(p, R, node, gl, M.grp, lane, coefL, bstride, e8, lo,
+                                                                  hi, Wn.t_b, S, C, dense_out);
                 S.t = Wn.t_b;
             }
-            if (valid && gl < 6) {
-                double* dst = p.x_out + job.xout_off + ((int64_t)e * job.n_obj + local) * 6;
-                const bool ok = S.active && S.status == 0;
-                dst[gl] = ok ? state_component(S.x0, S.v0, gl) : __builtin_nan("");
-            }
+            put(e_end, state_component(S.x0, S.v0, gl < 6 ? gl : 5), S.active && S.status == 0);
+            e = e_end + 1;
         }
         if (valid && gl == 0) p.status[gobj] = S.status;
     }
@@ -147,11 +192,20 @@ size_t batch_lds_bytes(const BatchParams& p) {
             (size_t)g8_wave_doubles(p.eph.n_body)) * sizeof(double);
 }
 
+// The dense-output rows of the constants into device memory (a tiny kernel,
+// so the copy is part of a captured graph too).
+__global__ void k_dense_coef(const BatchParams p) {
+    const int i = threadIdx.x;
+    if (i < 56) p.dense_coef[i] = p.rc.Ap[i / 8][i % 8];
+    else if (i < kDenseCoefDoubles) p.dense_coef[i] = p.rc.Bp[(i - 56) / 8][(i - 56) % 8];
+}
+
 hipError_t launch_batch(const BatchParams& p, int waves_per_cu, hipStream_t s) {
     int dev = 0, ncu = 256;
     if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     hipError_t e;
     if ((e = fill_zero(p.tile_counter, sizeof(unsigned int), s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_dense_coef, dim3(1), dim3(128), 0, s, p);
     if (p.n_jobs > 0 && p.n_buckets > 1)
         hipLaunchKernelGGL(k_job_bucket, dim3((unsigned)p.n_jobs), dim3(256), 0, s, p);
     const int grid = std::max(1, std::min(ncu * waves_per_cu, p.n_tiles));

@@ -30,7 +30,8 @@ struct BatchParams {
     int32_t max_iter;
     int32_t max_steps;
     int32_t zero_start;         // corrector starts from zero increments (no extrapolation)
-    int32_t pad_;
+    int32_t land_epochs;        // land on every epoch (else epochs inside a step come off its polynomial)
+    double* dense_coef;         // [kDenseCoefDoubles] Ap, Bp of rc, written by the launch
     double eps, h_min, h_max, h_init, safety;
 };
 
