@@ -482,6 +482,7 @@ struct ObjLin {
     unsigned long long gobj;    // global object index; bit 63 set: no linear test
 };
 constexpr int kLinQueue = 2 * kWave;
+constexpr int kItemChunk = 3;
 
 // Persistent join: every wavefront pops work items until none is left.
 // An item is up to 64 narrow objects of one (batch, cell), one per lane;
@@ -504,12 +505,18 @@ __global__ __launch_bounds__(256, 3) void k_fov_cells(const FovParams p) {
     unsigned long long* queue = queue_all[wv];
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     int nbuf = 0;
+    int item = 0, item_end = 0;
     for (;;) {
-        int item = 0;
-        if (lane == 0) item = (int)atomicAdd(p.item_next, 1u);
-        item = __shfl(item, 0, kWave);
+        // items are taken kItemChunk at a time: one atomic on the shared
+        // counter per chunk
+        if (item >= item_end) {
+            int first = 0;
+            if (lane == 0) first = (int)atomicAdd(p.item_next, (unsigned)kItemChunk);
+            item = __shfl(first, 0, kWave);
+            item_end = min(item + kItemChunk, n_items);
+        }
         if (item >= n_items) break;
-        const unsigned long long it = p.items[item];
+        const unsigned long long it = p.items[item++];
         const int64_t key = (int64_t)(it >> 32);
         const int chunk = (int)(it & 0xffffffffull);
         const int o1 = p.obj_start[key + 1];
