@@ -756,14 +756,19 @@ constexpr int kKeySlots = 2 * kKeyBlock;     // at most half full: probing alway
 __global__ __launch_bounds__(kKeyBlock) void k_obj_keys(const FovParams p, int32_t* __restrict__ okey,
                                                         int32_t* __restrict__ orank, int32_t* __restrict__ cnt) {
     __shared__ int32_t hkey[kKeySlots], hcnt[kKeySlots], hbase[kKeySlots];
+    __shared__ int b_first;
     const int tid = threadIdx.x;
     for (int k = tid; k < kKeySlots; k += kKeyBlock) { hkey[k] = -1; hcnt[k] = 0; }
+    // the block's items are consecutive: one search finds the batch of the
+    // first, and each item steps on from there
+    if (tid == 0) b_first = batch_of(p.b_poff, p.n_batch, (int64_t)blockIdx.x * kKeyBlock);
     __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * kKeyBlock + tid;
     const bool valid = i < p.n_pairs_total;
     int slot = 0, lrank = 0;
     if (valid) {
-        const int b = batch_of(p.b_poff, p.n_batch, i);
+        int b = b_first;
+        while (b + 1 < p.n_batch && p.b_poff[b + 1] <= i) ++b;
         const int64_t j = i - p.b_poff[b];
         ObjBounds o;
         const int G = p.b_G[b], G3 = G * G * G;
@@ -796,10 +801,14 @@ __global__ __launch_bounds__(kKeyBlock) void k_obj_keys(const FovParams p, int32
 // inside a cell is arbitrary: the pairs are sorted at the end).
 __global__ void k_obj_scatter(const FovParams p, const int32_t* __restrict__ okey, const int32_t* __restrict__ orank,
                               const int32_t* __restrict__ start, int32_t* __restrict__ sorted) {
+    __shared__ int b_first;
+    if (threadIdx.x == 0) b_first = batch_of(p.b_poff, p.n_batch, (int64_t)blockIdx.x * blockDim.x);
+    __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= p.n_pairs_total) return;
     const int key = okey[i];
-    const int b = batch_of(p.b_poff, p.n_batch, i);
+    int b = b_first;
+    while (b + 1 < p.n_batch && p.b_poff[b + 1] <= i) ++b;
     // keys are batch-major, so batch b occupies [b_poff[b], b_poff[b+1])
     sorted[start[key] + orank[i]] = (int32_t)(i - p.b_poff[b]);
 }
@@ -1051,7 +1060,7 @@ hipError_t fov_candidates(FovParams& p, int32_t* icnt, int32_t* istart, unsigned
     if ((e = exclusive_scan_i32(icnt, istart, p.n_keys, scan_scratch, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_item_scatter, dim3(gk), dim3(256), 0, s, p, (const int32_t*)icnt);
     if ((e = fill_zero(item_next, sizeof(unsigned int), s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_fov_cells, dim3((unsigned)(cu_count() * 2)), dim3(256), 0, s, p);
+    hipLaunchKernelGGL(k_fov_cells, dim3((unsigned)(cu_count() * 3)), dim3(256), 0, s, p);
     return hipGetLastError();
 }
 
