@@ -18,6 +18,7 @@ live with HIP events on the stream it runs on.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import math
 import os
@@ -337,6 +338,10 @@ def main():
     stats = torch.zeros(8, dtype=torch.int64, device=dev)
     L = _lib.lib()
     L.kete_timing_enable(1)
+    # as timeit does: collect first, then keep the interpreter's collector
+    # out of the timed steps
+    gc.collect()
+    gc.disable()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     marks = []
@@ -345,6 +350,7 @@ def main():
         marks.append(time.perf_counter())
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    gc.enable()
     # host-side return times of the steps (each step ends with the pair count read)
     log("step host times (ms): " + " ".join("%.1f" % (1e3 * (b - a)) for a, b in zip([t0] + marks[:-1], marks)))
     L.kete_timing_enable(0)
