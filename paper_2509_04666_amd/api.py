@@ -69,8 +69,9 @@ def _workspace(nbytes: int, device=DEV) -> torch.Tensor:
 
 
 def propagate(eph: DeviceEphemeris, x0: torch.Tensor, t0: float, t_out: Sequence[float],
-              opts: Optional[OptsT] = None, stats: bool = False, workspace: Optional[torch.Tensor] = None):
-    """States at every epoch: (x_out [E, N, 6], status [N] int32[, stats [8] int64])."""
+              opts: Optional[OptsT] = None, stats=False, workspace: Optional[torch.Tensor] = None):
+    """States at every epoch: (x_out [E, N, 6], status [N] int32[, stats [8] int64]).  stats may be
+    an int64 [8] device tensor that the kernels add their counters into."""
     opts = opts or default_opts()
     x0 = x0.contiguous()
     assert x0.dtype == torch.float64 and x0.is_cuda and x0.dim() == 2 and x0.shape[1] == 6
@@ -78,13 +79,17 @@ def propagate(eph: DeviceEphemeris, x0: torch.Tensor, t0: float, t_out: Sequence
     n, E = x0.shape[0], t_out.size
     x_out = torch.empty((E, n, 6), dtype=torch.float64, device=x0.device)
     status = torch.empty(n, dtype=torch.int32, device=x0.device)
-    st = torch.zeros(8, dtype=torch.int64, device=x0.device) if stats else None
+    if isinstance(stats, torch.Tensor):
+        assert stats.dtype == torch.int64 and stats.numel() == 8 and stats.device == x0.device
+        st = stats
+    else:
+        st = torch.zeros(8, dtype=torch.int64, device=x0.device) if stats else None
     need = lib().kete_propagate_workspace_size(n, E, C.byref(opts))
     ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, x0.device)
     check(lib().kete_propagate_nbody(C.byref(eph.c), _ptr(x0), float(t0), n,
                                      t_out.ctypes.data_as(C.c_void_p), E, _ptr(x_out), _ptr(status), _ptr(st),
                                      C.byref(opts), _ptr(ws), ws.numel(), _stream()))
-    return (x_out, status, st) if stats else (x_out, status)
+    return (x_out, status, st) if st is not None else (x_out, status)
 
 
 def make_batches(t: np.ndarray, span: float = 3.0):
