@@ -98,7 +98,8 @@ typedef struct {
     int32_t rebucket_epochs; /* epochs per integrator launch, 0 = all (0) */
     int32_t window_segs;     /* Chebyshev segments per staged window, 0 = auto (0: for the grouped
                                 integrators reading epochs off the step polynomials the most, up
-                                to 6, with which three blocks share a compute unit's LDS; else 2) */
+                                to 6, with which three blocks share a compute unit's LDS; for the
+                                adjoint 3; else 2) */
     int32_t lt_iter;         /* light-time iterations (10) */
     int32_t fov_block;       /* FoV threads per block: 64/128/256 (128) */
     int32_t adj_seg_steps;   /* adjoint: steps stored per checkpoint segment (32) */
@@ -294,12 +295,16 @@ size_t kete_adjoint_workspace_size(int64_t n_obj, int32_t k_obs, double t0, doub
  * and RA/Dec (radians) in the equatorial J2000 frame (ecliptic rotated by
  * the obliquity 84381.448").
  *   mode KETE_ADJ_FWD: writes sky_out [N][K][2] and status [N], and stores
- *     checkpoints every ckpt_days and each observation's light time in the
- *     workspace;
+ *     in the workspace a checkpoint per ckpt_days (checkpoint c: the state
+ *     at the first integration step starting at or after t0 + c ckpt_days,
+ *     so the steps are not cut at checkpoints) and each observation's
+ *     light time;
  *   mode KETE_ADJ_BWD: given dL_dsky [N][K][2] (device) for the same
- *     inputs and workspace, writes grad_x0 [N][6] = dL/dx0: the discrete
- *     adjoint of the forward computation, recomputing each checkpoint
- *     segment.  Objects with a non-zero status get a zero gradient.
+ *     inputs, options and workspace, writes grad_x0 [N][6] = dL/dx0: the
+ *     discrete adjoint of the forward computation, recomputing each
+ *     checkpoint segment (on a second, library-owned stream, ordered by
+ *     events; the call's stream sees the whole result).  Objects with a
+ *     non-zero status get a zero gradient.
  * All arrays are device memory; t0, t_end and ckpt_days are host values.
  * Errors: KETE_EINVAL, KETE_ERANGE, KETE_EWORKSPACE, KETE_EDEVICE. */
 int kete_propagate_adjoint(const kete_ephem_t *eph, int32_t mode, const double *x0, double t0, double t_end,

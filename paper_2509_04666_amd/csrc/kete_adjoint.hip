@@ -1,17 +1,19 @@
 // Gradient of sky-position residuals with respect to the initial state.
 //
 // Forward: the collocation integrator of the propagation kernels (8-lane
-// group per object, wave-shared steps) lands on checkpoint times every
-// ckpt_days; observations at per-object times are read off the step's
-// collocation polynomial, hopped with light time to the emission point
-// (Sect. 2) and turned into RA/Dec.
+// group per object, wave-shared steps) takes its own steps; checkpoint c
+// is the state at the first step start at or after t0 + c ckpt_days, and
+// observations at per-object times are read off the step's collocation
+// polynomial, hopped with light time to the emission point (Sect. 2) and
+// turned into RA/Dec.
 //
 // Backward: the discrete adjoint of that forward map.  Checkpoint
 // segments are processed last to first: the segment's steps are
-// recomputed from its checkpoint (same step sequence, bit for bit) while
-// each step's data and the force Jacobians at its 8 nodes are stored; the
-// steps are then swept in reverse, solving the linear stage equations of
-// the step's transpose by fixed-point iteration.  The light-time hop's
+// recomputed from its checkpoint (same windows and step sequence, bit for
+// bit) while each step's start, size and force Jacobians at its 8 nodes
+// are stored; the steps are then swept in reverse, solving the linear
+// stage equations of the step's transpose by fixed-point iteration.  The
+// recompute of the next segment runs on a second stream during a sweep.  The light-time hop's
 // Jacobian comes from one forward-mode (six-direction dual number)
 // evaluation of the universal-variable solution at its converged anomaly
 // plus the implicit light-time term.
@@ -19,6 +21,8 @@
 
 #include "kete_adjoint.hpp"
 #include "kete_radau.hpp"
+
+#include <mutex>
 
 namespace kete {
 namespace {
@@ -181,14 +185,14 @@ __device__ void hop_vjp(const AdjParams& p, const SunGlobal& sun, double t_obs, 
 // collocation node, 8 objects per wavefront, wave-shared steps) with the
 // step loop of the propagation kernels.
 
-// Checkpoint c of object j: state, the step size to resume with, a
-// failure flag, the force at the state (with whether it was evaluated
-// yet), and the last accepted step with its node increments, so that a
-// recompute repeats the forward's steps exactly (extrapolated corrector
-// starts included).  Lanes 0..7 of the group write the first eight
-// values, lanes 0..3 the force, lanes 0..6 their node's increment and
-// lane 7 the step.
-__device__ __forceinline__ void save_ckpt_g8(const AdjParams& p, int c, int j, int gl, const G8State& S) {
+// Checkpoint c of object j at time t: state, the step size to resume
+// with, a failure flag, the force at the state (with whether it was
+// evaluated yet), and the last accepted step with its node increments, so
+// that a recompute repeats the forward's steps exactly (extrapolated
+// corrector starts included).  Lanes 0..7 of the group write the first
+// eight values, lanes 0..3 the force, lanes 0..6 their node's increment
+// and lane 7 the step and the time.
+__device__ __forceinline__ void save_ckpt_g8(const AdjParams& p, int c, int j, int gl, const G8State& S, double t) {
     double* ck = p.ckpt + ((size_t)c * p.n_obj + j) * kCkptDoubles;
     const double v = gl < 6 ? state_component(S.x0, S.v0, gl)
                             : gl == 6 ? S.hw : (S.active ? 0.0 : (double)(S.status ? S.status : 1));
@@ -200,6 +204,7 @@ __device__ __forceinline__ void save_ckpt_g8(const AdjParams& p, int c, int j, i
         for (int i = 0; i < 3; ++i) ck[12 + 3 * gl + i] = S.Dp[i];
     } else {
         ck[33] = S.hprev;
+        ck[34] = t;
     }
 }
 
@@ -229,6 +234,10 @@ __global__ __launch_bounds__(64, 3) void k_adjoint_fwd(const AdjParams p) {
     g8_table_init(E, lane, e8);
     NodeRow R;
     load_node_row(p.rc, node, R);
+    // dense-output rows, read from LDS at the observations inside a step
+    __shared__ double dcoef[kDenseCoefDoubles];
+    for (int i = lane; i < kDenseCoefDoubles; i += 64) dcoef[i] = p.dense_coef[i];
+    __syncthreads();
     const long gi = ((long)blockIdx.x * 64 + lane) / kGroup;
     const bool valid = gi < p.n_obj;
     const int j = valid ? p.perm[gi] : 0;
@@ -246,37 +255,52 @@ __global__ __launch_bounds__(64, 3) void k_adjoint_fwd(const AdjParams p) {
     };
     // observations at the start epoch
     if (valid) while (kobs < K && tob[kobs] <= S.t) { store_obs(kobs, S.x0, S.v0); ++kobs; }
+    // Checkpoint c (1 .. C - 1) is the state at the first accepted step
+    // start at or after t0 + c ckpt_days (wave-uniform: the wavefront's
+    // objects share their steps), so steps are not cut at checkpoints.
+    int c_next = 1;
     auto visit = [&](double ts, double h, const double dn[3], const G8State& St) {
+        while (c_next < p.n_ckpt && ts >= p.t0 + c_next * p.ckpt_days) {
+            if (valid) save_ckpt_g8(p, c_next, j, gl, St, ts);
+            ++c_next;
+        }
         const double te = ts + h;
         auto pending = [&]() {
             return valid && St.active && kobs < K && (h > 0 ? tob[kobs] <= te : tob[kobs] >= te);
         };
         bool pend = pending();
         if (__ballot(pend) == 0ull) return;
-        double D[7][3];
-        g8_exchange(g8_xch(e8, E.n_body, lane / kGroup), gl, dn, D);
+        // the step's node increments into the group's exchange rows
+        double* xg = g8_xch(e8, E.n_body, lane / kGroup);
+        wave_lds_sync();
+        xg[gl] = dn[0];
+        xg[8 + gl] = dn[1];
+        xg[16 + gl] = dn[2];
+        wave_lds_sync();
         while (__ballot(pend) != 0ull) {
             if (pend) {
                 double X[3], V[3];
-                dense_state(p.rc, St.x0, St.v0, St.F0, D, h, (tob[kobs] - ts) / h, X, V);
+                dense_state_rows(dcoef, xg, St.x0, St.v0, St.F0, h, (tob[kobs] - ts) / h, X, V);
                 store_obs(kobs, X, V);
                 ++kobs;
             }
             pend = pending();
         }
     };
-    if (valid) save_ckpt_g8(p, 0, j, gl, S);
-    for (int c = 0; c < p.n_ckpt; ++c) {
-        for (int w = p.seg_win[c]; w < p.seg_win[c + 1]; ++w) {
-            const Window W = p.win[w];
-            __syncthreads();
-            stage_window(E, W.seg_lo, W.seg_hi, bstride, lane, 64, coefL);
-            __syncthreads();
-            g8_integrate<NB, NGR, DEG1, kGroup, kStartExtrapolateHeld>(p, R, node, gl, lane / kGroup, lane, coefL, bstride, e8,
-                                                      W.seg_lo, W.seg_hi, W.t_b, S, C, visit);
-        }
-        if (valid) save_ckpt_g8(p, c + 1, j, gl, S);
+    if (valid) save_ckpt_g8(p, 0, j, gl, S, S.t);
+    // windows on the fixed grid (aligned_window), so a recompute that starts
+    // at a checkpoint cuts its steps where this run did
+    const int wsegs = p.max_win_segs - 1;
+    int lo = 1, hi = 0;                          // nothing staged yet
+    while (S.t < p.t_end) {
+        const Window W = aligned_window(S.t, p.t_end, E.t_start, E.seg_days, E.inv_seg, E.n_seg, wsegs);
+        ensure_window(E, W.seg_lo, W.seg_hi, lo, hi, coefL, bstride);
+        g8_integrate<NB, NGR, DEG1, kGroup, kStartExtrapolateHeld>(p, R, node, gl, lane / kGroup, lane, coefL, bstride,
+                                                                   e8, lo, hi, W.t_b, S, C, visit);
     }
+    // checkpoints no step start reached: the end state
+    for (; c_next <= p.n_ckpt; ++c_next)
+        if (valid) save_ckpt_g8(p, c_next, j, gl, S, p.t_end);
     if (valid && gl == 0) p.status[j] = S.status;
 }
 
@@ -354,35 +378,44 @@ __device__ __forceinline__ void fill_node_rows(const RadauConst& rc, int tid, No
 }
 
 // Backward, first half for checkpoint segment c: recompute the segment from
-// its checkpoint with the forward's grouping and step sequence, storing
-// each step's data and this lane's node Jacobians (lane 7: node 0).  The
-// step count (plus kSegOverflow when the step store was too small) goes to
-// seg_ns[wave].
+// its checkpoint with the forward's grouping, windows and step sequence
+// (one wavefront per block: the checkpoints' times differ between
+// wavefronts), storing each step's start and size and this lane's node
+// Jacobians (lane 7: node 0).  The step count (plus kSegOverflow when the
+// step store was too small) goes to seg_ns[wave].
 constexpr int kSegOverflow = 1 << 30;
 static_assert(kAdjLanes == kGroup, "adjoint wavefronts hold 8 objects");
 
-template <int BLOCK, int NB, int NGR, int DEG1>
-__global__ __launch_bounds__(BLOCK, 2) void k_adj_recompute(const AdjParams p, const int c) {
+template <int NB, int NGR, int DEG1>
+__global__ __launch_bounds__(64, 2) void k_adj_recompute(const AdjParams p, const int c) {
     extern __shared__ double smem[];
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+    const int lane = threadIdx.x;
     const int gl = lane & (kGroup - 1);
     const int node = gl < 7 ? gl + 1 : 7;
     const int jnode = gl < 7 ? gl + 1 : 0;          // node whose Jacobians this lane keeps
     const EphemArgs& E = p.eph;
-    const int bstride = p.max_win_segs * 3 * E.deg1;
-    double* coefL = smem;
-    double* e8 = smem + (((size_t)E.n_body * bstride + 1) & ~(size_t)1) + (size_t)wid * g8_wave_doubles(E.n_body);
-    g8_table_init(E, lane, e8);
-    __shared__ NodeRow rows[kGroup];
-    fill_node_rows(p.rc, tid, rows);
-    __syncthreads();
-    const NodeRow& R = rows[gl];
-    const long wave = (long)blockIdx.x * (BLOCK / kWave) + wid;
+    const long wave = blockIdx.x;
     const long gi_raw = wave * kGroup + lane / kGroup;
     const bool valid = gi_raw < p.n_obj;
     const size_t gi = valid ? (size_t)gi_raw : 0;   // scratch slot (invalid groups read slot 0, never write)
     const int j = valid ? p.perm[gi] : 0;
     const size_t N = p.n_obj;
+    // this checkpoint's time and the next one's (the same for every object
+    // of the wavefront); a segment with no step start stores nothing
+    const double t_c = groups_max(valid ? p.ckpt[((size_t)c * N + j) * kCkptDoubles + 34] : -kInf);
+    const double t_stop = groups_max(valid ? p.ckpt[((size_t)(c + 1) * N + j) * kCkptDoubles + 34] : -kInf);
+    if (!(t_c < t_stop)) {
+        if (lane == 0) p.seg_ns[wave] = 0;
+        return;                                     // the whole block: one wavefront
+    }
+    const int bstride = p.max_win_segs * 3 * E.deg1;
+    double* coefL = smem;
+    double* e8 = smem + (((size_t)E.n_body * bstride + 1) & ~(size_t)1);
+    g8_table_init(E, lane, e8);
+    __shared__ NodeRow rows[kGroup];
+    fill_node_rows(p.rc, lane, rows);
+    __syncthreads();
+    const NodeRow& R = rows[gl];
     bool overflow_steps = false;
     G8State S;
     init_lane_state(p, false, j, S);
@@ -403,7 +436,7 @@ __global__ __launch_bounds__(BLOCK, 2) void k_adj_recompute(const AdjParams p, c
     S.hw = groups_max(valid ? hw : 0.0);        // the same value in every valid group
     S.hprev = groups_max(hprev);                // likewise (invalid groups give -inf)
     S.haveF0 = __ballot(have_f0) != 0ull;       // as in the forward at this checkpoint
-    S.t = p.win[p.seg_win[c]].t_a;
+    S.t = t_c;
     G8Count Cn;
     int ns = 0;
         auto store = [&](double ts, double h, const double dn[3], const G8State& St) {
@@ -437,13 +470,15 @@ __global__ __launch_bounds__(BLOCK, 2) void k_adj_recompute(const AdjParams p, c
             }
             ++ns;
         };
-    for (int w = p.seg_win[c]; w < p.seg_win[c + 1]; ++w) {
-        const Window W = p.win[w];
-        __syncthreads();
-        stage_window(E, W.seg_lo, W.seg_hi, bstride, tid, BLOCK, coefL);
-        __syncthreads();
-        g8_integrate<NB, NGR, DEG1, kGroup, kStartExtrapolateHeld>(p, R, node, gl, lane / kGroup, lane, coefL, bstride, e8, W.seg_lo,
-                                                  W.seg_hi, W.t_b, S, Cn, store, true);
+    // the forward's windows (aligned_window) from the checkpoint on, until
+    // the step start where the forward took the next checkpoint
+    const int wsegs = p.max_win_segs - 1;
+    int lo = 1, hi = 0;                          // nothing staged yet
+    while (S.t < t_stop) {
+        const Window W = aligned_window(S.t, p.t_end, E.t_start, E.seg_days, E.inv_seg, E.n_seg, wsegs);
+        ensure_window(E, W.seg_lo, W.seg_hi, lo, hi, coefL, bstride);
+        g8_integrate<NB, NGR, DEG1, kGroup, kStartExtrapolateHeld>(p, R, node, gl, lane / kGroup, lane, coefL, bstride,
+                                                                   e8, lo, hi, W.t_b, S, Cn, store, true, t_stop);
     }
     if (lane == 0 && wave * kGroup < p.n_obj) p.seg_ns[wave] = min(ns, p.s_max) | (overflow_steps ? kSegOverflow : 0);
 }
@@ -676,9 +711,46 @@ size_t adjoint_lds_bytes(const AdjParams& p) {
             (size_t)g8_wave_doubles(p.eph.n_body)) * sizeof(double);
 }
 
-// The backward recompute runs kAdjBlock threads per block: its wavefronts
-// share the staged Chebyshev window.
-constexpr int kAdjBlock = 128;
+
+// A second stream per device for the backward recomputes: created once, at
+// the default priority, not synchronizing with the null stream.
+static hipError_t aux_stream(hipStream_t* out) {
+    static std::mutex m;
+    static hipStream_t st[64] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(m);
+    if (!st[dev] && (e = hipStreamCreateWithFlags(&st[dev], hipStreamNonBlocking)) != hipSuccess) return e;
+    *out = st[dev];
+    return hipSuccess;
+}
+
+// The backward's five ordering events, created once per host thread and
+// recorded again by every call (a wait uses the record made before it).
+struct AdjEvents {
+    hipEvent_t ev[5] = {};
+    int next = 0;
+};
+static thread_local AdjEvents g_adj_events;
+static hipError_t pooled_event(hipEvent_t* out) {
+    AdjEvents& a = g_adj_events;
+    const int i = a.next++ % 5;
+    if (!a.ev[i]) {
+        const hipError_t e = hipEventCreateWithFlags(&a.ev[i], hipEventDisableTiming);
+        if (e != hipSuccess) return e;
+    }
+    *out = a.ev[i];
+    return hipSuccess;
+}
+
+// The dense-output rows of the constants into device memory for the forward.
+__global__ void k_adj_dense_coef(const AdjParams p) {
+    const int i = threadIdx.x;
+    if (i < 56) p.dense_coef[i] = p.rc.Ap[i / 8][i % 8];
+    else if (i < kDenseCoefDoubles) p.dense_coef[i] = p.rc.Bp[(i - 56) / 8][(i - 56) % 8];
+}
 
 hipError_t launch_adjoint(const AdjParams& p, int mode, hipStream_t s) {
     const int64_t waves = ((int64_t)p.n_obj + kGroup - 1) / kGroup;
@@ -689,6 +761,7 @@ hipError_t launch_adjoint(const AdjParams& p, int mode, hipStream_t s) {
     const size_t lds = adjoint_lds_bytes(p);
     const int nb = p.eph.n_body, ngr = p.eph.n_gr, d1 = p.eph.deg1;
     if (mode == KETE_ADJ_FWD) {
+        hipLaunchKernelGGL(k_adj_dense_coef, dim3(1), dim3(128), 0, s, p);
         if (nb == 9 && ngr == 3 && d1 == 13) hipLaunchKernelGGL((k_adjoint_fwd<9, 3, 13>), dim3(grid), dim3(64), lds, s, p);
         else if (nb == 3 && ngr == 2 && d1 == 13)
             hipLaunchKernelGGL((k_adjoint_fwd<3, 2, 13>), dim3(grid), dim3(64), lds, s, p);
@@ -698,17 +771,50 @@ hipError_t launch_adjoint(const AdjParams& p, int mode, hipStream_t s) {
     }
     if (n_o > 0) hipLaunchKernelGGL(k_obs_vjp, dim3(go), dim3(256), 0, s, p);
     hipLaunchKernelGGL(k_adj_tables, dim3(1), dim3(64), 0, s, p);
-    constexpr int wpb = kAdjBlock / kWave;
-    const int rgrid = (int)((waves + wpb - 1) / wpb);
-    const size_t rlds = ((((size_t)nb * p.max_win_segs * 3 * d1 + 1) & ~(size_t)1) +
-                         (size_t)wpb * g8_wave_doubles(nb)) * sizeof(double);
-    for (int c = p.n_ckpt - 1; c >= 0; --c) {
+    // The sweeps run on s, last segment first.  The recompute of segment c
+    // needs only its checkpoint, so it runs on a second stream ahead of the
+    // sweeps, into one of two step stores: the store of segment c is free
+    // once the sweep of segment c + 2 has read it.
+    hipStream_t r = nullptr;
+    hipError_t e;
+    if ((e = aux_stream(&r)) != hipSuccess) return e;
+    const int C = p.n_ckpt;
+    hipEvent_t ready[2] = {nullptr, nullptr}, freed[2] = {nullptr, nullptr}, start = nullptr;
+    g_adj_events.next = 0;
+    if ((e = pooled_event(&start)) != hipSuccess) return e;
+    for (int b = 0; b < 2; ++b) {
+        if ((e = pooled_event(&ready[b])) != hipSuccess || (e = pooled_event(&freed[b])) != hipSuccess) return e;
+    }
+    // the recomputes start after everything already queued on s (the forward's checkpoints)
+    if ((e = hipEventRecord(start, s)) != hipSuccess || (e = hipStreamWaitEvent(r, start, 0)) != hipSuccess) return e;
+    const size_t store = (size_t)p.s_max * kStepRecDoubles * p.n_obj;
+    const size_t ns_len = (size_t)((p.n_obj + kAdjLanes - 1) / kAdjLanes);
+    auto in_store = [&](int b) {
+        AdjParams q = p;
+        q.steps = p.steps + b * store;
+        q.jac = q.steps + (size_t)p.s_max * kStepDoubles * p.n_obj;
+        q.seg_ns = p.seg_ns + b * ns_len;
+        return q;
+    };
+    auto recompute = [&](int c) -> hipError_t {
+        const int b = c & 1;
+        if (c + 2 < C && (e = hipStreamWaitEvent(r, freed[b], 0)) != hipSuccess) return e;
+        const AdjParams q = in_store(b);
         if (nb == 9 && ngr == 3 && d1 == 13)
-            hipLaunchKernelGGL((k_adj_recompute<kAdjBlock, 9, 3, 13>), dim3(rgrid), dim3(kAdjBlock), rlds, s, p, c);
+            hipLaunchKernelGGL((k_adj_recompute<9, 3, 13>), dim3(grid), dim3(64), lds, r, q, c);
         else if (nb == 3 && ngr == 2 && d1 == 13)
-            hipLaunchKernelGGL((k_adj_recompute<kAdjBlock, 3, 2, 13>), dim3(rgrid), dim3(kAdjBlock), rlds, s, p, c);
-        else hipLaunchKernelGGL((k_adj_recompute<kAdjBlock, 0, 0, 0>), dim3(rgrid), dim3(kAdjBlock), rlds, s, p, c);
-        hipLaunchKernelGGL(k_adj_sweep, dim3(grid), dim3(64), 0, s, p, c);
+            hipLaunchKernelGGL((k_adj_recompute<3, 2, 13>), dim3(grid), dim3(64), lds, r, q, c);
+        else hipLaunchKernelGGL((k_adj_recompute<0, 0, 0>), dim3(grid), dim3(64), lds, r, q, c);
+        return hipEventRecord(ready[b], r);
+    };
+    if ((e = recompute(C - 1)) != hipSuccess) return e;
+    for (int c = C - 1; c >= 0; --c) {
+        const int b = c & 1;
+        if ((e = hipStreamWaitEvent(s, ready[b], 0)) != hipSuccess) return e;
+        // the next recompute is queued before this sweep, into the other store
+        if (c > 0 && (e = recompute(c - 1)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_adj_sweep, dim3(grid), dim3(64), 0, s, in_store(b), c);
+        if ((e = hipEventRecord(freed[b], s)) != hipSuccess) return e;
     }
     return hipGetLastError();
 }

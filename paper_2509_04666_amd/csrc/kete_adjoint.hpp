@@ -7,7 +7,7 @@
 namespace kete {
 
 // x[3], v[3], wave step, failed flag, force F0[3], F0 valid, the last accepted step's increments
-// at nodes 1..7 [7][3] and that step (0: none), 2 spare
+// at nodes 1..7 [7][3], that step (0: none), the checkpoint's time, 1 spare
 constexpr int kCkptDoubles = 36;
 constexpr int kAdjStateDoubles = 8; // lx[3], lv[3], next observation, overflow flag
 constexpr int kAdjLanes = 8;         // lanes per object in the adjoint kernels (8 objects per wavefront)
@@ -32,18 +32,19 @@ struct AdjParams {
     int32_t* status;            // [N]
     double* h_pref;             // [N]
     double* ckpt;               // [C+1][N][kCkptDoubles]
-    const Window* win;
-    const int32_t* seg_win;     // [C+1]: first window of each checkpoint segment
-    int32_t n_win;
+    double t_end;
+    double ckpt_days;           // checkpoint c: the first step start at or after t0 + c ckpt_days
     int32_t n_ckpt;             // C segments
+    int32_t pad_;
     double* obs_state;          // [N][K][6] states at the observation times (forward)
     double* obs_grad;           // [N][K][6] dL/d(state) at the observation times (backward)
     double* obs_hop;            // [N][K][2] light time and final universal anomaly (forward)
-    double* steps;              // [s_max][kStepDoubles][N]
+    double* steps;              // [s_max][kStepDoubles][N] (store 0; store 1 follows the Jacobians)
     double* jac;                // [s_max][kJacDoubles][N][8 nodes]: one object's nodes side by side
     double* adj_state;          // [N][kAdjStateDoubles] carried between backward segments
-    int32_t* seg_ns;            // [ceil(N / 8)] steps stored per wavefront in the current segment
+    int32_t* seg_ns;            // [2][ceil(N / 8)] steps stored per wavefront, per step store
     double* adj_tab;            // [kAdjTabDoubles] constant rows of the reverse sweep
+    double* dense_coef;         // [kDenseCoefDoubles] Ap, Bp of rc (written by the forward launch)
     int32_t s_max;
     int32_t max_win_segs;
     int32_t max_iter;

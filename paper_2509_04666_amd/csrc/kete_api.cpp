@@ -766,28 +766,22 @@ int kete_fov_check(const kete_ephem_t* eph, const double* x_epoch, const int32_t
     return KETE_OK;
 }
 
-static int adjoint_plan(const kete_ephem_t* eph, double t0, double t_end, double ckpt_days, int wsegs,
-                        std::vector<Window>& win, std::vector<int32_t>& seg_win) {
+// Checkpoint segments of the adjoint: C = ceil((t_end - t0) / ckpt_days).
+// The kernels plan their own windows (aligned_window) and take checkpoint c
+// at the first step start at or after t0 + c ckpt_days.
+static int adjoint_plan(const kete_ephem_t* eph, double t0, double t_end, double ckpt_days, int64_t& C) {
     if (!std::isfinite(t0) || !std::isfinite(t_end) || !(t_end > t0))
         return fail(KETE_EINVAL, "need finite t0 < t_end");
     if (!(ckpt_days > 0) || !std::isfinite(ckpt_days)) return fail(KETE_EINVAL, "ckpt_days must be positive");
     const double tlo = eph->t_start, thi = t_end_of(eph);
     if (!(t0 >= tlo && t_end <= thi)) return fail(KETE_ERANGE, "[t0, t_end] outside the ephemeris");
-    const int64_t C = (int64_t)std::ceil((t_end - t0) / ckpt_days - 1e-12);
+    C = (int64_t)std::ceil((t_end - t0) / ckpt_days - 1e-12);
     if (C < 1 || C > 1000000) return fail(KETE_EINVAL, "bad checkpoint count");
-    std::vector<double> tc(C);
-    for (int64_t c = 0; c < C; ++c) tc[c] = (c == C - 1) ? t_end : t0 + (c + 1) * ckpt_days;
-    std::vector<int> ew;
-    win = plan_windows(eph, t0, tc.data(), C, wsegs, ew);
-    seg_win.assign(C + 1, 0);
-    for (int64_t c = 1; c <= C; ++c) seg_win[c] = ew[c - 1] + 1;
     return KETE_OK;
 }
 
 static int adj_steps(const kete_opts_t* o) { return o->adj_seg_steps > 0 ? std::min(o->adj_seg_steps, 4096) : 32; }
 
-// Windows of the adjoint plan: at most 64 per checkpoint segment.
-static int64_t adjoint_max_windows(int64_t n_ckpt) { return 64 * (n_ckpt + 1) + 16; }
 
 size_t kete_adjoint_workspace_size(int64_t n_obj, int32_t k_obs, double t0, double t_end, double ckpt_days,
                                    const kete_opts_t* opts) {
@@ -799,17 +793,16 @@ size_t kete_adjoint_workspace_size(int64_t n_obj, int32_t k_obs, double t0, doub
     Carver c{nullptr};
     c.take<int32_t>((size_t)n_obj);                                   // perm
     c.take<double>((size_t)n_obj);                                    // h_pref
-    c.take<Window>((size_t)adjoint_max_windows(C));
-    c.take<int32_t>((size_t)C + 1);
     c.take<double>((size_t)(C + 1) * n_obj * kCkptDoubles);
-    c.take<double>((size_t)adj_steps(opts) * kStepRecDoubles * n_obj);
+    c.take<double>((size_t)2 * adj_steps(opts) * kStepRecDoubles * n_obj);   // two step stores
     c.take<double>((size_t)n_obj * std::max(0, k_obs) * 6);    // observation states
     c.take<double>((size_t)n_obj * std::max(0, k_obs) * 6);    // observation cotangents
     c.take<double>((size_t)n_obj * std::max(0, k_obs) * 2);    // light times and anomalies
     c.take<int32_t>(bucket_scratch_ints(n_obj, nbk));
     c.take<double>((size_t)n_obj * kAdjStateDoubles);                 // carried backward state
-    c.take<int32_t>((size_t)(n_obj + kAdjLanes - 1) / kAdjLanes);           // steps per wavefront
+    c.take<int32_t>((size_t)2 * ((n_obj + kAdjLanes - 1) / kAdjLanes));     // steps per wavefront, per store
     c.take<double>((size_t)kAdjTabDoubles);                           // reverse-sweep constants
+    c.take<double>((size_t)kDenseCoefDoubles);                        // dense-output rows
     return c.off;
 }
 
@@ -827,16 +820,14 @@ int kete_propagate_adjoint(const kete_ephem_t* eph, int32_t mode, const double* 
     if (rc) return rc;
     if (mode != KETE_ADJ_FWD && mode != KETE_ADJ_BWD) return fail(KETE_EINVAL, "mode must be KETE_ADJ_FWD or KETE_ADJ_BWD");
     if (n_obj < 0 || n_obj > KETE_MAX_OBJ || k_obs < 0) return fail(KETE_EINVAL, "bad sizes");
-    std::vector<Window> win;
-    std::vector<int32_t> seg_win;
-    if ((rc = adjoint_plan(eph, t0, t_end, ckpt_days, segs_or(opts, 2), win, seg_win))) return rc;
+    int64_t C = 0;
+    if ((rc = adjoint_plan(eph, t0, t_end, ckpt_days, C))) return rc;
     if (n_obj == 0) return KETE_OK;
     if (!x0 || !status || (k_obs > 0 && (!t_obs || !obs_pos))) return fail(KETE_EINVAL, "null pointer");
     if (mode == KETE_ADJ_FWD && k_obs > 0 && !sky_out) return fail(KETE_EINVAL, "sky_out is null");
     if (mode == KETE_ADJ_BWD && (!grad_x0 || (k_obs > 0 && !dL_dsky))) return fail(KETE_EINVAL, "null gradient pointer");
     if (!(opts->eps > 0) || !(opts->h_init > 0) || !(opts->h_min > 0) || opts->max_iter < 1 || opts->max_steps < 1)
         return fail(KETE_EINVAL, "eps, h_init, h_min, max_iter and max_steps must be positive");
-    const int64_t C = (int64_t)seg_win.size() - 1;
     const int nbk = std::min(std::max(1, opts->n_buckets), 32);
     if (!workspace) return fail(KETE_EWORKSPACE, "workspace is null");
     const size_t need = kete_adjoint_workspace_size(n_obj, k_obs, t0, t_end, ckpt_days, opts);
@@ -844,24 +835,18 @@ int kete_propagate_adjoint(const kete_ephem_t* eph, int32_t mode, const double* 
     Carver c{(char*)workspace};
     int32_t* perm = c.take<int32_t>((size_t)n_obj);
     double* h_pref = c.take<double>((size_t)n_obj);
-    const size_t max_win = (size_t)adjoint_max_windows(C);
-    if (win.size() > max_win) return fail(KETE_EINVAL, "too many integration windows (ckpt_days spans too many segments)");
-    Window* dwin = c.take<Window>(max_win);
-    int32_t* dseg = c.take<int32_t>((size_t)C + 1);
     double* ckpt = c.take<double>((size_t)(C + 1) * n_obj * kCkptDoubles);
-    double* scratch = c.take<double>((size_t)adj_steps(opts) * kStepRecDoubles * n_obj);
+    double* scratch = c.take<double>((size_t)2 * adj_steps(opts) * kStepRecDoubles * n_obj);
     double* obs_state = c.take<double>((size_t)n_obj * k_obs * 6);
     double* obs_grad = c.take<double>((size_t)n_obj * k_obs * 6);
     double* obs_hop = c.take<double>((size_t)n_obj * k_obs * 2);
     int32_t* bscratch = c.take<int32_t>(bucket_scratch_ints(n_obj, nbk));
     double* adj_state = c.take<double>((size_t)n_obj * kAdjStateDoubles);
-    int32_t* seg_ns = c.take<int32_t>((size_t)(n_obj + kAdjLanes - 1) / kAdjLanes);
+    int32_t* seg_ns = c.take<int32_t>((size_t)2 * ((n_obj + kAdjLanes - 1) / kAdjLanes));
     double* adj_tab = c.take<double>((size_t)kAdjTabDoubles);
+    double* dense_coef = c.take<double>((size_t)kDenseCoefDoubles);
 
     hipStream_t s = (hipStream_t)stream;
-    HIPCHK(hipMemcpyAsync(dwin, win.data(), win.size() * sizeof(Window), hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(dseg, seg_win.data(), seg_win.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    HIPCHK(hipStreamSynchronize(s));
 
     AdjParams P;
     std::memset(&P, 0, sizeof(P));
@@ -880,9 +865,8 @@ int kete_propagate_adjoint(const kete_ephem_t* eph, int32_t mode, const double* 
     P.status = status;
     P.h_pref = h_pref;
     P.ckpt = ckpt;
-    P.win = dwin;
-    P.seg_win = dseg;
-    P.n_win = (int32_t)win.size();
+    P.t_end = t_end;
+    P.ckpt_days = ckpt_days;
     P.n_ckpt = (int32_t)C;
     P.obs_state = obs_state;
     P.obs_grad = obs_grad;
@@ -893,7 +877,8 @@ int kete_propagate_adjoint(const kete_ephem_t* eph, int32_t mode, const double* 
     P.adj_state = adj_state;
     P.seg_ns = seg_ns;
     P.adj_tab = adj_tab;
-    P.max_win_segs = segs_or(opts, 2) + 1;
+    P.dense_coef = dense_coef;
+    P.max_win_segs = segs_or(opts, 3) + 1;      // the adjoint's own windows: 3 segments (auto)
     P.max_iter = opts->max_iter;
     P.max_steps = opts->max_steps;
     P.zero_start = opts->zero_start != 0;

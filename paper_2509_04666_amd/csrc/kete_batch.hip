@@ -60,15 +60,6 @@ __global__ __launch_bounds__(256) void k_job_bucket(const BatchParams p) {
     }
 }
 
-// Stage segments lo..hi into LDS unless they are already there.
-__device__ __forceinline__ void ensure_window(const EphemArgs& E, int a, int b, int& lo, int& hi, double* coefL,
-                                              int bstride) {
-    if (a >= lo && b <= hi) return;
-    __syncthreads();
-    stage_window(E, a, b, bstride, threadIdx.x, 64, coefL);
-    __syncthreads();
-    lo = a; hi = b;
-}
 
 // One wavefront per block; it pops tiles of KETE_BATCH_TILE bodies of one
 // job and integrates them as lane groups (one lane per collocation node,

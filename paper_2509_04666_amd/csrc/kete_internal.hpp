@@ -87,6 +87,28 @@ __host__ __device__ inline Window next_window(double t, double target, double t_
     return W;
 }
 
+// The same, forward in time only, with the window ends on a fixed grid:
+// multiples of w segments from t_start (or the target).  A run that resumes
+// inside a window (from a checkpoint) then ends its windows where the first
+// run did, so both cut their steps at the same times.
+__host__ __device__ inline Window aligned_window(double t, double target, double t_start, double seg_days,
+                                                 double inv_seg, int n_seg, int w) {
+    const double kk = floor((t - t_start) * inv_seg);
+    double limit = t_start + (floor(kk / w) + 1.0) * w * seg_days;
+    if (!(limit > t)) limit += w * seg_days;
+    Window W;
+    W.t_a = t;
+    W.t_b = limit < target ? limit : target;
+    const int lo = seg_clamped(t, t_start, inv_seg, n_seg);
+    int hi = seg_clamped(W.t_b, t_start, inv_seg, n_seg);
+    if (hi - lo > w) hi = lo + w;
+    W.seg_lo = lo;
+    W.seg_hi = hi;
+    W.out = -1;
+    W.pad = 0;
+    return W;
+}
+
 struct NbodyParams {
     EphemArgs eph;
     RadauConst rc;

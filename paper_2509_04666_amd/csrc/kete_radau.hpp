@@ -151,6 +151,17 @@ __device__ __forceinline__ void stage_window(const EphemArgs& E, int seg_lo, int
     }
 }
 
+// Stage segments a..b into LDS unless they are already there (one
+// wavefront per block: lanes 0..63 copy).
+__device__ __forceinline__ void ensure_window(const EphemArgs& E, int a, int b, int& lo, int& hi, double* coefL,
+                                              int bstride) {
+    if (a >= lo && b <= hi) return;
+    __syncthreads();
+    stage_window(E, a, b, bstride, threadIdx.x, 64, coefL);
+    __syncthreads();
+    lo = a; hi = b;
+}
+
 // The collocation corrector: fixed-point sweeps over the 7 nodes
 // (Gauss-Seidel: each node sees the increments already updated) until the
 // change of b6 relative to |a| is below 1e-16, stops decreasing after the
@@ -778,13 +789,15 @@ template <int NB, int NGR, int DEG1, int G, int START = kStartZero, class Params
 __device__ __forceinline__ void g8_integrate(const Params& p, const NodeRow& R, int node, int gl, int grp, int lane,
                                              const double* __restrict__ coefL, int bstride, double* __restrict__ e8,
                                              int seg_lo, int seg_hi, double tb, G8State& S, G8Count& C,
-                                             Visit&& visit = Visit(), bool need_node0 = false) {
+                                             Visit&& visit = Visit(), bool need_node0 = false,
+                                             double t_stop = kInf) {
     const EphemArgs& E = p.eph;
     const RadauConst& rc = p.rc;
     const int nb = E.n_body;
     double* xg = g8_xch(e8, nb, grp);
     if (__ballot(S.active) == 0ull) { S.t = tb; return; }
     while (S.t != tb) {
+        if (S.t >= t_stop) return;          // a recompute ends where the recorded run took its checkpoint
         const double dir = tb > S.t ? 1.0 : -1.0;
         double hmag = S.hw;
         if (p.h_max > 0.0 && hmag > p.h_max) hmag = p.h_max;
@@ -899,6 +912,41 @@ __device__ __forceinline__ void dense_state(const RadauConst& rc, const double x
         for (int m = 0; m < 7; ++m) { ax = fma(al[m], D[m][c], ax); av = fma(be[m], D[m][c], av); }
         X[c] = fma(hh, ax, fma(sig * h, v0[c], x0[c]));
         V[c] = fma(h, av, v0[c]);
+    }
+}
+
+// dense_state with the monomial rows read from a copy in LDS (cw: Ap[7][8]
+// then Bp[7][8]) rather than from the kernel's argument block, and the
+// step's node increments from the group's exchange rows xg (component c of
+// node m + 1 at xg[8 c + m]), one node at a time; sig may differ between
+// groups.
+__device__ __forceinline__ void dense_state_rows(const double* __restrict__ cw, const double* __restrict__ xg,
+                                                 const double x0[3], const double v0[3], const double F0[3],
+                                                 double h, double sig, double X[3], double V[3]) {
+    double ax[3], av[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) { ax[c] = 0.5 * sig * sig * F0[c]; av[c] = sig * F0[c]; }
+#pragma unroll 1
+    for (int m = 0; m < 7; ++m) {
+        const double* am = cw + 8 * m;
+        const double* bm = cw + 56 + 8 * m;
+        double a = am[7], b = bm[7];
+#pragma unroll
+        for (int k = 6; k >= 0; --k) { a = fma(a, sig, am[k]); b = fma(b, sig, bm[k]); }
+        a *= sig * sig;
+        b *= sig;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double d = xg[8 * c + m];
+            ax[c] = fma(a, d, ax[c]);
+            av[c] = fma(b, d, av[c]);
+        }
+    }
+    const double hh = h * h;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        X[c] = fma(hh, ax[c], fma(sig * h, v0[c], x0[c]));
+        V[c] = fma(h, av[c], v0[c]);
     }
 }
 
