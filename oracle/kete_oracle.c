@@ -24,7 +24,8 @@
  *   - brute-force field-of-view membership: inside iff every inward normal
  *     has a positive dot product with the object direction (Sect. 3.1);
  *   - forward-mode variational equations (6x6 state transition matrix)
- *     and the sky-residual loss gradient built from them.
+ *     and the sky-residual loss gradient built from them;
+ *   - apparent V magnitude per pair in the H-G system (Sect. 3.3).
  *
  * Compile with -O2 -ffp-contract=off (no fast-math).  OpenMP, when
  * enabled, only distributes independent objects over threads.
@@ -855,6 +856,65 @@ int orc_inside(int32_t n_sub, const double *normals, const double d[3], int32_t 
         if (edge) edge[s] = asin(mn);
     }
     return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Apparent V magnitude in the H-G system (Sect. 3.3: optical           */
+/* magnitudes follow Bowell et al. 1989, the MPC and Horizons form).    */
+/* ------------------------------------------------------------------ */
+
+/* V = H + 5 log10(r_H Delta) - 2.5 log10((1 - G) Phi_1 + G Phi_2), with
+ * Phi_i = exp(-A_i tan(alpha/2)^B_i), A = (3.33, 1.87), B = (0.63, 1.22);
+ * r_H and Delta in au, alpha the phase angle in radians. */
+double orc_hg_mag(double H, double G, double r_h, double delta, double alpha)
+{
+    double t = tan(0.5 * alpha);
+    double phi1 = exp(-3.33 * pow(t, 0.63));
+    double phi2 = exp(-1.87 * pow(t, 1.22));
+    return H + 5.0 * log10(r_h * delta) - 2.5 * log10((1.0 - G) * phi1 + G * phi2);
+}
+
+/* Magnitude of every pair (frame pf[i], object po[i]): the emission point
+ * of the object seen from the frame's observer (orc_lighttime from the
+ * state x_epoch[b][j] of the frame's batch b), r = emission point less the
+ * Sun at the emission time, d = emission point less the observer;
+ * r_H = |r|, Delta = |d|, phase angle alpha = angle between -r and -d
+ * (object to Sun, object to observer), taken here by acos of the cosine.
+ * geom (optional) receives {r_H, Delta, alpha} per pair. */
+int orc_pair_mags(const orc_ephem *E, double c_light, int64_t n_obj, const double *x_epoch,
+                  int64_t n_batch, const double *t_ref, const int64_t *batch_off, const int64_t *frame_order,
+                  int64_t n_frames, const double *frames_t, const double *frames_obs,
+                  int64_t n_pairs, const int32_t *pf, const int32_t *po, const double *H, const double *G,
+                  double *v_mag, double *geom)
+{
+    int64_t *fb = malloc(sizeof(int64_t) * (size_t)(n_frames > 0 ? n_frames : 1));
+    if (!fb) return ORC_EINVAL;
+    for (int64_t f = 0; f < n_frames; f++) fb[f] = -1;
+    for (int64_t b = 0; b < n_batch; b++)
+        for (int64_t q = batch_off[b]; q < batch_off[b + 1]; q++) fb[frame_order[q]] = b;
+    int rc = ORC_OK;
+    for (int64_t i = 0; i < n_pairs; i++) {
+        int64_t f = pf[i], j = po[i];
+        if (f < 0 || f >= n_frames || j < 0 || j >= n_obj || fb[f] < 0) { rc = ORC_EINVAL; break; }
+        int64_t b = fb[f];
+        double d[3], tau, xe[6], S[3], Sd[3];
+        int st = orc_lighttime(E, c_light, t_ref[b], x_epoch + 6 * (b * n_obj + j), frames_t[f],
+                               frames_obs + 3 * f, d, &tau, xe);
+        if (!st) st = orc_cheb(E, 0, frames_t[f] - tau, S, Sd);
+        if (st) {
+            v_mag[i] = NAN;
+            if (geom) geom[3 * i] = geom[3 * i + 1] = geom[3 * i + 2] = NAN;
+            continue;
+        }
+        double r[3] = { xe[0] - S[0], xe[1] - S[1], xe[2] - S[2] };
+        double rh = sqrt(dot3(r, r)), dl = sqrt(dot3(d, d));
+        double c = dot3(r, d) / (rh * dl);
+        double alpha = acos(c > 1.0 ? 1.0 : (c < -1.0 ? -1.0 : c));
+        v_mag[i] = orc_hg_mag(H[j], G[j], rh, dl, alpha);
+        if (geom) { geom[3 * i] = rh; geom[3 * i + 1] = dl; geom[3 * i + 2] = alpha; }
+    }
+    free(fb);
+    return rc;
 }
 
 /* State and 6x6 state transition matrix Phi[i][c] = d state_i(t1) / d state_c(t0)

@@ -249,6 +249,33 @@ def inside(normals, d):
     return ins.astype(bool), edge
 
 
+def hg_mag(H, G, r_h, delta, alpha):
+    """H-G apparent magnitude (Sect. 3.3) of one body from r_H, Delta (au), alpha (rad)."""
+    f = lib().orc_hg_mag
+    f.restype = C.c_double
+    return f(C.c_double(H), C.c_double(G), C.c_double(r_h), C.c_double(delta), C.c_double(alpha))
+
+
+def pair_mags(eph, x_epoch, frame_order, batch_off, t_ref, frames_t, frames_obs, pf, po, H, G,
+              c_light=C_AU_PER_DAY):
+    """V magnitude and {r_H, Delta, alpha} of every (frame, object) pair."""
+    e = _eph(eph)
+    x_epoch = _f64(x_epoch)
+    n_batch, n_obj = x_epoch.shape[:2]
+    pf = np.ascontiguousarray(pf, np.int32); po = np.ascontiguousarray(po, np.int32)
+    n = pf.size
+    v = np.zeros(n); geom = np.zeros((n, 3))
+    ft = _f64(frames_t)
+    rc = lib().orc_pair_mags(e.ref, C.c_double(c_light), C.c_int64(n_obj), _p(x_epoch), C.c_int64(n_batch),
+                             _p(_f64(t_ref)), _p(np.ascontiguousarray(batch_off, np.int64), C.c_int64),
+                             _p(np.ascontiguousarray(frame_order, np.int64), C.c_int64), C.c_int64(ft.size),
+                             _p(ft), _p(_f64(frames_obs)), C.c_int64(n), _p(pf, C.c_int32), _p(po, C.c_int32),
+                             _p(_f64(H)), _p(_f64(G)), _p(v), _p(geom))
+    if rc:
+        raise ValueError("oracle pair_mags: bad pair or frame")
+    return v, geom
+
+
 def stm(eph, x0, t0, t1, opts=None, **kw):
     """(state [6], Phi [6, 6]) at t1 from the variational equations."""
     e = _eph(eph)

@@ -271,6 +271,15 @@ def bodies_from_elements(model: PlanetModel, el: np.ndarray, epoch: float) -> np
     return st + model.sun(np.array(epoch))[None, :]
 
 
+def hg_params(rng: np.random.Generator, n: int) -> tuple[np.ndarray, np.ndarray]:
+    """Absolute magnitude H and slope G of n bodies for the H-G magnitude
+    system: H uniform in [8, 20] (numbered main-belt range), G normal
+    around the customary 0.15 (sigma 0.08) clipped to [-0.1, 0.6]."""
+    H = rng.uniform(8.0, 20.0, n)
+    G = np.clip(rng.normal(0.15, 0.08, n), -0.1, 0.6)
+    return H, G
+
+
 def make_population(rng, model, n, neo_frac, epoch):
     n_neo = int(round(n * neo_frac))
     el = np.concatenate([main_belt_elements(rng, n - n_neo), neo_elements(rng, n_neo)])

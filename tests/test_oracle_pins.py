@@ -395,6 +395,68 @@ def test_batching_rule(orc):
             assert order[i] > order[i - 1]
 
 
+# ---------------------------------------------------------------- magnitudes
+def test_hg_magnitude_closed_forms(orc):
+    ln10 = math.log(10.0)
+    rng = np.random.default_rng(30)
+    for _ in range(20):
+        H, G = rng.uniform(5, 20), rng.uniform(-0.1, 0.6)
+        r, d = rng.uniform(0.5, 5), rng.uniform(0.05, 6)
+        # zero phase: both phase functions are 1, only the distances remain
+        assert abs(orc.hg_mag(H, G, r, d, 0.0) - (H + 5 * math.log10(r) + 5 * math.log10(d))) < 1e-12
+    assert orc.hg_mag(7.25, 0.15, 1.0, 1.0, 0.0) == 7.25
+    # tan(alpha/2) = 1 fixes A1 (G = 0) and A2 (G = 1); tan(alpha/2) = 2 adds B1, B2
+    assert abs(orc.hg_mag(0.0, 0.0, 1, 1, math.pi / 2) - 2.5 * 3.33 / ln10) < 1e-12
+    assert abs(orc.hg_mag(0.0, 1.0, 1, 1, math.pi / 2) - 2.5 * 1.87 / ln10) < 1e-12
+    a2 = 2 * math.atan(2.0)
+    assert abs(orc.hg_mag(0.0, 0.0, 1, 1, a2) - 2.5 * 3.33 * 2 ** 0.63 / ln10) < 1e-12
+    assert abs(orc.hg_mag(0.0, 1.0, 1, 1, a2) - 2.5 * 1.87 * 2 ** 1.22 / ln10) < 1e-12
+
+
+def test_hg_magnitude_flux_linear_in_slope_and_monotone(orc):
+    # the reduced flux 10^(-0.4 (V - H)) at r = Delta = 1 is the G-weighted
+    # mix of two phase functions: affine in G; V grows with the phase angle
+    alphas = np.linspace(0.0, math.radians(120), 41)
+    for a in alphas[1:]:
+        fl = [10 ** (-0.4 * orc.hg_mag(0.0, g, 1, 1, a)) for g in (0.0, 0.3, 0.6)]
+        assert abs(fl[1] - 0.5 * (fl[0] + fl[2])) < 1e-14
+        assert 0 < fl[0] < 1 and 0 < fl[2] < 1
+    for g in (-0.1, 0.15, 0.6):
+        v = [orc.hg_mag(0.0, g, 1, 1, a) for a in alphas]
+        assert np.all(np.diff(v) > 0)
+
+
+def test_pair_magnitude_geometry(orc):
+    # over the pairs of a small survey: the phase angle is the angle at the
+    # body of the Sun-body-observer triangle (law of cosines with the
+    # Sun-observer distance taken from the ephemeris separately), Delta is
+    # c times the light time, r_H the body's distance from the Sun at
+    # emission, and V the H-G value at that geometry
+    case = synth.tiny_case(n_obj=300, n_frames=30, n_targeted=40)
+    fr = case.frames
+    order, off, t_ref = orc.make_batches(fr.t)
+    xe, st, _ = orc.propagate(case.ephem, case.x0, 0.0, t_ref)
+    pf, ps, po, _ = orc.fov(case.ephem, xe, st, order, off, t_ref, fr.t, fr.obs, fr.normals)
+    assert pf.size > 20
+    H, G = synth.hg_params(np.random.default_rng(31), case.x0.shape[0])
+    v, geom = orc.pair_mags(case.ephem, xe, order, off, t_ref, fr.t, fr.obs, pf, po, H, G)
+    fb = np.empty(fr.t.size, np.int64)
+    for b in range(t_ref.size):
+        fb[order[off[b]:off[b + 1]]] = b
+    for i in range(pf.size):
+        f, j = pf[i], po[i]
+        b = fb[f]
+        _, d, tau, x_emit = orc.lighttime(case.ephem, t_ref[b], xe[b, j], fr.t[f], fr.obs[f])
+        _, sun, _ = orc.cheb(case.ephem, 0, fr.t[f] - tau)
+        rh, dl, al = geom[i]
+        R = np.linalg.norm(np.asarray(sun) - fr.obs[f])
+        assert abs(dl - orc.C_AU_PER_DAY * tau) < 1e-12
+        assert abs(rh - np.linalg.norm(x_emit[:3] - np.asarray(sun))) < 1e-13
+        assert abs(math.cos(al) - (rh ** 2 + dl ** 2 - R ** 2) / (2 * rh * dl)) < 1e-12
+        assert abs(v[i] - orc.hg_mag(H[j], G[j], rh, dl, al)) < 1e-12
+    assert np.all(np.isfinite(v)) and geom[:, 2].max() < math.pi / 2
+
+
 # ---------------------------------------------------------------- variational
 def test_stm_symplectic_newtonian(orc):
     case = synth.survey_case(n_obj=4, n_frames=0, neo_frac=0.5)
