@@ -383,6 +383,28 @@ def main():
     ms_iso = np.zeros(4); cnt_iso = np.zeros(4, np.int64)
     _lib.check(L.kete_timing_read(ms_iso.ctypes.data_as(C.c_void_p), cnt_iso.ctypes.data_as(C.c_void_p)))
 
+    # H-G magnitudes of one step's pairs (Sect. 3.3), an epilogue timed on
+    # its own with events on the launching stream
+    hg_h, hg_g = synth.hg_params(np.random.default_rng(11), N)
+    hg_h, hg_g = torch.as_tensor(hg_h, device=dev), torch.as_tensor(hg_g, device=dev)
+    mb = api.Batches.from_host(order, off, t_ref, dev)
+    mx, mst = api.propagate(eph, x0, 0.0, t_ref, opts, workspace=ws[0][0])
+    mpf, _, mpo = api.fov_check(eph, mx, mb, frames, mst, opts, pairs_cap=cap, workspace=ws[0][1])
+    mws = torch.empty(L.kete_magnitudes_workspace_size(F), dtype=torch.uint8, device=dev)
+    v_mag = api.pair_magnitudes(eph, mx, mb, frames, mpf, mpo, hg_h, hg_g, opts=opts, workspace=mws)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    n_mag_reps = 5
+    ev0.record()
+    for _ in range(n_mag_reps):
+        api.pair_magnitudes(eph, mx, mb, frames, mpf, mpo, hg_h, hg_g, opts=opts, workspace=mws)
+    ev1.record()
+    torch.cuda.synchronize()
+    mag_ms = ev0.elapsed_time(ev1) / n_mag_reps
+    mag = {"pairs": int(mpf.numel()), "ms": mag_ms, "pairs_per_s": mpf.numel() / (mag_ms / 1e3),
+           "finite": bool(torch.isfinite(v_mag).all().item()),
+           "v_range": [float(v_mag.min().item()), float(v_mag.max().item())] if mpf.numel() else None}
+    del mx, mst, mpf, mpo, v_mag, mws
+
     ms_step = elapsed * 1e3 / args.steps
     obj_days = N * case.span
     value = obj_days / (ms_step / 1e3)
@@ -433,6 +455,7 @@ def main():
             "pairs": n_pairs, "fov_candidates": int(fst[0]), "fov_exact_tests": int(fst[1]),
             "fov_bruteforce_objects": int(fst[2]), "failed_objects": n_fail,
             "integrator_counters": st[:8].tolist(),
+            "magnitudes": mag,
         },
     }
     if not args.no_adjoint:

@@ -260,6 +260,37 @@ int kete_fov_check(const kete_ephem_t *eph, const double *x_epoch, const int32_t
  * records scanned by the per-cell join (per wavefront). */
 void kete_fov_last_stats(int64_t out[4]);
 
+/* Bytes of workspace needed by kete_pair_magnitudes (0 for a bad size). */
+size_t kete_magnitudes_workspace_size(int64_t n_frames);
+
+/* Apparent V magnitude of every (frame, object) pair in the H-G system
+ * (Sect. 3.3, which takes the system of Bowell et al. 1989):
+ *   V = H + 5 log10(r_H Delta) - 2.5 log10((1 - G) Phi_1 + G Phi_2),
+ *   Phi_i = exp(-A_i tan(alpha/2)^B_i), A = (3.33, 1.87), B = (0.63, 1.22),
+ * with r_H the body's distance from the Sun and Delta from the observer
+ * at the light-time corrected emission time (the hop of kete_fov_check
+ * from the state x_epoch[b][j] of the frame's batch b), and alpha the
+ * phase angle at the body between the Sun and the observer.
+ *   x_epoch, t_ref, batch_off, frame_order, frames: as for kete_fov_check
+ *               (the normals are not read)
+ *   pf, po      device [n_pairs]: frame and object of each pair, as
+ *               kete_fov_check returns them (any order)
+ *   h_mag       device [n_obj]: absolute magnitude H
+ *   g_slope     device [n_obj]: slope parameter G
+ *   v_mag       device out [n_pairs]
+ *   geom        device out [n_pairs][3] {r_H au, Delta au, alpha rad}, or NULL
+ * A pair whose frame is in no batch, whose indices are out of range or
+ * whose emission time leaves the ephemeris gets NaN; a hop that fails
+ * gives a non-finite value.  Like the membership test, the hop's value is
+ * used when its Kepler iteration stops on the iteration cap.
+ * Asynchronous on `stream`; the caller owns every buffer.
+ * Errors: KETE_EINVAL, KETE_EWORKSPACE, KETE_EDEVICE. */
+int kete_pair_magnitudes(const kete_ephem_t *eph, const double *x_epoch, int64_t n_obj, int64_t n_batch,
+                         const double *t_ref, const int32_t *batch_off, const int32_t *frame_order,
+                         const kete_frames_t *frames, const int32_t *pf, const int32_t *po, int64_t n_pairs,
+                         const double *h_mag, const double *g_slope, double *v_mag, double *geom,
+                         const kete_opts_t *opts, void *workspace, size_t ws_bytes, void *stream);
+
 /* Light-time corrected directions (the per-pair step of kete_fov_check,
  * exposed for checking): for every object j and query q, the direction
  * d = x_e - obs[q] of object j (state x_ref[j] at t_ref) at the emission

@@ -82,6 +82,11 @@ SIGNATURES = {
                                  C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(C.c_int64), C.c_void_p,
                                  C.c_size_t, C.c_void_p]),
     "kete_fov_last_stats": (None, [C.c_void_p]),
+    "kete_magnitudes_workspace_size": (C.c_size_t, [C.c_int64]),
+    "kete_pair_magnitudes": (C.c_int, [C.POINTER(EphemT), C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p,
+                                       C.c_void_p, C.POINTER(FramesT), C.c_void_p, C.c_void_p, C.c_int64,
+                                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(OptsT),
+                                       C.c_void_p, C.c_size_t, C.c_void_p]),
     "kete_lighttime_directions": (C.c_int, [C.POINTER(EphemT), C.c_void_p, C.c_double, C.c_int64, C.c_void_p,
                                             C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.POINTER(OptsT),
                                             C.c_void_p]),

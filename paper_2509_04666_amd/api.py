@@ -173,6 +173,29 @@ def fov_check(eph: DeviceEphemeris, x_epoch: torch.Tensor, batches: Batches, fra
     return out
 
 
+def pair_magnitudes(eph: DeviceEphemeris, x_epoch: torch.Tensor, batches: Batches, frames: DeviceFrames,
+                    pf: torch.Tensor, po: torch.Tensor, h_mag: torch.Tensor, g_slope: torch.Tensor,
+                    geometry: bool = False, opts: Optional[OptsT] = None, workspace: Optional[torch.Tensor] = None):
+    """H-G apparent V magnitude of every pair (pf[i], po[i]): a float64
+    tensor [P], plus {r_H, Delta, phase angle} [P, 3] with geometry=True."""
+    opts = opts or default_opts()
+    x_epoch = x_epoch.contiguous()
+    B, N = x_epoch.shape[0], x_epoch.shape[1]
+    P = pf.shape[0]
+    dev = x_epoch.device
+    v = torch.empty(P, dtype=torch.float64, device=dev)
+    geom = torch.empty((P, 3), dtype=torch.float64, device=dev) if geometry else None
+    need = lib().kete_magnitudes_workspace_size(frames.t.shape[0])
+    ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, dev)
+    fc = frames.c()
+    check(lib().kete_pair_magnitudes(C.byref(eph.c), _ptr(x_epoch), N, B, _ptr(batches.t_ref),
+                                     _ptr(batches.batch_off), _ptr(batches.frame_order), C.byref(fc),
+                                     _ptr(pf.contiguous()), _ptr(po.contiguous()), P, _ptr(h_mag.contiguous()),
+                                     _ptr(g_slope.contiguous()), _ptr(v), _ptr(geom), C.byref(opts), _ptr(ws),
+                                     ws.numel(), _stream()))
+    return (v, geom) if geometry else v
+
+
 def lighttime_directions(eph: DeviceEphemeris, x_ref: torch.Tensor, t_ref: float, t_obs: torch.Tensor,
                          obs: torch.Tensor, opts: Optional[OptsT] = None):
     """(d [Q, N, 3], tau [Q, N]) for states x_ref [N, 6] at t_ref."""

@@ -12,7 +12,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libkete_mi.so")
-SOURCES = ["kete_api.cpp", "kete_nbody.hip", "kete_fov.hip", "kete_scan.hip", "kete_adjoint.hip", "kete_batch.hip"]
+SOURCES = ["kete_api.cpp", "kete_nbody.hip", "kete_fov.hip", "kete_scan.hip", "kete_adjoint.hip", "kete_batch.hip", "kete_mag.hip"]
 ARCH = os.environ.get("KETE_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

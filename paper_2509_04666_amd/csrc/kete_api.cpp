@@ -17,6 +17,7 @@
 #include "kete_batch.hpp"
 #include "kete_fov.hpp"
 #include "kete_internal.hpp"
+#include "kete_mag.hpp"
 #include "kete_mi.h"
 
 namespace kete {
@@ -1432,6 +1433,67 @@ int kete_lighttime_directions(const kete_ephem_t* eph, const double* x_ref, doub
     P.lt_tol = opts->lt_tol > 0 ? opts->lt_tol : 1e-15;
     P.lt_iter = opts->lt_iter > 0 ? opts->lt_iter : 10;
     HIPCHK(launch_directions(P, x_ref, t_ref, t_obs, obs, n_q, d, tau, (hipStream_t)stream));
+    return KETE_OK;
+}
+
+size_t kete_magnitudes_workspace_size(int64_t n_frames) {
+    if (n_frames < 0 || n_frames > INT32_MAX) return 0;
+    return mag_workspace_bytes(n_frames);
+}
+
+int kete_pair_magnitudes(const kete_ephem_t* eph, const double* x_epoch, int64_t n_obj, int64_t n_batch,
+                         const double* t_ref, const int32_t* batch_off, const int32_t* frame_order,
+                         const kete_frames_t* frames, const int32_t* pf, const int32_t* po, int64_t n_pairs,
+                         const double* h_mag, const double* g_slope, double* v_mag, double* geom,
+                         const kete_opts_t* opts, void* workspace, size_t ws_bytes, void* stream) {
+    kete_opts_t dflt;
+    if (!opts) { kete_default_opts(&dflt); opts = &dflt; }
+    g_err.clear();
+    EphemArgs E;
+    const double cl = opts->c_light > 0 ? opts->c_light : kC;
+    int rc = ephem_args(eph, cl, E);
+    if (rc) return rc;
+    if (!frames) return fail(KETE_EINVAL, "frames is null");
+    if (n_obj < 0 || n_obj > KETE_MAX_OBJ) return fail(KETE_EINVAL, "n_obj %lld outside 0..%d", (long long)n_obj, KETE_MAX_OBJ);
+    if (n_batch < 0 || n_pairs < 0 || frames->n_frames < 0 || frames->n_frames > INT32_MAX)
+        return fail(KETE_EINVAL, "bad sizes");
+    if ((double)n_batch * (double)n_obj >= 2.0e9) return fail(KETE_EINVAL, "n_batch x n_obj must stay below 2^31");
+    if (n_pairs == 0) return KETE_OK;
+    if (!pf || !po || !h_mag || !g_slope || !v_mag) return fail(KETE_EINVAL, "null pointer");
+    const int64_t F = frames->n_frames;
+    if (n_obj > 0 && n_batch > 0 && F > 0 && (!x_epoch || !t_ref || !batch_off || !frame_order || !frames->t ||
+                                              !frames->obs))
+        return fail(KETE_EINVAL, "null pointer");
+    if (!workspace) return fail(KETE_EWORKSPACE, "workspace is null");
+    const size_t need = kete_magnitudes_workspace_size(F);
+    if (ws_bytes < need) return fail(KETE_EWORKSPACE, "workspace %zu bytes < %zu required", ws_bytes, need);
+    MagParams P;
+    std::memset(&P, 0, sizeof(P));
+    P.eph = E;
+    P.x_epoch = x_epoch;
+    P.n_obj = (int32_t)n_obj;
+    // with no bodies, batches or frames every pair is out of range: NaN
+    P.n_batch = (n_obj > 0 && F > 0) ? (int32_t)n_batch : 0;
+    P.n_frames = F;
+    P.t_ref = t_ref;
+    P.batch_off = batch_off;
+    P.frame_order = frame_order;
+    P.ft = frames->t;
+    P.fobs = frames->obs;
+    P.pf = pf;
+    P.po = po;
+    P.n_pairs = n_pairs;
+    P.h_mag = h_mag;
+    P.g_slope = g_slope;
+    P.v_mag = v_mag;
+    P.geom = geom;
+    P.smu = std::sqrt(E.gm[0]);
+    P.c_light = cl;
+    P.lt_tol = opts->lt_tol > 0 ? opts->lt_tol : 1e-15;
+    P.lt_iter = opts->lt_iter > 0 ? opts->lt_iter : 10;
+    P.t_lo = eph->t_start;
+    P.t_hi = t_end_of(eph);
+    HIPCHK(launch_pair_mag(P, workspace, (hipStream_t)stream));
     return KETE_OK;
 }
 

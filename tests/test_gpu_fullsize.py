@@ -115,6 +115,31 @@ def test_survey_full_size_sampled(torch_cuda, orc):
     n = _check_sampled(torch, api, orc, case, xg, sg, _pairs_of(torch, pairs, sample), order, off, t_ref, sample,
                        batches, "survey")
     assert n > 0
+    # H-G magnitudes of every pair, sampled bodies on the sampled batches against the oracle
+    fr = case.frames
+    H, G = synth.hg_params(np.random.default_rng(25), case.x0.shape[0])
+    b = api.Batches.from_host(order, off, t_ref)
+    pf, ps, po = pairs
+    v = api.pair_magnitudes(api.DeviceEphemeris.from_synth(case.ephem), xg, b, api.DeviceFrames.from_synth(fr),
+                            pf, po, _dev(torch, H), _dev(torch, G))
+    torch.cuda.synchronize()
+    pfh, poh, vh = pf.cpu().numpy(), po.cpu().numpy(), v.cpu().numpy()
+    bad = np.nonzero(~np.isfinite(vh))[0]
+    _say(f"survey: {bad.size} non-finite magnitudes; first (frame, body): "
+         f"{list(zip(pfh[bad[:5]].tolist(), poh[bad[:5]].tolist()))}")
+    assert bad.size == 0
+    loc = np.full(case.x0.shape[0], -1, np.int64)
+    loc[sample] = np.arange(sample.size)
+    in_b = np.zeros(fr.t.size, bool)
+    for bb in batches:
+        in_b[order[off[bb]:off[bb + 1]]] = True
+    keep = (loc[poh] >= 0) & in_b[pfh]
+    xo, _, _ = orc.propagate(case.ephem, case.x0[sample], case.t0, t_ref)
+    ov, _ = orc.pair_mags(case.ephem, xo, order, off, t_ref, fr.t, fr.obs, pfh[keep], loc[poh[keep]], H[sample],
+                          G[sample])
+    dv = np.abs(vh[keep] - ov).max()
+    _say(f"survey: magnitudes of {vh.size} pairs, {keep.sum()} sampled against the oracle: max |dV| {dv:.3e} mag")
+    assert keep.sum() > 0 and dv < 1e-8
 
 
 def test_footprint_full_size_sampled(torch_cuda, orc):
