@@ -217,15 +217,13 @@ struct SunTable {
 // barycentric frame, no aberration): heliocentric state (r0, v0) at t_ref,
 // emission point x_e = S(t_obs - tau) + hop(r0, v0, t_obs - tau - t_ref),
 // tau = |x_e - o| / c, iterated until the update is at most lt_tol.
-// Outputs d = x_e - o, tau and the barycentric emission velocity;
-// optionally the universal anomaly of the hop and the heliocentric
-// emission position.
+// Outputs d = x_e - o, tau and the barycentric emission velocity.
 template <class SunT>
 __device__ __forceinline__ int lighttime(const SunT& sun, double mu, double smu, double c_light,
                                          double lt_tol, int lt_iter, double t_ref,
                                          const double r0[3], const double v0[3], double t_obs,
                                          const double o[3], double d[3], double& tau, double ve[3],
-                                         double* chi_out = nullptr, double* r_out = nullptr) {
+                                         double* chi_out = nullptr) {
     double Se[3], Sde[3], r[3], v[3];
     double chi = __builtin_nan("");
     // first guess: straight line from the epoch state
@@ -249,8 +247,6 @@ __device__ __forceinline__ int lighttime(const SunT& sun, double mu, double smu,
         ve[i] = Sde[i] + v[i];
     }
     if (chi_out) *chi_out = chi;
-    if (r_out)
-        for (int i = 0; i < 3; ++i) r_out[i] = r[i];
     return st;
 }
 

@@ -4,7 +4,8 @@
 // One lane per pair.  The lane repeats the exact test's light-time hop
 // from the pair's batch epoch (it is cheap next to finding the pairs and
 // saves the field-of-view kernels a per-pair record), which gives the
-// heliocentric emission position r and the observer-to-body vector d.  With
+// observer-to-body vector d, and the heliocentric emission position r
+// from one more evaluation of the Sun.  With
 // c = r . d and s = |r x d| the phase angle is atan2(s, c) and
 // tan(alpha / 2) = s / (|r| |d| + c), so the phase functions need no
 // trigonometric call.  Reads per pair: two indices, the batch and frame
@@ -58,14 +59,19 @@ __global__ __launch_bounds__(256) void k_pair_mag(const MagParams p, const int32
         const double* st = p.x_epoch + 6 * ((int64_t)b * p.n_obj + j);
         const double r0[3] = {st[0] - S[0], st[1] - S[1], st[2] - S[2]};
         const double v0[3] = {st[3] - Sd[0], st[4] - Sd[1], st[5] - Sd[2]};
-        double d[3], tau, ve[3], r[3];
+        double d[3], tau, ve[3];
         // as in the membership test, the hop's value is used even when its
         // iteration ended on the step cap a few ulps from its tolerance; a
         // hop that really fails is non-finite and stays so below
         lighttime(sun, E.gm[0], p.smu, p.c_light, p.lt_tol, p.lt_iter, tr, r0, v0, tf, p.fobs + 3 * (int64_t)f, d,
-                  tau, ve, nullptr, r);
+                  tau, ve);
         const double te = tf - tau;
         if (te >= p.t_lo && te <= p.t_hi) {
+            // heliocentric emission point r = (d + o) - S(te)
+            double Se[3], Sde[3];
+            sun.eval(te, Se, Sde);
+            const double* o = p.fobs + 3 * (int64_t)f;
+            const double r[3] = {d[0] + o[0] - Se[0], d[1] + o[1] - Se[1], d[2] + o[2] - Se[2]};
             const double c = dot3(r, d);
             const double cx = r[1] * d[2] - r[2] * d[1];
             const double cy = r[2] * d[0] - r[0] * d[2];
