@@ -92,7 +92,7 @@ def workload_name(case, F):
             (case.x0.shape[0], case.span, F))
 
 
-def cpu_baseline(case, t_ref, order, off, n_obj_prop=1000, n_obj_fov=600, n_batches_fov=3):
+def cpu_baseline(case, t_ref, order, off, n_obj_prop=10000, n_obj_fov=4000, n_batches_fov=3):
     """The CPU oracle as it stands, on a bounded sample of the same
     workload, extrapolated to the whole step."""
     from oracle import oracle as O

@@ -54,6 +54,19 @@ _PLANETS = [
     ("neptune", 1.5243573478851939e-08, 30.06992276, 0.00859048, 1.77004347, -55.12002969, 44.96476227, 131.78422574),
 ]
 PLANET_NAMES = [p[0] for p in _PLANETS]
+# Extra perturbers: the largest main-belt asteroids on fixed ellipses, with
+# rounded published GM values and rounded osculating elements (stand-ins
+# for their ephemerides, same columns as above; L and long.peri in deg).
+_ASTEROIDS = [
+    ("ceres",      1.3962e-13, 2.7675, 0.0758, 10.594, 153.9 + 95.0, 153.9, 80.3),
+    ("vesta",      3.8548e-14, 2.3615, 0.0887, 7.140, 255.0 + 20.0, 255.0, 103.8),
+    ("pallas",     3.0471e-14, 2.7720, 0.2305, 34.840, 123.1 + 40.0, 123.1, 173.1),
+    ("hygiea",     1.2542e-14, 3.1421, 0.1125, 3.832, 235.5 + 200.0, 235.5, 283.2),
+    ("interamnia", 5.8e-15, 3.0560, 0.1550, 17.310, 15.7 + 100.0, 15.7, 280.3),
+    ("eunomia",    4.7e-15, 2.6440, 0.1870, 11.750, 31.5 + 300.0, 31.5, 292.9),
+    ("juno",       4.0e-15, 2.6690, 0.2570, 12.990, 57.9 + 250.0, 57.9, 169.8),
+]
+ASTEROID_NAMES = [p[0] for p in _ASTEROIDS]
 # Bodies that carry the first post-Newtonian correction (Sun, Jupiter, Earth).
 GR_BODIES = ("sun", "jupiter", "earth")
 
@@ -123,8 +136,9 @@ class PlanetModel:
     @staticmethod
     def make(planets: Optional[List[str]] = None) -> "PlanetModel":
         planets = PLANET_NAMES if planets is None else list(planets)
-        rows = [p for p in _PLANETS if p[0] in planets]
-        rows.sort(key=lambda p: PLANET_NAMES.index(p[0]))
+        order = PLANET_NAMES + ASTEROID_NAMES
+        rows = [p for p in _PLANETS + _ASTEROIDS if p[0] in planets]
+        rows.sort(key=lambda p: order.index(p[0]))
         gm = np.array([GM_SUN] + [p[1] for p in rows])
         el = []
         for p in rows:

@@ -93,6 +93,32 @@ def test_adjoint_gradient_matches_oracle_stm(torch_cuda, orc):
     assert rel_x.max() < 1e-8 and rel_v.max() < 1e-8
 
 
+def test_adjoint_gradient_sixteen_perturbers(torch_cuda, orc):
+    # the most perturbers the ABI takes (run-time body count path of the
+    # forward, recompute and sweep kernels)
+    import dataclasses
+    torch, api = torch_cuda
+    g = synth.gradient_case(n_obj=120, k_obs=20, arc=60.0, neo_frac=0.1)
+    model = synth.PlanetModel.make(synth.PLANET_NAMES + synth.ASTEROID_NAMES)
+    g = dataclasses.replace(g, ephem=synth.make_ephemeris(model, -8.0, g.ephem.coef.shape[1]))
+    assert g.ephem.coef.shape[0] == 16
+    eph, ctx = _setup(torch, api, g)
+    x0 = _t(torch, g.x0).requires_grad_(True)
+    sky = api.AdjointSky.apply(x0, ctx)
+    loss = api.sky_residual_loss(sky, _t(torch, g.radec_obs))
+    loss.backward()
+    gg = x0.grad.cpu().numpy()
+    st = ctx.status.cpu().numpy()
+    radec, oloss, og, ost = orc.sky_grad(g.ephem, g.x0, 0.0, g.t_obs, g.obs_pos, g.radec_obs)
+    ok = (st == 0) & (ost == 0)
+    assert ok.all()
+    dsky = _ang(sky.detach().cpu().numpy(), radec)[ok].max()
+    rel = np.linalg.norm(gg[ok] - og[ok], axis=1) / np.linalg.norm(og[ok], axis=1)
+    _say(f"16 perturbers: max sky difference {dsky / MAS:.3e} mas, max rel gradient difference {rel.max():.3e}")
+    assert dsky < 1e-3 * MAS
+    assert rel.max() < 1e-8
+
+
 def test_adjoint_checkpoint_interval_invariance(torch_cuda):
     torch, api = torch_cuda
     g = synth.gradient_case(n_obj=150, k_obs=12, arc=60.0, neo_frac=0.1)

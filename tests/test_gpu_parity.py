@@ -127,6 +127,32 @@ def test_propagate_survey_mix_one_year(torch_cuda, orc):
     assert err[ok].max() < 1e-10
 
 
+@pytest.mark.parametrize("n_ast", [4, 7])
+def test_propagate_extra_perturbers(torch_cuda, orc, n_ast):
+    # Sun + 8 planets + the largest asteroids as extra perturbers: 13
+    # bodies, and 16, the most the ABI takes (the run-time body count path)
+    torch, api = torch_cuda
+    model = synth.PlanetModel.make(synth.PLANET_NAMES + synth.ASTEROID_NAMES[:n_ast])
+    assert len(model.names) == 9 + n_ast
+    eph = synth.make_ephemeris(model, -8.0, 20)
+    rng = np.random.default_rng(16 + n_ast)
+    x0 = synth.bodies_from_elements(model, np.concatenate([synth.main_belt_elements(rng, 600),
+                                                           synth.neo_elements(rng, 30)]), 0.0)
+    t_out = np.arange(1.5, 120.0, 3.0)
+    xg, sg, xo, so = _propagate_both(torch, api, orc, eph, x0, 0.0, t_out)
+    ok = (sg == 0) & (so == 0)
+    assert ok.all()
+    err = np.abs(xg[..., :3] - xo[..., :3]).max()
+    # the asteroids move the bodies measurably against the planets alone
+    xp, _ = api.propagate(api.DeviceEphemeris.from_synth(synth.make_ephemeris(synth.PlanetModel.make(), -8.0, 20)),
+                          _dev_x(torch, x0), 0.0, t_out)
+    shift = np.abs(xp.cpu().numpy()[..., :3] - xg[..., :3]).max()
+    _say(f"{len(model.names)} perturbers, 120 d: max |dx| vs oracle {err:.3e} au, shift from the asteroids "
+         f"{shift:.3e} au")
+    assert err < 1e-10
+    assert shift > 1e-11
+
+
 def test_propagate_backward(torch_cuda, orc):
     torch, api = torch_cuda
     model = synth.PlanetModel.make()
