@@ -128,6 +128,31 @@ def cpu_baseline(case, t_ref, order, off, n_obj_prop=10000, n_obj_fov=4000, n_ba
     }
 
 
+def strict_component(api, torch, case, eph, x0, log, days=1.0, reps=3):
+    """Strict n-body mode (the two-body interval set to zero, Sect. 2) on
+    the first `days` of the survey's frames, every body: a batch span of
+    zero makes each distinct frame time a batch epoch.  Timed beside the
+    default 3-day batching of the same frames."""
+    fr = case.frames.subset(np.nonzero(case.frames.t < days)[0])
+    frames = api.DeviceFrames.from_synth(fr)
+    res = {"frames": int(fr.t.size), "days": days}
+    for name, span in (("default", 3.0), ("strict", 0.0)):
+        opts = api.default_opts(batch_span=span)
+        out = api.predict(eph, x0, 0.0, frames, fr.t, opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            out = api.predict(eph, x0, 0.0, frames, fr.t, opts)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        res[name] = {"batches": int(out[5].t_ref_host.size), "pairs": int(out[0].numel()), "ms": ms,
+                     "object_days_per_s": x0.shape[0] * days / (ms / 1e3)}
+        del out
+        log(f"strict component: {name} {res[name]}")
+    res["strict_over_default"] = res["strict"]["ms"] / res["default"]["ms"]
+    return res
+
+
 def adjoint_component(api, synth, torch, n_obj, log, reps=10):
     """Forward sky positions and the backward gradient of the summed squared
     sky residual: 100,000 bodies, 20 observations each over a 60-day arc,
@@ -269,6 +294,7 @@ def main():
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2509_04666_amd", "tuning.json"))
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-strict", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="copy a buffer of this size once before timing (HBM counter calibration)")
     args = ap.parse_args()
@@ -458,6 +484,9 @@ def main():
             "magnitudes": mag,
         },
     }
+    if not args.no_strict:
+        log("strict n-body component ...")
+        out["components"]["strict_nbody"] = strict_component(api, torch, case, eph, x0, log)
     if not args.no_adjoint:
         log("adjoint component ...")
         out["components"]["adjoint"] = adjoint_component(api, synth, torch, args.adjoint_objects, log)
