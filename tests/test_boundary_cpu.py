@@ -124,6 +124,27 @@ def test_fov_argument_errors():
     assert n.value == 0
 
 
+def test_magnitudes_argument_errors():
+    L = _lib.lib()
+    e, et, keep = _host_ephem()
+    o = api.default_opts()
+    fake = C.c_void_p(0x1000)
+    fr = _lib.FramesT(10, 1, 0, 0x1000, 0x1000, 0x1000)
+    assert L.kete_magnitudes_workspace_size(-1) == 0
+    need = L.kete_magnitudes_workspace_size(10)
+    assert need >= 40 and need % 256 == 0
+    args = lambda n_pairs, frames, pf, ws, ws_bytes: (C.byref(et), fake, 10, 2, fake, fake, fake, frames, pf, fake,
+                                                      n_pairs, fake, fake, fake, None, C.byref(o), ws, ws_bytes,
+                                                      None)
+    assert L.kete_pair_magnitudes(*args(5, None, fake, fake, need)) == _lib.KETE_EINVAL      # no frames
+    assert L.kete_pair_magnitudes(*args(-1, C.byref(fr), fake, fake, need)) == _lib.KETE_EINVAL
+    assert L.kete_pair_magnitudes(*args(5, C.byref(fr), None, fake, need)) == _lib.KETE_EINVAL
+    assert L.kete_pair_magnitudes(*args(5, C.byref(fr), fake, None, need)) == _lib.KETE_EWORKSPACE
+    assert L.kete_pair_magnitudes(*args(5, C.byref(fr), fake, fake, need - 1)) == _lib.KETE_EWORKSPACE
+    # no pairs: nothing to do
+    assert L.kete_pair_magnitudes(*args(0, C.byref(fr), None, None, 0)) == _lib.KETE_OK
+
+
 def test_ephem_eval_range_check():
     L = _lib.lib()
     e, et, keep = _host_ephem()
