@@ -291,6 +291,27 @@ int kete_pair_magnitudes(const kete_ephem_t *eph, const double *x_epoch, int64_t
                          const double *h_mag, const double *g_slope, double *v_mag, double *geom,
                          const kete_opts_t *opts, void *workspace, size_t ws_bytes, void *stream);
 
+/* kete_pair_magnitudes for callers that cannot allocate device memory:
+ * code recorded into a HIP graph, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, results and errors as
+ * kete_pair_magnitudes, without the workspace: the frame-to-batch map
+ * (4 bytes per frame) lives in a static device array of the library, of
+ * KETE_MAG_NOALLOC_MAX_FRAMES frames (8 MiB), one copy per GPU, held until
+ * the process ends.  Its device address is looked up on the first call on
+ * each device (the current device must be the one `stream` belongs to).
+ * The call allocates nothing and calls no allocating routine; the map is
+ * refilled by a kernel on every call, so the last call's contents do not
+ * leak into the next.  Calls that overlap in time on one GPU (on
+ * different streams or threads) share the array and race: serialize them.
+ * Errors: KETE_EWORKSPACE when n_frames exceeds
+ * KETE_MAG_NOALLOC_MAX_FRAMES, otherwise as kete_pair_magnitudes. */
+#define KETE_MAG_NOALLOC_MAX_FRAMES (1 << 21)
+int kete_pair_magnitudes_noalloc(const kete_ephem_t *eph, const double *x_epoch, int64_t n_obj, int64_t n_batch,
+                                 const double *t_ref, const int32_t *batch_off, const int32_t *frame_order,
+                                 const kete_frames_t *frames, const int32_t *pf, const int32_t *po, int64_t n_pairs,
+                                 const double *h_mag, const double *g_slope, double *v_mag, double *geom,
+                                 const kete_opts_t *opts, void *stream);
+
 /* Light-time corrected directions (the per-pair step of kete_fov_check,
  * exposed for checking): for every object j and query q, the direction
  * d = x_e - obs[q] of object j (state x_ref[j] at t_ref) at the emission

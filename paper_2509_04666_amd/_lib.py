@@ -16,6 +16,7 @@ KETE_OK, KETE_EINVAL, KETE_ERANGE, KETE_ECAPACITY, KETE_EDEVICE, KETE_EWORKSPACE
 ADJ_FWD, ADJ_BWD = 0, 1
 ST_OK, ST_NONFINITE, ST_STEP_UNDERFLOW, ST_MAX_STEPS, ST_KEPLER_NOCONV = 0, 1, 2, 3, 4
 MAX_BODIES, MAX_DEGREE, MAX_SUB, MAX_OBJ = 16, 15, 128, 1 << 25
+MAG_NOALLOC_MAX_FRAMES = 1 << 21
 
 ERROR_NAMES = {KETE_EINVAL: "EINVAL", KETE_ERANGE: "ERANGE", KETE_ECAPACITY: "ECAPACITY",
                KETE_EDEVICE: "EDEVICE", KETE_EWORKSPACE: "EWORKSPACE"}
@@ -87,6 +88,10 @@ SIGNATURES = {
                                        C.c_void_p, C.POINTER(FramesT), C.c_void_p, C.c_void_p, C.c_int64,
                                        C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(OptsT),
                                        C.c_void_p, C.c_size_t, C.c_void_p]),
+    "kete_pair_magnitudes_noalloc": (C.c_int, [C.POINTER(EphemT), C.c_void_p, C.c_int64, C.c_int64, C.c_void_p,
+                                               C.c_void_p, C.c_void_p, C.POINTER(FramesT), C.c_void_p, C.c_void_p,
+                                               C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                               C.POINTER(OptsT), C.c_void_p]),
     "kete_lighttime_directions": (C.c_int, [C.POINTER(EphemT), C.c_void_p, C.c_double, C.c_int64, C.c_void_p,
                                             C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.POINTER(OptsT),
                                             C.c_void_p]),

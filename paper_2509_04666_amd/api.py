@@ -196,6 +196,27 @@ def pair_magnitudes(eph: DeviceEphemeris, x_epoch: torch.Tensor, batches: Batche
     return (v, geom) if geometry else v
 
 
+def pair_magnitudes_noalloc(eph: DeviceEphemeris, x_epoch: torch.Tensor, batches: Batches, frames: DeviceFrames,
+                            pf: torch.Tensor, po: torch.Tensor, h_mag: torch.Tensor, g_slope: torch.Tensor,
+                            v_mag: torch.Tensor, geom: Optional[torch.Tensor] = None,
+                            opts: Optional[OptsT] = None) -> None:
+    """pair_magnitudes into caller-allocated outputs v_mag [P] (and geom
+    [P, 3]) through the entry point that allocates no device memory (its
+    frame-to-batch map is the library's static array)."""
+    opts = opts or default_opts()
+    x_epoch = x_epoch.contiguous()
+    B, N = x_epoch.shape[0], x_epoch.shape[1]
+    P = pf.shape[0]
+    if v_mag.numel() < P or (geom is not None and geom.numel() < 3 * P):
+        raise ValueError("output tensors are smaller than the pair count")
+    fc = frames.c()
+    check(lib().kete_pair_magnitudes_noalloc(C.byref(eph.c), _ptr(x_epoch), N, B, _ptr(batches.t_ref),
+                                             _ptr(batches.batch_off), _ptr(batches.frame_order), C.byref(fc),
+                                             _ptr(pf.contiguous()), _ptr(po.contiguous()), P,
+                                             _ptr(h_mag.contiguous()), _ptr(g_slope.contiguous()), _ptr(v_mag),
+                                             _ptr(geom), C.byref(opts), _stream()))
+
+
 def lighttime_directions(eph: DeviceEphemeris, x_ref: torch.Tensor, t_ref: float, t_obs: torch.Tensor,
                          obs: torch.Tensor, opts: Optional[OptsT] = None):
     """(d [Q, N, 3], tau [Q, N]) for states x_ref [N, 6] at t_ref."""

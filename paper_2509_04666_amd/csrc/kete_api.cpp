@@ -1441,11 +1441,20 @@ size_t kete_magnitudes_workspace_size(int64_t n_frames) {
     return mag_workspace_bytes(n_frames);
 }
 
-int kete_pair_magnitudes(const kete_ephem_t* eph, const double* x_epoch, int64_t n_obj, int64_t n_batch,
+}  // extern "C"
+
+namespace {
+
+// Shared body of the two magnitude entry points.  static_scratch: the
+// frame-to-batch map lives in the library's static device array (its
+// frame limit is checked, nothing is allocated) instead of the caller's
+// workspace.
+int pair_magnitudes_impl(const kete_ephem_t* eph, const double* x_epoch, int64_t n_obj, int64_t n_batch,
                          const double* t_ref, const int32_t* batch_off, const int32_t* frame_order,
                          const kete_frames_t* frames, const int32_t* pf, const int32_t* po, int64_t n_pairs,
                          const double* h_mag, const double* g_slope, double* v_mag, double* geom,
-                         const kete_opts_t* opts, void* workspace, size_t ws_bytes, void* stream) {
+                         const kete_opts_t* opts, void* workspace, size_t ws_bytes, bool static_scratch,
+                         void* stream) {
     kete_opts_t dflt;
     if (!opts) { kete_default_opts(&dflt); opts = &dflt; }
     g_err.clear();
@@ -1464,9 +1473,16 @@ int kete_pair_magnitudes(const kete_ephem_t* eph, const double* x_epoch, int64_t
     if (n_obj > 0 && n_batch > 0 && F > 0 && (!x_epoch || !t_ref || !batch_off || !frame_order || !frames->t ||
                                               !frames->obs))
         return fail(KETE_EINVAL, "null pointer");
-    if (!workspace) return fail(KETE_EWORKSPACE, "workspace is null");
-    const size_t need = kete_magnitudes_workspace_size(F);
-    if (ws_bytes < need) return fail(KETE_EWORKSPACE, "workspace %zu bytes < %zu required", ws_bytes, need);
+    if (static_scratch) {
+        if (F > kMagScratchFrames)
+            return fail(KETE_EWORKSPACE, "n_frames %lld exceeds the %lld frames of the static scratch",
+                        (long long)F, (long long)kMagScratchFrames);
+        HIPCHK(mag_static_scratch(&workspace));
+    } else {
+        if (!workspace) return fail(KETE_EWORKSPACE, "workspace is null");
+        const size_t need = kete_magnitudes_workspace_size(F);
+        if (ws_bytes < need) return fail(KETE_EWORKSPACE, "workspace %zu bytes < %zu required", ws_bytes, need);
+    }
     MagParams P;
     std::memset(&P, 0, sizeof(P));
     P.eph = E;
@@ -1495,6 +1511,28 @@ int kete_pair_magnitudes(const kete_ephem_t* eph, const double* x_epoch, int64_t
     P.t_hi = t_end_of(eph);
     HIPCHK(launch_pair_mag(P, workspace, (hipStream_t)stream));
     return KETE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int kete_pair_magnitudes(const kete_ephem_t* eph, const double* x_epoch, int64_t n_obj, int64_t n_batch,
+                         const double* t_ref, const int32_t* batch_off, const int32_t* frame_order,
+                         const kete_frames_t* frames, const int32_t* pf, const int32_t* po, int64_t n_pairs,
+                         const double* h_mag, const double* g_slope, double* v_mag, double* geom,
+                         const kete_opts_t* opts, void* workspace, size_t ws_bytes, void* stream) {
+    return pair_magnitudes_impl(eph, x_epoch, n_obj, n_batch, t_ref, batch_off, frame_order, frames, pf, po, n_pairs,
+                                h_mag, g_slope, v_mag, geom, opts, workspace, ws_bytes, false, stream);
+}
+
+int kete_pair_magnitudes_noalloc(const kete_ephem_t* eph, const double* x_epoch, int64_t n_obj, int64_t n_batch,
+                                 const double* t_ref, const int32_t* batch_off, const int32_t* frame_order,
+                                 const kete_frames_t* frames, const int32_t* pf, const int32_t* po, int64_t n_pairs,
+                                 const double* h_mag, const double* g_slope, double* v_mag, double* geom,
+                                 const kete_opts_t* opts, void* stream) {
+    return pair_magnitudes_impl(eph, x_epoch, n_obj, n_batch, t_ref, batch_off, frame_order, frames, pf, po, n_pairs,
+                                h_mag, g_slope, v_mag, geom, opts, nullptr, 0, true, stream);
 }
 
 int kete_ephem_eval(const kete_ephem_t* eph, const double* t, const double* t_host, int64_t n_q, double* out,

@@ -14,6 +14,8 @@
 // is bound by FP64 arithmetic, not by HBM.
 #include <math.h>
 
+#include <mutex>
+
 #include "kete_mag.hpp"
 
 namespace kete {
@@ -98,6 +100,37 @@ __global__ __launch_bounds__(256) void k_pair_mag(const MagParams p, const int32
 }
 
 }  // namespace
+
+// Frame-to-batch map of the entry point that allocates nothing: a
+// file-scope array in device memory (each GPU the library runs on holds
+// its own copy until the process ends).  Host code never passes the
+// array's name to a kernel: it is a host-side stand-in, not the device
+// address, which comes from hipGetSymbolAddress once per device.
+static __device__ __align__(256) int32_t scratch[kMagScratchFrames];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t mag_static_scratch(void** ptr) {
+    *ptr = nullptr;
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return hipSuccess;
+}
 
 size_t mag_workspace_bytes(int64_t n_frames) {
     return ((size_t)std::max<int64_t>(n_frames, 1) * sizeof(int32_t) + 255) & ~(size_t)255;

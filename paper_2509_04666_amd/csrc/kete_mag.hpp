@@ -33,6 +33,12 @@ struct MagParams {
 };
 
 size_t mag_workspace_bytes(int64_t n_frames);
+
+// Frames covered by the static frame-to-batch map (4 bytes per frame).
+constexpr int64_t kMagScratchFrames = KETE_MAG_NOALLOC_MAX_FRAMES;
+// Device address of that map on the current device, looked up on the
+// first call per device and kept.
+hipError_t mag_static_scratch(void** ptr);
 hipError_t launch_pair_mag(const MagParams& p, void* ws, hipStream_t s);
 
 }  // namespace kete

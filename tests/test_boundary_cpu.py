@@ -196,3 +196,22 @@ def test_batch_description_checks():
                                  _lib.TUNE_PROGRESS(), None, C.byref(best), None) == _lib.KETE_EINVAL
     assert L.kete_batch_graph_launch(None, None) == _lib.KETE_EINVAL
     assert L.kete_batch_graph_destroy(None) == _lib.KETE_OK
+
+
+def test_noalloc_magnitudes_rejects_too_many_frames():
+    """The magnitude entry point without a workspace holds its
+    frame-to-batch map in a static device array: more frames than it holds
+    is a clear error raised before any device work (the fake pointers are
+    never dereferenced on this path)."""
+    L = _lib.lib()
+    e, et, keep = _host_ephem()
+    fake = C.c_void_p(0x1000)
+    fr = _lib.FramesT(_lib.MAG_NOALLOC_MAX_FRAMES + 1, 1, 0, 0x1000, 0x1000, 0x1000)
+    rc = L.kete_pair_magnitudes_noalloc(C.byref(et), fake, 10, 2, fake, fake, fake, C.byref(fr), fake, fake, 5,
+                                        fake, fake, fake, None, None, None)
+    assert rc == _lib.KETE_EWORKSPACE
+    assert b"static scratch" in L.kete_last_error()
+    # no pairs: nothing to do, no device work, no error
+    rc = L.kete_pair_magnitudes_noalloc(C.byref(et), fake, 10, 2, fake, fake, fake, C.byref(fr), fake, fake, 0,
+                                        fake, fake, fake, None, None, None)
+    assert rc == _lib.KETE_OK
