@@ -719,6 +719,20 @@ static double wrap_pi(double a)
     return a;
 }
 
+/* Sky residual of one observation: r = ((ra - ra_obs) cos dec,
+ * dec - dec_obs), the RA difference taken in (-pi, pi]. */
+void orc_sky_residual(double ra, double dec, double ra_obs, double dec_obs, double r[2])
+{
+    r[0] = wrap_pi(ra - ra_obs) * cos(dec);
+    r[1] = dec - dec_obs;
+}
+
+/* orc_radec for the tests: out = {ra, dec}, J = d(ra, dec)/d(d) (2x3). */
+void orc_radec_of(const double d[3], double out[2], double J[6])
+{
+    orc_radec(d, &out[0], &out[1], J);
+}
+
 /* One object: integrate with (optionally) the 6x6 variational equations
  * from t0 through its k observation times (ascending), hop with light
  * time to each emission point, compute RA/Dec and the residual
@@ -761,7 +775,9 @@ static int orc_sky_one(const orc_ephem *E, const orc_opts *o, const double x0[6]
         orc_radec(d, &ra, &dec, J);
         radec_out[2 * q] = ra; radec_out[2 * q + 1] = dec;
         double dra = wrap_pi(ra - radec_obs[2 * q]);
-        double r1 = dra * cos(dec), r2 = dec - radec_obs[2 * q + 1];
+        double res[2];
+        orc_sky_residual(ra, dec, radec_obs[2 * q], radec_obs[2 * q + 1], res);
+        double r1 = res[0], r2 = res[1];
         L += r1 * r1 + r2 * r2;
         if (!want_grad) continue;
         /* dL/d(ra, dec) */

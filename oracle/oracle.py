@@ -240,6 +240,21 @@ def loss_steps(eph, x0, t0, t_obs, obs_pos, radec_obs, replay=None, opts=None, *
     return loss.value, (rec[:rec_n.value].copy() if replay is None else rp)
 
 
+def radec(d):
+    """(ra, dec) in the equatorial J2000 frame of an ecliptic direction d,
+    and the Jacobian d(ra, dec)/dd [2, 3]."""
+    out = np.zeros(2); jac = np.zeros(6)
+    lib().orc_radec_of(_p(_f64(d)), _p(out), _p(jac))
+    return out[0], out[1], jac.reshape(2, 3)
+
+
+def sky_residual(ra, dec, ra_obs, dec_obs):
+    """((ra - ra_obs) cos dec, dec - dec_obs), the RA difference wrapped to (-pi, pi]."""
+    r = np.zeros(2)
+    lib().orc_sky_residual(C.c_double(ra), C.c_double(dec), C.c_double(ra_obs), C.c_double(dec_obs), _p(r))
+    return r
+
+
 def inside(normals, d):
     """Membership of direction d in each sub-frame of one frame: (inside[S], edge[S])."""
     n = _f64(normals)

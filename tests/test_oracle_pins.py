@@ -501,3 +501,72 @@ def test_loss_gradient_vs_frozen_step_fd(orc):
             Lm, _ = orc.loss_steps(g.ephem, xm, 0.0, g.t_obs[j], g.obs_pos[j], g.radec_obs[j], replay=steps)
             fd[c] = (Lp - Lm) / (2 * h)
         np.testing.assert_allclose(grad[0], fd, rtol=1e-6, atol=1e-6 * np.max(np.abs(fd)))
+
+
+# ---------------------------------------------------------------- RA/Dec and residual
+OBLIQ = math.radians(84381.448 / 3600.0)     # IAU 1980 J2000 mean obliquity
+
+
+def test_radec_closed_forms(orc):
+    """Ecliptic J2000 -> equatorial RA/Dec: the equinox direction is
+    (0, 0); the ecliptic +y axis is the point of the ecliptic at longitude
+    90 deg, which lies at RA 90 deg and Dec +eps; the ecliptic north pole is
+    at RA 270 deg, Dec 90 deg - eps; the equatorial north pole written in
+    ecliptic coordinates, (0, sin eps, cos eps), has Dec 90 deg.  A wrong
+    obliquity sign, a swapped axis or a missing RA wrap fails one of these."""
+    e = OBLIQ
+    cases = [((1.0, 0.0, 0.0), 0.0, 0.0),
+             ((0.0, 1.0, 0.0), math.pi / 2, e),
+             ((0.0, 0.0, 1.0), 3 * math.pi / 2, math.pi / 2 - e),
+             ((-1.0, 0.0, 0.0), math.pi, 0.0),
+             ((0.0, -1.0, 0.0), 3 * math.pi / 2, -e)]
+    for d, ra0, dec0 in cases:
+        for scale in (1.0, 3.7):          # the length of d does not matter
+            ra, dec, _ = orc.radec(np.array(d) * scale)
+            assert abs(ra - ra0) < 1e-15 and abs(dec - dec0) < 1e-15, (d, ra, dec)
+    ra, dec, _ = orc.radec(np.array([0.0, math.sin(e), math.cos(e)]))
+    assert abs(dec - math.pi / 2) < 1e-8
+    # RA lies in [0, 2 pi): a direction just below the equinox on the equator
+    ra, dec, _ = orc.radec(np.array([1.0, -1e-9 * math.cos(e), 1e-9 * math.sin(e)]))
+    assert 2 * math.pi - 2e-9 < ra < 2 * math.pi and abs(dec) < 1e-15
+    # a point of the ecliptic at longitude lam: sin(dec) = sin(eps) sin(lam),
+    # tan(ra) = cos(eps) tan(lam) (spherical trigonometry of the ecliptic)
+    for lam in np.linspace(0.1, 6.2, 17):
+        ra, dec, _ = orc.radec(np.array([math.cos(lam), math.sin(lam), 0.0]))
+        assert abs(math.sin(dec) - math.sin(e) * math.sin(lam)) < 1e-15
+        assert abs(math.sin(ra) * math.cos(lam) - math.cos(e) * math.sin(lam) * math.cos(ra)) < 1e-15
+        assert (ra < math.pi) == (math.sin(lam) > 0)
+
+
+def test_radec_jacobian_matches_finite_differences(orc):
+    rng = np.random.default_rng(61)
+    for _ in range(20):
+        d = rng.normal(size=3) * rng.uniform(0.5, 4.0)
+        _, _, J = orc.radec(d)
+        num = np.zeros((2, 3))
+        for i in range(3):
+            h = 1e-6 * np.linalg.norm(d)
+            dp, dm = d.copy(), d.copy()
+            dp[i] += h
+            dm[i] -= h
+            rp, xp, _ = orc.radec(dp)
+            rm, xm, _ = orc.radec(dm)
+            dra = (rp - rm + math.pi) % (2 * math.pi) - math.pi
+            num[:, i] = [dra / (2 * h), (xp - xm) / (2 * h)]
+        assert np.abs(num - J).max() < 1e-7 * np.abs(J).max()
+
+
+def test_sky_residual_wraps_across_ra_zero(orc):
+    """r = ((ra - ra_obs) cos dec, dec - dec_obs) with the RA difference in
+    (-pi, pi]: two points 2 microradians apart across RA = 0 are 2 urad
+    apart, not 2 pi; the cos(dec) factor uses the computed declination."""
+    dec = 0.7
+    r = orc.sky_residual(2 * math.pi - 1e-6, dec, 1e-6, dec - 3e-7)
+    # (2 pi - 1e-6 carries the rounding of 2 pi, a few 1e-16)
+    assert abs(r[0] - (-2e-6 * math.cos(dec))) < 1e-15 and abs(r[1] - 3e-7) < 1e-15
+    r = orc.sky_residual(1e-6, -dec, 2 * math.pi - 1e-6, -dec)
+    assert abs(r[0] - 2e-6 * math.cos(dec)) < 1e-15 and r[1] == 0.0
+    r = orc.sky_residual(math.pi + 0.1, 0.0, 0.0, 0.0)
+    assert abs(r[0] - (0.1 - math.pi)) < 1e-15
+    r = orc.sky_residual(1.0, 0.2, 1.0, 0.2)
+    assert r[0] == 0.0 and r[1] == 0.0
