@@ -15,8 +15,14 @@ solar-system barycentre (NAIF id 0) through the segments' centres, and
 resamples the barycentric positions into uniform segments of
 `seg_days` days and a fixed degree (Chebyshev-Gauss interpolation), the
 layout `kete_ephem_t` takes.  Units become au and TDB days past J2000.
-Only little-endian files are read.  `write_spk` writes type-2 files (used
-to make test fixtures).
+
+Frames (App. A.1): the library integrates in the ecliptic J2000 frame,
+while planetary kernels such as DE440 store the equatorial J2000 frame
+(NAIF frame 1, taken as the ICRF).  Segments in frame 1 are rotated to the
+ecliptic by the J2000 obliquity about the common x axis (the equinox);
+segments in frame 17 (ECLIPJ2000) are taken as they are; any other frame
+is refused.  Only little-endian files are read.  `write_spk` writes
+type-2 and type-3 files (used to make test fixtures).
 """
 from __future__ import annotations
 
@@ -31,6 +37,18 @@ from . import synth
 AU_KM = synth.AU_KM
 DAY_S = 86400.0
 _REC = 1024
+
+FRAME_J2000 = 1            # NAIF: equatorial J2000 (ICRF)
+FRAME_ECLIPJ2000 = 17      # NAIF: ecliptic J2000
+OBLIQUITY_J2000 = np.radians(84381.448 / 3600.0)    # IAU mean obliquity at J2000, rad
+
+
+def equatorial_to_ecliptic(x: np.ndarray) -> np.ndarray:
+    """Vectors [..., 3] of the equatorial J2000 frame in the ecliptic J2000
+    frame: a rotation by the obliquity about the x axis (the equinox)."""
+    c, s = np.cos(OBLIQUITY_J2000), np.sin(OBLIQUITY_J2000)
+    x = np.asarray(x, float)
+    return np.stack([x[..., 0], c * x[..., 1] + s * x[..., 2], -s * x[..., 1] + c * x[..., 2]], -1)
 
 
 @dataclasses.dataclass
@@ -64,6 +82,16 @@ class Segment:
                 t_prev, t_cur = t_cur, 2.0 * x * t_cur - t_prev
                 out = out + c[..., j] * t_cur[..., None]
         return out
+
+    def position_ecliptic(self, et: np.ndarray) -> np.ndarray:
+        """position() in the ecliptic J2000 frame (km)."""
+        p = self.position(et)
+        if self.frame == FRAME_ECLIPJ2000:
+            return p
+        if self.frame == FRAME_J2000:
+            return equatorial_to_ecliptic(p)
+        raise ValueError(f"segment of body {self.target}: frame {self.frame} is neither J2000 (1) nor "
+                         f"ECLIPJ2000 (17)")
 
 
 def read_segments(path: str) -> List[Segment]:
@@ -115,13 +143,14 @@ def _covering(segs: Sequence[Segment], target: int, et: np.ndarray) -> Segment:
 
 def barycentric(segs: Sequence[Segment], target: int, et: np.ndarray) -> np.ndarray:
     """Position [..., 3] in km of `target` relative to the solar-system
-    barycentre, chaining segments through their centres."""
+    barycentre in the ecliptic J2000 frame, chaining segments through their
+    centres (each rotated from its own frame)."""
     et = np.asarray(et, float)
     pos = np.zeros(et.shape + (3,))
     body, hops = target, 0
     while body != 0:
         s = _covering(segs, body, et)
-        pos = pos + s.position(et)
+        pos = pos + s.position_ecliptic(et)
         body, hops = s.center, hops + 1
         if hops > 16:
             raise ValueError(f"centre chain of body {target} does not reach the barycentre")
@@ -152,9 +181,11 @@ def load_spk(paths: Sequence[str], bodies: Sequence[int], gm: Sequence[float], t
 
 
 def write_spk(path: str, segments: Sequence[dict]) -> None:
-    """Write a little-endian type-2 SPK file.  Each segment dict holds
-    target, center, frame, init (s), intlen (s) and coef [n_rec][3][deg+1]
-    (km); record i covers [init + i intlen, init + (i+1) intlen]."""
+    """Write a little-endian SPK file.  Each segment dict holds target,
+    center, frame (the frame its numbers are in: 1 equatorial J2000, 17
+    ecliptic J2000; required), init (s), intlen (s) and coef: [n_rec][3][deg+1]
+    km for type 2, or [n_rec][6][deg+1] (positions in km, then velocities in
+    km/s) for type 3; record i covers [init + i intlen, init + (i+1) intlen]."""
     nd, ni = 2, 6
     ss = nd + (ni + 1) // 2
     if len(segments) > (_REC // 8 - 3) // ss:
@@ -164,15 +195,18 @@ def write_spk(path: str, segments: Sequence[dict]) -> None:
     addr = 3 * (_REC // 8) + 1                  # data start after file, summary and name records
     for sg in segments:
         c = np.asarray(sg["coef"], float)
-        n, _, deg1 = c.shape
-        rsize = 2 + 3 * deg1
+        n, n_comp, deg1 = c.shape
+        if n_comp not in (3, 6):
+            raise ValueError("coef must hold 3 (type 2) or 6 (type 3) components")
+        rsize = 2 + n_comp * deg1
         init, intlen = float(sg["init"]), float(sg["intlen"])
         a0 = addr + len(words)
         for i in range(n):
             words += [init + (i + 0.5) * intlen, 0.5 * intlen] + c[i].reshape(-1).tolist()
         words += [init, intlen, float(rsize), float(n)]
         a1 = addr + len(words) - 1
-        summaries.append((init, init + n * intlen, sg["target"], sg["center"], sg.get("frame", 1), 2, a0, a1))
+        summaries.append((init, init + n * intlen, sg["target"], sg["center"], int(sg["frame"]),
+                          2 if n_comp == 3 else 3, a0, a1))
     free = addr + len(words)
     fr = bytearray(_REC)
     fr[0:8] = b"DAF/SPK "
