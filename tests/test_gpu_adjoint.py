@@ -51,8 +51,9 @@ def test_adjoint_forward_sky_matches_oracle(torch_cuda, orc):
     sky = ctx.forward(_t(torch, g.x0)).cpu().numpy()
     st = ctx.status.cpu().numpy()
     radec, loss, grad, ost = orc.sky_grad(g.ephem, g.x0, 0.0, g.t_obs, g.obs_pos, g.radec_obs, want_grad=False)
-    ok = (st == 0) & (ost == 0)
-    assert ok.mean() > 0.99
+    np.testing.assert_array_equal(st, ost)
+    ok = ost == 0
+    assert ok.all()
     diff = _ang(sky, radec)
     diff[~ok] = 0
     err = diff.max()

@@ -120,11 +120,12 @@ def test_propagate_survey_mix_one_year(torch_cuda, orc):
     case = synth.survey_case(n_obj=3000, n_frames=0, neo_frac=0.05)
     t_out = np.arange(1.5, 365.25, 3.0)
     xg, sg, xo, so = _propagate_both(torch, api, orc, case.ephem, case.x0, 0.0, t_out)
-    ok = (sg == 0) & (so == 0)
-    assert ok.mean() > 0.99
+    _say(f"survey mix 1 yr: status gpu {np.bincount(sg)}, oracle {np.bincount(so)}")
+    np.testing.assert_array_equal(sg, so)
+    ok = so == 0
     err = np.abs(xg[..., :3] - xo[..., :3]).max(axis=(0, 2))
-    _say(f"survey mix 1 yr: max |dx| {err[ok].max():.3e} au, status gpu {np.bincount(sg)}, oracle {np.bincount(so)}")
-    assert err[ok].max() < 1e-10
+    _say(f"survey mix 1 yr: max |dx| {err[ok].max():.3e} au over {ok.sum()} bodies")
+    assert ok.all() and err.max() < 1e-10
 
 
 @pytest.mark.parametrize("n_ast", [4, 7])
@@ -363,8 +364,10 @@ def test_fov_survey_geometry(torch_cuda, orc):
     keep = np.isin(po.cpu().numpy(), sample)
     gp = (pf.cpu().numpy()[keep], ps.cpu().numpy()[keep], po.cpu().numpy()[keep])
     extra = _compare_pairs(gp, (opf, ops, opo), oedge, "survey geometry sample")
-    assert len(extra) == 0 or all(abs(_edge_of(orc, case.ephem, xg.cpu().numpy(), order, off, t_ref, fr, p)) < 2 * MAS
-                                  for p in extra)
+    # an extra GPU pair lies within 1 mas of an edge, measured from the oracle's states
+    loc = {int(j): i for i, j in enumerate(sample)}
+    for f, s, j in extra:
+        assert abs(_edge_of(orc, case.ephem, xe, order, off, t_ref, fr, (f, s, loc[j]))) < MAS, (f, s, j)
 
 
 def test_fov_capacity_and_empty(torch_cuda, orc):
