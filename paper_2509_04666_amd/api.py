@@ -253,7 +253,13 @@ def predict(eph: DeviceEphemeris, x0: torch.Tensor, t0: float, frames: DeviceFra
 
 
 class AdjointContext:
-    """Inputs and workspace shared by the forward and backward adjoint calls."""
+    """Inputs and workspace shared by the forward and backward adjoint calls.
+
+    The forward call leaves its checkpoints, light times and status in the
+    shared workspace, and the backward call reads them.  Each forward bumps
+    `generation`; AdjointSky records it and its backward refuses to run
+    once a later forward on the same context has overwritten that state
+    (use one context per pending backward)."""
 
     def __init__(self, eph: DeviceEphemeris, t0: float, t_end: float, t_obs: torch.Tensor, obs_pos: torch.Tensor,
                  ckpt_days: float = 5.0, opts: Optional[OptsT] = None):
@@ -268,8 +274,18 @@ class AdjointContext:
             check(_lib.KETE_EINVAL)
         self.workspace = _workspace(need, self.t_obs.device)
         self.status = torch.zeros(self.n_obj, dtype=torch.int32, device=self.t_obs.device)
+        self.generation = 0
 
     def forward(self, x0: torch.Tensor) -> torch.Tensor:
+        """Sky positions [N, K, 2]; the workspace now belongs to this call."""
+        self.generation += 1
+        return self._run_forward(x0)
+
+    def backward(self, x0: torch.Tensor, dL_dsky: torch.Tensor) -> torch.Tensor:
+        """dL/dx0 [N, 6] of the latest forward call."""
+        return self._run_backward(x0, dL_dsky)
+
+    def _run_forward(self, x0: torch.Tensor) -> torch.Tensor:
         sky = torch.empty((self.n_obj, self.k_obs, 2), dtype=torch.float64, device=x0.device)
         check(lib().kete_propagate_adjoint(C.byref(self.eph.c), _lib.ADJ_FWD, _ptr(x0.contiguous()), self.t0,
                                            self.t_end, self.n_obj, self.k_obs, _ptr(self.t_obs), _ptr(self.obs_pos),
@@ -278,7 +294,7 @@ class AdjointContext:
                                            _stream()))
         return sky
 
-    def backward(self, x0: torch.Tensor, dL_dsky: torch.Tensor) -> torch.Tensor:
+    def _run_backward(self, x0: torch.Tensor, dL_dsky: torch.Tensor) -> torch.Tensor:
         grad = torch.empty((self.n_obj, 6), dtype=torch.float64, device=x0.device)
         check(lib().kete_propagate_adjoint(C.byref(self.eph.c), _lib.ADJ_BWD, _ptr(x0.contiguous()), self.t0,
                                            self.t_end, self.n_obj, self.k_obs, _ptr(self.t_obs), _ptr(self.obs_pos),
@@ -296,11 +312,17 @@ class AdjointSky(torch.autograd.Function):
     def forward(fctx, x0: torch.Tensor, actx: AdjointContext):
         fctx.actx = actx
         fctx.save_for_backward(x0)
-        return actx.forward(x0.detach())
+        sky = actx.forward(x0.detach())
+        fctx.generation = actx.generation
+        return sky
 
     @staticmethod
     def backward(fctx, g_sky):
         (x0,) = fctx.saved_tensors
+        if fctx.generation != fctx.actx.generation:
+            raise RuntimeError("AdjointSky backward: a later forward call on the same AdjointContext has "
+                               "overwritten the checkpoints this gradient needs; use one context per pending "
+                               "backward")
         return fctx.actx.backward(x0.detach(), g_sky), None
 
 

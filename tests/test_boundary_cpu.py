@@ -215,3 +215,30 @@ def test_noalloc_magnitudes_rejects_too_many_frames():
     rc = L.kete_pair_magnitudes_noalloc(C.byref(et), fake, 10, 2, fake, fake, fake, C.byref(fr), fake, fake, 0,
                                         fake, fake, fake, None, None, None)
     assert rc == _lib.KETE_OK
+
+
+def test_adjoint_sky_refuses_a_stale_backward():
+    """Two forwards on one adjoint context before backward: the first
+    graph's backward would read the second call's checkpoints, so it must
+    raise; the latest one still runs.  The device calls are replaced by
+    host stand-ins: this checks the binding's bookkeeping only."""
+    import torch
+
+    class HostCtx(api.AdjointContext):
+        def __init__(self):
+            self.n_obj, self.k_obs, self.generation = 3, 2, 0
+
+        def _run_forward(self, x0):
+            return torch.zeros((self.n_obj, self.k_obs, 2), dtype=torch.float64)
+
+        def _run_backward(self, x0, g):
+            return torch.ones((self.n_obj, 6), dtype=torch.float64)
+
+    ctx = HostCtx()
+    x = torch.zeros((3, 6), dtype=torch.float64, requires_grad=True)
+    s1 = api.AdjointSky.apply(x, ctx)
+    s2 = api.AdjointSky.apply(x, ctx)
+    s2.sum().backward()
+    assert torch.equal(x.grad, torch.ones((3, 6), dtype=torch.float64))
+    with pytest.raises(RuntimeError, match="later forward"):
+        s1.sum().backward()
