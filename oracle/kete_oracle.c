@@ -72,6 +72,10 @@ typedef struct {
     int32_t n_threads;       /* OpenMP threads (0 = runtime default) */
     int64_t max_steps;       /* per object */
     double h_max;            /* largest allowed step magnitude (0 = none) */
+    int32_t extrapolate;     /* 1: start each step's corrector from the previous step's
+                                acceleration polynomial (RADAU's predictor, which App. A.6
+                                removes); 0: from zero, as the paper does (default) */
+    int32_t pad;
 } orc_opts;
 
 /* ------------------------------------------------------------------ */
@@ -271,8 +275,36 @@ typedef struct {
     /* replay: when set, steps are taken from this list without control */
     const double *replay; int64_t replay_n; int64_t replay_i;
     /* counters */
-    int64_t n_steps, n_iter, n_reject, n_force;
+    int64_t n_steps, n_iter, n_reject, n_force, n_pred;
+    /* corrector start from the last accepted step (extrapolate = 1) */
+    int extrapolate;
+    double b_prev[7][ORC_MAXD], h_prev;      /* h_prev = 0: no accepted step yet */
 } orc_radau;
+
+/* Largest ratio of a new step to the previous accepted one for which the
+ * corrector starts from the extrapolated polynomial. */
+#define ORC_PRED_MAX_RATIO 3.0
+
+/* The acceleration polynomial of a step, a(s) = a0 + sum_k b_k s^(k+1) on
+ * s in [0, 1], re-expanded about the step's end for a next step q times
+ * as long: with s = 1 + q sigma,
+ *   a = a(1) + sum_k b'_k sigma^(k+1),  b'_k = q^(k+1) sum_{j>=k} C(j+1, k+1) b_j
+ * (the binomial expansion of (1 + q sigma)^(j+1)).  One coordinate. */
+void orc_predict_b(const double b[7], double q, double bn[7])
+{
+    double qk = q;
+    for (int k = 0; k < 7; k++) {
+        double s = 0.0;
+        for (int j = k; j < 7; j++) {
+            /* C(j+1, k+1) */
+            double c = 1.0;
+            for (int i = 1; i <= k + 1; i++) c = c * (double)(j + 2 - i) / (double)i;
+            s += c * b[j];
+        }
+        bn[k] = qk * s;
+        qk *= q;
+    }
+}
 
 /* Advance (t, x, v) to t_target exactly.  *h_io carries the desired step
  * size from call to call.  Returns a per-object status. */
@@ -302,6 +334,24 @@ static int orc_radau_advance(orc_radau *R, double *t, double *x, double *v, doub
         if (st) return ORC_ST_ERANGE;
         for (int k = 0; k < 7; k++)
             for (int c = 0; c < D; c++) b[k][c] = g[k][c] = 0.0;   /* no predictor */
+        double q = R->h_prev != 0.0 ? h / R->h_prev : 0.0;
+        if (R->extrapolate && q > 0.0 && q <= ORC_PRED_MAX_RATIO) {
+            /* start from the previous step's polynomial, re-expanded (b), and
+             * the divided differences that give the same polynomial (g):
+             * b_m = sum_{k>=m} cc[k][m] g_k, solved from g_6 = b_6 down */
+            for (int c = 0; c < D; c++) {
+                double bo[7], bn[7];
+                for (int k = 0; k < 7; k++) bo[k] = R->b_prev[k][c];
+                orc_predict_b(bo, q, bn);
+                for (int k = 0; k < 7; k++) b[k][c] = bn[k];
+                for (int m = 6; m >= 0; m--) {
+                    double s = bn[m];
+                    for (int k = m + 1; k < 7; k++) s -= orc_cc[k][m] * g[k][c];
+                    g[m][c] = s;
+                }
+            }
+            R->n_pred++;
+        }
 
         double pc_err = 1e300, pc_last = 2e300;
         int it = 0;
@@ -370,6 +420,9 @@ static int orc_radau_advance(orc_radau *R, double *t, double *x, double *v, doub
         for (int c = 0; c < D; c++) if (!isfinite(x[c]) || !isfinite(v[c])) return ORC_ST_NONFINITE;
         *t = landed ? t_target : *t + h;
         R->n_steps++;
+        for (int k = 0; k < 7; k++)
+            for (int c = 0; c < D; c++) R->b_prev[k][c] = b[k][c];
+        R->h_prev = h;
         if (R->replay) R->replay_i++;
         if (R->rec) { if (R->rec_n < R->rec_cap) R->rec[R->rec_n] = h; R->rec_n++; }
         if (landed) {
@@ -431,22 +484,24 @@ static void orc_opts_fill(const orc_opts *o, orc_radau *R)
     R->safety = o->safety > 0 ? o->safety : 0.25;
     R->max_iter = o->max_iter > 0 ? o->max_iter : 12;
     R->max_steps = o->max_steps > 0 ? o->max_steps : 10000000;
+    R->extrapolate = o->extrapolate != 0;
 }
 
 static double orc_c(const orc_opts *o) { return (o && o->c_light > 0) ? o->c_light : ORC_C_AU_PER_DAY; }
 
 /* Propagate n_obj states from t0 to each t_out[e] (monotone in one
  * direction), chaining epoch to epoch.  x_out is [n_out][n_obj][6].
- * stats (optional) receives [steps, iterations, rejections, force evals]. */
+ * stats (optional) receives [steps, iterations, rejections, force evals,
+ * steps started from the extrapolated polynomial]. */
 int orc_propagate(const orc_ephem *E, const orc_opts *o, int64_t n_obj, const double *x0, double t0,
                   int64_t n_out, const double *t_out, double *x_out, int32_t *status, int64_t *stats)
 {
     if (n_obj < 0 || n_out < 0) return ORC_EINVAL;
     orc_init_nodes();
-    int64_t s_steps = 0, s_iter = 0, s_rej = 0, s_force = 0;
+    int64_t s_steps = 0, s_iter = 0, s_rej = 0, s_force = 0, s_pred = 0;
 #ifdef _OPENMP
     int nt = o->n_threads > 0 ? o->n_threads : omp_get_max_threads();
-#pragma omp parallel for schedule(dynamic, 4) num_threads(nt) reduction(+:s_steps, s_iter, s_rej, s_force)
+#pragma omp parallel for schedule(dynamic, 4) num_threads(nt) reduction(+:s_steps, s_iter, s_rej, s_force, s_pred)
 #endif
     for (int64_t j = 0; j < n_obj; j++) {
         orc_nbody_ctx ctx = { E, orc_c(o), 0 };
@@ -465,9 +520,9 @@ int orc_propagate(const orc_ephem *E, const orc_opts *o, int64_t n_obj, const do
             }
         }
         if (status) status[j] = st;
-        s_steps += R.n_steps; s_iter += R.n_iter; s_rej += R.n_reject; s_force += R.n_force;
+        s_steps += R.n_steps; s_iter += R.n_iter; s_rej += R.n_reject; s_force += R.n_force; s_pred += R.n_pred;
     }
-    if (stats) { stats[0] = s_steps; stats[1] = s_iter; stats[2] = s_rej; stats[3] = s_force; }
+    if (stats) { stats[0] = s_steps; stats[1] = s_iter; stats[2] = s_rej; stats[3] = s_force; stats[4] = s_pred; }
     return ORC_OK;
 }
 
@@ -498,6 +553,11 @@ static void stumpff(double z, double *C, double *S)
         *C = c; *S = s;
     }
 }
+
+/* Newton iterations one Kepler solve may take before it is reported as
+ * not converged (a test can lower it to force that report). */
+static int orc_kep_max_iter = 200;
+void orc_set_kepler_max_iter(int n) { orc_kep_max_iter = n > 0 ? n : 200; }
 
 /* Two-body state at dt from (r0, v0) about a fixed centre with parameter mu.
  * Solves sqrt(mu) dt = sigma0 chi^2 C + (1 - alpha r0) chi^3 S + r0 chi for
@@ -534,7 +594,7 @@ int orc_kepler(double mu, const double r0[3], const double v0[3], double dt, dou
         }
         (void)Flo; (void)Fhi;
         int it;
-        for (it = 0; it < 200; it++) {
+        for (it = 0; it < orc_kep_max_iter; it++) {
             KEPF(chi, Fv, Fp);
             if (Fv == 0.0) break;
             if (Fv < 0) lo = chi; else hi = chi;
@@ -544,7 +604,7 @@ int orc_kepler(double mu, const double r0[3], const double v0[3], double dt, dou
             chi = nx;
             if (fabs(dchi) <= 4.0 * 2.220446049250313e-16 * fabs(chi)) break;
         }
-        if (it == 200) return ORC_ST_KEPLER_NOCONV;
+        if (it == orc_kep_max_iter) return ORC_ST_KEPLER_NOCONV;
     }
 done:;
     double z = alpha * chi * chi, C, S;
@@ -613,18 +673,23 @@ int orc_lighttime(const orc_ephem *E, double c_light, double t_ref, const double
  * sub-frame s have n.d > 0.  Also returns the signed angular distance to
  * the nearest edge, asin(min_i n_i.d/|d|).  Output order: batch, frame
  * (as listed), object, sub-frame; the caller sorts.  *n_pairs receives the
- * total even when it exceeds cap. */
+ * total even when it exceeds cap.  An object any of whose light-time hops
+ * fails has no pairs at all; status_out (when not NULL) gets its status
+ * code, 0 for the others. */
 int orc_fov(const orc_ephem *E, double c_light, int64_t n_obj, const double *x_epoch, const int32_t *status,
             int64_t n_batch, const double *t_ref, const int64_t *batch_off, const int64_t *frame_order,
             const double *ft, const double *fobs, int32_t n_sub, const double *normals,
-            int64_t cap, int32_t *pf, int32_t *ps, int32_t *po, double *edge, int64_t *n_pairs, int32_t n_threads)
+            int64_t cap, int32_t *pf, int32_t *ps, int32_t *po, double *edge, int64_t *n_pairs, int32_t n_threads,
+            int32_t *status_out)
 {
     if (c_light <= 0) c_light = ORC_C_AU_PER_DAY;
     int64_t total = 0;
     int64_t n_frames_all = batch_off[n_batch];
     /* per sorted-frame counts first, so the output order is deterministic */
     int64_t *cnt = (int64_t *)calloc((size_t)(n_frames_all + 1), sizeof(int64_t));
-    if (!cnt) return ORC_EINVAL;
+    int32_t *failed = (int32_t *)calloc((size_t)(n_obj > 0 ? n_obj : 1), sizeof(int32_t));
+    if (!cnt || !failed) { free(cnt); free(failed); return ORC_EINVAL; }
+    int any_failed = 0, recount = 0;
     for (int pass = 0; pass < 2; pass++) {
 #ifdef _OPENMP
         int nt = n_threads > 0 ? n_threads : omp_get_max_threads();
@@ -637,9 +702,24 @@ int orc_fov(const orc_ephem *E, double c_light, int64_t n_obj, const double *x_e
             int64_t k = pass ? cnt[q] : 0;
             for (int64_t j = 0; j < n_obj; j++) {
                 if (status && status[j]) continue;
+                if (pass == 1 || recount) {
+                    int fj;
+#ifdef _OPENMP
+#pragma omp atomic read
+#endif
+                    fj = failed[j];
+                    if (fj) continue;
+                }
                 const double *st = x_epoch + (b * n_obj + j) * 6;
                 double d[3], tau;
-                if (orc_lighttime(E, c_light, t_ref[b], st, ft[f], fobs + 3 * f, d, &tau, NULL)) continue;
+                int lst = orc_lighttime(E, c_light, t_ref[b], st, ft[f], fobs + 3 * f, d, &tau, NULL);
+                if (lst) {
+#ifdef _OPENMP
+#pragma omp atomic write
+#endif
+                    failed[j] = lst;
+                    continue;
+                }
                 double dn = sqrt(dot3(d, d));
                 for (int s = 0; s < n_sub; s++) {
                     const double *nn = normals + ((f * n_sub + s) * 4) * 3;
@@ -660,6 +740,15 @@ int orc_fov(const orc_ephem *E, double c_light, int64_t n_obj, const double *x_e
             }
             if (pass == 0) cnt[q] = k;
         }
+        if (pass == 0 && !recount) {
+            for (int64_t j = 0; j < n_obj; j++) if (failed[j]) any_failed = 1;
+            if (any_failed) {
+                /* count again without the failed objects' pairs */
+                recount = 1;
+                pass = -1;
+                continue;
+            }
+        }
         if (pass == 0) {
             /* exclusive scan */
             int64_t run = 0;
@@ -668,6 +757,8 @@ int orc_fov(const orc_ephem *E, double c_light, int64_t n_obj, const double *x_e
         }
     }
     free(cnt);
+    if (status_out) for (int64_t j = 0; j < n_obj; j++) status_out[j] = failed[j];
+    free(failed);
     *n_pairs = total;
     return total > cap ? ORC_ECAPACITY : ORC_OK;
 }

@@ -43,7 +43,8 @@ class Ephem(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("eps", C.c_double), ("h_init", C.c_double), ("h_min", C.c_double),
                 ("safety", C.c_double), ("c_light", C.c_double), ("max_iter", C.c_int32),
-                ("n_threads", C.c_int32), ("max_steps", C.c_int64), ("h_max", C.c_double)]
+                ("n_threads", C.c_int32), ("max_steps", C.c_int64), ("h_max", C.c_double),
+                ("extrapolate", C.c_int32), ("pad", C.c_int32)]
 
 
 _lib = None
@@ -87,11 +88,20 @@ def _eph(e):
 
 
 def make_opts(eps=1e-9, h_init=1.0, h_min=1e-9, safety=0.25, c_light=0.0, max_iter=12,
-              n_threads=0, max_steps=10_000_000, h_max=0.0):
-    return Opts(eps, h_init, h_min, safety, c_light, max_iter, n_threads, max_steps, h_max)
+              n_threads=0, max_steps=10_000_000, h_max=0.0, extrapolate=0):
+    return Opts(eps, h_init, h_min, safety, c_light, max_iter, n_threads, max_steps, h_max, extrapolate, 0)
 
 
 DEFAULT_OPTS = dict(eps=1e-9, h_init=1.0)
+
+
+def predict_b(b, q):
+    """RADAU's predictor for one coordinate: the coefficients b' of the
+    previous step's acceleration polynomial about its end, for a step q
+    times as long."""
+    bn = np.zeros(7)
+    lib().orc_predict_b(_p(_f64(b)), C.c_double(q), _p(bn))
+    return bn
 
 
 def radau_nodes():
@@ -145,12 +155,14 @@ def directions(eph, states, t_ref, t_obs, obs, c_light=C_AU_PER_DAY):
 
 
 def propagate(eph, x0, t0, t_out, opts=None, **kw):
-    """States at each t_out: returns (x_out [E, N, 6], status [N], stats[4])."""
+    """States at each t_out: returns (x_out [E, N, 6], status [N], stats[5]:
+    steps, corrector sweeps, rejections, force evaluations, steps started
+    from the extrapolated polynomial)."""
     e = _eph(eph)
     o = opts if opts is not None else make_opts(**{**DEFAULT_OPTS, **kw})
     x0 = _f64(x0); t_out = _f64(np.atleast_1d(t_out))
     n = x0.shape[0]; E = t_out.shape[0]
-    x_out = np.zeros((E, n, 6)); status = np.zeros(n, np.int32); stats = np.zeros(4, np.int64)
+    x_out = np.zeros((E, n, 6)); status = np.zeros(n, np.int32); stats = np.zeros(5, np.int64)
     rc = lib().orc_propagate(e.ref, C.byref(o), C.c_int64(n), _p(x0), C.c_double(t0), C.c_int64(E),
                              _p(t_out), _p(x_out), _p(status, C.c_int32), _p(stats, C.c_int64))
     if rc:
@@ -180,8 +192,10 @@ def make_batches(t, span=3.0):
 
 
 def fov(eph, x_epoch, status, frame_order, batch_off, t_ref, frames_t, frames_obs, normals,
-        cap=None, c_light=C_AU_PER_DAY, n_threads=0):
-    """Brute-force pairs sorted by (frame, sub, object), with edge distances."""
+        cap=None, c_light=C_AU_PER_DAY, n_threads=0, return_status=False):
+    """Brute-force pairs sorted by (frame, sub, object), with edge distances
+    (and, with return_status, the per-object status of the light-time hops:
+    an object with a failed hop has no pairs)."""
     e = _eph(eph)
     x_epoch = _f64(x_epoch)
     n_batch, n_obj = x_epoch.shape[:2]
@@ -191,6 +205,7 @@ def fov(eph, x_epoch, status, frame_order, batch_off, t_ref, frames_t, frames_ob
     fo = np.ascontiguousarray(frame_order, np.int64); bo = np.ascontiguousarray(batch_off, np.int64)
     tr = _f64(t_ref); ft = _f64(frames_t); fobs = _f64(frames_obs)
     n_pairs = C.c_int64(0)
+    st_out = np.zeros(n_obj, np.int32)
     for attempt in range(2):
         cap_ = cap if cap is not None else 1 << 16
         if attempt == 1:
@@ -200,7 +215,8 @@ def fov(eph, x_epoch, status, frame_order, batch_off, t_ref, frames_t, frames_ob
         rc = lib().orc_fov(e.ref, C.c_double(c_light), C.c_int64(n_obj), _p(x_epoch), _p(status, C.c_int32),
                            C.c_int64(n_batch), _p(tr), _p(bo, C.c_int64), _p(fo, C.c_int64), _p(ft), _p(fobs),
                            C.c_int32(n_sub), _p(normals), C.c_int64(cap_), _p(pf, C.c_int32), _p(ps, C.c_int32),
-                           _p(po, C.c_int32), _p(edge), C.byref(n_pairs), C.c_int32(n_threads))
+                           _p(po, C.c_int32), _p(edge), C.byref(n_pairs), C.c_int32(n_threads),
+                           _p(st_out, C.c_int32))
         if rc == 0:
             break
         if cap is not None:
@@ -208,7 +224,15 @@ def fov(eph, x_epoch, status, frame_order, batch_off, t_ref, frames_t, frames_ob
     n = int(n_pairs.value)
     pf, ps, po, edge = pf[:n], ps[:n], po[:n], edge[:n]
     order = np.lexsort((po, ps, pf))
+    if return_status:
+        return pf[order], ps[order], po[order], edge[order], st_out
     return pf[order], ps[order], po[order], edge[order]
+
+
+def set_kepler_max_iter(n: int) -> None:
+    """Newton iterations one Kepler solve may take (0 restores the default,
+    200); fewer force the not-converged report in tests."""
+    lib().orc_set_kepler_max_iter(C.c_int(n))
 
 
 def sky_grad(eph, x0, t0, t_obs, obs_pos, radec_obs, want_grad=True, opts=None, **kw):
