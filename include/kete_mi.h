@@ -112,7 +112,8 @@ typedef struct {
                                 0: grouped integrators land only on the last epoch of each
                                 launch and read the others off the collocation polynomial
                                 of the step that spans them (0) */
-    int32_t reserved;
+    int32_t kepler_iter;     /* iterations of one universal-variable solve before the hop is
+                                KETE_ST_KEPLER_NOCONV (60; 0 = default) */
 } kete_opts_t;
 
 /* Frames (Sect. 3.1): an instantaneous observation at time t from the
@@ -234,9 +235,12 @@ size_t kete_fov_workspace_size(int64_t n_obj, int64_t n_frames, int64_t n_batch,
  * (iterated to lt_tol); (f, s, j) is a pair when all four normals of
  * sub-frame s have a positive dot product with the direction.  Objects
  * are binned on the sky so that only bodies that can reach a frame within
- * the batch are tested exactly.
+ * the batch are tested exactly.  An object one of whose hops ends on
+ * the Kepler iteration cap (opts->kepler_iter) without converging loses all
+ * of its pairs and gets KETE_ST_KEPLER_NOCONV in status (when given).
  *   x_epoch     device [n_batch][n_obj][6]
- *   status      device [n_obj] or NULL
+ *   status      device [n_obj] or NULL: in, objects to skip (non-zero);
+ *               out, KETE_ST_KEPLER_NOCONV for objects whose hop failed
  *   t_ref       device [n_batch]
  *   batch_off   device [n_batch + 1]
  *   frame_order device [n_frames]
@@ -248,7 +252,7 @@ size_t kete_fov_workspace_size(int64_t n_obj, int64_t n_frames, int64_t n_batch,
  * KETE_ECAPACITY (outputs unspecified) when the pairs or the candidates
  * do not fit; *n_pairs then holds a pairs_cap to retry with, large
  * enough for both as far as they were counted. */
-int kete_fov_check(const kete_ephem_t *eph, const double *x_epoch, const int32_t *status,
+int kete_fov_check(const kete_ephem_t *eph, const double *x_epoch, int32_t *status,
                    int64_t n_obj, int64_t n_batch, const double *t_ref, const int32_t *batch_off,
                    const int32_t *frame_order, const kete_frames_t *frames, const kete_opts_t *opts,
                    int32_t *pf, int32_t *ps, int32_t *po, int64_t pairs_cap, int64_t *n_pairs,
@@ -279,10 +283,9 @@ size_t kete_magnitudes_workspace_size(int64_t n_frames);
  *   g_slope     device [n_obj]: slope parameter G
  *   v_mag       device out [n_pairs]
  *   geom        device out [n_pairs][3] {r_H au, Delta au, alpha rad}, or NULL
- * A pair whose frame is in no batch, whose indices are out of range or
- * whose emission time leaves the ephemeris gets NaN; a hop that fails
- * gives a non-finite value.  Like the membership test, the hop's value is
- * used when its Kepler iteration stops on the iteration cap.
+ * A pair whose frame is in no batch, whose indices are out of range,
+ * whose emission time leaves the ephemeris or whose hop ends on the Kepler
+ * iteration cap (opts->kepler_iter) without converging gets NaN.
  * Asynchronous on `stream`; the caller owns every buffer.
  * Errors: KETE_EINVAL, KETE_EWORKSPACE, KETE_EDEVICE. */
 int kete_pair_magnitudes(const kete_ephem_t *eph, const double *x_epoch, int64_t n_obj, int64_t n_batch,
@@ -317,7 +320,8 @@ int kete_pair_magnitudes_noalloc(const kete_ephem_t *eph, const double *x_epoch,
  * d = x_e - obs[q] of object j (state x_ref[j] at t_ref) at the emission
  * time t_obs[q] - tau.
  *   x_ref  device [n_obj][6]; t_obs device [n_q]; obs device [n_q][3]
- *   d      device out [n_q][n_obj][3]; tau device out [n_q][n_obj] or NULL */
+ *   d      device out [n_q][n_obj][3]; tau device out [n_q][n_obj] or NULL
+ * A hop that ends on the Kepler iteration cap without converging gives NaN. */
 int kete_lighttime_directions(const kete_ephem_t *eph, const double *x_ref, double t_ref, int64_t n_obj,
                               const double *t_obs, const double *obs, int64_t n_q,
                               double *d, double *tau, const kete_opts_t *opts, void *stream);
@@ -346,6 +350,9 @@ size_t kete_adjoint_workspace_size(int64_t n_obj, int32_t k_obs, double t0, doub
  * polynomial, the light-time hop of Sect. 2 back to the emission time,
  * and RA/Dec (radians) in the equatorial J2000 frame (ecliptic rotated by
  * the obliquity 84381.448").
+ *   An observation whose hop ends on the Kepler iteration cap
+ *   (opts->kepler_iter) gets a NaN sky position and its object
+ *   KETE_ST_KEPLER_NOCONV (so a zero gradient).
  *   mode KETE_ADJ_FWD: writes sky_out [N][K][2] and status [N], and stores
  *     in the workspace a checkpoint per ckpt_days (checkpoint c: the state
  *     at the first integration step starting at or after t0 + c ckpt_days,

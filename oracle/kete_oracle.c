@@ -526,6 +526,25 @@ int orc_propagate(const orc_ephem *E, const orc_opts *o, int64_t n_obj, const do
     return ORC_OK;
 }
 
+/* The accepted step sizes of one object integrated from t0 to t1 on its
+ * own (rec[0..*n) signed days, at most cap recorded; *n is the full count).
+ * For studying how well objects that share a wavefront's steps match. */
+int orc_step_trace(const orc_ephem *E, const orc_opts *o, const double x0[6], double t0, double t1,
+                   double *rec, int64_t cap, int64_t *n)
+{
+    orc_init_nodes();
+    orc_nbody_ctx ctx = { E, orc_c(o), 0 };
+    orc_radau R; memset(&R, 0, sizeof(R));
+    R.D = 3; R.D_ctrl = 3; R.force = orc_nbody_force; R.ctx = &ctx;
+    orc_opts_fill(o, &R);
+    R.rec = rec; R.rec_cap = cap;
+    double x[3], v[3], t = t0, h = o->h_init > 0 ? o->h_init : 1.0;
+    for (int i = 0; i < 3; i++) { x[i] = x0[i]; v[i] = x0[3 + i]; }
+    int st = orc_radau_advance(&R, &t, x, v, t1, &h);
+    *n = R.rec_n;
+    return st;
+}
+
 /* ------------------------------------------------------------------ */
 /* Universal-variable Kepler hop (Sect. 2: two-body motion in a batch). */
 /* ------------------------------------------------------------------ */

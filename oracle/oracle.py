@@ -170,6 +170,19 @@ def propagate(eph, x0, t0, t_out, opts=None, **kw):
     return x_out, status, stats
 
 
+def step_trace(eph, x0, t0, t1, opts=None, **kw):
+    """Accepted step sizes (days, signed) of one object integrated alone
+    from t0 to t1."""
+    e = _eph(eph)
+    o = opts if opts is not None else make_opts(**{**DEFAULT_OPTS, **kw})
+    rec = np.zeros(1 << 16); n = C.c_int64(0)
+    st = lib().orc_step_trace(e.ref, C.byref(o), _p(_f64(x0)), C.c_double(t0), C.c_double(t1), _p(rec),
+                              C.c_int64(rec.size), C.byref(n))
+    if st:
+        raise ValueError(f"oracle step trace status {st}")
+    return rec[:min(n.value, rec.size)].copy()
+
+
 def make_batches(t, span=3.0):
     """Greedy batching of frames (Sect. 2): sort by (time, index); a batch
     starts at its first frame and takes every following frame within

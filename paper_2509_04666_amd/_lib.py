@@ -42,7 +42,7 @@ class OptsT(C.Structure):
                 ("window_segs", C.c_int32), ("lt_iter", C.c_int32), ("fov_block", C.c_int32),
                 ("adj_seg_steps", C.c_int32), ("persist_waves", C.c_int32),
                 ("lanes_per_body", C.c_int32), ("zero_start", C.c_int32),
-                ("land_epochs", C.c_int32), ("reserved", C.c_int32)]
+                ("land_epochs", C.c_int32), ("kepler_iter", C.c_int32)]
 
 
 class FramesT(C.Structure):

@@ -138,7 +138,10 @@ class Batches:
 def fov_check(eph: DeviceEphemeris, x_epoch: torch.Tensor, batches: Batches, frames: DeviceFrames,
               status: Optional[torch.Tensor] = None, opts: Optional[OptsT] = None, pairs_cap: Optional[int] = None,
               workspace: Optional[torch.Tensor] = None, return_stats: bool = False):
-    """Pairs sorted by (frame, sub-frame, object): (pf, ps, po) int32 tensors."""
+    """Pairs sorted by (frame, sub-frame, object): (pf, ps, po) int32 tensors.
+    status [N] int32 (optional) is read (objects to skip) and updated in
+    place: an object whose hop ends on the Kepler iteration cap gets
+    KETE_ST_KEPLER_NOCONV and loses all of its pairs."""
     opts = opts or default_opts()
     x_epoch = x_epoch.contiguous()
     B, N = x_epoch.shape[0], x_epoch.shape[1]

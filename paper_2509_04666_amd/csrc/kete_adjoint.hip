@@ -135,7 +135,7 @@ __device__ __forceinline__ int hop(const AdjParams& p, const SunGlobal& sun, dou
     sun.eval(t_obs, S, Sd);
     for (int i = 0; i < 3; ++i) { r0[i] = xs[i] - S[i]; v0[i] = vs[i] - Sd[i]; }
     return lighttime(sun, p.eph.gm[0], p.smu, p.c_light, p.lt_tol, p.lt_iter, t_obs, r0, v0, t_obs, o, d, tau, ve,
-                     &chi);
+                     &chi, p.kepler_iter);
 }
 
 // The same hop from the light time and universal anomaly the forward
@@ -146,7 +146,7 @@ __device__ __forceinline__ void hop_known(const AdjParams& p, const SunGlobal& s
     double S[3], Sd[3], r[3], v[3], Se[3], Sde[3];
     sun.eval(t_obs, S, Sd);
     for (int i = 0; i < 3; ++i) { r0[i] = xs[i] - S[i]; v0[i] = vs[i] - Sd[i]; }
-    kepler_uv(p.eph.gm[0], p.smu, r0, v0, -tau, chi, r, v);
+    kepler_uv(p.eph.gm[0], p.smu, r0, v0, -tau, chi, r, v, p.kepler_iter);
     sun.eval(t_obs - tau, Se, Sde);
     for (int i = 0; i < 3; ++i) {
         d[i] = Se[i] + r[i] - o[i];
@@ -305,7 +305,9 @@ __global__ __launch_bounds__(64, 3) void k_adjoint_fwd(const AdjParams p) {
 }
 
 // Sky position of every observation from its stored state (forward), one
-// lane per (object, observation); failed objects get NaN.
+// lane per (object, observation); failed objects get NaN, and so does an
+// observation whose hop ends on the Kepler iteration cap (its light time
+// is stored as NaN for k_obs_status).
 __global__ __launch_bounds__(256) void k_obs_sky(const AdjParams p) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (int64_t)p.n_obj * p.k_obs) return;
@@ -315,13 +317,30 @@ __global__ __launch_bounds__(256) void k_obs_sky(const AdjParams p) {
     const SunGlobal sun{p.eph};
     const double* st = p.obs_state + 6 * i;
     double d[3], tau, ve[3], r0[3], v0[3], chi;
-    hop(p, sun, p.t_obs[i], st, st + 3, p.obs_pos + 3 * i, d, tau, ve, r0, v0, chi);
+    if (hop(p, sun, p.t_obs[i], st, st + 3, p.obs_pos + 3 * i, d, tau, ve, r0, v0, chi)) {
+        out[0] = out[1] = __builtin_nan("");
+        p.obs_hop[2 * i] = p.obs_hop[2 * i + 1] = __builtin_nan("");
+        return;
+    }
     double ra, dec, J[6];
     radec(d, p.cos_eps, p.sin_eps, ra, dec, J);
     out[0] = ra;
     out[1] = dec;
     p.obs_hop[2 * i] = tau;
     p.obs_hop[2 * i + 1] = chi;
+}
+
+// Objects with an observation whose hop failed (NaN light time) get
+// KETE_ST_KEPLER_NOCONV, so the backward gives them a zero gradient.  A
+// kernel of its own: k_obs_sky's lanes of one object read the status
+// they would otherwise be writing.
+__global__ void k_obs_status(const AdjParams p) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= p.n_obj || p.status[j] != 0) return;
+    for (int k = 0; k < p.k_obs; ++k) {
+        const double tau = p.obs_hop[2 * (j * p.k_obs + k)];
+        if (!(tau == tau)) { p.status[j] = KETE_ST_KEPLER_NOCONV; return; }
+    }
 }
 
 // dL/d(state) of every observation (backward), one lane per observation.
@@ -766,7 +785,10 @@ hipError_t launch_adjoint(const AdjParams& p, int mode, hipStream_t s) {
         else if (nb == 3 && ngr == 2 && d1 == 13)
             hipLaunchKernelGGL((k_adjoint_fwd<3, 2, 13>), dim3(grid), dim3(64), lds, s, p);
         else hipLaunchKernelGGL((k_adjoint_fwd<0, 0, 0>), dim3(grid), dim3(64), lds, s, p);
-        if (n_o > 0) hipLaunchKernelGGL(k_obs_sky, dim3(go), dim3(256), 0, s, p);
+        if (n_o > 0) {
+            hipLaunchKernelGGL(k_obs_sky, dim3(go), dim3(256), 0, s, p);
+            hipLaunchKernelGGL(k_obs_status, dim3((unsigned)((p.n_obj + 255) / 256)), dim3(256), 0, s, p);
+        }
         return hipGetLastError();
     }
     if (n_o > 0) hipLaunchKernelGGL(k_obs_vjp, dim3(go), dim3(256), 0, s, p);

@@ -52,6 +52,7 @@ struct AdjParams {
     double eps, h_min, h_max, h_init, safety;
     double smu, c_light, lt_tol, cos_eps, sin_eps;
     int32_t lt_iter;
+    int32_t kepler_iter;
     int32_t zero_start;         // correctors start from zero increments (no extrapolation)
 };
 

@@ -21,7 +21,10 @@
 #include "kete_mi.h"
 
 namespace kete {
-hipError_t launch_hpref_init(const double* x0, double* h_pref, int n, double mu, hipStream_t s);
+hipError_t launch_hpref_init(const double* x0, double* h_pref, uint32_t* keys, int n, double mu, double dt_lo,
+                             double dt_hi, int n_class, hipStream_t s);
+hipError_t launch_body_sort(const uint32_t* keys, int n, int n_class, int32_t* perm, int32_t* tmp, int32_t* counts,
+                            hipStream_t s);
 hipError_t launch_iota(int32_t* perm, int n, hipStream_t s);
 size_t bucket_scratch_ints(int64_t n_obj, int n_buckets);
 }  // namespace kete
@@ -343,6 +346,7 @@ void kete_default_opts(kete_opts_t* o) {
     o->lt_iter = 10;
     o->fov_block = 128;
     o->adj_seg_steps = 32;
+    o->kepler_iter = kKeplerIterDefault;
 }
 
 int kete_make_batches(const double* t, int64_t n_frames, double span, int32_t* frame_order, int32_t* batch_off,
@@ -404,6 +408,38 @@ static void auto_integrator_shape(const kete_ephem_t* eph, bool dense, int& bloc
 
 // The output epochs and the dense-output rows travel in front of the window
 // plan (one staged copy).
+// Step-size buckets of the batched jobs' sort: kBucketSub per octave over
+// opts->n_buckets octaves (1 octave: no sort).
+static int bucket_count(const kete_opts_t* o) {
+    const int oct = std::min(std::max(1, o->n_buckets), 32);
+    return oct > 1 ? oct * kBucketSub : 1;
+}
+
+// Step classes of the body sort (the critical class and kClassSub per
+// octave over opts->n_buckets octaves; 1: no sort).
+static int sort_classes(const kete_opts_t* o) {
+    const int oct = std::min(std::max(1, o->n_buckets), 32);
+    return oct > 1 ? 1 + kClassSub * oct : 1;
+}
+
+// Scratch of the body sort: counting-sort counts, then the keys and the
+// first pass's order (ints).
+static size_t sort_scratch_ints(int64_t n_obj) {
+    return bucket_scratch_ints(n_obj, kMaxBuckets) + 2 * (size_t)n_obj + 64;
+}
+struct SortScratch {
+    int32_t* counts;
+    uint32_t* keys;
+    int32_t* tmp;
+};
+static SortScratch sort_scratch(int32_t* base, int64_t n_obj) {
+    SortScratch S;
+    S.counts = base;
+    S.keys = reinterpret_cast<uint32_t*>(base + bucket_scratch_ints(n_obj, kMaxBuckets));
+    S.tmp = reinterpret_cast<int32_t*>(S.keys + n_obj);
+    return S;
+}
+
 static size_t epoch_table_bytes(int64_t n_out) {
     return ((((size_t)n_out + kDenseCoefDoubles) * sizeof(double)) + 31) & ~(size_t)31;
 }
@@ -411,7 +447,6 @@ static size_t epoch_table_bytes(int64_t n_out) {
 size_t kete_propagate_workspace_size(int64_t n_obj, int64_t n_out, const kete_opts_t* opts) {
     kete_opts_t d;
     if (!opts) { kete_default_opts(&d); opts = &d; }
-    const int nbk = std::max(1, opts->n_buckets);
     const int wsegs = std::max(1, opts->window_segs);
     // windows: epochs plus at most one extra per wsegs segments of span;
     // the span is unknown here, so reserve generously and check at call time
@@ -422,7 +457,7 @@ size_t kete_propagate_workspace_size(int64_t n_obj, int64_t n_out, const kete_op
     c.take<double>((size_t)n_obj);
     c.take<int32_t>((size_t)n_obj);
     c.take<char>(epoch_table_bytes(n_out) + (size_t)max_win * sizeof(Window));
-    c.take<int32_t>(bucket_scratch_ints(n_obj, nbk));
+    c.take<int32_t>(sort_scratch_ints(n_obj));
     return c.off;
 }
 
@@ -459,7 +494,7 @@ int kete_propagate_nbody(const kete_ephem_t* eph, const double* x0, double t0, i
         return fail(KETE_EINVAL, "lanes_per_body must be 1, 7 or 8");
     if (!(opts->eps > 0) || !(opts->h_init > 0) || !(opts->h_min > 0) || opts->max_iter < 1 || opts->max_steps < 1)
         return fail(KETE_EINVAL, "eps, h_init, h_min, max_iter and max_steps must be positive");
-    const int nbk = std::min(std::max(1, opts->n_buckets), 32);
+    const int ncls = sort_classes(opts);
     const bool dense = !opts->land_epochs && opts->lanes_per_body != 1;
     int block = opts->block, wsegs = opts->window_segs;
     auto_integrator_shape(eph, dense, block, wsegs);
@@ -506,7 +541,7 @@ int kete_propagate_nbody(const kete_ephem_t* eph, const double* x0, double t0, i
     double* dcoef = (double*)plan;
     double* dt_out = dcoef + kDenseCoefDoubles;
     Window* dwin = (Window*)(plan + epoch_table_bytes(n_out));
-    int32_t* bscratch = c.take<int32_t>(bucket_scratch_ints(n_obj, nbk));
+    const SortScratch sorts = sort_scratch(c.take<int32_t>(sort_scratch_ints(n_obj)), n_obj);
 
     hipStream_t s = (hipStream_t)stream;
     {
@@ -519,8 +554,7 @@ int kete_propagate_nbody(const kete_ephem_t* eph, const double* x0, double t0, i
         if ((rc = stage_to_device(plan, host.data(), host.size(), s))) return rc;
     }
     HIPCHK(hipMemcpyAsync(state, x0, (size_t)n_obj * 6 * sizeof(double), hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipMemsetAsync(status, 0, (size_t)n_obj * sizeof(int32_t), s));
-    HIPCHK(launch_hpref_init(x0, h_pref, (int)n_obj, E.gm[0], s));
+    HIPCHK(fill_zero(status, (size_t)n_obj * sizeof(int32_t), s));
 
     NbodyParams P;
     std::memset(&P, 0, sizeof(P));
@@ -550,16 +584,18 @@ int kete_propagate_nbody(const kete_ephem_t* eph, const double* x0, double t0, i
         const int last = epoch_win[e1];
         P.e_first = dense ? (int32_t)e0 : (int32_t)e1;
         P.e_land = (int32_t)e1;
-        if (nbk > 1) {
-            BucketParams B;
-            B.h_pref = h_pref;
-            B.status = status;
-            B.perm = perm;
-            B.counts = bscratch;
-            B.n_obj = (int32_t)n_obj;
-            B.n_buckets = nbk;
-            B.h_ref = 1.0 / 64.0;
-            HIPCHK(launch_bucket(B, s));
+        // predicted steps and the body order over this launch's span, from
+        // the bodies' states at its start
+        const double ta = e0 == 0 ? t0 : t_out[e0 - 1];
+        double dt_lo = 0.0, dt_hi = 0.0;
+        for (int64_t k = e0; k <= e1; ++k) {
+            dt_lo = std::min(dt_lo, t_out[k] - ta);
+            dt_hi = std::max(dt_hi, t_out[k] - ta);
+        }
+        HIPCHK(launch_hpref_init(state, h_pref, ncls > 1 ? sorts.keys : nullptr, (int)n_obj, E.gm[0], dt_lo, dt_hi,
+                                 ncls, s));
+        if (ncls > 1) {
+            HIPCHK(launch_body_sort(sorts.keys, (int)n_obj, ncls, perm, sorts.tmp, sorts.counts, s));
             P.perm = perm;
         } else {
             P.perm = nullptr;
@@ -583,6 +619,25 @@ static int64_t cand_capacity(int64_t n_frames, int64_t pairs_cap) {
 
 // pairs_cap to retry with after a capacity failure: room for the pairs
 // found and, with one pair per candidate, for every counted candidate.
+// Device counters of the FoV stages: [0] pairs, [1..4] statistics,
+// [5] candidates, [6] wide objects, [7] join work-queue cursor, [8] failed
+// hops, [9] pairs kept after dropping failed objects.
+constexpr int kFovCounters = 16;
+
+// Drops the pairs of objects whose hop failed (n_fail > 0): survivors of
+// keys[0..np) go to `out`, and their count is read back (one more
+// synchronization, taken only when a hop failed).
+static int drop_failed_pairs(const unsigned long long* keys, int64_t np, const int32_t* fail_flags,
+                             unsigned long long* out, unsigned long long* counters, int64_t* kept, hipStream_t s) {
+    HIPCHK(fill_zero(counters + 9, sizeof(unsigned long long), s));
+    HIPCHK(fov_drop_failed(keys, np, fail_flags, out, counters + 9, s));
+    unsigned long long k = 0;
+    HIPCHK(hipMemcpyAsync(&k, counters + 9, sizeof(k), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    *kept = (int64_t)k;
+    return KETE_OK;
+}
+
 static int64_t retry_pairs_cap(int64_t pairs, int64_t cands, int64_t pairs_cap) {
     return std::max<int64_t>(std::max<int64_t>(pairs, cands), pairs_cap + 1);
 }
@@ -600,7 +655,7 @@ size_t kete_fov_workspace_size(int64_t n_obj, int64_t n_frames, int64_t n_batch,
                                const kete_opts_t* opts) {
     kete_opts_t d;
     if (!opts) { kete_default_opts(&d); opts = &d; }
-    (void)n_obj; (void)n_sub;
+    (void)n_sub;
     int G; double L;
     if (grid_dims(opts, n_batch, G, L)) return 0;
     const int64_t nkeys = n_batch * ((int64_t)G * G * G + 1);
@@ -613,7 +668,7 @@ size_t kete_fov_workspace_size(int64_t n_obj, int64_t n_frames, int64_t n_batch,
     c.take<int32_t>((size_t)n_frames);
     c.take<double>((size_t)n_frames * 8);           // frame caps in cell order
     c.take<unsigned long long>((size_t)std::max<int64_t>(pairs_cap, 1));
-    c.take<unsigned long long>(8);
+    c.take<unsigned long long>(kFovCounters);
     c.take<int32_t>((size_t)n_frames + 1);
     c.take<int32_t>((size_t)n_frames + 1);
     c.take<unsigned long long>((size_t)std::max<int64_t>(pairs_cap, 1));
@@ -635,10 +690,11 @@ size_t kete_fov_workspace_size(int64_t n_obj, int64_t n_frames, int64_t n_batch,
     c.take<int64_t>((size_t)n_batch);
     c.take<int32_t>((size_t)n_batch);              // grid sizes and key offsets
     c.take<int64_t>((size_t)n_batch + 1);
+    c.take<int32_t>((size_t)std::max<int64_t>(n_obj, 1));   // objects whose hop failed
     return c.off;
 }
 
-int kete_fov_check(const kete_ephem_t* eph, const double* x_epoch, const int32_t* status, int64_t n_obj,
+int kete_fov_check(const kete_ephem_t* eph, const double* x_epoch, int32_t* status, int64_t n_obj,
                    int64_t n_batch, const double* t_ref, const int32_t* batch_off, const int32_t* frame_order,
                    const kete_frames_t* frames, const kete_opts_t* opts, int32_t* pf, int32_t* ps, int32_t* po,
                    int64_t pairs_cap, int64_t* n_pairs, void* workspace, size_t ws_bytes, void* stream) {
@@ -682,7 +738,7 @@ int kete_fov_check(const kete_ephem_t* eph, const double* x_epoch, const int32_t
     P.cell_frames = c.take<int32_t>((size_t)F);
     P.cell_caps = c.take<double>((size_t)F * 8);
     P.pairs = c.take<unsigned long long>((size_t)std::max<int64_t>(pairs_cap, 1));
-    unsigned long long* counters = c.take<unsigned long long>(8);
+    unsigned long long* counters = c.take<unsigned long long>(kFovCounters);
     int32_t* fcnt = c.take<int32_t>((size_t)F + 1);
     int32_t* fstart = c.take<int32_t>((size_t)F + 1);
     unsigned long long* sorted = c.take<unsigned long long>((size_t)std::max<int64_t>(pairs_cap, 1));
@@ -705,6 +761,9 @@ int kete_fov_check(const kete_ephem_t* eph, const double* x_epoch, const int32_t
     int64_t* b_xoff = c.take<int64_t>((size_t)n_batch);
     int32_t* b_G = c.take<int32_t>((size_t)n_batch);
     int64_t* b_koff = c.take<int64_t>((size_t)n_batch + 1);
+    P.fail = c.take<int32_t>((size_t)std::max<int64_t>(n_obj, 1));
+    P.status_out = status;
+    P.n_fail = counters + 8;
     P.b_poff = b_poff;
     P.b_obj0 = b_obj0;
     P.b_xoff = b_xoff;
@@ -735,11 +794,14 @@ int kete_fov_check(const kete_ephem_t* eph, const double* x_epoch, const int32_t
     P.c_light = cl;
     P.lt_tol = opts->lt_tol > 0 ? opts->lt_tol : 1e-15;
     P.lt_iter = opts->lt_iter > 0 ? opts->lt_iter : 10;
+    if (opts->kepler_iter < 0) return fail(KETE_EINVAL, "kepler_iter must be >= 0");
+    P.kepler_iter = opts->kepler_iter > 0 ? opts->kepler_iter : kKeplerIterDefault;
     P.max_cells = 1024;
     P.sin_overflow = 0.5;
 
     hipStream_t s = (hipStream_t)stream;
-    HIPCHK(fill_zero(counters, 8 * sizeof(unsigned long long), s));
+    HIPCHK(fill_zero(counters, kFovCounters * sizeof(unsigned long long), s));
+    HIPCHK(fill_zero(P.fail, (size_t)n_obj * sizeof(int32_t), s));
     HIPCHK(fov_single_job_layout(b_poff, b_obj0, b_xoff, b_G, b_koff, n_batch, n_obj, G, s));
     HIPCHK(fov_prepare(P, qkey, cnt, cnt, scan_scratch, s));
     P.n_wide = counters + 6;
@@ -752,16 +814,22 @@ int kete_fov_check(const kete_ephem_t* eph, const double* x_epoch, const int32_t
         HIPCHK(fov_candidates(P, icnt, istart, items, (unsigned int*)(counters + 7), oscan, s));
         HIPCHK(fov_exact(P, s));
     }
-    unsigned long long host_counters[8];
+    unsigned long long host_counters[kFovCounters];
     HIPCHK(hipMemcpyAsync(host_counters, counters, sizeof(host_counters), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     for (int i = 0; i < 4; ++i) g_fov_stats[i] = host_counters[1 + i];
-    const int64_t np = (int64_t)host_counters[0];
+    int64_t np = (int64_t)host_counters[0];
     *n_pairs = np;
     if ((int64_t)host_counters[5] > P.cand_cap || np > pairs_cap) {
         *n_pairs = retry_pairs_cap(np, (int64_t)host_counters[5], pairs_cap);
         return fail(KETE_ECAPACITY, "%lld pairs / %llu exact-test candidates exceed pairs_cap %lld / %lld",
                     (long long)np, host_counters[5], (long long)pairs_cap, (long long)P.cand_cap);
+    }
+    if (host_counters[8] > 0) {
+        if ((rc = drop_failed_pairs(P.pairs, np, P.fail, sorted, counters, &np, s))) return rc;
+        *n_pairs = np;
+        HIPCHK(fov_sort(sorted, np, F, fcnt, fstart, P.pairs, scan_scratch, pf, ps, po, s));
+        return KETE_OK;
     }
     HIPCHK(fov_sort(P.pairs, np, F, fcnt, fstart, sorted, scan_scratch, pf, ps, po, s));
     return KETE_OK;
@@ -790,7 +858,6 @@ size_t kete_adjoint_workspace_size(int64_t n_obj, int32_t k_obs, double t0, doub
     if (!opts) { kete_default_opts(&d); opts = &d; }
     if (!(t_end > t0) || !(ckpt_days > 0) || n_obj < 0 || k_obs < 0) return 0;
     const int64_t C = (int64_t)std::ceil((t_end - t0) / ckpt_days - 1e-12);
-    const int nbk = std::max(1, opts->n_buckets);
     Carver c{nullptr};
     c.take<int32_t>((size_t)n_obj);                                   // perm
     c.take<double>((size_t)n_obj);                                    // h_pref
@@ -799,7 +866,7 @@ size_t kete_adjoint_workspace_size(int64_t n_obj, int32_t k_obs, double t0, doub
     c.take<double>((size_t)n_obj * std::max(0, k_obs) * 6);    // observation states
     c.take<double>((size_t)n_obj * std::max(0, k_obs) * 6);    // observation cotangents
     c.take<double>((size_t)n_obj * std::max(0, k_obs) * 2);    // light times and anomalies
-    c.take<int32_t>(bucket_scratch_ints(n_obj, nbk));
+    c.take<int32_t>(sort_scratch_ints(n_obj));
     c.take<double>((size_t)n_obj * kAdjStateDoubles);                 // carried backward state
     c.take<int32_t>((size_t)2 * ((n_obj + kAdjLanes - 1) / kAdjLanes));     // steps per wavefront, per store
     c.take<double>((size_t)kAdjTabDoubles);                           // reverse-sweep constants
@@ -829,7 +896,7 @@ int kete_propagate_adjoint(const kete_ephem_t* eph, int32_t mode, const double* 
     if (mode == KETE_ADJ_BWD && (!grad_x0 || (k_obs > 0 && !dL_dsky))) return fail(KETE_EINVAL, "null gradient pointer");
     if (!(opts->eps > 0) || !(opts->h_init > 0) || !(opts->h_min > 0) || opts->max_iter < 1 || opts->max_steps < 1)
         return fail(KETE_EINVAL, "eps, h_init, h_min, max_iter and max_steps must be positive");
-    const int nbk = std::min(std::max(1, opts->n_buckets), 32);
+    const int ncls = sort_classes(opts);
     if (!workspace) return fail(KETE_EWORKSPACE, "workspace is null");
     const size_t need = kete_adjoint_workspace_size(n_obj, k_obs, t0, t_end, ckpt_days, opts);
     if (ws_bytes < need) return fail(KETE_EWORKSPACE, "workspace %zu bytes < %zu required", ws_bytes, need);
@@ -841,7 +908,7 @@ int kete_propagate_adjoint(const kete_ephem_t* eph, int32_t mode, const double* 
     double* obs_state = c.take<double>((size_t)n_obj * k_obs * 6);
     double* obs_grad = c.take<double>((size_t)n_obj * k_obs * 6);
     double* obs_hop = c.take<double>((size_t)n_obj * k_obs * 2);
-    int32_t* bscratch = c.take<int32_t>(bucket_scratch_ints(n_obj, nbk));
+    const SortScratch sorts = sort_scratch(c.take<int32_t>(sort_scratch_ints(n_obj)), n_obj);
     double* adj_state = c.take<double>((size_t)n_obj * kAdjStateDoubles);
     int32_t* seg_ns = c.take<int32_t>((size_t)2 * ((n_obj + kAdjLanes - 1) / kAdjLanes));
     double* adj_tab = c.take<double>((size_t)kAdjTabDoubles);
@@ -892,23 +959,18 @@ int kete_propagate_adjoint(const kete_ephem_t* eph, int32_t mode, const double* 
     P.c_light = cl;
     P.lt_tol = opts->lt_tol > 0 ? opts->lt_tol : 1e-15;
     P.lt_iter = opts->lt_iter > 0 ? opts->lt_iter : 10;
+    if (opts->kepler_iter < 0) return fail(KETE_EINVAL, "kepler_iter must be >= 0");
+    P.kepler_iter = opts->kepler_iter > 0 ? opts->kepler_iter : kKeplerIterDefault;
     const double obliq = 84381.448 / 3600.0 * 3.14159265358979323846 / 180.0;
     P.cos_eps = std::cos(obliq);
     P.sin_eps = std::sin(obliq);
 
     if (mode == KETE_ADJ_FWD) {
-        HIPCHK(hipMemsetAsync(status, 0, (size_t)n_obj * sizeof(int32_t), s));
-        HIPCHK(launch_hpref_init(x0, h_pref, (int)n_obj, E.gm[0], s));
-        if (nbk > 1) {
-            BucketParams B;
-            B.h_pref = h_pref;
-            B.status = status;
-            B.perm = perm;
-            B.counts = bscratch;
-            B.n_obj = (int32_t)n_obj;
-            B.n_buckets = nbk;
-            B.h_ref = 1.0 / 64.0;
-            HIPCHK(launch_bucket(B, s));
+        HIPCHK(fill_zero(status, (size_t)n_obj * sizeof(int32_t), s));
+        HIPCHK(launch_hpref_init(x0, h_pref, ncls > 1 ? sorts.keys : nullptr, (int)n_obj, E.gm[0], 0.0, t_end - t0,
+                                 ncls, s));
+        if (ncls > 1) {
+            HIPCHK(launch_body_sort(sorts.keys, (int)n_obj, ncls, perm, sorts.tmp, sorts.counts, s));
         } else {
             HIPCHK(launch_iota(perm, (int)n_obj, s));
         }
@@ -1053,7 +1115,7 @@ size_t batch_carve(const BatchDims& d, const kete_batch_t* bt, char* base, Batch
     P.cell_frames = c.take<int32_t>((size_t)d.F);
     P.cell_caps = c.take<double>((size_t)d.F * 8);
     P.pairs = c.take<unsigned long long>((size_t)std::max<int64_t>(d.pairs_cap, 1));
-    w.counters = c.take<unsigned long long>(8);
+    w.counters = c.take<unsigned long long>(kFovCounters);
     w.fcnt = c.take<int32_t>((size_t)d.F + 1);
     w.fstart = c.take<int32_t>((size_t)d.F + 1);
     w.sorted = c.take<unsigned long long>((size_t)std::max<int64_t>(d.pairs_cap, 1));
@@ -1075,6 +1137,7 @@ size_t batch_carve(const BatchDims& d, const kete_batch_t* bt, char* base, Batch
     w.b_xoff = c.take<int64_t>((size_t)d.B + 1);
     w.b_G = c.take<int32_t>((size_t)d.B + 1);
     w.b_koff = c.take<int64_t>((size_t)d.B + 1);
+    P.fail = c.take<int32_t>((size_t)std::max<int64_t>(bt->n_bodies, 1));
     return c.off;
 }
 
@@ -1150,7 +1213,7 @@ int kete_batch_run(const kete_ephem_t* eph, const kete_batch_t* batch, int64_t p
     B.x_out = x_out;
     B.status = status;
     B.perm = w.perm;
-    B.n_buckets = std::min(std::max(1, opts->n_buckets), 32);
+    B.n_buckets = bucket_count(opts);
     B.max_win_segs = segs_or(opts, 2) + 1;
     B.max_iter = opts->max_iter;
     B.max_steps = opts->max_steps;
@@ -1185,6 +1248,8 @@ int kete_batch_run(const kete_ephem_t* eph, const kete_batch_t* batch, int64_t p
     P.stats = w.counters + 1;
     P.n_cand = w.counters + 5;
     P.n_wide = w.counters + 6;
+    P.n_fail = w.counters + 8;
+    P.status_out = status;
     P.cap = cap;
     P.cand_cap = dc.cand_cap;
     P.b_poff = w.b_poff;
@@ -1199,9 +1264,12 @@ int kete_batch_run(const kete_ephem_t* eph, const kete_batch_t* batch, int64_t p
     P.c_light = cl;
     P.lt_tol = opts->lt_tol > 0 ? opts->lt_tol : 1e-15;
     P.lt_iter = opts->lt_iter > 0 ? opts->lt_iter : 10;
+    if (opts->kepler_iter < 0) return fail(KETE_EINVAL, "kepler_iter must be >= 0");
+    P.kepler_iter = opts->kepler_iter > 0 ? opts->kepler_iter : kKeplerIterDefault;
     P.max_cells = 1024;
     P.sin_overflow = 0.5;
-    HIPCHK(fill_zero(w.counters, 8 * sizeof(unsigned long long), s));
+    HIPCHK(fill_zero(w.counters, kFovCounters * sizeof(unsigned long long), s));
+    HIPCHK(fill_zero(P.fail, (size_t)std::max<int64_t>(batch->n_bodies, 1) * sizeof(int32_t), s));
     if (dc.B > 0 && dc.F > 0 && dc.NP > 0) {
         HIPCHK(fov_prepare(P, w.qkey, w.cnt, w.cnt, w.scan_scratch, s));
         HIPCHK(fov_sort_objects(P, w.okey, w.orank, w.ocnt, w.ostart, w.osorted, w.oscan, s));
@@ -1229,11 +1297,11 @@ int kete_batch_pairs(const kete_batch_t* batch, int64_t pairs_cap, const kete_op
     if (ws_bytes < batch_carve(d, batch, nullptr, w)) return fail(KETE_EWORKSPACE, "workspace too small");
     batch_carve(d, batch, (char*)workspace, w);
     hipStream_t s = (hipStream_t)stream;
-    unsigned long long hc[8];
+    unsigned long long hc[kFovCounters];
     HIPCHK(hipMemcpyAsync(hc, w.counters, sizeof(hc), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     for (int i = 0; i < 4; ++i) g_fov_stats[i] = hc[1 + i];
-    const int64_t np = (int64_t)hc[0];
+    int64_t np = (int64_t)hc[0];
     *n_pairs = np;
     if ((int64_t)hc[5] > d.cand_cap || np > pairs_cap) {
         *n_pairs = retry_pairs_cap(np, (int64_t)hc[5], pairs_cap);
@@ -1241,6 +1309,12 @@ int kete_batch_pairs(const kete_batch_t* batch, int64_t pairs_cap, const kete_op
                     (long long)np, hc[5], (long long)pairs_cap, (long long)d.cand_cap);
     }
     if (np > 0 && (!pf || !ps || !po)) return fail(KETE_EINVAL, "null output pointer");
+    if (hc[8] > 0) {
+        if ((rc = drop_failed_pairs(w.P.pairs, np, w.P.fail, w.sorted, w.counters, &np, s))) return rc;
+        *n_pairs = np;
+        HIPCHK(fov_sort(w.sorted, np, d.F, w.fcnt, w.fstart, w.P.pairs, w.scan_scratch, pf, ps, po, s));
+        return KETE_OK;
+    }
     HIPCHK(fov_sort(w.P.pairs, np, d.F, w.fcnt, w.fstart, w.sorted, w.scan_scratch, pf, ps, po, s));
     return KETE_OK;
 }
@@ -1432,6 +1506,8 @@ int kete_lighttime_directions(const kete_ephem_t* eph, const double* x_ref, doub
     P.c_light = cl;
     P.lt_tol = opts->lt_tol > 0 ? opts->lt_tol : 1e-15;
     P.lt_iter = opts->lt_iter > 0 ? opts->lt_iter : 10;
+    if (opts->kepler_iter < 0) return fail(KETE_EINVAL, "kepler_iter must be >= 0");
+    P.kepler_iter = opts->kepler_iter > 0 ? opts->kepler_iter : kKeplerIterDefault;
     HIPCHK(launch_directions(P, x_ref, t_ref, t_obs, obs, n_q, d, tau, (hipStream_t)stream));
     return KETE_OK;
 }
@@ -1507,6 +1583,8 @@ int pair_magnitudes_impl(const kete_ephem_t* eph, const double* x_epoch, int64_t
     P.c_light = cl;
     P.lt_tol = opts->lt_tol > 0 ? opts->lt_tol : 1e-15;
     P.lt_iter = opts->lt_iter > 0 ? opts->lt_iter : 10;
+    if (opts->kepler_iter < 0) return fail(KETE_EINVAL, "kepler_iter must be >= 0");
+    P.kepler_iter = opts->kepler_iter > 0 ? opts->kepler_iter : kKeplerIterDefault;
     P.t_lo = eph->t_start;
     P.t_hi = t_end_of(eph);
     HIPCHK(launch_pair_mag(P, workspace, (hipStream_t)stream));

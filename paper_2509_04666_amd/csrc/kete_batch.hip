@@ -16,19 +16,31 @@ namespace {
 // Stable per-job bucketing by the initial step estimate 0.05 (r^3/mu)^(1/2):
 // one block per job, two passes over the job's bodies in chunks of 256.
 __global__ __launch_bounds__(256) void k_job_bucket(const BatchParams p) {
-    __shared__ int hist[32], base[32], run[32], wcount[4][32];
+    __shared__ int hist[kMaxBuckets], base[kMaxBuckets], run[kMaxBuckets], wcount[4][kMaxBuckets];
+    __shared__ double ext[2][4];
     const int J = blockIdx.x;
     const kete_job_t job = p.jobs[J];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int nbk = p.n_buckets;
-    if (tid < 32) { hist[tid] = 0; run[tid] = 0; }
+    for (int b = tid; b < nbk; b += 256) { hist[b] = 0; run[b] = 0; }
+    // the job's time extent around its start, for the predicted steps
+    double lo = 0.0, hi = 0.0;
+    for (int64_t e = tid; e < job.n_epoch; e += 256) {
+        const double dt = p.epochs[job.epoch_off + e] - job.t0;
+        lo = fmin(lo, dt);
+        hi = fmax(hi, dt);
+    }
+    lo = wave_min(lo);
+    hi = wave_max(hi);
+    if (lane == 0) { ext[0][wid] = lo; ext[1][wid] = hi; }
     __syncthreads();
+    lo = fmin(fmin(ext[0][0], ext[0][1]), fmin(ext[0][2], ext[0][3]));
+    hi = fmax(fmax(ext[1][0], ext[1][1]), fmax(ext[1][2], ext[1][3]));
     auto key_of = [&](int64_t k) {
         const double* x = p.x0 + 6 * (job.obj_off + k);
-        const double r = sqrt(dot3(x, x));
-        const double h = 0.05 * sqrt(r * r * r / p.eph.gm[0]);
+        const double h = predicted_step(x, x + 3, p.eph.gm[0], lo, hi);
         if (!(h < kInf)) return nbk - 1;
-        int b = (int)floor(log2(h * 64.0));
+        int b = (int)floor(kBucketSub * log2(h * 64.0));
         return b < 0 ? 0 : (b >= nbk ? nbk - 1 : b);
     };
     for (int64_t k = tid; k < job.n_obj; k += 256) atomicAdd(&hist[key_of(k)], 1);

@@ -155,15 +155,23 @@ __device__ __forceinline__ void stumpff(double z, double& c0, double& c1, double
     }
 }
 
+// Iteration cap of one universal-variable solve unless the caller sets one.
+constexpr int kKeplerIterDefault = 60;
+
 // Two-body hop about a fixed centre: (r0, v0) -> (r, v) after dt.
 // Universal anomaly chi solves
 //   F(chi) = r0 chi c1 + s0 chi^2 c2 + chi^3 c3 - sqrt(mu) dt = 0,
 // z = alpha chi^2, alpha = 2/r0 - v0^2/mu, s0 = r0.v0/sqrt(mu), with
 // Laguerre-Conway iterations (order 5); then the Lagrange f, g functions.
-// `chi` carries a warm start in and the solution out (pass NaN for none).
-// Returns 0 or KETE_ST_KEPLER_NOCONV.
+// The solve has converged when the update is within 4 ulps of chi, when F
+// is exactly zero, or when the update stops shrinking while already below
+// 1e-12 |chi| (the rounding floor of F); it fails after max_iter updates
+// without that.  `chi` carries a warm start in and the solution out (pass
+// NaN for none).  Returns 0 or KETE_ST_KEPLER_NOCONV (the last iterate is
+// still returned).
 __device__ __forceinline__ int kepler_uv(double mu, double smu, const double r0[3], const double v0[3],
-                                         double dt, double& chi, double r[3], double v[3]) {
+                                         double dt, double& chi, double r[3], double v[3],
+                                         int max_iter = kKeplerIterDefault) {
     if (dt == 0.0) {
         for (int i = 0; i < 3; ++i) { r[i] = r0[i]; v[i] = v0[i]; }
         chi = 0.0;
@@ -176,7 +184,8 @@ __device__ __forceinline__ int kepler_uv(double mu, double smu, const double r0[
     double x = (chi == chi) ? chi : target / r0n;
     double c0, c1, c2, c3, z;
     int it = 0, ok = 0;
-    for (; it < 60; ++it) {
+    double adx_prev = 1e300;
+    for (; it < max_iter; ++it) {
         z = alpha * x * x;
         stumpff(z, c0, c1, c2, c3);
         double F = r0n * x * c1 + s0 * x * x * c2 + x * x * x * c3 - target;
@@ -187,7 +196,12 @@ __device__ __forceinline__ int kepler_uv(double mu, double smu, const double r0[
         double dx = 5.0 * F / den;
         x -= dx;
         if (!(x == x)) break;
-        if (fabs(dx) <= 2.5e-16 * fabs(x) || F == 0.0) { ok = 1; break; }
+        const double adx = fabs(dx);
+        if (adx <= 8.881784197001252e-16 * fabs(x) || F == 0.0 || (adx >= adx_prev && adx <= 1e-12 * fabs(x))) {
+            ok = 1;
+            break;
+        }
+        adx_prev = adx;
     }
     chi = x;
     z = alpha * x * x;
@@ -200,6 +214,59 @@ __device__ __forceinline__ int kepler_uv(double mu, double smu, const double r0[
     const double gd = 1.0 - x * x * c2 / rn;
     for (int i = 0; i < 3; ++i) v[i] = fd * r0[i] + gd * v0[i];
     return ok ? 0 : KETE_ST_KEPLER_NOCONV;
+}
+
+// Predicted integration step of a body (days) for sorting bodies into
+// wavefronts: a fixed fraction of the shortest local time scale r^2 / |r x v|
+// (the inverse angular rate, sqrt(r^3 / mu) on a circle) its two-body orbit
+// about the Sun (state x, v relative to it, gravitational parameter mu)
+// reaches over the interval [dt_lo, dt_hi] around the state's epoch
+// (dt_lo <= 0 <= dt_hi): the perihelion distance when the orbit passes
+// perihelion inside the interval, otherwise the smaller of the distances at
+// its ends.  t_min receives the time (relative to the epoch) of that
+// smallest distance.  Only orders the bodies; the integrator's own step
+// control decides every step.
+__device__ __forceinline__ double predicted_step(const double x[3], const double v[3], double mu, double dt_lo,
+                                                 double dt_hi, double* t_min = nullptr) {
+    const double pi2 = 6.283185307179586;
+    const double rn = sqrt(dot3(x, x)), rv = dot3(x, v), v2 = dot3(v, v);
+    const double hx = x[1] * v[2] - x[2] * v[1], hy = x[2] * v[0] - x[0] * v[2], hz = x[0] * v[1] - x[1] * v[0];
+    const double hm = sqrt(hx * hx + hy * hy + hz * hz);
+    double ev[3];
+    for (int i = 0; i < 3; ++i) ev[i] = ((v2 - mu / rn) * x[i] - rv * v[i]) / mu;
+    const double e = sqrt(dot3(ev, ev));
+    const double alpha = 2.0 / rn - v2 / mu;
+    bool peri;
+    double tp = 0.0;                                  // a perihelion passage inside the interval
+    if (alpha > 0.0) {
+        // mean anomaly from e cos E = 1 - r / a, e sin E = r.v / sqrt(mu a)
+        const double es = rv * sqrt(alpha / mu), M0 = atan2(es, 1.0 - rn * alpha) - es;
+        const double n = sqrt(mu * alpha * alpha * alpha);
+        const double next = (M0 <= 0.0 ? -M0 : pi2 - M0) / n, prev = (M0 >= 0.0 ? M0 : pi2 + M0) / n;
+        peri = next <= dt_hi || prev <= -dt_lo;
+        tp = next <= dt_hi ? next : -prev;
+    } else {
+        peri = (rv < 0.0 && dt_hi > 0.0) || (rv > 0.0 && dt_lo < 0.0);
+        tp = rv < 0.0 ? dt_hi : dt_lo;
+    }
+    const double q = hm * hm / (mu * (1.0 + e));      // perihelion distance
+    double rmin = q;
+    if (!peri) {
+        rmin = rn;
+        tp = 0.0;
+        const double smu = sqrt(mu);
+        for (int k = 0; k < 2; ++k) {
+            const double dt = k ? dt_hi : dt_lo;
+            if (dt == 0.0) continue;
+            double chi = __builtin_nan(""), r1[3], v1[3];
+            kepler_uv(mu, smu, x, v, dt, chi, r1, v1);
+            const double r1n = sqrt(dot3(r1, r1));
+            if (r1n < rmin) { rmin = r1n; tp = dt; }
+        }
+        if (!(rmin > 0.0)) rmin = q;
+    }
+    if (t_min) *t_min = tp;
+    return 0.05 * rmin * rmin / hm;
 }
 
 // Sun position at arbitrary times of one batch, from its coefficient
@@ -217,13 +284,15 @@ struct SunTable {
 // barycentric frame, no aberration): heliocentric state (r0, v0) at t_ref,
 // emission point x_e = S(t_obs - tau) + hop(r0, v0, t_obs - tau - t_ref),
 // tau = |x_e - o| / c, iterated until the update is at most lt_tol.
-// Outputs d = x_e - o, tau and the barycentric emission velocity.
+// Outputs d = x_e - o, tau and the barycentric emission velocity.  Returns
+// KETE_ST_KEPLER_NOCONV when any of its hops ended on the iteration cap
+// kepler_iter without converging, else 0.
 template <class SunT>
 __device__ __forceinline__ int lighttime(const SunT& sun, double mu, double smu, double c_light,
                                          double lt_tol, int lt_iter, double t_ref,
                                          const double r0[3], const double v0[3], double t_obs,
                                          const double o[3], double d[3], double& tau, double ve[3],
-                                         double* chi_out = nullptr) {
+                                         double* chi_out = nullptr, int kepler_iter = kKeplerIterDefault) {
     double Se[3], Sde[3], r[3], v[3];
     double chi = __builtin_nan("");
     // first guess: straight line from the epoch state
@@ -231,7 +300,7 @@ __device__ __forceinline__ int lighttime(const SunT& sun, double mu, double smu,
     int st = 0;
     for (int k = 0; k <= lt_iter; ++k) {
         double te = t_obs - tau;
-        st = kepler_uv(mu, smu, r0, v0, te - t_ref, chi, r, v);
+        st |= kepler_uv(mu, smu, r0, v0, te - t_ref, chi, r, v, kepler_iter);
         sun.eval(te, Se, Sde);
         for (int i = 0; i < 3; ++i) d[i] = Se[i] + r[i] - o[i];
         double tn = sqrt(dot3(d, d)) / c_light;
@@ -240,7 +309,7 @@ __device__ __forceinline__ int lighttime(const SunT& sun, double mu, double smu,
         if (fabs(dtau) <= lt_tol) break;
     }
     double te = t_obs - tau;
-    st |= kepler_uv(mu, smu, r0, v0, te - t_ref, chi, r, v);
+    st |= kepler_uv(mu, smu, r0, v0, te - t_ref, chi, r, v, kepler_iter);
     sun.eval(te, Se, Sde);
     for (int i = 0; i < 3; ++i) {
         d[i] = Se[i] + r[i] - o[i];

@@ -830,8 +830,16 @@ __global__ __launch_bounds__(256) void k_fov_exact(const FovParams p) {
         double r0[3], v0[3];
         for (int k = 0; k < 3; ++k) { r0[k] = st[k] - bt[k]; v0[k] = st[3 + k] - bt[3 + k]; }
         double d[3], tau, ve[3];
-        lighttime(sun, p.mu, p.smu, p.c_light, p.lt_tol, p.lt_iter, p.t_ref[b], r0, v0, p.ft[f], p.fobs + 3 * f,
-                  d, tau, ve);
+        const int kst = lighttime(sun, p.mu, p.smu, p.c_light, p.lt_tol, p.lt_iter, p.t_ref[b], r0, v0, p.ft[f],
+                                  p.fobs + 3 * f, d, tau, ve, nullptr, p.kepler_iter);
+        if (kst) {
+            // the object fails: none of its pairs is kept (the host drops
+            // those already appended by other candidates)
+            p.fail[j] = 1;
+            if (p.status_out) p.status_out[j] = KETE_ST_KEPLER_NOCONV;
+            atomicAdd(p.n_fail, 1ull);
+            continue;
+        }
         const double* nrm = p.normals + (size_t)f * p.n_sub * 12;
         for (int s = 0; s < p.n_sub; ++s) {
             const double* ns = nrm + 12 * s;
@@ -843,6 +851,23 @@ __global__ __launch_bounds__(256) void k_fov_exact(const FovParams p) {
 }
 
 // ---------------------------------------------------------------- sort
+// Pairs of objects whose hop failed somewhere in the call are dropped: the
+// survivors are copied to `out` (in any order; the sort that follows
+// fixes it) and counted in *n_out.
+__global__ void k_pair_drop_failed(const unsigned long long* __restrict__ keys, int64_t n,
+                                   const int32_t* __restrict__ fail, unsigned long long* __restrict__ out,
+                                   unsigned long long* __restrict__ n_out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool keep = i < n && fail[(int)(keys[i] & 0x1ffffffull)] == 0;
+    const unsigned long long m = __ballot(keep);
+    if (m == 0ull) return;
+    const int lane = threadIdx.x & 63;
+    unsigned long long base = 0;
+    if (lane == __ffsll((long long)m) - 1) base = atomicAdd(n_out, (unsigned long long)__popcll(m));
+    base = __shfl(base, __ffsll((long long)m) - 1, 64);
+    if (keep) out[base + __popcll(m & ((1ull << lane) - 1ull))] = keys[i];
+}
+
 __global__ void k_pair_hist(const unsigned long long* __restrict__ keys, int64_t n, int32_t* __restrict__ fcnt) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) atomicAdd(fcnt + (int)(keys[i] >> 32), 1);
@@ -981,9 +1006,11 @@ __global__ void k_directions(const FovParams p, const double* __restrict__ x_ref
     double r0[3] = {st[0] - S[0], st[1] - S[1], st[2] - S[2]};
     double v0[3] = {st[3] - Sd[0], st[4] - Sd[1], st[5] - Sd[2]};
     double d[3], tau, ve[3];
-    lighttime(sun, p.mu, p.smu, p.c_light, p.lt_tol, p.lt_iter, t_ref, r0, v0, t_obs[qn], obs + 3 * qn, d, tau, ve);
-    for (int c = 0; c < 3; ++c) d_out[3 * i + c] = d[c];
-    if (tau_out) tau_out[i] = tau;
+    const int kst = lighttime(sun, p.mu, p.smu, p.c_light, p.lt_tol, p.lt_iter, t_ref, r0, v0, t_obs[qn],
+                              obs + 3 * qn, d, tau, ve, nullptr, p.kepler_iter);
+    // a hop that ended on the Kepler iteration cap gives NaN
+    for (int c = 0; c < 3; ++c) d_out[3 * i + c] = kst ? __builtin_nan("") : d[c];
+    if (tau_out) tau_out[i] = kst ? __builtin_nan("") : tau;
 }
 
 __global__ void k_ephem_eval(EphemArgs E, const double* __restrict__ t, int64_t n_q, double* __restrict__ out) {
@@ -1073,6 +1100,14 @@ static int cu_count() {
 hipError_t fov_exact(const FovParams& p, hipStream_t s) {
     hipLaunchKernelGGL(k_fov_wide, dim3((unsigned)(cu_count() * 8)), dim3(256), 0, s, p);
     hipLaunchKernelGGL(k_fov_exact, dim3((unsigned)(cu_count() * 16)), dim3(256), 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t fov_drop_failed(const unsigned long long* keys, int64_t n, const int32_t* fail, unsigned long long* out,
+                           unsigned long long* n_out, hipStream_t s) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_pair_drop_failed, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, keys, n, fail, out,
+                           n_out);
     return hipGetLastError();
 }
 

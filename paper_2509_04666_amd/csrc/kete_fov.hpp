@@ -63,6 +63,14 @@ struct FovParams {
     int32_t lt_iter;
     int32_t max_cells;
     double sin_overflow;
+    int32_t kepler_iter;
+    int32_t pad1;
+    // hops that ended on the Kepler iteration cap: fail[j] = 1 for global
+    // object j (zeroed by the caller), and KETE_ST_KEPLER_NOCONV in
+    // status_out[j] when status_out is not null; *n_fail counts them
+    int32_t* fail;
+    int32_t* status_out;
+    unsigned long long* n_fail;
 };
 
 hipError_t fov_prepare(const FovParams& p, int32_t* qkey, int32_t* cnt, int32_t* cursor, void* scan_scratch,
@@ -77,6 +85,8 @@ hipError_t fov_candidates(FovParams& p, int32_t* icnt, int32_t* istart, unsigned
                           unsigned int* item_next, void* scan_scratch, hipStream_t s);
 inline int64_t fov_item_capacity(int64_t n_keys, int64_t n_pairs_total) { return n_keys + n_pairs_total / 64 + 1; }
 hipError_t fov_exact(const FovParams& p, hipStream_t s);
+hipError_t fov_drop_failed(const unsigned long long* keys, int64_t n, const int32_t* fail, unsigned long long* out,
+                           unsigned long long* n_out, hipStream_t s);
 hipError_t fov_sort(unsigned long long* keys, int64_t n, int64_t n_frames, int32_t* fcnt, int32_t* fstart,
                     unsigned long long* sorted, void* scan_scratch, int32_t* pf, int32_t* ps, int32_t* po,
                     hipStream_t s);

@@ -142,14 +142,38 @@ hipError_t launch_nbody(const NbodyParams& p, int block, int lanes_per_body, hip
 size_t nbody_g8_lds_bytes(int n_body, int deg1, int max_win_segs, int block);
 
 // Stable counting sort of objects into step-size buckets.
+// Buckets per octave of the predicted step (the batched jobs' sort), and
+// the most buckets one counting-sort pass takes.
+constexpr int kBucketSub = 8;
+constexpr int kMaxBuckets = 256;
+
+// Sort keys of the bodies of one integrator launch (k_hpref_init): the high
+// 16 bits hold the step class, the low 16 the time class; bodies are
+// ordered by class, then by time (two stable counting-sort passes).
+//   step class 0: "critical" bodies, whose predicted step count over the
+//     launch exceeds kCritSteps: they set the launch's longest wavefronts,
+//     so they come first, ordered by the time of their smallest distance
+//     alone (kCritTimeBins classes), which lines up their perihelion
+//     passages inside a wavefront;
+//   step class 1 + k: the others, kClassSub classes per octave of the
+//     predicted step above h_ref, then kTimeBins classes of that time.
+constexpr double kCritSteps = 100.0;
+constexpr int kClassSub = 2;
+constexpr int kTimeBins = 64;
+constexpr int kCritTimeBins = 256;
+
+// One counting-sort pass over a digit of the keys: item i of the input
+// order (in_perm[i], or i when in_perm is null) goes to its digit's
+// bucket, stably.
 struct BucketParams {
-    const double* h_pref;   // [N]
-    const int32_t* status;  // [N]
+    const uint32_t* keys;   // [N] packed keys
+    const int32_t* in_perm; // [N] input order or null
     int32_t* perm;          // [N] out
     int32_t* counts;        // [n_buckets][n_blocks] scratch
     int32_t n_obj;
-    int32_t n_buckets;
-    double h_ref;           // bucket k holds h in [h_ref 2^k, h_ref 2^(k+1))
+    int32_t n_buckets;      // digit range (<= kMaxBuckets)
+    int32_t shift;          // digit = (key >> shift) & 0xffff
+    int32_t pad;
 };
 hipError_t launch_bucket(const BucketParams& p, hipStream_t s);
 

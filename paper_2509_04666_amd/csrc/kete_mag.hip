@@ -62,13 +62,12 @@ __global__ __launch_bounds__(256) void k_pair_mag(const MagParams p, const int32
         const double r0[3] = {st[0] - S[0], st[1] - S[1], st[2] - S[2]};
         const double v0[3] = {st[3] - Sd[0], st[4] - Sd[1], st[5] - Sd[2]};
         double d[3], tau, ve[3];
-        // as in the membership test, the hop's value is used even when its
-        // iteration ended on the step cap a few ulps from its tolerance; a
-        // hop that really fails is non-finite and stays so below
-        lighttime(sun, E.gm[0], p.smu, p.c_light, p.lt_tol, p.lt_iter, tr, r0, v0, tf, p.fobs + 3 * (int64_t)f, d,
-                  tau, ve);
+        // a hop that ends on the Kepler iteration cap gives NaN, as a pair
+        // outside the ephemeris does
+        const int kst = lighttime(sun, E.gm[0], p.smu, p.c_light, p.lt_tol, p.lt_iter, tr, r0, v0, tf,
+                                  p.fobs + 3 * (int64_t)f, d, tau, ve, nullptr, p.kepler_iter);
         const double te = tf - tau;
-        if (te >= p.t_lo && te <= p.t_hi) {
+        if (kst == 0 && te >= p.t_lo && te <= p.t_hi) {
             // heliocentric emission point r = (d + o) - S(te)
             double Se[3], Sde[3];
             sun.eval(te, Se, Sde);

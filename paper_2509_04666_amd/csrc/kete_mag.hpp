@@ -28,7 +28,7 @@ struct MagParams {
     double* geom;               // [n_pairs][3] or null
     double smu, c_light, lt_tol;
     int32_t lt_iter;
-    int32_t pad_;
+    int32_t kepler_iter;
     double t_lo, t_hi;          // ephemeris span
 };
 

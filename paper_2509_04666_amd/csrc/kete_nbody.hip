@@ -16,6 +16,8 @@
 #include "kete_radau.hpp"
 
 namespace kete {
+hipError_t launch_bucket(const BucketParams& p, hipStream_t s);
+
 namespace {
 
 template <int BLOCK>
@@ -282,30 +284,32 @@ __global__ __launch_bounds__(BLOCK, 3) void k_nbody_g8(const NbodyParams p) {
 }
 
 // ---------------------------------------------------------------- buckets
-__device__ __forceinline__ int bucket_key(double h, int st, int nbk, double h_ref) {
-    if (st != 0 || !(h < kInf)) return nbk - 1;
-    int k = (int)floor(log2(h / h_ref));
-    return k < 0 ? 0 : (k >= nbk ? nbk - 1 : k);
+__device__ __forceinline__ int bucket_digit(const BucketParams& p, long i, int& item) {
+    item = p.in_perm ? p.in_perm[i] : (int)i;
+    const int d = (int)((p.keys[item] >> p.shift) & 0xffffu);
+    return d < p.n_buckets ? d : p.n_buckets - 1;
 }
 
 __global__ __launch_bounds__(256) void k_bucket_count(const BucketParams p) {
-    __shared__ int hist[32];
+    __shared__ int hist[kMaxBuckets];
     const int tid = threadIdx.x;
-    if (tid < 32) hist[tid] = 0;
+    for (int k = tid; k < p.n_buckets; k += 256) hist[k] = 0;
     __syncthreads();
-    const long j = (long)blockIdx.x * 256 + tid;
-    if (j < p.n_obj) atomicAdd(&hist[bucket_key(p.h_pref[j], p.status[j], p.n_buckets, p.h_ref)], 1);
+    const long i = (long)blockIdx.x * 256 + tid;
+    int item;
+    if (i < p.n_obj) atomicAdd(&hist[bucket_digit(p, i, item)], 1);
     __syncthreads();
-    if (tid < p.n_buckets) p.counts[(size_t)tid * gridDim.x + blockIdx.x] = hist[tid];
+    for (int k = tid; k < p.n_buckets; k += 256) p.counts[(size_t)k * gridDim.x + blockIdx.x] = hist[k];
 }
 
 // Stable scatter: the rank inside a block follows the object index.
 __global__ __launch_bounds__(256) void k_bucket_scatter(const BucketParams p, const int32_t* __restrict__ offs) {
-    __shared__ int wcount[4][32];
+    __shared__ int wcount[4][kMaxBuckets];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const long j = (long)blockIdx.x * 256 + tid;
-    const bool valid = j < p.n_obj;
-    const int key = valid ? bucket_key(p.h_pref[j], p.status[j], p.n_buckets, p.h_ref) : -1;
+    const long i = (long)blockIdx.x * 256 + tid;
+    const bool valid = i < p.n_obj;
+    int item = 0;
+    const int key = valid ? bucket_digit(p, i, item) : -1;
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     int rank = 0;
     for (int k = 0; k < p.n_buckets; ++k) {
@@ -318,7 +322,7 @@ __global__ __launch_bounds__(256) void k_bucket_scatter(const BucketParams p, co
         int before = 0;
         for (int w = 0; w < wid; ++w) before += wcount[w][key];
         const int pos = offs[(size_t)key * gridDim.x + blockIdx.x] + before + rank;
-        p.perm[pos] = (int32_t)j;
+        p.perm[pos] = (int32_t)item;
     }
 }
 
@@ -327,11 +331,30 @@ __global__ void k_iota(int32_t* __restrict__ perm, int n) {
     if (j < n) perm[j] = (int32_t)j;
 }
 
-__global__ void k_hpref_init(const double* __restrict__ x0, double* __restrict__ h_pref, int n, double mu) {
+// Predicted step and sort key (see BucketParams) of every body over the
+// launch's time span [dt_lo, dt_hi] from its start state (taken as
+// heliocentric: the Sun is within 0.01 au of the barycentre, which only
+// blurs the ordering).
+__global__ void k_hpref_init(const double* __restrict__ x0, double* __restrict__ h_pref, uint32_t* __restrict__ keys,
+                             int n, double mu, double dt_lo, double dt_hi, int n_class, double h_ref) {
     const long j = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
-    const double r = sqrt(dot3(x0 + 6 * j, x0 + 6 * j));
-    h_pref[j] = 0.05 * sqrt(r * r * r / mu);
+    double tm = 0.0;
+    const double h = predicted_step(x0 + 6 * j, x0 + 6 * j + 3, mu, dt_lo, dt_hi, &tm);
+    h_pref[j] = h;
+    if (!keys) return;
+    const double span = dt_hi - dt_lo;
+    const double frac = span > 0.0 ? fmin(fmax((tm - dt_lo) / span, 0.0), 1.0) : 0.0;
+    uint32_t hi, lo;
+    if (h > 0.0 && span / h > kCritSteps) {
+        hi = 0;
+        lo = (uint32_t)fmin(frac * kCritTimeBins, kCritTimeBins - 1.0);
+    } else {
+        const double c = (h > 0.0 && h < kInf) ? floor(kClassSub * log2(h / h_ref)) : (double)(n_class - 2);
+        hi = 1u + (uint32_t)fmin(fmax(c, 0.0), (double)(n_class - 2));
+        lo = (uint32_t)fmin(frac * kTimeBins, kTimeBins - 1.0);
+    }
+    keys[j] = hi << 16 | lo;
 }
 
 }  // namespace
@@ -393,10 +416,34 @@ hipError_t launch_nbody(const NbodyParams& p, int block, int lanes_per_body, hip
     return hipGetLastError();
 }
 
-hipError_t launch_hpref_init(const double* x0, double* h_pref, int n, double mu, hipStream_t s) {
+hipError_t launch_hpref_init(const double* x0, double* h_pref, uint32_t* keys, int n, double mu, double dt_lo,
+                             double dt_hi, int n_class, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_hpref_init, dim3((n + 255) / 256), dim3(256), 0, s, x0, h_pref, n, mu);
+    hipLaunchKernelGGL(k_hpref_init, dim3((n + 255) / 256), dim3(256), 0, s, x0, h_pref, keys, n, mu, dt_lo, dt_hi,
+                       n_class, 1.0 / 64.0);
     return hipGetLastError();
+}
+
+// Bodies ordered by their keys: the time class first, then (stably) the
+// step class, into perm; tmp [n] holds the first pass's order.
+hipError_t launch_body_sort(const uint32_t* keys, int n, int n_class, int32_t* perm, int32_t* tmp, int32_t* counts,
+                            hipStream_t s) {
+    BucketParams B;
+    B.keys = keys;
+    B.counts = counts;
+    B.n_obj = n;
+    B.pad = 0;
+    B.in_perm = nullptr;
+    B.perm = tmp;
+    B.n_buckets = kCritTimeBins;
+    B.shift = 0;
+    hipError_t e = launch_bucket(B, s);
+    if (e != hipSuccess) return e;
+    B.in_perm = tmp;
+    B.perm = perm;
+    B.n_buckets = n_class;
+    B.shift = 16;
+    return launch_bucket(B, s);
 }
 
 hipError_t launch_iota(int32_t* perm, int n, hipStream_t s) {

@@ -118,6 +118,12 @@ def test_fov_argument_errors():
     assert need > 0
     assert L.kete_fov_check(C.byref(et), fake, None, 10, 2, fake, fake, fake, C.byref(fr), C.byref(o), fake, fake,
                             fake, 10, C.byref(n), fake, need - 1, None) == _lib.KETE_EWORKSPACE
+    # a negative Kepler iteration cap is refused before any device work
+    ob = api.default_opts(kepler_iter=-1)
+    assert L.kete_fov_check(C.byref(et), fake, None, 10, 2, fake, fake, fake, C.byref(fr), C.byref(ob), fake, fake,
+                            fake, 10, C.byref(n), fake, 1 << 30, None) == _lib.KETE_EINVAL
+    assert b"kepler_iter" in L.kete_last_error()
+    assert api.default_opts().kepler_iter == 60
     # no objects / frames: nothing to do
     assert L.kete_fov_check(C.byref(et), None, None, 0, 2, None, None, None, C.byref(fr), C.byref(o), None, None,
                             None, 0, C.byref(n), None, 0, None) == _lib.KETE_OK

@@ -393,3 +393,61 @@ def test_fov_capacity_and_empty(torch_cuda, orc):
     status[opairs[2]] = 1
     pf, ps, po = api.fov_check(eph, _dev_x(torch, xe), b, api.DeviceFrames.from_synth(fr), status)
     assert pf.numel() == 0
+
+
+def test_kepler_cap_forced_from_the_host(torch_cuda, orc):
+    """Host-forced non-convergence (kepler_iter = 1): the membership test
+    returns no pairs and marks every object that had pairs with
+    KETE_ST_KEPLER_NOCONV, as the oracle does with its own cap; magnitudes,
+    light-time directions and the adjoint report NaN / the status; with the
+    default cap nothing fails and the pairs match the oracle's."""
+    torch, api = torch_cuda
+    from paper_2509_04666_amd import _lib
+    case = synth.tiny_case(n_obj=400, n_frames=40, n_targeted=120)
+    fr = case.frames
+    order, off, t_ref = orc.make_batches(fr.t)
+    xe, st, _ = orc.propagate(case.ephem, case.x0, 0.0, t_ref)
+    eph = api.DeviceEphemeris.from_synth(case.ephem)
+    dfr = api.DeviceFrames.from_synth(fr)
+    b = api.Batches.from_host(order.astype(np.int32), off.astype(np.int32), t_ref)
+    xd = _dev_x(torch, xe)
+    s0 = torch.zeros(400, dtype=torch.int32, device="cuda")
+    pf, ps, po = api.fov_check(eph, xd, b, dfr, s0)
+    assert pf.numel() > 50 and int(s0.abs().sum()) == 0
+    o = orc.fov(case.ephem, xe, st, order, off, t_ref, fr.t, fr.obs, fr.normals, return_status=True)
+    assert not o[4].any()
+    _say(f"kepler cap: default run {pf.numel()} pairs (oracle {len(o[0])})")
+    capped = api.default_opts(kepler_iter=1)
+    s1 = torch.zeros(400, dtype=torch.int32, device="cuda")
+    pf1, ps1, po1 = api.fov_check(eph, xd, b, dfr, s1, capped)
+    s1h = s1.cpu().numpy()
+    had = np.unique(po.cpu().numpy())
+    _say(f"kepler cap 1: {pf1.numel()} pairs, {np.count_nonzero(s1h)} objects flagged, {had.size} had pairs")
+    assert pf1.numel() == 0
+    assert np.all(s1h[had] == _lib.ST_KEPLER_NOCONV)
+    assert set(np.unique(s1h).tolist()) <= {0, _lib.ST_KEPLER_NOCONV}
+    # the same without a status array: still no pairs
+    pf2, _, _ = api.fov_check(eph, xd, b, dfr, None, capped)
+    assert pf2.numel() == 0
+    # magnitudes of the default run's pairs: NaN under the cap, finite without it
+    H, G = synth.hg_params(np.random.default_rng(42), 400)
+    Hd = torch.as_tensor(H, device="cuda")
+    Gd = torch.as_tensor(G, device="cuda")
+    v = api.pair_magnitudes(eph, xd, b, dfr, pf, po, Hd, Gd)
+    v1 = api.pair_magnitudes(eph, xd, b, dfr, pf, po, Hd, Gd, opts=capped)
+    assert torch.isfinite(v).all() and torch.isnan(v1).all()
+    # light-time directions
+    d, tau = api.lighttime_directions(eph, xd[0], float(t_ref[0]), torch.as_tensor(fr.t[:3], device="cuda"),
+                                      torch.as_tensor(fr.obs[:3], device="cuda"), capped)
+    assert torch.isnan(d).all() and torch.isnan(tau).all()
+    # adjoint: every object's hops fail, so status NOCONV, NaN sky, zero gradient
+    g = synth.gradient_case(n_obj=64, k_obs=5, arc=20.0)
+    ctx = api.AdjointContext(api.DeviceEphemeris.from_synth(g.ephem), g.t0, g.arc,
+                             torch.as_tensor(g.t_obs, device="cuda"), torch.as_tensor(g.obs_pos, device="cuda"),
+                             5.0, capped)
+    x0 = torch.as_tensor(g.x0, device="cuda").requires_grad_(True)
+    sky = api.AdjointSky.apply(x0, ctx)
+    assert torch.isnan(sky).all()
+    assert np.all(ctx.status.cpu().numpy() == _lib.ST_KEPLER_NOCONV)
+    sky.nan_to_num(0.0).sum().backward()
+    assert torch.equal(x0.grad, torch.zeros_like(x0))
