@@ -655,7 +655,6 @@ size_t kete_fov_workspace_size(int64_t n_obj, int64_t n_frames, int64_t n_batch,
                                const kete_opts_t* opts) {
     kete_opts_t d;
     if (!opts) { kete_default_opts(&d); opts = &d; }
-    (void)n_sub;
     int G; double L;
     if (grid_dims(opts, n_batch, G, L)) return 0;
     const int64_t nkeys = n_batch * ((int64_t)G * G * G + 1);
@@ -691,6 +690,7 @@ size_t kete_fov_workspace_size(int64_t n_obj, int64_t n_frames, int64_t n_batch,
     c.take<int32_t>((size_t)n_batch);              // grid sizes and key offsets
     c.take<int64_t>((size_t)n_batch + 1);
     c.take<int32_t>((size_t)std::max<int64_t>(n_obj, 1));   // objects whose hop failed
+    if (n_sub > 1) c.take<double>((size_t)n_frames * kLocStride);   // sub-frame locators
     return c.off;
 }
 
@@ -762,6 +762,7 @@ int kete_fov_check(const kete_ephem_t* eph, const double* x_epoch, int32_t* stat
     int32_t* b_G = c.take<int32_t>((size_t)n_batch);
     int64_t* b_koff = c.take<int64_t>((size_t)n_batch + 1);
     P.fail = c.take<int32_t>((size_t)std::max<int64_t>(n_obj, 1));
+    P.loc = frames->n_sub > 1 ? c.take<double>((size_t)F * kLocStride) : nullptr;
     P.status_out = status;
     P.n_fail = counters + 8;
     P.b_poff = b_poff;
@@ -1138,6 +1139,7 @@ size_t batch_carve(const BatchDims& d, const kete_batch_t* bt, char* base, Batch
     w.b_G = c.take<int32_t>((size_t)d.B + 1);
     w.b_koff = c.take<int64_t>((size_t)d.B + 1);
     P.fail = c.take<int32_t>((size_t)std::max<int64_t>(bt->n_bodies, 1));
+    P.loc = bt->frames.n_sub > 1 ? c.take<double>((size_t)d.F * kLocStride) : nullptr;
     return c.off;
 }
 

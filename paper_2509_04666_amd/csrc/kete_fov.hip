@@ -77,6 +77,75 @@ __global__ void k_frame_caps(const double* __restrict__ normals, int64_t n_frame
     o[5] = o[6] = o[7] = 0.0;
 }
 
+// Vertex k (0..3) of sub-frame quadrilateral n[4][3] (not normalized): the
+// intersection of normal i = k / 2 of the pair (0, 1) with normal 2 + k % 2
+// of the pair (2, 3), signed to lie inside the opposite edge.
+__device__ __forceinline__ void quad_vertex(const double* __restrict__ n, int k, double v[3]) {
+    const int i = k >> 1;
+    cross3(n + 3 * i, n + 3 * (2 + (k & 1)), v);
+    if (dot3(v, n + 3 * (1 - i)) < 0.0) { v[0] = -v[0]; v[1] = -v[1]; v[2] = -v[2]; }
+}
+
+// Sub-frame locator of every frame (see kLocStride).  The gnomonic image
+// of a quadrilateral with great-circle edges inside the hemisphere around
+// the centre is the convex quadrilateral of its vertices' images, so the
+// box of those four points holds it; each box, widened by a rounding pad,
+// marks the locator cells it overlaps.
+__global__ void k_frame_locator(const double* __restrict__ normals, int64_t n_frames, int n_sub,
+                                const double* __restrict__ cap, double* __restrict__ loc) {
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= n_frames) return;
+    double* L = loc + (size_t)kLocStride * f;
+    unsigned long long* M = reinterpret_cast<unsigned long long*>(L + kLocHead);
+    const double c[3] = {cap[8 * f], cap[8 * f + 1], cap[8 * f + 2]};
+    // tangent basis: e1 from the axis least aligned with c
+    int ax = 0;
+    if (fabs(c[1]) < fabs(c[ax])) ax = 1;
+    if (fabs(c[2]) < fabs(c[ax])) ax = 2;
+    double e1[3] = {-c[ax] * c[0], -c[ax] * c[1], -c[ax] * c[2]};
+    e1[ax] += 1.0;
+    const double n1 = sqrt(dot3(e1, e1));
+    for (int k = 0; k < 3; ++k) e1[k] /= n1;
+    double e2[3];
+    cross3(c, e1, e2);
+    for (int k = 0; k < 3; ++k) { L[k] = c[k]; L[3 + k] = e1[k]; L[6 + k] = e2[k]; }
+    const double* nf = normals + (size_t)f * n_sub * 12;
+    double x0 = 1e300, x1 = -1e300, y0 = 1e300, y1 = -1e300;
+    bool ok = true;
+    for (int s = 0; s < n_sub && ok; ++s)
+        for (int k = 0; k < 4; ++k) {
+            double v[3];
+            quad_vertex(nf + 12 * s, k, v);
+            const double vc = dot3(v, c);
+            if (!(vc > 1e-6 * sqrt(dot3(v, v)))) { ok = false; break; }
+            const double X = dot3(v, e1) / vc, Y = dot3(v, e2) / vc;
+            x0 = fmin(x0, X); x1 = fmax(x1, X); y0 = fmin(y0, Y); y1 = fmax(y1, Y);
+        }
+    for (int i = 0; i < 2 * kLocL * kLocL; ++i) M[i] = 0ull;
+    L[13] = 0.0;
+    L[14] = L[15] = 0.0;
+    if (!ok || !(x1 >= x0) || !(y1 >= y0) || !(x1 - x0 < 1e6) || !(y1 - y0 < 1e6)) return;
+    const double pad = 1e-9 * (1.0 + fmax(fmax(fabs(x0), fabs(x1)), fmax(fabs(y0), fabs(y1))));
+    x0 -= pad; x1 += pad; y0 -= pad; y1 += pad;
+    const double idx = kLocL / (x1 - x0), idy = kLocL / (y1 - y0);
+    L[9] = x0; L[10] = y0; L[11] = idx; L[12] = idy;
+    for (int s = 0; s < n_sub; ++s) {
+        double a0 = 1e300, a1 = -1e300, b0 = 1e300, b1 = -1e300;
+        for (int k = 0; k < 4; ++k) {
+            double v[3];
+            quad_vertex(nf + 12 * s, k, v);
+            const double vc = dot3(v, c);
+            const double X = dot3(v, e1) / vc, Y = dot3(v, e2) / vc;
+            a0 = fmin(a0, X); a1 = fmax(a1, X); b0 = fmin(b0, Y); b1 = fmax(b1, Y);
+        }
+        const int i0 = max(0, (int)floor((a0 - pad - x0) * idx)), i1 = min(kLocL - 1, (int)floor((a1 + pad - x0) * idx));
+        const int j0 = max(0, (int)floor((b0 - pad - y0) * idy)), j1 = min(kLocL - 1, (int)floor((b1 + pad - y0) * idy));
+        for (int i = i0; i <= i1; ++i)
+            for (int j = j0; j <= j1; ++j) M[2 * (i * kLocL + j) + (s >> 6)] |= 1ull << (s & 63);
+    }
+    L[13] = 1.0;
+}
+
 // Rigorous bounds of the Sun's speed and acceleration over segments
 // [lo, hi]: |T_n'| <= n^2 and |T_n''| <= n^2 (n^2 - 1) / 3 on [-1, 1].
 __device__ void sun_bounds(const EphemArgs& E, int lo, int hi, double& vmax, double& amax) {
@@ -373,50 +442,105 @@ __device__ __forceinline__ bool frame_cap_hit(const ObjBounds& o, const double* 
     return !(dot3(cp, o.dh) < thr - 1e-12);
 }
 
-// Linear-motion test of a frame that passed the cap test, with its
-// remainder bound: the object moves on x + v dt within eps of its true
-// position, so it is outside a sub-frame when some unit normal has
-// n . ul <= -2 eps (the true direction's dot product is then negative);
-// the test is void when 2 eps reaches |ul|.  dt is the frame time minus
-// the batch epoch, ob the observer, nrm the n_sub x 4 normals.
-__device__ __forceinline__ bool lin_may_contain(const ObjBounds& o, double dt, const double ob[3],
-                                                const double* __restrict__ nrm, int n_sub, double Asun) {
-    if (!o.lin_ok) return true;
-    double ul[3];
-    for (int c = 0; c < 3; ++c) ul[c] = o.x[c] + o.v[c] * dt - ob[c];
-    const double ad = fabs(dt) + o.taumax;
-    const double e2 = 2.0 * (o.vbn * o.taumax + 0.5 * (o.a2b + Asun) * ad * ad + 1e-12);
-    if (!(e2 * e2 < dot3(ul, ul))) return true;
-    for (int s = 0; s < n_sub; ++s) {
-        bool out = false;
-        for (int i = 0; i < 4; ++i) out |= dot3(nrm + 12 * s + 3 * i, ul) <= -e2;
-        if (!out) return true;
+// Sub-frames of frame f that a direction within angle atan(t) of u can lie
+// in: bit s of m[s / 64].  With a locator, u's gnomonic point widened by
+// the image of that angle (the map stretches by at most 1 + T^2 at
+// tangent-plane radius T) selects the locator cells; without one, or for
+// a wide query, every sub-frame.  A query box off the frame's box gives
+// none.
+__device__ __forceinline__ void sub_candidates(const FovParams& p, int f, const double u[3], double t,
+                                               unsigned long long m[2]) {
+    const int S = p.n_sub;
+    m[0] = S >= 64 ? ~0ull : ((1ull << S) - 1ull);
+    m[1] = S > 64 ? (S >= 128 ? ~0ull : ((1ull << (S - 64)) - 1ull)) : 0ull;
+    if (!p.loc) return;
+    const double* L = p.loc + (size_t)kLocStride * (unsigned)f;
+    if (!(L[13] > 0.5)) return;
+    const double uc = dot3(u, L);
+    if (!(uc > 0.0)) return;
+    const double X = dot3(u, L + 3) / uc, Y = dot3(u, L + 6) / uc;
+    const double ru = sqrt(X * X + Y * Y);
+    if (!(ru * t < 0.5)) return;
+    const double T = (ru + t) / (1.0 - ru * t);
+    const double mg = t * (1.0 + T * T) * (1.0 + 1e-9) + 1e-12 * (1.0 + ru);
+    const double fx0 = (X - mg - L[9]) * L[11], fx1 = (X + mg - L[9]) * L[11];
+    const double fy0 = (Y - mg - L[10]) * L[12], fy1 = (Y + mg - L[10]) * L[12];
+    if (fx1 < 0.0 || fy1 < 0.0 || fx0 >= kLocL || fy0 >= kLocL) {   // off the frame's box
+        m[0] = m[1] = 0ull;
+        return;
     }
-    return false;
+    if (!(fx0 >= -1e9 && fx1 <= 1e9 && fy0 >= -1e9 && fy1 <= 1e9)) return;
+    const int ix0 = (int)floor(fmax(fx0, 0.0)), ix1 = (int)floor(fmin(fx1, kLocL - 1.0));
+    const int iy0 = (int)floor(fmax(fy0, 0.0)), iy1 = (int)floor(fmin(fy1, kLocL - 1.0));
+    if ((ix1 - ix0 + 1) * (iy1 - iy0 + 1) > 9) return;
+    const unsigned long long* M = reinterpret_cast<const unsigned long long*>(L + kLocHead);
+    unsigned long long a = 0ull, b = 0ull;
+    for (int ix = ix0; ix <= ix1; ++ix)
+        for (int iy = iy0; iy <= iy1; ++iy) {
+            a |= M[2 * (ix * kLocL + iy)];
+            b |= M[2 * (ix * kLocL + iy) + 1];
+        }
+    m[0] = a;
+    m[1] = b;
 }
 
-__device__ __forceinline__ bool frame_may_contain_lin(const FovParams& p, const ObjBounds& o, int f, double tr,
-                                                      double Asun) {
-    const double* ob = p.fobs + 3 * f;
-    const double obv[3] = {ob[0], ob[1], ob[2]};
-    return lin_may_contain(o, p.ft[f] - tr, obv, p.normals + (size_t)f * p.n_sub * 12, p.n_sub, Asun);
-}
-
-__device__ __forceinline__ bool frame_may_contain(const FovParams& p, const ObjBounds& o, int f, double tr,
-                                                  double Asun, unsigned long long& n_cand) {
-    if (!frame_cap_hit(o, p.fcap + 8 * f)) return false;
-    ++n_cand;
-    return frame_may_contain_lin(p, o, f, tr, Asun);
-}
-
-// The same for the k-th frame of the cell lists (cap record read in place).
-__device__ __forceinline__ bool cell_frame_may_contain(const FovParams& p, const ObjBounds& o, int k, double tr,
-                                                       double Asun, unsigned long long& n_cand, int& f) {
-    const double* cp = p.cell_caps + 8 * (int64_t)k;
-    if (!frame_cap_hit(o, cp)) return false;
-    f = (int)cp[5];
-    ++n_cand;
-    return frame_may_contain_lin(p, o, f, tr, Asun);
+// Linear-motion test of an (object, frame) pair that passed the cap test,
+// with its remainder bound: the object moves on x + v dt within eps of its
+// true emission point, so with unit normals and ul = x + v dt - o a
+// sub-frame is out when some n . ul <= -2 eps, surely in when every
+// n . ul > 2 eps (the true direction's dot products then keep their
+// signs), and undecided otherwise; the test is void when 2 eps reaches
+// |ul|.  Every lane with `has` classifies its pair: sure pairs go to the
+// pair list, undecided (frame, sub-frame, object) keys, or one
+// (frame, kAllSubs, object) key for a void test, to the exact-test
+// candidates.  The whole wavefront calls it.
+__device__ void classify_emit(const FovParams& p, bool has, const ObjBounds& o, int f, double tr, double Asun,
+                              unsigned long long gobj, unsigned long long* cbuf, int& nc, unsigned long long* pbuf,
+                              int& np, unsigned long long& n_exact) {
+    bool all = false;
+    unsigned long long m0 = 0ull, m1 = 0ull;
+    double ul[3] = {0.0, 0.0, 0.0}, e2 = 0.0;
+    if (has) {
+        all = !o.lin_ok;
+        if (o.lin_ok) {
+            const double dt = p.ft[f] - tr;
+            for (int c = 0; c < 3; ++c) ul[c] = o.x[c] + o.v[c] * dt - p.fobs[3 * (size_t)f + c];
+            const double ad = fabs(dt) + o.taumax;
+            e2 = 2.0 * (o.vbn * o.taumax + 0.5 * (o.a2b + Asun) * ad * ad + 1e-12);
+            const double u2 = dot3(ul, ul);
+            if (!(e2 * e2 < u2)) {
+                all = true;
+            } else {
+                unsigned long long m[2];
+                sub_candidates(p, f, ul, e2 / sqrt(u2 - e2 * e2), m);
+                m0 = m[0];
+                m1 = m[1];
+            }
+        }
+    }
+    const unsigned long long base = ((unsigned long long)(unsigned)f << 32) | gobj;
+    if (all) ++n_exact;
+    buf_append(cbuf, nc, all, base | kAllSubs, p.cand, p.n_cand, p.cand_cap);
+    const double* nrm = p.normals + (size_t)(unsigned)f * p.n_sub * 12;
+    while (__ballot((m0 | m1) != 0ull) != 0ull) {
+        int s = -1;
+        if (m0) { s = __ffsll((long long)m0) - 1; m0 &= m0 - 1ull; }
+        else if (m1) { s = 64 + __ffsll((long long)m1) - 1; m1 &= m1 - 1ull; }
+        int r = 0;
+        if (s >= 0) {
+            const double* n = nrm + 12 * s;
+            r = 1;
+            for (int i = 0; i < 4; ++i) {
+                const double t = dot3(n + 3 * i, ul);
+                if (t <= -e2) r = 0;
+                else if (!(t > e2) && r == 1) r = 2;
+            }
+        }
+        const unsigned long long key = base | ((unsigned long long)(s < 0 ? 0 : s) << 25);
+        if (r == 2) ++n_exact;
+        buf_append(pbuf, np, r == 1, key, p.pairs, p.n_pairs, p.cap);
+        buf_append(cbuf, nc, r == 2, key, p.cand, p.n_cand, p.cand_cap);
+    }
 }
 
 // Narrow objects: one wavefront per (batch, sky cell) of objects.  The
@@ -495,11 +619,13 @@ __global__ __launch_bounds__(256, 3) void k_fov_cells(const FovParams p) {
     unsigned long long n_cand = 0, n_exact = 0, n_visit = 0;
     const double* __restrict__ caps = p.cell_caps;
     const int n_items = p.item_start[p.n_keys];
-    __shared__ unsigned long long bufs[4][kBufEntries];
+    __shared__ unsigned long long bufs[4][kBufEntries], pbufs[4][kBufEntries];
     __shared__ ObjLin objs_all[4][kWave];
     __shared__ unsigned long long queue_all[4][kLinQueue];
     __shared__ double6 fcap_all[4][kWave];
     unsigned long long* buf = bufs[wv];
+    unsigned long long* pbuf = pbufs[wv];
+    int npbuf = 0;
     double6* fcap = fcap_all[wv];
     ObjLin* objs = objs_all[wv];
     unsigned long long* queue = queue_all[wv];
@@ -565,27 +691,22 @@ __global__ __launch_bounds__(256, 3) void k_fov_cells(const FovParams p) {
         int nq = 0;                           // queued (object, frame) pairs, wave-uniform
         // linear test of the first n queued pairs, one per lane
         auto drain = [&](int n) {
-            bool may = false;
+            const bool has = lane < n;
             int f = 0;
             unsigned long long gobj = 0;
-            if (lane < n) {
+            ObjBounds lo;
+            lo.lin_ok = false;
+            if (has) {
                 const unsigned long long e = queue[lane];
                 const ObjLin& ol = objs[e & 63];
                 f = (int)(e >> 8);
                 gobj = ol.gobj & ~(1ull << 63);
-                if (ol.gobj >> 63) {
-                    may = true;
-                } else {
-                    ObjBounds lo;
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) { lo.x[c] = ol.x[c]; lo.v[c] = ol.v[c]; }
-                    lo.taumax = ol.taumax; lo.vbn = ol.vbn; lo.a2b = ol.a2b; lo.lin_ok = true;
-                    const double ob[3] = {p.fobs[3 * f], p.fobs[3 * f + 1], p.fobs[3 * f + 2]};
-                    may = lin_may_contain(lo, p.ft[f] - tr, ob, p.normals + (size_t)f * p.n_sub * 12, p.n_sub, Asun);
-                }
+                for (int c = 0; c < 3; ++c) { lo.x[c] = ol.x[c]; lo.v[c] = ol.v[c]; }
+                lo.taumax = ol.taumax; lo.vbn = ol.vbn; lo.a2b = ol.a2b;
+                lo.lin_ok = (ol.gobj >> 63) == 0ull;
             }
-            if (may) ++n_exact;
-            buf_append(buf, nbuf, may, ((unsigned long long)f << 32) | gobj, p.cand, p.n_cand, p.cand_cap);
+            classify_emit(p, has, lo, f, tr, Asun, gobj, buf, nbuf, pbuf, npbuf, n_exact);
         };
         for (int g0 = 0; g0 < total; g0 += kWave) {
             // lane l holds frame record g0 + l of the neighbourhood list
@@ -635,6 +756,7 @@ __global__ __launch_bounds__(256, 3) void k_fov_cells(const FovParams p) {
         }
     }
     buf_flush(buf, nbuf, p.cand, p.n_cand, p.cand_cap);
+    buf_flush(pbuf, npbuf, p.pairs, p.n_pairs, p.cap);
     if (p.stats) {
         unsigned long long a = n_cand, e = n_exact;
 #pragma unroll
@@ -664,9 +786,10 @@ __global__ __launch_bounds__(256) void k_fov_wide(const FovParams p) {
     const int64_t n_items = (int64_t)(nw < (unsigned long long)p.n_pairs_total ? nw : p.n_pairs_total);
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    __shared__ unsigned long long bufs[4][kBufEntries];
+    __shared__ unsigned long long bufs[4][kBufEntries], pbufs[4][kBufEntries];
     unsigned long long* buf = bufs[(threadIdx.x >> 6) & 3];
-    int nbuf = 0;
+    unsigned long long* pbuf = pbufs[(threadIdx.x >> 6) & 3];
+    int nbuf = 0, npbuf = 0;
     unsigned long long n_cand = 0, n_exact = 0, n_over = 0;
     for (int64_t it = wave; it < n_items; it += n_waves) {
         const unsigned long long w = p.wide[it];
@@ -683,9 +806,9 @@ __global__ __launch_bounds__(256) void k_fov_wide(const FovParams p) {
             for (int q0 = p.batch_off[b]; q0 < q1; q0 += 64) {
                 const int q = q0 + lane;
                 const int f = q < q1 ? p.frame_order[q] : 0;
-                const bool may = q < q1 && frame_may_contain(p, o, f, tr, Asun, n_cand);
-                if (may) ++n_exact;
-                buf_append(buf, nbuf, may, ((unsigned long long)f << 32) | gobj, p.cand, p.n_cand, p.cand_cap);
+                const bool hit = q < q1 && frame_cap_hit(o, p.fcap + 8 * (size_t)f);
+                if (hit) ++n_cand;
+                classify_emit(p, hit, o, f, tr, Asun, gobj, buf, nbuf, pbuf, npbuf, n_exact);
             }
         } else {
             const int G = p.b_G[b];
@@ -722,14 +845,20 @@ __global__ __launch_bounds__(256) void k_fov_wide(const FovParams p) {
                     for (int step = kWave / 2; step > 0; step >>= 1)
                         if (incl_w[i + step - 1] <= t) i += step;
                     int f = 0;
-                    const bool may = t < total && cell_frame_may_contain(p, o, base_w[i] + t, tr, Asun, n_cand, f);
-                    if (may) ++n_exact;
-                    buf_append(buf, nbuf, may, ((unsigned long long)f << 32) | gobj, p.cand, p.n_cand, p.cand_cap);
+                    bool hit = false;
+                    if (t < total) {
+                        const double* cp = p.cell_caps + 8 * (int64_t)(base_w[i] + t);
+                        hit = frame_cap_hit(o, cp);
+                        f = (int)cp[5];
+                    }
+                    if (hit) ++n_cand;
+                    classify_emit(p, hit, o, f, tr, Asun, gobj, buf, nbuf, pbuf, npbuf, n_exact);
                 }
             }
         }
     }
     buf_flush(buf, nbuf, p.cand, p.n_cand, p.cand_cap);
+    buf_flush(pbuf, npbuf, p.pairs, p.n_pairs, p.cap);
     if (p.stats) {
         unsigned long long a = n_cand, e = n_exact;
 #pragma unroll
@@ -813,7 +942,8 @@ __global__ void k_obj_scatter(const FovParams p, const int32_t* __restrict__ oke
     sorted[start[key] + orank[i]] = (int32_t)(i - p.b_poff[b]);
 }
 
-// Exact test of every candidate (one lane per candidate, grid-stride).
+// Exact test of every candidate (one lane per candidate, grid-stride): the
+// candidate's sub-frame, or every sub-frame of its frame for kAllSubs.
 __global__ __launch_bounds__(256) void k_fov_exact(const FovParams p) {
     const unsigned long long nc = *p.n_cand;
     const unsigned long long n = nc < (unsigned long long)p.cand_cap ? nc : (unsigned long long)p.cand_cap;
@@ -822,8 +952,10 @@ __global__ __launch_bounds__(256) void k_fov_exact(const FovParams p) {
     for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (unsigned long long)gridDim.x * blockDim.x) {
         const unsigned long long c = p.cand[i];
-        const int f = (int)(c >> 32);
-        const int j = (int)(c & 0xffffffffull);            // global object
+        const int f = (int)((c >> 32) & 0x7fffffffull);
+        const int s0 = (int)((c >> 25) & 0x7full);
+        const bool all_subs = (c & kAllSubs) != 0ull;
+        const int j = (int)(c & 0x1ffffffull);              // global object
         const int b = p.frame_batch[f];
         const double* bt = p.btab + kBatchStride * b;
         const double* st = p.x_epoch + p.b_xoff[b] + 6 * (int64_t)(j - p.b_obj0[b]);
@@ -841,7 +973,8 @@ __global__ __launch_bounds__(256) void k_fov_exact(const FovParams p) {
             continue;
         }
         const double* nrm = p.normals + (size_t)f * p.n_sub * 12;
-        for (int s = 0; s < p.n_sub; ++s) {
+        const int s_end = all_subs ? p.n_sub : s0 + 1;
+        for (int s = all_subs ? 0 : s0; s < s_end; ++s) {
             const double* ns = nrm + 12 * s;
             if (dot3(ns, d) > 0.0 && dot3(ns + 3, d) > 0.0 && dot3(ns + 6, d) > 0.0 && dot3(ns + 9, d) > 0.0)
                 wave_append(p.pairs, p.n_pairs, p.cap,
@@ -1033,6 +1166,9 @@ hipError_t fov_prepare(const FovParams& p, int32_t* qkey, int32_t* cnt, int32_t*
     const unsigned gF = (unsigned)((F + 255) / 256);
     hipError_t e;
     if (F > 0) hipLaunchKernelGGL(k_frame_caps, dim3(gF), dim3(256), 0, s, p.normals, F, p.n_sub, p.fcap);
+    if (F > 0 && p.loc)
+        hipLaunchKernelGGL(k_frame_locator, dim3(gF), dim3(256), 0, s, p.normals, F, p.n_sub, (const double*)p.fcap,
+                           p.loc);
     if (p.n_batch > 0) hipLaunchKernelGGL(k_batch_prep, dim3((unsigned)p.n_batch), dim3(256), 0, s, p);
     if ((e = fill_zero(cnt, (size_t)(n_keys + 1) * sizeof(int32_t), s)) != hipSuccess) return e;
     if (F > 0) hipLaunchKernelGGL(k_frame_keys, dim3(gF), dim3(256), 0, s, p, qkey, cnt);

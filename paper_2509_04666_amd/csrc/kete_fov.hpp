@@ -8,6 +8,22 @@ namespace kete {
 constexpr int kBatchStride = 17;        // doubles per batch record
 constexpr double kMaxLightDays = 1.0;   // light time covered by the staged window
 
+// Sub-frame locator of a frame with several sub-frames: a tangent basis at
+// the frame's cap centre and a kLocL x kLocL grid over the gnomonic
+// bounding box of its sub-frames, each cell with a bit mask (two 64-bit
+// words) of the sub-frames whose gnomonic box overlaps it.  Record:
+//   [0..2] centre c, [3..5] e1, [6..8] e2, [9] X0, [10] Y0, [11] 1/dX,
+//   [12] 1/dY, [13] 1 when usable (every vertex in the hemisphere around
+//   c), [14..15] unused, then kLocL^2 x 2 mask words.
+constexpr int kLocL = 8;
+constexpr int kLocHead = 16;
+constexpr int kLocStride = kLocHead + 2 * kLocL * kLocL;     // doubles per frame
+
+// Exact-test candidates and pairs share one 64-bit key: frame << 32 |
+// sub-frame << 25 | object; a candidate with bit 63 set stands for every
+// sub-frame of its frame.
+constexpr unsigned long long kAllSubs = 1ull << 63;
+
 struct FovParams {
     EphemArgs eph;
     const double* x_epoch;      // [B][N][6]
@@ -24,6 +40,7 @@ struct FovParams {
     int32_t n_sub;
     int32_t pad0;
     double* fcap;               // [F][8]: centre, cos R, sin R
+    double* loc;                // [F][kLocStride] sub-frame locators, or null (one sub-frame)
     double* btab;               // [B][kBatchStride]
     int32_t* cell_start;        // [B G^3 + 1]
     int32_t* cell_frames;       // [F]
@@ -32,7 +49,7 @@ struct FovParams {
     unsigned long long* n_pairs;
     int64_t cap;
     unsigned long long* stats;  // [4] or null: candidates, exact tests, brute-force objects
-    unsigned long long* cand;   // [cand_cap] packed (frame << 32 | obj) for the exact test
+    unsigned long long* cand;   // [cand_cap] keys (frame, sub-frame or kAllSubs, object) for the exact test
     unsigned long long* n_cand;
     int64_t cand_cap;
     int32_t* frame_batch;       // [F] batch of each frame
