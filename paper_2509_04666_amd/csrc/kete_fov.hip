@@ -442,6 +442,25 @@ __device__ __forceinline__ bool frame_cap_hit(const ObjBounds& o, const double* 
     return !(dot3(cp, o.dh) < thr - 1e-12);
 }
 
+// Can an object's direction cap (o.dh, theta) reach the gnomonic box of
+// frame f's sub-frames?  The same widening of the cap's image as in
+// sub_candidates; without a usable locator, yes.
+__device__ __forceinline__ bool loc_box_hit(const FovParams& p, const ObjBounds& o, int f) {
+    if (!p.loc || o.overflow) return true;
+    const double* L = p.loc + (size_t)kLocStride * (unsigned)f;
+    if (!(L[13] > 0.5)) return true;
+    const double uc = dot3(o.dh, L);
+    if (!(uc > 0.0) || !(o.cth > 0.0)) return true;
+    const double X = dot3(o.dh, L + 3) / uc, Y = dot3(o.dh, L + 6) / uc;
+    const double t = o.sth / o.cth;
+    const double ru = sqrt(X * X + Y * Y);
+    if (!(ru * t < 0.5)) return true;
+    const double T = (ru + t) / (1.0 - ru * t);
+    const double mg = t * (1.0 + T * T) * (1.0 + 1e-9) + 1e-12 * (1.0 + ru);
+    const double X1 = L[9] + kLocL / L[11], Y1 = L[10] + kLocL / L[12];
+    return !(X + mg < L[9] || X - mg > X1 || Y + mg < L[10] || Y - mg > Y1);
+}
+
 // Sub-frames of frame f that a direction within angle atan(t) of u can lie
 // in: bit s of m[s / 64].  With a locator, u's gnomonic point widened by
 // the image of that angle (the map stretches by at most 1 + T^2 at
@@ -731,11 +750,11 @@ __global__ __launch_bounds__(256, 3) void k_fov_cells(const FovParams p) {
             for (int m = 0; m < n; ++m) {
                 const double6 cm = fcap[m];
                 const double cpm[5] = {cm.a, cm.b, cm.c, cm.d, cm.e};
-                const bool hit = live && frame_cap_hit(o, cpm);
+                const unsigned long long f = (unsigned long long)(unsigned int)(int)cm.f;
+                const bool hit = live && frame_cap_hit(o, cpm) && loc_box_hit(p, o, (int)f);
                 const unsigned long long mask = __ballot(hit);
                 if (mask == 0ull) continue;
                 if (hit) ++n_cand;
-                const unsigned long long f = (unsigned long long)(unsigned int)(int)cm.f;
                 if (hit) queue[nq + __popcll(mask & lt)] = (f << 8) | (unsigned long long)lane;
                 nq += __popcll(mask);
                 if (nq >= kWave) {
@@ -806,7 +825,7 @@ __global__ __launch_bounds__(256) void k_fov_wide(const FovParams p) {
             for (int q0 = p.batch_off[b]; q0 < q1; q0 += 64) {
                 const int q = q0 + lane;
                 const int f = q < q1 ? p.frame_order[q] : 0;
-                const bool hit = q < q1 && frame_cap_hit(o, p.fcap + 8 * (size_t)f);
+                const bool hit = q < q1 && frame_cap_hit(o, p.fcap + 8 * (size_t)f) && loc_box_hit(p, o, f);
                 if (hit) ++n_cand;
                 classify_emit(p, hit, o, f, tr, Asun, gobj, buf, nbuf, pbuf, npbuf, n_exact);
             }
@@ -848,8 +867,8 @@ __global__ __launch_bounds__(256) void k_fov_wide(const FovParams p) {
                     bool hit = false;
                     if (t < total) {
                         const double* cp = p.cell_caps + 8 * (int64_t)(base_w[i] + t);
-                        hit = frame_cap_hit(o, cp);
                         f = (int)cp[5];
+                        hit = frame_cap_hit(o, cp) && loc_box_hit(p, o, f);
                     }
                     if (hit) ++n_cand;
                     classify_emit(p, hit, o, f, tr, Asun, gobj, buf, nbuf, pbuf, npbuf, n_exact);
@@ -1001,19 +1020,45 @@ __global__ void k_pair_drop_failed(const unsigned long long* __restrict__ keys, 
     if (keep) out[base + __popcll(m & ((1ull << lane) - 1ull))] = keys[i];
 }
 
+// Runs of equal frames among a wavefront's 64 consecutive keys (pairs are
+// appended frame by frame, so runs are common): the head lane of each run
+// gets the run's length, so the frame counters see one atomic per run.
+struct FrameRun {
+    int f;          // frame of this lane's key (-1 past the end)
+    int head;       // lane heading this lane's run
+    int len;        // run length (head lanes)
+};
+__device__ __forceinline__ FrameRun frame_run(const unsigned long long* __restrict__ keys, int64_t n, int64_t i) {
+    const int lane = threadIdx.x & 63;
+    const bool valid = i < n;
+    FrameRun r;
+    r.f = valid ? (int)(keys[i] >> 32) : -1;
+    const int fp = __shfl_up(r.f, 1, 64);
+    const bool is_head = valid && (lane == 0 || fp != r.f);
+    const unsigned long long heads = __ballot(is_head);
+    const int n_valid = __popcll(__ballot(valid));
+    const unsigned long long upto = lane == 63 ? ~0ull : ((1ull << (lane + 1)) - 1ull);
+    r.head = 63 - __clzll(heads & upto);
+    const unsigned long long above = lane == 63 ? 0ull : (heads & ~upto);
+    r.len = is_head ? ((above ? __ffsll((long long)above) - 1 : n_valid) - lane) : 0;
+    return r;
+}
+
 __global__ void k_pair_hist(const unsigned long long* __restrict__ keys, int64_t n, int32_t* __restrict__ fcnt) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) atomicAdd(fcnt + (int)(keys[i] >> 32), 1);
+    const FrameRun r = frame_run(keys, n, i);
+    if (r.len > 0) atomicAdd(fcnt + r.f, r.len);
 }
 
 __global__ void k_pair_scatter(const unsigned long long* __restrict__ keys, int64_t n,
                                const int32_t* __restrict__ fstart, int32_t* __restrict__ fcur,
                                unsigned long long* __restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const unsigned long long k = keys[i];
-    const int f = (int)(k >> 32);
-    out[fstart[f] + atomicAdd(fcur + f, 1)] = k;
+    const FrameRun r = frame_run(keys, n, i);
+    int base = 0;
+    if (r.len > 0) base = fstart[r.f] + atomicAdd(fcur + r.f, r.len);
+    base = __shfl(base, r.head < 0 ? 0 : r.head, 64);
+    if (i < n) out[base + ((int)(threadIdx.x & 63) - r.head)] = keys[i];
 }
 
 __device__ __forceinline__ void unpack_pair(unsigned long long k, int i, int32_t* __restrict__ pf,
@@ -1029,6 +1074,7 @@ __device__ __forceinline__ void unpack_pair(unsigned long long k, int i, int32_t
 // with bottom-up merge passes through global memory (merge-path
 // partitions), ping-ponging with `tmp` at the same offsets.
 constexpr int kSortSmall = 32;
+constexpr int kSortWave = 1024;
 constexpr int kSortLds = 4096;
 
 __global__ void k_pair_sort_small(unsigned long long* __restrict__ keys, const int32_t* __restrict__ fstart,
@@ -1047,6 +1093,47 @@ __global__ void k_pair_sort_small(unsigned long long* __restrict__ keys, const i
     for (int i = a; i < e; ++i) unpack_pair(keys[i], i, pf, ps, po);
 }
 
+// Bitonic network over P (a power of two) keys in LDS, run by one
+// wavefront or by a whole block (`nthr` threads from `t0`); every thread
+// takes compare-exchange pairs, `sync` separates the passes.
+template <class Sync>
+__device__ __forceinline__ void bitonic_lds(unsigned long long* __restrict__ sh, int P, int t0, int nthr, Sync&& sync) {
+    for (int k = 2; k <= P; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int t = t0; t < (P >> 1); t += nthr) {
+                // t-th pair (i, i + j): insert a zero bit at j's position
+                const int i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+                const int l = i | j;
+                const unsigned long long x = sh[i], y = sh[l];
+                const bool up = (i & k) == 0;
+                if ((x > y) == up) { sh[i] = y; sh[l] = x; }
+            }
+            sync();
+        }
+}
+
+// Segments of kSortSmall < n <= kSortWave keys: one wavefront per frame,
+// synchronized by wavefront barriers only.
+__global__ __launch_bounds__(256) void k_pair_sort_wave(const unsigned long long* __restrict__ keys,
+                                                       const int32_t* __restrict__ fstart, int64_t n_frames,
+                                                       int32_t* __restrict__ pf, int32_t* __restrict__ ps,
+                                                       int32_t* __restrict__ po) {
+    __shared__ unsigned long long sh_all[4][kSortWave];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    unsigned long long* sh = sh_all[wv];
+    for (int64_t f = (int64_t)blockIdx.x * 4 + wv; f < n_frames; f += (int64_t)gridDim.x * 4) {
+        const int a = fstart[f], n = fstart[f + 1] - a;
+        if (n <= kSortSmall || n > kSortWave) continue;
+        int P = 64;
+        while (P < n) P <<= 1;
+        for (int i = lane; i < P; i += 64) sh[i] = i < n ? keys[a + i] : ~0ull;
+        wave_lds_sync();
+        bitonic_lds(sh, P, lane, 64, [] { wave_lds_sync(); });
+        for (int i = lane; i < n; i += 64) unpack_pair(sh[i], a + i, pf, ps, po);
+        wave_lds_sync();
+    }
+}
+
 __global__ __launch_bounds__(256) void k_pair_sort_lds(const unsigned long long* __restrict__ keys,
                                                       const int32_t* __restrict__ fstart, int64_t n_frames,
                                                       int32_t* __restrict__ pf, int32_t* __restrict__ ps,
@@ -1054,23 +1141,12 @@ __global__ __launch_bounds__(256) void k_pair_sort_lds(const unsigned long long*
     __shared__ unsigned long long sh[kSortLds];
     for (int64_t f = blockIdx.x; f < n_frames; f += gridDim.x) {
         const int a = fstart[f], n = fstart[f + 1] - a;
-        if (n <= kSortSmall || n > kSortLds) continue;
+        if (n <= kSortWave || n > kSortLds) continue;
         int P = 1;
         while (P < n) P <<= 1;
         for (int i = threadIdx.x; i < P; i += blockDim.x) sh[i] = i < n ? keys[a + i] : ~0ull;
         __syncthreads();
-        for (int k = 2; k <= P; k <<= 1)
-            for (int j = k >> 1; j > 0; j >>= 1) {
-                for (int i = threadIdx.x; i < P; i += blockDim.x) {
-                    const int l = i ^ j;
-                    if (l > i) {
-                        const unsigned long long x = sh[i], y = sh[l];
-                        const bool up = (i & k) == 0;
-                        if ((x > y) == up) { sh[i] = y; sh[l] = x; }
-                    }
-                }
-                __syncthreads();
-            }
+        bitonic_lds(sh, P, (int)threadIdx.x, (int)blockDim.x, [] { __syncthreads(); });
         for (int i = threadIdx.x; i < n; i += blockDim.x) unpack_pair(sh[i], a + i, pf, ps, po);
         __syncthreads();
     }
@@ -1261,6 +1337,8 @@ hipError_t fov_sort(unsigned long long* keys, int64_t n, int64_t n_frames, int32
     if (n_frames > 0) {
         const unsigned gb = (unsigned)std::min<int64_t>(n_frames, (int64_t)cu_count() * 16);
         hipLaunchKernelGGL(k_pair_sort_small, dim3((unsigned)((n_frames + 255) / 256)), dim3(256), 0, s, sorted,
+                           (const int32_t*)fstart, n_frames, pf, ps, po);
+        hipLaunchKernelGGL(k_pair_sort_wave, dim3(gb), dim3(256), 0, s, (const unsigned long long*)sorted,
                            (const int32_t*)fstart, n_frames, pf, ps, po);
         hipLaunchKernelGGL(k_pair_sort_lds, dim3(gb), dim3(256), 0, s, (const unsigned long long*)sorted,
                            (const int32_t*)fstart, n_frames, pf, ps, po);
