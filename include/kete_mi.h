@@ -247,8 +247,9 @@ size_t kete_fov_workspace_size(int64_t n_obj, int64_t n_frames, int64_t n_batch,
  *   pf, ps, po  device [pairs_cap]: frame, sub-frame, object of each pair,
  *               sorted by (frame, sub-frame, object)
  *   n_pairs     host out: number of pairs
- * The workspace holds up to max(16 n_frames, 2 pairs_cap) exact-test
- * candidates.  Synchronizes `stream` once to read the counts.  Returns
+ * The workspace holds up to max(65536, 16 n_frames, pairs_cap / 2)
+ * exact-test candidates (the pairs that the linear-motion bound leaves
+ * undecided).  Synchronizes `stream` once to read the counts.  Returns
  * KETE_ECAPACITY (outputs unspecified) when the pairs or the candidates
  * do not fit; *n_pairs then holds a pairs_cap to retry with, large
  * enough for both as far as they were counted. */
@@ -263,6 +264,11 @@ int kete_fov_check(const kete_ephem_t *eph, const double *x_epoch, int32_t *stat
  * tests, out[2] objects handled by the brute-force path, out[3] frame
  * records scanned by the per-cell join (per wavefront). */
 void kete_fov_last_stats(int64_t out[4]);
+
+/* The same counters followed by out[4] exact-test candidates listed,
+ * out[5] (object, batch) items on the wide path, out[6] hops that ended on
+ * the Kepler iteration cap, out[7] 0. */
+void kete_fov_last_counts(int64_t out[8]);
 
 /* Bytes of workspace needed by kete_pair_magnitudes (0 for a bad size). */
 size_t kete_magnitudes_workspace_size(int64_t n_frames);
@@ -426,14 +432,18 @@ int kete_batch_autotune(const kete_ephem_t *eph, const kete_batch_t *batch, int6
                         size_t ws_bytes, void *stream, kete_tune_progress_fn progress, void *user,
                         kete_opts_t *best, double *best_ms);
 
-/* Live kernel timing for measurement.  While enabled, every integrator
- * and FoV-candidate launch made by the calling thread is bracketed by HIP
- * events on the stream it is launched on.  kete_timing_read waits for
- * those events and returns the summed milliseconds ms[k] and launch
- * counts count[k] per kind k (0 integrator, 1 FoV candidates, 2 adjoint,
- * 3 batched), then forgets them. */
+/* Live kernel timing for measurement.  While enabled, the library's
+ * launches made by the calling thread are bracketed by HIP events on the
+ * stream they are launched on, by kind k: 0 the integrator launch, 1 every
+ * kernel of a field-of-view check (two brackets per call: preparation
+ * through the exact test, and the pair sort), 2 the adjoint, 3 a batched
+ * run's propagation, 4 the field-of-view join (candidate kernels) alone.
+ * kete_timing_read_all waits for the events and returns the summed
+ * milliseconds ms[k] and bracket counts count[k] (k < 8), then forgets
+ * them; kete_timing_read returns kinds 0..3 only. */
 void kete_timing_enable(int on);
 int kete_timing_read(double ms[4], int64_t count[4]);
+int kete_timing_read_all(double ms[8], int64_t count[8]);
 
 #ifdef __cplusplus
 }

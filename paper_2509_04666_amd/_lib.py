@@ -118,6 +118,8 @@ SIGNATURES = {
                                       C.c_void_p, C.POINTER(OptsT), C.POINTER(C.c_double)]),
     "kete_timing_enable": (None, [C.c_int]),
     "kete_timing_read": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "kete_timing_read_all": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "kete_fov_last_counts": (None, [C.c_void_p]),
 }
 
 _lib = None

@@ -34,7 +34,7 @@ using namespace kete;
 namespace {
 
 thread_local std::string g_err;
-thread_local unsigned long long g_fov_stats[4] = {0, 0, 0, 0};
+thread_local unsigned long long g_fov_stats[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 
 int fail(int code, const char* fmt, ...) {
     char buf[512];
@@ -359,8 +359,37 @@ int kete_make_batches(const double* t, int64_t n_frames, double span, int32_t* f
         if (!std::isfinite(t[i])) return fail(KETE_EINVAL, "t[%lld] is not finite", (long long)i);
     std::vector<int32_t> idx(n_frames);
     std::iota(idx.begin(), idx.end(), 0);
-    if (!std::is_sorted(t, t + n_frames))
-        std::stable_sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) { return t[a] < t[b]; });
+    if (!std::is_sorted(t, t + n_frames)) {
+        // order by (t, index): a stable LSD radix sort, 8 bits per pass, of
+        // the times' bit patterns mapped to unsigned integers in the order
+        // of the values (sign bit flipped for t >= 0, all bits for t < 0;
+        // -0 and +0 map to neighbours, which keeps them in index order as
+        // equal times are)
+        std::vector<uint64_t> key(n_frames), key2(n_frames);
+        std::vector<int32_t> idx2(n_frames);
+        for (int64_t i = 0; i < n_frames; ++i) {
+            uint64_t u;
+            const double v = t[i] == 0.0 ? 0.0 : t[i];
+            std::memcpy(&u, &v, sizeof(u));
+            key[i] = (u >> 63) ? ~u : (u | (1ull << 63));
+        }
+        std::vector<int64_t> cnt(256);
+        for (int pass = 0; pass < 8; ++pass) {
+            const int sh = 8 * pass;
+            std::fill(cnt.begin(), cnt.end(), 0);
+            for (int64_t i = 0; i < n_frames; ++i) ++cnt[(key[i] >> sh) & 0xff];
+            if (cnt[key[0] >> sh & 0xff] == n_frames) continue;     // one digit value: nothing moves
+            int64_t run = 0;
+            for (auto& c : cnt) { const int64_t k = c; c = run; run += k; }
+            for (int64_t i = 0; i < n_frames; ++i) {
+                const int64_t pos = cnt[(key[i] >> sh) & 0xff]++;
+                key2[pos] = key[i];
+                idx2[pos] = idx[i];
+            }
+            key.swap(key2);
+            idx.swap(idx2);
+        }
+    }
     int64_t nb = 0;
     batch_off[0] = 0;
     int64_t i = 0;
@@ -612,13 +641,12 @@ int kete_propagate_nbody(const kete_ephem_t* eph, const double* x0, double t0, i
     return KETE_OK;
 }
 
-// Exact-test candidates kept between the two FoV kernels.
+// Exact-test candidates kept between the join and the exact test (only the
+// pairs the linear-motion bound leaves undecided).
 static int64_t cand_capacity(int64_t n_frames, int64_t pairs_cap) {
-    return std::max<int64_t>(1 << 16, std::max<int64_t>(16 * n_frames, 2 * pairs_cap));
+    return std::max<int64_t>(1 << 16, std::max<int64_t>(16 * n_frames, pairs_cap / 2));
 }
 
-// pairs_cap to retry with after a capacity failure: room for the pairs
-// found and, with one pair per candidate, for every counted candidate.
 // Device counters of the FoV stages: [0] pairs, [1..4] statistics,
 // [5] candidates, [6] wide objects, [7] join work-queue cursor, [8] failed
 // hops, [9] pairs kept after dropping failed objects.
@@ -638,8 +666,10 @@ static int drop_failed_pairs(const unsigned long long* keys, int64_t np, const i
     return KETE_OK;
 }
 
+// pairs_cap to retry with after a capacity failure: room for the pairs
+// found and, at cand_capacity's pairs_cap / 2, for every counted candidate.
 static int64_t retry_pairs_cap(int64_t pairs, int64_t cands, int64_t pairs_cap) {
-    return std::max<int64_t>(std::max<int64_t>(pairs, cands), pairs_cap + 1);
+    return std::max<int64_t>(std::max<int64_t>(pairs, 2 * cands), pairs_cap + 1);
 }
 
 static int grid_dims(const kete_opts_t* o, int64_t n_batch, int& G, double& L) {
@@ -801,24 +831,30 @@ int kete_fov_check(const kete_ephem_t* eph, const double* x_epoch, int32_t* stat
     P.sin_overflow = 0.5;
 
     hipStream_t s = (hipStream_t)stream;
-    HIPCHK(fill_zero(counters, kFovCounters * sizeof(unsigned long long), s));
-    HIPCHK(fill_zero(P.fail, (size_t)n_obj * sizeof(int32_t), s));
-    HIPCHK(fov_single_job_layout(b_poff, b_obj0, b_xoff, b_G, b_koff, n_batch, n_obj, G, s));
-    HIPCHK(fov_prepare(P, qkey, cnt, cnt, scan_scratch, s));
-    P.n_wide = counters + 6;
-    HIPCHK(fov_sort_objects(P, okey, orank, ocnt, ostart, osorted, oscan, s));
-    P.obj_sorted = osorted;
-    P.obj_start = ostart;
-    P.obj_count = ocnt;
     {
         TimedScope ts(kTimeFov, s);
-        HIPCHK(fov_candidates(P, icnt, istart, items, (unsigned int*)(counters + 7), oscan, s));
+        HIPCHK(fill_zero(counters, kFovCounters * sizeof(unsigned long long), s));
+        HIPCHK(fill_zero(P.fail, (size_t)n_obj * sizeof(int32_t), s));
+        HIPCHK(fov_single_job_layout(b_poff, b_obj0, b_xoff, b_G, b_koff, n_batch, n_obj, G, s));
+        HIPCHK(fov_prepare(P, qkey, cnt, cnt, scan_scratch, s));
+        P.n_wide = counters + 6;
+        HIPCHK(fov_sort_objects(P, okey, orank, ocnt, ostart, osorted, oscan, s));
+        P.obj_sorted = osorted;
+        P.obj_start = ostart;
+        P.obj_count = ocnt;
+        {
+            TimedScope tj(kTimeFovJoin, s);
+            HIPCHK(fov_candidates(P, icnt, istart, items, (unsigned int*)(counters + 7), oscan, s));
+        }
         HIPCHK(fov_exact(P, s));
     }
     unsigned long long host_counters[kFovCounters];
     HIPCHK(hipMemcpyAsync(host_counters, counters, sizeof(host_counters), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     for (int i = 0; i < 4; ++i) g_fov_stats[i] = host_counters[1 + i];
+    g_fov_stats[4] = host_counters[5];
+    g_fov_stats[5] = host_counters[6];
+    g_fov_stats[6] = host_counters[8];
     int64_t np = (int64_t)host_counters[0];
     *n_pairs = np;
     if ((int64_t)host_counters[5] > P.cand_cap || np > pairs_cap) {
@@ -826,6 +862,7 @@ int kete_fov_check(const kete_ephem_t* eph, const double* x_epoch, int32_t* stat
         return fail(KETE_ECAPACITY, "%lld pairs / %llu exact-test candidates exceed pairs_cap %lld / %lld",
                     (long long)np, host_counters[5], (long long)pairs_cap, (long long)P.cand_cap);
     }
+    TimedScope ts(kTimeFov, s);
     if (host_counters[8] > 0) {
         if ((rc = drop_failed_pairs(P.pairs, np, P.fail, sorted, counters, &np, s))) return rc;
         *n_pairs = np;
@@ -1270,6 +1307,7 @@ int kete_batch_run(const kete_ephem_t* eph, const kete_batch_t* batch, int64_t p
     P.kepler_iter = opts->kepler_iter > 0 ? opts->kepler_iter : kKeplerIterDefault;
     P.max_cells = 1024;
     P.sin_overflow = 0.5;
+    TimedScope ts(kTimeFov, s);
     HIPCHK(fill_zero(w.counters, kFovCounters * sizeof(unsigned long long), s));
     HIPCHK(fill_zero(P.fail, (size_t)std::max<int64_t>(batch->n_bodies, 1) * sizeof(int32_t), s));
     if (dc.B > 0 && dc.F > 0 && dc.NP > 0) {
@@ -1278,8 +1316,10 @@ int kete_batch_run(const kete_ephem_t* eph, const kete_batch_t* batch, int64_t p
         P.obj_sorted = w.osorted;
         P.obj_start = w.ostart;
         P.obj_count = w.ocnt;
-        TimedScope ts(kTimeFov, s);
-        HIPCHK(fov_candidates(P, w.icnt, w.istart, w.items, (unsigned int*)(w.counters + 7), w.oscan, s));
+        {
+            TimedScope tj(kTimeFovJoin, s);
+            HIPCHK(fov_candidates(P, w.icnt, w.istart, w.items, (unsigned int*)(w.counters + 7), w.oscan, s));
+        }
         HIPCHK(fov_exact(P, s));
     }
     return KETE_OK;
@@ -1460,10 +1500,9 @@ void kete_timing_enable(int on) {
 }
 
 // Waits for the recorded events, returns the summed milliseconds and the
-// launch count per kind (0 integrator, 1 FoV candidates, 2 adjoint,
-// 3 batched) and forgets them.
-int kete_timing_read(double ms[4], int64_t count[4]) {
-    for (int k = 0; k < 4; ++k) { ms[k] = 0.0; count[k] = 0; }
+// bracket count per kind (see kete_timing_read_all) and forgets them.
+int kete_timing_read_all(double ms[8], int64_t count[8]) {
+    for (int k = 0; k < kTimeKinds; ++k) { ms[k] = 0.0; count[k] = 0; }
     int rc = KETE_OK;
     for (auto& r : g_timed) {
         float t = 0.0f;
@@ -1480,10 +1519,20 @@ int kete_timing_read(double ms[4], int64_t count[4]) {
     return rc;
 }
 
-// Counters of the last kete_fov_check on this thread: candidate frames
-// visited, exact light-time tests, objects on the brute-force path.
+int kete_timing_read(double ms[4], int64_t count[4]) {
+    double m8[kTimeKinds];
+    int64_t c8[kTimeKinds];
+    const int rc = kete_timing_read_all(m8, c8);
+    for (int k = 0; k < 4; ++k) { ms[k] = m8[k]; count[k] = c8[k]; }
+    return rc;
+}
+
 void kete_fov_last_stats(int64_t out[4]) {
     for (int i = 0; i < 4; ++i) out[i] = (int64_t)g_fov_stats[i];
+}
+
+void kete_fov_last_counts(int64_t out[8]) {
+    for (int i = 0; i < 8; ++i) out[i] = (int64_t)g_fov_stats[i];
 }
 
 int kete_lighttime_directions(const kete_ephem_t* eph, const double* x_ref, double t_ref, int64_t n_obj,

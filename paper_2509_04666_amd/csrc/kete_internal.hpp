@@ -178,7 +178,11 @@ struct BucketParams {
 hipError_t launch_bucket(const BucketParams& p, hipStream_t s);
 
 // Optional live timing of kernel launches with HIP events (per thread).
-enum TimedKernel { kTimeNbody = 0, kTimeFov = 1, kTimeAdjoint = 2, kTimeBatch = 3, kTimeKinds = 4 };
+// kTimeFov brackets every kernel of a field-of-view call (preparation,
+// binning, join, exact test, pair sort); kTimeFovJoin the join alone.
+enum TimedKernel {
+    kTimeNbody = 0, kTimeFov = 1, kTimeAdjoint = 2, kTimeBatch = 3, kTimeFovJoin = 4, kTimeKinds = 8
+};
 struct TimedScope {
     TimedScope(int kind, hipStream_t s);
     ~TimedScope();
