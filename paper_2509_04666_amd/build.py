@@ -18,7 +18,7 @@ ARCH = os.environ.get("KETE_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
     "-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-ffp-contract=fast", "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
+    "-ffp-contract=fast", "-Wall", "-Wshadow", "-Wno-unused-function", "-Wno-unused-variable",
     "-I", INCLUDE, "-I", CSRC,
 ]
 

@@ -648,9 +648,12 @@ static int64_t cand_capacity(int64_t n_frames, int64_t pairs_cap) {
 }
 
 // Device counters of the FoV stages: [0] pairs, [1..4] statistics,
-// [5] candidates, [6] wide objects, [7] join work-queue cursor, [8] failed
-// hops, [9] pairs kept after dropping failed objects.
-constexpr int kFovCounters = 16;
+// [5] candidates, [6] wide objects, [8] failed hops, [9] pairs kept after
+// dropping failed objects; from [16] the work-queue cursors of the per-cell
+// join, then those of the wide join.
+constexpr int kFovCursorBase = 16;
+constexpr int kFovWideCursorBase = kFovCursorBase + kJoinCursorWords / 2;
+constexpr int kFovCounters = kFovWideCursorBase + kJoinCursorWords / 2;
 
 // Drops the pairs of objects whose hop failed (n_fail > 0): survivors of
 // keys[0..np) go to `out`, and their count is read back (one more
@@ -721,6 +724,10 @@ size_t kete_fov_workspace_size(int64_t n_obj, int64_t n_frames, int64_t n_batch,
     c.take<int64_t>((size_t)n_batch + 1);
     c.take<int32_t>((size_t)std::max<int64_t>(n_obj, 1));   // objects whose hop failed
     if (n_sub > 1) c.take<double>((size_t)n_frames * kLocStride);   // sub-frame locators
+    c.take<double>((size_t)fov_cell_frame_doubles(n_frames, n_sub));  // frame data in cell order
+    c.take<int32_t>((size_t)(n_batch * n_obj));     // parts of the wide objects and their scan
+    c.take<int32_t>((size_t)(n_batch * n_obj) + 1);
+    c.take<char>(scan_scratch_bytes(n_batch * n_obj));
     return c.off;
 }
 
@@ -793,6 +800,12 @@ int kete_fov_check(const kete_ephem_t* eph, const double* x_epoch, int32_t* stat
     int64_t* b_koff = c.take<int64_t>((size_t)n_batch + 1);
     P.fail = c.take<int32_t>((size_t)std::max<int64_t>(n_obj, 1));
     P.loc = frames->n_sub > 1 ? c.take<double>((size_t)F * kLocStride) : nullptr;
+    P.cell_obs = c.take<double>((size_t)fov_cell_frame_doubles(F, frames->n_sub));
+    P.cell_normals = P.cell_obs + 4 * F;
+    P.wide_parts = c.take<int32_t>((size_t)(n_batch * n_obj));
+    P.wide_off = c.take<int32_t>((size_t)(n_batch * n_obj) + 1);
+    void* wscan = c.take<char>(scan_scratch_bytes(n_batch * n_obj));
+    P.wide_next = (unsigned int*)(counters + kFovWideCursorBase);
     P.status_out = status;
     P.n_fail = counters + 8;
     P.b_poff = b_poff;
@@ -844,11 +857,11 @@ int kete_fov_check(const kete_ephem_t* eph, const double* x_epoch, int32_t* stat
         P.obj_count = ocnt;
         {
             TimedScope tj(kTimeFovJoin, s);
-            HIPCHK(fov_candidates(P, icnt, istart, items, (unsigned int*)(counters + 7), oscan, s));
+            HIPCHK(fov_candidates(P, icnt, istart, items, (unsigned int*)(counters + kFovCursorBase), oscan, wscan, s));
         }
         HIPCHK(fov_exact(P, s));
     }
-    unsigned long long host_counters[kFovCounters];
+    unsigned long long host_counters[kFovCursorBase];
     HIPCHK(hipMemcpyAsync(host_counters, counters, sizeof(host_counters), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     for (int i = 0; i < 4; ++i) g_fov_stats[i] = host_counters[1 + i];
@@ -1132,7 +1145,7 @@ struct BatchWs {
     int32_t *qkey, *cnt, *fcnt, *fstart, *okey, *orank, *osorted, *ostart, *ocnt, *icnt, *istart;
     unsigned long long* items;
     unsigned long long *counters, *sorted;
-    void *scan_scratch, *oscan;
+    void *scan_scratch, *oscan, *wscan;
     int64_t *b_poff, *b_xoff, *b_koff;
     int32_t *b_obj0, *b_G;
 };
@@ -1177,6 +1190,12 @@ size_t batch_carve(const BatchDims& d, const kete_batch_t* bt, char* base, Batch
     w.b_koff = c.take<int64_t>((size_t)d.B + 1);
     P.fail = c.take<int32_t>((size_t)std::max<int64_t>(bt->n_bodies, 1));
     P.loc = bt->frames.n_sub > 1 ? c.take<double>((size_t)d.F * kLocStride) : nullptr;
+    P.cell_obs = c.take<double>((size_t)fov_cell_frame_doubles(d.F, bt->frames.n_sub));
+    P.cell_normals = P.cell_obs ? P.cell_obs + 4 * d.F : nullptr;
+    P.wide_parts = c.take<int32_t>((size_t)std::max<int64_t>(d.NP, 1));
+    P.wide_off = c.take<int32_t>((size_t)d.NP + 1);
+    w.wscan = c.take<char>(scan_scratch_bytes(d.NP));
+    P.wide_next = w.counters ? (unsigned int*)(w.counters + kFovWideCursorBase) : nullptr;
     return c.off;
 }
 
@@ -1318,7 +1337,8 @@ int kete_batch_run(const kete_ephem_t* eph, const kete_batch_t* batch, int64_t p
         P.obj_count = w.ocnt;
         {
             TimedScope tj(kTimeFovJoin, s);
-            HIPCHK(fov_candidates(P, w.icnt, w.istart, w.items, (unsigned int*)(w.counters + 7), w.oscan, s));
+            HIPCHK(fov_candidates(P, w.icnt, w.istart, w.items, (unsigned int*)(w.counters + kFovCursorBase), w.oscan,
+                                  w.wscan, s));
         }
         HIPCHK(fov_exact(P, s));
     }
@@ -1339,7 +1359,7 @@ int kete_batch_pairs(const kete_batch_t* batch, int64_t pairs_cap, const kete_op
     if (ws_bytes < batch_carve(d, batch, nullptr, w)) return fail(KETE_EWORKSPACE, "workspace too small");
     batch_carve(d, batch, (char*)workspace, w);
     hipStream_t s = (hipStream_t)stream;
-    unsigned long long hc[kFovCounters];
+    unsigned long long hc[kFovCursorBase];
     HIPCHK(hipMemcpyAsync(hc, w.counters, sizeof(hc), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     for (int i = 0; i < 4; ++i) g_fov_stats[i] = hc[1 + i];

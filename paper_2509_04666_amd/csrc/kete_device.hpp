@@ -341,10 +341,15 @@ __device__ __forceinline__ double wave_min(double x) {
 }
 
 // LDS visibility between lanes of one wavefront (no block barrier).
+// The lanes of a wavefront issue their LDS accesses together and the LDS
+// serves one wavefront's accesses in order, so wavefront-scope fences
+// suffice: they keep the compiler from moving LDS accesses across the
+// call and, unlike wider scopes, make no wait for outstanding global
+// loads and stores.
 __device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 }  // namespace kete

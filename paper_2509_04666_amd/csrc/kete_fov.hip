@@ -86,64 +86,105 @@ __device__ __forceinline__ void quad_vertex(const double* __restrict__ n, int k,
     if (dot3(v, n + 3 * (1 - i)) < 0.0) { v[0] = -v[0]; v[1] = -v[1]; v[2] = -v[2]; }
 }
 
-// Sub-frame locator of every frame (see kLocStride).  The gnomonic image
-// of a quadrilateral with great-circle edges inside the hemisphere around
-// the centre is the convex quadrilateral of its vertices' images, so the
-// box of those four points holds it; each box, widened by a rounding pad,
+// Sub-frame locator of every frame (see kLocStride), in cell order, one
+// wavefront per frame with a lane per sub-frame.  The gnomonic image of a
+// quadrilateral with great-circle edges inside the hemisphere around the
+// centre is the convex quadrilateral of its vertices' images, so the box
+// of those four points holds it; each box, widened by a rounding pad,
 // marks the locator cells it overlaps.
-__global__ void k_frame_locator(const double* __restrict__ normals, int64_t n_frames, int n_sub,
-                                const double* __restrict__ cap, double* __restrict__ loc) {
-    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= n_frames) return;
-    double* L = loc + (size_t)kLocStride * f;
-    unsigned long long* M = reinterpret_cast<unsigned long long*>(L + kLocHead);
-    const double c[3] = {cap[8 * f], cap[8 * f + 1], cap[8 * f + 2]};
-    // tangent basis: e1 from the axis least aligned with c
-    int ax = 0;
-    if (fabs(c[1]) < fabs(c[ax])) ax = 1;
-    if (fabs(c[2]) < fabs(c[ax])) ax = 2;
-    double e1[3] = {-c[ax] * c[0], -c[ax] * c[1], -c[ax] * c[2]};
-    e1[ax] += 1.0;
-    const double n1 = sqrt(dot3(e1, e1));
-    for (int k = 0; k < 3; ++k) e1[k] /= n1;
-    double e2[3];
-    cross3(c, e1, e2);
-    for (int k = 0; k < 3; ++k) { L[k] = c[k]; L[3 + k] = e1[k]; L[6 + k] = e2[k]; }
-    const double* nf = normals + (size_t)f * n_sub * 12;
-    double x0 = 1e300, x1 = -1e300, y0 = 1e300, y1 = -1e300;
-    bool ok = true;
-    for (int s = 0; s < n_sub && ok; ++s)
-        for (int k = 0; k < 4; ++k) {
-            double v[3];
-            quad_vertex(nf + 12 * s, k, v);
-            const double vc = dot3(v, c);
-            if (!(vc > 1e-6 * sqrt(dot3(v, v)))) { ok = false; break; }
-            const double X = dot3(v, e1) / vc, Y = dot3(v, e2) / vc;
-            x0 = fmin(x0, X); x1 = fmax(x1, X); y0 = fmin(y0, Y); y1 = fmax(y1, Y);
+__global__ __launch_bounds__(256) void k_frame_locator(const FovParams p) {
+    const int lane = threadIdx.x & 63;
+    const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int S = p.n_sub;
+    for (int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; r < p.n_frames; r += n_waves) {
+        double* L = p.loc + (size_t)kLocStride * r;
+        unsigned long long* M = reinterpret_cast<unsigned long long*>(L + kLocHead);
+        const double* cp = p.cell_caps + 8 * r;
+        const double c[3] = {cp[0], cp[1], cp[2]};
+        // tangent basis: e1 from the axis least aligned with c
+        int ax = 0;
+        if (fabs(c[1]) < fabs(c[ax])) ax = 1;
+        if (fabs(c[2]) < fabs(c[ax])) ax = 2;
+        double e1[3] = {-c[ax] * c[0], -c[ax] * c[1], -c[ax] * c[2]};
+        e1[ax] += 1.0;
+        const double n1 = sqrt(dot3(e1, e1));
+        for (int k = 0; k < 3; ++k) e1[k] /= n1;
+        double e2[3];
+        cross3(c, e1, e2);
+        // gnomonic boxes of sub-frames lane and 64 + lane
+        const double* nf = p.cell_normals + (size_t)r * S * 12;
+        double a0[2], a1[2], b0[2], b1[2];
+        bool ok = true;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            a0[h] = 1e300; a1[h] = -1e300; b0[h] = 1e300; b1[h] = -1e300;
+            const int sf = lane + 64 * h;
+            if (sf >= S) continue;
+            for (int k = 0; k < 4; ++k) {
+                double v[3];
+                quad_vertex(nf + 12 * sf, k, v);
+                const double vc = dot3(v, c);
+                if (!(vc > 1e-6 * sqrt(dot3(v, v)))) { ok = false; continue; }
+                const double X = dot3(v, e1) / vc, Y = dot3(v, e2) / vc;
+                a0[h] = fmin(a0[h], X); a1[h] = fmax(a1[h], X); b0[h] = fmin(b0[h], Y); b1[h] = fmax(b1[h], Y);
+            }
         }
-    for (int i = 0; i < 2 * kLocL * kLocL; ++i) M[i] = 0ull;
-    L[13] = 0.0;
-    L[14] = L[15] = 0.0;
-    if (!ok || !(x1 >= x0) || !(y1 >= y0) || !(x1 - x0 < 1e6) || !(y1 - y0 < 1e6)) return;
-    const double pad = 1e-9 * (1.0 + fmax(fmax(fabs(x0), fabs(x1)), fmax(fabs(y0), fabs(y1))));
-    x0 -= pad; x1 += pad; y0 -= pad; y1 += pad;
-    const double idx = kLocL / (x1 - x0), idy = kLocL / (y1 - y0);
-    L[9] = x0; L[10] = y0; L[11] = idx; L[12] = idy;
-    for (int s = 0; s < n_sub; ++s) {
-        double a0 = 1e300, a1 = -1e300, b0 = 1e300, b1 = -1e300;
-        for (int k = 0; k < 4; ++k) {
-            double v[3];
-            quad_vertex(nf + 12 * s, k, v);
-            const double vc = dot3(v, c);
-            const double X = dot3(v, e1) / vc, Y = dot3(v, e2) / vc;
-            a0 = fmin(a0, X); a1 = fmax(a1, X); b0 = fmin(b0, Y); b1 = fmax(b1, Y);
+        ok = __ballot(!ok) == 0ull;
+        double x0 = wave_min(fmin(a0[0], a0[1])), x1 = wave_max(fmax(a1[0], a1[1]));
+        double y0 = wave_min(fmin(b0[0], b0[1])), y1 = wave_max(fmax(b1[0], b1[1]));
+        const bool usable = ok && x1 >= x0 && y1 >= y0 && x1 - x0 < 1e6 && y1 - y0 < 1e6;
+        unsigned long long w0 = 0ull, w1 = 0ull;      // mask words of locator cell `lane`
+        double pad = 0.0, idx = 0.0, idy = 0.0;
+        if (usable) {
+            pad = 1e-9 * (1.0 + fmax(fmax(fabs(x0), fabs(x1)), fmax(fabs(y0), fabs(y1))));
+            x0 -= pad; x1 += pad; y0 -= pad; y1 += pad;
+            idx = kLocL / (x1 - x0);
+            idy = kLocL / (y1 - y0);
+            int i0[2], i1[2], j0[2], j1[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                i0[h] = max(0, (int)floor((a0[h] - pad - x0) * idx));
+                i1[h] = min(kLocL - 1, (int)floor((a1[h] + pad - x0) * idx));
+                j0[h] = max(0, (int)floor((b0[h] - pad - y0) * idy));
+                j1[h] = min(kLocL - 1, (int)floor((b1[h] + pad - y0) * idy));
+                if (lane + 64 * h >= S) { i0[h] = 1; i1[h] = 0; }
+            }
+            for (int cell = 0; cell < kLocL * kLocL; ++cell) {
+                const int ci = cell / kLocL, cj = cell % kLocL;
+                const unsigned long long m0 = __ballot(i0[0] <= ci && ci <= i1[0] && j0[0] <= cj && cj <= j1[0]);
+                const unsigned long long m1 = __ballot(i0[1] <= ci && ci <= i1[1] && j0[1] <= cj && cj <= j1[1]);
+                if (lane == cell) { w0 = m0; w1 = m1; }
+            }
         }
-        const int i0 = max(0, (int)floor((a0 - pad - x0) * idx)), i1 = min(kLocL - 1, (int)floor((a1 + pad - x0) * idx));
-        const int j0 = max(0, (int)floor((b0 - pad - y0) * idy)), j1 = min(kLocL - 1, (int)floor((b1 + pad - y0) * idy));
-        for (int i = i0; i <= i1; ++i)
-            for (int j = j0; j <= j1; ++j) M[2 * (i * kLocL + j) + (s >> 6)] |= 1ull << (s & 63);
+        static_assert(kLocL * kLocL == kWave, "one locator cell per lane");
+        M[2 * lane] = w0;
+        M[2 * lane + 1] = w1;
+        if (lane < kLocHead) {
+            double v = 0.0;
+            if (lane < 3) v = c[lane];
+            else if (lane < 6) v = e1[lane - 3];
+            else if (lane < 9) v = e2[lane - 6];
+            else if (usable)
+                v = lane == 9 ? x0 : lane == 10 ? y0 : lane == 11 ? idx : lane == 12 ? idy : lane == 13 ? 1.0
+                  : lane == 14 ? x0 + kLocL / idx : y0 + kLocL / idy;
+            L[lane] = v;
+        }
     }
-    L[13] = 1.0;
+}
+
+// Cell-ordered copies of what the join reads of each frame: one wavefront
+// per frame.
+__global__ __launch_bounds__(256) void k_frame_gather(const FovParams p) {
+    const int lane = threadIdx.x & 63;
+    const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int nd = 12 * p.n_sub;
+    for (int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; r < p.n_frames; r += n_waves) {
+        const int f = p.cell_frames[r];
+        const double* src = p.normals + (size_t)f * nd;
+        double* dst = p.cell_normals + (size_t)r * nd;
+        for (int i = lane; i < nd; i += kWave) dst[i] = src[i];
+        if (lane < 4) p.cell_obs[4 * r + lane] = lane == 0 ? p.ft[f] : p.fobs[3 * (size_t)f + lane - 1];
+    }
 }
 
 // Rigorous bounds of the Sun's speed and acceleration over segments
@@ -301,10 +342,13 @@ __device__ __forceinline__ void wave_append(unsigned long long* list, unsigned l
 }
 
 // Per-wavefront staging of list appends in LDS: appends gather in `buf`
-// (128 entries) and reach the global list 64 or more at a time, so the
-// shared counter sees one atomic per flush instead of one per append.
-// Both calls must be made by the whole wavefront.
+// (kEntries entries) and reach the global list kEntries - 63 or more at a
+// time, so the shared counter, one address that every wavefront of the
+// chip updates, sees one atomic per flush instead of one per append.  The
+// pair list, by far the longest, gets the larger buffer.  Both calls must
+// be made by the whole wavefront.
 constexpr int kBufEntries = 128;
+constexpr int kPairBufEntries = 512;
 
 __device__ __forceinline__ void buf_flush(unsigned long long* __restrict__ buf, int& n,
                                           unsigned long long* __restrict__ list, unsigned long long* count,
@@ -323,6 +367,7 @@ __device__ __forceinline__ void buf_flush(unsigned long long* __restrict__ buf, 
     n = 0;
 }
 
+template <int kEntries>
 __device__ __forceinline__ void buf_append(unsigned long long* __restrict__ buf, int& n, bool pred,
                                            unsigned long long key, unsigned long long* __restrict__ list,
                                            unsigned long long* count, int64_t cap) {
@@ -332,7 +377,7 @@ __device__ __forceinline__ void buf_append(unsigned long long* __restrict__ buf,
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     if (pred) buf[n + __popcll(m & lt)] = key;
     n += __popcll(m);
-    if (n >= 64) buf_flush(buf, n, list, count, cap);
+    if (n > kEntries - kWave) buf_flush(buf, n, list, count, cap);
 }
 
 // Everything one (object, batch) needs to skip frames it cannot reach.
@@ -442,48 +487,64 @@ __device__ __forceinline__ bool frame_cap_hit(const ObjBounds& o, const double* 
     return !(dot3(cp, o.dh) < thr - 1e-12);
 }
 
+// Locator header of one frame (see kLocStride), read with eight 16-byte
+// loads issued together rather than one dependent read after another.
+struct LocHead {
+    double c[3], e1[3], e2[3];
+    double x0, y0, idx, idy, usable, x1, y1;
+};
+__device__ __forceinline__ LocHead loc_head(const double* __restrict__ L) {
+    const double2* q = reinterpret_cast<const double2*>(L);
+    const double2 a = q[0], b = q[1], c = q[2], d = q[3], e = q[4], f = q[5], g = q[6], k = q[7];
+    LocHead h;
+    h.c[0] = a.x; h.c[1] = a.y; h.c[2] = b.x;
+    h.e1[0] = b.y; h.e1[1] = c.x; h.e1[2] = c.y;
+    h.e2[0] = d.x; h.e2[1] = d.y; h.e2[2] = e.x;
+    h.x0 = e.y; h.y0 = f.x; h.idx = f.y; h.idy = g.x; h.usable = g.y;
+    h.x1 = k.x; h.y1 = k.y;
+    return h;
+}
+
 // Can an object's direction cap (o.dh, theta) reach the gnomonic box of
-// frame f's sub-frames?  The same widening of the cap's image as in
-// sub_candidates; without a usable locator, yes.
-__device__ __forceinline__ bool loc_box_hit(const FovParams& p, const ObjBounds& o, int f) {
+// the sub-frames of the frame at cell rank r?  The same widening of the
+// cap's image as in sub_candidates; without a usable locator, yes.
+__device__ __forceinline__ bool loc_box_hit(const FovParams& p, const ObjBounds& o, int r) {
     if (!p.loc || o.overflow) return true;
-    const double* L = p.loc + (size_t)kLocStride * (unsigned)f;
-    if (!(L[13] > 0.5)) return true;
-    const double uc = dot3(o.dh, L);
+    const LocHead h = loc_head(p.loc + (size_t)kLocStride * (unsigned)r);
+    if (!(h.usable > 0.5)) return true;
+    const double uc = dot3(o.dh, h.c);
     if (!(uc > 0.0) || !(o.cth > 0.0)) return true;
-    const double X = dot3(o.dh, L + 3) / uc, Y = dot3(o.dh, L + 6) / uc;
+    const double X = dot3(o.dh, h.e1) / uc, Y = dot3(o.dh, h.e2) / uc;
     const double t = o.sth / o.cth;
     const double ru = sqrt(X * X + Y * Y);
     if (!(ru * t < 0.5)) return true;
     const double T = (ru + t) / (1.0 - ru * t);
     const double mg = t * (1.0 + T * T) * (1.0 + 1e-9) + 1e-12 * (1.0 + ru);
-    const double X1 = L[9] + kLocL / L[11], Y1 = L[10] + kLocL / L[12];
-    return !(X + mg < L[9] || X - mg > X1 || Y + mg < L[10] || Y - mg > Y1);
+    return !(X + mg < h.x0 || X - mg > h.x1 || Y + mg < h.y0 || Y - mg > h.y1);
 }
 
-// Sub-frames of frame f that a direction within angle atan(t) of u can lie
-// in: bit s of m[s / 64].  With a locator, u's gnomonic point widened by
-// the image of that angle (the map stretches by at most 1 + T^2 at
-// tangent-plane radius T) selects the locator cells; without one, or for
-// a wide query, every sub-frame.  A query box off the frame's box gives
-// none.
-__device__ __forceinline__ void sub_candidates(const FovParams& p, int f, const double u[3], double t,
+// Sub-frames of a frame (locator header h, mask words M, or no locator)
+// that a direction within angle atan(t) of u can lie in: bit s of
+// m[s / 64].  With a locator, u's gnomonic point widened by the image of
+// that angle (the map stretches by at most 1 + T^2 at tangent-plane
+// radius T) selects the locator cells; without one, or for a wide query,
+// every sub-frame.  A query box off the frame's box gives none.  The mask
+// words of up to nine cells are read together.
+__device__ __forceinline__ void sub_candidates(int S, bool have_loc, const LocHead& h,
+                                               const ulonglong2* __restrict__ M, const double u[3], double t,
                                                unsigned long long m[2]) {
-    const int S = p.n_sub;
     m[0] = S >= 64 ? ~0ull : ((1ull << S) - 1ull);
     m[1] = S > 64 ? (S >= 128 ? ~0ull : ((1ull << (S - 64)) - 1ull)) : 0ull;
-    if (!p.loc) return;
-    const double* L = p.loc + (size_t)kLocStride * (unsigned)f;
-    if (!(L[13] > 0.5)) return;
-    const double uc = dot3(u, L);
+    if (!have_loc || !(h.usable > 0.5)) return;
+    const double uc = dot3(u, h.c);
     if (!(uc > 0.0)) return;
-    const double X = dot3(u, L + 3) / uc, Y = dot3(u, L + 6) / uc;
+    const double X = dot3(u, h.e1) / uc, Y = dot3(u, h.e2) / uc;
     const double ru = sqrt(X * X + Y * Y);
     if (!(ru * t < 0.5)) return;
     const double T = (ru + t) / (1.0 - ru * t);
     const double mg = t * (1.0 + T * T) * (1.0 + 1e-9) + 1e-12 * (1.0 + ru);
-    const double fx0 = (X - mg - L[9]) * L[11], fx1 = (X + mg - L[9]) * L[11];
-    const double fy0 = (Y - mg - L[10]) * L[12], fy1 = (Y + mg - L[10]) * L[12];
+    const double fx0 = (X - mg - h.x0) * h.idx, fx1 = (X + mg - h.x0) * h.idx;
+    const double fy0 = (Y - mg - h.y0) * h.idy, fy1 = (Y + mg - h.y0) * h.idy;
     if (fx1 < 0.0 || fy1 < 0.0 || fx0 >= kLocL || fy0 >= kLocL) {   // off the frame's box
         m[0] = m[1] = 0ull;
         return;
@@ -491,16 +552,30 @@ __device__ __forceinline__ void sub_candidates(const FovParams& p, int f, const 
     if (!(fx0 >= -1e9 && fx1 <= 1e9 && fy0 >= -1e9 && fy1 <= 1e9)) return;
     const int ix0 = (int)floor(fmax(fx0, 0.0)), ix1 = (int)floor(fmin(fx1, kLocL - 1.0));
     const int iy0 = (int)floor(fmax(fy0, 0.0)), iy1 = (int)floor(fmin(fy1, kLocL - 1.0));
-    if ((ix1 - ix0 + 1) * (iy1 - iy0 + 1) > 9) return;
-    const unsigned long long* M = reinterpret_cast<const unsigned long long*>(L + kLocHead);
+    const int ny = iy1 - iy0 + 1, n = (ix1 - ix0 + 1) * ny;
+    if (n > 9) return;
     unsigned long long a = 0ull, b = 0ull;
-    for (int ix = ix0; ix <= ix1; ++ix)
-        for (int iy = iy0; iy <= iy1; ++iy) {
-            a |= M[2 * (ix * kLocL + iy)];
-            b |= M[2 * (ix * kLocL + iy) + 1];
-        }
+    int dx = 0, dy = 0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const bool in = k < n;
+        const ulonglong2 w = M[in ? (ix0 + dx) * kLocL + iy0 + dy : ix0 * kLocL + iy0];
+        if (in) { a |= w.x; b |= w.y; }
+        if (++dy == ny) { dy = 0; ++dx; }
+    }
     m[0] = a;
     m[1] = b;
+}
+
+// The r-th set bit (counted from 0, r < popcount(w)) of a 64-bit word.
+__device__ __forceinline__ int nth_set_bit(unsigned long long w, int r) {
+    int pos = 0;
+#pragma unroll
+    for (int width = 32; width >= 1; width >>= 1) {
+        const int c = __popcll(w & ((1ull << width) - 1ull));
+        if (r >= c) { r -= c; w >>= width; pos += width; }
+    }
+    return pos;
 }
 
 // Linear-motion test of an (object, frame) pair that passed the cap test,
@@ -512,18 +587,31 @@ __device__ __forceinline__ void sub_candidates(const FovParams& p, int f, const 
 // |ul|.  Every lane with `has` classifies its pair: sure pairs go to the
 // pair list, undecided (frame, sub-frame, object) keys, or one
 // (frame, kAllSubs, object) key for a void test, to the exact-test
-// candidates.  The whole wavefront calls it.
-__device__ void classify_emit(const FovParams& p, bool has, const ObjBounds& o, int f, double tr, double Asun,
+// candidates.  The sub-frames the locator leaves to each pair are pooled
+// over the wavefront and tested 64 at a time, one per lane, so a pair with
+// many of them does not hold the others up.  Frames are named by their
+// cell rank r.  The whole wavefront calls it.
+__device__ void classify_emit(const FovParams& p, bool has, const ObjBounds& o, int r, double tr, double Asun,
                               unsigned long long gobj, unsigned long long* cbuf, int& nc, unsigned long long* pbuf,
                               int& np, unsigned long long& n_exact) {
+    const int lane = threadIdx.x & 63;
     bool all = false;
     unsigned long long m0 = 0ull, m1 = 0ull;
     double ul[3] = {0.0, 0.0, 0.0}, e2 = 0.0;
+    int f = 0;
     if (has) {
+        // every read of the frame's records is issued before the first use
+        f = p.cell_frames[r];
+        const double2* q = reinterpret_cast<const double2*>(p.cell_obs + 4 * (size_t)(unsigned)r);
+        const double2 ob01 = q[0], ob23 = q[1];
+        LocHead h;
+        h.usable = 0.0;
+        if (p.loc) h = loc_head(p.loc + (size_t)kLocStride * (unsigned)r);
         all = !o.lin_ok;
         if (o.lin_ok) {
-            const double dt = p.ft[f] - tr;
-            for (int c = 0; c < 3; ++c) ul[c] = o.x[c] + o.v[c] * dt - p.fobs[3 * (size_t)f + c];
+            const double ob[4] = {ob01.x, ob01.y, ob23.x, ob23.y};
+            const double dt = ob[0] - tr;
+            for (int c = 0; c < 3; ++c) ul[c] = o.x[c] + o.v[c] * dt - ob[1 + c];
             const double ad = fabs(dt) + o.taumax;
             e2 = 2.0 * (o.vbn * o.taumax + 0.5 * (o.a2b + Asun) * ad * ad + 1e-12);
             const double u2 = dot3(ul, ul);
@@ -531,7 +619,10 @@ __device__ void classify_emit(const FovParams& p, bool has, const ObjBounds& o, 
                 all = true;
             } else {
                 unsigned long long m[2];
-                sub_candidates(p, f, ul, e2 / sqrt(u2 - e2 * e2), m);
+                const ulonglong2* M = p.loc ? reinterpret_cast<const ulonglong2*>(
+                                                  p.loc + (size_t)kLocStride * (unsigned)r + kLocHead)
+                                            : nullptr;
+                sub_candidates(p.n_sub, p.loc != nullptr, h, M, ul, e2 / sqrt(u2 - e2 * e2), m);
                 m0 = m[0];
                 m1 = m[1];
             }
@@ -539,26 +630,47 @@ __device__ void classify_emit(const FovParams& p, bool has, const ObjBounds& o, 
     }
     const unsigned long long base = ((unsigned long long)(unsigned)f << 32) | gobj;
     if (all) ++n_exact;
-    buf_append(cbuf, nc, all, base | kAllSubs, p.cand, p.n_cand, p.cand_cap);
-    const double* nrm = p.normals + (size_t)(unsigned)f * p.n_sub * 12;
-    while (__ballot((m0 | m1) != 0ull) != 0ull) {
-        int s = -1;
-        if (m0) { s = __ffsll((long long)m0) - 1; m0 &= m0 - 1ull; }
-        else if (m1) { s = 64 + __ffsll((long long)m1) - 1; m1 &= m1 - 1ull; }
-        int r = 0;
-        if (s >= 0) {
-            const double* n = nrm + 12 * s;
-            r = 1;
-            for (int i = 0; i < 4; ++i) {
-                const double t = dot3(n + 3 * i, ul);
-                if (t <= -e2) r = 0;
-                else if (!(t > e2) && r == 1) r = 2;
+    buf_append<kBufEntries>(cbuf, nc, all, base | kAllSubs, p.cand, p.n_cand, p.cand_cap);
+    const int cnt = __popcll(m0) + __popcll(m1);
+    int incl = cnt;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int t = __shfl_up(incl, off, kWave);
+        if (lane >= off) incl += t;
+    }
+    const int total = __shfl(incl, kWave - 1, kWave);
+    for (int t0 = 0; t0 < total; t0 += kWave) {
+        const int t = t0 + lane;
+        // the pair holding test t: the first lane whose inclusive count exceeds t
+        int i = 0;
+#pragma unroll
+        for (int step = kWave / 2; step > 0; step >>= 1) {
+            const int v = __shfl(incl, i + step - 1, kWave);
+            if (v <= t) i += step;
+        }
+        const int nb = t - (__shfl(incl, i, kWave) - __shfl(cnt, i, kWave));   // its nb-th sub-frame
+        const unsigned long long w0 = __shfl(m0, i, kWave), w1 = __shfl(m1, i, kWave);
+        const double u0 = __shfl(ul[0], i, kWave), u1 = __shfl(ul[1], i, kWave), u2 = __shfl(ul[2], i, kWave);
+        const double e = __shfl(e2, i, kWave);
+        const int ri = __shfl(r, i, kWave);
+        const unsigned long long bi = __shfl(base, i, kWave);
+        int res = 0, s = 0;
+        if (t < total) {
+            const int c0 = __popcll(w0);
+            s = nb < c0 ? nth_set_bit(w0, nb) : 64 + nth_set_bit(w1, nb - c0);
+            const double* n = p.cell_normals + ((size_t)(unsigned)ri * p.n_sub + s) * 12;
+            res = 1;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const double d = n[3 * k] * u0 + n[3 * k + 1] * u1 + n[3 * k + 2] * u2;
+                if (d <= -e) res = 0;
+                else if (!(d > e) && res == 1) res = 2;
             }
         }
-        const unsigned long long key = base | ((unsigned long long)(s < 0 ? 0 : s) << 25);
-        if (r == 2) ++n_exact;
-        buf_append(pbuf, np, r == 1, key, p.pairs, p.n_pairs, p.cap);
-        buf_append(cbuf, nc, r == 2, key, p.cand, p.n_cand, p.cand_cap);
+        const unsigned long long key = bi | ((unsigned long long)s << 25);
+        if (res == 2) ++n_exact;
+        buf_append<kPairBufEntries>(pbuf, np, res == 1, key, p.pairs, p.n_pairs, p.cap);
+        buf_append<kBufEntries>(cbuf, nc, res == 2, key, p.cand, p.n_cand, p.cand_cap);
     }
 }
 
@@ -617,13 +729,6 @@ struct __align__(16) double6 {
     double a, b, c, d, e, f;
 };
 
-// Linear-motion data of one object of a join item, kept in LDS so that
-// any lane can run the linear test of any (object, frame) pair.
-struct ObjLin {
-    double x[3], v[3];
-    double taumax, vbn, a2b;
-    unsigned long long gobj;    // global object index; bit 63 set: no linear test
-};
 constexpr int kLinQueue = 2 * kWave;
 constexpr int kItemChunk = 3;
 
@@ -632,35 +737,50 @@ constexpr int kItemChunk = 3;
 // the frame records of the 27 neighbouring cells are read 64 at a time,
 // one per lane, and broadcast for the cap test.  (object, frame) pairs
 // that pass it are queued in LDS and take the linear-motion test 64 at a
-// time, one pair per lane.
-__global__ __launch_bounds__(256, 3) void k_fov_cells(const FovParams p) {
+// time, one pair per lane, reading their object's data from the lane that
+// holds it.  The cap-test loop reads LDS only: the locator-box test, a
+// global read, is left to the linear test's own locator query except for
+// objects without one.  Items are in (batch, cell) order; the waves of
+// one XCD start on their own slice of the list, so that neighbouring cells
+// share that XCD's L2, and help the other slices when theirs runs out.
+constexpr int kJoinWaves = 4;        // resident waves per SIMD of the join kernels
+__global__ __launch_bounds__(256, kJoinWaves) void k_fov_cells(const FovParams p) {
     const int lane = threadIdx.x & 63, wv = (threadIdx.x >> 6) & 3;
     unsigned long long n_cand = 0, n_exact = 0, n_visit = 0;
     const double* __restrict__ caps = p.cell_caps;
     const int n_items = p.item_start[p.n_keys];
-    __shared__ unsigned long long bufs[4][kBufEntries], pbufs[4][kBufEntries];
-    __shared__ ObjLin objs_all[4][kWave];
+    __shared__ unsigned long long bufs[4][kBufEntries], pbufs[4][kPairBufEntries];
     __shared__ unsigned long long queue_all[4][kLinQueue];
     __shared__ double6 fcap_all[4][kWave];
     unsigned long long* buf = bufs[wv];
     unsigned long long* pbuf = pbufs[wv];
     int npbuf = 0;
     double6* fcap = fcap_all[wv];
-    ObjLin* objs = objs_all[wv];
     unsigned long long* queue = queue_all[wv];
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     int nbuf = 0;
     int item = 0, item_end = 0;
+    const int home = (int)(blockIdx.x % kXcds);
+    int tried = 0;                            // slices found empty
     for (;;) {
-        // items are taken kItemChunk at a time: one atomic on the shared
-        // counter per chunk
+        // items are taken kItemChunk at a time: one atomic on a slice's
+        // cursor per chunk
         if (item >= item_end) {
-            int first = 0;
-            if (lane == 0) first = (int)atomicAdd(p.item_next, (unsigned)kItemChunk);
-            item = __shfl(first, 0, kWave);
-            item_end = min(item + kItemChunk, n_items);
+            while (tried < kXcds) {
+                const int x = (home + tried) % kXcds;
+                const int lo = (int)((int64_t)n_items * x / kXcds), hi = (int)((int64_t)n_items * (x + 1) / kXcds);
+                int first = 0;
+                if (lane == 0) first = (int)atomicAdd(p.item_next + kCursorStride * x, (unsigned)kItemChunk);
+                first = __shfl(first, 0, kWave);
+                if (first < hi - lo) {
+                    item = lo + first;
+                    item_end = min(item + kItemChunk, hi);
+                    break;
+                }
+                ++tried;
+            }
+            if (tried >= kXcds) break;
         }
-        if (item >= n_items) break;
         const unsigned long long it = p.items[item++];
         const int64_t key = (int64_t)(it >> 32);
         const int chunk = (int)(it & 0xffffffffull);
@@ -697,35 +817,33 @@ __global__ __launch_bounds__(256, 3) void k_fov_cells(const FovParams p) {
         const bool has = q < o1;
         const int64_t j = has ? p.obj_sorted[q] : 0;
         ObjBounds o;
-        const bool live = has && object_bounds(p, b, j, o);
-        wave_lds_sync();                      // the previous item's queue and objects are done
-        {
-            ObjLin& ol = objs[lane];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) { ol.x[c] = o.x[c]; ol.v[c] = o.v[c]; }
-            ol.taumax = o.taumax; ol.vbn = o.vbn; ol.a2b = o.a2b;
-            ol.gobj = (unsigned long long)(p.b_obj0[b] + j) | (o.lin_ok ? 0ull : (1ull << 63));
-        }
-        wave_lds_sync();
+        for (int c = 0; c < 3; ++c) { o.x[c] = 0.0; o.v[c] = 0.0; }
+        o.taumax = o.vbn = o.a2b = 0.0;
+        o.lin_ok = false;
+        const bool live = has && object_bounds(p, b, j, o);
+        // global object index; bit 63 set: no linear test
+        const unsigned long long gtag = (unsigned long long)(p.b_obj0[b] + j) | (o.lin_ok ? 0ull : (1ull << 63));
+        wave_lds_sync();                      // the previous item's queue is done
         int nq = 0;                           // queued (object, frame) pairs, wave-uniform
         // linear test of the first n queued pairs, one per lane
         auto drain = [&](int n) {
-            const bool has = lane < n;
-            int f = 0;
-            unsigned long long gobj = 0;
+            const bool queued = lane < n;
+            const unsigned long long e = queued ? queue[lane] : 0ull;
+            const int src = (int)(e & 63);
+            const int r = (int)(e >> 8);
             ObjBounds lo;
-            lo.lin_ok = false;
-            if (has) {
-                const unsigned long long e = queue[lane];
-                const ObjLin& ol = objs[e & 63];
-                f = (int)(e >> 8);
-                gobj = ol.gobj & ~(1ull << 63);
 #pragma unroll
-                for (int c = 0; c < 3; ++c) { lo.x[c] = ol.x[c]; lo.v[c] = ol.v[c]; }
-                lo.taumax = ol.taumax; lo.vbn = ol.vbn; lo.a2b = ol.a2b;
-                lo.lin_ok = (ol.gobj >> 63) == 0ull;
+            for (int c = 0; c < 3; ++c) {
+                lo.x[c] = __shfl(o.x[c], src, kWave);
+                lo.v[c] = __shfl(o.v[c], src, kWave);
             }
-            classify_emit(p, has, lo, f, tr, Asun, gobj, buf, nbuf, pbuf, npbuf, n_exact);
+            lo.taumax = __shfl(o.taumax, src, kWave);
+            lo.vbn = __shfl(o.vbn, src, kWave);
+            lo.a2b = __shfl(o.a2b, src, kWave);
+            const unsigned long long g = __shfl(gtag, src, kWave);
+            lo.lin_ok = (g >> 63) == 0ull;
+            classify_emit(p, queued, lo, r, tr, Asun, g & ~(1ull << 63), buf, nbuf, pbuf, npbuf, n_exact);
         };
         for (int g0 = 0; g0 < total; g0 += kWave) {
             // lane l holds frame record g0 + l of the neighbourhood list
@@ -733,14 +851,14 @@ __global__ __launch_bounds__(256, 3) void k_fov_cells(const FovParams p) {
             int nc = 0;
             for (int t = 1; t < 27; ++t) nc = (__shfl(excl, t, kWave) <= g) ? t : nc;
             const int rk = __shfl(my_a0, nc, kWave) + (g - __shfl(excl, nc, kWave));
-            // the chunk's cap records go to LDS and are read back as broadcasts
+            // the chunk's cap records (with the cell rank in place of the
+            // frame index) go to LDS and are read back as broadcasts
             double6 rec = {0.0, 0.0, 0.0, 2.0, 0.0, 0.0};
             if (g < total) {
                 const double* cp = caps + 8 * (int64_t)rk;
                 const double2 c01 = *reinterpret_cast<const double2*>(cp);
                 const double2 c23 = *reinterpret_cast<const double2*>(cp + 2);
-                const double2 c45 = *reinterpret_cast<const double2*>(cp + 4);
-                rec = {c01.x, c01.y, c23.x, c23.y, c45.x, c45.y};
+                rec = {c01.x, c01.y, c23.x, c23.y, cp[4], (double)rk};
             }
             wave_lds_sync();                  // the previous chunk's records are read
             fcap[lane] = rec;
@@ -750,12 +868,12 @@ __global__ __launch_bounds__(256, 3) void k_fov_cells(const FovParams p) {
             for (int m = 0; m < n; ++m) {
                 const double6 cm = fcap[m];
                 const double cpm[5] = {cm.a, cm.b, cm.c, cm.d, cm.e};
-                const unsigned long long f = (unsigned long long)(unsigned int)(int)cm.f;
-                const bool hit = live && frame_cap_hit(o, cpm) && loc_box_hit(p, o, (int)f);
+                const unsigned long long rq = (unsigned long long)(unsigned int)(int)cm.f;
+                const bool hit = live && frame_cap_hit(o, cpm) && (o.lin_ok || loc_box_hit(p, o, (int)rq));
                 const unsigned long long mask = __ballot(hit);
                 if (mask == 0ull) continue;
                 if (hit) ++n_cand;
-                if (hit) queue[nq + __popcll(mask & lt)] = (f << 8) | (unsigned long long)lane;
+                if (hit) queue[nq + __popcll(mask & lt)] = (rq << 8) | (unsigned long long)lane;
                 nq += __popcll(mask);
                 if (nq >= kWave) {
                     wave_lds_sync();
@@ -791,52 +909,150 @@ __global__ __launch_bounds__(256, 3) void k_fov_cells(const FovParams p) {
     }
 }
 
-// Wide objects: one wavefront per (object, batch).  Without a usable cap
-// its lanes split every frame of the batch; otherwise they take the cap's
-// grid cells 64 at a time, and the frame records of those cells are dealt
-// out 64 at a time across the lanes (a prefix sum of the cell lengths,
-// then a binary search per lane), so empty and short cells cost nothing.
-__global__ __launch_bounds__(256) void k_fov_wide(const FovParams p) {
-    const int lane = threadIdx.x & 63;
-    __shared__ int s_incl[4][kWave], s_base[4][kWave];
-    int* incl_w = s_incl[(threadIdx.x >> 6) & 3];
-    int* base_w = s_base[(threadIdx.x >> 6) & 3];
+// Work units of wide object w: the cells of its cap box, or the frames of
+// its batch when it has no usable cap (0 for a failed or non-finite
+// object), and the parts they split into: one per 64 cells or
+// kWidePartFrames frames, at most p.wide_max_parts.
+__device__ __forceinline__ int wide_units(const FovParams& p, int64_t w, ObjBounds& o, int& b, int64_t& j,
+                                          int& parts) {
+    const unsigned long long e = p.wide[w];
+    b = (int)(e >> 32);
+    j = (int64_t)(e & 0xffffffffull);
+    parts = 0;
+    if (!object_bounds(p, b, j, o)) return 0;
+    const int n = o.overflow ? p.cell_start[p.b_koff[b + 1]] - p.cell_start[p.b_koff[b]] : o.ncell;
+    const int per = o.overflow ? kWidePartFrames : kWave;
+    parts = min((n + per - 1) / per, p.wide_max_parts);
+    return n;
+}
+
+__global__ void k_wide_parts(const FovParams p) {
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= p.n_pairs_total) return;
     const unsigned long long nw = *p.n_wide;
-    const int64_t n_items = (int64_t)(nw < (unsigned long long)p.n_pairs_total ? nw : p.n_pairs_total);
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    __shared__ unsigned long long bufs[4][kBufEntries], pbufs[4][kBufEntries];
-    unsigned long long* buf = bufs[(threadIdx.x >> 6) & 3];
-    unsigned long long* pbuf = pbufs[(threadIdx.x >> 6) & 3];
+    int parts = 0;
+    if ((unsigned long long)w < nw) {
+        ObjBounds o;
+        int b;
+        int64_t j;
+        wide_units(p, w, o, b, j, parts);
+    }
+    p.wide_parts[w] = parts;
+}
+
+// Wide objects, one part per wavefront at a time: the cap-box cells of a
+// part (64 at most) or its frames of the batch for an object without a
+// usable cap.  The frame records of a part's cells are dealt out 64 at a
+// time across the lanes (a prefix sum of the cell lengths, then a binary
+// search per lane), so empty and short cells cost nothing.  Frames that
+// pass the cap test are queued in LDS and take the linear test 64 at a
+// time, one per lane.  Parts are taken through per-XCD cursors, as in the
+// per-cell join; a part's object is found by a 64-way search of the part
+// offsets, the lanes probing together.
+__global__ __launch_bounds__(256, kJoinWaves) void k_fov_wide(const FovParams p) {
+    const int lane = threadIdx.x & 63, wv = (threadIdx.x >> 6) & 3;
+    __shared__ int s_incl[4][kWave], s_base[4][kWave], s_queue[4][2 * kWave];
+    __shared__ unsigned long long bufs[4][kBufEntries], pbufs[4][kPairBufEntries];
+    int* incl_w = s_incl[wv];
+    int* base_w = s_base[wv];
+    int* queue = s_queue[wv];
+    unsigned long long* buf = bufs[wv];
+    unsigned long long* pbuf = pbufs[wv];
+    const unsigned long long nw = *p.n_wide;
+    const int n_obj_w = (int)(nw < (unsigned long long)p.n_pairs_total ? nw : p.n_pairs_total);
+    const int n_parts = p.wide_off[p.n_pairs_total];
+    const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     int nbuf = 0, npbuf = 0;
     unsigned long long n_cand = 0, n_exact = 0, n_over = 0;
-    for (int64_t it = wave; it < n_items; it += n_waves) {
-        const unsigned long long w = p.wide[it];
-        const int b = (int)(w >> 32);
-        const int64_t j = (int64_t)(w & 0xffffffffull);
+    const int home = (int)(blockIdx.x % kXcds);
+    int tried = 0, part = 0, part_end = 0;
+    int w = 0;                                   // object of the previous part
+    for (;;) {
+        if (part >= part_end) {
+            while (tried < kXcds) {
+                const int x = (home + tried) % kXcds;
+                const int lo = (int)((int64_t)n_parts * x / kXcds), hi = (int)((int64_t)n_parts * (x + 1) / kXcds);
+                int first = 0;
+                if (lane == 0) first = (int)atomicAdd(p.wide_next + kCursorStride * x, 4u);
+                first = __shfl(first, 0, kWave);
+                if (first < hi - lo) {
+                    part = lo + first;
+                    part_end = min(part + 4, hi);
+                    break;
+                }
+                ++tried;
+            }
+            if (tried >= kXcds) break;
+        }
+        const int pi = part++;
+        // object w of part pi: the last w with wide_off[w] <= pi
+        if (!(w < n_obj_w && p.wide_off[w] <= pi && pi < p.wide_off[w + 1])) {
+            int lo = 0, hi = n_obj_w;               // wide_off[lo] <= pi < wide_off[hi]
+            while (hi - lo > 1) {
+                const int q = lo + (int)(((int64_t)(hi - lo) * (lane + 1)) >> 6);
+                const bool le = lane < kWave - 1 && p.wide_off[q] <= pi;
+                const unsigned long long m = __ballot(le);
+                const int L = m ? 63 - __clzll((long long)m) : -1;
+                const int nlo = L >= 0 ? __shfl(q, L, kWave) : lo;
+                const int nhi = L + 1 < kWave - 1 ? __shfl(q, L + 1, kWave) : hi;
+                lo = nlo;
+                hi = nhi;
+            }
+            w = lo;
+        }
+        const int k = pi - p.wide_off[w];
         ObjBounds o;
-        if (!object_bounds(p, b, j, o)) continue;
+        int b, parts;
+        int64_t j;
+        const int n_units = wide_units(p, w, o, b, j, parts);
+        if (k >= parts) continue;
+        // units [u0, u1) of the object's n_units
+        const int u0 = (int)((int64_t)n_units * k / parts), u1 = (int)((int64_t)n_units * (k + 1) / parts);
         const unsigned long long gobj = (unsigned long long)(p.b_obj0[b] + j);
         const double tr = p.t_ref[b];
         const double Asun = p.btab[kBatchStride * b + 14];
+        int nq = 0;                              // queued frames, wave-uniform
+        // queue the frames (cell ranks) of the lanes with `hit`; run the
+        // linear test on every full 64
+        auto offer = [&](bool hit, int r) {
+            const unsigned long long m = __ballot(hit);
+            if (m == 0ull) return;
+            if (hit) {
+                ++n_cand;
+                queue[nq + __popcll(m & lt)] = r;
+            }
+            nq += __popcll(m);
+            if (nq >= kWave) {
+                wave_lds_sync();
+                const int fq = queue[lane];
+                classify_emit(p, true, o, fq, tr, Asun, gobj, buf, nbuf, pbuf, npbuf, n_exact);
+                // move the overflow to the front (fewer than 64 entries)
+                const int rest = lane < nq - kWave ? queue[kWave + lane] : 0;
+                wave_lds_sync();
+                if (lane < nq - kWave) queue[lane] = rest;
+                nq -= kWave;
+                wave_lds_sync();
+            }
+        };
         if (o.overflow) {
-            if (lane == 0) ++n_over;
-            const int q1 = p.batch_off[b + 1];
-            for (int q0 = p.batch_off[b]; q0 < q1; q0 += 64) {
+            if (lane == 0 && k == 0) ++n_over;
+            // frames u0 .. u1 - 1 of the batch, in cell order
+            const int qb = p.cell_start[p.b_koff[b]];
+            const int q1 = qb + u1;
+            for (int q0 = qb + u0; q0 < q1; q0 += 64) {
                 const int q = q0 + lane;
-                const int f = q < q1 ? p.frame_order[q] : 0;
-                const bool hit = q < q1 && frame_cap_hit(o, p.fcap + 8 * (size_t)f) && loc_box_hit(p, o, f);
-                if (hit) ++n_cand;
-                classify_emit(p, hit, o, f, tr, Asun, gobj, buf, nbuf, pbuf, npbuf, n_exact);
+                const bool hit = q < q1 && frame_cap_hit(o, p.cell_caps + 8 * (size_t)q) &&
+                                 (o.lin_ok || loc_box_hit(p, o, q));
+                offer(hit, q);
             }
         } else {
             const int G = p.b_G[b];
             const int ny = o.hi[1] - o.lo[1] + 1, nz = o.hi[2] - o.lo[2] + 1;
             const int64_t base = p.b_koff[b];
-            for (int c0 = 0; c0 < o.ncell; c0 += 64) {
+            for (int c0 = u0; c0 < u1; c0 += kWave) {
                 const int c = c0 + lane;
                 int a0 = 0, len = 0;
-                if (c < o.ncell) {
+                if (c < u1) {
                     const int ix = o.lo[0] + c / (ny * nz);
                     const int iy = o.lo[1] + (c / nz) % ny;
                     const int iz = o.lo[2] + c % nz;
@@ -851,29 +1067,35 @@ __global__ __launch_bounds__(256) void k_fov_wide(const FovParams p) {
                     if (lane >= off) incl += t;
                 }
                 const int total = __shfl(incl, kWave - 1, kWave);
-                if (total == 0) continue;
-                wave_lds_sync();                 // the previous chunk's searches are done
-                incl_w[lane] = incl;
-                base_w[lane] = a0 - (incl - len); // record of position t in this cell: base + t
-                wave_lds_sync();
-                for (int t0 = 0; t0 < total; t0 += kWave) {
-                    const int t = t0 + lane;
-                    // cell of position t: the first lane whose inclusive sum exceeds t
-                    int i = 0;
+                if (total > 0) {
+                    wave_lds_sync();                 // the previous chunk's searches are done
+                    incl_w[lane] = incl;
+                    base_w[lane] = a0 - (incl - len); // record of position t in this cell: base + t
+                    wave_lds_sync();
+                    for (int t0 = 0; t0 < total; t0 += kWave) {
+                        const int t = t0 + lane;
+                        // cell of position t: the first lane whose inclusive sum exceeds t
+                        int i = 0;
 #pragma unroll
-                    for (int step = kWave / 2; step > 0; step >>= 1)
-                        if (incl_w[i + step - 1] <= t) i += step;
-                    int f = 0;
-                    bool hit = false;
-                    if (t < total) {
-                        const double* cp = p.cell_caps + 8 * (int64_t)(base_w[i] + t);
-                        f = (int)cp[5];
-                        hit = frame_cap_hit(o, cp) && loc_box_hit(p, o, f);
+                        for (int step = kWave / 2; step > 0; step >>= 1)
+                            if (incl_w[i + step - 1] <= t) i += step;
+                        int rq = 0;
+                        bool hit = false;
+                        if (t < total) {
+                            rq = base_w[i] + t;
+                            hit = frame_cap_hit(o, p.cell_caps + 8 * (int64_t)rq) &&
+                                  (o.lin_ok || loc_box_hit(p, o, rq));
+                        }
+                        offer(hit, rq);
                     }
-                    if (hit) ++n_cand;
-                    classify_emit(p, hit, o, f, tr, Asun, gobj, buf, nbuf, pbuf, npbuf, n_exact);
                 }
             }
+        }
+        if (nq > 0) {
+            wave_lds_sync();
+            const int fq = lane < nq ? queue[lane] : 0;
+            classify_emit(p, lane < nq, o, fq, tr, Asun, gobj, buf, nbuf, pbuf, npbuf, n_exact);
+            wave_lds_sync();
         }
     }
     buf_flush(buf, nbuf, p.cand, p.n_cand, p.cand_cap);
@@ -1242,15 +1464,16 @@ hipError_t fov_prepare(const FovParams& p, int32_t* qkey, int32_t* cnt, int32_t*
     const unsigned gF = (unsigned)((F + 255) / 256);
     hipError_t e;
     if (F > 0) hipLaunchKernelGGL(k_frame_caps, dim3(gF), dim3(256), 0, s, p.normals, F, p.n_sub, p.fcap);
-    if (F > 0 && p.loc)
-        hipLaunchKernelGGL(k_frame_locator, dim3(gF), dim3(256), 0, s, p.normals, F, p.n_sub, (const double*)p.fcap,
-                           p.loc);
     if (p.n_batch > 0) hipLaunchKernelGGL(k_batch_prep, dim3((unsigned)p.n_batch), dim3(256), 0, s, p);
     if ((e = fill_zero(cnt, (size_t)(n_keys + 1) * sizeof(int32_t), s)) != hipSuccess) return e;
     if (F > 0) hipLaunchKernelGGL(k_frame_keys, dim3(gF), dim3(256), 0, s, p, qkey, cnt);
     if ((e = exclusive_scan_i32(cnt, (int32_t*)p.cell_start, n_keys, scan_scratch, s)) != hipSuccess) return e;
     if ((e = fill_zero(cursor, (size_t)n_keys * sizeof(int32_t), s)) != hipSuccess) return e;
     if (F > 0) hipLaunchKernelGGL(k_frame_scatter, dim3(gF), dim3(256), 0, s, p, (const int32_t*)qkey, cursor);
+    // one wavefront per frame, four per block
+    const unsigned gw = (unsigned)std::min<int64_t>((F + 3) / 4, 65536);
+    if (F > 0) hipLaunchKernelGGL(k_frame_gather, dim3(gw), dim3(256), 0, s, p);
+    if (F > 0 && p.loc) hipLaunchKernelGGL(k_frame_locator, dim3(gw), dim3(256), 0, s, p);
     return hipGetLastError();
 }
 
@@ -1285,10 +1508,16 @@ hipError_t fill_zero(void* p, size_t bytes, hipStream_t s) {
     return hipGetLastError();
 }
 
-static int cu_count();
+static int cu_count() {
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
+        ncu = 256;
+    return ncu;
+}
 
 hipError_t fov_candidates(FovParams& p, int32_t* icnt, int32_t* istart, unsigned long long* items,
-                          unsigned int* item_next, void* scan_scratch, hipStream_t s) {
+                          unsigned int* item_next, void* scan_scratch, void* wide_scan_scratch, hipStream_t s) {
     if (p.n_pairs_total == 0 || p.n_batch == 0) return hipSuccess;
     p.items = items;
     p.item_start = istart;
@@ -1298,19 +1527,19 @@ hipError_t fov_candidates(FovParams& p, int32_t* icnt, int32_t* istart, unsigned
     hipLaunchKernelGGL(k_item_count, dim3(gk), dim3(256), 0, s, p, icnt);
     if ((e = exclusive_scan_i32(icnt, istart, p.n_keys, scan_scratch, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_item_scatter, dim3(gk), dim3(256), 0, s, p, (const int32_t*)icnt);
-    if ((e = fill_zero(item_next, sizeof(unsigned int), s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_fov_cells, dim3((unsigned)(cu_count() * 3)), dim3(256), 0, s, p);
+    if ((e = fill_zero(item_next, kJoinCursorWords * sizeof(unsigned int), s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fov_cells, dim3((unsigned)(cu_count() * kJoinWaves)), dim3(256), 0, s, p);
+    // parts per wide object: up to 32, fewer when the total could pass 2^31
+    p.wide_max_parts = (int)std::max<int64_t>(1, std::min<int64_t>(32, (int64_t)(INT32_MAX - 1) / p.n_pairs_total));
+    const unsigned gw = (unsigned)((p.n_pairs_total + 255) / 256);
+    hipLaunchKernelGGL(k_wide_parts, dim3(gw), dim3(256), 0, s, p);
+    if ((e = exclusive_scan_i32(p.wide_parts, p.wide_off, p.n_pairs_total, wide_scan_scratch, s)) != hipSuccess) return e;
+    if ((e = fill_zero(p.wide_next, kJoinCursorWords * sizeof(unsigned int), s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fov_wide, dim3((unsigned)(cu_count() * kJoinWaves)), dim3(256), 0, s, p);
     return hipGetLastError();
 }
 
-static int cu_count() {
-    int dev = 0, ncu = 256;
-    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    return ncu;
-}
-
 hipError_t fov_exact(const FovParams& p, hipStream_t s) {
-    hipLaunchKernelGGL(k_fov_wide, dim3((unsigned)(cu_count() * 8)), dim3(256), 0, s, p);
     hipLaunchKernelGGL(k_fov_exact, dim3((unsigned)(cu_count() * 16)), dim3(256), 0, s, p);
     return hipGetLastError();
 }

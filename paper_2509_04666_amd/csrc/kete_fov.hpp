@@ -14,7 +14,7 @@ constexpr double kMaxLightDays = 1.0;   // light time covered by the staged wind
 // words) of the sub-frames whose gnomonic box overlaps it.  Record:
 //   [0..2] centre c, [3..5] e1, [6..8] e2, [9] X0, [10] Y0, [11] 1/dX,
 //   [12] 1/dY, [13] 1 when usable (every vertex in the hemisphere around
-//   c), [14..15] unused, then kLocL^2 x 2 mask words.
+//   c), [14] X1 = X0 + kLocL dX, [15] Y1, then kLocL^2 x 2 mask words.
 constexpr int kLocL = 8;
 constexpr int kLocHead = 16;
 constexpr int kLocStride = kLocHead + 2 * kLocL * kLocL;     // doubles per frame
@@ -40,11 +40,16 @@ struct FovParams {
     int32_t n_sub;
     int32_t pad0;
     double* fcap;               // [F][8]: centre, cos R, sin R
-    double* loc;                // [F][kLocStride] sub-frame locators, or null (one sub-frame)
+    double* loc;                // [F][kLocStride] sub-frame locators in cell order, or null (one sub-frame)
     double* btab;               // [B][kBatchStride]
     int32_t* cell_start;        // [B G^3 + 1]
     int32_t* cell_frames;       // [F]
     double* cell_caps;          // [F][8]: frame caps in cell order, slot 5 = frame index
+    // What the join reads of a frame, in cell order, so that the frames of
+    // neighbouring cells sit together in memory: time and observer
+    // position, and the sub-frame normals.
+    double* cell_obs;           // [F][4]: t, observer x, y, z
+    double* cell_normals;       // [F][S][4][3]
     unsigned long long* pairs;  // [cap] packed (frame << 32 | sub << 25 | obj)
     unsigned long long* n_pairs;
     int64_t cap;
@@ -73,9 +78,18 @@ struct FovParams {
     const int32_t* obj_count;   // [n_keys] objects per key
     unsigned long long* items;  // work items of the per-cell join: key << 32 | object chunk
     const int32_t* item_start;  // [n_keys + 1] exclusive scan of items per key (total at n_keys)
-    unsigned int* item_next;    // work-queue cursor
+    unsigned int* item_next;    // work-queue cursors, kJoinCursorWords unsigned ints
     unsigned long long* wide;   // [n_pairs_total] (batch << 32 | local obj) of objects with wide motion caps
     unsigned long long* n_wide;
+    // The wide join's work is split into parts: about 64 grid cells of an
+    // object's cap box, or kWidePartFrames frames of its batch when it has
+    // no usable cap, wide_max_parts at most.  wide_parts[w] counts the parts of wide object w and
+    // wide_off is their exclusive scan (total at n_pairs_total).
+    int32_t* wide_parts;        // [n_pairs_total]
+    int32_t* wide_off;          // [n_pairs_total + 1]
+    unsigned int* wide_next;    // work-queue cursors, kJoinCursorWords unsigned ints
+    int32_t wide_max_parts;     // parts per object at most (their total must stay below 2^31)
+    int32_t pad2;
     double mu, smu, c_light, lt_tol;
     int32_t lt_iter;
     int32_t max_cells;
@@ -95,12 +109,25 @@ hipError_t fov_prepare(const FovParams& p, int32_t* qkey, int32_t* cnt, int32_t*
 hipError_t fov_sort_objects(const FovParams& p, int32_t* okey, int32_t* orank, int32_t* cnt, int32_t* start,
                             int32_t* sorted,
                             void* scan_scratch, hipStream_t s);
+// Workgroups are dealt to the chip's XCDs round-robin (workgroup i to XCD
+// i mod kXcds), each XCD with its own L2.  The per-cell join splits its
+// work list into kXcds slices, one cursor each, kCursorStride unsigned ints
+// (128 bytes) apart.
+constexpr int kXcds = 8;
+constexpr int kCursorStride = 32;
+constexpr int kJoinCursorWords = kXcds * kCursorStride;
+constexpr int kWidePartFrames = 1024;
+
 // Candidate generation.  icnt and istart are [n_keys + 1] int32 scratch
 // (istart becomes p.item_start), items holds n_keys + n_pairs_total / 64 + 1
-// entries, scan_scratch >= scan_scratch_bytes(n_keys).
+// entries, scan_scratch >= scan_scratch_bytes(n_keys), wide_scan_scratch >=
+// scan_scratch_bytes(n_pairs_total); p.wide_parts, p.wide_off and
+// p.wide_next must be set.
 hipError_t fov_candidates(FovParams& p, int32_t* icnt, int32_t* istart, unsigned long long* items,
-                          unsigned int* item_next, void* scan_scratch, hipStream_t s);
+                          unsigned int* item_next, void* scan_scratch, void* wide_scan_scratch, hipStream_t s);
 inline int64_t fov_item_capacity(int64_t n_keys, int64_t n_pairs_total) { return n_keys + n_pairs_total / 64 + 1; }
+// Doubles of the cell-ordered frame copies (cell_obs, cell_normals).
+inline int64_t fov_cell_frame_doubles(int64_t n_frames, int n_sub) { return n_frames * (4 + 12 * (int64_t)n_sub); }
 hipError_t fov_exact(const FovParams& p, hipStream_t s);
 hipError_t fov_drop_failed(const unsigned long long* keys, int64_t n, const int32_t* fail, unsigned long long* out,
                            unsigned long long* n_out, hipStream_t s);
