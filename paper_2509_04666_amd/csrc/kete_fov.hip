@@ -487,6 +487,31 @@ __device__ __forceinline__ bool frame_cap_hit(const ObjBounds& o, const double* 
     return !(dot3(cp, o.dh) < thr - 1e-12);
 }
 
+// Linear prediction of an (object, frame) pair: ul = x + v dt - o for the
+// frame's time t and observer o (ob = {t, o}), and the bound e2 on the
+// distance from ul to the true line of sight (light time and curvature of
+// the path, see classify_emit).
+__device__ __forceinline__ double lin_predict(const ObjBounds& o, const double ob[4], double tr, double Asun,
+                                              double ul[3]) {
+    const double dt = ob[0] - tr;
+    for (int c = 0; c < 3; ++c) ul[c] = o.x[c] + o.v[c] * dt - ob[1 + c];
+    const double ad = fabs(dt) + o.taumax;
+    return 2.0 * (o.vbn * o.taumax + 0.5 * (o.a2b + Asun) * ad * ad + 1e-12);
+}
+
+// Can a line of sight within e2 of ul reach the frame's cap (centre cp,
+// cos and sin of the radius R)?  Its angle from ul is at most
+// asin(e2 / |ul|), so it misses the cap when the angle of ul from the centre
+// exceeds R + asin(e2 / |ul|), i.e. when ul . c < cos R sqrt(|ul|^2 - e2^2)
+// - sin R e2 (R below 90 degrees; a margin covers rounding).  A void bound
+// (e2 >= |ul|) or a wider frame passes.
+__device__ __forceinline__ bool lin_cap_hit(const double* __restrict__ cp, const double ul[3], double e2) {
+    const double u2 = dot3(ul, ul);
+    if (!(e2 * e2 < u2) || !(cp[3] > 0.0)) return true;
+    const double thr = cp[3] * sqrt(u2 - e2 * e2) - cp[4] * e2;
+    return !(dot3(ul, cp) < thr - 1e-12 * sqrt(u2));
+}
+
 // Locator header of one frame (see kLocStride), read with eight 16-byte
 // loads issued together rather than one dependent read after another.
 struct LocHead {
@@ -604,20 +629,20 @@ __device__ void classify_emit(const FovParams& p, bool has, const ObjBounds& o, 
         f = p.cell_frames[r];
         const double2* q = reinterpret_cast<const double2*>(p.cell_obs + 4 * (size_t)(unsigned)r);
         const double2 ob01 = q[0], ob23 = q[1];
+        const double* cr = p.cell_caps + 8 * (size_t)(unsigned)r;
+        const double2 c01 = *reinterpret_cast<const double2*>(cr), c23 = *reinterpret_cast<const double2*>(cr + 2);
+        const double cp[5] = {c01.x, c01.y, c23.x, c23.y, cr[4]};
         LocHead h;
         h.usable = 0.0;
         if (p.loc) h = loc_head(p.loc + (size_t)kLocStride * (unsigned)r);
         all = !o.lin_ok;
         if (o.lin_ok) {
             const double ob[4] = {ob01.x, ob01.y, ob23.x, ob23.y};
-            const double dt = ob[0] - tr;
-            for (int c = 0; c < 3; ++c) ul[c] = o.x[c] + o.v[c] * dt - ob[1 + c];
-            const double ad = fabs(dt) + o.taumax;
-            e2 = 2.0 * (o.vbn * o.taumax + 0.5 * (o.a2b + Asun) * ad * ad + 1e-12);
+            e2 = lin_predict(o, ob, tr, Asun, ul);
             const double u2 = dot3(ul, ul);
             if (!(e2 * e2 < u2)) {
                 all = true;
-            } else {
+            } else if (lin_cap_hit(cp, ul, e2)) {
                 unsigned long long m[2];
                 const ulonglong2* M = p.loc ? reinterpret_cast<const ulonglong2*>(
                                                   p.loc + (size_t)kLocStride * (unsigned)r + kLocHead)
@@ -631,6 +656,24 @@ __device__ void classify_emit(const FovParams& p, bool has, const ObjBounds& o, 
     const unsigned long long base = ((unsigned long long)(unsigned)f << 32) | gobj;
     if (all) ++n_exact;
     buf_append<kBufEntries>(cbuf, nc, all, base | kAllSubs, p.cand, p.n_cand, p.cand_cap);
+    // test of sub-frame s of pair (ri, bi) with ul = (u0, u1, u2), margin e
+    auto sub_test = [&](bool act, int ri, int s, double u0, double u1, double u2, double e, unsigned long long bi) {
+        int res = 0;
+        if (act) {
+            const double* n = p.cell_normals + ((size_t)(unsigned)ri * p.n_sub + s) * 12;
+            res = 1;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const double d = n[3 * k] * u0 + n[3 * k + 1] * u1 + n[3 * k + 2] * u2;
+                if (d <= -e) res = 0;
+                else if (!(d > e) && res == 1) res = 2;
+            }
+        }
+        const unsigned long long key = bi | ((unsigned long long)(act ? s : 0) << 25);
+        if (res == 2) ++n_exact;
+        buf_append<kPairBufEntries>(pbuf, np, res == 1, key, p.pairs, p.n_pairs, p.cap);
+        buf_append<kBufEntries>(cbuf, nc, res == 2, key, p.cand, p.n_cand, p.cand_cap);
+    };
     const int cnt = __popcll(m0) + __popcll(m1);
     int incl = cnt;
 #pragma unroll
@@ -654,23 +697,12 @@ __device__ void classify_emit(const FovParams& p, bool has, const ObjBounds& o, 
         const double e = __shfl(e2, i, kWave);
         const int ri = __shfl(r, i, kWave);
         const unsigned long long bi = __shfl(base, i, kWave);
-        int res = 0, s = 0;
+        int s = 0;
         if (t < total) {
             const int c0 = __popcll(w0);
             s = nb < c0 ? nth_set_bit(w0, nb) : 64 + nth_set_bit(w1, nb - c0);
-            const double* n = p.cell_normals + ((size_t)(unsigned)ri * p.n_sub + s) * 12;
-            res = 1;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const double d = n[3 * k] * u0 + n[3 * k + 1] * u1 + n[3 * k + 2] * u2;
-                if (d <= -e) res = 0;
-                else if (!(d > e) && res == 1) res = 2;
-            }
         }
-        const unsigned long long key = bi | ((unsigned long long)s << 25);
-        if (res == 2) ++n_exact;
-        buf_append<kPairBufEntries>(pbuf, np, res == 1, key, p.pairs, p.n_pairs, p.cap);
-        buf_append<kBufEntries>(cbuf, nc, res == 2, key, p.cand, p.n_cand, p.cand_cap);
+        sub_test(t < total, ri, s, u0, u1, u2, e, bi);
     }
 }
 
@@ -743,7 +775,7 @@ constexpr int kItemChunk = 3;
 // objects without one.  Items are in (batch, cell) order; the waves of
 // one XCD start on their own slice of the list, so that neighbouring cells
 // share that XCD's L2, and help the other slices when theirs runs out.
-constexpr int kJoinWaves = 4;        // resident waves per SIMD of the join kernels
+constexpr int kJoinWaves = 3;        // resident waves per SIMD of the join kernels (no register spills)
 __global__ __launch_bounds__(256, kJoinWaves) void k_fov_cells(const FovParams p) {
     const int lane = threadIdx.x & 63, wv = (threadIdx.x >> 6) & 3;
     unsigned long long n_cand = 0, n_exact = 0, n_visit = 0;
@@ -909,6 +941,22 @@ __global__ __launch_bounds__(256, kJoinWaves) void k_fov_cells(const FovParams p
     }
 }
 
+// Frame test of the wide join, one frame per lane: the motion-cap test, and
+// for an object with a linear test the much tighter linear cap test (its
+// frames are not shared across lanes, so each lane reads its own record);
+// without one, the locator-box test.
+__device__ __forceinline__ bool wide_frame_hit(const FovParams& p, const ObjBounds& o, int r, double tr, double Asun) {
+    const double* cp = p.cell_caps + 8 * (size_t)(unsigned)r;
+    if (!frame_cap_hit(o, cp)) return false;
+    if (!o.lin_ok) return loc_box_hit(p, o, r);
+    const double2* q = reinterpret_cast<const double2*>(p.cell_obs + 4 * (size_t)(unsigned)r);
+    const double2 ob01 = q[0], ob23 = q[1];
+    const double ob[4] = {ob01.x, ob01.y, ob23.x, ob23.y};
+    double ul[3];
+    const double e2 = lin_predict(o, ob, tr, Asun, ul);
+    return lin_cap_hit(cp, ul, e2);
+}
+
 // Work units of wide object w: the cells of its cap box, or the frames of
 // its batch when it has no usable cap (0 for a failed or non-finite
 // object), and the parts they split into: one per 64 cells or
@@ -1041,8 +1089,7 @@ __global__ __launch_bounds__(256, kJoinWaves) void k_fov_wide(const FovParams p)
             const int q1 = qb + u1;
             for (int q0 = qb + u0; q0 < q1; q0 += 64) {
                 const int q = q0 + lane;
-                const bool hit = q < q1 && frame_cap_hit(o, p.cell_caps + 8 * (size_t)q) &&
-                                 (o.lin_ok || loc_box_hit(p, o, q));
+                const bool hit = q < q1 && wide_frame_hit(p, o, q, tr, Asun);
                 offer(hit, q);
             }
         } else {
@@ -1083,8 +1130,7 @@ __global__ __launch_bounds__(256, kJoinWaves) void k_fov_wide(const FovParams p)
                         bool hit = false;
                         if (t < total) {
                             rq = base_w[i] + t;
-                            hit = frame_cap_hit(o, p.cell_caps + 8 * (int64_t)rq) &&
-                                  (o.lin_ok || loc_box_hit(p, o, rq));
+                            hit = wide_frame_hit(p, o, rq, tr, Asun);
                         }
                         offer(hit, rq);
                     }
