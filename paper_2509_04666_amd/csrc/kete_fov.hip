@@ -502,14 +502,16 @@ __device__ __forceinline__ double lin_predict(const ObjBounds& o, const double o
 // Can a line of sight within e2 of ul reach the frame's cap (centre cp,
 // cos and sin of the radius R)?  Its angle from ul is at most
 // asin(e2 / |ul|), so it misses the cap when the angle of ul from the centre
-// exceeds R + asin(e2 / |ul|), i.e. when ul . c < cos R sqrt(|ul|^2 - e2^2)
-// - sin R e2 (R below 90 degrees; a margin covers rounding).  A void bound
+// exceeds R + asin(e2 / |ul|), i.e. when A = ul . c + sin R e2 falls below
+// B = cos R sqrt(|ul|^2 - e2^2) (R below 90 degrees).  B >= 0, so the test
+// is A >= 0 and A^2 >= B^2, with no square root; A is raised by
+// 1e-12 |ul|_1 >= 1e-12 |ul| to cover rounding.  A void bound
 // (e2 >= |ul|) or a wider frame passes.
 __device__ __forceinline__ bool lin_cap_hit(const double* __restrict__ cp, const double ul[3], double e2) {
     const double u2 = dot3(ul, ul);
     if (!(e2 * e2 < u2) || !(cp[3] > 0.0)) return true;
-    const double thr = cp[3] * sqrt(u2 - e2 * e2) - cp[4] * e2;
-    return !(dot3(ul, cp) < thr - 1e-12 * sqrt(u2));
+    const double a = dot3(ul, cp) + cp[4] * e2 + 1e-12 * (fabs(ul[0]) + fabs(ul[1]) + fabs(ul[2]));
+    return a >= 0.0 && a * a >= cp[3] * cp[3] * (u2 - e2 * e2);
 }
 
 // Locator header of one frame (see kLocStride), read with eight 16-byte
@@ -603,7 +605,8 @@ __device__ __forceinline__ int nth_set_bit(unsigned long long w, int r) {
     return pos;
 }
 
-// Linear-motion test of an (object, frame) pair that passed the cap test,
+// Linear-motion test of an (object, frame) pair that passed the cap test
+// (and, with a linear test, the linear cap test),
 // with its remainder bound: the object moves on x + v dt within eps of its
 // true emission point, so with unit normals and ul = x + v dt - o a
 // sub-frame is out when some n . ul <= -2 eps, surely in when every
@@ -629,9 +632,6 @@ __device__ void classify_emit(const FovParams& p, bool has, const ObjBounds& o, 
         f = p.cell_frames[r];
         const double2* q = reinterpret_cast<const double2*>(p.cell_obs + 4 * (size_t)(unsigned)r);
         const double2 ob01 = q[0], ob23 = q[1];
-        const double* cr = p.cell_caps + 8 * (size_t)(unsigned)r;
-        const double2 c01 = *reinterpret_cast<const double2*>(cr), c23 = *reinterpret_cast<const double2*>(cr + 2);
-        const double cp[5] = {c01.x, c01.y, c23.x, c23.y, cr[4]};
         LocHead h;
         h.usable = 0.0;
         if (p.loc) h = loc_head(p.loc + (size_t)kLocStride * (unsigned)r);
@@ -642,7 +642,7 @@ __device__ void classify_emit(const FovParams& p, bool has, const ObjBounds& o, 
             const double u2 = dot3(ul, ul);
             if (!(e2 * e2 < u2)) {
                 all = true;
-            } else if (lin_cap_hit(cp, ul, e2)) {
+            } else {
                 unsigned long long m[2];
                 const ulonglong2* M = p.loc ? reinterpret_cast<const ulonglong2*>(
                                                   p.loc + (size_t)kLocStride * (unsigned)r + kLocHead)
@@ -755,10 +755,11 @@ __global__ void k_item_scatter(const FovParams p, const int32_t* __restrict__ ic
     for (int c = 0; c < n; ++c) p.items[s0 + c] = ((unsigned long long)key << 32) | (unsigned long long)c;
 }
 
-// A frame's cap record (centre, cos and sin of the radius, frame index) as
-// three 16-byte LDS words.
-struct __align__(16) double6 {
-    double a, b, c, d, e, f;
+// A frame's record for the per-cell join's broadcast loop: cap (centre,
+// cos and sin of the radius), cell rank, time and observer, as five
+// 16-byte LDS words.
+struct __align__(16) FrameRec {
+    double c[3], cosr, sinr, rank, t, o[3];
 };
 
 constexpr int kLinQueue = 2 * kWave;
@@ -770,9 +771,10 @@ constexpr int kItemChunk = 3;
 // one per lane, and broadcast for the cap test.  (object, frame) pairs
 // that pass it are queued in LDS and take the linear-motion test 64 at a
 // time, one pair per lane, reading their object's data from the lane that
-// holds it.  The cap-test loop reads LDS only: the locator-box test, a
-// global read, is left to the linear test's own locator query except for
-// objects without one.  Items are in (batch, cell) order; the waves of
+// holds it.  The broadcast loop reads LDS only: after the motion-cap test
+// an object with a linear test takes the linear cap test there (the frame
+// record carries the frame's time and observer), and only objects without
+// one take the locator-box test, a global read.  Items are in (batch, cell) order; the waves of
 // one XCD start on their own slice of the list, so that neighbouring cells
 // share that XCD's L2, and help the other slices when theirs runs out.
 constexpr int kJoinWaves = 3;        // resident waves per SIMD of the join kernels (no register spills)
@@ -783,11 +785,11 @@ __global__ __launch_bounds__(256, kJoinWaves) void k_fov_cells(const FovParams p
     const int n_items = p.item_start[p.n_keys];
     __shared__ unsigned long long bufs[4][kBufEntries], pbufs[4][kPairBufEntries];
     __shared__ unsigned long long queue_all[4][kLinQueue];
-    __shared__ double6 fcap_all[4][kWave];
+    __shared__ FrameRec fcap_all[4][kWave];
     unsigned long long* buf = bufs[wv];
     unsigned long long* pbuf = pbufs[wv];
     int npbuf = 0;
-    double6* fcap = fcap_all[wv];
+    FrameRec* fcap = fcap_all[wv];
     unsigned long long* queue = queue_all[wv];
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     int nbuf = 0;
@@ -883,14 +885,16 @@ __global__ __launch_bounds__(256, kJoinWaves) void k_fov_cells(const FovParams p
             int nc = 0;
             for (int t = 1; t < 27; ++t) nc = (__shfl(excl, t, kWave) <= g) ? t : nc;
             const int rk = __shfl(my_a0, nc, kWave) + (g - __shfl(excl, nc, kWave));
-            // the chunk's cap records (with the cell rank in place of the
-            // frame index) go to LDS and are read back as broadcasts
-            double6 rec = {0.0, 0.0, 0.0, 2.0, 0.0, 0.0};
+            // the chunk's frame records go to LDS and are read back as
+            // broadcasts
+            FrameRec rec = {{0.0, 0.0, 0.0}, 2.0, 0.0, 0.0, 0.0, {0.0, 0.0, 0.0}};
             if (g < total) {
                 const double* cp = caps + 8 * (int64_t)rk;
                 const double2 c01 = *reinterpret_cast<const double2*>(cp);
                 const double2 c23 = *reinterpret_cast<const double2*>(cp + 2);
-                rec = {c01.x, c01.y, c23.x, c23.y, cp[4], (double)rk};
+                const double2* ob = reinterpret_cast<const double2*>(p.cell_obs + 4 * (int64_t)rk);
+                const double2 o01 = ob[0], o23 = ob[1];
+                rec = {{c01.x, c01.y, c23.x}, c23.y, cp[4], (double)rk, o01.x, {o01.y, o23.x, o23.y}};
             }
             wave_lds_sync();                  // the previous chunk's records are read
             fcap[lane] = rec;
@@ -898,10 +902,20 @@ __global__ __launch_bounds__(256, kJoinWaves) void k_fov_cells(const FovParams p
             const int n = min(kWave, total - g0);
             n_visit += (unsigned long long)n;
             for (int m = 0; m < n; ++m) {
-                const double6 cm = fcap[m];
-                const double cpm[5] = {cm.a, cm.b, cm.c, cm.d, cm.e};
-                const unsigned long long rq = (unsigned long long)(unsigned int)(int)cm.f;
-                const bool hit = live && frame_cap_hit(o, cpm) && (o.lin_ok || loc_box_hit(p, o, (int)rq));
+                const FrameRec cm = fcap[m];
+                const double cpm[5] = {cm.c[0], cm.c[1], cm.c[2], cm.cosr, cm.sinr};
+                const unsigned long long rq = (unsigned long long)(unsigned int)(int)cm.rank;
+                bool hit = live && frame_cap_hit(o, cpm);
+                if (hit) {
+                    if (o.lin_ok) {
+                        const double ob[4] = {cm.t, cm.o[0], cm.o[1], cm.o[2]};
+                        double ul[3];
+                        const double e2 = lin_predict(o, ob, tr, Asun, ul);
+                        hit = lin_cap_hit(cpm, ul, e2);
+                    } else {
+                        hit = loc_box_hit(p, o, (int)rq);
+                    }
+                }
                 const unsigned long long mask = __ballot(hit);
                 if (mask == 0ull) continue;
                 if (hit) ++n_cand;
