@@ -879,10 +879,10 @@ int kete_fov_check(const kete_ephem_t* eph, const double* x_epoch, int32_t* stat
     if (host_counters[8] > 0) {
         if ((rc = drop_failed_pairs(P.pairs, np, P.fail, sorted, counters, &np, s))) return rc;
         *n_pairs = np;
-        HIPCHK(fov_sort(sorted, np, F, fcnt, fstart, P.pairs, scan_scratch, pf, ps, po, s));
+        HIPCHK(fov_sort(sorted, np, F, n_obj, frames->n_sub, fcnt, fstart, P.pairs, scan_scratch, pf, ps, po, s));
         return KETE_OK;
     }
-    HIPCHK(fov_sort(P.pairs, np, F, fcnt, fstart, sorted, scan_scratch, pf, ps, po, s));
+    HIPCHK(fov_sort(P.pairs, np, F, n_obj, frames->n_sub, fcnt, fstart, sorted, scan_scratch, pf, ps, po, s));
     return KETE_OK;
 }
 
@@ -1374,10 +1374,12 @@ int kete_batch_pairs(const kete_batch_t* batch, int64_t pairs_cap, const kete_op
     if (hc[8] > 0) {
         if ((rc = drop_failed_pairs(w.P.pairs, np, w.P.fail, w.sorted, w.counters, &np, s))) return rc;
         *n_pairs = np;
-        HIPCHK(fov_sort(w.sorted, np, d.F, w.fcnt, w.fstart, w.P.pairs, w.scan_scratch, pf, ps, po, s));
+        HIPCHK(fov_sort(w.sorted, np, d.F, batch->n_bodies, batch->frames.n_sub, w.fcnt, w.fstart, w.P.pairs,
+                        w.scan_scratch, pf, ps, po, s));
         return KETE_OK;
     }
-    HIPCHK(fov_sort(w.P.pairs, np, d.F, w.fcnt, w.fstart, w.sorted, w.scan_scratch, pf, ps, po, s));
+    HIPCHK(fov_sort(w.P.pairs, np, d.F, batch->n_bodies, batch->frames.n_sub, w.fcnt, w.fstart, w.sorted,
+                    w.scan_scratch, pf, ps, po, s));
     return KETE_OK;
 }
 

@@ -1352,12 +1352,13 @@ __device__ __forceinline__ void unpack_pair(unsigned long long k, int i, int32_t
 
 // Ordering inside each frame's segment of the pair keys (keys are unique),
 // by segment size: up to kSortSmall by one thread (insertion sort), up to
-// kSortLds by a block in LDS (bitonic network), larger ones by a block
-// with bottom-up merge passes through global memory (merge-path
-// partitions), ping-ponging with `tmp` at the same offsets.
+// kSortWave by one wavefront in LDS (radix sort), up to kSortLds by a
+// block in LDS (radix sort), larger ones by a block with bottom-up merge
+// passes through global memory (merge-path partitions), ping-ponging with
+// `tmp` at the same offsets.
 constexpr int kSortSmall = 32;
 constexpr int kSortWave = 1024;
-constexpr int kSortLds = 4096;
+constexpr int kSortLds = 8192;
 
 __global__ void k_pair_sort_small(unsigned long long* __restrict__ keys, const int32_t* __restrict__ fstart,
                                   int64_t n_frames, int32_t* __restrict__ pf, int32_t* __restrict__ ps,
@@ -1375,61 +1376,182 @@ __global__ void k_pair_sort_small(unsigned long long* __restrict__ keys, const i
     for (int i = a; i < e; ++i) unpack_pair(keys[i], i, pf, ps, po);
 }
 
-// Bitonic network over P (a power of two) keys in LDS, run by one
-// wavefront or by a whole block (`nthr` threads from `t0`); every thread
-// takes compare-exchange pairs, `sync` separates the passes.
-template <class Sync>
-__device__ __forceinline__ void bitonic_lds(unsigned long long* __restrict__ sh, int P, int t0, int nthr, Sync&& sync) {
-    for (int k = 2; k <= P; k <<= 1)
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int t = t0; t < (P >> 1); t += nthr) {
-                // t-th pair (i, i + j): insert a zero bit at j's position
-                const int i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
-                const int l = i | j;
-                const unsigned long long x = sh[i], y = sh[l];
-                const bool up = (i & k) == 0;
-                if ((x > y) == up) { sh[i] = y; sh[l] = x; }
-            }
-            sync();
-        }
-}
+// Stable LSD radix sort of one frame's keys by one wavefront in LDS.  The
+// keys of a frame differ only in (sub-frame, object), packed here into
+// bits = sb + ob <= 32 bits as sub << ob | obj.  Each pass of kRadixBits
+// counts its digits with LDS atomics, scans the counts, then scatters the
+// keys 64 at a time in order, a key's rank among the lanes sharing its
+// digit coming from kRadixBits ballots, so equal digits keep their order.
+constexpr int kRadixBits = 8;
+constexpr int kRadixBuckets = 1 << kRadixBits;
 
-// Segments of kSortSmall < n <= kSortWave keys: one wavefront per frame,
-// synchronized by wavefront barriers only.
-__global__ __launch_bounds__(256) void k_pair_sort_wave(const unsigned long long* __restrict__ keys,
-                                                       const int32_t* __restrict__ fstart, int64_t n_frames,
-                                                       int32_t* __restrict__ pf, int32_t* __restrict__ ps,
-                                                       int32_t* __restrict__ po) {
-    __shared__ unsigned long long sh_all[4][kSortWave];
+template <int kCap, int kWaves>
+__global__ __launch_bounds__(64 * kWaves) void k_pair_sort_radix(const unsigned long long* __restrict__ keys,
+                                                                const int32_t* __restrict__ fstart, int64_t n_frames,
+                                                                int lo_n, int ob, int bits, int32_t* __restrict__ pf,
+                                                                int32_t* __restrict__ ps, int32_t* __restrict__ po) {
+    __shared__ unsigned sh_a[kWaves][kCap], sh_b[kWaves][kCap];
+    __shared__ int sh_cnt[kWaves][kRadixBuckets];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    unsigned long long* sh = sh_all[wv];
-    for (int64_t f = (int64_t)blockIdx.x * 4 + wv; f < n_frames; f += (int64_t)gridDim.x * 4) {
-        const int a = fstart[f], n = fstart[f + 1] - a;
-        if (n <= kSortSmall || n > kSortWave) continue;
-        int P = 64;
-        while (P < n) P <<= 1;
-        for (int i = lane; i < P; i += 64) sh[i] = i < n ? keys[a + i] : ~0ull;
+    const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const unsigned omask = ob >= 32 ? ~0u : ((1u << ob) - 1u);
+    int* cnt = sh_cnt[wv];
+    for (int64_t f = (int64_t)blockIdx.x * kWaves + wv; f < n_frames; f += (int64_t)gridDim.x * kWaves) {
+        const int a0 = fstart[f], n = fstart[f + 1] - a0;
+        if (n <= lo_n || n > kCap) continue;
+        unsigned* A = sh_a[wv];
+        unsigned* B = sh_b[wv];
+        for (int i = lane; i < n; i += kWave) {
+            const unsigned long long k = keys[a0 + i];
+            A[i] = ((unsigned)((k >> 25) & 0x7f) << ob) | ((unsigned)k & 0x1ffffffu);
+        }
         wave_lds_sync();
-        bitonic_lds(sh, P, lane, 64, [] { wave_lds_sync(); });
-        for (int i = lane; i < n; i += 64) unpack_pair(sh[i], a + i, pf, ps, po);
+        for (int shift = 0; shift < bits; shift += kRadixBits) {
+            for (int d = lane; d < kRadixBuckets; d += kWave) cnt[d] = 0;
+            wave_lds_sync();
+            for (int i = lane; i < n; i += kWave) atomicAdd(&cnt[(A[i] >> shift) & (kRadixBuckets - 1)], 1);
+            wave_lds_sync();
+            // exclusive scan of the counts, kRadixBuckets / 64 per lane
+            constexpr int kPer = kRadixBuckets / kWave;
+            int c[kPer], tot = 0;
+#pragma unroll
+            for (int q = 0; q < kPer; ++q) { c[q] = cnt[kPer * lane + q]; tot += c[q]; }
+            int incl = tot;
+#pragma unroll
+            for (int off = 1; off < kWave; off <<= 1) {
+                const int t = __shfl_up(incl, off, kWave);
+                if (lane >= off) incl += t;
+            }
+            int run = incl - tot;
+#pragma unroll
+            for (int q = 0; q < kPer; ++q) { cnt[kPer * lane + q] = run; run += c[q]; }
+            wave_lds_sync();
+            for (int i0 = 0; i0 < n; i0 += kWave) {
+                const int i = i0 + lane;
+                const bool v = i < n;
+                const unsigned k = v ? A[i] : 0u;
+                const unsigned d = (k >> shift) & (kRadixBuckets - 1);
+                unsigned long long m = __ballot(v);
+#pragma unroll
+                for (int bit = 0; bit < kRadixBits; ++bit) {
+                    const bool set = (d >> bit) & 1u;
+                    const unsigned long long bb = __ballot(set);
+                    m &= set ? bb : ~bb;
+                }
+                // m: the valid lanes holding this lane's digit; the lowest
+                // one advances the digit's cursor for all of them
+                const int leader = m ? __ffsll((long long)m) - 1 : 0;
+                int base = 0;
+                if (v && lane == leader) {
+                    base = cnt[d];
+                    cnt[d] = base + __popcll(m);
+                }
+                base = __shfl(base, leader, kWave);
+                if (v) B[base + __popcll(m & lt)] = k;
+                wave_lds_sync();
+            }
+            unsigned* t = A;
+            A = B;
+            B = t;
+        }
+        for (int i = lane; i < n; i += kWave) {
+            const unsigned k = A[i];
+            pf[a0 + i] = (int32_t)f;
+            ps[a0 + i] = (int32_t)(k >> ob);
+            po[a0 + i] = (int32_t)(k & omask);
+        }
         wave_lds_sync();
     }
 }
 
-__global__ __launch_bounds__(256) void k_pair_sort_lds(const unsigned long long* __restrict__ keys,
-                                                      const int32_t* __restrict__ fstart, int64_t n_frames,
-                                                      int32_t* __restrict__ pf, int32_t* __restrict__ ps,
-                                                      int32_t* __restrict__ po) {
-    __shared__ unsigned long long sh[kSortLds];
+// The same radix sort by a block of kSortWaves wavefronts per segment: per
+// pass each wavefront counts the digits of its quarter of the keys (whole
+// 64-key chunks, in order), a block scan turns the per-wavefront counts
+// into per-wavefront cursors (digit-major, wavefront-minor), and each
+// wavefront scatters its quarter with its own cursors, so the order of
+// equal digits is kept across the block.
+constexpr int kSortWaves = 4;
+
+template <int kCap>
+__global__ __launch_bounds__(64 * kSortWaves) void k_pair_sort_radix_block(
+    const unsigned long long* __restrict__ keys, const int32_t* __restrict__ fstart, int64_t n_frames, int lo_n,
+    int ob, int bits, int32_t* __restrict__ pf, int32_t* __restrict__ ps, int32_t* __restrict__ po) {
+    __shared__ unsigned sh_a[kCap], sh_b[kCap];
+    __shared__ int cnt[kSortWaves][kRadixBuckets];
+    __shared__ int wsum[kSortWaves];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const unsigned omask = ob >= 32 ? ~0u : ((1u << ob) - 1u);
+    static_assert(kRadixBuckets == 64 * kSortWaves, "one digit per thread in the cursor scan");
     for (int64_t f = blockIdx.x; f < n_frames; f += gridDim.x) {
-        const int a = fstart[f], n = fstart[f + 1] - a;
-        if (n <= kSortWave || n > kSortLds) continue;
-        int P = 1;
-        while (P < n) P <<= 1;
-        for (int i = threadIdx.x; i < P; i += blockDim.x) sh[i] = i < n ? keys[a + i] : ~0ull;
+        const int a0 = fstart[f], n = fstart[f + 1] - a0;
+        if (n <= lo_n || n > kCap) continue;
+        unsigned* A = sh_a;
+        unsigned* B = sh_b;
+        for (int i = tid; i < n; i += 64 * kSortWaves) {
+            const unsigned long long k = keys[a0 + i];
+            A[i] = ((unsigned)((k >> 25) & 0x7f) << ob) | ((unsigned)k & 0x1ffffffu);
+        }
+        // this wavefront's keys: chunks c0 .. c1 - 1 of 64
+        const int nc = (n + kWave - 1) / kWave;
+        const int qa = kWave * (nc * wv / kSortWaves), qb = min(n, kWave * (nc * (wv + 1) / kSortWaves));
         __syncthreads();
-        bitonic_lds(sh, P, (int)threadIdx.x, (int)blockDim.x, [] { __syncthreads(); });
-        for (int i = threadIdx.x; i < n; i += blockDim.x) unpack_pair(sh[i], a + i, pf, ps, po);
+        for (int shift = 0; shift < bits; shift += kRadixBits) {
+            for (int d = lane; d < kRadixBuckets; d += kWave) cnt[wv][d] = 0;
+            wave_lds_sync();
+            for (int i = qa + lane; i < qb; i += kWave) atomicAdd(&cnt[wv][(A[i] >> shift) & (kRadixBuckets - 1)], 1);
+            __syncthreads();
+            // thread d: the digit's total, its exclusive scan over the digits,
+            // then the cursors of the wavefronts in order
+            int c[kSortWaves], tot = 0;
+#pragma unroll
+            for (int w = 0; w < kSortWaves; ++w) { c[w] = cnt[w][tid]; tot += c[w]; }
+            int incl = tot;
+#pragma unroll
+            for (int off = 1; off < kWave; off <<= 1) {
+                const int t = __shfl_up(incl, off, kWave);
+                if (lane >= off) incl += t;
+            }
+            if (lane == kWave - 1) wsum[wv] = incl;
+            __syncthreads();
+            int run = incl - tot;
+            for (int w = 0; w < wv; ++w) run += wsum[w];
+#pragma unroll
+            for (int w = 0; w < kSortWaves; ++w) { cnt[w][tid] = run; run += c[w]; }
+            __syncthreads();
+            for (int i0 = qa; i0 < qb; i0 += kWave) {
+                const int i = i0 + lane;
+                const bool v = i < qb;
+                const unsigned k = v ? A[i] : 0u;
+                const unsigned d = (k >> shift) & (kRadixBuckets - 1);
+                unsigned long long m = __ballot(v);
+#pragma unroll
+                for (int bit = 0; bit < kRadixBits; ++bit) {
+                    const bool set = (d >> bit) & 1u;
+                    const unsigned long long bb = __ballot(set);
+                    m &= set ? bb : ~bb;
+                }
+                const int leader = m ? __ffsll((long long)m) - 1 : 0;
+                int base = 0;
+                if (v && lane == leader) {
+                    base = cnt[wv][d];
+                    cnt[wv][d] = base + __popcll(m);
+                }
+                base = __shfl(base, leader, kWave);
+                if (v) B[base + __popcll(m & lt)] = k;
+                wave_lds_sync();
+            }
+            __syncthreads();
+            unsigned* t = A;
+            A = B;
+            B = t;
+        }
+        for (int i = tid; i < n; i += 64 * kSortWaves) {
+            const unsigned k = A[i];
+            pf[a0 + i] = (int32_t)f;
+            ps[a0 + i] = (int32_t)(k >> ob);
+            po[a0 + i] = (int32_t)(k & omask);
+        }
         __syncthreads();
     }
 }
@@ -1612,9 +1734,16 @@ hipError_t fov_drop_failed(const unsigned long long* keys, int64_t n, const int3
     return hipGetLastError();
 }
 
-hipError_t fov_sort(unsigned long long* keys, int64_t n, int64_t n_frames, int32_t* fcnt, int32_t* fstart,
-                    unsigned long long* sorted, void* scan_scratch, int32_t* pf, int32_t* ps, int32_t* po,
-                    hipStream_t s) {
+// Bits needed for values 0 .. n - 1.
+static int bits_for(int64_t n) {
+    int b = 0;
+    while (b < 62 && ((int64_t)1 << b) < n) ++b;
+    return b;
+}
+
+hipError_t fov_sort(unsigned long long* keys, int64_t n, int64_t n_frames, int64_t n_obj, int n_sub, int32_t* fcnt,
+                    int32_t* fstart, unsigned long long* sorted, void* scan_scratch, int32_t* pf, int32_t* ps,
+                    int32_t* po, hipStream_t s) {
     unsigned long long* tmp = keys;            // free once the keys are scattered by frame
     hipError_t e;
     if ((e = fill_zero(fcnt, (size_t)(n_frames + 1) * sizeof(int32_t), s)) != hipSuccess) return e;
@@ -1627,10 +1756,16 @@ hipError_t fov_sort(unsigned long long* keys, int64_t n, int64_t n_frames, int32
         const unsigned gb = (unsigned)std::min<int64_t>(n_frames, (int64_t)cu_count() * 16);
         hipLaunchKernelGGL(k_pair_sort_small, dim3((unsigned)((n_frames + 255) / 256)), dim3(256), 0, s, sorted,
                            (const int32_t*)fstart, n_frames, pf, ps, po);
-        hipLaunchKernelGGL(k_pair_sort_wave, dim3(gb), dim3(256), 0, s, (const unsigned long long*)sorted,
-                           (const int32_t*)fstart, n_frames, pf, ps, po);
-        hipLaunchKernelGGL(k_pair_sort_lds, dim3(gb), dim3(256), 0, s, (const unsigned long long*)sorted,
-                           (const int32_t*)fstart, n_frames, pf, ps, po);
+        const int ob = bits_for(n_obj), bits = ob + bits_for(n_sub);
+        hipLaunchKernelGGL((k_pair_sort_radix<kSortWave, 4>), dim3(gb), dim3(256), 0, s,
+                           (const unsigned long long*)sorted, (const int32_t*)fstart, n_frames, kSortSmall, ob, bits,
+                           pf, ps, po);
+        hipLaunchKernelGGL((k_pair_sort_radix_block<4096>), dim3(gb), dim3(64 * kSortWaves), 0, s,
+                           (const unsigned long long*)sorted, (const int32_t*)fstart, n_frames, kSortWave, ob, bits,
+                           pf, ps, po);
+        hipLaunchKernelGGL((k_pair_sort_radix_block<kSortLds>), dim3(gb), dim3(64 * kSortWaves), 0, s,
+                           (const unsigned long long*)sorted, (const int32_t*)fstart, n_frames, 4096, ob, bits,
+                           pf, ps, po);
         hipLaunchKernelGGL(k_pair_sort_large, dim3(gb), dim3(256), 0, s, sorted, tmp, (const int32_t*)fstart,
                            n_frames, pf, ps, po);
     }

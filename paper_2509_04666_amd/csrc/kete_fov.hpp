@@ -131,9 +131,11 @@ inline int64_t fov_cell_frame_doubles(int64_t n_frames, int n_sub) { return n_fr
 hipError_t fov_exact(const FovParams& p, hipStream_t s);
 hipError_t fov_drop_failed(const unsigned long long* keys, int64_t n, const int32_t* fail, unsigned long long* out,
                            unsigned long long* n_out, hipStream_t s);
-hipError_t fov_sort(unsigned long long* keys, int64_t n, int64_t n_frames, int32_t* fcnt, int32_t* fstart,
-                    unsigned long long* sorted, void* scan_scratch, int32_t* pf, int32_t* ps, int32_t* po,
-                    hipStream_t s);
+// Pair keys of objects 0 .. n_obj - 1 and n_sub sub-frames to the output
+// arrays, sorted by (frame, sub-frame, object).
+hipError_t fov_sort(unsigned long long* keys, int64_t n, int64_t n_frames, int64_t n_obj, int n_sub, int32_t* fcnt,
+                    int32_t* fstart, unsigned long long* sorted, void* scan_scratch, int32_t* pf, int32_t* ps,
+                    int32_t* po, hipStream_t s);
 hipError_t launch_directions(const FovParams& p, const double* x_ref, double t_ref, const double* t_obs,
                              const double* obs, int64_t n_q, double* d, double* tau, hipStream_t s);
 hipError_t launch_ephem_eval(const EphemArgs& E, const double* t, int64_t n_q, double* out, hipStream_t s);

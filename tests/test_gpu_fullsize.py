@@ -97,6 +97,10 @@ def _run_full(torch, api, case, label):
     torch.cuda.synchronize()
     _say(f"{label}: {case.x0.shape[0]} bodies, {fr.t.size} frames x {fr.n_sub} sub-frames, {t_ref.size} batches: "
          f"{pf.numel()} pairs ({time.perf_counter() - t0:.1f} s with uploads)")
+    # every pair once, in (frame, sub-frame, body) order, at full size
+    key = (pf.long() << 32) | (ps.long() << 25) | po.long()
+    assert bool((key[1:] > key[:-1]).all())
+    del key
     return xg, sg, (pf, ps, po), order, off, t_ref
 
 
