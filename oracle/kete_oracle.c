@@ -14,7 +14,8 @@
  *     the direct T_k / T_k' recurrences;
  *   - acceleration: Newtonian sum over registered masses (Eq. A.1, with
  *     the attractive sign written out) plus the eps = 0 post-Newtonian term
- *     (Eq. A.3) for flagged bodies;
+ *     (Eq. A.3) for flagged bodies and the J2 oblateness term (App. A.3,
+ *     Eq. A.4) for bodies given a J2, radius and pole;
  *   - integrator: Gauss-Radau 15th order in Everhart's b/g form with the
  *     IAS15 corrector-convergence test and the predictor removed (App. A.6:
  *     the b coefficients start from zero at every step), IAS15-style step
@@ -60,6 +61,8 @@ typedef struct {
     const double *coef;      /* [n_body][n_seg][3][degree+1] */
     const double *gm;        /* [n_body] au^3/day^2 */
     const uint32_t *flags;   /* [n_body], bit0: post-Newtonian term */
+    const double *j2;        /* [n_body][5] or NULL: J2, radius (au), unit pole
+                                (integration frame); J2 = 0: no term */
 } orc_ephem;
 
 typedef struct {
@@ -122,7 +125,61 @@ int orc_cheb(const orc_ephem *E, int body, double t, double pos[3], double vel[3
 
 static double dot3(const double *a, const double *b) { return a[0]*b[0] + a[1]*b[1] + a[2]*b[2]; }
 
-/* a = sum_m [ -mu_m r / |r|^3  +  (flagged) mu_m/(c^2 |r|^3) ((4 mu_m/|r| - |w|^2) r + 4 (r.w) w) ]
+/* J2 term of body m (App. A.3, Eq. A.4) written as the paper gives it:
+ * in the body's equatorial frame (z along the pole p, x and y any
+ * right-handed completion), with the relative position rho = x_m - x
+ * taken with the sign of Eq. A.2's Newtonian term mu rho / |rho|^3,
+ *   a = psi [(1 - 5 z^2/r^2) x, (1 - 5 z^2/r^2) y, (3 - 5 z^2/r^2) z],
+ *   psi = (3/2) J2 mu R^2 / r^5,
+ * then rotated back.  With jx, adds da/dx (= -da/drho), derived in the
+ * same frame: da_i/drho_j = dpsi/drho_j c_i rho_i - psi dq/drho_j rho_i
+ * + psi c_i delta_ij, q = 5 z^2/r^2, c = (1 - q, 1 - q, 3 - q). */
+static void orc_j2_term(const double *j2, double mu, const double pb[3], const double x[3], double a[3],
+                        double *jx)
+{
+    double J2 = j2[0], R = j2[1];
+    double pz[3] = { j2[2], j2[3], j2[4] };
+    /* x axis: the unit axis least aligned with the pole, made orthogonal */
+    int ax = 0;
+    if (fabs(pz[1]) < fabs(pz[ax])) ax = 1;
+    if (fabs(pz[2]) < fabs(pz[ax])) ax = 2;
+    double px[3] = { -pz[ax] * pz[0], -pz[ax] * pz[1], -pz[ax] * pz[2] };
+    px[ax] += 1.0;
+    double nx = sqrt(dot3(px, px));
+    for (int i = 0; i < 3; i++) px[i] /= nx;
+    double py[3] = { pz[1] * px[2] - pz[2] * px[1], pz[2] * px[0] - pz[0] * px[2], pz[0] * px[1] - pz[1] * px[0] };
+    const double *Rw[3] = { px, py, pz };            /* rows: frame axes in the integration frame */
+    double rw[3] = { pb[0] - x[0], pb[1] - x[1], pb[2] - x[2] };
+    double rho[3];
+    for (int i = 0; i < 3; i++) rho[i] = dot3(Rw[i], rw);
+    double r2 = dot3(rho, rho), r = sqrt(r2);
+    double psi = 1.5 * J2 * mu * R * R / (r2 * r2 * r);
+    double q = 5.0 * rho[2] * rho[2] / r2;
+    double c[3] = { 1.0 - q, 1.0 - q, 3.0 - q };
+    double af[3];
+    for (int i = 0; i < 3; i++) af[i] = psi * c[i] * rho[i];
+    for (int i = 0; i < 3; i++) a[i] += af[0] * Rw[0][i] + af[1] * Rw[1][i] + af[2] * Rw[2][i];
+    if (jx) {
+        double Jf[9];                                  /* d af / d rho in the body frame */
+        for (int i = 0; i < 3; i++)
+            for (int j = 0; j < 3; j++) {
+                double dpsi = -5.0 * psi * rho[j] / r2;
+                double dq = (j == 2 ? 10.0 * rho[2] / r2 : 0.0) - 10.0 * rho[2] * rho[2] * rho[j] / (r2 * r2);
+                Jf[3*i + j] = dpsi * c[i] * rho[i] - psi * dq * rho[i] + (i == j ? psi * c[i] : 0.0);
+            }
+        /* da/dx = Rw^T Jf Rw (d rho / dx = -Rw, so a minus sign) */
+        for (int i = 0; i < 3; i++)
+            for (int j = 0; j < 3; j++) {
+                double s = 0.0;
+                for (int k = 0; k < 3; k++)
+                    for (int l = 0; l < 3; l++) s += Rw[k][i] * Jf[3*k + l] * Rw[l][j];
+                jx[3*i + j] -= s;
+            }
+    }
+}
+
+/* a = sum_m [ -mu_m r / |r|^3  +  (flagged) mu_m/(c^2 |r|^3) ((4 mu_m/|r| - |w|^2) r + 4 (r.w) w)
+ *            + (J2 given) Eq. A.4 ]
  * with r = x - x_m and w = v - v_m.  Optional Jacobians jx = da/dx and
  * jv = da/dv (row-major 3x3). */
 int orc_accel_jac(const orc_ephem *E, double c_light, double t, const double x[3], const double v[3],
@@ -176,6 +233,7 @@ int orc_accel_jac(const orc_ephem *E, double c_light, double t, const double x[3
                     }
             }
         }
+        if (E->j2 && E->j2[5 * b] != 0.0) orc_j2_term(E->j2 + 5 * b, mu, pb, x, a, jx);
     }
     return ORC_OK;
 }

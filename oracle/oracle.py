@@ -37,7 +37,7 @@ class Ephem(C.Structure):
     _fields_ = [("n_body", C.c_int32), ("n_seg", C.c_int32), ("degree", C.c_int32), ("pad", C.c_int32),
                 ("t_start", C.c_double), ("seg_days", C.c_double),
                 ("coef", C.POINTER(C.c_double)), ("gm", C.POINTER(C.c_double)),
-                ("flags", C.POINTER(C.c_uint32))]
+                ("flags", C.POINTER(C.c_uint32)), ("j2", C.POINTER(C.c_double))]
 
 
 class Opts(C.Structure):
@@ -75,8 +75,11 @@ class OracleEphem:
         self.gm = _f64(eph.gm)
         self.flags = np.ascontiguousarray(eph.flags, dtype=np.uint32)
         nb, ns, _, m = self.coef.shape
+        j2 = getattr(eph, "j2", None)
+        self.j2 = None if j2 is None else _f64(j2).reshape(nb, 5)
         self.s = Ephem(nb, ns, m - 1, 0, float(eph.t_start), float(eph.seg_days),
-                       _p(self.coef), _p(self.gm), _p(self.flags, C.c_uint32))
+                       _p(self.coef), _p(self.gm), _p(self.flags, C.c_uint32),
+                       None if self.j2 is None else _p(self.j2))
 
     @property
     def ref(self):

@@ -27,7 +27,7 @@ from __future__ import annotations
 import dataclasses
 import math
 import os
-from typing import Dict, List, Optional
+from typing import Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -185,6 +185,7 @@ class Ephemeris:
     t_start: float
     seg_days: float
     names: List[str]
+    j2: Optional[np.ndarray] = None   # [n_body, 5]: J2, radius (au), unit pole; J2 = 0: no term (App. A.3)
 
     @property
     def n_body(self): return self.coef.shape[0]
@@ -231,11 +232,17 @@ def make_ephemeris(model: PlanetModel, t_start: float, n_seg: int,
 
 
 def sun_only_ephemeris(t_start: float, n_seg: int, gr: bool = False,
-                       seg_days: float = SEG_DAYS, degree: int = CHEB_DEGREE) -> Ephemeris:
-    """A single perturber (the Sun) fixed at the origin."""
+                       seg_days: float = SEG_DAYS, degree: int = CHEB_DEGREE,
+                       j2: Optional[Tuple[float, float, Sequence[float]]] = None) -> Ephemeris:
+    """A single perturber (the Sun) fixed at the origin; j2 = (J2, radius
+    in au, pole) gives it the oblateness term of App. A.3."""
     coef = np.zeros((1, n_seg, 3, degree + 1))
+    row = None
+    if j2 is not None:
+        pole = np.asarray(j2[2], float)
+        row = np.array([[float(j2[0]), float(j2[1]), *(pole / np.linalg.norm(pole))]])
     return Ephemeris(coef, np.array([GM_SUN]), np.array([1 if gr else 0], np.uint32),
-                     float(t_start), float(seg_days), ["sun"])
+                     float(t_start), float(seg_days), ["sun"], row)
 
 
 def polynomial_ephemeris(rng: np.random.Generator, n_body: int, t_start: float,
