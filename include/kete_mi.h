@@ -53,6 +53,7 @@ extern "C" {
 #define KETE_ST_KEPLER_NOCONV  4   /* universal-variable solve did not converge */
 
 #define KETE_MAX_BODIES  16        /* perturbers, body 0 = Sun */
+#define KETE_MAX_J2      4         /* bodies with the App. A.3 oblateness term */
 #define KETE_MAX_DEGREE  15        /* Chebyshev degree */
 #define KETE_MAX_SUB     128       /* sub-frames per frame */
 #define KETE_MAX_OBJ     (1 << 25) /* objects per call */
@@ -76,6 +77,10 @@ typedef struct {
     const double *coef;      /* device [n_body][n_seg][3][degree+1] */
     const double *gm;        /* host [n_body], au^3/day^2 (Eq. A.1 mu_m) */
     const uint32_t *flags;   /* host [n_body], bit0: add the Eq. A.3 term */
+    const double *j2;        /* host [n_body][5] or NULL: {J2, radius rho_m (au),
+                                pole (unit vector in the integration frame)}
+                                of the App. A.3 Eq. A.4 term; J2 = 0 for none,
+                                at most KETE_MAX_J2 bodies */
 } kete_ephem_t;
 
 /* Options.  kete_default_opts() fills every field; zero means "default"
@@ -203,11 +208,15 @@ size_t kete_propagate_workspace_size(int64_t n_obj, int64_t n_out, const kete_op
 /* n-body propagation of massless bodies (Sect. 2, App. A): every object
  * starts at the common epoch t0 and is integrated through the epochs
  * t_out[0..n_out) (strictly monotone, all after t0 or all before t0),
- * landing exactly on each.  Force: Eq. A.1 (attractive) plus Eq. A.3 for
- * bodies with flags bit0.  Integrator: Gauss-Radau collocation with 8
- * nodes (the method of App. A.6, predictor removed), step size shared by
- * the 64 objects of a wavefront, objects grouped into wavefronts by
- * predicted step size.
+ * their states at each.  Force: Eq. A.1 (attractive) plus Eq. A.3 for
+ * bodies with flags bit0 and Eq. A.4 (App. A.3) for bodies given a J2.
+ * Integrator: Gauss-Radau collocation with 8 nodes (the method of
+ * App. A.6, predictor removed), IAS15 step control.  By default 7 lanes
+ * share an object's force sums and the 9 objects of a wavefront share its
+ * step size (objects are grouped by a predicted step size); states at
+ * epochs inside a step are read off the step's collocation polynomial and
+ * only the last epoch of a launch is landed on (opts lanes_per_body,
+ * land_epochs).
  *   x0      device [n_obj][6]  (x, y, z, vx, vy, vz)
  *   t_out   host   [n_out]
  *   x_out   device [n_out][n_obj][6]

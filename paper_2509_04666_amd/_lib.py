@@ -31,7 +31,8 @@ class KeteError(RuntimeError):
 class EphemT(C.Structure):
     _fields_ = [("n_body", C.c_int32), ("n_seg", C.c_int32), ("degree", C.c_int32), ("reserved", C.c_int32),
                 ("t_start", C.c_double), ("seg_days", C.c_double), ("coef", C.c_void_p),
-                ("gm", C.POINTER(C.c_double)), ("flags", C.POINTER(C.c_uint32))]
+                ("gm", C.POINTER(C.c_double)), ("flags", C.POINTER(C.c_uint32)),
+                ("j2", C.POINTER(C.c_double))]
 
 
 class OptsT(C.Structure):

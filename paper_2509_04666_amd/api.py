@@ -41,7 +41,9 @@ def default_opts(**kw) -> OptsT:
 class DeviceEphemeris:
     """A Chebyshev ephemeris with its coefficient table in device memory."""
 
-    def __init__(self, coef, gm, flags, t_start: float, seg_days: float, device=DEV):
+    def __init__(self, coef, gm, flags, t_start: float, seg_days: float, device=DEV, j2=None):
+        """j2: None, or [n_body, 5] rows {J2, radius au, unit pole} of the
+        App. A.3 term (J2 = 0: none)."""
         self.coef = torch.as_tensor(np.ascontiguousarray(coef), dtype=torch.float64).to(device).contiguous()
         self.gm = np.ascontiguousarray(gm, dtype=np.float64)
         self.flags = np.ascontiguousarray(flags, dtype=np.uint32)
@@ -49,13 +51,15 @@ class DeviceEphemeris:
         self.seg_days = float(seg_days)
         nb, ns, three, m = self.coef.shape
         assert three == 3
+        self.j2 = None if j2 is None else np.ascontiguousarray(np.asarray(j2, dtype=np.float64).reshape(nb, 5))
         self.c = EphemT(nb, ns, m - 1, 0, self.t_start, self.seg_days, self.coef.data_ptr(),
                         self.gm.ctypes.data_as(C.POINTER(C.c_double)),
-                        self.flags.ctypes.data_as(C.POINTER(C.c_uint32)))
+                        self.flags.ctypes.data_as(C.POINTER(C.c_uint32)),
+                        None if self.j2 is None else self.j2.ctypes.data_as(C.POINTER(C.c_double)))
 
     @staticmethod
     def from_synth(e, device=DEV) -> "DeviceEphemeris":
-        return DeviceEphemeris(e.coef, e.gm, e.flags, e.t_start, e.seg_days, device)
+        return DeviceEphemeris(e.coef, e.gm, e.flags, e.t_start, e.seg_days, device, getattr(e, "j2", None))
 
     @property
     def n_body(self): return self.coef.shape[0]

@@ -781,7 +781,7 @@ hipError_t launch_adjoint(const AdjParams& p, int mode, hipStream_t s) {
     const int nb = p.eph.n_body, ngr = p.eph.n_gr, d1 = p.eph.deg1;
     if (mode == KETE_ADJ_FWD) {
         hipLaunchKernelGGL(k_adj_dense_coef, dim3(1), dim3(128), 0, s, p);
-        if (nb == 9 && ngr == 3 && d1 == 13) hipLaunchKernelGGL((k_adjoint_fwd<9, 3, 13>), dim3(grid), dim3(64), lds, s, p);
+        if (nb == 10 && ngr == 3 && d1 == 13) hipLaunchKernelGGL((k_adjoint_fwd<10, 3, 13>), dim3(grid), dim3(64), lds, s, p);
         else if (nb == 3 && ngr == 2 && d1 == 13)
             hipLaunchKernelGGL((k_adjoint_fwd<3, 2, 13>), dim3(grid), dim3(64), lds, s, p);
         else hipLaunchKernelGGL((k_adjoint_fwd<0, 0, 0>), dim3(grid), dim3(64), lds, s, p);
@@ -822,8 +822,8 @@ hipError_t launch_adjoint(const AdjParams& p, int mode, hipStream_t s) {
         const int b = c & 1;
         if (c + 2 < C && (e = hipStreamWaitEvent(r, freed[b], 0)) != hipSuccess) return e;
         const AdjParams q = in_store(b);
-        if (nb == 9 && ngr == 3 && d1 == 13)
-            hipLaunchKernelGGL((k_adj_recompute<9, 3, 13>), dim3(grid), dim3(64), lds, r, q, c);
+        if (nb == 10 && ngr == 3 && d1 == 13)
+            hipLaunchKernelGGL((k_adj_recompute<10, 3, 13>), dim3(grid), dim3(64), lds, r, q, c);
         else if (nb == 3 && ngr == 2 && d1 == 13)
             hipLaunchKernelGGL((k_adj_recompute<3, 2, 13>), dim3(grid), dim3(64), lds, r, q, c);
         else hipLaunchKernelGGL((k_adj_recompute<0, 0, 0>), dim3(grid), dim3(64), lds, r, q, c);

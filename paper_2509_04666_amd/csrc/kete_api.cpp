@@ -248,6 +248,21 @@ int ephem_args(const kete_ephem_t* eph, double c_light, EphemArgs& E) {
                 ++slot;
                 if (pass == 0) ++E.n_gr;
             }
+    if (eph->j2) {
+        for (int b = 0; b < eph->n_body; ++b) {
+            const double* q = eph->j2 + 5 * b;
+            if (q[0] == 0.0) continue;
+            const double pn = std::sqrt(q[2] * q[2] + q[3] * q[3] + q[4] * q[4]);
+            if (!std::isfinite(q[0]) || !(q[1] > 0) || !std::isfinite(q[1]) || !(std::fabs(pn - 1.0) < 1e-6))
+                return fail(KETE_EINVAL, "j2[%d]: need finite J2, radius > 0 and a unit pole", b);
+            if (E.n_j2 >= KETE_MAX_J2) return fail(KETE_EINVAL, "more than %d bodies with J2", KETE_MAX_J2);
+            const int i = E.n_j2++;
+            E.j2_body[i] = b;
+            E.j2_slot[i] = body_slot(E, b);
+            E.j2k[i] = 1.5 * q[0] * eph->gm[b] * q[1] * q[1];
+            for (int c = 0; c < 3; ++c) E.j2p[i][c] = q[2 + c] / pn;
+        }
+    }
     return KETE_OK;
 }
 

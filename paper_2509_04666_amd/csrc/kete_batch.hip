@@ -214,7 +214,7 @@ hipError_t launch_batch(const BatchParams& p, int waves_per_cu, hipStream_t s) {
     const int grid = std::max(1, std::min(ncu * waves_per_cu, p.n_tiles));
     const size_t lds = batch_lds_bytes(p);
     const int nb = p.eph.n_body, ngr = p.eph.n_gr, d1 = p.eph.deg1;
-    if (nb == 9 && ngr == 3 && d1 == 13) hipLaunchKernelGGL((k_batch_g8<9, 3, 13>), dim3(grid), dim3(64), lds, s, p);
+    if (nb == 10 && ngr == 3 && d1 == 13) hipLaunchKernelGGL((k_batch_g8<10, 3, 13>), dim3(grid), dim3(64), lds, s, p);
     else if (nb == 3 && ngr == 2 && d1 == 13)
         hipLaunchKernelGGL((k_batch_g8<3, 2, 13>), dim3(grid), dim3(64), lds, s, p);
     else hipLaunchKernelGGL((k_batch_g8<0, 0, 0>), dim3(grid), dim3(64), lds, s, p);

@@ -25,6 +25,12 @@ struct EphemArgs {
     int32_t n_gr, pad_;
     unsigned long long slot_of;    // slot of body b: 4 bits at 4 b
     unsigned long long body_at;    // body in slot s: 4 bits at 4 s
+    // Bodies with the Eq. A.4 term: body index, grouped-table slot,
+    // k = (3/2) J2 mu R^2 and the unit pole.
+    int32_t n_j2, pad2_;
+    int32_t j2_body[KETE_MAX_J2], j2_slot[KETE_MAX_J2];
+    double j2k[KETE_MAX_J2];
+    double j2p[KETE_MAX_J2][3];
 };
 
 __host__ __device__ inline int body_slot(const EphemArgs& E, int b) { return (int)((E.slot_of >> (4 * b)) & 15ull); }

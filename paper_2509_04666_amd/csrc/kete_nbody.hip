@@ -380,8 +380,8 @@ hipError_t launch_nbody(const NbodyParams& p, int block, int lanes_per_body, hip
         const int nb = p.eph.n_body, ngr = p.eph.n_gr, d1 = p.eph.deg1;
 #define KETE_G8(B, G)                                                                                           \
     do {                                                                                                        \
-        if (nb == 9 && ngr == 3 && d1 == 13)                                                                    \
-            hipLaunchKernelGGL((k_nbody_g8<B, G, 9, 3, 13>), dim3(grid), dim3(B), lds8, s, p);                  \
+        if (nb == 10 && ngr == 3 && d1 == 13)                                                                   \
+            hipLaunchKernelGGL((k_nbody_g8<B, G, 10, 3, 13>), dim3(grid), dim3(B), lds8, s, p);                 \
         else if (nb == 3 && ngr == 2 && d1 == 13)                                                               \
             hipLaunchKernelGGL((k_nbody_g8<B, G, 3, 2, 13>), dim3(grid), dim3(B), lds8, s, p);                  \
         else hipLaunchKernelGGL((k_nbody_g8<B, G, 0, 0, 0>), dim3(grid), dim3(B), lds8, s, p);                  \

@@ -10,8 +10,47 @@ namespace kete {
 constexpr int kNodes = 9;   // s_0 = 0, s_1..s_7, and s = 1 (step end)
 constexpr double kInf = 1e300;
 
+// Eq. A.4 (App. A.3) of J2 body q in vector form.  With d = x - x_m the
+// object's offset from the body (Eq. A.4's r is -d, the sign of Eq. A.2's
+// Newtonian term), z = d . p along the unit pole p and k = (3/2) J2 mu R^2,
+// the componentwise expression in the body's equatorial frame reads
+//   a = -k / |d|^5 [(1 - 5 z^2 / |d|^2) d + 2 z p].
+// id = 1 / |d|.
+__device__ __forceinline__ void j2_add(const EphemArgs& E, int q, const double d[3], double id, double a[3]) {
+    const double* p = E.j2p[q];
+    const double id2 = id * id;
+    const double s = -E.j2k[q] * (id2 * id2 * id);
+    const double z = fma(d[0], p[0], fma(d[1], p[1], d[2] * p[2]));
+    const double c = s * fma(-5.0 * z * id2, z, 1.0);
+    const double e = 2.0 * s * z;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) a[i] = fma(c, d[i], fma(e, p[i], a[i]));
+}
+
+// Its Jacobian da/dx, added to Jx (symmetric, the Hessian of the J2
+// potential):
+//   -k [A I + B d d^T + C (d p^T + p d^T) + E p p^T],
+//   A = |d|^-5 - 5 z^2 |d|^-7, B = 35 z^2 |d|^-9 - 5 |d|^-7,
+//   C = -10 z |d|^-7, E = 2 |d|^-5.
+__device__ __forceinline__ void j2_jac_add(const EphemArgs& E, int q, const double d[3], double id, double Jx[9]) {
+    const double* p = E.j2p[q];
+    const double k = E.j2k[q];
+    const double id2 = id * id, id5 = id2 * id2 * id, id7 = id5 * id2;
+    const double z = fma(d[0], p[0], fma(d[1], p[1], d[2] * p[2]));
+    const double A = -k * (id5 - 5.0 * z * z * id7);
+    const double B = -k * (35.0 * z * z * id7 * id2 - 5.0 * id7);
+    const double C = -k * (-10.0 * z * id7);
+    const double Ee = -k * 2.0 * id5;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            Jx[3 * i + j] += (i == j ? A : 0.0) + B * d[i] * d[j] + C * (d[i] * p[j] + p[i] * d[j]) + Ee * p[i] * p[j];
+}
+
 // Acceleration at one node from the LDS perturber table e[b][6]:
-// Eq. A.1 with the attractive sign, plus Eq. A.3 (eps = 0) where kgr != 0.
+// Eq. A.1 with the attractive sign, plus Eq. A.3 (eps = 0) where kgr != 0
+// and Eq. A.4 for the J2 bodies.
 __device__ __forceinline__ void accel(const double* __restrict__ e, const EphemArgs& E,
                                       const double X[3], const double V[3], double F[3]) {
     double ax = 0.0, ay = 0.0, az = 0.0;
@@ -36,82 +75,10 @@ __device__ __forceinline__ void accel(const double* __restrict__ e, const EphemA
         ax = fma(f, rx, ax); ay = fma(f, ry, ay); az = fma(f, rz, az);
     }
     F[0] = ax; F[1] = ay; F[2] = az;
-}
-
-// The same force with the perturber count fixed at compile time (NB > 0):
-// the loop is unrolled, so the perturber loads of all bodies can be in
-// flight together and GM values stay in scalar registers.  NB = 0 falls
-// back to the runtime loop.
-template <int NB>
-__device__ __forceinline__ void accel_n(const double* __restrict__ e, const EphemArgs& E, const double X[3],
-                                        const double V[3], double F[3]) {
-    if constexpr (NB == 0) {
-        accel(e, E, X, V, F);
-    } else {
-        double ax = 0.0, ay = 0.0, az = 0.0;
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            const double* pb = e + 6 * b;
-            const double rx = X[0] - pb[0], ry = X[1] - pb[1], rz = X[2] - pb[2];
-            const double r2 = fma(rx, rx, fma(ry, ry, rz * rz));
-            const double ir = rsqrt(r2);
-            const double ir3 = ir * ir * ir;
-            const double gm = E.gm[b];
-            double f = -gm * ir3;
-            const double k = E.kgr[b];
-            if (k != 0.0) {
-                const double wx = V[0] - pb[3], wy = V[1] - pb[4], wz = V[2] - pb[5];
-                const double w2 = fma(wx, wx, fma(wy, wy, wz * wz));
-                const double rw = fma(rx, wx, fma(ry, wy, rz * wz));
-                const double g = k * ir3;
-                f = fma(g, 4.0 * gm * ir - w2, f);
-                const double q = 4.0 * g * rw;
-                ax = fma(q, wx, ax); ay = fma(q, wy, ay); az = fma(q, wz, az);
-            }
-            ax = fma(f, rx, ax); ay = fma(f, ry, ay); az = fma(f, rz, az);
-        }
-        F[0] = ax; F[1] = ay; F[2] = az;
-    }
-}
-
-// Jacobians Jx = da/dx and Jv = da/dv (row-major 3x3) of the same force.
-// Newtonian part: mu (3 r r^T / r^5 - I / r^3).  Eq. A.3 part, with
-// a = k/r^3 (s1 r + 4 (r.w) w), s1 = 4 mu/r - w^2:
-//   da/dr = k [ -3 P r^T / r^5 - 4 mu r r^T / r^6 + s1 I / r^3 + 4 w w^T / r^3 ]
-//   da/dw = k / r^3 [ -2 r w^T + 4 w r^T + 4 (r.w) I ]
-// where P = s1 r + 4 (r.w) w.
-__device__ __forceinline__ void accel_jac(const double* __restrict__ e, const EphemArgs& E, const double X[3],
-                                          const double V[3], double Jx[9], double Jv[9]) {
-    for (int i = 0; i < 9; ++i) { Jx[i] = 0.0; Jv[i] = 0.0; }
-    for (int b = 0; b < E.n_body; ++b) {
-        const double* pb = e + 6 * b;
-        const double r[3] = {X[0] - pb[0], X[1] - pb[1], X[2] - pb[2]};
-        const double r2 = dot3(r, r);
-        const double ir = rsqrt(r2);
-        const double ir2 = ir * ir, ir3 = ir2 * ir, ir5 = ir3 * ir2;
-        const double gm = E.gm[b];
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j)
-                Jx[3 * i + j] += gm * (3.0 * r[i] * r[j] * ir5 - (i == j ? ir3 : 0.0));
-        const double k = E.kgr[b];
-        if (k != 0.0) {
-            const double w[3] = {V[0] - pb[3], V[1] - pb[4], V[2] - pb[5]};
-            const double w2 = dot3(w, w), rw = dot3(r, w);
-            const double s1 = 4.0 * gm * ir - w2;
-            const double P[3] = {s1 * r[0] + 4.0 * rw * w[0], s1 * r[1] + 4.0 * rw * w[1], s1 * r[2] + 4.0 * rw * w[2]};
-            const double ir6 = ir3 * ir3;
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-#pragma unroll
-                for (int j = 0; j < 3; ++j) {
-                    const double d = (i == j) ? 1.0 : 0.0;
-                    Jx[3 * i + j] += k * (-3.0 * P[i] * r[j] * ir5 - 4.0 * gm * r[i] * r[j] * ir6 + s1 * d * ir3 +
-                                          4.0 * w[i] * w[j] * ir3);
-                    Jv[3 * i + j] += k * ir3 * (-2.0 * r[i] * w[j] + 4.0 * w[i] * r[j] + 4.0 * rw * d);
-                }
-        }
+    for (int q = 0; q < E.n_j2; ++q) {
+        const double* pb = e + 6 * E.j2_body[q];
+        const double d[3] = {X[0] - pb[0], X[1] - pb[1], X[2] - pb[2]};
+        j2_add(E, q, d, rsqrt(fma(d[0], d[0], fma(d[1], d[1], d[2] * d[2]))), F);
     }
 }
 
@@ -452,8 +419,9 @@ __device__ __forceinline__ double rsqrt_pos(double x) {
     return fma(y0 * e, fma(e, 0.375, 0.5), y0);
 }
 
-// Force of Eqs. A.1 + A.3 from the grouped table e8 (one node): slots
-// below NGR carry the Eq. A.3 term.  NB = 0 takes the counts at run time.
+// Force of Eqs. A.1 + A.3 + A.4 from the grouped table e8 (one node):
+// slots below NGR carry the Eq. A.3 term, the J2 bodies (found by slot)
+// the Eq. A.4 term.  NB = 0 takes the counts at run time.
 template <int NB, int NGR>
 __device__ __forceinline__ void accel8(const double* __restrict__ e8, const EphemArgs& E, const double X[3],
                                        const double V[3], double F[3]) {
@@ -495,6 +463,11 @@ __device__ __forceinline__ void accel8(const double* __restrict__ e8, const Ephe
         ax = fma(f, rx, ax); ay = fma(f, ry, ay); az = fma(f, rz, az);
     }
     F[0] = ax; F[1] = ay; F[2] = az;
+    for (int q = 0; q < E.n_j2; ++q) {
+        const double* pb = e8 + kSlot * E.j2_slot[q];
+        const double d[3] = {X[0] - pb[0], X[1] - pb[1], X[2] - pb[2]};
+        j2_add(E, q, d, rsqrt_pos(fma(d[0], d[0], fma(d[1], d[1], d[2] * d[2]))), F);
+    }
 }
 
 // The same force computed by a group together: node lane gl < 7 takes
@@ -527,7 +500,12 @@ __device__ __forceinline__ void accel8_group(const double* __restrict__ e8, cons
         }
         ax = fma(f, rx, ax); ay = fma(f, ry, ay); az = fma(f, rz, az);
     }
-    const double part[3] = {ax, ay, az};
+    double part[3] = {ax, ay, az};
+    if (gl < E.n_j2) {                         // node lane q takes J2 body q
+        const double* pb = e8 + kSlot * E.j2_slot[gl];
+        const double d[3] = {X[0] - pb[0], X[1] - pb[1], X[2] - pb[2]};
+        j2_add(E, gl, d, rsqrt_pos(fma(d[0], d[0], fma(d[1], d[1], d[2] * d[2]))), part);
+    }
     double D[7][3];
     g8_exchange(xg, gl, part, D);
 #pragma unroll
@@ -540,7 +518,7 @@ __device__ __forceinline__ void accel8_group(const double* __restrict__ e8, cons
 }
 
 // Jacobians Jx = da/dx, Jv = da/dv (row-major 3x3) from the grouped
-// table e8 (one node); same force as accel_jac.  The Newtonian part is
+// table e8 (one node) of the force of accel8, Eq. A.4 included.  The Newtonian part is
 // symmetric and accumulated once per pair (i <= j); the Eq. A.3 part,
 // with P = s1 r + 4 (r.w) w and s1 = 4 mu / r - w^2, is
 //   Jx += k [(-3 P / r^5 - 4 mu r / r^6) r^T + 4 w w^T / r^3 + s1 I / r^3]
@@ -605,6 +583,11 @@ __device__ __forceinline__ void accel_jac8(const double* __restrict__ e8, const 
     Jx[0] += S[0] + dg; Jx[1] += S[1]; Jx[2] += S[2];
     Jx[3] += S[1]; Jx[4] += S[3] + dg; Jx[5] += S[4];
     Jx[6] += S[2]; Jx[7] += S[4]; Jx[8] += S[5] + dg;
+    for (int q = 0; q < E.n_j2; ++q) {
+        const double* pb = e8 + kSlot * E.j2_slot[q];
+        const double d[3] = {X[0] - pb[0], X[1] - pb[1], X[2] - pb[2]};
+        j2_jac_add(E, q, d, rsqrt_pos(fma(d[0], d[0], fma(d[1], d[1], d[2] * d[2]))), Jx);
+    }
 }
 
 // Step-size factor (eps / e)^(1/7) of the IAS15 control, in single

@@ -70,6 +70,27 @@ ASTEROID_NAMES = [p[0] for p in _ASTEROIDS]
 # Bodies that carry the first post-Newtonian correction (Sun, Jupiter, Earth).
 GR_BODIES = ("sun", "jupiter", "earth")
 
+# The Moon as a registered mass: the "earth" row above is the Earth-Moon
+# barycentre; with the Moon, the Earth and the Moon (DE440 GM values) sit
+# on either side of it, the Moon's geocentric orbit a mean ellipse whose
+# node regresses and perigee advances uniformly (rounded published mean
+# elements at J2000, ecliptic; angles in degrees, rates in degrees/day).
+GM_EARTH = 8.8876924467071033e-10
+GM_MOON = 1.0931894624024351e-11
+_MOON_ORBIT = dict(a=384400.0 / 149597870.7, e=0.0549, I=5.145,
+                   L0=218.3164477, Ldot=13.17639648, peri0=83.3532465, peridot=0.1114040,
+                   node0=125.0445479, nodedot=-0.0529539)
+
+# Oblateness of the bodies that carry the App. A.3 term: J2, equatorial
+# radius (km) and the pole's right ascension and declination (deg,
+# equatorial J2000), rounded published values (IAU rotation elements;
+# helioseismic solar J2; Juno gravity field).
+_J2_BODIES = {
+    "sun": (2.2e-7, 696000.0, 286.13, 63.87),
+    "jupiter": (1.4696514e-2, 71492.0, 268.056595, 64.495303),
+}
+AU_KM = 149597870.7
+
 SEG_DAYS = 8.0
 CHEB_DEGREE = 12
 
@@ -127,42 +148,86 @@ def elements_to_state(a, e, inc, node, peri, M, mu):
 @dataclasses.dataclass
 class PlanetModel:
     """Sun plus planets on fixed heliocentric ellipses (an analytic stand-in
-    for a planetary ephemeris)."""
+    for a planetary ephemeris), optionally the Moon about the Earth."""
     names: List[str]
-    gm: np.ndarray          # [n_body] (index 0 = Sun)
+    gm: np.ndarray          # [n_body] (index 0 = Sun) registered masses
     el: np.ndarray          # [n_planet, 6]: a, e, I, node, peri, M0 (radians)
     n: np.ndarray           # mean motions [rad/day]
+    msys: np.ndarray        # [n_planet] mass of each ellipse's system (Earth + Moon for "earth")
+    moon: bool = False      # last body: the Moon; the "earth" ellipse carries their barycentre
 
     @staticmethod
-    def make(planets: Optional[List[str]] = None) -> "PlanetModel":
+    def make(planets: Optional[List[str]] = None, moon: Optional[bool] = None) -> "PlanetModel":
+        """The planets (all eight by default) and, by default when the
+        Earth is among them, the Moon (the default registered masses of
+        Sect. 3.2)."""
         planets = PLANET_NAMES if planets is None else list(planets)
+        moon = ("earth" in planets) if moon is None else bool(moon)
+        if moon and "earth" not in planets:
+            raise ValueError("the Moon needs the Earth")
         order = PLANET_NAMES + ASTEROID_NAMES
         rows = [p for p in _PLANETS + _ASTEROIDS if p[0] in planets]
         rows.sort(key=lambda p: order.index(p[0]))
-        gm = np.array([GM_SUN] + [p[1] for p in rows])
+        msys = np.array([p[1] for p in rows])
         el = []
         for p in rows:
             a, e, I, L, varpi, node = p[2:]
             el.append([a, e, math.radians(I), math.radians(node),
                        math.radians(varpi - node), math.radians(L - varpi)])
         el = np.array(el).reshape(-1, 6)
-        n = np.sqrt((GM_SUN + gm[1:]) / el[:, 0] ** 3)
-        return PlanetModel(["sun"] + [p[0] for p in rows], gm, el, n)
+        n = np.sqrt((GM_SUN + msys) / el[:, 0] ** 3)
+        names = ["sun"] + [p[0] for p in rows]
+        gm = np.concatenate([[GM_SUN], msys])
+        if moon:
+            gm[names.index("earth")] = GM_EARTH
+            gm = np.concatenate([gm, [GM_MOON]])
+            names = names + ["moon"]
+        return PlanetModel(names, gm, el, n, msys, moon)
 
     def helio(self, t: np.ndarray) -> np.ndarray:
-        """Heliocentric planet states [..., n_planet, 6] at times t [...]."""
+        """Heliocentric states [..., n_planet, 6] of the ellipses (the
+        Earth-Moon barycentre for "earth") at times t [...]."""
         t = np.asarray(t, float)
         M = self.el[:, 5] + self.n * t[..., None]
-        mu = GM_SUN + self.gm[1:]
+        mu = GM_SUN + self.msys
         return elements_to_state(self.el[:, 0], self.el[:, 1], self.el[:, 2],
                                  self.el[:, 3], self.el[:, 4], M, mu)
+
+    def moon_geo(self, t: np.ndarray) -> np.ndarray:
+        """Geocentric state [..., 6] of the Moon at times t [...]: the
+        position on the mean ellipse and its exact time derivative
+        (motion in mean anomaly plus the turning node and perigee)."""
+        t = np.asarray(t, float)
+        o = _MOON_ORBIT
+        mu = GM_EARTH + GM_MOON
+        node = np.radians(o["node0"] + o["nodedot"] * t)
+        varpi = np.radians(o["peri0"] + o["peridot"] * t)
+        M = np.radians(o["L0"] + o["Ldot"] * t) - varpi
+        st = elements_to_state(o["a"], o["e"], math.radians(o["I"]), node, varpi - node, M, mu)
+        r, vk = st[..., :3], st[..., 3:]
+        n_kep = math.sqrt(mu / o["a"] ** 3)
+        Mdot = math.radians(o["Ldot"] - o["peridot"])
+        Odot = math.radians(o["nodedot"])
+        wdot = math.radians(o["peridot"] - o["nodedot"])
+        h = np.cross(r, vk)
+        h /= np.linalg.norm(h, axis=-1, keepdims=True)
+        zr = np.stack([-r[..., 1], r[..., 0], np.zeros_like(r[..., 0])], axis=-1)     # z x r
+        v = vk * (Mdot / n_kep) + Odot * zr + wdot * np.cross(h, r)
+        return np.concatenate([r, v], axis=-1)
 
     def bary(self, t: np.ndarray) -> np.ndarray:
         """Barycentric states [..., n_body, 6]; body 0 is the Sun."""
         h = self.helio(t)
-        m = self.gm[1:] / self.gm.sum()
+        m = self.msys / (GM_SUN + self.msys.sum())
         sun = -(m[:, None] * h).sum(axis=-2)
-        return np.concatenate([sun[..., None, :], sun[..., None, :] + h], axis=-2)
+        out = np.concatenate([sun[..., None, :], sun[..., None, :] + h], axis=-2)
+        if self.moon:
+            ie = self.names.index("earth")
+            g = self.moon_geo(t)
+            emb = out[..., ie, :].copy()
+            out[..., ie, :] = emb - (GM_MOON / (GM_EARTH + GM_MOON)) * g
+            out = np.concatenate([out, (emb + (GM_EARTH / (GM_EARTH + GM_MOON)) * g)[..., None, :]], axis=-2)
+        return out
 
     def sun(self, t):
         return self.bary(t)[..., 0, :]
@@ -213,11 +278,26 @@ def cheb_fit_matrix(degree: int) -> np.ndarray:
     return W
 
 
+def j2_rows(names: List[str]) -> Optional[np.ndarray]:
+    """[n_body, 5] J2 rows (J2, radius au, unit pole in the ecliptic
+    integration frame) of the bodies in _J2_BODIES, zero rows for the
+    others; None when no body has one."""
+    rows = np.zeros((len(names), 5))
+    for i, nm in enumerate(names):
+        if nm in _J2_BODIES:
+            j2, r_km, ra, dec = _J2_BODIES[nm]
+            ra, dec = math.radians(ra), math.radians(dec)
+            pole_eq = np.array([math.cos(dec) * math.cos(ra), math.cos(dec) * math.sin(ra), math.sin(dec)])
+            rows[i] = [j2, r_km / AU_KM, *equatorial_to_ecliptic(pole_eq)]
+    return rows if rows[:, 0].any() else None
+
+
 def make_ephemeris(model: PlanetModel, t_start: float, n_seg: int,
                    seg_days: float = SEG_DAYS, degree: int = CHEB_DEGREE,
-                   gr: bool = True) -> Ephemeris:
+                   gr: bool = True, j2: bool = True) -> Ephemeris:
     """Tabulate `model` as Chebyshev segments by interpolation at the
-    Chebyshev-Gauss nodes of every segment."""
+    Chebyshev-Gauss nodes of every segment; the Sun and Jupiter get their
+    J2 term (App. A.3) unless j2 is False."""
     x = cheb_fit_nodes(degree)
     W = cheb_fit_matrix(degree)
     seg0 = t_start + seg_days * np.arange(n_seg)
@@ -228,7 +308,8 @@ def make_ephemeris(model: PlanetModel, t_start: float, n_seg: int,
     flags = np.array([1 if (gr and nm in GR_BODIES) else 0 for nm in model.names],
                      dtype=np.uint32)
     return Ephemeris(np.ascontiguousarray(coef), model.gm.copy(), flags,
-                     float(t_start), float(seg_days), list(model.names))
+                     float(t_start), float(seg_days), list(model.names),
+                     j2_rows(list(model.names)) if j2 else None)
 
 
 def sun_only_ephemeris(t_start: float, n_seg: int, gr: bool = False,

@@ -92,6 +92,22 @@ def test_propagate_argument_errors():
     et2 = _lib.EphemT(17, et.n_seg, et.degree, 0, et.t_start, et.seg_days, 0x1000, et.gm, et.flags)
     assert L.kete_propagate_nbody(C.byref(et2), fake, 0.0, 10, tp, 2, fake, fake, None, C.byref(o), fake, 1 << 30,
                                   None) == _lib.KETE_EINVAL
+    # EINVAL: bad J2 rows (non-unit pole, zero radius, more than KETE_MAX_J2 bodies)
+    nb = e.n_body
+    for row in ([1e-3, 0.01, 0.0, 0.0, 2.0], [1e-3, 0.0, 0.0, 0.0, 1.0], [np.nan, 0.01, 0.0, 0.0, 1.0]):
+        j2 = np.zeros((nb, 5))
+        j2[0] = row
+        et3 = _lib.EphemT(nb, et.n_seg, et.degree, 0, et.t_start, et.seg_days, 0x1000, et.gm, et.flags,
+                          j2.ctypes.data_as(C.POINTER(C.c_double)))
+        assert L.kete_propagate_nbody(C.byref(et3), fake, 0.0, 10, tp, 2, fake, fake, None, C.byref(o), fake,
+                                      1 << 30, None) == _lib.KETE_EINVAL
+        assert b"j2[0]" in L.kete_last_error()
+    gm5, fl5, j25 = np.full(5, 1e-10), np.zeros(5, np.uint32), np.tile([1e-3, 0.01, 0.0, 0.0, 1.0], (5, 1))
+    many = _lib.EphemT(5, et.n_seg, et.degree, 0, et.t_start, et.seg_days, 0x1000,
+                       gm5.ctypes.data_as(C.POINTER(C.c_double)), fl5.ctypes.data_as(C.POINTER(C.c_uint32)),
+                       j25.ctypes.data_as(C.POINTER(C.c_double)))
+    assert L.kete_propagate_nbody(C.byref(many), fake, 0.0, 10, tp, 2, fake, fake, None, C.byref(o), fake, 1 << 30,
+                                  None) == _lib.KETE_EINVAL
     # EWORKSPACE
     need = L.kete_propagate_workspace_size(10, 2, C.byref(o))
     assert need > 0

@@ -104,6 +104,75 @@ def test_propagate_sun_only_one_year(torch_cuda, orc):
     assert err < 1e-10
 
 
+def test_propagate_j2_enlarged(torch_cuda, orc):
+    # Eq. A.4 (App. A.3): an oblate Sun with J2 and radius enlarged so that
+    # the term moves close-in bodies far beyond the tolerance, about a
+    # tilted pole; the post-Newtonian term on as well
+    torch, api = torch_cuda
+    rng = np.random.default_rng(31)
+    pole = rng.normal(size=3)
+    pole /= np.linalg.norm(pole)
+    eph = synth.sun_only_ephemeris(-8.0, 45, gr=True, j2=(1e-2, 0.02, pole))
+    el = synth.main_belt_elements(rng, 256)
+    el[:, 0] = rng.uniform(0.15, 0.8, 256)
+    x0 = synth.elements_to_state(*[el[:, k] for k in range(6)], synth.GM_SUN)
+    t_out = np.arange(10.0, 340.0, 15.0)
+    xg, sg, xo, so = _propagate_both(torch, api, orc, eph, x0, 0.0, t_out)
+    assert np.all(sg == 0) and np.all(so == 0)
+    err = np.max(np.abs(xg[..., :3] - xo[..., :3]))
+    xn, _ = api.propagate(api.DeviceEphemeris.from_synth(synth.sun_only_ephemeris(-8.0, 45, gr=True)),
+                          torch.as_tensor(x0).cuda(), 0.0, t_out)
+    shift = np.max(np.abs(xn.cpu().numpy()[..., :3] - xg[..., :3]))
+    _say(f"enlarged solar J2, 330 d: max |dx| vs oracle {err:.3e} au, J2 shift {shift:.3e} au")
+    assert err < 1e-10
+    assert shift > 1e-4
+
+
+def test_propagate_default_model_j2_moon(torch_cuda, orc):
+    # the default force model: Sun, planets and the Moon, the Eq. A.3 term
+    # for the Sun, Jupiter and the Earth, Eq. A.4 for the Sun and Jupiter;
+    # bodies passing close to Jupiter and to the Earth-Moon system
+    torch, api = torch_cuda
+    model = synth.PlanetModel.make()
+    assert model.names[-1] == "moon"
+    eph = synth.make_ephemeris(model, -8.0, 50)
+    assert eph.j2 is not None and eph.j2[model.names.index("jupiter"), 0] > 0
+    rng = np.random.default_rng(32)
+    st = model.bary(np.array([100.0]))[0]
+    near = []
+    # hyperbolic flybys across the offset (closest approach near `dist`),
+    # whose straight path keeps clear of the Earth and the Moon
+    ie, im = model.names.index("earth"), model.names.index("moon")
+    for nm, dist, n, speed in (("jupiter", 0.01, 24, 0.0225), ("earth", 0.003, 24, 5e-3), ("moon", 0.002, 16, 1e-2)):
+        b = st[model.names.index(nm)]
+        rows = []
+        while len(rows) < n:
+            off = rng.normal(size=3)
+            if nm == "moon":                      # start on the far side from the Earth
+                off = 0.3 * off + (b[:3] - st[ie, :3]) / np.linalg.norm(b[:3] - st[ie, :3])
+            off *= dist / np.linalg.norm(off)
+            dv = np.cross(off, rng.normal(size=3))
+            dv *= speed / np.linalg.norm(dv)
+            x = np.concatenate([b[:3] + off, b[3:] + dv])
+            clear = True
+            for k in (ie, im):
+                rel, w = x[:3] - st[k, :3], x[3:] - st[k, 3:]
+                s = max(0.0, -(rel @ w) / (w @ w))
+                clear &= np.linalg.norm(rel + s * w) > 1e-3
+            if clear:
+                rows.append(x)
+        near.append(np.array(rows))
+    near = np.concatenate(near)
+    far = synth.bodies_from_elements(model, synth.main_belt_elements(rng, 100), 100.0)
+    x0 = np.concatenate([near, far])
+    t_out = np.arange(103.0, 380.0, 12.0)
+    xg, sg, xo, so = _propagate_both(torch, api, orc, eph, x0, 100.0, t_out)
+    assert np.all(sg == 0) and np.all(so == 0)
+    err = np.max(np.abs(xg[..., :3] - xo[..., :3]))
+    _say(f"default model (10 bodies, J2, Moon), flybys of Jupiter, the Earth and the Moon: max |dx| {err:.3e} au")
+    assert err < 1e-10
+
+
 def test_propagate_tiny_config(torch_cuda, orc):
     torch, api = torch_cuda
     case = synth.tiny_case(n_obj=1000, n_frames=100)
@@ -133,7 +202,7 @@ def test_propagate_extra_perturbers(torch_cuda, orc, n_ast):
     # Sun + 8 planets + the largest asteroids as extra perturbers: 13
     # bodies, and 16, the most the ABI takes (the run-time body count path)
     torch, api = torch_cuda
-    model = synth.PlanetModel.make(synth.PLANET_NAMES + synth.ASTEROID_NAMES[:n_ast])
+    model = synth.PlanetModel.make(synth.PLANET_NAMES + synth.ASTEROID_NAMES[:n_ast], moon=False)
     assert len(model.names) == 9 + n_ast
     eph = synth.make_ephemeris(model, -8.0, 20)
     rng = np.random.default_rng(16 + n_ast)
@@ -145,8 +214,8 @@ def test_propagate_extra_perturbers(torch_cuda, orc, n_ast):
     assert ok.all()
     err = np.abs(xg[..., :3] - xo[..., :3]).max()
     # the asteroids move the bodies measurably against the planets alone
-    xp, _ = api.propagate(api.DeviceEphemeris.from_synth(synth.make_ephemeris(synth.PlanetModel.make(), -8.0, 20)),
-                          _dev_x(torch, x0), 0.0, t_out)
+    xp, _ = api.propagate(api.DeviceEphemeris.from_synth(
+        synth.make_ephemeris(synth.PlanetModel.make(moon=False), -8.0, 20)), _dev_x(torch, x0), 0.0, t_out)
     shift = np.abs(xp.cpu().numpy()[..., :3] - xg[..., :3]).max()
     _say(f"{len(model.names)} perturbers, 120 d: max |dx| vs oracle {err:.3e} au, shift from the asteroids "
          f"{shift:.3e} au")

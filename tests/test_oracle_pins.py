@@ -61,13 +61,17 @@ def test_cheb_reproduces_polynomials(orc):
 def test_cheb_matches_analytic_planets(orc):
     case = synth.survey_case(n_obj=1, n_frames=0)
     rng = np.random.default_rng(1)
+    # the Moon's 27-day orbit fits degree 12 over 8 days to about 4 cm
+    # (its table is the tightest; planets stay at the rounding level)
+    tol = {"moon": (1e-12, 2e-11)}
     for t in rng.uniform(0.0, 365.0, 50):
         ref = case.model.bary(np.array(t))
         for b in range(case.ephem.n_body):
             st, p, v = orc.cheb(case.ephem, b, t)
+            tp, tv = tol.get(case.ephem.names[b], (2e-13, 1e-12))
             assert st == 0
-            assert np.max(np.abs(p - ref[b, :3])) < 2e-13
-            assert np.max(np.abs(v - ref[b, 3:])) < 1e-12
+            assert np.max(np.abs(p - ref[b, :3])) < tp
+            assert np.max(np.abs(v - ref[b, 3:])) < tv
 
 
 def test_cheb_joint_continuity_and_range(orc):
@@ -475,7 +479,9 @@ def test_stm_matches_state_finite_differences(orc):
         _, phi = orc.stm(case.ephem, s, 0.0, 40.0)
         fd = np.zeros((6, 6))
         for c in range(6):
-            h = 1e-7 if c < 3 else 1e-9
+            # steps well above the noise of the adaptive step control (1e-7 au
+            # and 1e-9 au/day sat at the tolerance) and well below curvature
+            h = 1e-6 if c < 3 else 1e-8
             sp = s.copy(); sp[c] += h
             sm = s.copy(); sm[c] -= h
             xp, _, _ = orc.propagate(case.ephem, sp[None], 0.0, [40.0], h_max=0.5)
