@@ -8,9 +8,11 @@ One step is the whole path over one workload:
 Inputs are resident in device memory before the timed region.
 
 The headline workload is the full-scale one: 750,000 bodies (95% main
-belt, 5% NEO-like), Sun + 8 planets as 8-day degree-12 Chebyshev segments,
-one year, 2,000,000 ground footprints of 7 x 7.3 deg made of 8 x 8
-sub-frames of 0.87 deg.  Its steps run one after the other on one stream.
+belt, 5% NEO-like), the default force model (Sun, 8 planets and the Moon
+as 8-day degree-12 Chebyshev segments; the post-Newtonian term of the Sun,
+Jupiter and the Earth; the J2 term of the Sun and Jupiter), one year,
+2,000,000 ground footprints of 7 x 7.3 deg made of 8 x 8 sub-frames of
+0.87 deg.  Its steps run one after the other on one stream.
 The survey workload (100,000 bodies, 500,000 frames of 0.78 deg) is a
 component; its steps alternate between two streams so that one step's
 integrator overlaps the previous step's field-of-view kernels (stated in
@@ -54,25 +56,32 @@ PREDICT_FLOPS = 7 * (2 + 7 + 7 + 7 * 10) + 1
 DENSE_FLOPS = 6 * (7 * 2 + 4) + (14 * 17 + 8) // 9
 
 
-def node_flops(n_body: int, n_gr: int) -> int:
+def force_flops(n_body: int, n_gr: int, n_j2: int) -> int:
+    """One force evaluation: per body the Newtonian term, the Eq. A.3 term
+    for n_gr of them and the Eq. A.4 term for n_j2 of them (offset, its
+    inverse norm, pole component, the two coefficients, three FMAs)."""
+    return 18 * n_body + 27 * n_gr + 45 * n_j2
+
+
+def node_flops(n_body: int, n_gr: int, n_j2: int = 0) -> int:
     """Predictor and force at one collocation node of one body."""
     pred_x = 3 * (1 + 14 + 4) + 1          # half_s2 F0 + 7 FMA + 2 FMA, s h
     pred_v = 3 * (1 + 14 + 2) if n_gr else 0
-    force = 18 * n_body + 27 * n_gr        # per-body Newtonian and Eq. A.3 terms
-    return pred_x + pred_v + force + 3     # + D update
+    return pred_x + pred_v + force_flops(n_body, n_gr, n_j2) + 3     # + D update
 
 
-def sweep_flops(n_body: int, n_gr: int) -> int:
+def sweep_flops(n_body: int, n_gr: int, n_j2: int = 0) -> int:
     """One corrector sweep of one body: 7 nodes plus b6 and the test."""
-    return 7 * node_flops(n_body, n_gr) + 3 * 14 + 12
+    return 7 * node_flops(n_body, n_gr, n_j2) + 3 * 14 + 12
 
 
-def step_flops(n_body: int, n_gr: int) -> int:
+def step_flops(n_body: int, n_gr: int, n_j2: int = 0) -> int:
     """Step end of one body: position and velocity sums, force, control."""
-    return 3 * (1 + 28 + 4 + 2) + (18 * n_body + 27 * n_gr) + 10
+    return 3 * (1 + 28 + 4 + 2) + force_flops(n_body, n_gr, n_j2) + 10
 
 
-def algorithmic_flops(counts: dict, n_obj: int, span: float, n_body: int, n_gr: int, n_epochs: int) -> float:
+def algorithmic_flops(counts: dict, n_obj: int, span: float, n_body: int, n_gr: int, n_epochs: int,
+                      n_j2: int = 0) -> float:
     """FP64 flops of the method for n_obj bodies over `span` days: the
     oracle's natural steps, sweeps and extrapolated starts per body-day
     (each body integrated alone), weighted per operation, plus the epochs
@@ -80,20 +89,20 @@ def algorithmic_flops(counts: dict, n_obj: int, span: float, n_body: int, n_gr: 
     a wavefront evaluates it once for its bodies."""
     c = counts["extrapolated_start"]
     body_days = n_obj * span
-    return (body_days * (c["steps_per_body_day"] * step_flops(n_body, n_gr)
-                         + c["sweeps_per_body_day"] * sweep_flops(n_body, n_gr)
+    return (body_days * (c["steps_per_body_day"] * step_flops(n_body, n_gr, n_j2)
+                         + c["sweeps_per_body_day"] * sweep_flops(n_body, n_gr, n_j2)
                          + c["extrapolated_starts_per_body_day"] * PREDICT_FLOPS)
             + max(n_epochs - 1, 0) * n_obj * DENSE_FLOPS)
 
 
-def executed_flops(stats, n_body: int, n_gr: int, deg1: int, dense_epochs: int) -> float:
+def executed_flops(stats, n_body: int, n_gr: int, deg1: int, dense_epochs: int, n_j2: int = 0) -> float:
     """FP64 flops the kernel executes by its own counters: stats = [wave
     steps, wave sweeps, rejections, body-steps, body-sweeps, Clenshaw
     chains with derivative, value-only chains, body-steps started from an
     extrapolated corrector]."""
     lane_steps, lane_iter, chains, vchains = float(stats[3]), float(stats[4]), float(stats[5]), float(stats[6])
     pred = float(stats[7]) if len(stats) > 7 else 0.0
-    return (lane_iter * sweep_flops(n_body, n_gr) + lane_steps * step_flops(n_body, n_gr)
+    return (lane_iter * sweep_flops(n_body, n_gr, n_j2) + lane_steps * step_flops(n_body, n_gr, n_j2)
             + chains * CLENSHAW_CHAIN_FLOPS(deg1) + vchains * CLENSHAW_VALUE_FLOPS(deg1)
             + pred * PREDICT_FLOPS + dense_epochs * DENSE_FLOPS)
 
@@ -133,16 +142,25 @@ def cpu_model() -> str:
     return platform.processor() or "unknown"
 
 
+def force_model_name(eph) -> str:
+    names = list(eph.names)
+    planets = [n for n in names if n not in ("sun", "moon")]
+    j2 = [] if eph.j2 is None else [names[i].capitalize() for i in np.nonzero(eph.j2[:, 0])[0]]
+    return ("Sun + %d planets%s as %g-day degree-%d Chebyshev segments, J2 of %s"
+            % (len(planets), " + Moon" if "moon" in names else "", eph.seg_days, eph.degree,
+               " and ".join(j2) if j2 else "none"))
+
+
 def workload_name(case) -> str:
     fr = case.frames
     if case.name == "footprint":
-        return ("full-scale footprints: %d bodies (95%% main belt, 5%% NEO-like), Sun + 8 planets as 8-day "
-                "degree-12 Chebyshev segments, %.2f days, %d ground footprints of 7 x 7.3 deg in %d sub-frames "
-                "of 0.87 deg, six sites at latitude 33 deg, 30 s exposures in 8 h nights"
-                % (case.x0.shape[0], case.span, fr.n_frames, fr.n_sub))
-    return ("survey: %d bodies (95%% main belt, 5%% NEO-like), Sun + 8 planets as 8-day degree-12 Chebyshev "
-            "segments, %.2f days, %d frames of 0.78 deg in 11 s sequences of 12 from a 1 au orbit with a "
-            "7,000 km offset orbit" % (case.x0.shape[0], case.span, fr.n_frames))
+        return ("full-scale footprints: %d bodies (95%% main belt, 5%% NEO-like), %s, %.2f days, %d ground "
+                "footprints of 7 x 7.3 deg in %d sub-frames of 0.87 deg, six sites at latitude 33 deg, 30 s "
+                "exposures in 8 h nights"
+                % (case.x0.shape[0], force_model_name(case.ephem), case.span, fr.n_frames, fr.n_sub))
+    return ("survey: %d bodies (95%% main belt, 5%% NEO-like), %s, %.2f days, %d frames of 0.78 deg in 11 s "
+            "sequences of 12 from a 1 au orbit with a 7,000 km offset orbit"
+            % (case.x0.shape[0], force_model_name(case.ephem), case.span, fr.n_frames))
 
 
 class Workload:
@@ -166,6 +184,7 @@ class Workload:
         self.order, self.off, self.t_ref = order, off, t_ref
         self.B = t_ref.size
         self.n_gr = int(np.sum(case.ephem.flags & 1))
+        self.n_j2 = 0 if case.ephem.j2 is None else int(np.count_nonzero(case.ephem.j2[:, 0]))
         # learn the pair count once, then size the pair buffers to it
         b = api.Batches.from_host(order, off, t_ref, dev)
         x, st = api.propagate(self.eph, self.x0, case.t0, t_ref, self.opts)
@@ -264,8 +283,9 @@ class Workload:
         ms_step = elapsed * 1e3 / steps
         obj_days = N * case.span
         alg = algorithmic_flops(oracle_counts("survey" if case.name == "survey" else "footprints"), N, case.span,
-                                eph.n_body, self.n_gr, B)
-        exe = executed_flops(st, eph.n_body, self.n_gr, eph.degree + 1, (B - 1) * N * int(cnt[0])) / max(cnt[0], 1)
+                                eph.n_body, self.n_gr, B, self.n_j2)
+        exe = executed_flops(st, eph.n_body, self.n_gr, eph.degree + 1, (B - 1) * N * int(cnt[0]),
+                             self.n_j2) / max(cnt[0], 1)
         t_int = ms[0] / max(cnt[0], 1) / 1e3
         t_int_iso = ms_iso[0] / max(cnt_iso[0], 1) / 1e3
         fov_ms = ms[1] / steps
@@ -416,7 +436,8 @@ def adjoint_component(api, synth, torch, n_obj, log, reps=10):
     t_b = (time.perf_counter() - t0) / reps
     n_fail = int((ctx.status != 0).sum().item())
     return {
-        "workload": f"{n_obj} bodies x 20 observations over 60 days, Sun + 8 planets, checkpoints every 5 days",
+        "workload": f"{n_obj} bodies x 20 observations over 60 days, {force_model_name(g.ephem)}, "
+                    "checkpoints every 5 days",
         "forward_ms": t_f * 1e3, "backward_ms": t_b * 1e3, "backward_over_forward": t_b / t_f,
         "gradient_over_forward": (t_f + t_b) / t_f,
         "forward_object_days_per_s": n_obj * 60.0 / t_f, "failed_objects": n_fail,
