@@ -208,8 +208,9 @@ size_t kete_propagate_workspace_size(int64_t n_obj, int64_t n_out, const kete_op
 /* n-body propagation of massless bodies (Sect. 2, App. A): every object
  * starts at the common epoch t0 and is integrated through the epochs
  * t_out[0..n_out) (strictly monotone, all after t0 or all before t0),
- * their states at each.  Force: Eq. A.1 (attractive) plus Eq. A.3 for
- * bodies with flags bit0 and Eq. A.4 (App. A.3) for bodies given a J2.
+ * and its state at each epoch is written.  Force: Eq. A.1 (attractive)
+ * plus Eq. A.3 for bodies with flags bit0 and Eq. A.4 (App. A.3) for
+ * bodies given a J2.
  * Integrator: Gauss-Radau collocation with 8 nodes (the method of
  * App. A.6, predictor removed), IAS15 step control.  By default 7 lanes
  * share an object's force sums and the 9 objects of a wavefront share its
