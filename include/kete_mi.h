@@ -4,7 +4,7 @@
  * The path follows Sect. 2 of "Kete: Predicting Known Minor Bodies in
  * Images" (arXiv 2509.04666): frames are grouped into time batches; the
  * small bodies are integrated with the n-body force model (App. A, Eqs.
- * A.1 and A.3, perturbers read from Chebyshev segments as in Sect. 3.2) to
+ * A.1, A.3 and A.4, perturbers read from Chebyshev segments as in Sect. 3.2) to
  * the mid time of every batch; inside a batch each body is moved by
  * two-body motion with a light-delay correction to every frame; a body is
  * in a frame when every inward great-circle normal of the frame has a
