@@ -856,6 +856,40 @@ __global__ __launch_bounds__(256, kJoinWaves) void k_fov_cells(const FovParams p
         o.taumax = o.vbn = o.a2b = 0.0;
         o.lin_ok = false;
         const bool live = has && object_bounds(p, b, j, o);
+        if (__ballot(live) == 0ull) continue;
+        // A cap around every live object's motion cap: centre ic the
+        // normalized sum of their directions, cos of the radius the least
+        // cos(A + theta) over them (A the angle of the object's direction
+        // from ic, its sine from the cross product).  A frame whose cap
+        // misses it can reach none of the item's objects.  Usable when
+        // every A + theta stays below 90 degrees (else every frame is kept).
+        double ic[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double v = live ? o.dh[c] : 0.0;
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+            ic[c] = v;
+        }
+        bool item_cap = false;
+        double icr = -1.0, isr = 1.0;        // cos and sin of the item cap's radius
+        {
+            const double in = sqrt(dot3(ic, ic));
+            if (in > 0.0) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) ic[c] /= in;
+                double cA = 2.0;
+                if (live) {
+                    double cx[3];
+                    cross3(ic, o.dh, cx);
+                    const double ca = dot3(ic, o.dh), sa = sqrt(dot3(cx, cx));
+                    cA = ca > 0.0 ? ca * o.cth - sa * o.sth : -2.0;
+                }
+                icr = wave_min(cA) - 1e-12;
+                item_cap = icr > 0.0;
+                isr = sqrt(fmax(0.0, 1.0 - icr * icr));
+            }
+        }
         // global object index; bit 63 set: no linear test
         const unsigned long long gtag = (unsigned long long)(p.b_obj0[b] + j) | (o.lin_ok ? 0ull : (1ull << 63));
         wave_lds_sync();                      // the previous item's queue is done
@@ -885,21 +919,30 @@ __global__ __launch_bounds__(256, kJoinWaves) void k_fov_cells(const FovParams p
             int nc = 0;
             for (int t = 1; t < 27; ++t) nc = (__shfl(excl, t, kWave) <= g) ? t : nc;
             const int rk = __shfl(my_a0, nc, kWave) + (g - __shfl(excl, nc, kWave));
-            // the chunk's frame records go to LDS and are read back as
-            // broadcasts
+            // the chunk's frame records that can meet the item's cap go to
+            // LDS, packed, and are read back as broadcasts
             FrameRec rec = {{0.0, 0.0, 0.0}, 2.0, 0.0, 0.0, 0.0, {0.0, 0.0, 0.0}};
+            bool keep = false;
             if (g < total) {
                 const double* cp = caps + 8 * (int64_t)rk;
                 const double2 c01 = *reinterpret_cast<const double2*>(cp);
                 const double2 c23 = *reinterpret_cast<const double2*>(cp + 2);
-                const double2* ob = reinterpret_cast<const double2*>(p.cell_obs + 4 * (int64_t)rk);
-                const double2 o01 = ob[0], o23 = ob[1];
-                rec = {{c01.x, c01.y, c23.x}, c23.y, cp[4], (double)rk, o01.x, {o01.y, o23.x, o23.y}};
+                const double sr = cp[4];
+                // cos of the angle between the caps' centres against
+                // cos(R_item + R_f); frames of 90 degrees or more are kept
+                keep = !item_cap || !(c23.y > 0.0) ||
+                       !(c01.x * ic[0] + c01.y * ic[1] + c23.x * ic[2] < icr * c23.y - isr * sr - 1e-12);
+                if (keep) {
+                    const double2* ob = reinterpret_cast<const double2*>(p.cell_obs + 4 * (int64_t)rk);
+                    const double2 o01 = ob[0], o23 = ob[1];
+                    rec = {{c01.x, c01.y, c23.x}, c23.y, sr, (double)rk, o01.x, {o01.y, o23.x, o23.y}};
+                }
             }
+            const unsigned long long kmask = __ballot(keep);
             wave_lds_sync();                  // the previous chunk's records are read
-            fcap[lane] = rec;
+            if (keep) fcap[__popcll(kmask & lt)] = rec;
             wave_lds_sync();
-            const int n = min(kWave, total - g0);
+            const int n = __popcll(kmask);
             n_visit += (unsigned long long)n;
             for (int m = 0; m < n; ++m) {
                 const FrameRec cm = fcap[m];
