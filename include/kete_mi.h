@@ -93,7 +93,7 @@ typedef struct {
     double c_light;          /* speed of light in au/day (173.144632674...) */
     double batch_span;       /* frame batch span in days (3.0, Sect. 2) */
     double cell_chord;       /* FoV sky-grid cell size (chord units; 0 = auto: 0.10) */
-    double lt_tol;           /* light-time convergence in days (1e-15) */
+    double lt_tol;           /* light-time convergence: last update in days (1e-15) */
     int32_t max_steps;       /* per object per call (2,000,000) */
     int32_t max_iter;        /* corrector iterations per step (12) */
     int32_t n_buckets;       /* step-size buckets (octaves of the predicted step), 1 = none (16) */
@@ -105,7 +105,7 @@ typedef struct {
                                 integrators reading epochs off the step polynomials the most, up
                                 to 6, with which three blocks share a compute unit's LDS; for the
                                 adjoint 3; else 2) */
-    int32_t lt_iter;         /* light-time iterations (10) */
+    int32_t lt_iter;         /* light-time updates at most (10) */
     int32_t fov_block;       /* FoV threads per block: 64/128/256 (128) */
     int32_t adj_seg_steps;   /* adjoint: steps stored per checkpoint segment (32) */
     int32_t persist_waves;   /* batched runs: resident waves per compute unit (8) */

@@ -139,6 +139,93 @@ __device__ __forceinline__ void cheb_body(const double* __restrict__ tab, int se
     }
 }
 
+// A body's motion near one time t0 as a cubic in t - t0: position,
+// velocity, acceleration and jerk of its Chebyshev segment at t0 (the
+// segment's polynomial differentiated three times).  Over a light time of
+// a fraction of a day it differs from the segment's own value by the
+// fourth-order term, |x''''| tau^4 / 24, which for the Sun's barycentric
+// wobble is about 1e-18 au: far below the fit error of the ephemeris.  Its
+// evaluations load nothing, so a light-time loop that takes the Sun from it
+// waits on no memory between hops.
+struct SunCubic {
+    double t0, s[3], v[3], a[3], j[3];
+    __device__ __forceinline__ void eval(double t, double pos[3], double vel[3]) const {
+        const double h = t - t0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            pos[i] = fma(h, fma(h, fma(h, j[i] * (1.0 / 6.0), 0.5 * a[i]), v[i]), s[i]);
+            vel[i] = fma(h, fma(h, 0.5 * j[i], a[i]), v[i]);
+        }
+    }
+};
+
+// The cubic of one body row of a segment table (layout as cheb_body) at t.
+// T_n and its first three derivatives follow the Chebyshev recurrence
+// T_{n+1} = 2x T_n - T_{n-1} differentiated:
+//   T'_{n+1}   = 2 T_n   + 2x T'_n   - T'_{n-1}
+//   T''_{n+1}  = 4 T'_n  + 2x T''_n  - T''_{n-1}
+//   T'''_{n+1} = 6 T''_n + 2x T'''_n - T'''_{n-1}.
+// Terms n >= 2 go in chunks of kChunk: a chunk's coefficient loads (all
+// three coordinates) are issued together, and only one chunk is held in
+// registers at a time.
+__device__ __forceinline__ SunCubic sun_cubic(const double* __restrict__ tab, int seg_base, int deg1, double t,
+                                              double t_start, double seg_days, double inv_seg, int lo, int hi) {
+    constexpr int kChunk = 7;
+    static_assert((KETE_MAX_DEGREE - 1) % kChunk == 0, "terms 2..KETE_MAX_DEGREE split into whole chunks");
+    const int k = seg_index(t, t_start, inv_seg, lo, hi);
+    const double x = 2.0 * (t - (t_start + (double)k * seg_days)) * inv_seg - 1.0;
+    const double* c = tab + (size_t)(k - seg_base) * 3 * deg1;
+    const double x2 = x + x;
+    double p[3], d1[3], d2[3], d3[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const double c0 = c[i * deg1];
+        const double c1 = deg1 > 1 ? c[i * deg1 + 1] : 0.0;
+        p[i] = fma(c1, x, c0);
+        d1[i] = c1;
+        d2[i] = 0.0;
+        d3[i] = 0.0;
+    }
+    double t_a = 1.0, t_b = x;                      // T_{n-2}, T_{n-1}
+    double u_a = 0.0, u_b = 1.0;                    // T'
+    double w_a = 0.0, w_b = 0.0;                    // T''
+    double z_a = 0.0, z_b = 0.0;                    // T'''
+#pragma unroll 1
+    for (int n0 = 2; n0 < deg1; n0 += kChunk) {
+        double cc[3][kChunk];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int m = 0; m < kChunk; ++m) cc[i][m] = n0 + m < deg1 ? c[i * deg1 + n0 + m] : 0.0;
+#pragma unroll
+        for (int m = 0; m < kChunk; ++m) {
+            const double tn = fma(x2, t_b, -t_a);
+            const double un = fma(x2, u_b, fma(2.0, t_b, -u_a));
+            const double wn = fma(x2, w_b, fma(4.0, u_b, -w_a));
+            const double zn = fma(x2, z_b, fma(6.0, w_b, -z_a));
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                p[i] = fma(cc[i][m], tn, p[i]);
+                d1[i] = fma(cc[i][m], un, d1[i]);
+                d2[i] = fma(cc[i][m], wn, d2[i]);
+                d3[i] = fma(cc[i][m], zn, d3[i]);
+            }
+            t_a = t_b; t_b = tn; u_a = u_b; u_b = un; w_a = w_b; w_b = wn; z_a = z_b; z_b = zn;
+        }
+    }
+    const double sc = 2.0 * inv_seg;
+    SunCubic S;
+    S.t0 = t;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        S.s[i] = p[i];
+        S.v[i] = d1[i] * sc;
+        S.a[i] = d2[i] * (sc * sc);
+        S.j[i] = d3[i] * (sc * sc * sc);
+    }
+    return S;
+}
+
 // Stumpff functions c0..c3 of z: series on |z| <= 0.1 after quartering
 // the argument, then c_k(4z) from c_k(z):
 //   c0' = 2 c0^2 - 1, c1' = c0 c1, c2' = c1^2 / 2, c3' = (c2 + c0 c3) / 4.
@@ -289,8 +376,16 @@ struct SunTable {
 // Light-time corrected direction of a body from an observer (Newtonian,
 // barycentric frame, no aberration): heliocentric state (r0, v0) at t_ref,
 // emission point x_e = S(t_obs - tau) + hop(r0, v0, t_obs - tau - t_ref),
-// tau = |x_e - o| / c, iterated until the update is at most lt_tol.
-// Outputs d = x_e - o, tau and the barycentric emission velocity.  Returns
+// tau the root of h(tau) = |x_e - o| / c - tau.  The first guess takes the
+// body along its epoch velocity in a straight line to t_obs; each hop then
+// gives h and its slope h' = -(1 + u.v_e / c) (u the unit direction, v_e
+// the barycentric emission velocity), and Newton's update -h / h' is taken
+// until it is at most lt_tol (at most lt_iter updates).  The fixed point is
+// the one the plain iteration tau <- |x_e - o| / c reaches; Newton reaches
+// it in two or three hops where the plain iteration from zero takes six,
+// since its error shrinks quadratically instead of by |v_e| / c a hop.
+// Outputs d = x_e - o, the tau of that last hop (so that |d| / c - tau is
+// within lt_tol) and the barycentric emission velocity.  Returns
 // KETE_ST_KEPLER_NOCONV when any of its hops ended on the iteration cap
 // kepler_iter without converging, else 0.
 template <class SunT>
@@ -301,25 +396,26 @@ __device__ __forceinline__ int lighttime(const SunT& sun, double mu, double smu,
                                          double* chi_out = nullptr, int kepler_iter = kKeplerIterDefault) {
     double Se[3], Sde[3], r[3], v[3];
     double chi = __builtin_nan("");
-    // first guess: straight line from the epoch state
-    tau = 0.0;
+    {
+        sun.eval(t_obs, Se, Sde);
+        const double dt = t_obs - t_ref;
+        for (int i = 0; i < 3; ++i) d[i] = Se[i] + r0[i] + v0[i] * dt - o[i];
+        tau = sqrt(dot3(d, d)) / c_light;
+    }
     int st = 0;
-    for (int k = 0; k <= lt_iter; ++k) {
-        double te = t_obs - tau;
+    for (int k = 0;; ++k) {
+        const double te = t_obs - tau;
         st |= kepler_uv(mu, smu, r0, v0, te - t_ref, chi, r, v, kepler_iter);
         sun.eval(te, Se, Sde);
-        for (int i = 0; i < 3; ++i) d[i] = Se[i] + r[i] - o[i];
-        double tn = sqrt(dot3(d, d)) / c_light;
-        double dtau = tn - tau;
-        tau = tn;
-        if (fabs(dtau) <= lt_tol) break;
-    }
-    double te = t_obs - tau;
-    st |= kepler_uv(mu, smu, r0, v0, te - t_ref, chi, r, v, kepler_iter);
-    sun.eval(te, Se, Sde);
-    for (int i = 0; i < 3; ++i) {
-        d[i] = Se[i] + r[i] - o[i];
-        ve[i] = Sde[i] + v[i];
+        for (int i = 0; i < 3; ++i) {
+            d[i] = Se[i] + r[i] - o[i];
+            ve[i] = Sde[i] + v[i];
+        }
+        if (k == lt_iter) break;
+        const double dn = sqrt(dot3(d, d));
+        const double step = (dn / c_light - tau) / (1.0 + dot3(d, ve) / (dn * c_light));
+        if (fabs(step) <= lt_tol) break;
+        tau += step;
     }
     if (chi_out) *chi_out = chi;
     return st;

@@ -317,15 +317,6 @@ __global__ void k_frame_scatter(const FovParams p, const int32_t* __restrict__ q
     dst[6] = dst[7] = 0.0;
 }
 
-struct SunLds {
-    const double* tab;
-    int lo, hi, deg1;
-    double t_start, seg_days, inv_seg;
-    __device__ __forceinline__ void eval(double t, double pos[3], double vel[3]) const {
-        cheb_body(tab, lo, deg1, t, t_start, seg_days, inv_seg, lo, hi, pos, vel);
-    }
-};
-
 // Append a key to a bounded list with one atomic per wavefront: the
 // active lanes take consecutive slots in lane order (ballot + popcount).
 __device__ __forceinline__ void wave_append(unsigned long long* list, unsigned long long* count, int64_t cap,
@@ -1286,45 +1277,113 @@ __global__ void k_obj_scatter(const FovParams p, const int32_t* __restrict__ oke
     sorted[start[key] + orank[i]] = (int32_t)(i - p.b_poff[b]);
 }
 
+// One exact-test record per frame (layout at FovParams::exact_rec), so
+// that a candidate reaches everything its frame contributes in one round
+// of loads and the light-time loop takes the Sun from a cubic.
+__global__ void k_frame_exact_rec(const FovParams p) {
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= p.n_frames) return;
+    double* R = p.exact_rec + (size_t)kExactRec * f;
+    const int b = p.frame_batch[f];
+    if (b < 0 || b >= p.n_batch) {
+        for (int k = 0; k < kExactRec; ++k) R[k] = 0.0;
+        return;
+    }
+    const EphemArgs& E = p.eph;
+    const double tf = p.ft[f];
+    const double* bt = p.btab + kBatchStride * b;
+    const SunCubic S = sun_cubic(E.coef, 0, E.deg1, tf, E.t_start, E.seg_days, E.inv_seg, 0, E.n_seg - 1);
+    R[0] = tf;
+    R[1] = p.t_ref[b];
+    for (int k = 0; k < 3; ++k) {
+        R[2 + k] = p.fobs[3 * f + k];
+        R[5 + k] = bt[k];
+        R[8 + k] = bt[3 + k];
+        R[12 + k] = S.s[k];
+        R[15 + k] = S.v[k];
+        R[18 + k] = S.a[k];
+        R[21 + k] = S.j[k];
+    }
+    R[11] = __longlong_as_double((long long)(p.b_xoff[b] - 6 * (int64_t)p.b_obj0[b]));
+}
+
 // Exact test of every candidate (one lane per candidate, grid-stride): the
 // candidate's sub-frame, or every sub-frame of its frame for kAllSubs.
-__global__ __launch_bounds__(256) void k_fov_exact(const FovParams p) {
+// Each wavefront runs the same trips (lanes past the end idle), reads the
+// next trip's candidate key ahead, and stages its pairs in LDS so that the
+// shared pair counter takes one atomic per kPairBufEntries - 63 or more
+// pairs.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_fov_exact(const FovParams p) {
+    __shared__ unsigned long long s_buf[4][kPairBufEntries];
+    unsigned long long* buf = s_buf[threadIdx.x >> 6];
+    int nbuf = 0;
     const unsigned long long nc = *p.n_cand;
     const unsigned long long n = nc < (unsigned long long)p.cand_cap ? nc : (unsigned long long)p.cand_cap;
-    const EphemArgs& E = p.eph;
-    const SunLds sun{E.coef, 0, E.n_seg - 1, E.deg1, E.t_start, E.seg_days, E.inv_seg};
-    for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (unsigned long long)gridDim.x * blockDim.x) {
-        const unsigned long long c = p.cand[i];
+    const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+    const unsigned long long w0 = (unsigned long long)blockIdx.x * blockDim.x + (threadIdx.x & ~63u);
+    unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long c_next = i < n ? p.cand[i] : 0ull;
+    for (unsigned long long w = w0; w < n; w += stride, i += stride) {
+        const bool valid = i < n;
+        const unsigned long long c = c_next;
+        c_next = i + stride < n ? p.cand[i + stride] : 0ull;
         const int f = (int)((c >> 32) & 0x7fffffffull);
         const int s0 = (int)((c >> 25) & 0x7full);
         const bool all_subs = (c & kAllSubs) != 0ull;
         const int j = (int)(c & 0x1ffffffull);              // global object
-        const int b = p.frame_batch[f];
-        const double* bt = p.btab + kBatchStride * b;
-        const double* st = p.x_epoch + p.b_xoff[b] + 6 * (int64_t)(j - p.b_obj0[b]);
-        double r0[3], v0[3];
-        for (int k = 0; k < 3; ++k) { r0[k] = st[k] - bt[k]; v0[k] = st[3 + k] - bt[3 + k]; }
-        double d[3], tau, ve[3];
-        const int kst = lighttime(sun, p.mu, p.smu, p.c_light, p.lt_tol, p.lt_iter, p.t_ref[b], r0, v0, p.ft[f],
-                                  p.fobs + 3 * f, d, tau, ve, nullptr, p.kepler_iter);
-        if (kst) {
-            // the object fails: none of its pairs is kept (the host drops
-            // those already appended by other candidates)
-            p.fail[j] = 1;
-            if (p.status_out) p.status_out[j] = KETE_ST_KEPLER_NOCONV;
-            atomicAdd(p.n_fail, 1ull);
-            continue;
+        bool ok = false;
+        double d[3] = {0.0, 0.0, 0.0};
+        if (valid) {
+            const double2* R = reinterpret_cast<const double2*>(p.exact_rec + (size_t)kExactRec * f);
+            double r[kExactRec];
+#pragma unroll
+            for (int k = 0; k < kExactRec / 2; ++k) {
+                const double2 q = R[k];
+                r[2 * k] = q.x;
+                r[2 * k + 1] = q.y;
+            }
+            const double* st = p.x_epoch + __double_as_longlong(r[11]) + 6 * (int64_t)j;
+            double r0[3], v0[3];
+            for (int k = 0; k < 3; ++k) { r0[k] = st[k] - r[5 + k]; v0[k] = st[3 + k] - r[8 + k]; }
+            SunCubic sun;
+            sun.t0 = r[0];
+            for (int k = 0; k < 3; ++k) {
+                sun.s[k] = r[12 + k];
+                sun.v[k] = r[15 + k];
+                sun.a[k] = r[18 + k];
+                sun.j[k] = r[21 + k];
+            }
+            const double o[3] = {r[2], r[3], r[4]};
+            double tau, ve[3];
+            const int kst = lighttime(sun, p.mu, p.smu, p.c_light, p.lt_tol, p.lt_iter, r[1], r0, v0, r[0], o, d,
+                                      tau, ve, nullptr, p.kepler_iter);
+            if (kst) {
+                // the object fails: none of its pairs is kept (the host
+                // drops those already appended by other candidates)
+                p.fail[j] = 1;
+                if (p.status_out) p.status_out[j] = KETE_ST_KEPLER_NOCONV;
+                atomicAdd(p.n_fail, 1ull);
+            }
+            ok = kst == 0;
         }
+        // sub-frame tests: one trip for single sub-frames, n_sub when a lane
+        // of the wavefront tests a whole frame
+        const int trips = __ballot(ok && all_subs) != 0ull ? p.n_sub : (__ballot(ok) != 0ull ? 1 : 0);
         const double* nrm = p.normals + (size_t)f * p.n_sub * 12;
-        const int s_end = all_subs ? p.n_sub : s0 + 1;
-        for (int s = all_subs ? 0 : s0; s < s_end; ++s) {
-            const double* ns = nrm + 12 * s;
-            if (dot3(ns, d) > 0.0 && dot3(ns + 3, d) > 0.0 && dot3(ns + 6, d) > 0.0 && dot3(ns + 9, d) > 0.0)
-                wave_append(p.pairs, p.n_pairs, p.cap,
-                            ((unsigned long long)f << 32) | ((unsigned long long)s << 25) | (unsigned long long)j);
+        for (int t = 0; t < trips; ++t) {
+            const int s = all_subs ? t : s0;
+            bool in = false;
+            if (ok && (all_subs || t == 0)) {
+                const double* ns = nrm + 12 * s;
+                in = dot3(ns, d) > 0.0 && dot3(ns + 3, d) > 0.0 && dot3(ns + 6, d) > 0.0 && dot3(ns + 9, d) > 0.0;
+            }
+            buf_append<kPairBufEntries>(buf, nbuf, in,
+                                        ((unsigned long long)f << 32) | ((unsigned long long)s << 25) |
+                                            (unsigned long long)j,
+                                        p.pairs, p.n_pairs, p.cap);
         }
     }
+    buf_flush(buf, nbuf, p.pairs, p.n_pairs, p.cap);
 }
 
 // ---------------------------------------------------------------- sort
@@ -1648,7 +1707,7 @@ __global__ void k_fill_zero(unsigned int* __restrict__ p, size_t n_words) {
 }
 
 // ---------------------------------------------------------------- checks
-__global__ void k_directions(const FovParams p, const double* __restrict__ x_ref, double t_ref,
+__global__ __launch_bounds__(128) void k_directions(const FovParams p, const double* __restrict__ x_ref, double t_ref,
                              const double* __restrict__ t_obs, const double* __restrict__ obs, int64_t n_q,
                              double* __restrict__ d_out, double* __restrict__ tau_out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1661,8 +1720,9 @@ __global__ void k_directions(const FovParams p, const double* __restrict__ x_ref
     const double* st = x_ref + 6 * j;
     double r0[3] = {st[0] - S[0], st[1] - S[1], st[2] - S[2]};
     double v0[3] = {st[3] - Sd[0], st[4] - Sd[1], st[5] - Sd[2]};
+    const SunCubic sun_e = sun_cubic(E.coef, 0, E.deg1, t_obs[qn], E.t_start, E.seg_days, E.inv_seg, 0, E.n_seg - 1);
     double d[3], tau, ve[3];
-    const int kst = lighttime(sun, p.mu, p.smu, p.c_light, p.lt_tol, p.lt_iter, t_ref, r0, v0, t_obs[qn],
+    const int kst = lighttime(sun_e, p.mu, p.smu, p.c_light, p.lt_tol, p.lt_iter, t_ref, r0, v0, t_obs[qn],
                               obs + 3 * qn, d, tau, ve, nullptr, p.kepler_iter);
     // a hop that ended on the Kepler iteration cap gives NaN
     for (int c = 0; c < 3; ++c) d_out[3 * i + c] = kst ? __builtin_nan("") : d[c];
@@ -1765,6 +1825,8 @@ hipError_t fov_candidates(FovParams& p, int32_t* icnt, int32_t* istart, unsigned
 }
 
 hipError_t fov_exact(const FovParams& p, hipStream_t s) {
+    if (p.n_frames > 0)
+        hipLaunchKernelGGL(k_frame_exact_rec, dim3((unsigned)((p.n_frames + 255) / 256)), dim3(256), 0, s, p);
     hipLaunchKernelGGL(k_fov_exact, dim3((unsigned)(cu_count() * 16)), dim3(256), 0, s, p);
     return hipGetLastError();
 }

@@ -6,6 +6,7 @@
 namespace kete {
 
 constexpr int kBatchStride = 17;        // doubles per batch record
+constexpr int kExactRec = 24;           // doubles per exact-test frame record
 constexpr double kMaxLightDays = 1.0;   // light time covered by the staged window
 
 // Sub-frame locator of a frame with several sub-frames: a tangent basis at
@@ -50,6 +51,12 @@ struct FovParams {
     // position, and the sub-frame normals.
     double* cell_obs;           // [F][4]: t, observer x, y, z
     double* cell_normals;       // [F][S][4][3]
+    // What the exact test reads of a frame, by frame index, in one record
+    // (kExactRec doubles): its time, its batch's epoch, the observer, the
+    // Sun's state at the epoch, the offset of the batch's states in
+    // x_epoch (int64 bits) and the Sun's cubic about the frame time
+    // (position, velocity, acceleration, jerk).
+    double* exact_rec;          // [F][kExactRec]
     unsigned long long* pairs;  // [cap] packed (frame << 32 | sub << 25 | obj)
     unsigned long long* n_pairs;
     int64_t cap;
@@ -126,8 +133,10 @@ constexpr int kWidePartFrames = 1024;
 hipError_t fov_candidates(FovParams& p, int32_t* icnt, int32_t* istart, unsigned long long* items,
                           unsigned int* item_next, void* scan_scratch, void* wide_scan_scratch, hipStream_t s);
 inline int64_t fov_item_capacity(int64_t n_keys, int64_t n_pairs_total) { return n_keys + n_pairs_total / 64 + 1; }
-// Doubles of the cell-ordered frame copies (cell_obs, cell_normals).
-inline int64_t fov_cell_frame_doubles(int64_t n_frames, int n_sub) { return n_frames * (4 + 12 * (int64_t)n_sub); }
+// Doubles of the frame copies (cell_obs, cell_normals, exact_rec).
+inline int64_t fov_cell_frame_doubles(int64_t n_frames, int n_sub) {
+    return n_frames * (4 + 12 * (int64_t)n_sub + kExactRec);
+}
 hipError_t fov_exact(const FovParams& p, hipStream_t s);
 hipError_t fov_drop_failed(const unsigned long long* keys, int64_t n, const int32_t* fail, unsigned long long* out,
                            unsigned long long* n_out, hipStream_t s);

@@ -64,13 +64,14 @@ __global__ __launch_bounds__(256) void k_pair_mag(const MagParams p, const int32
         double d[3], tau, ve[3];
         // a hop that ends on the Kepler iteration cap gives NaN, as a pair
         // outside the ephemeris does
-        const int kst = lighttime(sun, E.gm[0], p.smu, p.c_light, p.lt_tol, p.lt_iter, tr, r0, v0, tf,
+        const SunCubic sun_e = sun_cubic(E.coef, 0, E.deg1, tf, E.t_start, E.seg_days, E.inv_seg, 0, E.n_seg - 1);
+        const int kst = lighttime(sun_e, E.gm[0], p.smu, p.c_light, p.lt_tol, p.lt_iter, tr, r0, v0, tf,
                                   p.fobs + 3 * (int64_t)f, d, tau, ve, nullptr, p.kepler_iter);
         const double te = tf - tau;
         if (kst == 0 && te >= p.t_lo && te <= p.t_hi) {
             // heliocentric emission point r = (d + o) - S(te)
             double Se[3], Sde[3];
-            sun.eval(te, Se, Sde);
+            sun_e.eval(te, Se, Sde);
             const double* o = p.fobs + 3 * (int64_t)f;
             const double r[3] = {d[0] + o[0] - Se[0], d[1] + o[1] - Se[1], d[2] + o[2] - Se[2]};
             const double c = dot3(r, d);
