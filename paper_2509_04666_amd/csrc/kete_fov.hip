@@ -34,49 +34,6 @@ __device__ __forceinline__ void cross3(const double* a, const double* b, double*
     c[2] = a[0] * b[1] - a[1] * b[0];
 }
 
-// Bounding cap of a frame: unit centre and cos/sin of the radius.  The
-// vertices of every quadrilateral are the intersections of one normal of
-// the pair (0, 1) with one of the pair (2, 3), signed to lie inside the
-// opposite edges.
-__global__ void k_frame_caps(const double* __restrict__ normals, int64_t n_frames, int n_sub,
-                             double* __restrict__ cap) {
-    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= n_frames) return;
-    double sum[3] = {0.0, 0.0, 0.0};
-    for (int s = 0; s < n_sub; ++s) {
-        const double* n = normals + ((f * n_sub + s) * 4) * 3;
-        for (int i = 0; i < 2; ++i)
-            for (int k = 2; k < 4; ++k) {
-                double v[3];
-                cross3(n + 3 * i, n + 3 * k, v);
-                if (dot3(v, n + 3 * (1 - i)) < 0.0) { v[0] = -v[0]; v[1] = -v[1]; v[2] = -v[2]; }
-                const double vn = sqrt(dot3(v, v));
-                for (int c = 0; c < 3; ++c) sum[c] += v[c] / vn;
-            }
-    }
-    const double sn = sqrt(dot3(sum, sum));
-    double ctr[3] = {sum[0] / sn, sum[1] / sn, sum[2] / sn};
-    double cmin = 1.0;
-    for (int s = 0; s < n_sub; ++s) {
-        const double* n = normals + ((f * n_sub + s) * 4) * 3;
-        for (int i = 0; i < 2; ++i)
-            for (int k = 2; k < 4; ++k) {
-                double v[3];
-                cross3(n + 3 * i, n + 3 * k, v);
-                if (dot3(v, n + 3 * (1 - i)) < 0.0) { v[0] = -v[0]; v[1] = -v[1]; v[2] = -v[2]; }
-                const double vn = sqrt(dot3(v, v));
-                cmin = fmin(cmin, dot3(v, ctr) / vn);
-            }
-    }
-    cmin -= 1e-12;                       // rounding margin (radius grows)
-    if (!(sn > 0.0) || !(cmin > -1.0)) { ctr[0] = 1.0; ctr[1] = ctr[2] = 0.0; cmin = -1.0; }
-    double* o = cap + 8 * f;
-    o[0] = ctr[0]; o[1] = ctr[1]; o[2] = ctr[2];
-    o[3] = cmin;
-    o[4] = sqrt(fmax(0.0, 1.0 - cmin * cmin));
-    o[5] = o[6] = o[7] = 0.0;
-}
-
 // Vertex k (0..3) of sub-frame quadrilateral n[4][3] (not normalized): the
 // intersection of normal i = k / 2 of the pair (0, 1) with normal 2 + k % 2
 // of the pair (2, 3), signed to lie inside the opposite edge.
@@ -86,13 +43,72 @@ __device__ __forceinline__ void quad_vertex(const double* __restrict__ n, int k,
     if (dot3(v, n + 3 * (1 - i)) < 0.0) { v[0] = -v[0]; v[1] = -v[1]; v[2] = -v[2]; }
 }
 
+// Sum over the 64 lanes of a wavefront (wave-uniform result).
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, kWave);
+    return uniform(x);
+}
+
+// Cap of every frame: centre the normalized sum of its sub-frames' unit
+// vertex directions, radius the widest vertex seen from it (less a
+// rounding margin).  One wavefront per frame, a lane per sub-frame (and
+// 64 + lane), so that the normals are read in whole lines.
+__global__ __launch_bounds__(256) void k_frame_caps(const double* __restrict__ normals, int64_t n_frames, int n_sub,
+                                                    double* __restrict__ cap) {
+    const int lane = threadIdx.x & 63;
+    const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t f = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; f < n_frames; f += n_waves) {
+        double u[2][4][3];
+        double sum[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int sf = lane + 64 * h;
+            if (sf >= n_sub) continue;
+            const double* n = normals + (f * n_sub + sf) * 12;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                double v[3];
+                quad_vertex(n, k, v);
+                const double vn = sqrt(dot3(v, v));
+                for (int c = 0; c < 3; ++c) {
+                    u[h][k][c] = v[c] / vn;
+                    sum[c] += u[h][k][c];
+                }
+            }
+        }
+        for (int c = 0; c < 3; ++c) sum[c] = wave_sum(sum[c]);
+        const double sn = sqrt(dot3(sum, sum));
+        double ctr[3] = {sum[0] / sn, sum[1] / sn, sum[2] / sn};
+        double cmin = 1.0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (lane + 64 * h >= n_sub) continue;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) cmin = fmin(cmin, dot3(u[h][k], ctr));
+        }
+        cmin = wave_min(cmin) - 1e-12;       // rounding margin (radius grows)
+        if (!(sn > 0.0) || !(cmin > -1.0)) { ctr[0] = 1.0; ctr[1] = ctr[2] = 0.0; cmin = -1.0; }
+        if (lane < 8) {
+            const double v = lane < 3 ? ctr[lane] : lane == 3 ? cmin : lane == 4 ? sqrt(fmax(0.0, 1.0 - cmin * cmin))
+                                                                             : 0.0;
+            cap[8 * f + lane] = v;
+        }
+    }
+}
+
 // Sub-frame locator of every frame (see kLocStride), in cell order, one
-// wavefront per frame with a lane per sub-frame.  The gnomonic image of a
-// quadrilateral with great-circle edges inside the hemisphere around the
-// centre is the convex quadrilateral of its vertices' images, so the box
-// of those four points holds it; each box, widened by a rounding pad,
-// marks the locator cells it overlaps.
+// wavefront per frame with a lane per sub-frame (and 64 + lane).  The
+// gnomonic image of a quadrilateral with great-circle edges inside the
+// hemisphere around the centre is the convex quadrilateral of its
+// vertices' images, so the box of those four points holds it; each box,
+// widened by a rounding pad, marks the locator cells it overlaps (bits
+// set with LDS OR atomics, each lane walking its own boxes' cells).  The
+// same pass writes the cell-ordered copy of the frame's time, observer and
+// normals the join reads.
 __global__ __launch_bounds__(256) void k_frame_locator(const FovParams p) {
+    __shared__ unsigned long long s_mask[4][2 * kLocL * kLocL];
+    unsigned long long* wm = s_mask[threadIdx.x >> 6];
     const int lane = threadIdx.x & 63;
     const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     const int S = p.n_sub;
@@ -100,6 +116,7 @@ __global__ __launch_bounds__(256) void k_frame_locator(const FovParams p) {
         double* L = p.loc + (size_t)kLocStride * r;
         unsigned long long* M = reinterpret_cast<unsigned long long*>(L + kLocHead);
         const double* cp = p.cell_caps + 8 * r;
+        const int f = p.cell_frames[r];
         const double c[3] = {cp[0], cp[1], cp[2]};
         // tangent basis: e1 from the axis least aligned with c
         int ax = 0;
@@ -111,8 +128,10 @@ __global__ __launch_bounds__(256) void k_frame_locator(const FovParams p) {
         for (int k = 0; k < 3; ++k) e1[k] /= n1;
         double e2[3];
         cross3(c, e1, e2);
-        // gnomonic boxes of sub-frames lane and 64 + lane
-        const double* nf = p.cell_normals + (size_t)r * S * 12;
+        // gnomonic boxes of sub-frames lane and 64 + lane, whose normals are
+        // copied to the cell-ordered table on the way
+        const double* src = p.normals + (size_t)f * S * 12;
+        double* dst = p.cell_normals + (size_t)r * S * 12;
         double a0[2], a1[2], b0[2], b1[2];
         bool ok = true;
 #pragma unroll
@@ -120,45 +139,49 @@ __global__ __launch_bounds__(256) void k_frame_locator(const FovParams p) {
             a0[h] = 1e300; a1[h] = -1e300; b0[h] = 1e300; b1[h] = -1e300;
             const int sf = lane + 64 * h;
             if (sf >= S) continue;
+            double nq[12];
+            for (int k = 0; k < 12; ++k) nq[k] = src[12 * sf + k];
+            for (int k = 0; k < 12; ++k) dst[12 * sf + k] = nq[k];
             for (int k = 0; k < 4; ++k) {
                 double v[3];
-                quad_vertex(nf + 12 * sf, k, v);
+                quad_vertex(nq, k, v);
                 const double vc = dot3(v, c);
                 if (!(vc > 1e-6 * sqrt(dot3(v, v)))) { ok = false; continue; }
                 const double X = dot3(v, e1) / vc, Y = dot3(v, e2) / vc;
                 a0[h] = fmin(a0[h], X); a1[h] = fmax(a1[h], X); b0[h] = fmin(b0[h], Y); b1[h] = fmax(b1[h], Y);
             }
         }
+        if (lane < 4) p.cell_obs[4 * r + lane] = lane == 0 ? p.ft[f] : p.fobs[3 * (size_t)f + lane - 1];
         ok = __ballot(!ok) == 0ull;
         double x0 = wave_min(fmin(a0[0], a0[1])), x1 = wave_max(fmax(a1[0], a1[1]));
         double y0 = wave_min(fmin(b0[0], b0[1])), y1 = wave_max(fmax(b1[0], b1[1]));
         const bool usable = ok && x1 >= x0 && y1 >= y0 && x1 - x0 < 1e6 && y1 - y0 < 1e6;
-        unsigned long long w0 = 0ull, w1 = 0ull;      // mask words of locator cell `lane`
+        wm[2 * lane] = 0ull;
+        wm[2 * lane + 1] = 0ull;
+        wave_lds_sync();
         double pad = 0.0, idx = 0.0, idy = 0.0;
         if (usable) {
             pad = 1e-9 * (1.0 + fmax(fmax(fabs(x0), fabs(x1)), fmax(fabs(y0), fabs(y1))));
             x0 -= pad; x1 += pad; y0 -= pad; y1 += pad;
             idx = kLocL / (x1 - x0);
             idy = kLocL / (y1 - y0);
-            int i0[2], i1[2], j0[2], j1[2];
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                i0[h] = max(0, (int)floor((a0[h] - pad - x0) * idx));
-                i1[h] = min(kLocL - 1, (int)floor((a1[h] + pad - x0) * idx));
-                j0[h] = max(0, (int)floor((b0[h] - pad - y0) * idy));
-                j1[h] = min(kLocL - 1, (int)floor((b1[h] + pad - y0) * idy));
-                if (lane + 64 * h >= S) { i0[h] = 1; i1[h] = 0; }
-            }
-            for (int cell = 0; cell < kLocL * kLocL; ++cell) {
-                const int ci = cell / kLocL, cj = cell % kLocL;
-                const unsigned long long m0 = __ballot(i0[0] <= ci && ci <= i1[0] && j0[0] <= cj && cj <= j1[0]);
-                const unsigned long long m1 = __ballot(i0[1] <= ci && ci <= i1[1] && j0[1] <= cj && cj <= j1[1]);
-                if (lane == cell) { w0 = m0; w1 = m1; }
+                if (lane + 64 * h >= S) continue;
+                const int i0 = max(0, (int)floor((a0[h] - pad - x0) * idx));
+                const int i1 = min(kLocL - 1, (int)floor((a1[h] + pad - x0) * idx));
+                const int j0 = max(0, (int)floor((b0[h] - pad - y0) * idy));
+                const int j1 = min(kLocL - 1, (int)floor((b1[h] + pad - y0) * idy));
+                const unsigned long long bit = 1ull << lane;
+                for (int ci = i0; ci <= i1; ++ci)
+                    for (int cj = j0; cj <= j1; ++cj) atomicOr(&wm[2 * (ci * kLocL + cj) + h], bit);
             }
         }
+        wave_lds_sync();
         static_assert(kLocL * kLocL == kWave, "one locator cell per lane");
-        M[2 * lane] = w0;
-        M[2 * lane + 1] = w1;
+        M[2 * lane] = wm[2 * lane];
+        M[2 * lane + 1] = wm[2 * lane + 1];
+        wave_lds_sync();
         if (lane < kLocHead) {
             double v = 0.0;
             if (lane < 3) v = c[lane];
@@ -1480,18 +1503,20 @@ __global__ void k_pair_sort_small(unsigned long long* __restrict__ keys, const i
 
 // Stable LSD radix sort of one frame's keys by one wavefront in LDS.  The
 // keys of a frame differ only in (sub-frame, object), packed here into
-// bits = sb + ob <= 32 bits as sub << ob | obj.  Each pass of kRadixBits
+// bits = sb + ob <= 32 bits as sub << ob | obj.  Each pass of rb bits
+// (the fewest passes of at most kMaxRadixBits, see radix_digit_bits)
 // counts its digits with LDS atomics, scans the counts, then scatters the
 // keys 64 at a time in order, a key's rank among the lanes sharing its
-// digit coming from kRadixBits ballots, so equal digits keep their order.
-constexpr int kRadixBits = 8;
-constexpr int kRadixBuckets = 1 << kRadixBits;
+// digit coming from rb ballots, so equal digits keep their order.
+constexpr int kMaxRadixBits = 8;
+constexpr int kRadixBuckets = 1 << kMaxRadixBits;
 
 template <int kCap, int kWaves>
 __global__ __launch_bounds__(64 * kWaves) void k_pair_sort_radix(const unsigned long long* __restrict__ keys,
                                                                 const int32_t* __restrict__ fstart, int64_t n_frames,
-                                                                int lo_n, int ob, int bits, int32_t* __restrict__ pf,
-                                                                int32_t* __restrict__ ps, int32_t* __restrict__ po) {
+                                                                int lo_n, int ob, int bits, int rb,
+                                                                int32_t* __restrict__ pf, int32_t* __restrict__ ps,
+                                                                int32_t* __restrict__ po) {
     __shared__ unsigned sh_a[kWaves][kCap], sh_b[kWaves][kCap];
     __shared__ int sh_cnt[kWaves][kRadixBuckets];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -1508,10 +1533,11 @@ __global__ __launch_bounds__(64 * kWaves) void k_pair_sort_radix(const unsigned 
             A[i] = ((unsigned)((k >> 25) & 0x7f) << ob) | ((unsigned)k & 0x1ffffffu);
         }
         wave_lds_sync();
-        for (int shift = 0; shift < bits; shift += kRadixBits) {
+        const unsigned dm = (1u << rb) - 1u;
+        for (int shift = 0; shift < bits; shift += rb) {
             for (int d = lane; d < kRadixBuckets; d += kWave) cnt[d] = 0;
             wave_lds_sync();
-            for (int i = lane; i < n; i += kWave) atomicAdd(&cnt[(A[i] >> shift) & (kRadixBuckets - 1)], 1);
+            for (int i = lane; i < n; i += kWave) atomicAdd(&cnt[(A[i] >> shift) & dm], 1);
             wave_lds_sync();
             // exclusive scan of the counts, kRadixBuckets / 64 per lane
             constexpr int kPer = kRadixBuckets / kWave;
@@ -1532,10 +1558,9 @@ __global__ __launch_bounds__(64 * kWaves) void k_pair_sort_radix(const unsigned 
                 const int i = i0 + lane;
                 const bool v = i < n;
                 const unsigned k = v ? A[i] : 0u;
-                const unsigned d = (k >> shift) & (kRadixBuckets - 1);
+                const unsigned d = (k >> shift) & dm;
                 unsigned long long m = __ballot(v);
-#pragma unroll
-                for (int bit = 0; bit < kRadixBits; ++bit) {
+                for (int bit = 0; bit < rb; ++bit) {
                     const bool set = (d >> bit) & 1u;
                     const unsigned long long bb = __ballot(set);
                     m &= set ? bb : ~bb;
@@ -1577,14 +1602,16 @@ constexpr int kSortWaves = 4;
 template <int kCap>
 __global__ __launch_bounds__(64 * kSortWaves) void k_pair_sort_radix_block(
     const unsigned long long* __restrict__ keys, const int32_t* __restrict__ fstart, int64_t n_frames, int lo_n,
-    int ob, int bits, int32_t* __restrict__ pf, int32_t* __restrict__ ps, int32_t* __restrict__ po) {
+    int ob, int bits, int rb, int32_t* __restrict__ pf, int32_t* __restrict__ ps, int32_t* __restrict__ po) {
     __shared__ unsigned sh_a[kCap], sh_b[kCap];
     __shared__ int cnt[kSortWaves][kRadixBuckets];
     __shared__ int wsum[kSortWaves];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const unsigned omask = ob >= 32 ? ~0u : ((1u << ob) - 1u);
-    static_assert(kRadixBuckets == 64 * kSortWaves, "one digit per thread in the cursor scan");
+    constexpr int kPerT = kRadixBuckets / (64 * kSortWaves);      // digits per thread in the cursor scan
+    static_assert(kPerT * 64 * kSortWaves == kRadixBuckets, "whole digits per thread");
+    const unsigned dm = (1u << rb) - 1u;
     for (int64_t f = blockIdx.x; f < n_frames; f += gridDim.x) {
         const int a0 = fstart[f], n = fstart[f + 1] - a0;
         if (n <= lo_n || n > kCap) continue;
@@ -1598,16 +1625,19 @@ __global__ __launch_bounds__(64 * kSortWaves) void k_pair_sort_radix_block(
         const int nc = (n + kWave - 1) / kWave;
         const int qa = kWave * (nc * wv / kSortWaves), qb = min(n, kWave * (nc * (wv + 1) / kSortWaves));
         __syncthreads();
-        for (int shift = 0; shift < bits; shift += kRadixBits) {
+        for (int shift = 0; shift < bits; shift += rb) {
             for (int d = lane; d < kRadixBuckets; d += kWave) cnt[wv][d] = 0;
             wave_lds_sync();
-            for (int i = qa + lane; i < qb; i += kWave) atomicAdd(&cnt[wv][(A[i] >> shift) & (kRadixBuckets - 1)], 1);
+            for (int i = qa + lane; i < qb; i += kWave) atomicAdd(&cnt[wv][(A[i] >> shift) & dm], 1);
             __syncthreads();
-            // thread d: the digit's total, its exclusive scan over the digits,
-            // then the cursors of the wavefronts in order
-            int c[kSortWaves], tot = 0;
+            // thread tid: digits kPerT tid .. kPerT tid + kPerT - 1, their
+            // total, its exclusive scan over the threads, then the cursors of
+            // the digits and wavefronts in order
+            int c[kPerT][kSortWaves], tot = 0;
 #pragma unroll
-            for (int w = 0; w < kSortWaves; ++w) { c[w] = cnt[w][tid]; tot += c[w]; }
+            for (int q = 0; q < kPerT; ++q)
+#pragma unroll
+                for (int w = 0; w < kSortWaves; ++w) { c[q][w] = cnt[w][kPerT * tid + q]; tot += c[q][w]; }
             int incl = tot;
 #pragma unroll
             for (int off = 1; off < kWave; off <<= 1) {
@@ -1619,16 +1649,17 @@ __global__ __launch_bounds__(64 * kSortWaves) void k_pair_sort_radix_block(
             int run = incl - tot;
             for (int w = 0; w < wv; ++w) run += wsum[w];
 #pragma unroll
-            for (int w = 0; w < kSortWaves; ++w) { cnt[w][tid] = run; run += c[w]; }
+            for (int q = 0; q < kPerT; ++q)
+#pragma unroll
+                for (int w = 0; w < kSortWaves; ++w) { cnt[w][kPerT * tid + q] = run; run += c[q][w]; }
             __syncthreads();
             for (int i0 = qa; i0 < qb; i0 += kWave) {
                 const int i = i0 + lane;
                 const bool v = i < qb;
                 const unsigned k = v ? A[i] : 0u;
-                const unsigned d = (k >> shift) & (kRadixBuckets - 1);
+                const unsigned d = (k >> shift) & dm;
                 unsigned long long m = __ballot(v);
-#pragma unroll
-                for (int bit = 0; bit < kRadixBits; ++bit) {
+                for (int bit = 0; bit < rb; ++bit) {
                     const bool set = (d >> bit) & 1u;
                     const unsigned long long bb = __ballot(set);
                     m &= set ? bb : ~bb;
@@ -1748,16 +1779,17 @@ hipError_t fov_prepare(const FovParams& p, int32_t* qkey, int32_t* cnt, int32_t*
     const int64_t F = p.n_frames;
     const unsigned gF = (unsigned)((F + 255) / 256);
     hipError_t e;
-    if (F > 0) hipLaunchKernelGGL(k_frame_caps, dim3(gF), dim3(256), 0, s, p.normals, F, p.n_sub, p.fcap);
+    // one wavefront per frame, four per block
+    const unsigned gw = (unsigned)std::min<int64_t>((F + 3) / 4, 65536);
+    if (F > 0) hipLaunchKernelGGL(k_frame_caps, dim3(gw), dim3(256), 0, s, p.normals, F, p.n_sub, p.fcap);
     if (p.n_batch > 0) hipLaunchKernelGGL(k_batch_prep, dim3((unsigned)p.n_batch), dim3(256), 0, s, p);
     if ((e = fill_zero(cnt, (size_t)(n_keys + 1) * sizeof(int32_t), s)) != hipSuccess) return e;
     if (F > 0) hipLaunchKernelGGL(k_frame_keys, dim3(gF), dim3(256), 0, s, p, qkey, cnt);
     if ((e = exclusive_scan_i32(cnt, (int32_t*)p.cell_start, n_keys, scan_scratch, s)) != hipSuccess) return e;
     if ((e = fill_zero(cursor, (size_t)n_keys * sizeof(int32_t), s)) != hipSuccess) return e;
     if (F > 0) hipLaunchKernelGGL(k_frame_scatter, dim3(gF), dim3(256), 0, s, p, (const int32_t*)qkey, cursor);
-    // one wavefront per frame, four per block
-    const unsigned gw = (unsigned)std::min<int64_t>((F + 3) / 4, 65536);
-    if (F > 0) hipLaunchKernelGGL(k_frame_gather, dim3(gw), dim3(256), 0, s, p);
+    // the locator pass writes the cell-ordered frame copies itself
+    if (F > 0 && !p.loc) hipLaunchKernelGGL(k_frame_gather, dim3(gw), dim3(256), 0, s, p);
     if (F > 0 && p.loc) hipLaunchKernelGGL(k_frame_locator, dim3(gw), dim3(256), 0, s, p);
     return hipGetLastError();
 }
@@ -1846,6 +1878,13 @@ static int bits_for(int64_t n) {
     return b;
 }
 
+// Digit width of the radix segment sorts for keys of `bits` bits: the
+// fewest passes of at most kMaxRadixBits, split evenly (26 bits: 4 x 7).
+static int radix_digit_bits(int bits) {
+    const int passes = std::max(1, (bits + kMaxRadixBits - 1) / kMaxRadixBits);
+    return std::max(1, (bits + passes - 1) / passes);
+}
+
 hipError_t fov_sort(unsigned long long* keys, int64_t n, int64_t n_frames, int64_t n_obj, int n_sub, int32_t* fcnt,
                     int32_t* fstart, unsigned long long* sorted, void* scan_scratch, int32_t* pf, int32_t* ps,
                     int32_t* po, hipStream_t s) {
@@ -1861,16 +1900,16 @@ hipError_t fov_sort(unsigned long long* keys, int64_t n, int64_t n_frames, int64
         const unsigned gb = (unsigned)std::min<int64_t>(n_frames, (int64_t)cu_count() * 16);
         hipLaunchKernelGGL(k_pair_sort_small, dim3((unsigned)((n_frames + 255) / 256)), dim3(256), 0, s, sorted,
                            (const int32_t*)fstart, n_frames, pf, ps, po);
-        const int ob = bits_for(n_obj), bits = ob + bits_for(n_sub);
+        const int ob = bits_for(n_obj), bits = ob + bits_for(n_sub), rb = radix_digit_bits(bits);
         hipLaunchKernelGGL((k_pair_sort_radix<kSortWave, 4>), dim3(gb), dim3(256), 0, s,
                            (const unsigned long long*)sorted, (const int32_t*)fstart, n_frames, kSortSmall, ob, bits,
-                           pf, ps, po);
+                           rb, pf, ps, po);
         hipLaunchKernelGGL((k_pair_sort_radix_block<4096>), dim3(gb), dim3(64 * kSortWaves), 0, s,
                            (const unsigned long long*)sorted, (const int32_t*)fstart, n_frames, kSortWave, ob, bits,
-                           pf, ps, po);
+                           rb, pf, ps, po);
         hipLaunchKernelGGL((k_pair_sort_radix_block<kSortLds>), dim3(gb), dim3(64 * kSortWaves), 0, s,
                            (const unsigned long long*)sorted, (const int32_t*)fstart, n_frames, 4096, ob, bits,
-                           pf, ps, po);
+                           rb, pf, ps, po);
         hipLaunchKernelGGL(k_pair_sort_large, dim3(gb), dim3(256), 0, s, sorted, tmp, (const int32_t*)fstart,
                            n_frames, pf, ps, po);
     }

@@ -5,7 +5,7 @@
 // from the pair's batch epoch (it is cheap next to finding the pairs and
 // saves the field-of-view kernels a per-pair record), which gives the
 // observer-to-body vector d, and the heliocentric emission position r
-// from one more evaluation of the Sun.  With
+// from the Sun's cubic about the frame time.  With
 // c = r . d and s = |r x d| the phase angle is atan2(s, c) and
 // tan(alpha / 2) = s / (|r| |d| + c), so the phase functions need no
 // trigonometric call.  Reads per pair: two indices, the batch and frame
@@ -54,13 +54,14 @@ __global__ __launch_bounds__(256) void k_pair_mag(const MagParams p, const int32
     double v = kNaN, rh = kNaN, dl = kNaN, al = kNaN;
     if (b >= 0 && j >= 0 && j < p.n_obj) {
         const EphemArgs& E = p.eph;
-        const SunTable sun{E.coef, 0, E.n_seg - 1, E.deg1, E.t_start, E.seg_days, E.inv_seg};
         const double tr = p.t_ref[b], tf = p.ft[f];
-        double S[3], Sd[3];
-        sun.eval(tr, S, Sd);
+        // the Sun at the epoch from the same chunked evaluation as its cubic
+        // about the frame time: a few rounds of coefficient loads, not one
+        // dependent load per coefficient
+        const SunCubic s_ref = sun_cubic(E.coef, 0, E.deg1, tr, E.t_start, E.seg_days, E.inv_seg, 0, E.n_seg - 1);
         const double* st = p.x_epoch + 6 * ((int64_t)b * p.n_obj + j);
-        const double r0[3] = {st[0] - S[0], st[1] - S[1], st[2] - S[2]};
-        const double v0[3] = {st[3] - Sd[0], st[4] - Sd[1], st[5] - Sd[2]};
+        const double r0[3] = {st[0] - s_ref.s[0], st[1] - s_ref.s[1], st[2] - s_ref.s[2]};
+        const double v0[3] = {st[3] - s_ref.v[0], st[4] - s_ref.v[1], st[5] - s_ref.v[2]};
         double d[3], tau, ve[3];
         // a hop that ends on the Kepler iteration cap gives NaN, as a pair
         // outside the ephemeris does
