@@ -725,6 +725,7 @@ size_t kete_fov_workspace_size(int64_t n_obj, int64_t n_frames, int64_t n_batch,
     c.take<int32_t>((size_t)(n_batch * n_obj));     // object cell keys
     c.take<int32_t>((size_t)(n_batch * n_obj));     // object ranks inside their cell
     c.take<int32_t>((size_t)(n_batch * n_obj));     // objects sorted by cell
+    c.take<int32_t>((size_t)(n_batch * n_obj));     // object sub-cell keys
     c.take<int32_t>((size_t)nkeys + 1);             // object cell starts and counts
     c.take<int32_t>((size_t)nkeys + 1);
     c.take<unsigned long long>((size_t)(n_batch * n_obj));   // wide objects
@@ -801,6 +802,7 @@ int kete_fov_check(const kete_ephem_t* eph, const double* x_epoch, int32_t* stat
     int32_t* okey = c.take<int32_t>((size_t)(n_batch * n_obj));
     int32_t* orank = c.take<int32_t>((size_t)(n_batch * n_obj));
     int32_t* osorted = c.take<int32_t>((size_t)(n_batch * n_obj));
+    int32_t* osub = c.take<int32_t>((size_t)(n_batch * n_obj));
     int32_t* ostart = c.take<int32_t>((size_t)nkeys + 1);
     int32_t* ocnt = c.take<int32_t>((size_t)nkeys + 1);
     P.wide = c.take<unsigned long long>((size_t)(n_batch * n_obj));
@@ -867,7 +869,7 @@ int kete_fov_check(const kete_ephem_t* eph, const double* x_epoch, int32_t* stat
         HIPCHK(fov_single_job_layout(b_poff, b_obj0, b_xoff, b_G, b_koff, n_batch, n_obj, G, s));
         HIPCHK(fov_prepare(P, qkey, cnt, cnt, scan_scratch, s));
         P.n_wide = counters + 6;
-        HIPCHK(fov_sort_objects(P, okey, orank, ocnt, ostart, osorted, oscan, s));
+        HIPCHK(fov_sort_objects(P, okey, orank, ocnt, ostart, osorted, osub, oscan, s));
         P.obj_sorted = osorted;
         P.obj_start = ostart;
         P.obj_count = ocnt;
@@ -1158,7 +1160,7 @@ struct BatchWs {
     double* dense_coef;
     int32_t* perm;
     FovParams P;
-    int32_t *qkey, *cnt, *fcnt, *fstart, *okey, *orank, *osorted, *ostart, *ocnt, *icnt, *istart;
+    int32_t *qkey, *cnt, *fcnt, *fstart, *okey, *orank, *osorted, *osub, *ostart, *ocnt, *icnt, *istart;
     unsigned long long* items;
     unsigned long long *counters, *sorted;
     void *scan_scratch, *oscan, *wscan;
@@ -1192,6 +1194,7 @@ size_t batch_carve(const BatchDims& d, const kete_batch_t* bt, char* base, Batch
     w.okey = c.take<int32_t>((size_t)d.NP);
     w.orank = c.take<int32_t>((size_t)d.NP);
     w.osorted = c.take<int32_t>((size_t)d.NP);
+    w.osub = c.take<int32_t>((size_t)d.NP);
     w.ostart = c.take<int32_t>((size_t)d.nkeys + 1);
     w.ocnt = c.take<int32_t>((size_t)d.nkeys + 1);
     P.wide = c.take<unsigned long long>((size_t)std::max<int64_t>(d.NP, 1));
@@ -1348,7 +1351,7 @@ int kete_batch_run(const kete_ephem_t* eph, const kete_batch_t* batch, int64_t p
     HIPCHK(fill_zero(P.fail, (size_t)std::max<int64_t>(batch->n_bodies, 1) * sizeof(int32_t), s));
     if (dc.B > 0 && dc.F > 0 && dc.NP > 0) {
         HIPCHK(fov_prepare(P, w.qkey, w.cnt, w.cnt, w.scan_scratch, s));
-        HIPCHK(fov_sort_objects(P, w.okey, w.orank, w.ocnt, w.ostart, w.osorted, w.oscan, s));
+        HIPCHK(fov_sort_objects(P, w.okey, w.orank, w.ocnt, w.ostart, w.osorted, w.osub, w.oscan, s));
         P.obj_sorted = w.osorted;
         P.obj_start = w.ostart;
         P.obj_count = w.ocnt;

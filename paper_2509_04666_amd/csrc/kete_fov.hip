@@ -1240,8 +1240,30 @@ __global__ __launch_bounds__(256, kJoinWaves) void k_fov_wide(const FovParams p)
 // do not queue on its global counter one by one.
 constexpr int kKeyBlock = 256;
 constexpr int kKeySlots = 2 * kKeyBlock;     // at most half full: probing always ends
+// Sub-cell key of a narrow object: the Morton code of its direction's
+// position on a kSubL^3 grid inside its sky cell, with the objects whose
+// motion cap is wider than kFastCapSin after all the others, so that runs
+// of the cell's objects in key order cover small patches of sky and share
+// similar caps.
+constexpr int kSubL = 8;
+constexpr int kSubBits = 3;                  // log2(kSubL)
+constexpr int kSubKeys = 2 * kSubL * kSubL * kSubL;
+constexpr double kFastCapSin = 0.035;        // about 2 degrees
+__device__ __forceinline__ int sub_cell_key(const ObjBounds& o, int G) {
+    int m = 0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        int lc = cell_coord(o.dh[c], kSubL * G) - kSubL * cell_coord(o.dh[c], G);
+        lc = lc < 0 ? 0 : (lc >= kSubL ? kSubL - 1 : lc);
+#pragma unroll
+        for (int k = 0; k < kSubBits; ++k) m |= ((lc >> k) & 1) << (3 * k + c);
+    }
+    return m | (o.sth > kFastCapSin ? kSubL * kSubL * kSubL : 0);
+}
+
 __global__ __launch_bounds__(kKeyBlock) void k_obj_keys(const FovParams p, int32_t* __restrict__ okey,
-                                                        int32_t* __restrict__ orank, int32_t* __restrict__ cnt) {
+                                                        int32_t* __restrict__ orank, int32_t* __restrict__ cnt,
+                                                        int32_t* __restrict__ osub) {
     __shared__ int32_t hkey[kKeySlots], hcnt[kKeySlots], hbase[kKeySlots];
     __shared__ int b_first;
     const int tid = threadIdx.x;
@@ -1259,16 +1281,18 @@ __global__ __launch_bounds__(kKeyBlock) void k_obj_keys(const FovParams p, int32
         const int64_t j = i - p.b_poff[b];
         ObjBounds o;
         const int G = p.b_G[b], G3 = G * G * G;
-        int key;
+        int key, sk = 0;
         const bool live = object_bounds(p, b, j, o);
         if (live && is_narrow(o, G)) {
             key = (int)(p.b_koff[b] + cell_of(o.dh, G));
+            sk = sub_cell_key(o, G);
         } else {
             key = (int)(p.b_koff[b] + G3);
             if (live)
                 wave_append(p.wide, p.n_wide, p.n_pairs_total, ((unsigned long long)b << 32) | (unsigned long long)j);
         }
         okey[i] = key;
+        osub[i] = sk;
         slot = (int)(((unsigned)key * 2654435761u) >> 23) & (kKeySlots - 1);
         for (;;) {
             const int prev = atomicCAS(&hkey[slot], -1, key);
@@ -1298,6 +1322,62 @@ __global__ void k_obj_scatter(const FovParams p, const int32_t* __restrict__ oke
     while (b + 1 < p.n_batch && p.b_poff[b + 1] <= i) ++b;
     // keys are batch-major, so batch b occupies [b_poff[b], b_poff[b+1])
     sorted[start[key] + orank[i]] = (int32_t)(i - p.b_poff[b]);
+}
+
+// Each sky cell's objects ordered by sub-cell key (counting sort in LDS,
+// kCellSortCap objects at a time; longer cells are ordered chunk by chunk).
+// The order of equal keys is arbitrary: the join's results do not depend on
+// the order of a cell's objects, only its speed does.  Cells of fewer than
+// two items' worth of objects, and the wide/dead slot of each batch, are
+// left as they are.
+constexpr int kCellSortCap = 4096;
+__global__ __launch_bounds__(256) void k_obj_cell_sort(const FovParams p, const int32_t* __restrict__ start,
+                                                      int32_t* __restrict__ sorted, const int32_t* __restrict__ osub) {
+    __shared__ int32_t sj[kCellSortCap], sk[kCellSortCap];
+    __shared__ int cnt[kSubKeys];
+    __shared__ int wsum[4];
+    constexpr int kPer = kSubKeys / 256;
+    static_assert(kPer * 256 == kSubKeys, "whole keys per thread");
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    for (int64_t key = blockIdx.x; key < p.n_keys; key += gridDim.x) {
+        const int s0 = start[key], s1 = start[key + 1];
+        if (s1 - s0 <= 2 * kWave) continue;
+        const int b = batch_of_key(p.b_koff, p.n_batch, key);
+        const int G = p.b_G[b];
+        if (key - p.b_koff[b] >= (int64_t)G * G * G) continue;
+        const int64_t xo = p.b_poff[b];
+        for (int c0 = s0; c0 < s1; c0 += kCellSortCap) {
+            const int n = min(kCellSortCap, s1 - c0);
+            for (int k = tid; k < kSubKeys; k += 256) cnt[k] = 0;
+            __syncthreads();
+            for (int i = tid; i < n; i += 256) {
+                const int j = sorted[c0 + i];
+                const int k = osub[xo + j];
+                sj[i] = j;
+                sk[i] = k;
+                atomicAdd(&cnt[k], 1);
+            }
+            __syncthreads();
+            int c[kPer], tot = 0;
+#pragma unroll
+            for (int q = 0; q < kPer; ++q) { c[q] = cnt[kPer * tid + q]; tot += c[q]; }
+            int incl = tot;
+#pragma unroll
+            for (int off = 1; off < kWave; off <<= 1) {
+                const int t = __shfl_up(incl, off, kWave);
+                if (lane >= off) incl += t;
+            }
+            if (lane == kWave - 1) wsum[wv] = incl;
+            __syncthreads();
+            int run = incl - tot;
+            for (int w = 0; w < wv; ++w) run += wsum[w];
+#pragma unroll
+            for (int q = 0; q < kPer; ++q) { cnt[kPer * tid + q] = run; run += c[q]; }
+            __syncthreads();
+            for (int i = tid; i < n; i += 256) sorted[c0 + atomicAdd(&cnt[sk[i]], 1)] = sj[i];
+            __syncthreads();
+        }
+    }
 }
 
 // One exact-test record per frame (layout at FovParams::exact_rec), so
@@ -1794,8 +1874,16 @@ hipError_t fov_prepare(const FovParams& p, int32_t* qkey, int32_t* cnt, int32_t*
     return hipGetLastError();
 }
 
+static int cu_count() {
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
+        ncu = 256;
+    return ncu;
+}
+
 hipError_t fov_sort_objects(const FovParams& p, int32_t* okey, int32_t* orank, int32_t* cnt, int32_t* start,
-                            int32_t* sorted, void* scan_scratch, hipStream_t s) {
+                            int32_t* sorted, int32_t* osub, void* scan_scratch, hipStream_t s) {
     const int64_t n = p.n_pairs_total;
     const int64_t nkeys = p.n_keys;
     if (n == 0) return hipSuccess;
@@ -1803,10 +1891,12 @@ hipError_t fov_sort_objects(const FovParams& p, int32_t* okey, int32_t* orank, i
     if ((e = fill_zero(cnt, (size_t)(nkeys + 1) * sizeof(int32_t), s)) != hipSuccess) return e;
     const unsigned g = (unsigned)((n + 255) / 256);
     hipLaunchKernelGGL(k_obj_keys, dim3((unsigned)((n + kKeyBlock - 1) / kKeyBlock)), dim3(kKeyBlock), 0, s, p, okey,
-                       orank, cnt);
+                       orank, cnt, osub);
     if ((e = exclusive_scan_i32(cnt, start, nkeys, scan_scratch, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_obj_scatter, dim3(g), dim3(256), 0, s, p, (const int32_t*)okey, (const int32_t*)orank,
                        (const int32_t*)start, sorted);
+    hipLaunchKernelGGL(k_obj_cell_sort, dim3((unsigned)std::min<int64_t>(nkeys, (int64_t)cu_count() * 8)), dim3(256),
+                       0, s, p, (const int32_t*)start, sorted, (const int32_t*)osub);
     return hipGetLastError();
 }
 
@@ -1823,14 +1913,6 @@ hipError_t fill_zero(void* p, size_t bytes, hipStream_t s) {
     unsigned g = (unsigned)std::min<size_t>((words + 255) / 256, 65536);
     hipLaunchKernelGGL(k_fill_zero, dim3(g), dim3(256), 0, s, (unsigned int*)p, words);
     return hipGetLastError();
-}
-
-static int cu_count() {
-    int dev = 0, ncu = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
-        ncu = 256;
-    return ncu;
 }
 
 hipError_t fov_candidates(FovParams& p, int32_t* icnt, int32_t* istart, unsigned long long* items,

@@ -113,9 +113,11 @@ struct FovParams {
 
 hipError_t fov_prepare(const FovParams& p, int32_t* qkey, int32_t* cnt, int32_t* cursor, void* scan_scratch,
                        hipStream_t s);
+// Objects of every batch into sky-cell order (sorted, with start/cnt per
+// key), each cell's objects ordered by their sub-cell key (osub, scratch of
+// n_pairs_total entries) so that the join's 64-object items are compact.
 hipError_t fov_sort_objects(const FovParams& p, int32_t* okey, int32_t* orank, int32_t* cnt, int32_t* start,
-                            int32_t* sorted,
-                            void* scan_scratch, hipStream_t s);
+                            int32_t* sorted, int32_t* osub, void* scan_scratch, hipStream_t s);
 // Workgroups are dealt to the chip's XCDs round-robin (workgroup i to XCD
 // i mod kXcds), each XCD with its own L2.  The per-cell join splits its
 // work list into kXcds slices, one cursor each, kCursorStride unsigned ints
