@@ -833,6 +833,7 @@ int kete_fov_check(const kete_ephem_t* eph, const double* x_epoch, int32_t* stat
     P.b_koff = b_koff;
     P.n_keys = nkeys;
     P.n_pairs_total = n_batch * n_obj;
+    P.max_batch_obj = n_obj;
 
     P.eph = E;
     P.x_epoch = x_epoch;
@@ -1057,7 +1058,7 @@ namespace {
 // Sizes and host-side tables of a batched run (recomputed identically by
 // every batch call from the host copies).
 struct BatchDims {
-    int64_t F = 0, B = 0, NP = 0, nkeys = 0, cand_cap = 0, pairs_cap = 0;
+    int64_t F = 0, B = 0, NP = 0, nkeys = 0, cand_cap = 0, pairs_cap = 0, max_batch_obj = 0;
     int32_t n_tiles = 0, n_sub = 1;
     std::vector<int2> tiles;
     std::vector<int64_t> b_poff, b_xoff, b_koff;
@@ -1127,6 +1128,7 @@ int batch_dims(const kete_ephem_t* eph, const kete_batch_t* bt, int64_t pairs_ca
         }
         np += J[j].n_obj;
         nk += (int64_t)G * G * G + 1;
+        d.max_batch_obj = std::max<int64_t>(d.max_batch_obj, J[j].n_obj);
     }
     if (tables) { d.b_poff[d.B] = np; d.b_koff[d.B] = nk; }
     if (np >= 2000000000LL || nk >= 2000000000LL) return fail(KETE_EINVAL, "batch too large for 32-bit indices");
@@ -1337,6 +1339,7 @@ int kete_batch_run(const kete_ephem_t* eph, const kete_batch_t* batch, int64_t p
     P.b_koff = w.b_koff;
     P.n_keys = dc.nkeys;
     P.n_pairs_total = dc.NP;
+    P.max_batch_obj = dc.max_batch_obj;
     P.mu = E.gm[0];
     P.smu = std::sqrt(E.gm[0]);
     P.c_light = cl;

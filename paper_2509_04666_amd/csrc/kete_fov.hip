@@ -1265,20 +1265,22 @@ __global__ __launch_bounds__(kKeyBlock) void k_obj_keys(const FovParams p, int32
                                                         int32_t* __restrict__ orank, int32_t* __restrict__ cnt,
                                                         int32_t* __restrict__ osub) {
     __shared__ int32_t hkey[kKeySlots], hcnt[kKeySlots], hbase[kKeySlots];
-    __shared__ int b_first;
+    __shared__ int s_nwide;
+    __shared__ unsigned long long s_wbase;
     const int tid = threadIdx.x;
     for (int k = tid; k < kKeySlots; k += kKeyBlock) { hkey[k] = -1; hcnt[k] = 0; }
-    // the block's items are consecutive: one search finds the batch of the
-    // first, and each item steps on from there
-    if (tid == 0) b_first = batch_of(p.b_poff, p.n_batch, (int64_t)blockIdx.x * kKeyBlock);
+    if (tid == 0) s_nwide = 0;
     __syncthreads();
-    const int64_t i = (int64_t)blockIdx.x * kKeyBlock + tid;
-    const bool valid = i < p.n_pairs_total;
-    int slot = 0, lrank = 0;
+    // block k takes chunk k / n_batch of batch k % n_batch: the blocks in
+    // flight at any time spread over every batch, so that the per-cell
+    // counters they update (disjoint between batches) are not all hit at
+    // once
+    const int b = (int)(blockIdx.x % (unsigned)p.n_batch);
+    const int64_t j = (int64_t)(blockIdx.x / (unsigned)p.n_batch) * kKeyBlock + tid;
+    const int64_t i = p.b_poff[b] + j;
+    const bool valid = i < p.b_poff[b + 1];
+    int slot = 0, lrank = 0, wrank = -1;
     if (valid) {
-        int b = b_first;
-        while (b + 1 < p.n_batch && p.b_poff[b + 1] <= i) ++b;
-        const int64_t j = i - p.b_poff[b];
         ObjBounds o;
         const int G = p.b_G[b], G3 = G * G * G;
         int key, sk = 0;
@@ -1288,8 +1290,7 @@ __global__ __launch_bounds__(kKeyBlock) void k_obj_keys(const FovParams p, int32
             sk = sub_cell_key(o, G);
         } else {
             key = (int)(p.b_koff[b] + G3);
-            if (live)
-                wave_append(p.wide, p.n_wide, p.n_pairs_total, ((unsigned long long)b << 32) | (unsigned long long)j);
+            if (live) wrank = atomicAdd(&s_nwide, 1);      // a wide object: listed below
         }
         okey[i] = key;
         osub[i] = sk;
@@ -1304,24 +1305,25 @@ __global__ __launch_bounds__(kKeyBlock) void k_obj_keys(const FovParams p, int32
     __syncthreads();
     for (int k = tid; k < kKeySlots; k += kKeyBlock)
         if (hkey[k] >= 0) hbase[k] = atomicAdd(cnt + hkey[k], hcnt[k]);
+    if (tid == 0 && s_nwide > 0) s_wbase = atomicAdd(p.n_wide, (unsigned long long)s_nwide);
     __syncthreads();
     if (valid) orank[i] = hbase[slot] + lrank;
+    if (wrank >= 0) {
+        const unsigned long long w = s_wbase + (unsigned long long)wrank;
+        if (w < (unsigned long long)p.n_pairs_total) p.wide[w] = ((unsigned long long)b << 32) | (unsigned long long)j;
+    }
 }
 
 // Objects into their cell's slots, at the rank the key pass drew (the order
 // inside a cell is arbitrary: the pairs are sorted at the end).
 __global__ void k_obj_scatter(const FovParams p, const int32_t* __restrict__ okey, const int32_t* __restrict__ orank,
                               const int32_t* __restrict__ start, int32_t* __restrict__ sorted) {
-    __shared__ int b_first;
-    if (threadIdx.x == 0) b_first = batch_of(p.b_poff, p.n_batch, (int64_t)blockIdx.x * blockDim.x);
-    __syncthreads();
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= p.n_pairs_total) return;
-    const int key = okey[i];
-    int b = b_first;
-    while (b + 1 < p.n_batch && p.b_poff[b + 1] <= i) ++b;
-    // keys are batch-major, so batch b occupies [b_poff[b], b_poff[b+1])
-    sorted[start[key] + orank[i]] = (int32_t)(i - p.b_poff[b]);
+    // blocks map to (batch, chunk) as in k_obj_keys
+    const int b = (int)(blockIdx.x % (unsigned)p.n_batch);
+    const int64_t j = (int64_t)(blockIdx.x / (unsigned)p.n_batch) * blockDim.x + threadIdx.x;
+    const int64_t i = p.b_poff[b] + j;
+    if (i >= p.b_poff[b + 1]) return;
+    sorted[start[okey[i]] + orank[i]] = (int32_t)j;
 }
 
 // Each sky cell's objects ordered by sub-cell key (counting sort in LDS,
@@ -1889,11 +1891,14 @@ hipError_t fov_sort_objects(const FovParams& p, int32_t* okey, int32_t* orank, i
     if (n == 0) return hipSuccess;
     hipError_t e;
     if ((e = fill_zero(cnt, (size_t)(nkeys + 1) * sizeof(int32_t), s)) != hipSuccess) return e;
-    const unsigned g = (unsigned)((n + 255) / 256);
-    hipLaunchKernelGGL(k_obj_keys, dim3((unsigned)((n + kKeyBlock - 1) / kKeyBlock)), dim3(kKeyBlock), 0, s, p, okey,
-                       orank, cnt, osub);
+    // one block per (batch, chunk of kKeyBlock objects)
+    const int64_t chunks = (p.max_batch_obj + kKeyBlock - 1) / kKeyBlock;
+    if (p.n_batch <= 0 || chunks <= 0) return hipSuccess;
+    const unsigned gk = (unsigned)(p.n_batch * chunks);
+    hipLaunchKernelGGL(k_obj_keys, dim3(gk), dim3(kKeyBlock), 0, s, p, okey, orank, cnt, osub);
     if ((e = exclusive_scan_i32(cnt, start, nkeys, scan_scratch, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_obj_scatter, dim3(g), dim3(256), 0, s, p, (const int32_t*)okey, (const int32_t*)orank,
+    static_assert(kKeyBlock == 256, "the scatter uses the key pass's chunks");
+    hipLaunchKernelGGL(k_obj_scatter, dim3(gk), dim3(256), 0, s, p, (const int32_t*)okey, (const int32_t*)orank,
                        (const int32_t*)start, sorted);
     hipLaunchKernelGGL(k_obj_cell_sort, dim3((unsigned)std::min<int64_t>(nkeys, (int64_t)cu_count() * 8)), dim3(256),
                        0, s, p, (const int32_t*)start, sorted, (const int32_t*)osub);

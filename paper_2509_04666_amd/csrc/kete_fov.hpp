@@ -74,6 +74,7 @@ struct FovParams {
     const int32_t* b_obj0;      // [B]
     const int64_t* b_xoff;      // [B]
     int64_t n_pairs_total;      // b_poff[B]
+    int64_t max_batch_obj;      // the most objects of any batch
     // Sky grid of batch b: G_b cells per axis over [-1, 1]^3 (G_b = 1 puts
     // every frame in one cell); its keys start at b_koff[b] and number
     // G_b^3 + 1 (the last one collects objects with wide motion caps).
