@@ -818,8 +818,8 @@ int kete_fov_check(const kete_ephem_t* eph, const double* x_epoch, int32_t* stat
     P.fail = c.take<int32_t>((size_t)std::max<int64_t>(n_obj, 1));
     P.loc = frames->n_sub > 1 ? c.take<double>((size_t)F * kLocStride) : nullptr;
     P.cell_obs = c.take<double>((size_t)fov_cell_frame_doubles(F, frames->n_sub));
-    P.cell_normals = P.cell_obs + 4 * F;
-    P.exact_rec = P.cell_normals + 12 * (int64_t)frames->n_sub * F;
+    P.cell_normals = reinterpret_cast<float*>(P.cell_obs + 4 * F);
+    P.exact_rec = P.cell_obs + 4 * F + 6 * (int64_t)frames->n_sub * F;
     P.wide_parts = c.take<int32_t>((size_t)(n_batch * n_obj));
     P.wide_off = c.take<int32_t>((size_t)(n_batch * n_obj) + 1);
     void* wscan = c.take<char>(scan_scratch_bytes(n_batch * n_obj));
@@ -1212,8 +1212,8 @@ size_t batch_carve(const BatchDims& d, const kete_batch_t* bt, char* base, Batch
     P.fail = c.take<int32_t>((size_t)std::max<int64_t>(bt->n_bodies, 1));
     P.loc = bt->frames.n_sub > 1 ? c.take<double>((size_t)d.F * kLocStride) : nullptr;
     P.cell_obs = c.take<double>((size_t)fov_cell_frame_doubles(d.F, bt->frames.n_sub));
-    P.cell_normals = P.cell_obs ? P.cell_obs + 4 * d.F : nullptr;
-    P.exact_rec = P.cell_obs ? P.cell_normals + 12 * (int64_t)bt->frames.n_sub * d.F : nullptr;
+    P.cell_normals = P.cell_obs ? reinterpret_cast<float*>(P.cell_obs + 4 * d.F) : nullptr;
+    P.exact_rec = P.cell_obs ? P.cell_obs + 4 * d.F + 6 * (int64_t)bt->frames.n_sub * d.F : nullptr;
     P.wide_parts = c.take<int32_t>((size_t)std::max<int64_t>(d.NP, 1));
     P.wide_off = c.take<int32_t>((size_t)d.NP + 1);
     w.wscan = c.take<char>(scan_scratch_bytes(d.NP));

@@ -131,7 +131,7 @@ __global__ __launch_bounds__(256) void k_frame_locator(const FovParams p) {
         // gnomonic boxes of sub-frames lane and 64 + lane, whose normals are
         // copied to the cell-ordered table on the way
         const double* src = p.normals + (size_t)f * S * 12;
-        double* dst = p.cell_normals + (size_t)r * S * 12;
+        float* dst = p.cell_normals + (size_t)r * S * 12;
         double a0[2], a1[2], b0[2], b1[2];
         bool ok = true;
 #pragma unroll
@@ -141,7 +141,7 @@ __global__ __launch_bounds__(256) void k_frame_locator(const FovParams p) {
             if (sf >= S) continue;
             double nq[12];
             for (int k = 0; k < 12; ++k) nq[k] = src[12 * sf + k];
-            for (int k = 0; k < 12; ++k) dst[12 * sf + k] = nq[k];
+            for (int k = 0; k < 12; ++k) dst[12 * sf + k] = (float)nq[k];
             for (int k = 0; k < 4; ++k) {
                 double v[3];
                 quad_vertex(nq, k, v);
@@ -204,8 +204,8 @@ __global__ __launch_bounds__(256) void k_frame_gather(const FovParams p) {
     for (int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; r < p.n_frames; r += n_waves) {
         const int f = p.cell_frames[r];
         const double* src = p.normals + (size_t)f * nd;
-        double* dst = p.cell_normals + (size_t)r * nd;
-        for (int i = lane; i < nd; i += kWave) dst[i] = src[i];
+        float* dst = p.cell_normals + (size_t)r * nd;
+        for (int i = lane; i < nd; i += kWave) dst[i] = (float)src[i];
         if (lane < 4) p.cell_obs[4 * r + lane] = lane == 0 ? p.ft[f] : p.fobs[3 * (size_t)f + lane - 1];
     }
 }
@@ -670,17 +670,26 @@ __device__ void classify_emit(const FovParams& p, bool has, const ObjBounds& o, 
     const unsigned long long base = ((unsigned long long)(unsigned)f << 32) | gobj;
     if (all) ++n_exact;
     buf_append<kBufEntries>(cbuf, nc, all, base | kAllSubs, p.cand, p.n_cand, p.cand_cap);
-    // test of sub-frame s of pair (ri, bi) with ul = (u0, u1, u2), margin e
+    // test of sub-frame s of pair (ri, bi) with ul = (u0, u1, u2), margin e.
+    // The normals are single-precision copies: each component is within
+    // 2^-24 of its own magnitude of the double, so n . u moves by at most
+    // 2^-24 sum |n_i u_i| (to first order; 2^-23 covers the rest), which
+    // widens the margin; the undecided band grows by about 1e-7 rad.
     auto sub_test = [&](bool act, int ri, int s, double u0, double u1, double u2, double e, unsigned long long bi) {
         int res = 0;
         if (act) {
-            const double* n = p.cell_normals + ((size_t)(unsigned)ri * p.n_sub + s) * 12;
+            const float4* n4 = reinterpret_cast<const float4*>(p.cell_normals +
+                                                               ((size_t)(unsigned)ri * p.n_sub + s) * 12);
+            const float4 q0 = n4[0], q1 = n4[1], q2 = n4[2];
+            const double n[12] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, q2.x, q2.y, q2.z, q2.w};
             res = 1;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                const double d = n[3 * k] * u0 + n[3 * k + 1] * u1 + n[3 * k + 2] * u2;
-                if (d <= -e) res = 0;
-                else if (!(d > e) && res == 1) res = 2;
+                const double a = n[3 * k] * u0, b = n[3 * k + 1] * u1, c = n[3 * k + 2] * u2;
+                const double d = a + b + c;
+                const double ek = e + 0x1p-23 * (fabs(a) + fabs(b) + fabs(c));
+                if (d <= -ek) res = 0;
+                else if (!(d > ek) && res == 1) res = 2;
             }
         }
         const unsigned long long key = bi | ((unsigned long long)(act ? s : 0) << 25);

@@ -50,7 +50,7 @@ struct FovParams {
     // neighbouring cells sit together in memory: time and observer
     // position, and the sub-frame normals.
     double* cell_obs;           // [F][4]: t, observer x, y, z
-    double* cell_normals;       // [F][S][4][3]
+    float* cell_normals;        // [F][S][4][3] single-precision copies (the join widens its margin by their rounding)
     // What the exact test reads of a frame, by frame index, in one record
     // (kExactRec doubles): its time, its batch's epoch, the observer, the
     // Sun's state at the epoch, the offset of the batch's states in
@@ -136,9 +136,9 @@ constexpr int kWidePartFrames = 1024;
 hipError_t fov_candidates(FovParams& p, int32_t* icnt, int32_t* istart, unsigned long long* items,
                           unsigned int* item_next, void* scan_scratch, void* wide_scan_scratch, hipStream_t s);
 inline int64_t fov_item_capacity(int64_t n_keys, int64_t n_pairs_total) { return n_keys + n_pairs_total / 64 + 1; }
-// Doubles of the frame copies (cell_obs, cell_normals, exact_rec).
+// Doubles of the frame copies (cell_obs, cell_normals as floats, exact_rec).
 inline int64_t fov_cell_frame_doubles(int64_t n_frames, int n_sub) {
-    return n_frames * (4 + 12 * (int64_t)n_sub + kExactRec);
+    return n_frames * (4 + 6 * (int64_t)n_sub + kExactRec);
 }
 hipError_t fov_exact(const FovParams& p, hipStream_t s);
 hipError_t fov_drop_failed(const unsigned long long* keys, int64_t n, const int32_t* fail, unsigned long long* out,
