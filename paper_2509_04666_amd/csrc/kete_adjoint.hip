@@ -123,6 +123,8 @@ struct SunGlobal {
     __device__ __forceinline__ void eval(double t, double pos[3], double vel[3]) const {
         cheb_body(E.coef, 0, E.deg1, t, E.t_start, E.seg_days, E.inv_seg, 0, E.n_seg - 1, pos, vel);
     }
+    __device__ bool covers(double) const { return true; }
+    __device__ void center(double) const {}
 };
 
 // Light-time hop of the state (x, v) at t_obs seen from o: direction d,

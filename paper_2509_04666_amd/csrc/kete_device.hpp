@@ -141,25 +141,29 @@ __device__ __forceinline__ void cheb_body(const double* __restrict__ tab, int se
 
 // A body's motion near one time t0 as a cubic in t - t0: position,
 // velocity, acceleration and jerk of its Chebyshev segment at t0 (the
-// segment's polynomial differentiated three times).  Over a light time of
-// a fraction of a day it differs from the segment's own value by the
-// fourth-order term, |x''''| tau^4 / 24, which for the Sun's barycentric
-// wobble is about 1e-18 au: far below the fit error of the ephemeris.  Its
-// evaluations load nothing, so a light-time loop that takes the Sun from it
-// waits on no memory between hops.
+// segment's polynomial differentiated three times).  It differs from the
+// segment's own value by the fourth-order term, which for the Sun's
+// barycentric wobble (the inner planets' pull dominates its high
+// derivatives) is below 1e-17 au within kCubicSpan of t0 but grows as
+// |t - t0|^4 beyond: 3e-13 au at one day (and a segment's polynomial
+// carried across the segment's end departs from the next segment's).  A
+// user whose times may leave the span asks covers(t) and re-expands with
+// center(t) (the light-time loop does this once for a body beyond about
+// 10 au).  Evaluations load nothing, so a light-time loop that takes the
+// Sun from the cubic waits on no memory between hops.
+constexpr double kCubicSpan = 0.0625;        // days
 struct SunCubic {
     double t0, s[3], v[3], a[3], j[3];
-    __device__ __forceinline__ void eval(double t, double pos[3], double vel[3]) const {
-        const double h = t - t0;
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            pos[i] = fma(h, fma(h, fma(h, j[i] * (1.0 / 6.0), 0.5 * a[i]), v[i]), s[i]);
-            vel[i] = fma(h, fma(h, 0.5 * j[i], a[i]), v[i]);
-        }
-    }
+    // the body row of the segment table the cubic comes from (as cheb_body)
+    const double* tab;
+    int seg_base, deg1, lo, hi;
+    double t_start, seg_days, inv_seg;
+    __device__ void eval(double t, double pos[3], double vel[3]) const;
+    __device__ bool covers(double t) const { return fabs(t - t0) <= kCubicSpan; }
+    __device__ void center(double t);
 };
 
-// The cubic of one body row of a segment table (layout as cheb_body) at t.
+// The cubic of the table row at t, into S (whose table fields are set).
 // T_n and its first three derivatives follow the Chebyshev recurrence
 // T_{n+1} = 2x T_n - T_{n-1} differentiated:
 //   T'_{n+1}   = 2 T_n   + 2x T'_n   - T'_{n-1}
@@ -167,14 +171,14 @@ struct SunCubic {
 //   T'''_{n+1} = 6 T''_n + 2x T'''_n - T'''_{n-1}.
 // Terms n >= 2 go in chunks of kChunk: a chunk's coefficient loads (all
 // three coordinates) are issued together, and only one chunk is held in
-// registers at a time.
-__device__ __forceinline__ SunCubic sun_cubic(const double* __restrict__ tab, int seg_base, int deg1, double t,
-                                              double t_start, double seg_days, double inv_seg, int lo, int hi) {
-    constexpr int kChunk = 7;
+// registers at a time (small chunks where registers are scarce).
+template <int kChunk = 7>
+__device__ __forceinline__ void sun_cubic_at(SunCubic& S, double t) {
     static_assert((KETE_MAX_DEGREE - 1) % kChunk == 0, "terms 2..KETE_MAX_DEGREE split into whole chunks");
-    const int k = seg_index(t, t_start, inv_seg, lo, hi);
-    const double x = 2.0 * (t - (t_start + (double)k * seg_days)) * inv_seg - 1.0;
-    const double* c = tab + (size_t)(k - seg_base) * 3 * deg1;
+    const int deg1 = S.deg1;
+    const int k = seg_index(t, S.t_start, S.inv_seg, S.lo, S.hi);
+    const double x = 2.0 * (t - (S.t_start + (double)k * S.seg_days)) * S.inv_seg - 1.0;
+    const double* c = S.tab + (size_t)(k - S.seg_base) * 3 * deg1;
     const double x2 = x + x;
     double p[3], d1[3], d2[3], d3[3];
 #pragma unroll
@@ -213,8 +217,7 @@ __device__ __forceinline__ SunCubic sun_cubic(const double* __restrict__ tab, in
             t_a = t_b; t_b = tn; u_a = u_b; u_b = un; w_a = w_b; w_b = wn; z_a = z_b; z_b = zn;
         }
     }
-    const double sc = 2.0 * inv_seg;
-    SunCubic S;
+    const double sc = 2.0 * S.inv_seg;
     S.t0 = t;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -223,6 +226,41 @@ __device__ __forceinline__ SunCubic sun_cubic(const double* __restrict__ tab, in
         S.a[i] = d2[i] * (sc * sc);
         S.j[i] = d3[i] * (sc * sc * sc);
     }
+}
+
+// Re-expansion inside a light-time loop: one term at a time, which keeps
+// the loop's register count down (it runs for distant bodies only).
+__device__ __forceinline__ void SunCubic::center(double t) { sun_cubic_at<1>(*this, t); }
+
+__device__ __forceinline__ void SunCubic::eval(double t, double pos[3], double vel[3]) const {
+    const double h = t - t0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        pos[i] = fma(h, fma(h, fma(h, j[i] * (1.0 / 6.0), 0.5 * a[i]), v[i]), s[i]);
+        vel[i] = fma(h, fma(h, 0.5 * j[i], a[i]), v[i]);
+    }
+}
+
+// The table fields of a cubic for body row `tab` (layout as cheb_body).
+__device__ __forceinline__ SunCubic sun_table(const double* __restrict__ tab, int seg_base, int deg1, double t_start,
+                                              double seg_days, double inv_seg, int lo, int hi) {
+    SunCubic S;
+    S.tab = tab;
+    S.seg_base = seg_base;
+    S.deg1 = deg1;
+    S.lo = lo;
+    S.hi = hi;
+    S.t_start = t_start;
+    S.seg_days = seg_days;
+    S.inv_seg = inv_seg;
+    return S;
+}
+
+// The cubic of a table row about t.
+__device__ __forceinline__ SunCubic sun_cubic(const double* __restrict__ tab, int seg_base, int deg1, double t,
+                                              double t_start, double seg_days, double inv_seg, int lo, int hi) {
+    SunCubic S = sun_table(tab, seg_base, deg1, t_start, seg_days, inv_seg, lo, hi);
+    sun_cubic_at(S, t);
     return S;
 }
 
@@ -371,6 +409,8 @@ struct SunTable {
     __device__ __forceinline__ void eval(double t, double pos[3], double vel[3]) const {
         cheb_body(tab, lo, deg1, t, t_start, seg_days, inv_seg, lo, hi, pos, vel);
     }
+    __device__ bool covers(double) const { return true; }
+    __device__ void center(double) const {}
 };
 
 // Light-time corrected direction of a body from an observer (Newtonian,
@@ -389,7 +429,7 @@ struct SunTable {
 // KETE_ST_KEPLER_NOCONV when any of its hops ended on the iteration cap
 // kepler_iter without converging, else 0.
 template <class SunT>
-__device__ __forceinline__ int lighttime(const SunT& sun, double mu, double smu, double c_light,
+__device__ __forceinline__ int lighttime(SunT& sun, double mu, double smu, double c_light,
                                          double lt_tol, int lt_iter, double t_ref,
                                          const double r0[3], const double v0[3], double t_obs,
                                          const double o[3], double d[3], double& tau, double ve[3],
@@ -403,19 +443,27 @@ __device__ __forceinline__ int lighttime(const SunT& sun, double mu, double smu,
         tau = sqrt(dot3(d, d)) / c_light;
     }
     int st = 0;
-    for (int k = 0;; ++k) {
-        const double te = t_obs - tau;
-        st |= kepler_uv(mu, smu, r0, v0, te - t_ref, chi, r, v, kepler_iter);
-        sun.eval(te, Se, Sde);
-        for (int i = 0; i < 3; ++i) {
-            d[i] = Se[i] + r[i] - o[i];
-            ve[i] = Sde[i] + v[i];
+    // a Sun model that holds near one time only (SunCubic) is centred on
+    // the first guess when that lies outside it, and once more on the
+    // solution if the loop ends outside it
+#pragma unroll 1
+    for (int pass = 0; pass < 2; ++pass) {
+        if (!sun.covers(t_obs - tau)) sun.center(t_obs - tau);
+        for (int k = 0;; ++k) {
+            const double te = t_obs - tau;
+            st |= kepler_uv(mu, smu, r0, v0, te - t_ref, chi, r, v, kepler_iter);
+            sun.eval(te, Se, Sde);
+            for (int i = 0; i < 3; ++i) {
+                d[i] = Se[i] + r[i] - o[i];
+                ve[i] = Sde[i] + v[i];
+            }
+            if (k == lt_iter) break;
+            const double dn = sqrt(dot3(d, d));
+            const double step = (dn / c_light - tau) / (1.0 + dot3(d, ve) / (dn * c_light));
+            if (fabs(step) <= lt_tol) break;
+            tau += step;
         }
-        if (k == lt_iter) break;
-        const double dn = sqrt(dot3(d, d));
-        const double step = (dn / c_light - tau) / (1.0 + dot3(d, ve) / (dn * c_light));
-        if (fabs(step) <= lt_tol) break;
-        tau += step;
+        if (sun.covers(t_obs - tau)) break;
     }
     if (chi_out) *chi_out = chi;
     return st;

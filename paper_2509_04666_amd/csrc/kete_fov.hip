@@ -1274,11 +1274,8 @@ __global__ __launch_bounds__(kKeyBlock) void k_obj_keys(const FovParams p, int32
                                                         int32_t* __restrict__ orank, int32_t* __restrict__ cnt,
                                                         int32_t* __restrict__ osub) {
     __shared__ int32_t hkey[kKeySlots], hcnt[kKeySlots], hbase[kKeySlots];
-    __shared__ int s_nwide;
-    __shared__ unsigned long long s_wbase;
     const int tid = threadIdx.x;
     for (int k = tid; k < kKeySlots; k += kKeyBlock) { hkey[k] = -1; hcnt[k] = 0; }
-    if (tid == 0) s_nwide = 0;
     __syncthreads();
     // block k takes chunk k / n_batch of batch k % n_batch: the blocks in
     // flight at any time spread over every batch, so that the per-cell
@@ -1288,18 +1285,21 @@ __global__ __launch_bounds__(kKeyBlock) void k_obj_keys(const FovParams p, int32
     const int64_t j = (int64_t)(blockIdx.x / (unsigned)p.n_batch) * kKeyBlock + tid;
     const int64_t i = p.b_poff[b] + j;
     const bool valid = i < p.b_poff[b + 1];
-    int slot = 0, lrank = 0, wrank = -1;
+    int slot = 0, lrank = 0;
     if (valid) {
         ObjBounds o;
         const int G = p.b_G[b], G3 = G * G * G;
-        int key, sk = 0;
+        int key, sk;
         const bool live = object_bounds(p, b, j, o);
         if (live && is_narrow(o, G)) {
             key = (int)(p.b_koff[b] + cell_of(o.dh, G));
             sk = sub_cell_key(o, G);
         } else {
+            // the batch's wide slot: wide objects ordered by a coarse sky
+            // key (the Morton code of the direction on a kSubL^3 grid of the
+            // whole sphere's cube), objects out of the join last
             key = (int)(p.b_koff[b] + G3);
-            if (live) wrank = atomicAdd(&s_nwide, 1);      // a wide object: listed below
+            sk = live ? sub_cell_key(o, 1) : kSubKeys - 1;
         }
         okey[i] = key;
         osub[i] = sk;
@@ -1314,13 +1314,8 @@ __global__ __launch_bounds__(kKeyBlock) void k_obj_keys(const FovParams p, int32
     __syncthreads();
     for (int k = tid; k < kKeySlots; k += kKeyBlock)
         if (hkey[k] >= 0) hbase[k] = atomicAdd(cnt + hkey[k], hcnt[k]);
-    if (tid == 0 && s_nwide > 0) s_wbase = atomicAdd(p.n_wide, (unsigned long long)s_nwide);
     __syncthreads();
     if (valid) orank[i] = hbase[slot] + lrank;
-    if (wrank >= 0) {
-        const unsigned long long w = s_wbase + (unsigned long long)wrank;
-        if (w < (unsigned long long)p.n_pairs_total) p.wide[w] = ((unsigned long long)b << 32) | (unsigned long long)j;
-    }
 }
 
 // Objects into their cell's slots, at the rank the key pass drew (the order
@@ -1339,8 +1334,8 @@ __global__ void k_obj_scatter(const FovParams p, const int32_t* __restrict__ oke
 // kCellSortCap objects at a time; longer cells are ordered chunk by chunk).
 // The order of equal keys is arbitrary: the join's results do not depend on
 // the order of a cell's objects, only its speed does.  Cells of fewer than
-// two items' worth of objects, and the wide/dead slot of each batch, are
-// left as they are.
+// two items' worth of objects are left as they are.  Each batch's wide slot
+// is ordered the same way by its coarse sky key.
 constexpr int kCellSortCap = 4096;
 __global__ __launch_bounds__(256) void k_obj_cell_sort(const FovParams p, const int32_t* __restrict__ start,
                                                       int32_t* __restrict__ sorted, const int32_t* __restrict__ osub) {
@@ -1354,8 +1349,6 @@ __global__ __launch_bounds__(256) void k_obj_cell_sort(const FovParams p, const 
         const int s0 = start[key], s1 = start[key + 1];
         if (s1 - s0 <= 2 * kWave) continue;
         const int b = batch_of_key(p.b_koff, p.n_batch, key);
-        const int G = p.b_G[b];
-        if (key - p.b_koff[b] >= (int64_t)G * G * G) continue;
         const int64_t xo = p.b_poff[b];
         for (int c0 = s0; c0 < s1; c0 += kCellSortCap) {
             const int n = min(kCellSortCap, s1 - c0);
@@ -1389,6 +1382,31 @@ __global__ __launch_bounds__(256) void k_obj_cell_sort(const FovParams p, const 
             __syncthreads();
         }
     }
+}
+
+// The wide list, batch-major: batch b's wide objects are its wide slot of
+// the cell-sorted objects (sky-ordered, objects out of the join at the end,
+// where the wide join gives them no parts).  k_wide_count writes each
+// batch's count, a scan their offsets (wpos[B] = the total), k_wide_list
+// copies the slots, one wavefront per batch, and sets the list's length.
+__global__ void k_wide_count(const FovParams p, int32_t* __restrict__ cnt) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= p.n_batch) return;
+    const int G = p.b_G[b];
+    const int64_t kw = p.b_koff[b] + (int64_t)G * G * G;
+    cnt[b] = p.obj_start[kw + 1] - p.obj_start[kw];
+}
+__global__ void k_wide_list(const FovParams p, const int32_t* __restrict__ wpos) {
+    const int lane = threadIdx.x & 63;
+    const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t b = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; b < p.n_batch; b += n_waves) {
+        const int G = p.b_G[b];
+        const int64_t kw = p.b_koff[b] + (int64_t)G * G * G;
+        const int q0 = p.obj_start[kw], n = p.obj_start[kw + 1] - q0, w0 = wpos[b];
+        for (int q = lane; q < n; q += kWave)
+            p.wide[w0 + q] = ((unsigned long long)b << 32) | (unsigned long long)(unsigned)p.obj_sorted[q0 + q];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *p.n_wide = (unsigned long long)wpos[p.n_batch];
 }
 
 // One exact-test record per frame (layout at FovParams::exact_rec), so
@@ -1427,7 +1445,7 @@ __global__ void k_frame_exact_rec(const FovParams p) {
 // next trip's candidate key ahead, and stages its pairs in LDS so that the
 // shared pair counter takes one atomic per kPairBufEntries - 63 or more
 // pairs.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_fov_exact(const FovParams p) {
+__global__ __launch_bounds__(256) void k_fov_exact(const FovParams p) {
     __shared__ unsigned long long s_buf[4][kPairBufEntries];
     unsigned long long* buf = s_buf[threadIdx.x >> 6];
     int nbuf = 0;
@@ -1459,7 +1477,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
             const double* st = p.x_epoch + __double_as_longlong(r[11]) + 6 * (int64_t)j;
             double r0[3], v0[3];
             for (int k = 0; k < 3; ++k) { r0[k] = st[k] - r[5 + k]; v0[k] = st[3 + k] - r[8 + k]; }
-            SunCubic sun;
+            const EphemArgs& E = p.eph;
+            SunCubic sun = sun_table(E.coef, 0, E.deg1, E.t_start, E.seg_days, E.inv_seg, 0, E.n_seg - 1);
             sun.t0 = r[0];
             for (int k = 0; k < 3; ++k) {
                 sun.s[k] = r[12 + k];
@@ -1842,7 +1861,7 @@ __global__ __launch_bounds__(128) void k_directions(const FovParams p, const dou
     const double* st = x_ref + 6 * j;
     double r0[3] = {st[0] - S[0], st[1] - S[1], st[2] - S[2]};
     double v0[3] = {st[3] - Sd[0], st[4] - Sd[1], st[5] - Sd[2]};
-    const SunCubic sun_e = sun_cubic(E.coef, 0, E.deg1, t_obs[qn], E.t_start, E.seg_days, E.inv_seg, 0, E.n_seg - 1);
+    SunCubic sun_e = sun_cubic(E.coef, 0, E.deg1, t_obs[qn], E.t_start, E.seg_days, E.inv_seg, 0, E.n_seg - 1);
     double d[3], tau, ve[3];
     const int kst = lighttime(sun_e, p.mu, p.smu, p.c_light, p.lt_tol, p.lt_iter, t_ref, r0, v0, t_obs[qn],
                               obs + 3 * qn, d, tau, ve, nullptr, p.kepler_iter);
@@ -1942,6 +1961,11 @@ hipError_t fov_candidates(FovParams& p, int32_t* icnt, int32_t* istart, unsigned
     hipLaunchKernelGGL(k_item_scatter, dim3(gk), dim3(256), 0, s, p, (const int32_t*)icnt);
     if ((e = fill_zero(item_next, kJoinCursorWords * sizeof(unsigned int), s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_fov_cells, dim3((unsigned)(cu_count() * kJoinWaves)), dim3(256), 0, s, p);
+    // the wide list, with the join's item counts as scratch (free now)
+    hipLaunchKernelGGL(k_wide_count, dim3((unsigned)((p.n_batch + 255) / 256)), dim3(256), 0, s, p, icnt);
+    if ((e = exclusive_scan_i32(icnt, istart, p.n_batch, scan_scratch, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_wide_list, dim3((unsigned)std::min<int64_t>((p.n_batch + 3) / 4, 65536)), dim3(256), 0, s, p,
+                       (const int32_t*)istart);
     // parts per wide object: up to 32, fewer when the total could pass 2^31
     p.wide_max_parts = (int)std::max<int64_t>(1, std::min<int64_t>(32, (int64_t)(INT32_MAX - 1) / p.n_pairs_total));
     const unsigned gw = (unsigned)((p.n_pairs_total + 255) / 256);

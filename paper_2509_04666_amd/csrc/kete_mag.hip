@@ -65,7 +65,7 @@ __global__ __launch_bounds__(256) void k_pair_mag(const MagParams p, const int32
         double d[3], tau, ve[3];
         // a hop that ends on the Kepler iteration cap gives NaN, as a pair
         // outside the ephemeris does
-        const SunCubic sun_e = sun_cubic(E.coef, 0, E.deg1, tf, E.t_start, E.seg_days, E.inv_seg, 0, E.n_seg - 1);
+        SunCubic sun_e = sun_cubic(E.coef, 0, E.deg1, tf, E.t_start, E.seg_days, E.inv_seg, 0, E.n_seg - 1);
         const int kst = lighttime(sun_e, E.gm[0], p.smu, p.c_light, p.lt_tol, p.lt_iter, tr, r0, v0, tf,
                                   p.fobs + 3 * (int64_t)f, d, tau, ve, nullptr, p.kepler_iter);
         const double te = tf - tau;

@@ -81,6 +81,60 @@ def test_lighttime_matches_oracle(torch_cuda, orc):
     assert worst_ang < 1e-12 and worst_tau < 1e-15
 
 
+def test_lighttime_extreme_geometries(torch_cuda, orc):
+    """Bodies far and near, slow and fast, and hops of up to 8 days: distant
+    (40 au) and very distant (400 au) bodies, bodies 0.002 au from the
+    observer, a Sun-grazer near perihelion and fast hyperbolic bodies.  The
+    light time reaches 2.3 days for the farthest; the directions must match
+    the oracle's plain iteration to the same bar as the survey bodies."""
+    torch, api = torch_cuda
+    case = synth.survey_case(n_obj=1, n_frames=0)
+    rng = np.random.default_rng(13)
+    t_ref = 40.0
+    gm = synth.GM_SUN
+    sun = case.model.sun(np.array([t_ref]))[0]
+    rows = []
+    def add(r, v):
+        rows.append(np.concatenate([np.asarray(r, float) + sun[:3], np.asarray(v, float) + sun[3:]]))
+    for dist in (40.0, 400.0):
+        for _ in range(8):
+            u = rng.normal(size=3); u /= np.linalg.norm(u)
+            w = np.cross(u, rng.normal(size=3)); w /= np.linalg.norm(w)
+            add(dist * u, math.sqrt(gm / dist) * w * rng.uniform(0.5, 1.3))
+    for _ in range(8):                                   # fast hyperbolic bodies at 1-3 au
+        u = rng.normal(size=3); u /= np.linalg.norm(u)
+        w = rng.normal(size=3); w /= np.linalg.norm(w)
+        add(rng.uniform(1.0, 3.0) * u, rng.uniform(0.03, 0.08) * w)
+    for _ in range(4):                                   # Sun-grazers near perihelion
+        u = rng.normal(size=3); u /= np.linalg.norm(u)
+        w = np.cross(u, rng.normal(size=3)); w /= np.linalg.norm(w)
+        q = rng.uniform(0.02, 0.1)
+        add(q * u, math.sqrt(1.9 * gm / q) * w)
+    t_obs = t_ref + np.concatenate([rng.uniform(-8.0, 8.0, 6), [0.0, 1e-9]])
+    obs = synth.circular_observer(case.model, t_obs)
+    o_ref = synth.circular_observer(case.model, np.array([t_ref]))[0]
+    for _ in range(6):                                   # bodies 0.002 au from the observer at t_ref
+        u = rng.normal(size=3); u /= np.linalg.norm(u)
+        w = rng.normal(size=3); w /= np.linalg.norm(w)
+        rows.append(np.concatenate([o_ref + 0.002 * u, sun[3:] + 0.02 * w]))
+    states = np.array(rows)
+    eph = api.DeviceEphemeris.from_synth(case.ephem)
+    d, tau = api.lighttime_directions(eph, _dev_x(torch, states), t_ref, _dev_x(torch, t_obs), _dev_x(torch, obs))
+    d = d.cpu().numpy(); tau = tau.cpu().numpy()
+    worst_ang = worst_tau = 0.0
+    for q in range(t_obs.size):
+        dref, tref = orc.directions(case.ephem, states, t_ref, t_obs[q], obs[q])
+        assert np.all(np.isfinite(dref)) and np.all(np.isfinite(d[q]))
+        n1, n2 = np.linalg.norm(d[q], axis=1), np.linalg.norm(dref, axis=1)
+        cr = np.linalg.norm(np.cross(d[q], dref), axis=1) / n1 / n2
+        worst_ang = max(worst_ang, float(np.max(cr)))
+        worst_tau = max(worst_tau, float(np.max(np.abs(tau[q] - tref))))
+        np.testing.assert_allclose(d[q], dref, rtol=1e-14, atol=1e-13)
+    _say(f"light-time (extreme geometries) max angle {worst_ang:.3e} rad, max |dtau| {worst_tau:.3e} d, "
+         f"max tau {tau.max():.3f} d")
+    assert worst_ang < 1e-12 and worst_tau < 3e-15
+
+
 # ---------------------------------------------------------------- propagation
 def _propagate_both(torch, api, orc, ephem, x0, t0, t_out, **opts):
     eph = api.DeviceEphemeris.from_synth(ephem)
