@@ -97,6 +97,42 @@ __global__ __launch_bounds__(256) void k_frame_caps(const double* __restrict__ n
     }
 }
 
+// The same caps with one lane per frame, for frames of a few sub-frames
+// (a wavefront per frame would leave most of its lanes idle).
+__global__ void k_frame_caps_lane(const double* __restrict__ normals, int64_t n_frames, int n_sub,
+                                  double* __restrict__ cap) {
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= n_frames) return;
+    double sum[3] = {0.0, 0.0, 0.0};
+    for (int sf = 0; sf < n_sub; ++sf) {
+        const double* n = normals + (f * n_sub + sf) * 12;
+        for (int k = 0; k < 4; ++k) {
+            double v[3];
+            quad_vertex(n, k, v);
+            const double vn = sqrt(dot3(v, v));
+            for (int c = 0; c < 3; ++c) sum[c] += v[c] / vn;
+        }
+    }
+    const double sn = sqrt(dot3(sum, sum));
+    double ctr[3] = {sum[0] / sn, sum[1] / sn, sum[2] / sn};
+    double cmin = 1.0;
+    for (int sf = 0; sf < n_sub; ++sf) {
+        const double* n = normals + (f * n_sub + sf) * 12;
+        for (int k = 0; k < 4; ++k) {
+            double v[3];
+            quad_vertex(n, k, v);
+            cmin = fmin(cmin, dot3(v, ctr) / sqrt(dot3(v, v)));
+        }
+    }
+    cmin -= 1e-12;                       // rounding margin (radius grows)
+    if (!(sn > 0.0) || !(cmin > -1.0)) { ctr[0] = 1.0; ctr[1] = ctr[2] = 0.0; cmin = -1.0; }
+    double* o = cap + 8 * f;
+    o[0] = ctr[0]; o[1] = ctr[1]; o[2] = ctr[2];
+    o[3] = cmin;
+    o[4] = sqrt(fmax(0.0, 1.0 - cmin * cmin));
+    o[5] = o[6] = o[7] = 0.0;
+}
+
 // Sub-frame locator of every frame (see kLocStride), in cell order, one
 // wavefront per frame with a lane per sub-frame (and 64 + lane).  The
 // gnomonic image of a quadrilateral with great-circle edges inside the
@@ -1337,50 +1373,71 @@ __global__ void k_obj_scatter(const FovParams p, const int32_t* __restrict__ oke
 // two items' worth of objects are left as they are.  Each batch's wide slot
 // is ordered the same way by its coarse sky key.
 constexpr int kCellSortCap = 4096;
+
+// One cell's objects sorted[s0, s1) by sub-cell key, by the whole block.
+__device__ __forceinline__ void sort_cell(int s0, int s1, int64_t xo, int32_t* __restrict__ sorted,
+                                          const int32_t* __restrict__ osub, int32_t* sj, int32_t* sk, int* cnt,
+                                          int* wsum) {
+    constexpr int kPer = kSubKeys / 256;
+    static_assert(kPer * 256 == kSubKeys, "whole keys per thread");
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    for (int c0 = s0; c0 < s1; c0 += kCellSortCap) {
+        const int n = min(kCellSortCap, s1 - c0);
+        for (int k = tid; k < kSubKeys; k += 256) cnt[k] = 0;
+        __syncthreads();
+        for (int i = tid; i < n; i += 256) {
+            const int j = sorted[c0 + i];
+            const int k = osub[xo + j];
+            sj[i] = j;
+            sk[i] = k;
+            atomicAdd(&cnt[k], 1);
+        }
+        __syncthreads();
+        int c[kPer], tot = 0;
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) { c[q] = cnt[kPer * tid + q]; tot += c[q]; }
+        int incl = tot;
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const int t = __shfl_up(incl, off, kWave);
+            if (lane >= off) incl += t;
+        }
+        if (lane == kWave - 1) wsum[wv] = incl;
+        __syncthreads();
+        int run = incl - tot;
+        for (int w = 0; w < wv; ++w) run += wsum[w];
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) { cnt[kPer * tid + q] = run; run += c[q]; }
+        __syncthreads();
+        for (int i = tid; i < n; i += 256) sorted[c0 + atomicAdd(&cnt[sk[i]], 1)] = sj[i];
+        __syncthreads();
+    }
+}
+
 __global__ __launch_bounds__(256) void k_obj_cell_sort(const FovParams p, const int32_t* __restrict__ start,
                                                       int32_t* __restrict__ sorted, const int32_t* __restrict__ osub) {
     __shared__ int32_t sj[kCellSortCap], sk[kCellSortCap];
     __shared__ int cnt[kSubKeys];
     __shared__ int wsum[4];
-    constexpr int kPer = kSubKeys / 256;
-    static_assert(kPer * 256 == kSubKeys, "whole keys per thread");
+    __shared__ unsigned long long s_need[4];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    for (int64_t key = blockIdx.x; key < p.n_keys; key += gridDim.x) {
-        const int s0 = start[key], s1 = start[key + 1];
-        if (s1 - s0 <= 2 * kWave) continue;
-        const int b = batch_of_key(p.b_koff, p.n_batch, key);
-        const int64_t xo = p.b_poff[b];
-        for (int c0 = s0; c0 < s1; c0 += kCellSortCap) {
-            const int n = min(kCellSortCap, s1 - c0);
-            for (int k = tid; k < kSubKeys; k += 256) cnt[k] = 0;
-            __syncthreads();
-            for (int i = tid; i < n; i += 256) {
-                const int j = sorted[c0 + i];
-                const int k = osub[xo + j];
-                sj[i] = j;
-                sk[i] = k;
-                atomicAdd(&cnt[k], 1);
+    // the block's threads look at 256 keys at once; the keys with more
+    // than two items' worth of objects are then sorted one after another
+    for (int64_t k0 = (int64_t)blockIdx.x * 256; k0 < p.n_keys; k0 += (int64_t)gridDim.x * 256) {
+        const int64_t kt = k0 + tid;
+        const bool need = kt < p.n_keys && start[kt + 1] - start[kt] > 2 * kWave;
+        const unsigned long long m = __ballot(need);
+        if (lane == 0) s_need[wv] = m;
+        __syncthreads();
+        unsigned long long need_w[4];
+        for (int q = 0; q < 4; ++q) need_w[q] = s_need[q];
+        __syncthreads();
+        for (int q = 0; q < 4; ++q)
+            for (unsigned long long mm = need_w[q]; mm != 0ull; mm &= mm - 1ull) {
+                const int64_t key = k0 + 64 * q + (__ffsll((long long)mm) - 1);
+                const int b = batch_of_key(p.b_koff, p.n_batch, key);
+                sort_cell(start[key], start[key + 1], p.b_poff[b], sorted, osub, sj, sk, cnt, wsum);
             }
-            __syncthreads();
-            int c[kPer], tot = 0;
-#pragma unroll
-            for (int q = 0; q < kPer; ++q) { c[q] = cnt[kPer * tid + q]; tot += c[q]; }
-            int incl = tot;
-#pragma unroll
-            for (int off = 1; off < kWave; off <<= 1) {
-                const int t = __shfl_up(incl, off, kWave);
-                if (lane >= off) incl += t;
-            }
-            if (lane == kWave - 1) wsum[wv] = incl;
-            __syncthreads();
-            int run = incl - tot;
-            for (int w = 0; w < wv; ++w) run += wsum[w];
-#pragma unroll
-            for (int q = 0; q < kPer; ++q) { cnt[kPer * tid + q] = run; run += c[q]; }
-            __syncthreads();
-            for (int i = tid; i < n; i += 256) sorted[c0 + atomicAdd(&cnt[sk[i]], 1)] = sj[i];
-            __syncthreads();
-        }
     }
 }
 
@@ -1891,7 +1948,10 @@ hipError_t fov_prepare(const FovParams& p, int32_t* qkey, int32_t* cnt, int32_t*
     hipError_t e;
     // one wavefront per frame, four per block
     const unsigned gw = (unsigned)std::min<int64_t>((F + 3) / 4, 65536);
-    if (F > 0) hipLaunchKernelGGL(k_frame_caps, dim3(gw), dim3(256), 0, s, p.normals, F, p.n_sub, p.fcap);
+    if (F > 0 && p.n_sub >= 8)
+        hipLaunchKernelGGL(k_frame_caps, dim3(gw), dim3(256), 0, s, p.normals, F, p.n_sub, p.fcap);
+    else if (F > 0)
+        hipLaunchKernelGGL(k_frame_caps_lane, dim3(gF), dim3(256), 0, s, p.normals, F, p.n_sub, p.fcap);
     if (p.n_batch > 0) hipLaunchKernelGGL(k_batch_prep, dim3((unsigned)p.n_batch), dim3(256), 0, s, p);
     if ((e = fill_zero(cnt, (size_t)(n_keys + 1) * sizeof(int32_t), s)) != hipSuccess) return e;
     if (F > 0) hipLaunchKernelGGL(k_frame_keys, dim3(gF), dim3(256), 0, s, p, qkey, cnt);
