@@ -280,7 +280,8 @@ void kete_fov_last_stats(int64_t out[4]);
  * the Kepler iteration cap, out[7] 0. */
 void kete_fov_last_counts(int64_t out[8]);
 
-/* Bytes of workspace needed by kete_pair_magnitudes (0 for a bad size). */
+/* Bytes of workspace needed by kete_pair_magnitudes (0 for a bad size):
+ * a frame-to-batch map and one 192-byte record per frame. */
 size_t kete_magnitudes_workspace_size(int64_t n_frames);
 
 /* Apparent V magnitude of every (frame, object) pair in the H-G system
@@ -320,7 +321,9 @@ int kete_pair_magnitudes(const kete_ephem_t *eph, const double *x_epoch, int64_t
  * each device (the current device must be the one `stream` belongs to).
  * The call allocates nothing and calls no allocating routine; the map is
  * refilled by a kernel on every call, so the last call's contents do not
- * leak into the next.  Calls that overlap in time on one GPU (on
+ * leak into the next.  With no room for kete_pair_magnitudes' per-frame
+ * records, each pair computes its frame's quantities itself: slower, with
+ * the same results bit for bit.  Calls that overlap in time on one GPU (on
  * different streams or threads) share the array and race: serialize them.
  * Errors: KETE_EWORKSPACE when n_frames exceeds
  * KETE_MAG_NOALLOC_MAX_FRAMES, otherwise as kete_pair_magnitudes. */

@@ -1683,7 +1683,7 @@ int pair_magnitudes_impl(const kete_ephem_t* eph, const double* x_epoch, int64_t
     P.kepler_iter = opts->kepler_iter > 0 ? opts->kepler_iter : kKeplerIterDefault;
     P.t_lo = eph->t_start;
     P.t_hi = t_end_of(eph);
-    HIPCHK(launch_pair_mag(P, workspace, (hipStream_t)stream));
+    HIPCHK(launch_pair_mag(P, workspace, !static_scratch, (hipStream_t)stream));
     return KETE_OK;
 }
 

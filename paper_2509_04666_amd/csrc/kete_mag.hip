@@ -46,7 +46,49 @@ __global__ void k_mag_frame_batch(const MagParams p, int32_t* __restrict__ fb) {
     if (f >= 0 && f < p.n_frames) fb[f] = lo;
 }
 
-__global__ __launch_bounds__(256) void k_pair_mag(const MagParams p, const int32_t* __restrict__ fb) {
+// What a pair needs of its frame, computed once per frame when the caller's
+// workspace has room (kMagRec doubles): frame time, batch epoch, observer,
+// the Sun's position and velocity at the epoch, and its cubic about the
+// frame time.  Frames outside every batch get a NaN epoch.
+__device__ __forceinline__ void mag_frame_quantities(const MagParams& p, int b, int64_t f, double* R) {
+    const EphemArgs& E = p.eph;
+    const double tr = p.t_ref[b], tf = p.ft[f];
+    // the Sun at the epoch from the same chunked evaluation as its cubic
+    // about the frame time: a few rounds of coefficient loads, not one
+    // dependent load per coefficient
+    const SunCubic s_ref = sun_cubic(E.coef, 0, E.deg1, tr, E.t_start, E.seg_days, E.inv_seg, 0, E.n_seg - 1);
+    const SunCubic s_f = sun_cubic(E.coef, 0, E.deg1, tf, E.t_start, E.seg_days, E.inv_seg, 0, E.n_seg - 1);
+    R[0] = tf;
+    R[1] = tr;
+    for (int k = 0; k < 3; ++k) {
+        R[2 + k] = p.fobs[3 * f + k];
+        R[5 + k] = s_ref.s[k];
+        R[8 + k] = s_ref.v[k];
+        R[11 + k] = s_f.s[k];
+        R[14 + k] = s_f.v[k];
+        R[17 + k] = s_f.a[k];
+        R[20 + k] = s_f.j[k];
+    }
+    R[23] = 0.0;
+}
+
+__global__ void k_mag_frame_rec(const MagParams p, const int32_t* __restrict__ fb, double* __restrict__ rec) {
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= p.n_frames) return;
+    double* R = rec + (size_t)kMagRec * f;
+    const int b = fb[f];
+    if (b < 0) {
+        for (int k = 0; k < kMagRec; ++k) R[k] = kNaN;
+        return;
+    }
+    mag_frame_quantities(p, b, f, R);
+}
+
+// One lane per pair; the frame's quantities come from its record when
+// there is one (rec), else the lane computes them (the same functions, so
+// the results are the same bits).
+__global__ __launch_bounds__(256) void k_pair_mag(const MagParams p, const int32_t* __restrict__ fb,
+                                                 const double* __restrict__ rec) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= p.n_pairs) return;
     const int32_t f = p.pf[i], j = p.po[i];
@@ -54,26 +96,41 @@ __global__ __launch_bounds__(256) void k_pair_mag(const MagParams p, const int32
     double v = kNaN, rh = kNaN, dl = kNaN, al = kNaN;
     if (b >= 0 && j >= 0 && j < p.n_obj) {
         const EphemArgs& E = p.eph;
-        const double tr = p.t_ref[b], tf = p.ft[f];
-        // the Sun at the epoch from the same chunked evaluation as its cubic
-        // about the frame time: a few rounds of coefficient loads, not one
-        // dependent load per coefficient
-        const SunCubic s_ref = sun_cubic(E.coef, 0, E.deg1, tr, E.t_start, E.seg_days, E.inv_seg, 0, E.n_seg - 1);
+        double R[kMagRec];
+        if (rec) {
+            const double2* q = reinterpret_cast<const double2*>(rec + (size_t)kMagRec * f);
+#pragma unroll
+            for (int k = 0; k < kMagRec / 2; ++k) {
+                const double2 w = q[k];
+                R[2 * k] = w.x;
+                R[2 * k + 1] = w.y;
+            }
+        } else {
+            mag_frame_quantities(p, b, f, R);
+        }
+        const double tf = R[0], tr = R[1];
         const double* st = p.x_epoch + 6 * ((int64_t)b * p.n_obj + j);
-        const double r0[3] = {st[0] - s_ref.s[0], st[1] - s_ref.s[1], st[2] - s_ref.s[2]};
-        const double v0[3] = {st[3] - s_ref.v[0], st[4] - s_ref.v[1], st[5] - s_ref.v[2]};
+        const double r0[3] = {st[0] - R[5], st[1] - R[6], st[2] - R[7]};
+        const double v0[3] = {st[3] - R[8], st[4] - R[9], st[5] - R[10]};
+        SunCubic sun_e = sun_table(E.coef, 0, E.deg1, E.t_start, E.seg_days, E.inv_seg, 0, E.n_seg - 1);
+        sun_e.t0 = tf;
+        for (int k = 0; k < 3; ++k) {
+            sun_e.s[k] = R[11 + k];
+            sun_e.v[k] = R[14 + k];
+            sun_e.a[k] = R[17 + k];
+            sun_e.j[k] = R[20 + k];
+        }
+        const double o[3] = {R[2], R[3], R[4]};
         double d[3], tau, ve[3];
         // a hop that ends on the Kepler iteration cap gives NaN, as a pair
         // outside the ephemeris does
-        SunCubic sun_e = sun_cubic(E.coef, 0, E.deg1, tf, E.t_start, E.seg_days, E.inv_seg, 0, E.n_seg - 1);
-        const int kst = lighttime(sun_e, E.gm[0], p.smu, p.c_light, p.lt_tol, p.lt_iter, tr, r0, v0, tf,
-                                  p.fobs + 3 * (int64_t)f, d, tau, ve, nullptr, p.kepler_iter);
+        const int kst = lighttime(sun_e, E.gm[0], p.smu, p.c_light, p.lt_tol, p.lt_iter, tr, r0, v0, tf, o, d,
+                                  tau, ve, nullptr, p.kepler_iter);
         const double te = tf - tau;
         if (kst == 0 && te >= p.t_lo && te <= p.t_hi) {
             // heliocentric emission point r = (d + o) - S(te)
             double Se[3], Sde[3];
             sun_e.eval(te, Se, Sde);
-            const double* o = p.fobs + 3 * (int64_t)f;
             const double r[3] = {d[0] + o[0] - Se[0], d[1] + o[1] - Se[1], d[2] + o[2] - Se[2]};
             const double c = dot3(r, d);
             const double cx = r[1] * d[2] - r[2] * d[1];
@@ -133,22 +190,32 @@ hipError_t mag_static_scratch(void** ptr) {
     return hipSuccess;
 }
 
-size_t mag_workspace_bytes(int64_t n_frames) {
+static size_t mag_map_bytes(int64_t n_frames) {
     return ((size_t)std::max<int64_t>(n_frames, 1) * sizeof(int32_t) + 255) & ~(size_t)255;
 }
 
-hipError_t launch_pair_mag(const MagParams& p, void* ws, hipStream_t s) {
+size_t mag_workspace_bytes(int64_t n_frames) {
+    const size_t rec = (size_t)std::max<int64_t>(n_frames, 1) * kMagRec * sizeof(double);
+    return mag_map_bytes(n_frames) + ((rec + 255) & ~(size_t)255);
+}
+
+hipError_t launch_pair_mag(const MagParams& p, void* ws, bool frame_records, hipStream_t s) {
     int32_t* fb = static_cast<int32_t*>(ws);
+    double* rec = frame_records ? reinterpret_cast<double*>(static_cast<char*>(ws) + mag_map_bytes(p.n_frames))
+                                : nullptr;
     if (p.n_frames > 0) {
         const unsigned g = (unsigned)std::min<int64_t>((p.n_frames + 255) / 256, 4096);
         hipLaunchKernelGGL(k_mag_fill, dim3(g), dim3(256), 0, s, fb, p.n_frames);
         if (p.n_batch > 0)
             hipLaunchKernelGGL(k_mag_frame_batch, dim3((unsigned)((p.n_frames + 255) / 256)), dim3(256), 0, s, p,
                                fb);
+        if (rec)
+            hipLaunchKernelGGL(k_mag_frame_rec, dim3((unsigned)((p.n_frames + 255) / 256)), dim3(256), 0, s, p,
+                               (const int32_t*)fb, rec);
     }
     if (p.n_pairs > 0)
         hipLaunchKernelGGL(k_pair_mag, dim3((unsigned)((p.n_pairs + 255) / 256)), dim3(256), 0, s, p,
-                           (const int32_t*)fb);
+                           (const int32_t*)fb, (const double*)rec);
     return hipGetLastError();
 }
 

@@ -32,6 +32,9 @@ struct MagParams {
     double t_lo, t_hi;          // ephemeris span
 };
 
+// Doubles of a frame's record (the quantities every pair of the frame uses).
+constexpr int kMagRec = 24;
+// Workspace: the frame-to-batch map, then the frame records.
 size_t mag_workspace_bytes(int64_t n_frames);
 
 // Frames covered by the static frame-to-batch map (4 bytes per frame).
@@ -39,6 +42,9 @@ constexpr int64_t kMagScratchFrames = KETE_MAG_NOALLOC_MAX_FRAMES;
 // Device address of that map on the current device, looked up on the
 // first call per device and kept.
 hipError_t mag_static_scratch(void** ptr);
-hipError_t launch_pair_mag(const MagParams& p, void* ws, hipStream_t s);
+// ws: the map, and the frame records after it when frame_records (the
+// static map of the entry point that allocates nothing has no room for
+// them: its pairs compute their frame's quantities themselves).
+hipError_t launch_pair_mag(const MagParams& p, void* ws, bool frame_records, hipStream_t s);
 
 }  // namespace kete
