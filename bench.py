@@ -575,6 +575,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-strict", action="store_true")
     ap.add_argument("--no-magnitudes", action="store_true")
+    ap.add_argument("--head-streams", type=int, default=0,
+                    help="streams the headline steps alternate over (0: the workload's default)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="copy a buffer of this size once before timing (HBM counter calibration)")
     args = ap.parse_args()
@@ -601,7 +603,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    head = Workload(api, torch, head_case, 1 if head_case.name == "footprint" else 2, log)
+    head_streams = args.head_streams if args.head_streams > 0 else (1 if head_case.name == "footprint" else 2)
+    head = Workload(api, torch, head_case, head_streams, log)
     hrec = head.measure(args.steps, args.warmup)
     components = {}
     if head_case.name == "footprint" and not args.no_magnitudes:
