@@ -451,6 +451,38 @@ def test_fov_given_oracle_states(torch_cuda, orc):
     assert len(opairs[0]) > 200
 
 
+def test_fov_distant_bodies(torch_cuda, orc):
+    """Bodies from 30 au to 400 au (light times up to 2.3 days, where the
+    exact test's Sun cubic is re-expanded about each body's emission time)
+    among main-belt bodies, with frames aimed at them: the pair sets must
+    match the oracle's."""
+    torch, api = torch_cuda
+    case = synth.tiny_case(n_obj=600, n_frames=40)
+    rng = np.random.default_rng(16)
+    n_far = 240
+    a = np.concatenate([rng.uniform(30.0, 60.0, n_far - 40), rng.uniform(150.0, 400.0, 40)])
+    e = rng.uniform(0.0, 0.2, n_far)
+    inc = rng.rayleigh(math.radians(10.0), n_far)
+    ang = rng.uniform(0.0, 2.0 * np.pi, (3, n_far))
+    el_far = np.stack([a, e, inc, ang[0], ang[1], ang[2]], axis=1)
+    x_far = synth.bodies_from_elements(case.model, el_far, 0.0)
+    x0 = np.concatenate([case.x0, x_far])
+    fr = synth.Frames.concat([case.frames, synth.frames_targeted(rng, case.model, el_far, 0.0, case.span, 160)])
+    fr = fr.subset(np.argsort(fr.t, kind="stable"))
+    case = synth.PropagationCase("tiny-far", case.ephem, case.model, x0, None, np.zeros(x0.shape[0], bool), 0.0,
+                                 case.span, fr, 16)
+    order, off, t_ref = orc.make_batches(fr.t)
+    xe, st, _ = orc.propagate(case.ephem, x0, 0.0, t_ref)
+    opairs = orc.fov(case.ephem, xe, st, order, off, t_ref, fr.t, fr.obs, fr.normals)
+    gp = _fov_case(torch, api, orc, case, xe, order, off, t_ref)
+    extra = _compare_pairs(gp, opairs[:3], opairs[3], "distant bodies given oracle states")
+    for p in extra:
+        assert abs(_edge_of(orc, case.ephem, xe, order, off, t_ref, fr, p)) < MAS
+    far_pairs = int(np.sum(np.asarray(opairs[2]) >= 600))
+    _say(f"pairs of the distant bodies: {far_pairs}")
+    assert far_pairs > 100
+
+
 def test_fov_full_chain_tiny(torch_cuda, orc):
     torch, api = torch_cuda
     case = synth.tiny_case(n_obj=1000, n_frames=100, n_targeted=300)
