@@ -549,6 +549,26 @@ __device__ __forceinline__ double lin_predict(const ObjBounds& o, const double o
     return 2.0 * (o.vbn * o.taumax + 0.5 * (o.a2b + Asun) * ad * ad + 1e-12);
 }
 
+// The same prediction carried back over the light time as well, for the
+// sub-frame tests: with u0 = x + v dt - o and tau0 = |u0| / c,
+// ul = u0 - v tau0 (the straight line at t - tau0).  The body's position
+// at the emission time t - tau is within eps0 = |v| tau_max + a ad^2 / 2
+// of x + v dt (a the acceleration bound, ad = |dt| + tau_max), so |tau -
+// tau0| <= eps0 / c, and it is within a ad^2 / 2 + |v| eps0 / c of ul: the
+// light-time term |v| tau_max, which dominates eps0 for most bodies, is
+// scaled down by |v| / c.  Returns the bound, doubled as lin_predict's.
+__device__ __forceinline__ double lin_predict_lt(const ObjBounds& o, const double ob[4], double tr, double Asun,
+                                                 double c_light, double ul[3]) {
+    const double dt = ob[0] - tr;
+    double u0[3];
+    for (int c = 0; c < 3; ++c) u0[c] = o.x[c] + o.v[c] * dt - ob[1 + c];
+    const double tau0 = sqrt(dot3(u0, u0)) / c_light;
+    for (int c = 0; c < 3; ++c) ul[c] = u0[c] - o.v[c] * tau0;
+    const double ad = fabs(dt) + o.taumax;
+    const double acc = 0.5 * (o.a2b + Asun) * ad * ad;
+    return 2.0 * (acc + o.vbn * (o.vbn * o.taumax + acc) / c_light + 1e-12);
+}
+
 // Can a line of sight within e2 of ul reach the frame's cap (centre cp,
 // cos and sin of the radius R)?  Its angle from ul is at most
 // asin(e2 / |ul|), so it misses the cap when the angle of ul from the centre
@@ -688,7 +708,7 @@ __device__ void classify_emit(const FovParams& p, bool has, const ObjBounds& o, 
         all = !o.lin_ok;
         if (o.lin_ok) {
             const double ob[4] = {ob01.x, ob01.y, ob23.x, ob23.y};
-            e2 = lin_predict(o, ob, tr, Asun, ul);
+            e2 = lin_predict_lt(o, ob, tr, Asun, p.c_light, ul);
             const double u2 = dot3(ul, ul);
             if (!(e2 * e2 < u2)) {
                 all = true;

@@ -4,6 +4,7 @@ against the CPU oracle on the same seeded inputs.
 Tolerances: positions within 1e-10 au after a year of integration; the
 light-time direction from a given state within 1e-12 rad; pair sets
 identical except pairs whose oracle edge distance is below 1 mas."""
+import dataclasses
 import math
 import sys
 
@@ -561,9 +562,31 @@ def test_kepler_cap_forced_from_the_host(torch_cuda, orc):
     torch, api = torch_cuda
     from paper_2509_04666_amd import _lib
     case = synth.tiny_case(n_obj=400, n_frames=40, n_targeted=120)
-    fr = case.frames
+    # 24 more frames, each with an edge through the oracle's apparent
+    # direction of one body: no motion bound decides such a pair, so each
+    # of these bodies needs a hop
+    rng = np.random.default_rng(11)
+    pick = rng.choice(400, 24, replace=False)
+    te = rng.uniform(1.0, case.span - 1.0, 24)
+    oe = synth.circular_observer(case.model, te)
+    h = np.full(24, math.radians(0.75))
+    nrm = np.zeros((24, 1, 4, 3))
+    fr = synth.Frames.concat([case.frames, synth.Frames(te, oe, None, None, None, None, None, nrm)])
+    srt = np.argsort(fr.t, kind="stable")
+    fr = fr.subset(srt)
     order, off, t_ref = orc.make_batches(fr.t)
     xe, st, _ = orc.propagate(case.ephem, case.x0, 0.0, t_ref)
+    pos = np.argsort(srt)[case.frames.t.size:]      # where the new frames went
+    for k, f in enumerate(pos):
+        b = int(np.searchsorted(off, int(np.nonzero(order == f)[0][0]), side="right") - 1)
+        d = orc.lighttime(case.ephem, t_ref[b], xe[b, pick[k]], fr.t[f], fr.obs[f])[1]
+        d = d / np.linalg.norm(d)
+        e = synth.tangent_basis(d)[0]
+        c = math.cos(h[k]) * d + math.sin(h[k]) * e
+        u = math.cos(h[k]) * e - math.sin(h[k]) * d
+        fr.normals[f, 0] = synth.rect_normals(c, u, np.cross(c, u), h[k], h[k])
+        assert abs(fr.normals[f, 0, 1] @ d) < 1e-15
+    case = dataclasses.replace(case, frames=fr)
     eph = api.DeviceEphemeris.from_synth(case.ephem)
     dfr = api.DeviceFrames.from_synth(fr)
     b = api.Batches.from_host(order.astype(np.int32), off.astype(np.int32), t_ref)
@@ -580,7 +603,7 @@ def test_kepler_cap_forced_from_the_host(torch_cuda, orc):
     s1h = s1.cpu().numpy()
     had = np.unique(po.cpu().numpy())
     _say(f"kepler cap 1: {pf1.numel()} pairs, {np.count_nonzero(s1h)} objects flagged, {had.size} had pairs")
-    assert np.count_nonzero(s1h) > 0
+    assert np.count_nonzero(s1h) > 0 and np.all(s1h[pick] != 0)
     assert set(np.unique(s1h).tolist()) <= {0, _lib.ST_KEPLER_NOCONV}
     kept = set(zip(pf1.cpu().tolist(), ps1.cpu().tolist(), po1.cpu().tolist()))
     assert kept <= set(zip(pf.cpu().tolist(), ps.cpu().tolist(), po.cpu().tolist()))
