@@ -1694,9 +1694,39 @@ __global__ void k_pair_sort_small(unsigned long long* __restrict__ keys, const i
 // (the fewest passes of at most kMaxRadixBits, see radix_digit_bits)
 // counts its digits with LDS atomics, scans the counts, then scatters the
 // keys 64 at a time in order, a key's rank among the lanes sharing its
-// digit coming from rb ballots, so equal digits keep their order.
+// digit coming from that digit's lane mask, so equal digits keep their
+// order.
 constexpr int kMaxRadixBits = 8;
 constexpr int kRadixBuckets = 1 << kMaxRadixBits;
+
+// Scatter of one chunk of up to 64 keys (lane l holds key k of digit d
+// when v) to B at the digit cursors cnt, keeping the lanes' order among
+// equal digits.  The lanes sharing a digit find each other through mk, a
+// per-wavefront array of one 64-bit lane mask per digit that is all zero
+// on entry and on exit: each lane ORs its bit into its digit's mask, reads
+// the mask and the cursor back, and the lowest lane of each digit advances
+// the cursor and clears the mask.  LDS instructions of one wavefront run in
+// order, so the reads see every lane's OR and the old cursor; the fences
+// only keep the compiler from reordering them.
+__device__ __forceinline__ void radix_scatter_chunk(bool v, unsigned k, unsigned d, int* cnt,
+                                                    unsigned long long* mk, unsigned* B, unsigned long long lt) {
+    const int lane = threadIdx.x & 63;
+    if (v) atomicOr(mk + d, 1ull << lane);
+    wave_lds_sync();
+    unsigned long long m = 0ull;
+    int base = 0;
+    if (v) {
+        m = mk[d];
+        base = cnt[d];
+    }
+    wave_lds_sync();
+    if (v && (m & lt) == 0ull) {
+        cnt[d] = base + __popcll(m);
+        mk[d] = 0ull;
+    }
+    if (v) B[base + __popcll(m & lt)] = k;
+    wave_lds_sync();
+}
 
 template <int kCap, int kWaves>
 __global__ __launch_bounds__(64 * kWaves) void k_pair_sort_radix(const unsigned long long* __restrict__ keys,
@@ -1706,10 +1736,14 @@ __global__ __launch_bounds__(64 * kWaves) void k_pair_sort_radix(const unsigned 
                                                                 int32_t* __restrict__ po) {
     __shared__ unsigned sh_a[kWaves][kCap], sh_b[kWaves][kCap];
     __shared__ int sh_cnt[kWaves][kRadixBuckets];
+    __shared__ unsigned long long sh_mk[kWaves][kRadixBuckets];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const unsigned omask = ob >= 32 ? ~0u : ((1u << ob) - 1u);
     int* cnt = sh_cnt[wv];
+    unsigned long long* mk = sh_mk[wv];
+    for (int d = lane; d < kRadixBuckets; d += kWave) mk[d] = 0ull;
+    wave_lds_sync();
     for (int64_t f = (int64_t)blockIdx.x * kWaves + wv; f < n_frames; f += (int64_t)gridDim.x * kWaves) {
         const int a0 = fstart[f], n = fstart[f + 1] - a0;
         if (n <= lo_n || n > kCap) continue;
@@ -1745,24 +1779,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_pair_sort_radix(const unsigned 
                 const int i = i0 + lane;
                 const bool v = i < n;
                 const unsigned k = v ? A[i] : 0u;
-                const unsigned d = (k >> shift) & dm;
-                unsigned long long m = __ballot(v);
-                for (int bit = 0; bit < rb; ++bit) {
-                    const bool set = (d >> bit) & 1u;
-                    const unsigned long long bb = __ballot(set);
-                    m &= set ? bb : ~bb;
-                }
-                // m: the valid lanes holding this lane's digit; the lowest
-                // one advances the digit's cursor for all of them
-                const int leader = m ? __ffsll((long long)m) - 1 : 0;
-                int base = 0;
-                if (v && lane == leader) {
-                    base = cnt[d];
-                    cnt[d] = base + __popcll(m);
-                }
-                base = __shfl(base, leader, kWave);
-                if (v) B[base + __popcll(m & lt)] = k;
-                wave_lds_sync();
+                radix_scatter_chunk(v, k, (k >> shift) & dm, cnt, mk, B, lt);
             }
             unsigned* t = A;
             A = B;
@@ -1792,8 +1809,11 @@ __global__ __launch_bounds__(64 * kSortWaves) void k_pair_sort_radix_block(
     int ob, int bits, int rb, int32_t* __restrict__ pf, int32_t* __restrict__ ps, int32_t* __restrict__ po) {
     __shared__ unsigned sh_a[kCap], sh_b[kCap];
     __shared__ int cnt[kSortWaves][kRadixBuckets];
+    __shared__ unsigned long long sh_mk[kSortWaves][kRadixBuckets];
     __shared__ int wsum[kSortWaves];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    for (int d = lane; d < kRadixBuckets; d += kWave) sh_mk[wv][d] = 0ull;
+    wave_lds_sync();
     const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const unsigned omask = ob >= 32 ? ~0u : ((1u << ob) - 1u);
     constexpr int kPerT = kRadixBuckets / (64 * kSortWaves);      // digits per thread in the cursor scan
@@ -1844,22 +1864,7 @@ __global__ __launch_bounds__(64 * kSortWaves) void k_pair_sort_radix_block(
                 const int i = i0 + lane;
                 const bool v = i < qb;
                 const unsigned k = v ? A[i] : 0u;
-                const unsigned d = (k >> shift) & dm;
-                unsigned long long m = __ballot(v);
-                for (int bit = 0; bit < rb; ++bit) {
-                    const bool set = (d >> bit) & 1u;
-                    const unsigned long long bb = __ballot(set);
-                    m &= set ? bb : ~bb;
-                }
-                const int leader = m ? __ffsll((long long)m) - 1 : 0;
-                int base = 0;
-                if (v && lane == leader) {
-                    base = cnt[wv][d];
-                    cnt[wv][d] = base + __popcll(m);
-                }
-                base = __shfl(base, leader, kWave);
-                if (v) B[base + __popcll(m & lt)] = k;
-                wave_lds_sync();
+                radix_scatter_chunk(v, k, (k >> shift) & dm, cnt[wv], sh_mk[wv], B, lt);
             }
             __syncthreads();
             unsigned* t = A;
