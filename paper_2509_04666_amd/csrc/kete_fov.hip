@@ -856,7 +856,7 @@ constexpr int kItemChunk = 3;
 // one take the locator-box test, a global read.  Items are in (batch, cell) order; the waves of
 // one XCD start on their own slice of the list, so that neighbouring cells
 // share that XCD's L2, and help the other slices when theirs runs out.
-constexpr int kJoinWaves = 3;        // resident waves per SIMD of the join kernels (no register spills)
+constexpr int kJoinWaves = 3;        // resident waves per SIMD of the join kernels (168 VGPRs, a few spilled)
 __global__ __launch_bounds__(256, kJoinWaves) void k_fov_cells(const FovParams p) {
     const int lane = threadIdx.x & 63, wv = (threadIdx.x >> 6) & 3;
     unsigned long long n_cand = 0, n_exact = 0, n_visit = 0;
@@ -1728,13 +1728,22 @@ __device__ __forceinline__ void radix_scatter_chunk(bool v, unsigned k, unsigned
     wave_lds_sync();
 }
 
+// A key of a frame's segment as the radix sorts order it: sub << ob | obj.
+__device__ __forceinline__ unsigned radix_key(unsigned long long k, int ob) {
+    return ((unsigned)((k >> 25) & 0x7f) << ob) | ((unsigned)k & 0x1ffffffu);
+}
+
+// Each wavefront sorts segments of up to kCap keys on its own; a lane
+// keeps its keys of a pass in registers (key c * 64 + lane in slot c), so
+// the pass scatters them back over the one LDS array they came from.
 template <int kCap, int kWaves>
 __global__ __launch_bounds__(64 * kWaves) void k_pair_sort_radix(const unsigned long long* __restrict__ keys,
                                                                 const int32_t* __restrict__ fstart, int64_t n_frames,
                                                                 int lo_n, int ob, int bits, int rb,
                                                                 int32_t* __restrict__ pf, int32_t* __restrict__ ps,
                                                                 int32_t* __restrict__ po) {
-    __shared__ unsigned sh_a[kWaves][kCap], sh_b[kWaves][kCap];
+    constexpr int kChunks = kCap / kWave;
+    __shared__ unsigned sh_a[kWaves][kCap];
     __shared__ int sh_cnt[kWaves][kRadixBuckets];
     __shared__ unsigned long long sh_mk[kWaves][kRadixBuckets];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -1742,29 +1751,38 @@ __global__ __launch_bounds__(64 * kWaves) void k_pair_sort_radix(const unsigned 
     const unsigned omask = ob >= 32 ? ~0u : ((1u << ob) - 1u);
     int* cnt = sh_cnt[wv];
     unsigned long long* mk = sh_mk[wv];
+    unsigned* A = sh_a[wv];
     for (int d = lane; d < kRadixBuckets; d += kWave) mk[d] = 0ull;
     wave_lds_sync();
+    const unsigned dm = (1u << rb) - 1u;
     for (int64_t f = (int64_t)blockIdx.x * kWaves + wv; f < n_frames; f += (int64_t)gridDim.x * kWaves) {
         const int a0 = fstart[f], n = fstart[f + 1] - a0;
         if (n <= lo_n || n > kCap) continue;
-        unsigned* A = sh_a[wv];
-        unsigned* B = sh_b[wv];
-        for (int i = lane; i < n; i += kWave) {
-            const unsigned long long k = keys[a0 + i];
-            A[i] = ((unsigned)((k >> 25) & 0x7f) << ob) | ((unsigned)k & 0x1ffffffu);
+        unsigned kr[kChunks];
+#pragma unroll
+        for (int c = 0; c < kChunks; ++c) {
+            const int i = kWave * c + lane;
+            kr[c] = i < n ? radix_key(keys[a0 + i], ob) : 0u;
         }
-        wave_lds_sync();
-        const unsigned dm = (1u << rb) - 1u;
         for (int shift = 0; shift < bits; shift += rb) {
+            if (shift > 0) {
+#pragma unroll
+                for (int c = 0; c < kChunks; ++c) {
+                    const int i = kWave * c + lane;
+                    kr[c] = i < n ? A[i] : 0u;
+                }
+            }
             for (int d = lane; d < kRadixBuckets; d += kWave) cnt[d] = 0;
             wave_lds_sync();
-            for (int i = lane; i < n; i += kWave) atomicAdd(&cnt[(A[i] >> shift) & dm], 1);
+#pragma unroll
+            for (int c = 0; c < kChunks; ++c)
+                if (kWave * c + lane < n) atomicAdd(&cnt[(kr[c] >> shift) & dm], 1);
             wave_lds_sync();
             // exclusive scan of the counts, kRadixBuckets / 64 per lane
             constexpr int kPer = kRadixBuckets / kWave;
-            int c[kPer], tot = 0;
+            int cc[kPer], tot = 0;
 #pragma unroll
-            for (int q = 0; q < kPer; ++q) { c[q] = cnt[kPer * lane + q]; tot += c[q]; }
+            for (int q = 0; q < kPer; ++q) { cc[q] = cnt[kPer * lane + q]; tot += cc[q]; }
             int incl = tot;
 #pragma unroll
             for (int off = 1; off < kWave; off <<= 1) {
@@ -1773,17 +1791,12 @@ __global__ __launch_bounds__(64 * kWaves) void k_pair_sort_radix(const unsigned 
             }
             int run = incl - tot;
 #pragma unroll
-            for (int q = 0; q < kPer; ++q) { cnt[kPer * lane + q] = run; run += c[q]; }
+            for (int q = 0; q < kPer; ++q) { cnt[kPer * lane + q] = run; run += cc[q]; }
             wave_lds_sync();
-            for (int i0 = 0; i0 < n; i0 += kWave) {
-                const int i = i0 + lane;
-                const bool v = i < n;
-                const unsigned k = v ? A[i] : 0u;
-                radix_scatter_chunk(v, k, (k >> shift) & dm, cnt, mk, B, lt);
-            }
-            unsigned* t = A;
-            A = B;
-            B = t;
+#pragma unroll
+            for (int c = 0; c < kChunks; ++c)
+                if (kWave * c < n)
+                    radix_scatter_chunk(kWave * c + lane < n, kr[c], (kr[c] >> shift) & dm, cnt, mk, A, lt);
         }
         for (int i = lane; i < n; i += kWave) {
             const unsigned k = A[i];
@@ -1797,17 +1810,18 @@ __global__ __launch_bounds__(64 * kWaves) void k_pair_sort_radix(const unsigned 
 
 // The same radix sort by a block of kSortWaves wavefronts per segment: per
 // pass each wavefront counts the digits of its quarter of the keys (whole
-// 64-key chunks, in order), a block scan turns the per-wavefront counts
-// into per-wavefront cursors (digit-major, wavefront-minor), and each
-// wavefront scatters its quarter with its own cursors, so the order of
-// equal digits is kept across the block.
+// 64-key chunks, in order, held in registers), a block scan turns the
+// per-wavefront counts into per-wavefront cursors (digit-major,
+// wavefront-minor), and each wavefront scatters its quarter with its own
+// cursors, so the order of equal digits is kept across the block.
 constexpr int kSortWaves = 4;
 
 template <int kCap>
 __global__ __launch_bounds__(64 * kSortWaves) void k_pair_sort_radix_block(
     const unsigned long long* __restrict__ keys, const int32_t* __restrict__ fstart, int64_t n_frames, int lo_n,
     int ob, int bits, int rb, int32_t* __restrict__ pf, int32_t* __restrict__ ps, int32_t* __restrict__ po) {
-    __shared__ unsigned sh_a[kCap], sh_b[kCap];
+    constexpr int kChunks = kCap / (kWave * kSortWaves);          // chunks of one wavefront at most
+    __shared__ unsigned A[kCap];
     __shared__ int cnt[kSortWaves][kRadixBuckets];
     __shared__ unsigned long long sh_mk[kSortWaves][kRadixBuckets];
     __shared__ int wsum[kSortWaves];
@@ -1822,29 +1836,38 @@ __global__ __launch_bounds__(64 * kSortWaves) void k_pair_sort_radix_block(
     for (int64_t f = blockIdx.x; f < n_frames; f += gridDim.x) {
         const int a0 = fstart[f], n = fstart[f + 1] - a0;
         if (n <= lo_n || n > kCap) continue;
-        unsigned* A = sh_a;
-        unsigned* B = sh_b;
-        for (int i = tid; i < n; i += 64 * kSortWaves) {
-            const unsigned long long k = keys[a0 + i];
-            A[i] = ((unsigned)((k >> 25) & 0x7f) << ob) | ((unsigned)k & 0x1ffffffu);
-        }
-        // this wavefront's keys: chunks c0 .. c1 - 1 of 64
+        // this wavefront's keys: chunks ca .. cb - 1 of 64 (at most kChunks)
         const int nc = (n + kWave - 1) / kWave;
-        const int qa = kWave * (nc * wv / kSortWaves), qb = min(n, kWave * (nc * (wv + 1) / kSortWaves));
-        __syncthreads();
+        const int ca = nc * wv / kSortWaves, cb = nc * (wv + 1) / kSortWaves;
+        unsigned kr[kChunks];
+#pragma unroll
+        for (int c = 0; c < kChunks; ++c) {
+            const int i = kWave * (ca + c) + lane;
+            kr[c] = (ca + c < cb && i < n) ? radix_key(keys[a0 + i], ob) : 0u;
+        }
         for (int shift = 0; shift < bits; shift += rb) {
+            if (shift > 0) {
+#pragma unroll
+                for (int c = 0; c < kChunks; ++c) {
+                    const int i = kWave * (ca + c) + lane;
+                    kr[c] = (ca + c < cb && i < n) ? A[i] : 0u;
+                }
+            }
             for (int d = lane; d < kRadixBuckets; d += kWave) cnt[wv][d] = 0;
             wave_lds_sync();
-            for (int i = qa + lane; i < qb; i += kWave) atomicAdd(&cnt[wv][(A[i] >> shift) & dm], 1);
+#pragma unroll
+            for (int c = 0; c < kChunks; ++c)
+                if (ca + c < cb && kWave * (ca + c) + lane < n) atomicAdd(&cnt[wv][(kr[c] >> shift) & dm], 1);
+            // (every wavefront has read its keys out of A before this barrier)
             __syncthreads();
             // thread tid: digits kPerT tid .. kPerT tid + kPerT - 1, their
             // total, its exclusive scan over the threads, then the cursors of
             // the digits and wavefronts in order
-            int c[kPerT][kSortWaves], tot = 0;
+            int cc[kPerT][kSortWaves], tot = 0;
 #pragma unroll
             for (int q = 0; q < kPerT; ++q)
 #pragma unroll
-                for (int w = 0; w < kSortWaves; ++w) { c[q][w] = cnt[w][kPerT * tid + q]; tot += c[q][w]; }
+                for (int w = 0; w < kSortWaves; ++w) { cc[q][w] = cnt[w][kPerT * tid + q]; tot += cc[q][w]; }
             int incl = tot;
 #pragma unroll
             for (int off = 1; off < kWave; off <<= 1) {
@@ -1858,18 +1881,14 @@ __global__ __launch_bounds__(64 * kSortWaves) void k_pair_sort_radix_block(
 #pragma unroll
             for (int q = 0; q < kPerT; ++q)
 #pragma unroll
-                for (int w = 0; w < kSortWaves; ++w) { cnt[w][kPerT * tid + q] = run; run += c[q][w]; }
+                for (int w = 0; w < kSortWaves; ++w) { cnt[w][kPerT * tid + q] = run; run += cc[q][w]; }
             __syncthreads();
-            for (int i0 = qa; i0 < qb; i0 += kWave) {
-                const int i = i0 + lane;
-                const bool v = i < qb;
-                const unsigned k = v ? A[i] : 0u;
-                radix_scatter_chunk(v, k, (k >> shift) & dm, cnt[wv], sh_mk[wv], B, lt);
-            }
+#pragma unroll
+            for (int c = 0; c < kChunks; ++c)
+                if (ca + c < cb)
+                    radix_scatter_chunk(kWave * (ca + c) + lane < n, kr[c], (kr[c] >> shift) & dm, cnt[wv],
+                                        sh_mk[wv], A, lt);
             __syncthreads();
-            unsigned* t = A;
-            A = B;
-            B = t;
         }
         for (int i = tid; i < n; i += 64 * kSortWaves) {
             const unsigned k = A[i];
