@@ -689,9 +689,12 @@ __device__ __forceinline__ int nth_set_bit(unsigned long long w, int r) {
 // over the wavefront and tested 64 at a time, one per lane, so a pair with
 // many of them does not hold the others up.  Frames are named by their
 // cell rank r.  The whole wavefront calls it.
+constexpr int kTestList = 256;          // tests a wavefront lists in LDS at once
+constexpr int kTestListPer = 8;         // and per pair
 __device__ void classify_emit(const FovParams& p, bool has, const ObjBounds& o, int r, double tr, double Asun,
                               unsigned long long gobj, unsigned long long* cbuf, int& nc, unsigned long long* pbuf,
                               int& np, unsigned long long& n_exact) {
+    __shared__ unsigned short s_tests[4][kTestList];
     const int lane = threadIdx.x & 63;
     bool all = false;
     unsigned long long m0 = 0ull, m1 = 0ull;
@@ -761,6 +764,38 @@ __device__ void classify_emit(const FovParams& p, bool has, const ObjBounds& o, 
         if (lane >= off) incl += t;
     }
     const int total = __shfl(incl, kWave - 1, kWave);
+    if (total == 0) return;
+    if (total <= kTestList && __ballot(cnt > kTestListPer) == 0ull) {
+        // The usual case, a few tests per pair: each lane lists its tests
+        // (lane << 8 | sub-frame) at its exclusive prefix in LDS, one
+        // sub-frame per round, and lane t of a pass reads test t back.
+        unsigned short* tl = s_tests[(threadIdx.x >> 6) & 3];
+        unsigned long long a = m0, b = m1;
+        int pos = incl - cnt;
+#pragma unroll 1
+        for (int k = 0; k < kTestListPer; ++k) {
+            const bool more = (a | b) != 0ull;
+            if (__ballot(more) == 0ull) break;
+            if (more) {
+                const int sb = a ? __ffsll((long long)a) - 1 : 64 + __ffsll((long long)b) - 1;
+                if (a) a &= a - 1ull; else b &= b - 1ull;
+                tl[pos++] = (unsigned short)((lane << 8) | sb);
+            }
+        }
+        wave_lds_sync();
+        for (int t0 = 0; t0 < total; t0 += kWave) {
+            const int t = t0 + lane;
+            const unsigned te = t < total ? tl[t] : 0u;
+            const int i = (int)(te >> 8);
+            const double u0 = __shfl(ul[0], i, kWave), u1 = __shfl(ul[1], i, kWave), u2 = __shfl(ul[2], i, kWave);
+            const double e = __shfl(e2, i, kWave);
+            const int ri = __shfl(r, i, kWave);
+            const unsigned long long bi = __shfl(base, i, kWave);
+            sub_test(t < total, ri, (int)(te & 0xffu), u0, u1, u2, e, bi);
+        }
+        wave_lds_sync();                      // the list is read before the next call writes it
+        return;
+    }
     for (int t0 = 0; t0 < total; t0 += kWave) {
         const int t = t0 + lane;
         // the pair holding test t: the first lane whose inclusive count exceeds t
