@@ -1679,22 +1679,30 @@ __global__ void k_pair_hist(const unsigned long long* __restrict__ keys, int64_t
     if (r.len > 0) atomicAdd(fcnt + r.f, r.len);
 }
 
+// The keys of one frame differ only in (sub-frame, object): inside a
+// frame's segment a key is sub << ob | obj, ob the bits of the object
+// index (sub < 128, obj < 2^25, so ob + 7 <= 32 bits suffice).
+__device__ __forceinline__ unsigned radix_key(unsigned long long k, int ob) {
+    return ((unsigned)((k >> 25) & 0x7f) << ob) | ((unsigned)k & 0x1ffffffu);
+}
+
 __global__ void k_pair_scatter(const unsigned long long* __restrict__ keys, int64_t n,
-                               const int32_t* __restrict__ fstart, int32_t* __restrict__ fcur,
-                               unsigned long long* __restrict__ out) {
+                               const int32_t* __restrict__ fstart, int32_t* __restrict__ fcur, int ob,
+                               unsigned* __restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const FrameRun r = frame_run(keys, n, i);
     int base = 0;
     if (r.len > 0) base = fstart[r.f] + atomicAdd(fcur + r.f, r.len);
     base = __shfl(base, r.head < 0 ? 0 : r.head, 64);
-    if (i < n) out[base + ((int)(threadIdx.x & 63) - r.head)] = keys[i];
+    if (i < n) out[base + ((int)(threadIdx.x & 63) - r.head)] = radix_key(keys[i], ob);
 }
 
-__device__ __forceinline__ void unpack_pair(unsigned long long k, int i, int32_t* __restrict__ pf,
+// Pair i of frame f from its segment key k.
+__device__ __forceinline__ void unpack_pair(unsigned k, int64_t f, int ob, int i, int32_t* __restrict__ pf,
                                             int32_t* __restrict__ ps, int32_t* __restrict__ po) {
-    pf[i] = (int32_t)(k >> 32);
-    ps[i] = (int32_t)((k >> 25) & 0x7f);
-    po[i] = (int32_t)(k & 0x1ffffff);
+    pf[i] = (int32_t)f;
+    ps[i] = (int32_t)(k >> ob);
+    po[i] = (int32_t)(ob >= 32 ? k : (k & ((1u << ob) - 1u)));
 }
 
 // Ordering inside each frame's segment of the pair keys (keys are unique),
@@ -1707,20 +1715,20 @@ constexpr int kSortSmall = 32;
 constexpr int kSortWave = 1024;
 constexpr int kSortLds = 8192;
 
-__global__ void k_pair_sort_small(unsigned long long* __restrict__ keys, const int32_t* __restrict__ fstart,
-                                  int64_t n_frames, int32_t* __restrict__ pf, int32_t* __restrict__ ps,
+__global__ void k_pair_sort_small(unsigned* __restrict__ keys, const int32_t* __restrict__ fstart,
+                                  int64_t n_frames, int ob, int32_t* __restrict__ pf, int32_t* __restrict__ ps,
                                   int32_t* __restrict__ po) {
     const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= n_frames) return;
     const int a = fstart[f], e = fstart[f + 1];
     if (e - a > kSortSmall) return;
     for (int i = a + 1; i < e; ++i) {
-        const unsigned long long k = keys[i];
+        const unsigned k = keys[i];
         int j = i - 1;
         while (j >= a && keys[j] > k) { keys[j + 1] = keys[j]; --j; }
         keys[j + 1] = k;
     }
-    for (int i = a; i < e; ++i) unpack_pair(keys[i], i, pf, ps, po);
+    for (int i = a; i < e; ++i) unpack_pair(keys[i], f, ob, i, pf, ps, po);
 }
 
 // Stable LSD radix sort of one frame's keys by one wavefront in LDS.  The
@@ -1763,16 +1771,11 @@ __device__ __forceinline__ void radix_scatter_chunk(bool v, unsigned k, unsigned
     wave_lds_sync();
 }
 
-// A key of a frame's segment as the radix sorts order it: sub << ob | obj.
-__device__ __forceinline__ unsigned radix_key(unsigned long long k, int ob) {
-    return ((unsigned)((k >> 25) & 0x7f) << ob) | ((unsigned)k & 0x1ffffffu);
-}
-
 // Each wavefront sorts segments of up to kCap keys on its own; a lane
 // keeps its keys of a pass in registers (key c * 64 + lane in slot c), so
 // the pass scatters them back over the one LDS array they came from.
 template <int kCap, int kWaves>
-__global__ __launch_bounds__(64 * kWaves) void k_pair_sort_radix(const unsigned long long* __restrict__ keys,
+__global__ __launch_bounds__(64 * kWaves) void k_pair_sort_radix(const unsigned* __restrict__ keys,
                                                                 const int32_t* __restrict__ fstart, int64_t n_frames,
                                                                 int lo_n, int ob, int bits, int rb,
                                                                 int32_t* __restrict__ pf, int32_t* __restrict__ ps,
@@ -1797,7 +1800,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_pair_sort_radix(const unsigned 
 #pragma unroll
         for (int c = 0; c < kChunks; ++c) {
             const int i = kWave * c + lane;
-            kr[c] = i < n ? radix_key(keys[a0 + i], ob) : 0u;
+            kr[c] = i < n ? keys[a0 + i] : 0u;
         }
         for (int shift = 0; shift < bits; shift += rb) {
             if (shift > 0) {
@@ -1853,7 +1856,7 @@ constexpr int kSortWaves = 4;
 
 template <int kCap>
 __global__ __launch_bounds__(64 * kSortWaves) void k_pair_sort_radix_block(
-    const unsigned long long* __restrict__ keys, const int32_t* __restrict__ fstart, int64_t n_frames, int lo_n,
+    const unsigned* __restrict__ keys, const int32_t* __restrict__ fstart, int64_t n_frames, int lo_n,
     int ob, int bits, int rb, int32_t* __restrict__ pf, int32_t* __restrict__ ps, int32_t* __restrict__ po) {
     constexpr int kChunks = kCap / (kWave * kSortWaves);          // chunks of one wavefront at most
     __shared__ unsigned A[kCap];
@@ -1878,7 +1881,7 @@ __global__ __launch_bounds__(64 * kSortWaves) void k_pair_sort_radix_block(
 #pragma unroll
         for (int c = 0; c < kChunks; ++c) {
             const int i = kWave * (ca + c) + lane;
-            kr[c] = (ca + c < cb && i < n) ? radix_key(keys[a0 + i], ob) : 0u;
+            kr[c] = (ca + c < cb && i < n) ? keys[a0 + i] : 0u;
         }
         for (int shift = 0; shift < bits; shift += rb) {
             if (shift > 0) {
@@ -1935,16 +1938,15 @@ __global__ __launch_bounds__(64 * kSortWaves) void k_pair_sort_radix_block(
     }
 }
 
-__global__ __launch_bounds__(256) void k_pair_sort_large(unsigned long long* __restrict__ keys,
-                                                        unsigned long long* __restrict__ tmp,
+__global__ __launch_bounds__(256) void k_pair_sort_large(unsigned* __restrict__ keys, unsigned* __restrict__ tmp,
                                                         const int32_t* __restrict__ fstart, int64_t n_frames,
-                                                        int32_t* __restrict__ pf, int32_t* __restrict__ ps,
+                                                        int ob, int32_t* __restrict__ pf, int32_t* __restrict__ ps,
                                                         int32_t* __restrict__ po) {
     for (int64_t f = blockIdx.x; f < n_frames; f += gridDim.x) {
         const int a = fstart[f], n = fstart[f + 1] - a;
         if (n <= kSortLds) continue;
-        unsigned long long* src = keys + a;
-        unsigned long long* dst = tmp + a;
+        unsigned* src = keys + a;
+        unsigned* dst = tmp + a;
         for (int w = 1; w < n; w <<= 1) {
             for (int i = threadIdx.x; i < n; i += blockDim.x) {
                 const int p0 = (i / (2 * w)) * (2 * w);
@@ -1955,14 +1957,14 @@ __global__ __launch_bounds__(256) void k_pair_sort_large(unsigned long long* __r
                     const int mid = (lo + hi) >> 1;
                     if (src[p0 + mid] < src[a1 + k - mid - 1]) lo = mid + 1; else hi = mid;
                 }
-                const unsigned long long va = lo < m ? src[p0 + lo] : ~0ull;
-                const unsigned long long vb = k - lo < m2 ? src[a1 + k - lo] : ~0ull;
+                const unsigned va = lo < m ? src[p0 + lo] : ~0u;
+                const unsigned vb = k - lo < m2 ? src[a1 + k - lo] : ~0u;
                 dst[i] = va < vb ? va : vb;
             }
             __syncthreads();
-            unsigned long long* t = src; src = dst; dst = t;
+            unsigned* t = src; src = dst; dst = t;
         }
-        for (int i = threadIdx.x; i < n; i += blockDim.x) unpack_pair(src[i], a + i, pf, ps, po);
+        for (int i = threadIdx.x; i < n; i += blockDim.x) unpack_pair(src[i], f, ob, a + i, pf, ps, po);
         __syncthreads();
     }
 }
@@ -2147,30 +2149,31 @@ static int radix_digit_bits(int bits) {
 hipError_t fov_sort(unsigned long long* keys, int64_t n, int64_t n_frames, int64_t n_obj, int n_sub, int32_t* fcnt,
                     int32_t* fstart, unsigned long long* sorted, void* scan_scratch, int32_t* pf, int32_t* ps,
                     int32_t* po, hipStream_t s) {
-    unsigned long long* tmp = keys;            // free once the keys are scattered by frame
+    // the scatter writes 32-bit segment keys into `sorted`; `keys` is free
+    // once they are scattered and holds the merge sort's second copy
+    unsigned* seg = reinterpret_cast<unsigned*>(sorted);
+    unsigned* tmp = reinterpret_cast<unsigned*>(keys);
+    const int ob = bits_for(n_obj), bits = ob + bits_for(n_sub), rb = radix_digit_bits(bits);
     hipError_t e;
     if ((e = fill_zero(fcnt, (size_t)(n_frames + 1) * sizeof(int32_t), s)) != hipSuccess) return e;
     if (n > 0) hipLaunchKernelGGL(k_pair_hist, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, keys, n, fcnt);
     if ((e = exclusive_scan_i32(fcnt, fstart, n_frames, scan_scratch, s)) != hipSuccess) return e;
     if ((e = fill_zero(fcnt, (size_t)n_frames * sizeof(int32_t), s)) != hipSuccess) return e;
     if (n > 0) hipLaunchKernelGGL(k_pair_scatter, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, keys, n,
-                                  (const int32_t*)fstart, fcnt, sorted);
+                                  (const int32_t*)fstart, fcnt, ob, seg);
     if (n_frames > 0) {
         const unsigned gb = (unsigned)std::min<int64_t>(n_frames, (int64_t)cu_count() * 16);
-        hipLaunchKernelGGL(k_pair_sort_small, dim3((unsigned)((n_frames + 255) / 256)), dim3(256), 0, s, sorted,
-                           (const int32_t*)fstart, n_frames, pf, ps, po);
-        const int ob = bits_for(n_obj), bits = ob + bits_for(n_sub), rb = radix_digit_bits(bits);
-        hipLaunchKernelGGL((k_pair_sort_radix<kSortWave, 4>), dim3(gb), dim3(256), 0, s,
-                           (const unsigned long long*)sorted, (const int32_t*)fstart, n_frames, kSortSmall, ob, bits,
-                           rb, pf, ps, po);
+        hipLaunchKernelGGL(k_pair_sort_small, dim3((unsigned)((n_frames + 255) / 256)), dim3(256), 0, s, seg,
+                           (const int32_t*)fstart, n_frames, ob, pf, ps, po);
+        hipLaunchKernelGGL((k_pair_sort_radix<kSortWave, 4>), dim3(gb), dim3(256), 0, s, (const unsigned*)seg,
+                           (const int32_t*)fstart, n_frames, kSortSmall, ob, bits, rb, pf, ps, po);
         hipLaunchKernelGGL((k_pair_sort_radix_block<4096>), dim3(gb), dim3(64 * kSortWaves), 0, s,
-                           (const unsigned long long*)sorted, (const int32_t*)fstart, n_frames, kSortWave, ob, bits,
-                           rb, pf, ps, po);
+                           (const unsigned*)seg, (const int32_t*)fstart, n_frames, kSortWave, ob, bits, rb, pf, ps,
+                           po);
         hipLaunchKernelGGL((k_pair_sort_radix_block<kSortLds>), dim3(gb), dim3(64 * kSortWaves), 0, s,
-                           (const unsigned long long*)sorted, (const int32_t*)fstart, n_frames, 4096, ob, bits,
-                           rb, pf, ps, po);
-        hipLaunchKernelGGL(k_pair_sort_large, dim3(gb), dim3(256), 0, s, sorted, tmp, (const int32_t*)fstart,
-                           n_frames, pf, ps, po);
+                           (const unsigned*)seg, (const int32_t*)fstart, n_frames, 4096, ob, bits, rb, pf, ps, po);
+        hipLaunchKernelGGL(k_pair_sort_large, dim3(gb), dim3(256), 0, s, seg, tmp, (const int32_t*)fstart,
+                           n_frames, ob, pf, ps, po);
     }
     return hipGetLastError();
 }
