@@ -635,10 +635,13 @@ __device__ __forceinline__ void sub_candidates(int S, bool have_loc, const LocHe
     if (!have_loc || !(h.usable > 0.5)) return;
     const double uc = dot3(u, h.c);
     if (!(uc > 0.0)) return;
-    const double X = dot3(u, h.e1) / uc, Y = dot3(u, h.e2) / uc;
+    // (the product with 1 / uc and the bound 1 / (1 - q) <= 1 + 2q for
+    // q <= 1/2 replace two divisions; both errors are far inside the margin)
+    const double iuc = 1.0 / uc;
+    const double X = dot3(u, h.e1) * iuc, Y = dot3(u, h.e2) * iuc;
     const double ru = sqrt(X * X + Y * Y);
     if (!(ru * t < 0.5)) return;
-    const double T = (ru + t) / (1.0 - ru * t);
+    const double T = (ru + t) * (1.0 + 2.0 * ru * t);
     const double mg = t * (1.0 + T * T) * (1.0 + 1e-9) + 1e-12 * (1.0 + ru);
     const double fx0 = (X - mg - h.x0) * h.idx, fx1 = (X + mg - h.x0) * h.idx;
     const double fy0 = (Y - mg - h.y0) * h.idy, fy1 = (Y + mg - h.y0) * h.idy;
@@ -1657,11 +1660,10 @@ struct FrameRun {
     int head;       // lane heading this lane's run
     int len;        // run length (head lanes)
 };
-__device__ __forceinline__ FrameRun frame_run(const unsigned long long* __restrict__ keys, int64_t n, int64_t i) {
+__device__ __forceinline__ FrameRun frame_run(unsigned long long key, bool valid) {
     const int lane = threadIdx.x & 63;
-    const bool valid = i < n;
     FrameRun r;
-    r.f = valid ? (int)(keys[i] >> 32) : -1;
+    r.f = valid ? (int)(key >> 32) : -1;
     const int fp = __shfl_up(r.f, 1, 64);
     const bool is_head = valid && (lane == 0 || fp != r.f);
     const unsigned long long heads = __ballot(is_head);
@@ -1673,10 +1675,23 @@ __device__ __forceinline__ FrameRun frame_run(const unsigned long long* __restri
     return r;
 }
 
-__global__ void k_pair_hist(const unsigned long long* __restrict__ keys, int64_t n, int32_t* __restrict__ fcnt) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const FrameRun r = frame_run(keys, n, i);
-    if (r.len > 0) atomicAdd(fcnt + r.f, r.len);
+// Each wavefront of the frame counting sort takes kRunChunks chunks of 64
+// consecutive keys, all loaded before the first is used.
+constexpr int kRunChunks = 4;
+constexpr int kRunKeysPerBlock = 256 * kRunChunks;       // 256-thread blocks
+
+__global__ __launch_bounds__(256) void k_pair_hist(const unsigned long long* __restrict__ keys, int64_t n,
+                                                   int32_t* __restrict__ fcnt) {
+    const int64_t i0 = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * (kWave * kRunChunks) +
+                       (threadIdx.x & 63);
+    unsigned long long k[kRunChunks];
+#pragma unroll
+    for (int c = 0; c < kRunChunks; ++c) k[c] = i0 + kWave * c < n ? keys[i0 + kWave * c] : 0ull;
+#pragma unroll
+    for (int c = 0; c < kRunChunks; ++c) {
+        const FrameRun r = frame_run(k[c], i0 + kWave * c < n);
+        if (r.len > 0) atomicAdd(fcnt + r.f, r.len);
+    }
 }
 
 // The keys of one frame differ only in (sub-frame, object): inside a
@@ -1686,15 +1701,27 @@ __device__ __forceinline__ unsigned radix_key(unsigned long long k, int ob) {
     return ((unsigned)((k >> 25) & 0x7f) << ob) | ((unsigned)k & 0x1ffffffu);
 }
 
-__global__ void k_pair_scatter(const unsigned long long* __restrict__ keys, int64_t n,
-                               const int32_t* __restrict__ fstart, int32_t* __restrict__ fcur, int ob,
-                               unsigned* __restrict__ out) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const FrameRun r = frame_run(keys, n, i);
-    int base = 0;
-    if (r.len > 0) base = fstart[r.f] + atomicAdd(fcur + r.f, r.len);
-    base = __shfl(base, r.head < 0 ? 0 : r.head, 64);
-    if (i < n) out[base + ((int)(threadIdx.x & 63) - r.head)] = radix_key(keys[i], ob);
+__global__ __launch_bounds__(256) void k_pair_scatter(const unsigned long long* __restrict__ keys, int64_t n,
+                                                      const int32_t* __restrict__ fstart,
+                                                      int32_t* __restrict__ fcur, int ob, unsigned* __restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const int64_t i0 = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * (kWave * kRunChunks) + lane;
+    unsigned long long k[kRunChunks];
+#pragma unroll
+    for (int c = 0; c < kRunChunks; ++c) k[c] = i0 + kWave * c < n ? keys[i0 + kWave * c] : 0ull;
+    FrameRun r[kRunChunks];
+    int base[kRunChunks];
+#pragma unroll
+    for (int c = 0; c < kRunChunks; ++c) {
+        r[c] = frame_run(k[c], i0 + kWave * c < n);
+        base[c] = 0;
+        if (r[c].len > 0) base[c] = fstart[r[c].f] + atomicAdd(fcur + r[c].f, r[c].len);
+    }
+#pragma unroll
+    for (int c = 0; c < kRunChunks; ++c) {
+        const int b = __shfl(base[c], r[c].head < 0 ? 0 : r[c].head, 64);
+        if (i0 + kWave * c < n) out[b + (lane - r[c].head)] = radix_key(k[c], ob);
+    }
 }
 
 // Pair i of frame f from its segment key k.
@@ -2156,10 +2183,11 @@ hipError_t fov_sort(unsigned long long* keys, int64_t n, int64_t n_frames, int64
     const int ob = bits_for(n_obj), bits = ob + bits_for(n_sub), rb = radix_digit_bits(bits);
     hipError_t e;
     if ((e = fill_zero(fcnt, (size_t)(n_frames + 1) * sizeof(int32_t), s)) != hipSuccess) return e;
-    if (n > 0) hipLaunchKernelGGL(k_pair_hist, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, keys, n, fcnt);
+    const unsigned run_blocks = (unsigned)((n + kRunKeysPerBlock - 1) / kRunKeysPerBlock);
+    if (n > 0) hipLaunchKernelGGL(k_pair_hist, dim3(run_blocks), dim3(256), 0, s, keys, n, fcnt);
     if ((e = exclusive_scan_i32(fcnt, fstart, n_frames, scan_scratch, s)) != hipSuccess) return e;
     if ((e = fill_zero(fcnt, (size_t)n_frames * sizeof(int32_t), s)) != hipSuccess) return e;
-    if (n > 0) hipLaunchKernelGGL(k_pair_scatter, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, keys, n,
+    if (n > 0) hipLaunchKernelGGL(k_pair_scatter, dim3(run_blocks), dim3(256), 0, s, keys, n,
                                   (const int32_t*)fstart, fcnt, ob, seg);
     if (n_frames > 0) {
         const unsigned gb = (unsigned)std::min<int64_t>(n_frames, (int64_t)cu_count() * 16);
