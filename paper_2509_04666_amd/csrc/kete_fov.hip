@@ -1676,12 +1676,28 @@ __device__ __forceinline__ FrameRun frame_run(unsigned long long key, bool valid
 }
 
 // Each wavefront of the frame counting sort takes kRunChunks chunks of 64
-// consecutive keys, all loaded before the first is used.
+// consecutive keys, all loaded before the first is used.  The runs of a
+// block meet in an LDS table keyed by frame (open addressing, one slot per
+// key of the block at most, so it never fills), and the frame counters see
+// one atomic per frame of the block.
 constexpr int kRunChunks = 4;
 constexpr int kRunKeysPerBlock = 256 * kRunChunks;       // 256-thread blocks
+constexpr int kRunSlots = kRunKeysPerBlock;
+
+__device__ __forceinline__ int run_slot(int* hkey, int f) {
+    int slot = (int)(((unsigned)f * 2654435761u) >> 22) & (kRunSlots - 1);
+    for (;;) {
+        const int prev = atomicCAS(&hkey[slot], -1, f);
+        if (prev == -1 || prev == f) return slot;
+        slot = (slot + 1) & (kRunSlots - 1);
+    }
+}
 
 __global__ __launch_bounds__(256) void k_pair_hist(const unsigned long long* __restrict__ keys, int64_t n,
                                                    int32_t* __restrict__ fcnt) {
+    __shared__ int hkey[kRunSlots], hcnt[kRunSlots];
+    for (int k = threadIdx.x; k < kRunSlots; k += 256) { hkey[k] = -1; hcnt[k] = 0; }
+    __syncthreads();
     const int64_t i0 = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * (kWave * kRunChunks) +
                        (threadIdx.x & 63);
     unsigned long long k[kRunChunks];
@@ -1690,8 +1706,11 @@ __global__ __launch_bounds__(256) void k_pair_hist(const unsigned long long* __r
 #pragma unroll
     for (int c = 0; c < kRunChunks; ++c) {
         const FrameRun r = frame_run(k[c], i0 + kWave * c < n);
-        if (r.len > 0) atomicAdd(fcnt + r.f, r.len);
+        if (r.len > 0) atomicAdd(&hcnt[run_slot(hkey, r.f)], r.len);
     }
+    __syncthreads();
+    for (int q = threadIdx.x; q < kRunSlots; q += 256)
+        if (hkey[q] >= 0) atomicAdd(fcnt + hkey[q], hcnt[q]);
 }
 
 // The keys of one frame differ only in (sub-frame, object): inside a
@@ -1701,25 +1720,41 @@ __device__ __forceinline__ unsigned radix_key(unsigned long long k, int ob) {
     return ((unsigned)((k >> 25) & 0x7f) << ob) | ((unsigned)k & 0x1ffffffu);
 }
 
+// Each run takes its place in the block's share of its frame's segment
+// from the LDS table, and each frame of the block takes that share with
+// one atomic on the frame's cursor.
 __global__ __launch_bounds__(256) void k_pair_scatter(const unsigned long long* __restrict__ keys, int64_t n,
                                                       const int32_t* __restrict__ fstart,
                                                       int32_t* __restrict__ fcur, int ob, unsigned* __restrict__ out) {
+    __shared__ int hkey[kRunSlots], hcnt[kRunSlots];
+    for (int q = threadIdx.x; q < kRunSlots; q += 256) { hkey[q] = -1; hcnt[q] = 0; }
+    __syncthreads();
     const int lane = threadIdx.x & 63;
     const int64_t i0 = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * (kWave * kRunChunks) + lane;
     unsigned long long k[kRunChunks];
 #pragma unroll
     for (int c = 0; c < kRunChunks; ++c) k[c] = i0 + kWave * c < n ? keys[i0 + kWave * c] : 0ull;
     FrameRun r[kRunChunks];
-    int base[kRunChunks];
+    int slot[kRunChunks], off[kRunChunks];
 #pragma unroll
     for (int c = 0; c < kRunChunks; ++c) {
         r[c] = frame_run(k[c], i0 + kWave * c < n);
-        base[c] = 0;
-        if (r[c].len > 0) base[c] = fstart[r[c].f] + atomicAdd(fcur + r[c].f, r[c].len);
+        slot[c] = 0;
+        off[c] = 0;
+        if (r[c].len > 0) {
+            slot[c] = run_slot(hkey, r[c].f);
+            off[c] = atomicAdd(&hcnt[slot[c]], r[c].len);
+        }
     }
+    __syncthreads();
+    // hcnt becomes the block's base in each frame's segment
+    for (int q = threadIdx.x; q < kRunSlots; q += 256)
+        if (hkey[q] >= 0) hcnt[q] = fstart[hkey[q]] + atomicAdd(fcur + hkey[q], hcnt[q]);
+    __syncthreads();
 #pragma unroll
     for (int c = 0; c < kRunChunks; ++c) {
-        const int b = __shfl(base[c], r[c].head < 0 ? 0 : r[c].head, 64);
+        const int pos = r[c].len > 0 ? hcnt[slot[c]] + off[c] : 0;
+        const int b = __shfl(pos, r[c].head < 0 ? 0 : r[c].head, 64);
         if (i0 + kWave * c < n) out[b + (lane - r[c].head)] = radix_key(k[c], ob);
     }
 }
