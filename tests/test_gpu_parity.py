@@ -662,13 +662,16 @@ def _random_layout_frames(rng, fr, n_sub=16):
 
 def test_fov_multi_subframe_layouts(torch_cuda, orc):
     """Frames of many sub-frames, which the sub-frame locator prunes:
-    ground footprints of 8 x 8 sub-frames, and the same frames with 16
-    rectangles of random size, roll and place (overlapping, with gaps),
-    against the oracle's brute force, given the oracle's states."""
+    ground footprints of 8 x 8 sub-frames, and the same frames with 16 or
+    120 rectangles of random size, roll and place (overlapping, with gaps;
+    120 fills both mask words and gives pairs more candidate sub-frames
+    than the drains list in LDS), against the oracle's brute force, given
+    the oracle's states."""
     torch, api = torch_cuda
     case = synth.footprint_case(n_obj=4000, n_frames=1500, span=12.0)
     layouts = [("footprints 8x8", case.frames),
-               ("random 16", _random_layout_frames(np.random.default_rng(81), case.frames))]
+               ("random 16", _random_layout_frames(np.random.default_rng(81), case.frames)),
+               ("random 120", _random_layout_frames(np.random.default_rng(82), case.frames, n_sub=120))]
     order, off, t_ref = orc.make_batches(case.frames.t)
     xe, st, _ = orc.propagate(case.ephem, case.x0, 0.0, t_ref)
     assert not st.any()
