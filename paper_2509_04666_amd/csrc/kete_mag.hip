@@ -139,14 +139,17 @@ __global__ __launch_bounds__(256) void k_pair_mag(const MagParams p, const int32
             const double s = sqrt(cx * cx + cy * cy + cz * cz);
             rh = sqrt(dot3(r, r));
             dl = sqrt(dot3(d, d));
-            al = atan2(s, c);
+            // the phase angle itself only when the geometry is asked for
+            if (p.geom) al = atan2(s, c);
             const double t = s / (rh * dl + c);
             // t^B as exp(B log t); t = 0 (zero phase) gives Phi = 1
             const double lt = log(t);
             const double phi1 = t > 0.0 ? exp(-kA1 * exp(kB1 * lt)) : 1.0;
             const double phi2 = t > 0.0 ? exp(-kA2 * exp(kB2 * lt)) : 1.0;
             const double G = p.g_slope[j];
-            v = p.h_mag[j] + 5.0 * log10(rh * dl) - 2.5 * log10((1.0 - G) * phi1 + G * phi2);
+            // 5 log10(r D) - 2.5 log10(Phi) with one logarithm
+            const double rd = rh * dl;
+            v = p.h_mag[j] + 2.5 * log10(rd * rd / ((1.0 - G) * phi1 + G * phi2));
         }
     }
     p.v_mag[i] = v;
