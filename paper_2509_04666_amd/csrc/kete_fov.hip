@@ -137,11 +137,13 @@ __global__ void k_frame_caps_lane(const double* __restrict__ normals, int64_t n_
 // wavefront per frame with a lane per sub-frame (and 64 + lane).  The
 // gnomonic image of a quadrilateral with great-circle edges inside the
 // hemisphere around the centre is the convex quadrilateral of its
-// vertices' images, so the box of those four points holds it; each box,
-// widened by a rounding pad, marks the locator cells it overlaps (bits
-// set with LDS OR atomics, each lane walking its own boxes' cells).  The
-// same pass writes the cell-ordered copy of the frame's time, observer and
-// normals the join reads.
+// vertices' images, so the box of those four points holds it; of the
+// locator cells the box (widened by a rounding pad) overlaps, each lane
+// marks those its quadrilateral really meets (bits set with LDS OR
+// atomics).  The tangent basis follows the first edge of sub-frame 0, so
+// that the cells of a regular mosaic line up with its rows and columns and
+// most cells name one sub-frame.  The same pass writes the cell-ordered
+// copy of the frame's time, observer and normals the join reads.
 __global__ __launch_bounds__(256) void k_frame_locator(const FovParams p) {
     __shared__ unsigned long long s_mask[4][2 * kLocL * kLocL];
     unsigned long long* wm = s_mask[threadIdx.x >> 6];
@@ -154,20 +156,37 @@ __global__ __launch_bounds__(256) void k_frame_locator(const FovParams p) {
         const double* cp = p.cell_caps + 8 * r;
         const int f = p.cell_frames[r];
         const double c[3] = {cp[0], cp[1], cp[2]};
-        // tangent basis: e1 from the axis least aligned with c
-        int ax = 0;
-        if (fabs(c[1]) < fabs(c[ax])) ax = 1;
-        if (fabs(c[2]) < fabs(c[ax])) ax = 2;
-        double e1[3] = {-c[ax] * c[0], -c[ax] * c[1], -c[ax] * c[2]};
-        e1[ax] += 1.0;
-        const double n1 = sqrt(dot3(e1, e1));
+        const double* src = p.normals + (size_t)f * S * 12;
+        float* dst = p.cell_normals + (size_t)r * S * 12;
+        // tangent basis: e1 along the first edge of sub-frame 0 (the cells of
+        // a regular mosaic then line up with its sub-frames), else from the
+        // axis least aligned with c; any orthonormal basis is correct
+        double dv[3] = {0.0, 0.0, 0.0};
+        if (lane == 0) {
+            double va[3], vb[3];
+            quad_vertex(src, 0, va);
+            quad_vertex(src, 1, vb);
+            const double na = sqrt(dot3(va, va)), nb = sqrt(dot3(vb, vb));
+            if (na > 0.0 && nb > 0.0)
+                for (int k = 0; k < 3; ++k) dv[k] = vb[k] / nb - va[k] / na;
+        }
+        for (int k = 0; k < 3; ++k) dv[k] = __shfl(dv[k], 0, kWave);
+        const double dc = dot3(dv, c);
+        double e1[3] = {dv[0] - dc * c[0], dv[1] - dc * c[1], dv[2] - dc * c[2]};
+        double n1 = sqrt(dot3(e1, e1));
+        if (!(n1 > 1e-9)) {
+            int ax = 0;
+            if (fabs(c[1]) < fabs(c[ax])) ax = 1;
+            if (fabs(c[2]) < fabs(c[ax])) ax = 2;
+            for (int k = 0; k < 3; ++k) e1[k] = -c[ax] * c[k];
+            e1[ax] += 1.0;
+            n1 = sqrt(dot3(e1, e1));
+        }
         for (int k = 0; k < 3; ++k) e1[k] /= n1;
         double e2[3];
         cross3(c, e1, e2);
         // gnomonic boxes of sub-frames lane and 64 + lane, whose normals are
         // copied to the cell-ordered table on the way
-        const double* src = p.normals + (size_t)f * S * 12;
-        float* dst = p.cell_normals + (size_t)r * S * 12;
         double a0[2], a1[2], b0[2], b1[2];
         bool ok = true;
 #pragma unroll
@@ -201,6 +220,7 @@ __global__ __launch_bounds__(256) void k_frame_locator(const FovParams p) {
             x0 -= pad; x1 += pad; y0 -= pad; y1 += pad;
             idx = kLocL / (x1 - x0);
             idy = kLocL / (y1 - y0);
+            const double cw = (x1 - x0) / kLocL, ch = (y1 - y0) / kLocL;
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 if (lane + 64 * h >= S) continue;
@@ -208,9 +228,36 @@ __global__ __launch_bounds__(256) void k_frame_locator(const FovParams p) {
                 const int i1 = min(kLocL - 1, (int)floor((a1[h] + pad - x0) * idx));
                 const int j0 = max(0, (int)floor((b0[h] - pad - y0) * idy));
                 const int j1 = min(kLocL - 1, (int)floor((b1[h] + pad - y0) * idy));
+                // a cell in the box is marked unless one edge of the
+                // sub-frame has the whole cell outside it: with v = c + X e1 +
+                // Y e2 the edge's n . v is linear in (X, Y), so its largest
+                // value over the cell is at a corner (an exact separating-axis
+                // test of the two convex gnomonic images, the box giving the
+                // cell's own axes; cells widened by a rounding pad)
+                double A[4], B[4], Cg[4];
+                const double* nh = src + 12 * (lane + 64 * h);     // read again (cached)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const double nk[3] = {nh[3 * k], nh[3 * k + 1], nh[3 * k + 2]};
+                    A[k] = dot3(nk, c);
+                    B[k] = dot3(nk, e1);
+                    Cg[k] = dot3(nk, e2);
+                }
                 const unsigned long long bit = 1ull << lane;
-                for (int ci = i0; ci <= i1; ++ci)
-                    for (int cj = j0; cj <= j1; ++cj) atomicOr(&wm[2 * (ci * kLocL + cj) + h], bit);
+                for (int ci = i0; ci <= i1; ++ci) {
+                    const double xa = x0 + ci * cw - pad, xb = x0 + (ci + 1) * cw + pad;
+                    for (int cj = j0; cj <= j1; ++cj) {
+                        const double ya = y0 + cj * ch - pad, yb = y0 + (cj + 1) * ch + pad;
+                        const double tol = 1e-9 * (1.0 + fmax(fabs(xa), fabs(xb)) + fmax(fabs(ya), fabs(yb)));
+                        bool sep = false;
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            const double m = A[k] + fmax(B[k] * xa, B[k] * xb) + fmax(Cg[k] * ya, Cg[k] * yb);
+                            sep = sep || m < -tol;
+                        }
+                        if (!sep) atomicOr(&wm[2 * (ci * kLocL + cj) + h], bit);
+                    }
+                }
             }
         }
         wave_lds_sync();
