@@ -234,6 +234,11 @@ __global__ __launch_bounds__(256) void k_frame_locator(const FovParams p) {
                 // value over the cell is at a corner (an exact separating-axis
                 // test of the two convex gnomonic images, the box giving the
                 // cell's own axes; cells widened by a rounding pad)
+                const unsigned long long bit = 1ull << lane;
+                if (i0 == i1 && j0 == j1) {           // a box in one cell: that cell
+                    atomicOr(&wm[2 * (i0 * kLocL + j0) + h], bit);
+                    continue;
+                }
                 double A[4], B[4], Cg[4];
                 const double* nh = src + 12 * (lane + 64 * h);     // read again (cached)
 #pragma unroll
@@ -243,7 +248,6 @@ __global__ __launch_bounds__(256) void k_frame_locator(const FovParams p) {
                     B[k] = dot3(nk, e1);
                     Cg[k] = dot3(nk, e2);
                 }
-                const unsigned long long bit = 1ull << lane;
                 for (int ci = i0; ci <= i1; ++ci) {
                     const double xa = x0 + ci * cw - pad, xb = x0 + (ci + 1) * cw + pad;
                     for (int cj = j0; cj <= j1; ++cj) {
