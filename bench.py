@@ -632,12 +632,16 @@ def main():
                                                   tune_cache=args.tune_cache)
         torch.cuda.empty_cache()
 
-    # roofline of the headline step's dominant kernel
+    # roofline of the headline step's dominant kernel; valu_issue_frac is the
+    # share of its time the SIMDs spend issuing its vector instructions (SQ
+    # counters in the committed profile, None once its sources changed)
     integ, fov = hrec["integrator"], hrec["fov"]
     if integ["avg_launch_ms"] >= fov["join_ms_per_step"]:
         roof = {"kernel": "k_nbody_g8 (integrator)", "bound": "alu", "achieved": integ["algorithmic_TFLOPs"],
                 "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": integ["algorithmic_frac_fp64_peak"],
                 "traffic": profile_figure("traffic_k_nbody_g8_%s.md" % head_case.name, "traffic_bytes_per_launch"),
+                "valu_issue_frac": profile_figure("sq_counters_%s.md" % head_case.name,
+                                                  "valu_issue_share_integrator"),
                 "launches_per_step": 1, "avg_launch_ms": integ["avg_launch_ms"],
                 "algorithmic_flops_per_launch": integ["algorithmic_flops_per_launch"]}
     else:
@@ -648,6 +652,7 @@ def main():
                 "achieved": jb / (fov["join_ms_per_step"] / 1e3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": jb / (fov["join_ms_per_step"] / 1e3) / 1e9 / HBM_PEAK_GBS,
                 "traffic": profile_figure("traffic_fov_join_%s.md" % head_case.name, "traffic_bytes_per_step"),
+                "valu_issue_frac": profile_figure("sq_counters_%s.md" % head_case.name, "valu_issue_share_join"),
                 "launches_per_step": 1, "avg_launch_ms": fov["join_ms_per_step"],
                 "algorithmic_bytes_per_launch": jb}
     out = {
